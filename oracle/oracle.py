@@ -1,0 +1,274 @@
+"""ctypes binding of the serial FP64 oracle (test infrastructure only).
+
+Each function passes numpy arrays to one C routine of tbkpm_oracle.c and
+returns numpy arrays; there is no arithmetic of the method here beyond
+argument marshalling, except the small compositions at the bottom that chain
+oracle routines in the order the path runs them.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_c128p = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f64 = ctypes.c_double
+
+
+def _lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = _build.LIB
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        _build.build()
+    L = ctypes.CDLL(path)
+    L.orc_neighbor_pairs.restype = _i64
+    L.orc_neighbor_pairs.argtypes = [_i64, _f64p, _f64p, _i32p, _f64, _i64, _i32p, _i32p, _f64p]
+    L.orc_assemble_csr.restype = ctypes.c_int
+    L.orc_assemble_csr.argtypes = [_i64, _i32p, _i32, _f64p, _f64p, _f64, _f64, _i64,
+                                   _i32p, _i32p, _f64p, ctypes.c_void_p,
+                                   _i64p, _i32p, _f64p, _f64p]
+    L.orc_gershgorin.restype = None
+    L.orc_gershgorin.argtypes = [_i64, _i64p, _f64p, _f64p, _f64p]
+    L.orc_kpm_moments.restype = ctypes.c_int
+    L.orc_kpm_moments.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64, _f64,
+                                  _c128p, _i32, _i32, _f64p, _f64p]
+    L.orc_jackson.restype = None
+    L.orc_jackson.argtypes = [_i32, _f64p]
+    L.orc_kpm_dos.restype = ctypes.c_int
+    L.orc_kpm_dos.argtypes = [_f64p, _i32, _f64, _f64, _i32, _f64p, _i32, _f64p]
+    L.orc_radial.restype = None
+    L.orc_radial.argtypes = [_f64, _f64, _i32, _f64p]
+    L.orc_descriptor.restype = None
+    L.orc_descriptor.argtypes = [_i64, _i64, _i32p, _i32p, _f64p, _f64, _i32, _f64p]
+    L.orc_bf16.restype = _f64
+    L.orc_bf16.argtypes = [_f64]
+    L.orc_mlp_forward.restype = None
+    L.orc_mlp_forward.argtypes = [_i64, _f64p, _f64p, _i32, _f64p, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_mlp_loss_grad.restype = _f64
+    L.orc_mlp_loss_grad.argtypes = [_i64, _f64p, _f64p, ctypes.c_void_p, _f64p, _i32, _f64p]
+    L.orc_bond_features.restype = None
+    L.orc_bond_features.argtypes = [_i64, _i32p, _i32p, _f64p, _f64p, _f64, _i32, _f64p, _f64p, _f64p]
+    L.orc_target_scale.restype = None
+    L.orc_target_scale.argtypes = [_i64, _i32p, _i32p, _f64p, _i32, _f64, _f64, _f64p]
+    L.orc_adamw_step.restype = None
+    L.orc_adamw_step.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _f64, _f64, _f64, _f64, _f64]
+    _LIB = L
+    return L
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+# --------------------------------------------------------------------------
+# Geometry and Hamiltonian
+# --------------------------------------------------------------------------
+
+def neighbor_pairs(pos, box, periodic, r_cut):
+    """Pairs i<j with minimum-image distance < r_cut: (pi, pj, dist)."""
+    pos = _c(pos, np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    box = _c(box, np.float64)
+    per = _c(periodic, np.int32)
+    cap = max(16, 4 * n)
+    while True:
+        pi = np.empty(cap, np.int32)
+        pj = np.empty(cap, np.int32)
+        d = np.empty(cap, np.float64)
+        cnt = _lib().orc_neighbor_pairs(n, pos.reshape(-1), box, per, float(r_cut), cap, pi, pj, d)
+        if cnt < 0:
+            raise OracleError("orc_neighbor_pairs: invalid argument")
+        if cnt <= cap:
+            return pi[:cnt].copy(), pj[:cnt].copy(), d[:cnt].copy()
+        cap = int(cnt)
+
+
+class CSR:
+    """Off-diagonal CSR part plus the onsite diagonal of H (both FP64)."""
+
+    def __init__(self, row_ptr, col, val, diag):
+        self.row_ptr, self.col, self.val, self.diag = row_ptr, col, val, diag
+
+    @property
+    def n(self):
+        return self.diag.shape[0]
+
+    def dense(self):
+        n = self.n
+        H = np.zeros((n, n))
+        for i in range(n):
+            for q in range(self.row_ptr[i], self.row_ptr[i + 1]):
+                H[i, self.col[q]] += self.val[q]
+            H[i, i] += self.diag[i]
+        return H
+
+
+def assemble_csr(n, species, n_species, onsite, t_pair, r0, beta, pairs, t_scale=None):
+    pi, pj, d = pairs
+    npairs = pi.shape[0]
+    row_ptr = np.empty(n + 1, np.int64)
+    col = np.empty(2 * npairs, np.int32)
+    val = np.empty(2 * npairs, np.float64)
+    diag = np.empty(n, np.float64)
+    ts = None
+    if t_scale is not None:
+        ts = _c(t_scale, np.float64)
+        assert ts.shape[0] == npairs
+    rc = _lib().orc_assemble_csr(n, _c(species, np.int32), int(n_species), _c(onsite, np.float64),
+                                 _c(t_pair, np.float64).reshape(-1), float(r0), float(beta), npairs,
+                                 pi, pj, d, None if ts is None else ts.ctypes.data,
+                                 row_ptr, col, val, diag)
+    if rc != 0:
+        raise OracleError("orc_assemble_csr: invalid argument")
+    return CSR(row_ptr, col, val, diag)
+
+
+def gershgorin(csr):
+    out = np.empty(2)
+    _lib().orc_gershgorin(csr.n, csr.row_ptr, csr.val, csr.diag, out)
+    return float(out[0]), float(out[1])
+
+
+# --------------------------------------------------------------------------
+# KPM
+# --------------------------------------------------------------------------
+
+def kpm_moments(csr, a, b, r, M):
+    """mu_re, mu_im of shape [R][M] for vectors r [N][R] (complex128)."""
+    r = _c(r, np.complex128)
+    if r.ndim == 1:
+        r = r.reshape(-1, 1)
+    n, R = r.shape
+    assert n == csr.n
+    mu_re = np.empty((R, M))
+    mu_im = np.empty((R, M))
+    rc = _lib().orc_kpm_moments(n, csr.row_ptr, csr.col, csr.val, csr.diag, float(a), float(b),
+                                r.reshape(-1), R, M, mu_re, mu_im)
+    if rc != 0:
+        raise OracleError("orc_kpm_moments: invalid argument")
+    return mu_re, mu_im
+
+
+def jackson(M):
+    g = np.empty(M)
+    _lib().orc_jackson(M, g)
+    return g
+
+
+def kpm_dos(mu, a, b, E, kernel=0):
+    mu = _c(mu, np.float64)
+    E = _c(E, np.float64)
+    rho = np.empty(E.shape[0])
+    rc = _lib().orc_kpm_dos(mu, mu.shape[0], float(a), float(b), int(kernel), E, E.shape[0], rho)
+    if rc != 0:
+        raise OracleError("orc_kpm_dos: invalid argument")
+    return rho
+
+
+# --------------------------------------------------------------------------
+# Learned hoppings
+# --------------------------------------------------------------------------
+
+def radial(r, rc, nk=8):
+    f = np.empty(nk)
+    _lib().orc_radial(float(r), float(rc), nk, f)
+    return f
+
+
+def descriptor(n, pairs, rc, nk=8):
+    pi, pj, d = pairs
+    v = np.empty((n, nk))
+    _lib().orc_descriptor(n, pi.shape[0], pi, pj, d, float(rc), nk, v.reshape(-1))
+    return v
+
+
+def bf16(x):
+    f = _lib().orc_bf16
+    x = np.asarray(x, np.float64)
+    return np.vectorize(f, otypes=[np.float64])(x) if x.ndim else f(float(x))
+
+
+N_PARAMS = 1633
+
+
+def bond_features(pairs, v, rc, shift=None, scale=None):
+    """[npairs][2 nk] MLP inputs [f(r_ij) || v_i + v_j], standardised by (shift, scale)."""
+    pi, pj, d = pairs
+    nk = v.shape[1]
+    shift = np.zeros(2 * nk) if shift is None else _c(shift, np.float64)
+    scale = np.ones(2 * nk) if scale is None else _c(scale, np.float64)
+    X = np.empty((pi.shape[0], 2 * nk))
+    _lib().orc_bond_features(pi.shape[0], pi, pj, d, _c(v, np.float64).reshape(-1), float(rc), nk,
+                             shift, scale, X.reshape(-1))
+    return X
+
+
+def target_scale(pairs, v, kappa, z0):
+    """Coordination-corrected hopping factor 1 + kappa (z_i + z_j - 2 z0) per pair."""
+    pi, pj, _ = pairs
+    out = np.empty(pi.shape[0])
+    _lib().orc_target_scale(pi.shape[0], pi, pj, _c(v, np.float64).reshape(-1), v.shape[1],
+                            float(kappa), float(z0), out)
+    return out
+
+
+def mlp_forward(X, prm, bf16_ops=True, keep=False):
+    X = _c(X, np.float64)
+    B = X.shape[0]
+    y = np.empty(B)
+    h1 = np.empty((B, 32)) if keep else None
+    h2 = np.empty((B, 32)) if keep else None
+    _lib().orc_mlp_forward(B, X.reshape(-1), _c(prm, np.float64), int(bool(bf16_ops)), y,
+                           None if h1 is None else h1.ctypes.data,
+                           None if h2 is None else h2.ctypes.data)
+    return (y, h1, h2) if keep else y
+
+
+def mlp_loss_grad(X, target, prm, w=None, bf16_ops=True):
+    X = _c(X, np.float64)
+    B = X.shape[0]
+    g = np.empty(N_PARAMS)
+    wv = None if w is None else _c(w, np.float64)
+    loss = _lib().orc_mlp_loss_grad(B, X.reshape(-1), _c(target, np.float64),
+                                    None if wv is None else wv.ctypes.data,
+                                    _c(prm, np.float64), int(bool(bf16_ops)), g)
+    return loss, g
+
+
+def adamw_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-2):
+    """In-place AdamW update of float64 arrays p, m, v (step count t after the update)."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _lib().orc_adamw_step(p.shape[0], p, _c(g, np.float64), m, v, int(t), float(lr),
+                          float(beta1), float(beta2), float(eps), float(wd))
+
+
+# --------------------------------------------------------------------------
+# Compositions in path order
+# --------------------------------------------------------------------------
+
+def hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0=1.42, beta=3.37,
+                t_scale=None, pairs=None):
+    """Neighbour pairs, then the CSR Hamiltonian of Eq. (1); returns (csr, pairs)."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    if pairs is None:
+        pairs = neighbor_pairs(pos, box, periodic, r_cut)
+    t_pair = np.asarray(t_pair, np.float64)
+    S = int(round(np.sqrt(t_pair.size)))
+    csr = assemble_csr(pos.shape[0], species, S, onsite, t_pair, r0, beta, pairs, t_scale)
+    return csr, pairs

@@ -1,0 +1,543 @@
+/*
+ * tbkpm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, serial FP64 CPU implementation of what the density-of-states
+ * hot path computes: neighbour pairs, the orthogonal tight-binding Hamiltonian
+ * of Eq. (1), the kernel-polynomial (Chebyshev) moments over random-phase
+ * vectors, Jackson damping and the DOS of Eq. (4); plus, for the learned-hopping
+ * variant, the Chebyshev radial descriptor of Eq. (2), a per-bond MLP forward and
+ * analytic backward with BF16 operand rounding, and one AdamW step.
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load this file.  It shares no code, header or constant generator with the HIP
+ * library; it is never called by the product path.
+ *
+ * Where the paper only names an ingredient (Sec. 2.4 names Chebyshev expansion,
+ * KPM, sparse matrix-vector products and random phases), the steps follow the
+ * published kernel polynomial method: Weisse, Wellein, Alvermann & Fehske,
+ * Rev. Mod. Phys. 78, 275 (2006) -- Chebyshev recurrence (their Sec. II.A),
+ * stochastic trace (Sec. II.D), Jackson kernel (Sec. II.C.3) and the DOS
+ * reconstruction (Sec. III.A).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (see oracle/build.py).
+ * Every routine is serial and allocation-light; errors are reported by a
+ * negative return value, never by aborting.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------- */
+/* Geometry: minimum-image displacement (periodic axes) and neighbour pairs.  */
+/* ------------------------------------------------------------------------- */
+
+/* Nearest periodic image of a displacement along one axis of length L. */
+static double orc_min_image(double d, double L, int periodic)
+{
+    if (!periodic) return d;
+    return d - L * nearbyint(d / L);
+}
+
+/* Displacement x_j - x_i under the minimum-image convention; returns |d|. */
+static double orc_displacement(const double *pos, int64_t i, int64_t j,
+                               const double box[3], const int32_t periodic[3],
+                               double d[3])
+{
+    for (int k = 0; k < 3; ++k)
+        d[k] = orc_min_image(pos[3 * j + k] - pos[3 * i + k], box[k], periodic[k]);
+    return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+/* Cell index of a coordinate along one axis with n cells over [lo, lo + L). */
+static int64_t orc_cell_of(double x, double lo, double L, int64_t n, int periodic)
+{
+    double u = (x - lo) / L;
+    if (periodic) u -= floor(u);
+    int64_t c = (int64_t)floor(u * (double)n);
+    if (c < 0) c = 0;
+    if (c >= n) c = n - 1;
+    return c;
+}
+
+/*
+ * All unordered pairs {i, j}, i < j, whose minimum-image distance is strictly
+ * below r_cut (the neighbour set N(i) of Eq. (1)).  Brute force over all pairs
+ * for n <= 5000, a plain cell list above.  Pairs are written in an arbitrary
+ * order; callers needing an order sort them.
+ *
+ * Returns the number of pairs found; if it exceeds `cap`, only the first `cap`
+ * are stored (call again with a larger buffer).  Returns -1 on a bad argument
+ * (periodic box shorter than 2 r_cut, non-finite coordinate, r_cut <= 0).
+ */
+int64_t orc_neighbor_pairs(int64_t n, const double *pos, const double box[3],
+                           const int32_t periodic[3], double r_cut, int64_t cap,
+                           int32_t *pi, int32_t *pj, double *dist)
+{
+    if (n < 0 || !(r_cut > 0.0)) return -1;
+    for (int k = 0; k < 3; ++k)
+        if (periodic[k] && !(box[k] >= 2.0 * r_cut)) return -1;
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!isfinite(pos[i])) return -1;
+
+    int64_t count = 0;
+    double d[3];
+    if (n <= 5000) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double r = orc_displacement(pos, i, j, box, periodic, d);
+                if (r < r_cut) {
+                    if (count < cap) { pi[count] = (int32_t)i; pj[count] = (int32_t)j; dist[count] = r; }
+                    ++count;
+                }
+            }
+        return count;
+    }
+
+    /* Cell list: cells at least r_cut wide; an axis with fewer than three cells
+     * is scanned whole so that no cell is visited twice. */
+    double lo[3], len[3];
+    int64_t nc[3];
+    for (int k = 0; k < 3; ++k) {
+        if (periodic[k]) { lo[k] = 0.0; len[k] = box[k]; }
+        else {
+            double mn = pos[k], mx = pos[k];
+            for (int64_t i = 1; i < n; ++i) {
+                if (pos[3 * i + k] < mn) mn = pos[3 * i + k];
+                if (pos[3 * i + k] > mx) mx = pos[3 * i + k];
+            }
+            lo[k] = mn; len[k] = (mx - mn) + 1e-9;
+        }
+        nc[k] = (int64_t)floor(len[k] / r_cut);
+        if (nc[k] < 1) nc[k] = 1;
+    }
+    int64_t ncell = nc[0] * nc[1] * nc[2];
+    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!head || !next || !cell) { free(head); free(next); free(cell); return -2; }
+    for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int64_t c0 = orc_cell_of(pos[3 * i + 0], lo[0], len[0], nc[0], periodic[0]);
+        int64_t c1 = orc_cell_of(pos[3 * i + 1], lo[1], len[1], nc[1], periodic[1]);
+        int64_t c2 = orc_cell_of(pos[3 * i + 2], lo[2], len[2], nc[2], periodic[2]);
+        cell[i] = (c2 * nc[1] + c1) * nc[0] + c0;
+        next[i] = head[cell[i]];
+        head[cell[i]] = i;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ci[3];
+        ci[0] = cell[i] % nc[0];
+        ci[1] = (cell[i] / nc[0]) % nc[1];
+        ci[2] = cell[i] / (nc[0] * nc[1]);
+        /* Offsets per axis: {-1,0,1} when there are >= 3 cells, else every cell. */
+        int64_t off[3][3], noff[3];
+        for (int k = 0; k < 3; ++k) {
+            if (nc[k] >= 3) { off[k][0] = -1; off[k][1] = 0; off[k][2] = 1; noff[k] = 3; }
+            else { noff[k] = nc[k]; for (int64_t t = 0; t < nc[k]; ++t) off[k][t] = t - ci[k]; }
+        }
+        for (int64_t a = 0; a < noff[2]; ++a)
+            for (int64_t b = 0; b < noff[1]; ++b)
+                for (int64_t c = 0; c < noff[0]; ++c) {
+                    int64_t cc[3] = {ci[0] + off[0][c], ci[1] + off[1][b], ci[2] + off[2][a]};
+                    int skip = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        if (cc[k] < 0 || cc[k] >= nc[k]) {
+                            if (periodic[k]) cc[k] = (cc[k] + nc[k]) % nc[k];
+                            else skip = 1;
+                        }
+                    }
+                    if (skip) continue;
+                    int64_t cid = (cc[2] * nc[1] + cc[1]) * nc[0] + cc[0];
+                    for (int64_t j = head[cid]; j >= 0; j = next[j]) {
+                        if (j <= i) continue;
+                        double r = orc_displacement(pos, i, j, box, periodic, d);
+                        if (r < r_cut) {
+                            if (count < cap) { pi[count] = (int32_t)i; pj[count] = (int32_t)j; dist[count] = r; }
+                            ++count;
+                        }
+                    }
+                }
+    }
+    free(head); free(next); free(cell);
+    return count;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hamiltonian of Eq. (1) in CSR form.                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Distance-scaled hopping between species s and u at distance r. */
+static double orc_hopping(double r, int32_t s, int32_t u, int32_t n_species,
+                          const double *t_pair, double r0, double beta)
+{
+    return t_pair[s * n_species + u] * exp(-beta * (r / r0 - 1.0));
+}
+
+static int orc_cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * CSR of the off-diagonal part of H (Eq. (1)): for every pair {i, j} found by
+ * orc_neighbor_pairs, H_ij = H_ji = t_pair[s_i][s_j] * exp(-beta (r/r0 - 1)).
+ * Columns of each row are sorted ascending.  When `t_scale` is non-NULL the
+ * hopping of pair p is multiplied by t_scale[p] (used for the learned and the
+ * target Hamiltonians, whose per-bond factors are computed by the callers).
+ * The onsite part H_ii = onsite[s_i] goes to `diag` [n].
+ *
+ * row_ptr has n+1 entries; col/val have 2*npairs entries.
+ * Returns 0, or -1 on a species index outside [0, n_species).
+ */
+int orc_assemble_csr(int64_t n, const int32_t *species, int32_t n_species,
+                     const double *onsite, const double *t_pair, double r0, double beta,
+                     int64_t npairs, const int32_t *pi, const int32_t *pj,
+                     const double *dist, const double *t_scale,
+                     int64_t *row_ptr, int32_t *col, double *val, double *diag)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (species[i] < 0 || species[i] >= n_species) return -1;
+    for (int64_t i = 0; i <= n; ++i) row_ptr[i] = 0;
+    for (int64_t p = 0; p < npairs; ++p) { row_ptr[pi[p] + 1]++; row_ptr[pj[p] + 1]++; }
+    for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!fill) return -2;
+    for (int64_t i = 0; i < n; ++i) fill[i] = row_ptr[i];
+    for (int64_t p = 0; p < npairs; ++p) { col[fill[pi[p]]++] = pj[p]; col[fill[pj[p]]++] = pi[p]; }
+    free(fill);
+    for (int64_t i = 0; i < n; ++i)
+        qsort(col + row_ptr[i], (size_t)(row_ptr[i + 1] - row_ptr[i]), sizeof(int32_t), orc_cmp_i32);
+    /* Values: look the pair up again so that each entry is computed from its own
+     * distance (both triangles from the same number, hence exactly symmetric). */
+    for (int64_t p = 0; p < npairs; ++p) {
+        int32_t i = pi[p], j = pj[p];
+        double t = orc_hopping(dist[p], species[i], species[j], n_species, t_pair, r0, beta);
+        if (t_scale) t *= t_scale[p];
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) if (col[q] == j) val[q] = t;
+        for (int64_t q = row_ptr[j]; q < row_ptr[j + 1]; ++q) if (col[q] == i) val[q] = t;
+    }
+    for (int64_t i = 0; i < n; ++i) diag[i] = onsite[species[i]];
+    return 0;
+}
+
+/* Row Gershgorin bounds of H = diag + off-diagonal CSR: [min_i (H_ii - sum|H_ij|),
+ * max_i (H_ii + sum|H_ij|)]. */
+void orc_gershgorin(int64_t n, const int64_t *row_ptr, const double *val,
+                    const double *diag, double bounds[2])
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) s += fabs(val[q]);
+        if (diag[i] - s < lo) lo = diag[i] - s;
+        if (diag[i] + s > hi) hi = diag[i] + s;
+    }
+    bounds[0] = lo;
+    bounds[1] = hi;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kernel polynomial method.                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* y = Htilde x with Htilde = (H - b) / a. */
+static void orc_apply_scaled(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const double *val, const double *diag, double a, double b,
+                             const double complex *x, double complex *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double complex s = (diag[i] - b) * x[i];
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) s += val[q] * x[col[q]];
+        y[i] = s / a;
+    }
+}
+
+/* Re and Im of <r|t> = sum_i conj(r_i) t_i. */
+static double complex orc_dot(int64_t n, const double complex *r, const double complex *t)
+{
+    double complex s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += conj(r[i]) * t[i];
+    return s;
+}
+
+/*
+ * Chebyshev moments mu_n^(v) = <r_v| T_n(Htilde) |r_v>, n = 0..M-1, for each
+ * of the R vectors r_v (stored interleaved: element (i, v) at r[i*R + v]).
+ * T_0 = r, T_1 = Htilde r, T_{n+1} = 2 Htilde T_n - T_{n-1}.  The moment is
+ * the direct overlap with the starting vector (no doubling identities).
+ * Outputs mu_re and mu_im, each [R][M].  Returns 0, -1 on bad arguments.
+ */
+int orc_kpm_moments(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *val, const double *diag, double a, double b,
+                    const double complex *r, int32_t R, int32_t M,
+                    double *mu_re, double *mu_im)
+{
+    if (n <= 0 || R < 1 || M < 1 || !(a > 0.0)) return -1;
+    double complex *rv = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t0 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t1 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t2 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    if (!rv || !t0 || !t1 || !t2) { free(rv); free(t0); free(t1); free(t2); return -2; }
+    for (int32_t v = 0; v < R; ++v) {
+        for (int64_t i = 0; i < n; ++i) rv[i] = r[i * R + v];
+        double complex m;
+        /* n = 0 */
+        for (int64_t i = 0; i < n; ++i) t0[i] = rv[i];
+        m = orc_dot(n, rv, t0);
+        mu_re[(int64_t)v * M + 0] = creal(m); mu_im[(int64_t)v * M + 0] = cimag(m);
+        if (M == 1) continue;
+        /* n = 1 */
+        orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t0, t1);
+        m = orc_dot(n, rv, t1);
+        mu_re[(int64_t)v * M + 1] = creal(m); mu_im[(int64_t)v * M + 1] = cimag(m);
+        /* n >= 2 */
+        for (int32_t k = 2; k < M; ++k) {
+            orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t1, t2);
+            for (int64_t i = 0; i < n; ++i) t2[i] = 2.0 * t2[i] - t0[i];
+            m = orc_dot(n, rv, t2);
+            mu_re[(int64_t)v * M + k] = creal(m); mu_im[(int64_t)v * M + k] = cimag(m);
+            double complex *tmp = t0; t0 = t1; t1 = t2; t2 = tmp;
+        }
+    }
+    free(rv); free(t0); free(t1); free(t2);
+    return 0;
+}
+
+/* Jackson damping factors g_n, n = 0..M-1, for an expansion of M moments. */
+void orc_jackson(int32_t M, double *g)
+{
+    double q = ORC_PI / (M + 1.0);
+    for (int32_t k = 0; k < M; ++k)
+        g[k] = ((M - k + 1.0) * cos(q * k) + sin(q * k) * cos(q) / sin(q)) / (M + 1.0);
+}
+
+/*
+ * DOS of Eq. (4) from moments mu (already averaged over random vectors):
+ *   rho(E) = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(x)] / (a pi sqrt(1 - x^2)),
+ *   x = (E - b)/a,  rho = 0 for |x| >= 1.
+ * The result is in states per energy unit for the whole system (it integrates
+ * to mu_0); the spin and volume factor 2/Omega of Eq. (4) is left to callers.
+ * kernel = 0: Jackson damping; kernel = 1: no damping (g_n = 1).
+ */
+int orc_kpm_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
+                const double *E, int32_t nE, double *rho)
+{
+    if (M < 1 || !(a > 0.0) || (kernel != 0 && kernel != 1)) return -1;
+    double *g = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!g) return -2;
+    if (kernel == 0) orc_jackson(M, g);
+    else for (int32_t k = 0; k < M; ++k) g[k] = 1.0;
+    for (int32_t e = 0; e < nE; ++e) {
+        double x = (E[e] - b) / a;
+        if (!(fabs(x) < 1.0)) { rho[e] = 0.0; continue; }
+        double s = g[0] * mu[0];
+        double tm = 1.0, tn = x;      /* T_0(x), T_1(x) */
+        for (int32_t k = 1; k < M; ++k) {
+            s += 2.0 * g[k] * mu[k] * tn;
+            double tp = 2.0 * x * tn - tm;
+            tm = tn; tn = tp;
+        }
+        rho[e] = s / (a * ORC_PI * sqrt(1.0 - x * x));
+    }
+    free(g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Learned hoppings: descriptor of Eq. (2), per-bond MLP, AdamW.              */
+/* ------------------------------------------------------------------------- */
+
+/* Smooth cutoff f_c(r) = (1 + cos(pi r / rc)) / 2 for r < rc, else 0. */
+static double orc_fc(double r, double rc)
+{
+    return r < rc ? 0.5 * (1.0 + cos(ORC_PI * r / rc)) : 0.0;
+}
+
+/* Chebyshev radial functions f_k(r) = (T_k(2 (r/rc - 1)^2 - 1) + 1) / 2 * f_c(r),
+ * k = 0..nk-1, with T_k evaluated by its three-term recurrence. */
+void orc_radial(double r, double rc, int32_t nk, double *f)
+{
+    double u = r / rc - 1.0;
+    double x = 2.0 * u * u - 1.0;
+    double c = orc_fc(r, rc);
+    double tm = 1.0, tn = x;
+    for (int32_t k = 0; k < nk; ++k) {
+        double tk;
+        if (k == 0) tk = 1.0;
+        else if (k == 1) tk = x;
+        else { double tp = 2.0 * x * tn - tm; tm = tn; tn = tp; tk = tp; }
+        f[k] = 0.5 * (tk + 1.0) * c;
+    }
+}
+
+/* Node feature v_i = sum_{j in N(i)} f(r_ij) (Eq. (2) with the identity c_nk),
+ * from the pair list of a descriptor cutoff: v [n][nk]. */
+void orc_descriptor(int64_t n, int64_t npairs, const int32_t *pi, const int32_t *pj,
+                    const double *dist, double rc, int32_t nk, double *v)
+{
+    double f[64];
+    for (int64_t i = 0; i < n * nk; ++i) v[i] = 0.0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        orc_radial(dist[p], rc, nk, f);
+        for (int32_t k = 0; k < nk; ++k) { v[(int64_t)pi[p] * nk + k] += f[k]; v[(int64_t)pj[p] * nk + k] += f[k]; }
+    }
+}
+
+/* Round a double to the nearest bfloat16 value (ties to even), returned as a
+ * double.  bfloat16 keeps 8 significand bits and the FP32 exponent range. */
+double orc_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    double m = frexp(x, &e);            /* x = m 2^e, 0.5 <= |m| < 1 */
+    if (e < -125) {                     /* subnormal range of FP32 */
+        double q = ldexp(1.0, -133);    /* spacing of bfloat16 subnormals */
+        return nearbyint(x / q) * q;
+    }
+    double s = ldexp(m, 8);             /* 8 significand bits */
+    return ldexp(nearbyint(s), e - 8);  /* default rounding: nearest, ties to even */
+}
+
+/*
+ * Per-bond MLP  x (16) -> 32 -> tanh -> 32 -> tanh -> 1, applied to B rows of X
+ * [B][16] (already normalised).  Parameters, packed in this order:
+ *   W1 [32][16], b1 [32], W2 [32][32], b2 [32], W3 [32], b3 [1]   (1633 values).
+ * bf16 != 0: every multiply's two operands are rounded to bfloat16 (RNE) first
+ * (weights and activations of the three matrix products), accumulation is FP64.
+ * Outputs y [B]; when h1/h2 are non-NULL the post-tanh activations [B][32] are
+ * stored for the backward pass.
+ */
+#define ORC_NI 16
+#define ORC_NH 32
+static double orc_rnd(double x, int bf16) { return bf16 ? orc_bf16(x) : x; }
+
+void orc_mlp_forward(int64_t B, const double *X, const double *prm, int32_t bf16,
+                     double *y, double *h1, double *h2)
+{
+    const double *W1 = prm, *b1 = W1 + ORC_NH * ORC_NI, *W2 = b1 + ORC_NH;
+    const double *b2 = W2 + ORC_NH * ORC_NH, *W3 = b2 + ORC_NH, *b3 = W3 + ORC_NH;
+    double a1[ORC_NH], a2[ORC_NH];
+    for (int64_t e = 0; e < B; ++e) {
+        const double *x = X + e * ORC_NI;
+        for (int h = 0; h < ORC_NH; ++h) {
+            double s = 0.0;
+            for (int k = 0; k < ORC_NI; ++k) s += orc_rnd(W1[h * ORC_NI + k], bf16) * orc_rnd(x[k], bf16);
+            a1[h] = tanh(s + b1[h]);
+        }
+        for (int h = 0; h < ORC_NH; ++h) {
+            double s = 0.0;
+            for (int k = 0; k < ORC_NH; ++k) s += orc_rnd(W2[h * ORC_NH + k], bf16) * orc_rnd(a1[k], bf16);
+            a2[h] = tanh(s + b2[h]);
+        }
+        double s = 0.0;
+        for (int k = 0; k < ORC_NH; ++k) s += orc_rnd(W3[k], bf16) * orc_rnd(a2[k], bf16);
+        y[e] = s + b3[0];
+        if (h1) for (int h = 0; h < ORC_NH; ++h) h1[e * ORC_NH + h] = a1[h];
+        if (h2) for (int h = 0; h < ORC_NH; ++h) h2[e * ORC_NH + h] = a2[h];
+    }
+}
+
+/*
+ * Loss L = (1/B) sum_e w_e (y_e - y*_e)^2 and its gradient with respect to the
+ * packed parameters (same layout as orc_mlp_forward), by the chain rule through
+ * the three layers.  The backward products use the same bf16 operand rounding
+ * as the forward ones when bf16 != 0: in dL/dW3 and dL/dW2, dL/dW1 both factors;
+ * in the propagated deltas (delta2 = (W3 dy) * (1 - h2^2), delta1 = (W2^T delta2)
+ * * (1 - h1^2)) the weight and the incoming delta.  `w` may be NULL (all ones).
+ * Returns the loss.
+ */
+double orc_mlp_loss_grad(int64_t B, const double *X, const double *target,
+                         const double *w, const double *prm, int32_t bf16, double *grad)
+{
+    const double *W1 = prm, *W2 = W1 + ORC_NH * ORC_NI + ORC_NH;
+    const double *W3 = W2 + ORC_NH * ORC_NH + ORC_NH;
+    double *gW1 = grad, *gb1 = gW1 + ORC_NH * ORC_NI, *gW2 = gb1 + ORC_NH;
+    double *gb2 = gW2 + ORC_NH * ORC_NH, *gW3 = gb2 + ORC_NH, *gb3 = gW3 + ORC_NH;
+    for (int i = 0; i < 1633; ++i) grad[i] = 0.0;
+    double h1[ORC_NH], h2[ORC_NH], d1[ORC_NH], d2[ORC_NH], y;
+    double loss = 0.0;
+    for (int64_t e = 0; e < B; ++e) {
+        const double *x = X + e * ORC_NI;
+        orc_mlp_forward(1, x, prm, bf16, &y, h1, h2);
+        double we = w ? w[e] : 1.0;
+        double diff = y - target[e];
+        loss += we * diff * diff;
+        double dy = 2.0 * we * diff / (double)B;
+        /* output layer */
+        gb3[0] += dy;
+        for (int k = 0; k < ORC_NH; ++k) gW3[k] += orc_rnd(dy, bf16) * orc_rnd(h2[k], bf16);
+        for (int k = 0; k < ORC_NH; ++k) d2[k] = orc_rnd(W3[k], bf16) * orc_rnd(dy, bf16) * (1.0 - h2[k] * h2[k]);
+        /* second hidden layer */
+        for (int h = 0; h < ORC_NH; ++h) {
+            gb2[h] += d2[h];
+            for (int k = 0; k < ORC_NH; ++k) gW2[h * ORC_NH + k] += orc_rnd(d2[h], bf16) * orc_rnd(h1[k], bf16);
+        }
+        for (int k = 0; k < ORC_NH; ++k) {
+            double s = 0.0;
+            for (int h = 0; h < ORC_NH; ++h) s += orc_rnd(W2[h * ORC_NH + k], bf16) * orc_rnd(d2[h], bf16);
+            d1[k] = s * (1.0 - h1[k] * h1[k]);
+        }
+        /* first hidden layer */
+        for (int h = 0; h < ORC_NH; ++h) {
+            gb1[h] += d1[h];
+            for (int k = 0; k < ORC_NI; ++k) gW1[h * ORC_NI + k] += orc_rnd(d1[h], bf16) * orc_rnd(x[k], bf16);
+        }
+    }
+    return loss / (double)B;
+}
+
+/*
+ * One AdamW step (Loshchilov & Hutter, decoupled weight decay) on n parameters:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr * ( (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps) + wd * p ),
+ * with t the 1-based step count after this update.
+ */
+void orc_adamw_step(int64_t n, double *p, const double *g, double *m, double *v,
+                    int64_t t, double lr, double beta1, double beta2, double eps, double wd)
+{
+    double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+        double mh = m[i] / c1, vh = v[i] / c2;
+        p[i] -= lr * (mh / (sqrt(vh) + eps) + wd * p[i]);
+    }
+}
+
+/*
+ * Per-bond MLP input of the learned model: for pair p = {i, j},
+ *   x_p = [f_0..f_{nk-1}(r_ij) || v_i + v_j]      (2 nk values, symmetric in i, j)
+ * followed by the fixed standardisation x <- (x - shift) / scale per feature.
+ * X is [npairs][2 nk].
+ */
+void orc_bond_features(int64_t npairs, const int32_t *pi, const int32_t *pj,
+                       const double *dist, const double *v, double rc, int32_t nk,
+                       const double *shift, const double *scale, double *X)
+{
+    double f[64];
+    for (int64_t p = 0; p < npairs; ++p) {
+        double *x = X + p * 2 * nk;
+        orc_radial(dist[p], rc, nk, f);
+        for (int32_t k = 0; k < nk; ++k) x[k] = f[k];
+        for (int32_t k = 0; k < nk; ++k) x[nk + k] = v[(int64_t)pi[p] * nk + k] + v[(int64_t)pj[p] * nk + k];
+        for (int32_t k = 0; k < 2 * nk; ++k) x[k] = (x[k] - shift[k]) / scale[k];
+    }
+}
+
+/*
+ * Synthetic "true" hopping factor of the learned-hopping workload: the plain
+ * distance formula times a coordination correction
+ *   s_p = 1 + kappa (z_i + z_j - 2 z0),   z_i = sum_{j: r_ij < rc} f_c(r_ij),
+ * where z is the zeroth radial descriptor component v_{i,0}.
+ */
+void orc_target_scale(int64_t npairs, const int32_t *pi, const int32_t *pj,
+                      const double *v, int32_t nk, double kappa, double z0, double *s)
+{
+    for (int64_t p = 0; p < npairs; ++p)
+        s[p] = 1.0 + kappa * (v[(int64_t)pi[p] * nk] + v[(int64_t)pj[p] * nk] - 2.0 * z0);
+}

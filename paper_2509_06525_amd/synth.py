@@ -1,0 +1,167 @@
+"""Seeded synthetic inputs: graphene-family structures and random-phase vectors.
+
+This module only generates inputs (coordinates, species, model parameter
+tables, random phases).  It contains none of the method's arithmetic and is the
+one module that both the HIP path's callers and the oracle's callers use.
+
+The paper's structures come from NEP molecular dynamics and DFT data that are
+not available; thermally displaced sheets are modelled here by independent
+Gaussian displacements of every coordinate of a periodic rectangular sheet.
+
+Sheet geometry: rectangular 4-atom cells of graphene (C-C bond a = 1.42 A),
+cell 3a x sqrt(3)a, zigzag direction along y.  Atoms are numbered cell-major:
+index = 4 * (cy * nx + cx) + basis.  Sublattice A = basis {0, 2}, B = {1, 3}.
+"""
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+A_CC = 1.42                                   # C-C bond length (A)
+CELL_X = 3.0 * A_CC                           # 4.26 A
+CELL_Y = math.sqrt(3.0) * A_CC                # 2.4595 A
+BASIS = np.array([[0.0, 0.0],
+                  [0.5 * A_CC, 0.5 * CELL_Y],
+                  [1.5 * A_CC, 0.5 * CELL_Y],
+                  [2.0 * A_CC, 0.0]])
+SHEET_LZ = 20.0                               # open (non-periodic) z extent (A)
+
+# Species table of the heterojunction model: 0 = C, 1 = B, 2 = N.
+SPECIES = ("C", "B", "N")
+ONSITE_EV = np.array([0.0, 2.3, -1.9])
+T_PAIR_EV = np.array([[-2.7, -2.2, -2.5],
+                      [-2.2, 0.0, -2.6],
+                      [-2.5, -2.6, 0.0]])
+T_CC_EV = -2.7
+
+# Distance-scaled hopping model: t(r) = t_pair * exp(-BETA (r / R0 - 1)), r < R_HOP.
+R0 = 1.42
+BETA = 3.37
+R_HOP = 2.0
+R_DESC = 4.0        # descriptor cutoff of the learned model
+N_RADIAL = 8        # Chebyshev radial functions per descriptor
+
+
+@dataclass
+class Structure:
+    pos: np.ndarray            # [N][3] float64 (A)
+    species: np.ndarray        # [N] int32
+    box: np.ndarray            # [3] float64 (A)
+    periodic: np.ndarray       # [3] int32
+    onsite: np.ndarray = field(default_factory=lambda: np.array([0.0]))   # [S] eV
+    t_pair: np.ndarray = field(default_factory=lambda: np.array([[T_CC_EV]]))  # [S][S] eV
+    nx: int = 0
+    ny: int = 0
+    sigma: float = 0.0
+
+    @property
+    def n(self):
+        return int(self.pos.shape[0])
+
+
+def graphene_sheet(nx, ny, sigma=0.0, seed=None):
+    """Periodic nx x ny sheet of 4-atom cells; Gaussian displacements of std sigma (A)."""
+    cx = np.arange(nx, dtype=np.float64)
+    cy = np.arange(ny, dtype=np.float64)
+    n = 4 * nx * ny
+    pos = np.empty((ny, nx, 4, 3), np.float64)
+    pos[..., 0] = cx[None, :, None] * CELL_X + BASIS[None, None, :, 0]
+    pos[..., 1] = cy[:, None, None] * CELL_Y + BASIS[None, None, :, 1]
+    pos[..., 2] = 0.5 * SHEET_LZ
+    pos = pos.reshape(n, 3)
+    if sigma > 0.0:
+        rng = np.random.default_rng(seed)
+        pos += rng.normal(0.0, sigma, size=pos.shape)
+    return Structure(pos=pos, species=np.zeros(n, np.int32),
+                     box=np.array([nx * CELL_X, ny * CELL_Y, SHEET_LZ]),
+                     periodic=np.array([1, 1, 0], np.int32),
+                     onsite=np.array([0.0]), t_pair=np.array([[T_CC_EV]]),
+                     nx=nx, ny=ny, sigma=sigma)
+
+
+def hbn_stripes(nx, ny, stripe_cells=50, sigma=0.0, seed=None):
+    """h-BN/graphene stripes normal to x, each `stripe_cells` cells wide.
+
+    Even stripes are carbon; in odd stripes sublattice A (basis 0, 2) is boron
+    and sublattice B (basis 1, 3) is nitrogen, so B-B and N-N bonds never occur.
+    """
+    s = graphene_sheet(nx, ny, sigma, seed)
+    cx = np.broadcast_to(np.arange(nx)[None, :, None], (ny, nx, 4)).reshape(-1)
+    b = np.broadcast_to(np.arange(4)[None, None, :], (ny, nx, 4)).reshape(-1)
+    bn = (cx // stripe_cells) % 2 == 1
+    sp = np.zeros(s.n, np.int32)
+    sp[bn & ((b == 0) | (b == 2))] = 1
+    sp[bn & ((b == 1) | (b == 3))] = 2
+    s.species = sp
+    s.onsite = ONSITE_EV.copy()
+    s.t_pair = T_PAIR_EV.copy()
+    return s
+
+
+def sheet_dims_for(n_atoms):
+    """Cells (nx, ny) of a near-square sheet with about n_atoms atoms."""
+    nx = max(3, int(round(math.sqrt(n_atoms / (4.0 * math.sqrt(3.0))))))
+    ny = max(3, int(round(math.sqrt(3.0) * nx)))
+    return nx, ny
+
+
+def snapshot_set(count, seed, n_min=1000, n_max=50000, sigma_lo=0.02, sigma_hi=0.08):
+    """`count` thermally displaced sheets, sizes log-uniform on [n_min, n_max]."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=count))
+    sigmas = rng.uniform(sigma_lo, sigma_hi, size=count)
+    seeds = rng.integers(0, 2**62, size=count)
+    out = []
+    for k in range(count):
+        nx, ny = sheet_dims_for(sizes[k])
+        out.append(graphene_sheet(nx, ny, float(sigmas[k]), int(seeds[k])))
+    return out
+
+
+def random_phase(n, R, seed, dtype=np.complex128):
+    """Random-phase vectors r[i, v] = exp(i phi), phi ~ U[0, 2 pi): shape [n][R]."""
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=(n, R))
+    out = np.empty((n, R), dtype)
+    out.real = np.cos(phi)
+    out.imag = np.sin(phi)
+    return out
+
+
+def energy_grid(a, b, n=2001, lo=None, hi=None):
+    """Uniform grid; defaults to [b - 0.99 a, b + 0.99 a]."""
+    if lo is None:
+        lo = b - 0.99 * a
+    if hi is None:
+        hi = b + 0.99 * a
+    return np.linspace(lo, hi, n)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (sizes, seeds and KPM settings).
+# ---------------------------------------------------------------------------
+
+WORKLOADS = {
+    "graphene_pristine_2304": dict(kind="sheet", nx=24, ny=24, sigma=0.0, M=256, R=4,
+                                   fmt="csr_f64", precision="f64", a=9.0, b=0.0,
+                                   e_lo=-8.5, e_hi=8.5, n_e=2001, seed=1000),
+    "graphene_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=3000, R=16,
+                                fmt="ell_f32", precision="c32", seed=1001),
+    "hbn_graphene_stripes_4M": dict(kind="stripes", nx=1000, ny=1000, sigma=0.03, M=2000,
+                                    R=32, fmt="ell_f32", precision="c32", seed=1002),
+    "graphene_snapshots_256": dict(kind="snapshots", count=256, M=1024, R=8,
+                                   fmt="ell_f32", precision="c32", seed=3004,
+                                   train_seed=4004),
+    "graphene_pristine_100M": dict(kind="sheet", nx=5000, ny=5000, sigma=0.0, M=1000, R=1,
+                                   fmt="ell_f32", precision="c32", seed=1004),
+}
+VECTOR_SEED_OFFSET = 1000   # vector seed = structure seed + 1000
+
+
+def make_structure(name):
+    w = WORKLOADS[name]
+    if w["kind"] == "sheet":
+        return graphene_sheet(w["nx"], w["ny"], w["sigma"], w["seed"])
+    if w["kind"] == "stripes":
+        return hbn_stripes(w["nx"], w["ny"], 50, w["sigma"], w["seed"])
+    raise ValueError("use snapshot_set for the snapshot workload")
