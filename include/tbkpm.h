@@ -1,0 +1,198 @@
+/*
+ * tbkpm.h -- C ABI of the MI355X (gfx950) kernel-polynomial DOS library.
+ *
+ * The library computes, on one GPU, the density-of-states step of linear-scaling
+ * quantum transport (paper Sec. 2.4): a sparse orthogonal tight-binding
+ * Hamiltonian (Eq. (1)) assembled from a neighbour list, the Chebyshev
+ * recurrence T_{n+1} = 2 Ht T_n - T_{n-1} with Ht = (H - b)/a, the moments
+ * mu_n = <r|T_n|r> over random-phase vectors r, and the Jackson-damped DOS of
+ * Eq. (4).  The KPM details follow the published kernel polynomial method
+ * (Weisse, Wellein, Alvermann & Fehske, Rev. Mod. Phys. 78, 275 (2006)).
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a tbk_status; TBK_OK is 0.  On an error nothing is
+ *    written to the outputs unless stated, and tbk_last_error() describes it.
+ *    No call aborts, exits or throws across the ABI.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary CPU memory owned by the caller.  The library keeps
+ *    no pointer after a call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ *    on it and return without waiting, except where a host output is written:
+ *    those synchronise `stream` before returning.
+ *  - Builders may allocate temporary device memory (stream-ordered) and free it
+ *    before returning; kpm_moments allocates nothing and uses `work`.
+ *  - Complex vectors are interleaved (re, im) pairs: c128 = 2 x double,
+ *    c64 = 2 x float.  A block of R vectors is stored row-major [rows][R]:
+ *    element (row i, vector v) at index i*R + v.
+ */
+#ifndef TBKPM_H
+#define TBKPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TBK_OK = 0,
+    TBK_ERR_INVALID_ARG = 1,      /* an argument is outside its documented range   */
+    TBK_ERR_BUFFER_TOO_SMALL = 2, /* a caller buffer is smaller than required       */
+    TBK_ERR_NOT_FINITE = 3,       /* NaN/Inf in coordinates or parameters           */
+    TBK_ERR_SPECTRUM = 4,         /* |mu_n| > mu_0: (a, b) does not bound spec(H)   */
+    TBK_ERR_UNSUPPORTED = 5,      /* valid but unsupported (e.g. degree > 64)       */
+    TBK_ERR_DEVICE = 6            /* a HIP call failed; text in tbk_last_error()    */
+} tbk_status;
+
+/* Text of the last error on the calling thread; valid until its next call. */
+const char *tbk_last_error(void);
+
+/* ABI revision of this header (incremented on any incompatible change). */
+#define TBK_ABI_VERSION 1
+int32_t tbk_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Hamiltonian storage                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Storage formats of the off-diagonal part of H (the onsite diagonal is a
+ * separate vector).  SELL = sliced ELLPACK: rows are grouped in slices of
+ * `slice` consecutive rows; slice s stores w_s entries per row (w_s = largest
+ * degree in the slice) column-major: entry k of row i lives at
+ *   ptr[s] + k * slice + (i - s * slice).
+ * Padding entries hold col = own row and value 0. */
+typedef enum {
+    TBK_CSR_F64 = 0,   /* CSR, double values: entries of row i at [ptr[i], ptr[i+1]) */
+    TBK_SELL_F64 = 1,  /* SELL, double values                                          */
+    TBK_SELL_F32 = 2   /* SELL, float values (for the complex-float recurrence)         */
+} tbk_format;
+
+/* Distance-scaled hopping model of Eq. (1):
+ *   t_ij = t_pair[s_i * n_species + s_j] * exp(-beta (r_ij / r0 - 1)),  r_ij < r_cut
+ *   H_ii = onsite[s_i]
+ * onsite and t_pair are host arrays ([n_species], [n_species^2], symmetric). */
+typedef struct {
+    double r_cut;          /* hopping cutoff (A), strict r < r_cut            */
+    double r0;             /* reference bond length (A)                       */
+    double beta;           /* decay exponent                                  */
+    int32_t n_species;     /* S >= 1                                          */
+    int32_t reorder;       /* 1: rows in spatial cell order (perm filled);
+                              0: rows in the caller's atom order              */
+    const double *onsite;  /* host [S] (eV)                                   */
+    const double *t_pair;  /* host [S*S] (eV)                                 */
+} tbk_tb_params;
+
+/* A Hamiltonian in device memory.  tbk_hamiltonian_size fills the size fields;
+ * the caller allocates the device arrays with those sizes and sets the
+ * pointers; tb_build_hamiltonian fills the arrays. */
+typedef struct {
+    int32_t fmt;           /* tbk_format                                        */
+    int32_t slice;         /* SELL slice height (rows), a power of two in
+                              [1, 1024]; ignored for CSR                        */
+    int64_t n_rows;        /* rows = atoms (one orbital per atom)               */
+    int64_t n_ptr;         /* entries of ptr: n_rows+1 (CSR), n_slices+1 (SELL) */
+    int64_t n_entries;     /* stored entries incl. SELL padding                 */
+    int64_t n_bonds;       /* unordered neighbour pairs                         */
+    int32_t max_degree;    /* largest row degree                                */
+    int32_t has_onsite;    /* 1 if some onsite energy is non-zero               */
+    int32_t n_seg;         /* independent systems stacked along the rows (>= 1) */
+    int64_t *ptr;          /* device int64 [n_ptr]                              */
+    int32_t *col;          /* device int32 [n_entries] (row indices of H)       */
+    void *val;             /* device double|float [n_entries]                   */
+    void *onsite;          /* device double|float [n_rows] (same type as val)   */
+    int32_t *perm;         /* device int32 [n_rows]: row -> caller atom index   */
+    int64_t *seg_rows;     /* device int64 [n_seg+1]: rows of system s are
+                              [seg_rows[s], seg_rows[s+1]); may be NULL when
+                              n_seg == 1                                       */
+} tbk_ham;
+
+/*
+ * Size query (neighbour search + degree count on the GPU, Eq. (1)'s N(i)).
+ *   pos     device double [n][3] (A); periodic axes may hold any value, they
+ *           are wrapped; open axes are binned over the coordinates' range.
+ *   species device int32 [n], each in [0, n_species).
+ *   box     host double[3]: periodic lengths (ignored on open axes).
+ *   periodic host int32[3]: 1 = periodic axis.
+ *   h       in: fmt, slice; out: n_rows, n_ptr, n_entries, n_bonds, max_degree,
+ *           has_onsite, n_seg = 1.
+ * Errors: INVALID_ARG (n < 1, n >= 2^31, periodic length < 2 r_cut, species
+ * out of range, bad fmt/slice, r_cut/r0/beta not positive), NOT_FINITE (a
+ * coordinate is NaN/Inf), UNSUPPORTED (degree > 64), DEVICE.
+ * Synchronises `stream`.
+ */
+tbk_status tbk_hamiltonian_size(const double *pos, const int32_t *species, int64_t n,
+                                const double box[3], const int32_t periodic[3],
+                                const tbk_tb_params *p, tbk_ham *h, void *stream);
+
+/*
+ * Builds H (Eq. (1)) into the buffers of `h` (sized by tbk_hamiltonian_size
+ * for the same inputs): columns of each row ascending, both triangles computed
+ * from the same FP64 distance (H is exactly symmetric), onsite[i] = onsite of
+ * the row's species, perm[i] = caller atom of row i.  Writes the row
+ * Gershgorin bounds [E_lo, E_hi] (eV, FP64) to spec_bounds (host).
+ * Errors: as tbk_hamiltonian_size, plus BUFFER_TOO_SMALL when the sizes in `h`
+ * are smaller than what these inputs need, INVALID_ARG for a NULL array.
+ * Synchronises `stream`.
+ */
+tbk_status tb_build_hamiltonian(const double *pos, const int32_t *species, int64_t n,
+                                const double box[3], const int32_t periodic[3],
+                                const tbk_tb_params *p, tbk_ham *h,
+                                double spec_bounds[2], void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev moments                                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef enum {
+    TBK_PREC_F64 = 0,  /* c128 vectors, double H (CSR_F64 or SELL_F64)              */
+    TBK_PREC_C32 = 1   /* c64 vectors, float H (SELL_F32); moments summed in double  */
+} tbk_precision;
+
+/* Bytes of device workspace kpm_moments needs for (h, R, M, precision). */
+tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
+                              int64_t *bytes);
+
+/*
+ * Chebyshev moments of Ht = (H - b)/a over R random vectors:
+ *   T_0 = r, T_1 = Ht r, T_{n+1} = 2 Ht T_n - T_{n-1},
+ *   mu[s][v][n] = Re <r_v|T_n>_s  (n = 0..M-1; the overlap is restricted to the
+ *   rows of system s).
+ * Every step is one pass over H on the GPU with the overlap accumulated in
+ * double inside the same kernel; per-block partial sums are reduced in a fixed
+ * order, so results are bitwise reproducible.
+ *   a, b   host double [n_seg]: scale a > 0 and shift of each system.
+ *   r      device c128|c64 [n_rows][R] in the CALLER's atom order.
+ *   work   device, >= kpm_workspace_size bytes, 256-byte aligned.
+ *   mu     device double [n_seg][R][M].
+ * Errors: INVALID_ARG (R < 1 or R > 64, M < 2, a <= 0, precision/format
+ * mismatch), BUFFER_TOO_SMALL (work_bytes), SPECTRUM (some |mu_n| >
+ * mu_0 (1 + 1e-6): (a, b) does not bound the spectrum; mu is still written),
+ * DEVICE.  Synchronises `stream` (to read the spectrum check).
+ */
+tbk_status kpm_moments(const tbk_ham *h, const double *a, const double *b, const void *r,
+                       int32_t R, int32_t M, int32_t precision, void *work,
+                       int64_t work_bytes, double *mu, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* DOS reconstruction                                                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Jackson-damped DOS of Eq. (4) from moments averaged over vectors:
+ *   rho(E) = [g_0 mu_0 + 2 sum_{n=1}^{M-1} g_n mu_n T_n(x)] / (a pi sqrt(1-x^2)),
+ *   x = (E - b)/a, rho = 0 for |x| >= 1,
+ *   g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))] / (M+1)
+ *   (kernel = 0), or g_n = 1 (kernel = 1, no damping).
+ * rho integrates to mu_0 (states per eV of the whole system); the spin and
+ * volume factor 2/Omega of Eq. (4) is the caller's.
+ *   mu device double [M]; E device double [nE]; rho device double [nE].
+ * Errors: INVALID_ARG (M < 1, a <= 0, nE < 0, kernel not 0/1), DEVICE.
+ */
+tbk_status kpm_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
+                   const double *E, int32_t nE, double *rho, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBKPM_H */

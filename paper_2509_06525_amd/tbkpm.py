@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libtbkpm.so (C ABI in include/tbkpm.h).
+
+Arguments are marshalled from torch tensors (device memory) and Python
+numbers; every step of the computation runs in the library's HIP kernels.
+The binding raises TBKError when the library reports an error and refuses to
+run when the library is not built: there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtbkpm.so")
+
+TBK_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BUFFER_TOO_SMALL", 3: "NOT_FINITE",
+                4: "SPECTRUM", 5: "UNSUPPORTED", 6: "DEVICE"}
+FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2}
+PRECISIONS = {"f64": 0, "c32": 1}
+
+
+class TBKError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+
+
+class TbParams(ctypes.Structure):
+    _fields_ = [("r_cut", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double),
+                ("n_species", ctypes.c_int32), ("reorder", ctypes.c_int32),
+                ("onsite", ctypes.POINTER(ctypes.c_double)),
+                ("t_pair", ctypes.POINTER(ctypes.c_double))]
+
+
+class HamStruct(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("slice", ctypes.c_int32),
+                ("n_rows", ctypes.c_int64), ("n_ptr", ctypes.c_int64),
+                ("n_entries", ctypes.c_int64), ("n_bonds", ctypes.c_int64),
+                ("max_degree", ctypes.c_int32), ("has_onsite", ctypes.c_int32),
+                ("n_seg", ctypes.c_int32),
+                ("ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("onsite", ctypes.c_void_p), ("perm", ctypes.c_void_p),
+                ("seg_rows", ctypes.c_void_p)]
+
+
+_LIB = None
+ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
+               "tb_build_hamiltonian", "kpm_workspace_size", "kpm_moments", "kpm_dos")
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2509_06525_amd/build.py "
+                           "(or __graft_entry__.build()) first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.tbk_last_error.restype = ctypes.c_char_p
+    L.tbk_last_error.argtypes = []
+    L.tbk_abi_version.restype = i32
+    L.tbk_hamiltonian_size.restype = ctypes.c_int
+    L.tbk_hamiltonian_size.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                       ctypes.POINTER(TbParams), ctypes.POINTER(HamStruct), vp]
+    L.tb_build_hamiltonian.restype = ctypes.c_int
+    L.tb_build_hamiltonian.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                       ctypes.POINTER(TbParams), ctypes.POINTER(HamStruct),
+                                       ctypes.POINTER(f64), vp]
+    L.kpm_workspace_size.restype = ctypes.c_int
+    L.kpm_workspace_size.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, ctypes.POINTER(i64)]
+    L.kpm_moments.restype = ctypes.c_int
+    L.kpm_moments.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64), vp,
+                              i32, i32, i32, vp, i64, vp, vp]
+    L.kpm_dos.restype = ctypes.c_int
+    L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
+    _LIB = L
+    return L
+
+
+def _check(status):
+    if status != TBK_OK:
+        raise TBKError(status, lib().tbk_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(t, dtype):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor, got {t.dtype} on {t.device}")
+    return t
+
+
+def _f64arr(x):
+    a = (ctypes.c_double * len(x))(*[float(v) for v in x])
+    return a
+
+
+def _params(onsite, t_pair, r_cut, r0, beta, reorder):
+    onsite = [float(v) for v in onsite]
+    flat = [float(v) for row in t_pair for v in (row if hasattr(row, "__len__") else [row])]
+    S = len(onsite)
+    if len(flat) != S * S:
+        raise ValueError("t_pair must be S x S")
+    on = _f64arr(onsite)
+    tp = _f64arr(flat)
+    p = TbParams(r_cut=r_cut, r0=r0, beta=beta, n_species=S, reorder=int(bool(reorder)),
+                 onsite=ctypes.cast(on, ctypes.POINTER(ctypes.c_double)),
+                 t_pair=ctypes.cast(tp, ctypes.POINTER(ctypes.c_double)))
+    return p, (on, tp)
+
+
+class Hamiltonian:
+    """A Hamiltonian built by tb_build_hamiltonian; owns its device tensors."""
+
+    def __init__(self, st, tensors, bounds):
+        self.st = st
+        self.tensors = tensors
+        self.bounds = bounds
+
+    @property
+    def n_rows(self):
+        return self.st.n_rows
+
+    @property
+    def n_entries(self):
+        return self.st.n_entries
+
+    @property
+    def fmt(self):
+        return self.st.fmt
+
+    @property
+    def perm(self):
+        return self.tensors["perm"]
+
+    def scale(self, margin=1.01):
+        """(a, b) with a = margin (E_hi - E_lo)/2, b = (E_hi + E_lo)/2 from the Gershgorin bounds."""
+        lo, hi = self.bounds
+        return margin * (hi - lo) / 2.0, (hi + lo) / 2.0
+
+    def nbytes(self):
+        return sum(t.numel() * t.element_size() for t in self.tensors.values())
+
+
+def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0=1.42, beta=3.37,
+                      fmt="sell_f32", slice=256, reorder=True, stream=None):
+    """Neighbour list + Eq. (1) assembly on the GPU.  pos: float64 [N,3], species: int32 [N]."""
+    L = lib()
+    pos = _dev(pos, torch.float64)
+    species = _dev(species, torch.int32)
+    n = pos.shape[0]
+    p, keep = _params(onsite, t_pair, r_cut, r0, beta, reorder)
+    boxa = _f64arr(box)
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
+    s = _stream(stream)
+    _check(L.tbk_hamiltonian_size(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p),
+                                  ctypes.byref(st), s))
+    dev = pos.device
+    vdt = torch.float32 if fmt == "sell_f32" else torch.float64
+    t = {
+        "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
+        "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),
+        "val": torch.empty(max(st.n_entries, 1), dtype=vdt, device=dev),
+        "onsite": torch.empty(n, dtype=vdt, device=dev),
+        "perm": torch.empty(n, dtype=torch.int32, device=dev),
+    }
+    st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
+    st.onsite, st.perm = t["onsite"].data_ptr(), t["perm"].data_ptr()
+    bounds = (ctypes.c_double * 2)()
+    _check(L.tb_build_hamiltonian(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p),
+                                  ctypes.byref(st), bounds, s))
+    del keep
+    return Hamiltonian(st, t, (bounds[0], bounds[1]))
+
+
+def workspace_size(H, R, M, precision):
+    out = ctypes.c_int64(0)
+    _check(lib().kpm_workspace_size(ctypes.byref(H.st), int(R), int(M), PRECISIONS[precision],
+                                    ctypes.byref(out)))
+    return out.value
+
+
+def alloc_workspace(H, R, M, precision, device=None):
+    nbytes = workspace_size(H, R, M, precision)
+    dev = device if device is not None else H.tensors["ptr"].device
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+
+def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None):
+    """Chebyshev moments mu[v][n] (float64, device) of Ht = (H - b)/a for vectors r [N, R]."""
+    L = lib()
+    if precision is None:
+        precision = "c32" if r.dtype == torch.complex64 else "f64"
+    want = torch.complex64 if precision == "c32" else torch.complex128
+    r = _dev(r, want)
+    if r.dim() == 1:
+        r = r.reshape(-1, 1)
+    R = r.shape[1]
+    if work is None:
+        work = alloc_workspace(H, R, M, precision, r.device)
+    if mu is None:
+        mu = torch.empty((R, M), dtype=torch.float64, device=r.device)
+    av = (ctypes.c_double * 1)(float(a))
+    bv = (ctypes.c_double * 1)(float(b))
+    _check(L.kpm_moments(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
+                         _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
+    return mu
+
+
+def kpm_dos(mu, a, b, E, kernel=0, stream=None):
+    """Jackson-damped DOS (Eq. (4)) on the energies E (float64 device tensors)."""
+    mu = _dev(mu, torch.float64)
+    E = _dev(E, torch.float64)
+    rho = torch.empty_like(E)
+    _check(lib().kpm_dos(_ptr(mu), mu.numel(), float(a), float(b), int(kernel), _ptr(E), E.numel(),
+                         _ptr(rho), _stream(stream)))
+    return rho

@@ -1,0 +1,53 @@
+"""Helpers shared by the GPU tests: device transfers and decoding of the library's
+Hamiltonian arrays into the caller's atom order (test code only)."""
+import numpy as np
+import torch
+
+from paper_2509_06525_amd import synth, tbkpm
+
+DEV = "cuda:0"
+
+
+def to_dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def build(s, fmt="sell_f64", slice=64, reorder=True, r_cut=synth.R_HOP):
+    return tbkpm.build_hamiltonian(to_dev(s.pos, torch.float64), to_dev(s.species, torch.int32),
+                                   s.box, s.periodic, s.onsite, s.t_pair, r_cut=r_cut,
+                                   r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice, reorder=reorder)
+
+
+def entries_in_atom_order(H):
+    """(rows, cols, vals, onsite) of the stored non-padding entries, mapped back to atom indices."""
+    t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
+    n = H.n_rows
+    C = 1 if H.fmt == tbkpm.FORMATS["csr_f64"] else H.st.slice
+    ptr, col, val, perm = t["ptr"], t["col"], t["val"].astype(np.float64), t["perm"]
+    rows, cols, vals = [], [], []
+    for s in range(ptr.shape[0] - 1):
+        w = (ptr[s + 1] - ptr[s]) // C
+        for lane in range(C):
+            i = s * C + lane
+            if i >= n:
+                break
+            for k in range(w):
+                q = ptr[s] + k * C + lane
+                if col[q] == i and val[q] == 0.0:
+                    continue        # padding
+                rows.append(perm[i]); cols.append(perm[col[q]]); vals.append(val[q])
+    onsite = np.empty(n)
+    onsite[perm] = t["onsite"].astype(np.float64)
+    return np.array(rows), np.array(cols), np.array(vals), onsite
+
+
+def csr_entries(csr):
+    rows = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
+    return rows, csr.col.astype(np.int64), csr.val
+
+
+def rel_l2(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))

@@ -1,0 +1,61 @@
+"""The C-ABI library loads on the host and exports every function include/tbkpm.h declares.
+
+No compute call is made here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2509_06525_amd import tbkpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tbkpm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\*?\s*([A-Za-z_]\w*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tbkpm.LIB_PATH):
+        from paper_2509_06525_amd import build
+        build.build()
+    return tbkpm.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("tb_build_hamiltonian", "kpm_moments", "kpm_dos"):
+        assert required in names
+    assert set(names) == set(tbkpm.ABI_SYMBOLS), names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = ctypes.CDLL(tbkpm.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_version_and_error_text_without_gpu(lib):
+    assert lib.tbk_abi_version() == 1
+    assert lib.tbk_last_error() == b""
+
+
+def test_host_side_validation_without_gpu(lib):
+    """Argument checks run before any device call: a bad R is rejected on the host."""
+    st = tbkpm.HamStruct(fmt=2, slice=256, n_rows=10)
+    out = ctypes.c_int64(0)
+    rc = lib.kpm_workspace_size(ctypes.byref(st), 0, 10, 1, ctypes.byref(out))
+    assert rc == 1
+    assert b"R = 0" in lib.tbk_last_error()
+    rc = lib.kpm_workspace_size(ctypes.byref(st), 4, 10, 0, ctypes.byref(out))   # FP64 on float H
+    assert rc == 1
+    rc = lib.kpm_workspace_size(ctypes.byref(st), 4, 10, 1, ctypes.byref(out))
+    assert rc == 0 and out.value > 3 * 10 * 4 * 8
+    rc = lib.kpm_dos(None, 0, 1.0, 0.0, 0, None, 0, None, None)
+    assert rc == 1
