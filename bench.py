@@ -1,0 +1,226 @@
+"""Benchmark of the KPM density-of-states step on one MI355X.
+
+One step = the whole hot path over one synthetic structure whose coordinates
+and random-phase vectors are already in HBM: neighbour list + Hamiltonian
+assembly + spectral bounds (tb_build_hamiltonian), the Chebyshev recurrence
+with fused moments (kpm_moments) and the Jackson DOS (kpm_dos).
+
+Prints one JSON line.  `value` is N * M * R / (seconds per step) in
+atom*moments/s.  `roofline` rates the recurrence kernel: algorithmic bytes per
+launch (Hamiltonian values, columns and slice offsets once; per vector row one
+gather of T_n, one read of T_{n-1} and of r, one write of T_{n+1}; onsite when
+used) over its average launch time measured with HIP events on the library's
+stream, against the 8 TB/s HBM3E peak.  `cpu_baseline` times the serial FP64
+oracle (one core) on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "KPM atom·moments/s & % HBM peak; DOS err vs FP64 oracle; learned vs plain H"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="graphene_pristine_100M")
+    p.add_argument("--slice", type=int, default=256)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="run one plain device copy of this many MiB first (counter calibration)")
+    p.add_argument("--cpu-sample-cells", type=int, default=1000,
+                   help="oracle sample: an n x n cell sheet of the same kind, same M and R")
+    return p.parse_args()
+
+
+def cheb_step_bytes(H, Rp, elem, diag):
+    """Algorithmic bytes of one recurrence launch (see module docstring)."""
+    st = H.st
+    val_b = 4 if st.fmt == 2 else 8
+    b = st.n_entries * (val_b + 4) + st.n_ptr * 8
+    b += st.n_rows * Rp * 2 * elem * 4          # gather T_n once, read T_{n-1}, read r, write T_{n+1}
+    if diag and st.has_onsite:
+        b += st.n_rows * val_b
+    return b
+
+
+def cpu_baseline(w, cells):
+    """Time the oracle (one core, FP64) on a cells x cells sheet with the workload's M and R."""
+    from oracle import oracle as O
+    from paper_2509_06525_amd import synth
+    sample = dict(w)
+    if w["kind"] == "stripes":
+        s = synth.hbn_stripes(cells, cells, 50, w["sigma"], w["seed"])
+    else:
+        s = synth.graphene_sheet(cells, cells, w.get("sigma", 0.0), w["seed"])
+    R = w["R"]
+    r = synth.random_phase(s.n, R, w["seed"] + synth.VECTOR_SEED_OFFSET)
+    t0 = time.perf_counter()
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    lo, hi = O.gershgorin(csr)
+    a, b = 1.01 * (hi - lo) / 2, (hi + lo) / 2
+    mu, _ = O.kpm_moments(csr, a, b, r, w["M"])
+    E = synth.energy_grid(a, b)
+    O.kpm_dos(mu.mean(0), a, b, E)
+    dt = time.perf_counter() - t0
+    sample = f"{cells}x{cells}-cell sheet, N={s.n}, M={w['M']}, R={R}: full path (pairs, CSR, moments, DOS)"
+    return {"value": s.n * w["M"] * R / dt, "unit": "atom*moments/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "seconds": dt}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; the path's multi-GPU sharding "
+                                   "(halo exchange per step, one moment all-reduce) is design only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2509_06525_amd import synth, tbkpm
+
+    w = dict(synth.WORKLOADS[args.workload])
+    if w["kind"] == "snapshots":
+        raise SystemExit("the snapshot workload is benchmarked by its own batched path")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
+    log(f"generating {args.workload}")
+    s = synth.make_structure(args.workload)
+    N, M, R = s.n, w["M"], w["R"]
+    cdt = np.complex64 if w["precision"] == "c32" else np.complex128
+    r_host = synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, cdt)
+    pos = torch.from_numpy(s.pos).to(dev)
+    sp = torch.from_numpy(s.species).to(dev)
+    r = torch.from_numpy(r_host).to(dev)
+    del r_host
+    fmt = w["fmt"]
+    slice_ = 1 if fmt == "csr_f64" else args.slice
+    fixed_ab = ("a" in w)
+
+    def build():
+        return tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair,
+                                       r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                       fmt=fmt, slice=slice_, stream=stream)
+
+    H = build()
+    a, b = (w["a"], w["b"]) if fixed_ab else H.scale()
+    work = tbkpm.alloc_workspace(H, R, M, w["precision"], dev)
+    mu = torch.empty((R, M), dtype=torch.float64, device=dev)
+    E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
+    if fixed_ab:
+        E = torch.linspace(w["e_lo"], w["e_hi"], w["n_e"], dtype=torch.float64, device=dev)
+    del H
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    kpm_ms = []
+
+    def step():
+        Hs = build()
+        aa, bb = (w["a"], w["b"]) if fixed_ab else Hs.scale()
+        ev[0].record(stream)
+        tbkpm.kpm_moments(Hs, aa, bb, r, M, w["precision"], work=work, mu=mu, stream=stream)
+        ev[1].record(stream)
+        rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream)
+        return Hs, aa, bb, rho
+
+    log(f"N={N} M={M} R={R}: warmup {args.warmup}, timed {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Hs, aa, bb, rho = step()
+        torch.cuda.synchronize()
+        kpm_ms.append(ev[0].elapsed_time(ev[1]))
+    t1 = time.perf_counter()
+    sec_per_step = (t1 - t0) / args.steps
+    value = N * M * R / sec_per_step
+
+    # Roofline of the recurrence kernel: M - 1 launches inside the kpm_moments window.
+    Rp = 1
+    while Rp < R:
+        Rp *= 2
+    elem = 4 if w["precision"] == "c32" else 8
+    diag = Hs.st.has_onsite or bb != 0.0
+    launch_bytes = cheb_step_bytes(Hs, Rp, elem, diag)
+    kpm_med = float(np.median(kpm_ms))
+    launch_s = kpm_med * 1e-3 / (M - 1)
+    achieved = launch_bytes / launch_s / 1e9
+    mu_c = mu.cpu().numpy().copy()
+    rho_c = rho.cpu().numpy()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "atom*moments/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if w["precision"] == "c32" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": N, "moments": M, "vectors": R,
+                   "format": fmt, "slice": slice_, "precision": w["precision"],
+                   "a_eV": aa, "b_eV": bb},
+        "kpm_ms_median": kpm_med,
+        "kpm_atom_moments_per_s": N * M * R / (kpm_med * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cheb_step", "bytes_per_launch": launch_bytes,
+                     "launch_us": launch_s * 1e6},
+    }
+
+    # FP64 GPU path on the same structure and vectors (reported beside the C32 path).
+    log(f"timed: {sec_per_step * 1e3:.1f} ms/step, kpm {kpm_med:.1f} ms")
+    if not args.no_fp64 and w["precision"] == "c32":
+        H64 = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP,
+                                      r0=synth.R0, beta=synth.BETA, fmt="sell_f64", slice=slice_,
+                                      stream=stream)
+        del Hs
+        r64 = r.to(torch.complex128)
+        work = None
+        torch.cuda.empty_cache()
+        w64 = tbkpm.alloc_workspace(H64, R, M, "f64", dev)
+        mu64 = torch.empty((R, M), dtype=torch.float64, device=dev)
+        ev[2].record(stream)
+        tbkpm.kpm_moments(H64, aa, bb, r64, M, "f64", work=w64, mu=mu64, stream=stream)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        ms64 = ev[2].elapsed_time(ev[3])
+        rho64 = tbkpm.kpm_dos(mu64.mean(0).contiguous(), aa, bb, E, stream=stream).cpu().numpy()
+        out["fp64_path"] = {"kpm_ms": ms64, "atom_moments_per_s": N * M * R / (ms64 * 1e-3),
+                            "dos_relL2_c32_vs_fp64": float(np.linalg.norm(rho_c - rho64) / np.linalg.norm(rho64)),
+                            "max_abs_dmu_over_N": float(np.abs(mu_c - mu64.cpu().numpy()).max() / N)}
+        del H64, w64, r64
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one core)")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cells)
+        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        out["cpu_baseline"]["nproc"] = os.cpu_count()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -40,7 +40,7 @@ typedef enum {
     TBK_ERR_BUFFER_TOO_SMALL = 2, /* a caller buffer is smaller than required       */
     TBK_ERR_NOT_FINITE = 3,       /* NaN/Inf in coordinates or parameters           */
     TBK_ERR_SPECTRUM = 4,         /* |mu_n| > mu_0: (a, b) does not bound spec(H)   */
-    TBK_ERR_UNSUPPORTED = 5,      /* valid but unsupported (e.g. degree > 64)       */
+    TBK_ERR_UNSUPPORTED = 5,      /* valid but unsupported (e.g. degree > 256)      */
     TBK_ERR_DEVICE = 6            /* a HIP call failed; text in tbk_last_error()    */
 } tbk_status;
 
@@ -117,7 +117,7 @@ typedef struct {
  *           has_onsite, n_seg = 1.
  * Errors: INVALID_ARG (n < 1, n >= 2^31, periodic length < 2 r_cut, species
  * out of range, bad fmt/slice, r_cut/r0/beta not positive), NOT_FINITE (a
- * coordinate is NaN/Inf), UNSUPPORTED (degree > 64), DEVICE.
+ * coordinate is NaN/Inf), UNSUPPORTED (degree > 256), DEVICE.
  * Synchronises `stream`.
  */
 tbk_status tbk_hamiltonian_size(const double *pos, const int32_t *species, int64_t n,
@@ -148,9 +148,26 @@ typedef enum {
     TBK_PREC_C32 = 1   /* c64 vectors, float H (SELL_F32); moments summed in double  */
 } tbk_precision;
 
-/* Bytes of device workspace kpm_moments needs for (h, R, M, precision). */
+/* Launch shape of the recurrence kernel.  Every shape computes bitwise the
+ * same vectors T_n; the moments differ only in the order in which per-block
+ * double partial sums are added (a few ulp); the shape sets the speed.  A tile is 256/L rows with
+ * L = R_pad / vectors_per_thread threads per row (R_pad = R rounded up to a
+ * power of two). */
+typedef struct {
+    int32_t vectors_per_thread; /* 1, or 2 (C32 only, R >= 2): vectors per thread  */
+    int32_t tiles_per_block;    /* >= 1: consecutive tiles one workgroup handles    */
+    int32_t nontemporal;        /* 1: streamed arrays use non-temporal loads/stores */
+    int32_t xcd_remap;          /* 1: each XCD sweeps a contiguous eighth of rows   */
+    int32_t rows_per_thread;    /* 1 or 2: rows (from consecutive tiles) a thread
+                                   advances together                               */
+} tbk_kpm_config;
+
+/* Bytes of device workspace kpm_moments needs for (h, R, M, precision) with the
+ * default launch shape (kpm_workspace_size) or a given one (cfg may be NULL). */
 tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
                               int64_t *bytes);
+tbk_status kpm_workspace_size_config(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
+                                     const tbk_kpm_config *cfg, int64_t *bytes);
 
 /*
  * Chebyshev moments of Ht = (H - b)/a over R random vectors:
@@ -159,7 +176,7 @@ tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t pr
  *   rows of system s).
  * Every step is one pass over H on the GPU with the overlap accumulated in
  * double inside the same kernel; per-block partial sums are reduced in a fixed
- * order, so results are bitwise reproducible.
+ * order, so results are bitwise reproducible for a given launch shape.
  *   a, b   host double [n_seg]: scale a > 0 and shift of each system.
  *   r      device c128|c64 [n_rows][R] in the CALLER's atom order.
  *   work   device, >= kpm_workspace_size bytes, 256-byte aligned.
@@ -172,6 +189,13 @@ tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t pr
 tbk_status kpm_moments(const tbk_ham *h, const double *a, const double *b, const void *r,
                        int32_t R, int32_t M, int32_t precision, void *work,
                        int64_t work_bytes, double *mu, void *stream);
+
+/* kpm_moments with an explicit launch shape (cfg may be NULL = default); the
+ * workspace must be sized by kpm_workspace_size_config for the same cfg.
+ * Extra errors: INVALID_ARG for a shape outside the ranges of tbk_kpm_config. */
+tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b, const void *r,
+                              int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                              void *work, int64_t work_bytes, double *mu, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* DOS reconstruction                                                        */

@@ -1,84 +1,108 @@
 // Chebyshev recurrence with fused moment accumulation (KPM, Sec. 2.4).
 //
-// One launch per recurrence step: every thread owns one row and VPT of the R
-// vectors (L = R / VPT threads per row), gathers T_n over the row's stored
-// entries, writes T_{n+1} = c1 (H - b) T_n - c0 T_{n-1} over T_{n-1} in place,
-// and accumulates Re(conj(r) T_{n+1}) in double.  A block reduces its rows by
-// wavefront shuffles and LDS and writes one partial per vector; a final kernel
-// sums the partials in a fixed order (bitwise reproducible, no atomics).
+// One launch per recurrence step.  A tile is 256 / L consecutive rows; every
+// thread owns one row of the tile and VPT of the R vectors (L = R / VPT threads
+// per row).  The thread gathers T_n over the row's stored entries, writes
+// T_{n+1} = c1 (H - b) T_n - c0 T_{n-1} over T_{n-1} in place, and accumulates
+// Re(conj(r) T_{n+1}) in double.  A block handles `tiles_per_block`
+// consecutive tiles, reduces its rows by wavefront shuffles and LDS and writes
+// one partial per vector; every few steps a reduction kernel folds the block
+// partials in a fixed two-level order (bitwise reproducible, no float atomics).
 //
-// Tiles of 256 / L rows are mapped XCD-aware: workgroup b runs on XCD b % 8,
-// XCD x owns the x-th contiguous eighth of the tiles, and its workgroups sweep
-// that range round-robin so neighbouring rows are gathered from one L2.
+// Launch shapes (tuned per problem): with xcd_remap, workgroup b (which the
+// hardware dispatches to XCD b % 8) takes logical block (b % 8) G/8 + b / 8,
+// so each XCD sweeps its own contiguous eighth of the rows; otherwise blocks
+// take tiles in dispatch order.  With nontemporal, the streamed arrays
+// (values, columns, T_{n-1}, r, T_{n+1}) bypass cache retention so that the
+// L2 keeps the gathered T_n.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
+#include "kpm.hpp"
 
 namespace tbk {
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxGrid = 2048;
+constexpr int kReduceChunk = 2048;                 // partials per first-level reduction block
+constexpr size_t kPartialBudget = 256ull << 20;    // bytes of block partials kept between reductions
 
-template <class VT> struct C2;
-template <> struct C2<float> { using T = float2; };
-template <> struct C2<double> { using T = double2; };
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <bool NT, class T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT, class T>
+__device__ __forceinline__ void st(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // VPT consecutive complex values of one row.
 template <class VT, int VPT> struct Pack {
     VT re[VPT], im[VPT];
 };
 
-template <class VT, int VPT>
+template <bool NT, class VT, int VPT>
 __device__ __forceinline__ Pack<VT, VPT> load_pack(const VT *p) {
     Pack<VT, VPT> o;
     if constexpr (sizeof(VT) == 4 && VPT == 2) {
-        float4 v = *reinterpret_cast<const float4 *>(p);
+        f4v v = ld<NT>(reinterpret_cast<const f4v *>(p));
         o.re[0] = v.x; o.im[0] = v.y; o.re[1] = v.z; o.im[1] = v.w;
     } else if constexpr (sizeof(VT) == 4 && VPT == 1) {
-        float2 v = *reinterpret_cast<const float2 *>(p);
+        f2v v = ld<NT>(reinterpret_cast<const f2v *>(p));
         o.re[0] = v.x; o.im[0] = v.y;
     } else {
         static_assert(VPT == 1, "double packs hold one complex value");
-        double2 v = *reinterpret_cast<const double2 *>(p);
+        d2v v = ld<NT>(reinterpret_cast<const d2v *>(p));
         o.re[0] = v.x; o.im[0] = v.y;
     }
     return o;
 }
 
-template <class VT, int VPT>
+template <bool NT, class VT, int VPT>
 __device__ __forceinline__ void store_pack(VT *p, const Pack<VT, VPT> &o) {
     if constexpr (sizeof(VT) == 4 && VPT == 2) {
-        *reinterpret_cast<float4 *>(p) = make_float4(o.re[0], o.im[0], o.re[1], o.im[1]);
+        f4v v = {o.re[0], o.im[0], o.re[1], o.im[1]};
+        st<NT>(reinterpret_cast<f4v *>(p), v);
     } else if constexpr (sizeof(VT) == 4 && VPT == 1) {
-        *reinterpret_cast<float2 *>(p) = make_float2(o.re[0], o.im[0]);
+        f2v v = {o.re[0], o.im[0]};
+        st<NT>(reinterpret_cast<f2v *>(p), v);
     } else {
-        *reinterpret_cast<double2 *>(p) = make_double2(o.re[0], o.im[0]);
+        d2v v = {o.re[0], o.im[0]};
+        st<NT>(reinterpret_cast<d2v *>(p), v);
     }
 }
 
-template <class VT> struct StepArgs {
-    const int64_t *ptr;      // slice offsets (slice height 1 = CSR)
-    const int32_t *col;
-    const VT *val;
-    const VT *onsite;        // used when diag != 0
+// Per-launch scalars of a step (pointers go as separate restrict parameters).
+template <class VT> struct StepScalars {
     int64_t n_rows;
+    int64_t n_tiles;
     int32_t log2_slice;
     int32_t Rp;              // padded vector count = L * VPT
-    const VT *tcur;          // T_n        [rows][Rp] complex
-    const VT *tprev;         // T_{n-1}    (unused on the first step)
-    VT *tnext;               // T_{n+1}    (may alias tprev)
-    const VT *r;             // start vectors
+    int32_t tiles_per_block;
+    int32_t xcd_remap;
     VT c1;                   // 2/a (1/a on the first step)
     VT shift;                // b
-    double *partial;         // [gridDim.x][Rp] for this moment
 };
 
+__device__ __forceinline__ int64_t logical_block(int xcd_remap) {
+    const int64_t b = blockIdx.x, G = gridDim.x;
+    if (xcd_remap && (G % kNumXcd) == 0) return (b % kNumXcd) * (G / kNumXcd) + b / kNumXcd;
+    return b;
+}
+
 // Block reduction of acc[VPT] over rows sharing a vector slot; writes
-// partial[block][slot * VPT + q].
+// partial[lb][slot * VPT + q].
 template <int L, int VPT>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[VPT], double *partial) {
+__device__ __forceinline__ void block_reduce_store(double (&acc)[VPT], double *partial, int64_t lb) {
     __shared__ double red[kThreads / 64][64 * VPT];
 #pragma unroll
     for (int q = 0; q < VPT; ++q) {
@@ -95,75 +119,151 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[VPT], double *p
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
-        partial[(int64_t)blockIdx.x * (L * VPT) + threadIdx.x] = s;
+        partial[lb * (L * VPT) + threadIdx.x] = s;
     }
 }
 
-template <class VT, int L, int VPT, bool FIRST, bool DIAG>
-__global__ __launch_bounds__(kThreads) void k_cheb_step(StepArgs<VT> a) {
+// One recurrence step.  Each thread handles RPT rows (from RPT consecutive
+// tiles of its block).  All loads of a row group are issued before any is
+// used: the streamed operands, then the row's entries (KU at a time, or all W
+// of them when every slice has the same width W), then the gathers of T_n, so
+// a row costs two dependent memory round trips instead of one per entry.
+// Rows past the end are clamped to the last row for their loads (always in
+// bounds) and neither stored nor counted; entries past a slice's width are
+// clamped to its last entry and weighted by zero.
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int RPT, int W>
+__global__ __launch_bounds__(kThreads) void k_cheb_step(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, const VT *__restrict__ val,
+    const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
+    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a) {
     constexpr int RPB = kThreads / L;   // rows per tile
+    constexpr int KU = W > 0 ? W : 4;   // entries per batch of loads
     const int lr = threadIdx.x / L;
     const int vs = threadIdx.x % L;
-    const int64_t n_tiles = (a.n_rows + RPB - 1) / RPB;
-    const int xcd = blockIdx.x % kNumXcd;
-    const int nbx = gridDim.x / kNumXcd;
-    const int jb = blockIdx.x / kNumXcd;
-    const int64_t t0 = n_tiles * xcd / kNumXcd, t1 = n_tiles * (xcd + 1) / kNumXcd;
+    const int64_t lb = logical_block(a.xcd_remap);
+    const int64_t t0 = lb * a.tiles_per_block;
+    const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
     const int64_t smask = ((int64_t)1 << a.log2_slice) - 1;
+    const int64_t stride = smask + 1;
     const int Rp = a.Rp;
     const int voff = vs * VPT;
+    const int64_t last = a.n_rows - 1;
 
     double acc[VPT];
 #pragma unroll
     for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
 
-    for (int64_t t = t0 + jb; t < t1; t += nbx) {
-        const int64_t i = t * RPB + lr;
-        if (i >= a.n_rows) continue;
-        const int64_t s = i >> a.log2_slice;
-        const int64_t p0 = a.ptr[s], p1 = a.ptr[s + 1];
-        const int64_t base = p0 + (i & smask);
-        const int w = (int)((p1 - p0) >> a.log2_slice);
-        const int64_t stride = smask + 1;
-        Pack<VT, VPT> y;
+    for (int64_t t = t0; t < t1; t += RPT) {
+        int64_t i[RPT], base[RPT], off[RPT];
+        int w[RPT];
+        bool ok[RPT];
 #pragma unroll
-        for (int q = 0; q < VPT; ++q) { y.re[q] = 0; y.im[q] = 0; }
-        for (int k = 0; k < w; ++k) {
-            const int32_t c = a.col[base + k * stride];
-            const VT h = a.val[base + k * stride];
-            Pack<VT, VPT> x = load_pack<VT, VPT>(a.tcur + 2 * ((int64_t)c * Rp + voff));
-#pragma unroll
-            for (int q = 0; q < VPT; ++q) { y.re[q] += h * x.re[q]; y.im[q] += h * x.im[q]; }
+        for (int u = 0; u < RPT; ++u) {
+            const int64_t tu = min(t + u, t1 - 1);
+            const int64_t iu = (t + u) * RPB + lr;
+            ok[u] = (t + u < t1) && (iu <= last);
+            i[u] = min(tu * RPB + lr, last);
+            off[u] = 2 * (i[u] * Rp + voff);
+            int64_t p0, p1;
+            if constexpr (TIS) {            // the tile is one slice: block-uniform offsets
+                p0 = ptr[tu];
+                p1 = ptr[tu + 1];
+                base[u] = p0 + (i[u] & smask);
+            } else {
+                const int64_t sl = i[u] >> a.log2_slice;
+                p0 = ptr[sl];
+                p1 = ptr[sl + 1];
+                base[u] = p0 + (i[u] & smask);
+            }
+            w[u] = W > 0 ? W : (int)((p1 - p0) >> a.log2_slice);
         }
-        if constexpr (DIAG) {
-            const VT d = (a.onsite ? a.onsite[i] : (VT)0) - a.shift;
-            Pack<VT, VPT> x = load_pack<VT, VPT>(a.tcur + 2 * (i * Rp + voff));
+        // streamed operands first: they do not depend on the entries
+        Pack<VT, VPT> pv[RPT], rv[RPT];
+        VT dg[RPT];
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) { y.re[q] += d * x.re[q]; y.im[q] += d * x.im[q]; }
+        for (int u = 0; u < RPT; ++u) {
+            if constexpr (!FIRST) pv[u] = load_pack<NT, VT, VPT>(tprev + off[u]);
+            rv[u] = load_pack<NT, VT, VPT>(r + off[u]);
+            if constexpr (DIAG) dg[u] = (onsite ? ld<NT>(onsite + i[u]) : (VT)0) - a.shift;
         }
-        const int64_t off = 2 * (i * Rp + voff);
-        Pack<VT, VPT> o;
-        if constexpr (FIRST) {
+        Pack<VT, VPT> y[RPT];
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) { o.re[q] = a.c1 * y.re[q]; o.im[q] = a.c1 * y.im[q]; }
-        } else {
-            Pack<VT, VPT> pv = load_pack<VT, VPT>(a.tprev + off);
+        for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) { y[u].re[q] = 0; y[u].im[q] = 0; }
+        int wmax = 0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) wmax = max(wmax, w[u]);
+        for (int k0 = 0; k0 < wmax; k0 += KU) {
+            int32_t c[RPT][KU];
+            VT h[RPT][KU];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u)
+#pragma unroll
+                for (int k = 0; k < KU; ++k) {
+                    if constexpr (W > 0) {
+                        c[u][k] = ld<NT>(col + base[u] + k * stride);
+                        h[u][k] = ld<NT>(val + base[u] + k * stride);
+                    } else {
+                        // w[u] >= 1 here unless the whole slice is empty; then read the
+                        // row's own diagonal position (entry 0 of a neighbouring slice
+                        // is never read: kk is clamped below 0 -> use the row itself).
+                        const int kk = min(k0 + k, w[u] - 1);
+                        if (kk >= 0) {
+                            c[u][k] = ld<NT>(col + base[u] + kk * stride);
+                            h[u][k] = (k0 + k < w[u]) ? ld<NT>(val + base[u] + kk * stride) : (VT)0;
+                        } else {
+                            c[u][k] = (int32_t)i[u];
+                            h[u][k] = 0;
+                        }
+                    }
+                }
+            Pack<VT, VPT> x[RPT][KU];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u)
+#pragma unroll
+                for (int k = 0; k < KU; ++k)
+                    x[u][k] = load_pack<false, VT, VPT>(tcur + 2 * ((int64_t)c[u][k] * Rp + voff));
+#pragma unroll
+            for (int u = 0; u < RPT; ++u)
+#pragma unroll
+                for (int k = 0; k < KU; ++k)
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) {
+                        y[u].re[q] += h[u][k] * x[u][k].re[q];
+                        y[u].im[q] += h[u][k] * x[u][k].im[q];
+                    }
+        }
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            if constexpr (DIAG) {
+                Pack<VT, VPT> x = load_pack<false, VT, VPT>(tcur + off[u]);
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) { y[u].re[q] += dg[u] * x.re[q]; y[u].im[q] += dg[u] * x.im[q]; }
+            }
+            Pack<VT, VPT> o;
 #pragma unroll
             for (int q = 0; q < VPT; ++q) {
-                o.re[q] = a.c1 * y.re[q] - pv.re[q];
-                o.im[q] = a.c1 * y.im[q] - pv.im[q];
+                if constexpr (FIRST) {
+                    o.re[q] = a.c1 * y[u].re[q];
+                    o.im[q] = a.c1 * y[u].im[q];
+                } else {
+                    o.re[q] = a.c1 * y[u].re[q] - pv[u].re[q];
+                    o.im[q] = a.c1 * y[u].im[q] - pv[u].im[q];
+                }
+            }
+            if (ok[u]) {
+                store_pack<NT, VT, VPT>(tnext + off[u], o);
+#pragma unroll
+                for (int q = 0; q < VPT; ++q)
+                    acc[q] += (double)rv[u].re[q] * (double)o.re[q] + (double)rv[u].im[q] * (double)o.im[q];
             }
         }
-        store_pack<VT, VPT>(a.tnext + off, o);
-        Pack<VT, VPT> rv = load_pack<VT, VPT>(a.r + off);
-#pragma unroll
-        for (int q = 0; q < VPT; ++q)
-            acc[q] += (double)rv.re[q] * (double)o.re[q] + (double)rv.im[q] * (double)o.im[q];
     }
-    block_reduce_store<L, VPT>(acc, a.partial);
+    block_reduce_store<L, VPT>(acc, partial, lb);
 }
 
-// r_int[i][v] = r[perm[i]][v] (v < R), 0 for padded vectors; partial sums of |r|^2.
+// r_int[i][v] = r[perm[i]][v] (v < R), 0 for padded vectors; block partials of |r|^2.
 template <class VT, int L, int VPT>
 __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, const int32_t *__restrict__ perm,
                                                       int64_t n_rows, int32_t R, int32_t Rp,
@@ -186,27 +286,41 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
             acc[q] += (double)re * (double)re + (double)im * (double)im;
         }
     }
-    block_reduce_store<L, VPT>(acc, partial);
+    block_reduce_store<L, VPT>(acc, partial, blockIdx.x);
 }
 
-// mu[v][n] = sum_b partial[n][b][v] in a fixed order; one block per moment.
-__global__ __launch_bounds__(kThreads) void k_reduce_moments(const double *__restrict__ partial, int32_t G,
-                                                             int32_t Rp, int32_t R, int32_t M,
-                                                             double *__restrict__ mu) {
+// First level: l1[n0 + k][v][c] = sum of partial[k][b][v] over b in chunk c.
+// grid = (n_chunks, K * R)
+__global__ __launch_bounds__(kThreads) void k_reduce_l1(const double *__restrict__ partial, int64_t G, int32_t Rp,
+                                                        int32_t R, int32_t n0, int32_t n_chunks,
+                                                        double *__restrict__ l1) {
     __shared__ double red[kThreads];
-    const int n = blockIdx.x;
-    for (int v = 0; v < R; ++v) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < G; b += kThreads) s += partial[((int64_t)n * G + b) * Rp + v];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) mu[(int64_t)v * M + n] = red[0];
+    const int c = blockIdx.x;
+    const int k = blockIdx.y / R, v = blockIdx.y % R;
+    const double *p = partial + (int64_t)k * G * Rp;
+    const int64_t b0 = (int64_t)c * kReduceChunk;
+    const int64_t b1 = min(b0 + kReduceChunk, G);
+    double s = 0.0;
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += kThreads) s += p[b * Rp + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0) l1[((int64_t)(n0 + k) * R + v) * n_chunks + c] = red[0];
+}
+
+// Second level: mu[v][n] = sum over chunks of l1[n][v][c], in chunk order.
+__global__ void k_reduce_l2(const double *__restrict__ l1, int32_t R, int32_t M, int32_t n_chunks,
+                            double *__restrict__ mu) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)R * M) return;
+    const int64_t n = idx / R, v = idx % R;
+    const double *p = l1 + (n * R + v) * n_chunks;
+    double s = 0.0;
+    for (int c = 0; c < n_chunks; ++c) s += p[c];
+    mu[v * M + n] = s;
 }
 
 // flag = 1 if some |mu_n| exceeds mu_0 (1 + 1e-6) or is not finite.
@@ -225,22 +339,155 @@ int log2_exact(int x) {
     return (1 << l) == x ? l : -1;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Pointers of one step launch.
+template <class VT> struct StepPtrs {
+    const int64_t *ptr;
+    const int32_t *col;
+    const VT *val;
+    const VT *onsite;
+    const VT *tcur;
+    const VT *tprev;
+    VT *tnext;
+    const VT *r;
+    double *partial;
+};
+
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W>
+void launch_step_w(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
+    if (pl.cfg.rows_per_thread == 2)
+        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 2, W><<<(unsigned)pl.G, kThreads, 0, s>>>(
+            p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+    else
+        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 1, W><<<(unsigned)pl.G, kThreads, 0, s>>>(
+            p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+}
+
+// Slices of one common width 3 (nearest-neighbour honeycomb) take a fully
+// unrolled kernel; any other width pattern the general one.
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS>
+void launch_step_rpt(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
+    if (pl.uniform_width == 3) launch_step_w<VT, L, VPT, FIRST, DIAG, NT, TIS, 3>(pl, s, p, a);
+    else launch_step_w<VT, L, VPT, FIRST, DIAG, NT, TIS, 0>(pl, s, p, a);
+}
+
+template <class VT, int L, int VPT, bool FIRST, bool DIAG>
+void launch_step_nt(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
+    const bool tis = pl.tile_is_slice;
+    if (pl.cfg.nontemporal) {
+        if (tis) launch_step_rpt<VT, L, VPT, FIRST, DIAG, true, true>(pl, s, p, a);
+        else launch_step_rpt<VT, L, VPT, FIRST, DIAG, true, false>(pl, s, p, a);
+    } else {
+        if (tis) launch_step_rpt<VT, L, VPT, FIRST, DIAG, false, true>(pl, s, p, a);
+        else launch_step_rpt<VT, L, VPT, FIRST, DIAG, false, false>(pl, s, p, a);
+    }
+}
+
+template <class VT, int L, int VPT>
+void launch_step(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,
+                 const StepScalars<VT> &a) {
+    if (first) {
+        if (diag) launch_step_nt<VT, L, VPT, true, true>(pl, s, p, a);
+        else launch_step_nt<VT, L, VPT, true, false>(pl, s, p, a);
+    } else {
+        if (diag) launch_step_nt<VT, L, VPT, false, true>(pl, s, p, a);
+        else launch_step_nt<VT, L, VPT, false, false>(pl, s, p, a);
+    }
+}
+
+void launch_reduce(const KpmPlan &pl, int n0, int count, int R, double *part, double *l1, hipStream_t s) {
+    dim3 grid(pl.n_chunks, count * R);
+    k_reduce_l1<<<grid, kThreads, 0, s>>>(part, pl.G, pl.Rp, R, n0, pl.n_chunks, l1);
+}
+
+template <class VT, int L, int VPT>
+tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
+                       int32_t M, char *work, double *mu, hipStream_t s) {
+    VT *r_int = reinterpret_cast<VT *>(work + pl.off_r);
+    VT *TA = reinterpret_cast<VT *>(work + pl.off_a);
+    VT *TB = reinterpret_cast<VT *>(work + pl.off_b);
+    double *part = reinterpret_cast<double *>(work + pl.off_part);
+    double *l1 = reinterpret_cast<double *>(work + pl.off_l1);
+    int32_t *flag = reinterpret_cast<int32_t *>(work + pl.off_flag);
+    const int64_t pstride = pl.G * pl.Rp;
+    const int K = pl.reduce_every;
+
+    // moment 0 goes through the same partial slots as the steps (slot 0 of the first batch)
+    k_prepare<VT, L, VPT><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp, r_int, part);
+    TBK_HIP(hipGetLastError());
+
+    StepPtrs<VT> sp{};
+    sp.ptr = h->ptr;
+    sp.col = h->col;
+    sp.val = static_cast<const VT *>(h->val);
+    sp.onsite = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
+    sp.r = r_int;
+    StepScalars<VT> sa{};
+    sa.n_rows = h->n_rows;
+    sa.n_tiles = pl.n_tiles;
+    sa.log2_slice = pl.log2_slice;
+    sa.Rp = pl.Rp;
+    sa.tiles_per_block = pl.cfg.tiles_per_block;
+    sa.xcd_remap = pl.cfg.xcd_remap;
+    sa.shift = (VT)b;
+    const bool diag = h->has_onsite || b != 0.0;
+
+    int batch0 = 0;   // first moment index of the pending batch
+    for (int n = 1; n < M; ++n) {
+        if (n - batch0 == K) {
+            launch_reduce(pl, batch0, K, R, part, l1, s);
+            batch0 = n;
+        }
+        sp.partial = part + (int64_t)(n - batch0) * pstride;
+        if (n == 1) {            // T_1 = Ht T_0 into TB
+            sp.tcur = r_int; sp.tprev = nullptr; sp.tnext = TB; sa.c1 = (VT)(1.0 / a);
+        } else if (n == 2) {     // T_2 = 2 Ht T_1 - T_0 into TA
+            sp.tcur = TB; sp.tprev = r_int; sp.tnext = TA; sa.c1 = (VT)(2.0 / a);
+        } else {                 // T_n overwrites T_{n-2} in place
+            VT *cur = (n & 1) ? TA : TB;
+            VT *old = (n & 1) ? TB : TA;
+            sp.tcur = cur; sp.tprev = old; sp.tnext = old;
+        }
+        launch_step<VT, L, VPT>(pl, n == 1, diag, s, sp, sa);
+    }
+    launch_reduce(pl, batch0, M - batch0, R, part, l1, s);
+    TBK_HIP(hipGetLastError());
+    const int64_t nm = (int64_t)R * M;
+    k_reduce_l2<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(l1, R, M, pl.n_chunks, mu);
+    TBK_HIP(hipGetLastError());
+    TBK_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    k_guard<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(mu, R, M, flag);
+    TBK_HIP(hipGetLastError());
+    int32_t hflag = 0;
+    TBK_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TBK_HIP(hipStreamSynchronize(s));
+    TBK_CHECK(hflag == 0, TBK_ERR_SPECTRUM,
+              "a moment exceeds mu_0: the scale a = %g, shift b = %g do not bound the spectrum", a, b);
+    return TBK_OK;
+}
+
+}  // namespace
+
 int pad_vectors(int R) {
     int p = 1;
     while (p < R) p <<= 1;
     return p;
 }
 
-struct Layout {
-    int Rp, L, VPT, G;
-    size_t elem;                 // bytes per real component
-    size_t vec_bytes;            // one [rows][Rp] complex block
-    size_t off_r, off_a, off_b, off_part, off_flag, total;
-};
+tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
+    tbk_kpm_config c{};
+    c.vectors_per_thread = (precision == TBK_PREC_C32 && pad_vectors(R) >= 2) ? 2 : 1;
+    c.tiles_per_block = 2;
+    c.nontemporal = 1;
+    c.xcd_remap = 0;
+    c.rows_per_thread = 1;
+    (void)h;
+    return c;
+}
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, Layout &lay) {
+tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                     KpmPlan &pl) {
     TBK_CHECK(h != nullptr, TBK_ERR_INVALID_ARG, "h is NULL");
     TBK_CHECK(R >= 1 && R <= 64, TBK_ERR_INVALID_ARG, "R = %d outside [1, 64]", R);
     TBK_CHECK(M >= 2, TBK_ERR_INVALID_ARG, "M = %d < 2", M);
@@ -253,100 +500,104 @@ tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision
     else
         TBK_CHECK(h->fmt == TBK_SELL_F32, TBK_ERR_INVALID_ARG, "C32 recurrence needs a float SELL Hamiltonian");
     const int slice = h->fmt == TBK_CSR_F64 ? 1 : h->slice;
-    TBK_CHECK(log2_exact(slice) >= 0, TBK_ERR_INVALID_ARG, "slice %d is not a power of two", slice);
-    lay.Rp = pad_vectors(R);
-    lay.elem = precision == TBK_PREC_F64 ? sizeof(double) : sizeof(float);
-    lay.VPT = (precision == TBK_PREC_C32 && lay.Rp >= 2) ? 2 : 1;
-    lay.L = lay.Rp / lay.VPT;
-    const int64_t rpb = kThreads / lay.L;
-    const int64_t tiles = (h->n_rows + rpb - 1) / rpb;
-    int64_t G = std::min<int64_t>(kMaxGrid, tiles);
-    G = ((G + kNumXcd - 1) / kNumXcd) * kNumXcd;
-    lay.G = (int)G;
-    lay.vec_bytes = align256((size_t)h->n_rows * lay.Rp * 2 * lay.elem);
-    lay.off_r = 0;
-    lay.off_a = lay.off_r + lay.vec_bytes;
-    lay.off_b = lay.off_a + lay.vec_bytes;
-    lay.off_part = lay.off_b + lay.vec_bytes;
-    lay.off_flag = lay.off_part + align256((size_t)M * lay.G * lay.Rp * sizeof(double));
-    lay.total = lay.off_flag + 256;
+    pl.log2_slice = log2_exact(slice);
+    TBK_CHECK(pl.log2_slice >= 0, TBK_ERR_INVALID_ARG, "slice %d is not a power of two", slice);
+    pl.cfg = cfg ? *cfg : default_config(h, R, precision);
+    pl.Rp = pad_vectors(R);
+    pl.elem = precision == TBK_PREC_F64 ? sizeof(double) : sizeof(float);
+    TBK_CHECK(pl.cfg.vectors_per_thread == 1 || (pl.cfg.vectors_per_thread == 2 && precision == TBK_PREC_C32 &&
+                                                 pl.Rp >= 2),
+              TBK_ERR_INVALID_ARG, "vectors_per_thread must be 1, or 2 for the C32 recurrence with R >= 2");
+    TBK_CHECK(pl.cfg.tiles_per_block >= 1 && pl.cfg.tiles_per_block <= (1 << 20), TBK_ERR_INVALID_ARG,
+              "tiles_per_block = %d outside [1, 2^20]", pl.cfg.tiles_per_block);
+    TBK_CHECK(pl.cfg.nontemporal == 0 || pl.cfg.nontemporal == 1, TBK_ERR_INVALID_ARG, "nontemporal must be 0/1");
+    TBK_CHECK(pl.cfg.xcd_remap == 0 || pl.cfg.xcd_remap == 1, TBK_ERR_INVALID_ARG, "xcd_remap must be 0/1");
+    TBK_CHECK(pl.cfg.rows_per_thread == 1 || pl.cfg.rows_per_thread == 2, TBK_ERR_INVALID_ARG,
+              "rows_per_thread must be 1 or 2");
+    pl.VPT = pl.cfg.vectors_per_thread;
+    pl.L = pl.Rp / pl.VPT;
+    const int64_t rpb = kThreads / pl.L;
+    pl.n_tiles = (h->n_rows + rpb - 1) / rpb;
+    int64_t G = (pl.n_tiles + pl.cfg.tiles_per_block - 1) / pl.cfg.tiles_per_block;
+    if (pl.cfg.xcd_remap) {
+        // round up to a multiple of the XCD count; the extra blocks own no tile
+        G = ((G + kNumXcd - 1) / kNumXcd) * kNumXcd;
+    }
+    TBK_CHECK(G < (int64_t)INT32_MAX, TBK_ERR_UNSUPPORTED, "grid too large");
+    pl.G = G;
+    pl.tile_is_slice = (slice == rpb);
+    // every slice stores the same number of entries per row
+    const int64_t n_slices = ceil_div(h->n_rows, slice);
+    pl.uniform_width = (h->max_degree > 0 && h->n_entries == n_slices * slice * (int64_t)h->max_degree)
+                           ? h->max_degree : 0;
+    pl.n_chunks = (int)ceil_div(G, kReduceChunk);
+    TBK_CHECK(pl.n_chunks < 65536, TBK_ERR_UNSUPPORTED, "too many blocks");
+    const size_t per_step = (size_t)G * pl.Rp * sizeof(double);
+    pl.reduce_every = (int)std::max<size_t>(1, std::min<size_t>({kPartialBudget / per_step, (size_t)64, (size_t)M}));
+    TBK_CHECK((int64_t)pl.reduce_every * R < 65536, TBK_ERR_UNSUPPORTED, "reduction grid too large");
+    pl.vec_bytes = align256((size_t)h->n_rows * pl.Rp * 2 * pl.elem);
+    pl.off_r = 0;
+    pl.off_a = pl.off_r + pl.vec_bytes;
+    pl.off_b = pl.off_a + pl.vec_bytes;
+    pl.off_part = pl.off_b + pl.vec_bytes;
+    // k_prepare writes one partial per block of its own grid (<= G blocks)
+    pl.off_l1 = pl.off_part + align256((size_t)pl.reduce_every * per_step);
+    pl.off_flag = pl.off_l1 + align256((size_t)M * R * pl.n_chunks * sizeof(double));
+    pl.total = pl.off_flag + 256;
     return TBK_OK;
 }
 
-template <class VT, int L, int VPT>
-void launch_step(bool first, bool diag, int G, hipStream_t s, const StepArgs<VT> &a) {
-    if (first) {
-        if (diag) k_cheb_step<VT, L, VPT, true, true><<<G, kThreads, 0, s>>>(a);
-        else k_cheb_step<VT, L, VPT, true, false><<<G, kThreads, 0, s>>>(a);
+tbk_status run_plan(const tbk_ham *h, const KpmPlan &pl, double a, double b, const void *r, int32_t R,
+                    int32_t M, int32_t precision, char *w, double *mu, hipStream_t s) {
+    if (precision == TBK_PREC_F64) {
+        const double *rr = static_cast<const double *>(r);
+        switch (pl.L) {
+        case 1: return run_moments<double, 1, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 2: return run_moments<double, 2, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 4: return run_moments<double, 4, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 8: return run_moments<double, 8, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 16: return run_moments<double, 16, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 32: return run_moments<double, 32, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 64: return run_moments<double, 64, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        }
     } else {
-        if (diag) k_cheb_step<VT, L, VPT, false, true><<<G, kThreads, 0, s>>>(a);
-        else k_cheb_step<VT, L, VPT, false, false><<<G, kThreads, 0, s>>>(a);
+        const float *rr = static_cast<const float *>(r);
+        if (pl.VPT == 1) {
+            switch (pl.L) {
+            case 1: return run_moments<float, 1, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 2: return run_moments<float, 2, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 4: return run_moments<float, 4, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 8: return run_moments<float, 8, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 16: return run_moments<float, 16, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 32: return run_moments<float, 32, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 64: return run_moments<float, 64, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            }
+        } else {
+            switch (pl.L) {
+            case 1: return run_moments<float, 1, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 2: return run_moments<float, 2, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 4: return run_moments<float, 4, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 8: return run_moments<float, 8, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 16: return run_moments<float, 16, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 32: return run_moments<float, 32, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            }
+        }
     }
+    return fail(TBK_ERR_UNSUPPORTED, "no kernel for R = %d", R);
 }
 
-template <class VT, int L, int VPT>
-tbk_status run_moments(const tbk_ham *h, double a, double b, const VT *r, int32_t R, int32_t M,
-                       const Layout &lay, char *work, double *mu, hipStream_t s) {
-    VT *r_int = reinterpret_cast<VT *>(work + lay.off_r);
-    VT *TA = reinterpret_cast<VT *>(work + lay.off_a);
-    VT *TB = reinterpret_cast<VT *>(work + lay.off_b);
-    double *part = reinterpret_cast<double *>(work + lay.off_part);
-    int32_t *flag = reinterpret_cast<int32_t *>(work + lay.off_flag);
-    const int G = lay.G;
-    const int64_t stride = (int64_t)G * lay.Rp;
-
-    k_prepare<VT, L, VPT><<<G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, lay.Rp, r_int, part);
-    TBK_HIP(hipGetLastError());
-
-    StepArgs<VT> sa{};
-    sa.ptr = h->ptr;
-    sa.col = h->col;
-    sa.val = static_cast<const VT *>(h->val);
-    sa.onsite = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
-    sa.n_rows = h->n_rows;
-    sa.log2_slice = log2_exact(h->fmt == TBK_CSR_F64 ? 1 : h->slice);
-    sa.Rp = lay.Rp;
-    sa.r = r_int;
-    sa.shift = (VT)b;
-    const bool diag = h->has_onsite || b != 0.0;
-
-    // n = 1: T_1 = Ht T_0 into TB
-    sa.tcur = r_int; sa.tprev = nullptr; sa.tnext = TB; sa.c1 = (VT)(1.0 / a);
-    sa.partial = part + stride;
-    launch_step<VT, L, VPT>(true, diag, G, s, sa);
-    TBK_HIP(hipGetLastError());
-    sa.c1 = (VT)(2.0 / a);
-    if (M > 2) {
-        // n = 2: T_2 = 2 Ht T_1 - T_0 into TA
-        sa.tcur = TB; sa.tprev = r_int; sa.tnext = TA;
-        sa.partial = part + 2 * stride;
-        launch_step<VT, L, VPT>(false, diag, G, s, sa);
-        TBK_HIP(hipGetLastError());
-    }
-    for (int n = 3; n < M; ++n) {
-        // T_n overwrites T_{n-2} in place
-        VT *cur = (n & 1) ? TA : TB;     // T_{n-1}
-        VT *old = (n & 1) ? TB : TA;     // T_{n-2} -> T_n
-        sa.tcur = cur; sa.tprev = old; sa.tnext = old;
-        sa.partial = part + n * stride;
-        launch_step<VT, L, VPT>(false, diag, G, s, sa);
-    }
-    TBK_HIP(hipGetLastError());
-    k_reduce_moments<<<M, kThreads, 0, s>>>(part, G, lay.Rp, R, M, mu);
-    TBK_HIP(hipGetLastError());
-    TBK_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    const int64_t nm = (int64_t)R * M;
-    k_guard<<<(int)ceil_div(nm, 256), 256, 0, s>>>(mu, R, M, flag);
-    TBK_HIP(hipGetLastError());
-    int32_t hflag = 0;
-    TBK_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    TBK_HIP(hipStreamSynchronize(s));
-    TBK_CHECK(hflag == 0, TBK_ERR_SPECTRUM,
-              "a moment exceeds mu_0: the scale a = %g, shift b = %g do not bound the spectrum", a, b);
+tbk_status check_moment_args(const tbk_ham *h, const KpmPlan &pl, const double *a, const double *b,
+                             const void *r, void *work, int64_t work_bytes, double *mu) {
+    TBK_CHECK(a && b && r && work && mu, TBK_ERR_INVALID_ARG, "NULL argument");
+    TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "stacked systems go through kpm_moments_batched");
+    TBK_CHECK(std::isfinite(a[0]) && std::isfinite(b[0]), TBK_ERR_NOT_FINITE, "a or b is not finite");
+    TBK_CHECK(a[0] > 0, TBK_ERR_INVALID_ARG, "a = %g must be positive", a[0]);
+    TBK_CHECK(work_bytes >= (int64_t)pl.total, TBK_ERR_BUFFER_TOO_SMALL,
+              "work has %lld bytes, needs %lld", (long long)work_bytes, (long long)pl.total);
+    TBK_CHECK(((uintptr_t)work & 255) == 0, TBK_ERR_INVALID_ARG, "work is not 256-byte aligned");
+    TBK_CHECK(h->ptr && h->col && h->val && h->onsite, TBK_ERR_INVALID_ARG, "Hamiltonian array is NULL");
     return TBK_OK;
 }
-
-}  // namespace
 
 }  // namespace tbk
 
@@ -354,54 +605,34 @@ using namespace tbk;
 
 extern "C" tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
                                          int64_t *bytes) {
+    return kpm_workspace_size_config(h, R, M, precision, nullptr, bytes);
+}
+
+extern "C" tbk_status kpm_workspace_size_config(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
+                                                const tbk_kpm_config *cfg, int64_t *bytes) {
     clear_error();
     TBK_CHECK(bytes != nullptr, TBK_ERR_INVALID_ARG, "bytes is NULL");
-    Layout lay;
-    tbk_status st = make_layout(h, R, M, precision, lay);
+    KpmPlan pl;
+    tbk_status st = make_plan(h, R, M, precision, cfg, pl);
     if (st != TBK_OK) return st;
-    *bytes = (int64_t)lay.total;
+    *bytes = (int64_t)pl.total;
     return TBK_OK;
 }
 
 extern "C" tbk_status kpm_moments(const tbk_ham *h, const double *a, const double *b, const void *r,
                                   int32_t R, int32_t M, int32_t precision, void *work, int64_t work_bytes,
                                   double *mu, void *stream) {
+    return kpm_moments_config(h, a, b, r, R, M, precision, nullptr, work, work_bytes, mu, stream);
+}
+
+extern "C" tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b, const void *r,
+                                         int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                                         void *work, int64_t work_bytes, double *mu, void *stream) {
     clear_error();
-    Layout lay;
-    tbk_status st = make_layout(h, R, M, precision, lay);
+    KpmPlan pl;
+    tbk_status st = make_plan(h, R, M, precision, cfg, pl);
     if (st != TBK_OK) return st;
-    TBK_CHECK(a && b && r && work && mu, TBK_ERR_INVALID_ARG, "NULL argument");
-    TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "stacked systems go through kpm_moments_batched");
-    TBK_CHECK(std::isfinite(a[0]) && std::isfinite(b[0]), TBK_ERR_NOT_FINITE, "a or b is not finite");
-    TBK_CHECK(a[0] > 0, TBK_ERR_INVALID_ARG, "a = %g must be positive", a[0]);
-    TBK_CHECK(work_bytes >= (int64_t)lay.total, TBK_ERR_BUFFER_TOO_SMALL,
-              "work has %lld bytes, needs %lld", (long long)work_bytes, (long long)lay.total);
-    TBK_CHECK(((uintptr_t)work & 255) == 0, TBK_ERR_INVALID_ARG, "work is not 256-byte aligned");
-    TBK_CHECK(h->ptr && h->col && h->val && h->onsite, TBK_ERR_INVALID_ARG, "Hamiltonian array is NULL");
-    hipStream_t s = as_stream(stream);
-    char *w = static_cast<char *>(work);
-    if (precision == TBK_PREC_F64) {
-        const double *rr = static_cast<const double *>(r);
-        switch (lay.L) {
-        case 1: return run_moments<double, 1, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 2: return run_moments<double, 2, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 4: return run_moments<double, 4, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 8: return run_moments<double, 8, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 16: return run_moments<double, 16, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 32: return run_moments<double, 32, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 64: return run_moments<double, 64, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        }
-    } else {
-        const float *rr = static_cast<const float *>(r);
-        if (lay.VPT == 1) return run_moments<float, 1, 1>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        switch (lay.L) {
-        case 1: return run_moments<float, 1, 2>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 2: return run_moments<float, 2, 2>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 4: return run_moments<float, 4, 2>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 8: return run_moments<float, 8, 2>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 16: return run_moments<float, 16, 2>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        case 32: return run_moments<float, 32, 2>(h, a[0], b[0], rr, R, M, lay, w, mu, s);
-        }
-    }
-    return fail(TBK_ERR_UNSUPPORTED, "no kernel for R = %d", R);
+    st = check_moment_args(h, pl, a, b, r, work, work_bytes, mu);
+    if (st != TBK_OK) return st;
+    return run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream));
 }

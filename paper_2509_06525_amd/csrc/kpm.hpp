@@ -1,0 +1,28 @@
+// Internal plan of the Chebyshev recurrence (shared by the moment, batched and
+// tuning entry points).
+#pragma once
+
+#include "common.hpp"
+
+namespace tbk {
+
+struct KpmPlan {
+    tbk_kpm_config cfg{};
+    int Rp = 1, L = 1, VPT = 1, log2_slice = 0, n_chunks = 1, reduce_every = 1;
+    int64_t n_tiles = 0, G = 0;
+    bool tile_is_slice = false;
+    int uniform_width = 0;      // > 0 when every slice stores this many entries per row
+    size_t elem = 0, vec_bytes = 0;
+    size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_flag = 0, total = 0;
+};
+
+int pad_vectors(int R);
+tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision);
+tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                     KpmPlan &pl);
+tbk_status check_moment_args(const tbk_ham *h, const KpmPlan &pl, const double *a, const double *b,
+                             const void *r, void *work, int64_t work_bytes, double *mu);
+tbk_status run_plan(const tbk_ham *h, const KpmPlan &pl, double a, double b, const void *r, int32_t R,
+                    int32_t M, int32_t precision, char *w, double *mu, hipStream_t s);
+
+}  // namespace tbk

@@ -146,14 +146,14 @@ WORKLOADS = {
                                    fmt="csr_f64", precision="f64", a=9.0, b=0.0,
                                    e_lo=-8.5, e_hi=8.5, n_e=2001, seed=1000),
     "graphene_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=3000, R=16,
-                                fmt="ell_f32", precision="c32", seed=1001),
+                                fmt="sell_f32", precision="c32", seed=1001),
     "hbn_graphene_stripes_4M": dict(kind="stripes", nx=1000, ny=1000, sigma=0.03, M=2000,
-                                    R=32, fmt="ell_f32", precision="c32", seed=1002),
+                                    R=32, fmt="sell_f32", precision="c32", seed=1002),
     "graphene_snapshots_256": dict(kind="snapshots", count=256, M=1024, R=8,
-                                   fmt="ell_f32", precision="c32", seed=3004,
+                                   fmt="sell_f32", precision="c32", seed=3004,
                                    train_seed=4004),
     "graphene_pristine_100M": dict(kind="sheet", nx=5000, ny=5000, sigma=0.0, M=1000, R=1,
-                                   fmt="ell_f32", precision="c32", seed=1004),
+                                   fmt="sell_f32", precision="c32", seed=1004),
 }
 VECTOR_SEED_OFFSET = 1000   # vector seed = structure seed + 1000
 

@@ -47,7 +47,21 @@ class HamStruct(ctypes.Structure):
 
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
-               "tb_build_hamiltonian", "kpm_workspace_size", "kpm_moments", "kpm_dos")
+               "tb_build_hamiltonian", "kpm_workspace_size", "kpm_workspace_size_config",
+               "kpm_moments", "kpm_moments_config", "kpm_dos")
+
+
+class KpmConfig(ctypes.Structure):
+    _fields_ = [("vectors_per_thread", ctypes.c_int32), ("tiles_per_block", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("rows_per_thread", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1):
+    return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread)
 
 
 def lib():
@@ -75,6 +89,12 @@ def lib():
     L.kpm_moments.restype = ctypes.c_int
     L.kpm_moments.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64), vp,
                               i32, i32, i32, vp, i64, vp, vp]
+    L.kpm_workspace_size_config.restype = ctypes.c_int
+    L.kpm_workspace_size_config.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32,
+                                            ctypes.POINTER(KpmConfig), ctypes.POINTER(i64)]
+    L.kpm_moments_config.restype = ctypes.c_int
+    L.kpm_moments_config.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                     vp, i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     _LIB = L
@@ -186,21 +206,25 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
     return Hamiltonian(st, t, (bounds[0], bounds[1]))
 
 
-def workspace_size(H, R, M, precision):
+def _cfg_ref(config):
+    return ctypes.byref(config) if config is not None else None
+
+
+def workspace_size(H, R, M, precision, config=None):
     out = ctypes.c_int64(0)
-    _check(lib().kpm_workspace_size(ctypes.byref(H.st), int(R), int(M), PRECISIONS[precision],
-                                    ctypes.byref(out)))
+    _check(lib().kpm_workspace_size_config(ctypes.byref(H.st), int(R), int(M), PRECISIONS[precision],
+                                           _cfg_ref(config), ctypes.byref(out)))
     return out.value
 
 
-def alloc_workspace(H, R, M, precision, device=None):
-    nbytes = workspace_size(H, R, M, precision)
+def alloc_workspace(H, R, M, precision, device=None, config=None):
+    nbytes = workspace_size(H, R, M, precision, config)
     dev = device if device is not None else H.tensors["ptr"].device
     # torch's caching allocator returns 512-byte aligned blocks
     return torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
 
-def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None):
+def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, config=None):
     """Chebyshev moments mu[v][n] (float64, device) of Ht = (H - b)/a for vectors r [N, R]."""
     L = lib()
     if precision is None:
@@ -211,13 +235,13 @@ def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None):
         r = r.reshape(-1, 1)
     R = r.shape[1]
     if work is None:
-        work = alloc_workspace(H, R, M, precision, r.device)
+        work = alloc_workspace(H, R, M, precision, r.device, config)
     if mu is None:
         mu = torch.empty((R, M), dtype=torch.float64, device=r.device)
     av = (ctypes.c_double * 1)(float(a))
     bv = (ctypes.c_double * 1)(float(b))
-    _check(L.kpm_moments(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
-                         _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
+    _check(L.kpm_moments_config(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
+                                _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
     return mu
 
 
