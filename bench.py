@@ -38,11 +38,13 @@ def parse():
     p.add_argument("--workload", default="graphene_pristine_100M")
     p.add_argument("--slice", type=int, default=256)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run one plain device copy of this many MiB first (counter calibration)")
-    p.add_argument("--cpu-sample-cells", type=int, default=1000,
-                   help="oracle sample: an n x n cell sheet of the same kind, same M and R")
+    p.add_argument("--cpu-sample-cells", type=int, default=0,
+                   help="oracle sample: an n x n cell sheet of the same kind, same M and R "
+                        "(default: sized for about 4e9 atom*moments, 10-30 s on one core)")
     return p.parse_args()
 
 
@@ -122,6 +124,16 @@ def main():
     fmt = w["fmt"]
     slice_ = 1 if fmt == "csr_f64" else args.slice
     fixed_ab = ("a" in w)
+    config = None
+    tune = None
+    if fmt != "csr_f64" and not args.no_tune:
+        log("autotuning slice height and launch shape")
+        tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, R, w["precision"],
+                              r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, stream=stream)
+        slice_ = tune.slice
+        config = tune.config
+        log(f"tuned: slice {slice_} {config.as_dict()} {tune.ms_per_step:.4f} ms/step "
+            f"({tune.candidates} candidates)")
 
     def build():
         return tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair,
@@ -130,7 +142,7 @@ def main():
 
     H = build()
     a, b = (w["a"], w["b"]) if fixed_ab else H.scale()
-    work = tbkpm.alloc_workspace(H, R, M, w["precision"], dev)
+    work = tbkpm.alloc_workspace(H, R, M, w["precision"], dev, config)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
     if fixed_ab:
@@ -144,7 +156,7 @@ def main():
         Hs = build()
         aa, bb = (w["a"], w["b"]) if fixed_ab else Hs.scale()
         ev[0].record(stream)
-        tbkpm.kpm_moments(Hs, aa, bb, r, M, w["precision"], work=work, mu=mu, stream=stream)
+        tbkpm.kpm_moments(Hs, aa, bb, r, M, w["precision"], work=work, mu=mu, stream=stream, config=config)
         ev[1].record(stream)
         rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream)
         return Hs, aa, bb, rho
@@ -184,6 +196,9 @@ def main():
                    "format": fmt, "slice": slice_, "precision": w["precision"],
                    "a_eV": aa, "b_eV": bb},
         "kpm_ms_median": kpm_med,
+        "tuning": None if tune is None else {"slice": tune.slice, "launch": tune.config.as_dict(),
+                                             "tuned_ms_per_step": tune.ms_per_step,
+                                             "candidates": tune.candidates},
         "kpm_atom_moments_per_s": N * M * R / (kpm_med * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -216,7 +231,10 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one core)")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cells)
+        cells = args.cpu_sample_cells or max(8, int(math.sqrt(4e9 / (4.0 * M * R))))
+        if "nx" in w:
+            cells = min(cells, w["nx"])
+        out["cpu_baseline"] = cpu_baseline(w, cells)
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
         out["cpu_baseline"]["nproc"] = os.cpu_count()
     print(json.dumps(out), flush=True)

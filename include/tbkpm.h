@@ -198,6 +198,38 @@ tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b
                               void *work, int64_t work_bytes, double *mu, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Autotuning                                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t slice;              /* chosen SELL slice height                      */
+    tbk_kpm_config config;      /* chosen launch shape                           */
+    double ms_per_step;         /* measured time of one recurrence step (ms);
+                                   -1 when tuning is switched off               */
+    int32_t candidates;         /* (slice, shape) pairs timed                    */
+    int32_t from_cache;         /* 1 when the answer came from the cache         */
+} tbk_tune_result;
+
+/*
+ * Picks the SELL slice height and the recurrence launch shape for one
+ * structure (same inputs as tb_build_hamiltonian) and vector count R: builds
+ * H for each candidate slice, times `steps` recurrence steps of every
+ * candidate shape on the GPU (HIP events on `stream`), returns the fastest.
+ * Only speed depends on the choice.  Results are cached per device and
+ * problem class (size bucket, R, precision, format, degree, onsite) in
+ * memory, and in the file named by the environment variable
+ * TBKPM_AUTOTUNE_CACHE when set; TBKPM_AUTOTUNE=0 returns the defaults
+ * untimed.  Allocates (and frees) temporary device memory.
+ * Errors: as tb_build_hamiltonian; INVALID_ARG for R outside [1, 64], steps
+ * outside [1, 1000], a CSR format or a precision/format mismatch.
+ * Synchronises `stream`.
+ */
+tbk_status tbk_autotune(const double *pos, const int32_t *species, int64_t n,
+                        const double box[3], const int32_t periodic[3],
+                        const tbk_tb_params *p, int32_t fmt, int32_t R, int32_t precision,
+                        int32_t steps, tbk_tune_result *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* DOS reconstruction                                                        */
 /* ------------------------------------------------------------------------ */
 

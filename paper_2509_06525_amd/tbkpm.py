@@ -48,7 +48,7 @@ class HamStruct(ctypes.Structure):
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
                "tb_build_hamiltonian", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_dos")
+               "kpm_moments", "kpm_moments_config", "kpm_dos", "tbk_autotune")
 
 
 class KpmConfig(ctypes.Structure):
@@ -58,6 +58,11 @@ class KpmConfig(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("slice", ctypes.c_int32), ("config", KpmConfig), ("ms_per_step", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
 def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1):
@@ -95,6 +100,9 @@ def lib():
     L.kpm_moments_config.restype = ctypes.c_int
     L.kpm_moments_config.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64),
                                      vp, i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+    L.tbk_autotune.restype = ctypes.c_int
+    L.tbk_autotune.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(TbParams),
+                               i32, i32, i32, i32, ctypes.POINTER(TuneResult), vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     _LIB = L
@@ -253,3 +261,21 @@ def kpm_dos(mu, a, b, E, kernel=0, stream=None):
     _check(lib().kpm_dos(_ptr(mu), mu.numel(), float(a), float(b), int(kernel), _ptr(E), E.numel(),
                          _ptr(rho), _stream(stream)))
     return rho
+
+
+def autotune(pos, species, box, periodic, onsite, t_pair, R, precision="c32", r_cut=2.0, r0=1.42,
+             beta=3.37, reorder=True, steps=8, stream=None):
+    """Fastest (slice, launch shape) for this structure and R; returns a TuneResult."""
+    L = lib()
+    pos = _dev(pos, torch.float64)
+    species = _dev(species, torch.int32)
+    p, keep = _params(onsite, t_pair, r_cut, r0, beta, reorder)
+    boxa = _f64arr(box)
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    out = TuneResult()
+    fmt = "sell_f32" if precision == "c32" else "sell_f64"
+    _check(L.tbk_autotune(_ptr(pos), _ptr(species), pos.shape[0], boxa, per, ctypes.byref(p),
+                          FORMATS[fmt], int(R), PRECISIONS[precision], int(steps), ctypes.byref(out),
+                          _stream(stream)))
+    del keep
+    return out
