@@ -23,6 +23,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kMaxDegree = 256;
 constexpr int kMaxSpecies = 16;
+constexpr int kCellStrip = 64;      // cells per strip of the row order
 
 __global__ void k_scan_positions(const double *__restrict__ pos, const int32_t *__restrict__ species,
                                  int64_t n, int32_t n_species, double *__restrict__ part) {
@@ -66,7 +67,7 @@ __global__ void k_cell_of(const double *__restrict__ pos, int64_t n, CellGrid g,
     int32_t cx = cell_coord(pos[3 * i], g, 0);
     int32_t cy = cell_coord(pos[3 * i + 1], g, 1);
     int32_t cz = cell_coord(pos[3 * i + 2], g, 2);
-    int32_t c = (int32_t)(((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
+    int32_t c = (int32_t)cell_id(g, cx, cy, cz);
     cell[i] = c;
     slot[i] = atomicAdd(&count[c], 1);
 }
@@ -277,6 +278,9 @@ tbk_status CellListOwner::build(const double *pos, const int32_t *species, int32
         g.nc[k] = std::max(1, g.nc[k] / 2);
         ncell *= g.nc[k];
     }
+    g.strip = std::min<int32_t>(g.nc[0], kCellStrip);
+    g.nstrip = (g.nc[0] + g.strip - 1) / g.strip;
+    ncell = (int64_t)g.nc[2] * g.nstrip * g.nc[1] * g.strip;
     g.ncell = ncell;
     TBK_CHECK(ncell < (int64_t)INT32_MAX, TBK_ERR_UNSUPPORTED, "too many cells");
 

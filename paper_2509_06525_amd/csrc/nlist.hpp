@@ -9,14 +9,25 @@
 
 namespace tbk {
 
+// Cells are numbered in strips: the x axis is cut into strips of `strip`
+// cells; cells are ordered by (z, strip, y, x within the strip), so cells that
+// touch in y are `strip` ids apart and atoms sorted by cell id keep their
+// neighbours close in memory.
 struct CellGrid {
     double lo[3];       // origin of the binned range
     double len[3];      // length of the binned range
     int32_t nc[3];      // cells per axis (>= 1)
     int32_t periodic[3];
     double box[3];      // periodic lengths
-    int64_t ncell;
+    int32_t strip;      // cells per strip along x (>= 1)
+    int32_t nstrip;     // ceil(nc[0] / strip)
+    int64_t ncell;      // number of cell ids: nc[2] * nstrip * nc[1] * strip
 };
+
+__host__ __device__ __forceinline__ int64_t cell_id(const CellGrid &g, int32_t cx, int32_t cy, int32_t cz) {
+    const int32_t st = cx / g.strip, wx = cx - st * g.strip;
+    return (((int64_t)cz * g.nstrip + st) * g.nc[1] + cy) * g.strip + wx;
+}
 
 // Device-side view of a built cell list.
 struct CellList {
@@ -71,7 +82,7 @@ __device__ __forceinline__ void for_each_neighbor(const CellList &cl, const doub
                     if (!g.periodic[0]) continue;
                     cx = (cx + g.nc[0]) % g.nc[0];
                 }
-                int64_t cid = ((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx;
+                int64_t cid = cell_id(g, cx, cy, cz);
                 int32_t s0 = cl.cell_start[cid], s1 = cl.cell_start[cid + 1];
                 for (int32_t s = s0; s < s1; ++s) {
                     int32_t j = cl.sorted[s];
