@@ -290,25 +290,31 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
 }
 
 // First level: l1[n0 + k][v][c] = sum of partial[k][b][v] over b in chunk c.
-// grid = (n_chunks, K * R)
+// grid = (n_chunks, K).  Thread t reads vector v = t % Rp of blocks
+// b0 + t / Rp, b0 + t / Rp + 256 / Rp, ..., so a wavefront reads whole rows of
+// partial[k][b][0..Rp) (contiguous); the per-vector sums are then folded in LDS
+// over the 256 / Rp thread groups in a fixed tree.
 __global__ __launch_bounds__(kThreads) void k_reduce_l1(const double *__restrict__ partial, int64_t G, int32_t Rp,
                                                         int32_t R, int32_t n0, int32_t n_chunks,
                                                         double *__restrict__ l1) {
     __shared__ double red[kThreads];
     const int c = blockIdx.x;
-    const int k = blockIdx.y / R, v = blockIdx.y % R;
+    const int k = blockIdx.y;
+    const int v = threadIdx.x % Rp;
+    const int j = threadIdx.x / Rp;
+    const int groups = kThreads / Rp;
     const double *p = partial + (int64_t)k * G * Rp;
     const int64_t b0 = (int64_t)c * kReduceChunk;
     const int64_t b1 = min(b0 + kReduceChunk, G);
     double s = 0.0;
-    for (int64_t b = b0 + threadIdx.x; b < b1; b += kThreads) s += p[b * Rp + v];
+    for (int64_t b = b0 + j; b < b1; b += groups) s += p[b * Rp + v];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int g = groups / 2; g > 0; g >>= 1) {
+        if (j < g) red[threadIdx.x] += red[threadIdx.x + g * Rp];
         __syncthreads();
     }
-    if (threadIdx.x == 0) l1[((int64_t)(n0 + k) * R + v) * n_chunks + c] = red[0];
+    if (j == 0 && v < R) l1[((int64_t)(n0 + k) * R + v) * n_chunks + c] = red[v];
 }
 
 // Second level: mu[v][n] = sum over chunks of l1[n][v][c], in chunk order.
@@ -397,7 +403,7 @@ void launch_step(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const 
 }
 
 void launch_reduce(const KpmPlan &pl, int n0, int count, int R, double *part, double *l1, hipStream_t s) {
-    dim3 grid(pl.n_chunks, count * R);
+    dim3 grid(pl.n_chunks, count);
     k_reduce_l1<<<grid, kThreads, 0, s>>>(part, pl.G, pl.Rp, R, n0, pl.n_chunks, l1);
 }
 
@@ -534,7 +540,7 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     TBK_CHECK(pl.n_chunks < 65536, TBK_ERR_UNSUPPORTED, "too many blocks");
     const size_t per_step = (size_t)G * pl.Rp * sizeof(double);
     pl.reduce_every = (int)std::max<size_t>(1, std::min<size_t>({kPartialBudget / per_step, (size_t)64, (size_t)M}));
-    TBK_CHECK((int64_t)pl.reduce_every * R < 65536, TBK_ERR_UNSUPPORTED, "reduction grid too large");
+    TBK_CHECK(pl.reduce_every < 65536, TBK_ERR_UNSUPPORTED, "reduction grid too large");
     pl.vec_bytes = align256((size_t)h->n_rows * pl.Rp * 2 * pl.elem);
     pl.off_r = 0;
     pl.off_a = pl.off_r + pl.vec_bytes;
