@@ -139,6 +139,27 @@ tbk_status tb_build_hamiltonian(const double *pos, const int32_t *species, int64
                                 const tbk_tb_params *p, tbk_ham *h,
                                 double spec_bounds[2], void *stream);
 
+/*
+ * Several independent structures at once ("segments", e.g. finite-temperature
+ * snapshots of different sizes), stacked along the atom index: structure s
+ * holds atoms [seg_atoms[s], seg_atoms[s+1]) of pos/species (seg_atoms: host
+ * int64 [n_seg+1], seg_atoms[0] = 0, strictly increasing), its periodic box is
+ * boxes[3 s .. 3 s + 2] (host), and periodic[3] applies to all.  Neighbours are
+ * searched only inside a structure; the rows of structure s are the row range
+ * [seg_atoms[s], seg_atoms[s+1]) of the stacked H, whose table tb_build_*
+ * copies to h->seg_rows (device int64 [n_seg+1], caller-allocated).
+ * spec_bounds: host double [n_seg][2], Gershgorin [E_lo, E_hi] per structure.
+ * Errors as the single-structure calls, plus INVALID_ARG for a bad table.
+ */
+tbk_status tbk_hamiltonian_size_batched(const double *pos, const int32_t *species, int32_t n_seg,
+                                        const int64_t *seg_atoms, const double *boxes,
+                                        const int32_t periodic[3], const tbk_tb_params *p,
+                                        tbk_ham *h, void *stream);
+tbk_status tb_build_hamiltonian_batched(const double *pos, const int32_t *species, int32_t n_seg,
+                                        const int64_t *seg_atoms, const double *boxes,
+                                        const int32_t periodic[3], const tbk_tb_params *p,
+                                        tbk_ham *h, double *spec_bounds, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Chebyshev moments                                                         */
 /* ------------------------------------------------------------------------ */
@@ -196,6 +217,23 @@ tbk_status kpm_moments(const tbk_ham *h, const double *a, const double *b, const
 tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b, const void *r,
                               int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
                               void *work, int64_t work_bytes, double *mu, void *stream);
+
+/*
+ * Moments of every structure of a stacked Hamiltonian (tb_build_hamiltonian_
+ * batched) in one recurrence launch per step: structure s is scaled by its own
+ * a[s] > 0, b[s] (host double [n_seg]) and mu is device double
+ * [n_seg][R][M], mu[s][v][n] = Re <r_v|T_n>_s over the rows of s.  r is
+ * [n_rows][R] in the caller's stacked atom order.  The workspace size depends
+ * on the structures' sizes and is queried with kpm_workspace_size_batched
+ * (which reads h->seg_rows and synchronises `stream`).  Launch shapes as in
+ * kpm_moments_config (xcd_remap and rows_per_thread are not used here).
+ * Errors as kpm_moments; SPECTRUM if any structure's moments leave [-mu_0, mu_0].
+ */
+tbk_status kpm_workspace_size_batched(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
+                                      const tbk_kpm_config *cfg, int64_t *bytes, void *stream);
+tbk_status kpm_moments_batched(const tbk_ham *h, const double *a, const double *b, const void *r,
+                               int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                               void *work, int64_t work_bytes, double *mu, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuning                                                                */

@@ -3,6 +3,9 @@
 // Atoms are binned into cells at least r_cut wide; an axis with fewer than
 // three cells is scanned whole so no cell is visited twice.  Displacements are
 // formed in FP64 under the minimum-image convention on periodic axes.
+// Several independent structures ("segments", stacked along the atom index)
+// can be binned at once: each has its own cell grid and its own range of
+// global cell ids, and neighbours are only searched inside the segment.
 #pragma once
 
 #include "common.hpp"
@@ -22,6 +25,7 @@ struct CellGrid {
     int32_t strip;      // cells per strip along x (>= 1)
     int32_t nstrip;     // ceil(nc[0] / strip)
     int64_t ncell;      // number of cell ids: nc[2] * nstrip * nc[1] * strip
+    int64_t cell_off;   // first global cell id of this grid's segment
 };
 
 __host__ __device__ __forceinline__ int64_t cell_id(const CellGrid &g, int32_t cx, int32_t cy, int32_t cz) {
@@ -31,8 +35,9 @@ __host__ __device__ __forceinline__ int64_t cell_id(const CellGrid &g, int32_t c
 
 // Device-side view of a built cell list.
 struct CellList {
-    CellGrid g;
-    const int32_t *cell_start;  // [ncell + 1]
+    const CellGrid *grids;      // [n_seg]
+    const int32_t *seg_of;      // [n] segment of each atom
+    const int32_t *cell_start;  // [ncell_total + 1]
     const int32_t *sorted;      // [n] atom indices, cell-major, ascending within a cell
 };
 
@@ -49,12 +54,12 @@ __device__ __forceinline__ int32_t cell_coord(double x, const CellGrid &g, int k
     return c;
 }
 
-// Calls f(j, r, dx, dy, dz) for every atom j != i with |x_j - x_i| < r_cut
-// (minimum image), visiting cells in a fixed order.
+// Calls f(j, r, dx, dy, dz) for every atom j != i of i's segment with
+// |x_j - x_i| < r_cut (minimum image), visiting cells in a fixed order.
 template <class F>
 __device__ __forceinline__ void for_each_neighbor(const CellList &cl, const double *__restrict__ pos,
                                                   int32_t i, double r_cut, F &&f) {
-    const CellGrid &g = cl.g;
+    const CellGrid g = cl.grids[cl.seg_of[i]];
     const double xi = pos[3 * (int64_t)i], yi = pos[3 * (int64_t)i + 1], zi = pos[3 * (int64_t)i + 2];
     int32_t c[3] = {cell_coord(xi, g, 0), cell_coord(yi, g, 1), cell_coord(zi, g, 2)};
     int32_t lo[3], cnt[3];
@@ -82,7 +87,7 @@ __device__ __forceinline__ void for_each_neighbor(const CellList &cl, const doub
                     if (!g.periodic[0]) continue;
                     cx = (cx + g.nc[0]) % g.nc[0];
                 }
-                int64_t cid = cell_id(g, cx, cy, cz);
+                const int64_t cid = g.cell_off + cell_id(g, cx, cy, cz);
                 int32_t s0 = cl.cell_start[cid], s1 = cl.cell_start[cid + 1];
                 for (int32_t s = s0; s < s1; ++s) {
                     int32_t j = cl.sorted[s];
@@ -102,14 +107,18 @@ __device__ __forceinline__ void for_each_neighbor(const CellList &cl, const doub
     }
 }
 
-// Owns the device buffers of a cell list built for one structure.
+// Owns the device buffers of a cell list built for stacked structures.
 struct CellListOwner {
     CellList view{};
-    DevBuf cell_start, sorted, scratch;
-    // Fills `view` for positions pos[n][3].  Validates box lengths, finiteness
-    // and (when species != nullptr) species range.
-    tbk_status build(const double *pos, const int32_t *species, int32_t n_species, int64_t n,
-                     const double box[3], const int32_t periodic[3], double r_cut, hipStream_t s);
+    int32_t n_seg = 0;
+    DevBuf grids, seg_of, seg_atoms, cell_start, sorted;
+    // Bins positions pos[n][3] of n_seg structures; structure s holds atoms
+    // [seg_atoms[s], seg_atoms[s+1]) (host array) and, on periodic axes, the
+    // box boxes[3 s .. 3 s + 2] (host).  Validates box lengths, finiteness and
+    // (when species != nullptr) the species range.
+    tbk_status build(const double *pos, const int32_t *species, int32_t n_species, int64_t n, int32_t n_seg,
+                     const int64_t *seg_atoms, const double *boxes, const int32_t periodic[3], double r_cut,
+                     hipStream_t s);
 };
 
 }  // namespace tbk

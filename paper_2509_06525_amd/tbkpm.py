@@ -48,7 +48,9 @@ class HamStruct(ctypes.Structure):
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
                "tb_build_hamiltonian", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_dos", "tbk_autotune")
+               "kpm_moments", "kpm_moments_config", "kpm_dos", "tbk_autotune",
+               "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
+               "kpm_workspace_size_batched", "kpm_moments_batched")
 
 
 class KpmConfig(ctypes.Structure):
@@ -103,6 +105,20 @@ def lib():
     L.tbk_autotune.restype = ctypes.c_int
     L.tbk_autotune.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(TbParams),
                                i32, i32, i32, i32, ctypes.POINTER(TuneResult), vp]
+    L.tbk_hamiltonian_size_batched.restype = ctypes.c_int
+    L.tbk_hamiltonian_size_batched.argtypes = [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
+                                               ctypes.POINTER(i32), ctypes.POINTER(TbParams),
+                                               ctypes.POINTER(HamStruct), vp]
+    L.tb_build_hamiltonian_batched.restype = ctypes.c_int
+    L.tb_build_hamiltonian_batched.argtypes = [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
+                                               ctypes.POINTER(i32), ctypes.POINTER(TbParams),
+                                               ctypes.POINTER(HamStruct), ctypes.POINTER(f64), vp]
+    L.kpm_workspace_size_batched.restype = ctypes.c_int
+    L.kpm_workspace_size_batched.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, ctypes.POINTER(KpmConfig),
+                                             ctypes.POINTER(i64), vp]
+    L.kpm_moments_batched.restype = ctypes.c_int
+    L.kpm_moments_batched.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64), vp,
+                                      i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     _LIB = L
@@ -279,3 +295,81 @@ def autotune(pos, species, box, periodic, onsite, t_pair, R, precision="c32", r_
                           _stream(stream)))
     del keep
     return out
+
+
+class BatchedHamiltonian(Hamiltonian):
+    """Stacked Hamiltonian of several structures; bounds is a list of (E_lo, E_hi)."""
+
+    @property
+    def n_seg(self):
+        return self.st.n_seg
+
+    def scales(self, margin=1.01):
+        a = [margin * (hi - lo) / 2.0 for lo, hi in self.bounds]
+        b = [(hi + lo) / 2.0 for lo, hi in self.bounds]
+        return a, b
+
+
+def build_hamiltonian_batched(pos, species, seg_atoms, boxes, periodic, onsite, t_pair, r_cut=2.0, r0=1.42,
+                              beta=3.37, fmt="sell_f32", slice=64, reorder=True, stream=None):
+    """Stacked structures: atoms [seg_atoms[s], seg_atoms[s+1]) form structure s with box boxes[s]."""
+    L = lib()
+    pos = _dev(pos, torch.float64)
+    species = _dev(species, torch.int32)
+    n_seg = len(seg_atoms) - 1
+    p, keep = _params(onsite, t_pair, r_cut, r0, beta, reorder)
+    seg = (ctypes.c_int64 * (n_seg + 1))(*[int(v) for v in seg_atoms])
+    bx = (ctypes.c_double * (3 * n_seg))(*[float(v) for b3 in boxes for v in b3])
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
+    s = _stream(stream)
+    _check(L.tbk_hamiltonian_size_batched(_ptr(pos), _ptr(species), n_seg, seg, bx, per, ctypes.byref(p),
+                                          ctypes.byref(st), s))
+    dev = pos.device
+    n = pos.shape[0]
+    vdt = torch.float32 if fmt == "sell_f32" else torch.float64
+    t = {
+        "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
+        "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),
+        "val": torch.empty(max(st.n_entries, 1), dtype=vdt, device=dev),
+        "onsite": torch.empty(n, dtype=vdt, device=dev),
+        "perm": torch.empty(n, dtype=torch.int32, device=dev),
+        "seg_rows": torch.empty(n_seg + 1, dtype=torch.int64, device=dev),
+    }
+    st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
+    st.onsite, st.perm, st.seg_rows = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["seg_rows"].data_ptr()
+    bounds = (ctypes.c_double * (2 * n_seg))()
+    _check(L.tb_build_hamiltonian_batched(_ptr(pos), _ptr(species), n_seg, seg, bx, per, ctypes.byref(p),
+                                          ctypes.byref(st), bounds, s))
+    del keep
+    return BatchedHamiltonian(st, t, [(bounds[2 * k], bounds[2 * k + 1]) for k in range(n_seg)])
+
+
+def workspace_size_batched(H, R, M, precision, config=None, stream=None):
+    out = ctypes.c_int64(0)
+    _check(lib().kpm_workspace_size_batched(ctypes.byref(H.st), int(R), int(M), PRECISIONS[precision],
+                                            _cfg_ref(config), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def kpm_moments_batched(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, config=None):
+    """mu[s][v][n] (float64, device) for every structure s of a stacked Hamiltonian."""
+    L = lib()
+    if precision is None:
+        precision = "c32" if r.dtype == torch.complex64 else "f64"
+    want = torch.complex64 if precision == "c32" else torch.complex128
+    r = _dev(r, want)
+    if r.dim() == 1:
+        r = r.reshape(-1, 1)
+    R = r.shape[1]
+    ns = H.n_seg
+    if work is None:
+        work = torch.empty(workspace_size_batched(H, R, M, precision, config, stream), dtype=torch.uint8,
+                           device=r.device)
+    if mu is None:
+        mu = torch.empty((ns, R, M), dtype=torch.float64, device=r.device)
+    av = (ctypes.c_double * ns)(*[float(v) for v in a])
+    bv = (ctypes.c_double * ns)(*[float(v) for v in b])
+    _check(L.kpm_moments_batched(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
+                                 _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
+    return mu

@@ -1,0 +1,123 @@
+"""GPU parity of the stacked-structure (snapshot batch) builder and recurrence.
+
+Each structure of the batch must give what the oracle gives for it alone:
+the same neighbour pattern (bit-exact) and hoppings, its own Gershgorin
+bounds, and FP64 moments within 1e-10 N_s of the oracle's with the structure's
+own (a, b); the complex-float path within 1e-4 DOS relative L2.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(3, 3, 0.02), (7, 5, 0.08), (12, 10, 0.05), (4, 6, 0.0), (20, 17, 0.06), (2, 3, 0.03)]
+
+
+def make_batch(shapes=SHAPES, seed=100):
+    sheets = [synth.graphene_sheet(nx, ny, sg, seed + k) for k, (nx, ny, sg) in enumerate(shapes)]
+    pos = np.concatenate([s.pos for s in sheets])
+    sp = np.concatenate([s.species for s in sheets])
+    seg = np.concatenate([[0], np.cumsum([s.n for s in sheets])]).astype(np.int64)
+    boxes = [s.box for s in sheets]
+    return sheets, pos, sp, seg, boxes
+
+
+def build(pos, sp, seg, boxes, fmt="sell_f64", slice=32):
+    return tbkpm.build_hamiltonian_batched(G.to_dev(pos), G.to_dev(sp), seg, boxes, (1, 1, 0), [0.0], [[-2.7]],
+                                           fmt=fmt, slice=slice)
+
+
+@pytest.mark.parametrize("fmt,slice", [("sell_f64", 32), ("sell_f64", 1), ("sell_f32", 64)])
+def test_batched_builder_per_structure(fmt, slice):
+    sheets, pos, sp, seg, boxes = make_batch()
+    H = build(pos, sp, seg, boxes, fmt, slice)
+    assert H.n_seg == len(sheets)
+    np.testing.assert_array_equal(H.tensors["seg_rows"].cpu().numpy(), seg)
+    rows, cols, vals, onsite = G.entries_in_atom_order(H)
+    perm = H.perm.cpu().numpy()
+    for k, s in enumerate(sheets):
+        # rows of structure k are its own atoms
+        assert set(perm[seg[k]:seg[k + 1]].tolist()) == set(range(seg[k], seg[k + 1]))
+        m = (rows >= seg[k]) & (rows < seg[k + 1])
+        assert np.all((cols[m] >= seg[k]) & (cols[m] < seg[k + 1]))
+        csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+        orow, ocol, oval = G.csr_entries(csr)
+        r, c, v = rows[m] - seg[k], cols[m] - seg[k], vals[m]
+        o1, o2 = np.lexsort((c, r)), np.lexsort((ocol, orow))
+        np.testing.assert_array_equal(r[o1], orow[o2])
+        np.testing.assert_array_equal(c[o1], ocol[o2])
+        np.testing.assert_allclose(v[o1], oval[o2], rtol=1e-6 if fmt == "sell_f32" else 2e-15)
+        lo, hi = O.gershgorin(csr)
+        assert H.bounds[k][0] == pytest.approx(lo, rel=1e-14)
+        assert H.bounds[k][1] == pytest.approx(hi, rel=1e-14)
+
+
+@pytest.mark.parametrize("R", [1, 3, 8])
+@pytest.mark.parametrize("tpb,nt", [(1, 1), (3, 0), (2, 1)])
+def test_batched_fp64_moments_per_structure(R, tpb, nt):
+    sheets, pos, sp, seg, boxes = make_batch()
+    H = build(pos, sp, seg, boxes, "sell_f64", 16)
+    a, b = H.scales()
+    M = 64
+    r = synth.random_phase(pos.shape[0], R, 11)
+    cfg = tbkpm.make_config(1, tpb, nt, 0, 1)
+    mu = tbkpm.kpm_moments_batched(H, a, b, G.to_dev(r), M, "f64", config=cfg).cpu().numpy()
+    assert mu.shape == (len(sheets), R, M)
+    for k, s in enumerate(sheets):
+        csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+        mu_o, _ = O.kpm_moments(csr, a[k], b[k], np.ascontiguousarray(r[seg[k]:seg[k + 1]]), M)
+        assert np.abs(mu[k] - mu_o).max() <= 1e-10 * s.n, k
+
+
+def test_batched_equals_single_structure_calls():
+    sheets, pos, sp, seg, boxes = make_batch()
+    Hb = build(pos, sp, seg, boxes, "sell_f64", 32)
+    a, b = Hb.scales()
+    r = synth.random_phase(pos.shape[0], 4, 12)
+    mu_b = tbkpm.kpm_moments_batched(Hb, a, b, G.to_dev(r), 50, "f64").cpu().numpy()
+    for k, s in enumerate(sheets):
+        H1 = G.build(s, fmt="sell_f64", slice=32)
+        mu1 = tbkpm.kpm_moments(H1, a[k], b[k], G.to_dev(np.ascontiguousarray(r[seg[k]:seg[k + 1]])), 50,
+                                "f64").cpu().numpy()
+        assert np.abs(mu_b[k] - mu1).max() <= 1e-12 * s.n
+
+
+def test_batched_c32_dos():
+    sheets, pos, sp, seg, boxes = make_batch([(30, 26, 0.05), (11, 19, 0.07), (45, 40, 0.02)])
+    H = build(pos, sp, seg, boxes, "sell_f32", 64)
+    a, b = H.scales()
+    M = 256
+    r = synth.random_phase(pos.shape[0], 8, 13, np.complex64)
+    mu = tbkpm.kpm_moments_batched(H, a, b, G.to_dev(r), M, "c32",
+                                   config=tbkpm.make_config(2, 2, 1, 0, 1)).cpu().numpy()
+    for k, s in enumerate(sheets):
+        csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+        mu_o, _ = O.kpm_moments(csr, a[k], b[k], r[seg[k]:seg[k + 1]].astype(np.complex128), M)
+        E = synth.energy_grid(a[k], b[k])
+        err = G.rel_l2(O.kpm_dos(mu[k].mean(0), a[k], b[k], E), O.kpm_dos(mu_o.mean(0), a[k], b[k], E))
+        assert err <= 1e-4, (k, err)
+
+
+def test_batched_errors():
+    sheets, pos, sp, seg, boxes = make_batch()
+    bad = seg.copy()
+    bad[2] = bad[1]                       # empty structure
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(pos, sp, bad, boxes)
+    assert e.value.name == "INVALID_ARG"
+    small = [list(b) for b in boxes]
+    small[1][1] = 3.0                     # periodic length below 2 r_cut
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(pos, sp, seg, small)
+    assert e.value.name == "INVALID_ARG"
+    H = build(pos, sp, seg, boxes)
+    a, b = H.scales()
+    a[3] = 0.3 * a[3]
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.kpm_moments_batched(H, a, b, G.to_dev(synth.random_phase(pos.shape[0], 1, 1)), 128, "f64")
+    assert e.value.name == "SPECTRUM"

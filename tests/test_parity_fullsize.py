@@ -1,0 +1,108 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (autotuned slice height and launch shape).
+
+The expected moments are the serial FP64 oracle's, stored under tests/golden/
+by tests/golden/make_golden.py for the leading random vectors of each workload
+(the complex64 phases widened to complex128), together with the (a, b) the
+oracle derived; the GPU runs with that same (a, b).
+
+Bars: complex-float path, DOS relative L2 <= 1e-4 on 2001 energies and
+|mu_gpu - mu_oracle| <= 1e-4 mu_0 per moment; FP64 path <= 1e-10 mu_0.
+The 100M-atom pristine sheet is also checked against its exact spectrum
+(commensurate Bloch sum of a smaller periodic sheet, exact for walks shorter
+than the smaller sheet's period): |mu_n/N - tau_n| <= 5/sqrt(N) for n < 300.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+from tests import ref_numpy as ref
+from tests.golden import make_golden
+
+pytestmark = pytest.mark.gpu
+
+WORKLOADS = ["graphene_thermal_1M", "hbn_graphene_stripes_4M", "graphene_pristine_100M"]
+
+
+def _have(name):
+    return os.path.exists(make_golden.golden_path(name))
+
+
+def _run(name, precision):
+    w = synth.WORKLOADS[name]
+    a, b, mu_o = make_golden.load(name)
+    nv = mu_o.shape[0]
+    s = synth.make_structure(name)
+    print(f"[fullsize] {name}: N={s.n} M={w['M']} R={w['R']} {precision}", flush=True)
+    r = synth.random_phase(s.n, w["R"], w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)
+    pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
+    if precision == "c32":
+        tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, w["R"], "c32")
+        H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32",
+                                    slice=tune.slice)
+        rd = G.to_dev(r)
+        cfg = tune.config
+    else:
+        H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f64", slice=64)
+        rd = G.to_dev(r.astype(np.complex128))
+        cfg = None
+    n = s.n
+    del s, pos, sp
+    mu = tbkpm.kpm_moments(H, a, b, rd, w["M"], precision, config=cfg).cpu().numpy()
+    return n, a, b, mu, mu_o, nv
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fullsize_c32_against_oracle(name):
+    if not _have(name):
+        pytest.skip(f"golden moments for {name} not generated")
+    n, a, b, mu, mu_o, nv = _run(name, "c32")
+    E = synth.energy_grid(a, b)
+    from oracle import oracle as O
+    rho_g = O.kpm_dos(mu[:nv].mean(0), a, b, E)
+    rho_o = O.kpm_dos(mu_o.mean(0), a, b, E)
+    err = G.rel_l2(rho_g, rho_o)
+    dmu = np.abs(mu[:nv] - mu_o).max() / n
+    print(f"[fullsize] {name}: DOS relL2 {err:.3e}, max|dmu|/N {dmu:.3e}", flush=True)
+    assert err <= 1e-4
+    assert dmu <= 1e-4
+    np.testing.assert_allclose(mu[:, 0], n, rtol=1e-6)        # mu_0 = sum |r|^2 for every vector
+
+
+def test_fullsize_fp64_against_oracle():
+    name = "graphene_thermal_1M"
+    if not _have(name):
+        pytest.skip("golden moments not generated")
+    n, a, b, mu, mu_o, nv = _run(name, "f64")
+    dmu = np.abs(mu[:nv] - mu_o).max() / n
+    print(f"[fullsize] {name} FP64: max|dmu|/N {dmu:.3e}", flush=True)
+    assert dmu <= 1e-10
+
+
+def test_fullsize_100M_against_exact_spectrum():
+    name = "graphene_pristine_100M"
+    w = synth.WORKLOADS[name]
+    s = synth.make_structure(name)
+    n = s.n
+    r = synth.random_phase(n, 1, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)
+    pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
+    tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, 1, "c32")
+    H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32", slice=tune.slice)
+    del s, pos, sp
+    a, b = H.scale()
+    assert abs(b) < 1e-12 and a == pytest.approx(1.01 * 8.1, rel=1e-10)
+    Mc = 300
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), Mc, "c32", config=tune.config).cpu().numpy()[0]
+    # 200 x 200 cells: closed walks that wrap the torus need > 300 hops, so moments n < 300 are exact
+    eig = ref.supercell_spectrum(200, 200)
+    tau = ref.trace_moments_from_eigs(eig, a, b, Mc) / eig.size
+    bound = 5.0 / math.sqrt(n)
+    dev = np.abs(mu / n - tau)
+    print(f"[fullsize] 100M vs exact: max dev {dev.max():.3e} (bound {bound:.3e})", flush=True)
+    assert np.all(dev <= bound)
+    assert tau[2] == pytest.approx(2 * 3 * 2.7 ** 2 / a ** 2 - 1, abs=1e-12)
