@@ -268,6 +268,112 @@ tbk_status tbk_autotune(const double *pos, const int32_t *species, int64_t n,
                         int32_t steps, tbk_tune_result *out, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Learned hoppings (radial descriptor + per-bond MLP)                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Model of the learned hoppings.  Per unordered bond {i, j} (r_ij below the
+ * hopping cutoff) the MLP input is x = [f_0..f_7(r_ij) || v_i + v_j] (16
+ * values), standardised as (x - shift) / scale, where v_i = sum_j f(r_ij) over
+ * the descriptor cutoff (node feature of Eq. (2) with identity c_nk) and
+ * f_k(r) = [T_k(2 (r/r_cut - 1)^2 - 1) + 1] / 2 * f_c(r),
+ * f_c(r) = [1 + cos(pi r / r_cut)] / 2 (Eq. (2) radial functions; the cosine
+ * form of the smooth cutoff is this library's choice).  The MLP is
+ * 16 -> 32 -> tanh -> 32 -> tanh -> 1 with parameters (FP32, 1633, device)
+ *   W1 [32][16], b1 [32], W2 [32][32], b2 [32], W3 [32], b3 [1]
+ * and every product uses bfloat16 operands (round to nearest even) with FP32
+ * accumulation.  The hopping is t_ij = t_plain(r_ij) (1 + y_ij).
+ */
+typedef struct {
+    double r_cut;          /* descriptor cutoff (A)                       */
+    int32_t n_radial;      /* radial functions per atom; must be 8        */
+    const double *shift;   /* host [16] feature shifts                    */
+    const double *scale;   /* host [16] feature scales (non-zero)         */
+    const float *params;   /* device [1633] MLP parameters                */
+} tbk_mlp_model;
+
+#define TBK_MLP_PARAMS 1633
+
+/* Node features v [n][n_radial] (device double) of stacked structures (same
+ * structure arguments as tb_build_hamiltonian_batched), cutoff r_cut. */
+tbk_status tbk_descriptor(const double *pos, int32_t n_seg, const int64_t *seg_atoms,
+                          const double *boxes, const int32_t periodic[3], double r_cut,
+                          int32_t n_radial, double *v, void *stream);
+
+/* Unordered bonds i < j (atom indices) within r_cut, ordered by (i, j):
+ * bi, bj int32 and br double (device, capacity cap).  *n_bonds receives the
+ * count; BUFFER_TOO_SMALL (nothing written) if it exceeds cap.
+ * Synchronises `stream`. */
+tbk_status tbk_bonds(const double *pos, int32_t n_seg, const int64_t *seg_atoms,
+                     const double *boxes, const int32_t periodic[3], double r_cut, int64_t cap,
+                     int32_t *bi, int32_t *bj, double *br, int64_t *n_bonds, void *stream);
+
+/* Standardised MLP inputs X [nb][16] as bfloat16 bits (device uint16), one
+ * rounding from double.  shift, scale: host [16]. */
+tbk_status tbk_bond_features(int64_t nb, const int32_t *bi, const int32_t *bj, const double *br,
+                             const double *v, int32_t n_radial, double r_cut, const double *shift,
+                             const double *scale, uint16_t *X, void *stream);
+
+/* Mean and standard deviation (host double [16] each) of the unstandardised
+ * bond features over nb bonds (FP64, fixed summation order); used as the
+ * fixed feature shift and scale of a model.  Synchronises `stream`. */
+tbk_status tbk_feature_moments(int64_t nb, const int32_t *bi, const int32_t *bj, const double *br,
+                               const double *v, int32_t n_radial, double r_cut, double *mean,
+                               double *stddev, void *stream);
+
+/* Synthetic training target of the learned-hopping workload: the residual
+ * y*_b = kappa (z_i + z_j - 2 z0) of a coordination-corrected hopping
+ * t = t_plain (1 + y*), with z_i = v[i][0] (device float [nb] output). */
+tbk_status tbk_coordination_target(int64_t nb, const int32_t *bi, const int32_t *bj,
+                                   const double *v, int32_t n_radial, double kappa, double z0,
+                                   float *y, void *stream);
+
+/* MLP outputs y [nb] (device float) of inputs X (bf16 bits [nb][16]). */
+tbk_status tbk_mlp_forward(int64_t nb, const uint16_t *X, const float *params, float *y,
+                           void *stream);
+
+/* Loss L = (1/nb) sum_b w_b (y_b - y*_b)^2 (w = NULL: all ones) and dL/dparams:
+ * grad device float [1633], loss device double [1] (may be NULL).  Uses `work`
+ * (device, >= tbk_mlp_workspace_size(nb) bytes).  Deterministic. */
+tbk_status tbk_mlp_workspace_size(int64_t nb, int64_t *bytes);
+tbk_status tbk_mlp_loss_grad(int64_t nb, const uint16_t *X, const float *target,
+                             const float *weight, const float *params, float *grad,
+                             double *loss, void *work, int64_t work_bytes, void *stream);
+
+/* One AdamW step (decoupled weight decay) on n FP32 parameters with FP32
+ * moment estimates m, v; t = 1-based step count after this update. */
+tbk_status tbk_adamw_step(int64_t n, float *p, const float *g, float *m, float *v, int64_t t,
+                          double lr, double beta1, double beta2, double eps, double wd,
+                          void *stream);
+
+/* Training loop on the GPU: `epochs` passes over the nb bonds in minibatches
+ * of `batch` (in order), one loss/gradient and one AdamW step per minibatch;
+ * *step counts the updates.  loss_history (host [epochs]) receives each
+ * epoch's mean loss.  work >= tbk_mlp_workspace_size(min(batch, nb)) + 7168
+ * bytes.  Synchronises `stream` once per epoch. */
+tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *target, const float *weight,
+                         float *params, float *m, float *v, int64_t *step, int32_t epochs,
+                         int64_t batch, double lr, double beta1, double beta2, double eps,
+                         double wd, double *loss_history, void *work, int64_t work_bytes,
+                         void *stream);
+
+/*
+ * Learned assembly (inference fused into assembly): as
+ * tb_build_hamiltonian_batched (SELL formats), but each bond's hopping is
+ * t_plain(r) (1 + y) with y the MLP output of the bond, evaluated once per
+ * unordered bond and written to both H_ij and H_ji.  bond_y (device float,
+ * capacity bond_cap, may be NULL) receives y per bond in tbk_bonds order;
+ * *n_bonds (may be NULL) the bond count.  spec_bounds as in the batched build,
+ * from the learned values.
+ */
+tbk_status tb_build_hamiltonian_learned(const double *pos, const int32_t *species, int32_t n_seg,
+                                        const int64_t *seg_atoms, const double *boxes,
+                                        const int32_t periodic[3], const tbk_tb_params *p,
+                                        const tbk_mlp_model *model, tbk_ham *h,
+                                        double *spec_bounds, float *bond_y, int64_t bond_cap,
+                                        int64_t *n_bonds, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* DOS reconstruction                                                        */
 /* ------------------------------------------------------------------------ */
 

@@ -165,3 +165,40 @@ def make_structure(name):
     if w["kind"] == "stripes":
         return hbn_stripes(w["nx"], w["ny"], 50, w["sigma"], w["seed"])
     raise ValueError("use snapshot_set for the snapshot workload")
+
+
+# ---------------------------------------------------------------------------
+# Learned-hopping workload: seeded initial MLP parameters and target constants.
+# ---------------------------------------------------------------------------
+
+MLP_SHAPES = ((32, 16), (32,), (32, 32), (32,), (32,), (1,))   # W1, b1, W2, b2, W3, b3
+MLP_N_PARAMS = 1633
+COORD_KAPPA = 0.25          # strength of the coordination correction of the target hoppings
+COORD_Z0 = 4.7357           # pristine coordination sum_j f_c(r_ij) within 4.0 A (rounded)
+
+
+def init_mlp_params(seed, out_scale=0.1):
+    """Seeded initial parameters (float32): uniform(+-1/sqrt(fan_in)) weights, zero biases,
+    output layer scaled by out_scale."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            lim = 1.0 / math.sqrt(shape[1])
+            parts.append(rng.uniform(-lim, lim, size=shape).reshape(-1))
+        elif shape == (32,) and len(parts) == 4:       # W3
+            parts.append(rng.uniform(-out_scale, out_scale, size=shape) / math.sqrt(32))
+        else:
+            parts.append(np.zeros(shape))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == MLP_N_PARAMS
+    return p
+
+
+def stack(structures):
+    """Concatenate structures: positions, species, segment offsets, boxes."""
+    pos = np.concatenate([s.pos for s in structures])
+    sp = np.concatenate([s.species for s in structures])
+    seg = np.concatenate([[0], np.cumsum([s.n for s in structures])]).astype(np.int64)
+    boxes = np.array([s.box for s in structures])
+    return pos, sp, seg, boxes

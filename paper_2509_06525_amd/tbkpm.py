@@ -50,7 +50,16 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
                "tb_build_hamiltonian", "kpm_workspace_size", "kpm_workspace_size_config",
                "kpm_moments", "kpm_moments_config", "kpm_dos", "tbk_autotune",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
-               "kpm_workspace_size_batched", "kpm_moments_batched")
+               "kpm_workspace_size_batched", "kpm_moments_batched",
+               "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
+               "tbk_coordination_target", "tbk_mlp_forward", "tbk_mlp_workspace_size",
+               "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned")
+
+
+class MlpModel(ctypes.Structure):
+    _fields_ = [("r_cut", ctypes.c_double), ("n_radial", ctypes.c_int32),
+                ("shift", ctypes.POINTER(ctypes.c_double)), ("scale", ctypes.POINTER(ctypes.c_double)),
+                ("params", ctypes.c_void_p)]
 
 
 class KpmConfig(ctypes.Structure):
@@ -119,6 +128,36 @@ def lib():
     L.kpm_moments_batched.restype = ctypes.c_int
     L.kpm_moments_batched.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64), vp,
                                       i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+    u16p = vp
+    L.tbk_descriptor.restype = ctypes.c_int
+    L.tbk_descriptor.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(i32), f64, i32,
+                                 vp, vp]
+    L.tbk_bonds.restype = ctypes.c_int
+    L.tbk_bonds.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(i32), f64, i64,
+                            vp, vp, vp, ctypes.POINTER(i64), vp]
+    L.tbk_bond_features.restype = ctypes.c_int
+    L.tbk_bond_features.argtypes = [i64, vp, vp, vp, vp, i32, f64, ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                    u16p, vp]
+    L.tbk_feature_moments.restype = ctypes.c_int
+    L.tbk_feature_moments.argtypes = [i64, vp, vp, vp, vp, i32, f64, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
+    L.tbk_coordination_target.restype = ctypes.c_int
+    L.tbk_coordination_target.argtypes = [i64, vp, vp, vp, i32, f64, f64, vp, vp]
+    L.tbk_mlp_forward.restype = ctypes.c_int
+    L.tbk_mlp_forward.argtypes = [i64, u16p, vp, vp, vp]
+    L.tbk_mlp_workspace_size.restype = ctypes.c_int
+    L.tbk_mlp_workspace_size.argtypes = [i64, ctypes.POINTER(i64)]
+    L.tbk_mlp_loss_grad.restype = ctypes.c_int
+    L.tbk_mlp_loss_grad.argtypes = [i64, u16p, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.tbk_adamw_step.restype = ctypes.c_int
+    L.tbk_adamw_step.argtypes = [i64, vp, vp, vp, vp, i64, f64, f64, f64, f64, f64, vp]
+    L.tbk_mlp_train.restype = ctypes.c_int
+    L.tbk_mlp_train.argtypes = [i64, u16p, vp, vp, vp, vp, vp, ctypes.POINTER(i64), i32, i64, f64, f64, f64, f64,
+                                f64, ctypes.POINTER(f64), vp, i64, vp]
+    L.tb_build_hamiltonian_learned.restype = ctypes.c_int
+    L.tb_build_hamiltonian_learned.argtypes = [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
+                                               ctypes.POINTER(i32), ctypes.POINTER(TbParams),
+                                               ctypes.POINTER(MlpModel), ctypes.POINTER(HamStruct),
+                                               ctypes.POINTER(f64), vp, i64, ctypes.POINTER(i64), vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     _LIB = L
@@ -373,3 +412,171 @@ def kpm_moments_batched(H, a, b, r, M, precision=None, work=None, mu=None, strea
     _check(L.kpm_moments_batched(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
                                  _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
     return mu
+
+
+# ---------------------------------------------------------------------------
+# Learned hoppings
+# ---------------------------------------------------------------------------
+
+def _segs(seg_atoms, boxes):
+    n_seg = len(seg_atoms) - 1
+    seg = (ctypes.c_int64 * (n_seg + 1))(*[int(v) for v in seg_atoms])
+    bx = (ctypes.c_double * (3 * n_seg))(*[float(v) for b3 in boxes for v in b3])
+    return n_seg, seg, bx
+
+
+def descriptor(pos, seg_atoms, boxes, periodic, r_cut=4.0, n_radial=8, stream=None):
+    """Node features v [N][n_radial] (float64, device)."""
+    pos = _dev(pos, torch.float64)
+    n_seg, seg, bx = _segs(seg_atoms, boxes)
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    v = torch.empty((pos.shape[0], n_radial), dtype=torch.float64, device=pos.device)
+    _check(lib().tbk_descriptor(_ptr(pos), n_seg, seg, bx, per, float(r_cut), int(n_radial), _ptr(v),
+                                _stream(stream)))
+    return v
+
+
+def bonds(pos, seg_atoms, boxes, periodic, r_cut=2.0, stream=None):
+    """Unordered bonds i < j within r_cut: (bi, bj, br) device tensors ordered by (i, j)."""
+    pos = _dev(pos, torch.float64)
+    n_seg, seg, bx = _segs(seg_atoms, boxes)
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    nb = ctypes.c_int64(0)
+    L = lib()
+    # size query: a zero-capacity call reports the count (BUFFER_TOO_SMALL when non-zero)
+    st = L.tbk_bonds(_ptr(pos), n_seg, seg, bx, per, float(r_cut), 0, None, None, None, ctypes.byref(nb),
+                     _stream(stream))
+    if st not in (TBK_OK, 2):
+        _check(st)
+    n = nb.value
+    dev = pos.device
+    bi = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    bj = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    br = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    _check(L.tbk_bonds(_ptr(pos), n_seg, seg, bx, per, float(r_cut), n, _ptr(bi), _ptr(bj), _ptr(br),
+                       ctypes.byref(nb), _stream(stream)))
+    return bi[:n], bj[:n], br[:n]
+
+
+def feature_moments(bonds_, v, r_cut=4.0, stream=None):
+    bi, bj, br = bonds_
+    mean = (ctypes.c_double * 16)()
+    std = (ctypes.c_double * 16)()
+    _check(lib().tbk_feature_moments(bi.numel(), _ptr(bi), _ptr(bj), _ptr(br), _ptr(v), v.shape[1], float(r_cut),
+                                     mean, std, _stream(stream)))
+    return list(mean), list(std)
+
+
+def bond_features(bonds_, v, shift, scale, r_cut=4.0, stream=None):
+    """Standardised MLP inputs as bfloat16 bits: int16 tensor [nb][16]."""
+    bi, bj, br = bonds_
+    nb = bi.numel()
+    X = torch.empty((nb, 16), dtype=torch.int16, device=bi.device)
+    _check(lib().tbk_bond_features(nb, _ptr(bi), _ptr(bj), _ptr(br), _ptr(v), v.shape[1], float(r_cut),
+                                   _f64arr(shift), _f64arr(scale), _ptr(X), _stream(stream)))
+    return X
+
+
+def coordination_target(bonds_, v, kappa, z0, stream=None):
+    bi, bj, _ = bonds_
+    y = torch.empty(bi.numel(), dtype=torch.float32, device=bi.device)
+    _check(lib().tbk_coordination_target(bi.numel(), _ptr(bi), _ptr(bj), _ptr(v), v.shape[1], float(kappa),
+                                         float(z0), _ptr(y), _stream(stream)))
+    return y
+
+
+def mlp_forward(X, params, stream=None):
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib().tbk_mlp_forward(X.shape[0], _ptr(X), _ptr(_dev(params, torch.float32)), _ptr(y), _stream(stream)))
+    return y
+
+
+def mlp_workspace_size(nb):
+    out = ctypes.c_int64(0)
+    _check(lib().tbk_mlp_workspace_size(int(nb), ctypes.byref(out)))
+    return out.value
+
+
+def mlp_loss_grad(X, target, params, weight=None, stream=None):
+    nb = X.shape[0]
+    grad = torch.empty(1633, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    work = torch.empty(mlp_workspace_size(nb), dtype=torch.uint8, device=X.device)
+    _check(lib().tbk_mlp_loss_grad(nb, _ptr(X), _ptr(target), _ptr(weight), _ptr(params), _ptr(grad), _ptr(loss),
+                                   _ptr(work), work.numel(), _stream(stream)))
+    return float(loss.item()), grad
+
+
+def adamw_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-2, stream=None):
+    _check(lib().tbk_adamw_step(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(t), float(lr), float(beta1),
+                                float(beta2), float(eps), float(wd), _stream(stream)))
+
+
+class MlpTrainer:
+    """FP32 parameters and AdamW state on the device; training runs in the library."""
+
+    def __init__(self, params):
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+
+    def train(self, X, target, epochs, batch, lr=3e-3, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-4,
+              weight=None, stream=None):
+        nb = X.shape[0]
+        bsz = min(batch, nb)
+        work = torch.empty(mlp_workspace_size(bsz) + 256 + ((1633 * 4 + 255) // 256) * 256,
+                           dtype=torch.uint8, device=X.device)
+        hist = (ctypes.c_double * epochs)()
+        st = ctypes.c_int64(self.step)
+        _check(lib().tbk_mlp_train(nb, _ptr(X), _ptr(target), _ptr(weight), _ptr(self.params), _ptr(self.m),
+                                   _ptr(self.v), ctypes.byref(st), int(epochs), int(batch), float(lr), float(beta1),
+                                   float(beta2), float(eps), float(wd), hist, _ptr(work), work.numel(),
+                                   _stream(stream)))
+        self.step = st.value
+        return list(hist)
+
+
+def build_hamiltonian_learned(pos, species, seg_atoms, boxes, periodic, onsite, t_pair, params, shift, scale,
+                              r_cut=2.0, r0=1.42, beta=3.37, r_desc=4.0, fmt="sell_f32", slice=64, reorder=True,
+                              with_bond_y=False, stream=None):
+    """Stacked structures with MLP hoppings t = t_plain (1 + y) (inference fused into assembly)."""
+    L = lib()
+    pos = _dev(pos, torch.float64)
+    species = _dev(species, torch.int32)
+    n_seg, seg, bx = _segs(seg_atoms, boxes)
+    p, keep = _params(onsite, t_pair, r_cut, r0, beta, reorder)
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    sh, sc = _f64arr(shift), _f64arr(scale)
+    model = MlpModel(r_cut=float(r_desc), n_radial=8, shift=ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
+                     scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)),
+                     params=_dev(params, torch.float32).data_ptr())
+    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
+    s = _stream(stream)
+    _check(L.tbk_hamiltonian_size_batched(_ptr(pos), _ptr(species), n_seg, seg, bx, per, ctypes.byref(p),
+                                          ctypes.byref(st), s))
+    dev = pos.device
+    n = pos.shape[0]
+    vdt = torch.float32 if fmt == "sell_f32" else torch.float64
+    t = {
+        "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
+        "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),
+        "val": torch.empty(max(st.n_entries, 1), dtype=vdt, device=dev),
+        "onsite": torch.empty(n, dtype=vdt, device=dev),
+        "perm": torch.empty(n, dtype=torch.int32, device=dev),
+        "seg_rows": torch.empty(n_seg + 1, dtype=torch.int64, device=dev),
+    }
+    st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
+    st.onsite, st.perm, st.seg_rows = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["seg_rows"].data_ptr()
+    nbonds = st.n_bonds
+    y = torch.empty(max(nbonds, 1), dtype=torch.float32, device=dev) if with_bond_y else None
+    bounds = (ctypes.c_double * (2 * n_seg))()
+    nb_out = ctypes.c_int64(0)
+    _check(L.tb_build_hamiltonian_learned(_ptr(pos), _ptr(species), n_seg, seg, bx, per, ctypes.byref(p),
+                                          ctypes.byref(model), ctypes.byref(st), bounds, _ptr(y),
+                                          nbonds if y is not None else 0, ctypes.byref(nb_out), s))
+    del keep
+    H = BatchedHamiltonian(st, t, [(bounds[2 * k], bounds[2 * k + 1]) for k in range(n_seg)])
+    if with_bond_y:
+        H.bond_y = y[:nb_out.value]
+    return H
