@@ -181,6 +181,10 @@ typedef struct {
     int32_t xcd_remap;          /* 1: each XCD sweeps a contiguous eighth of rows   */
     int32_t rows_per_thread;    /* 1 or 2: rows (from consecutive tiles) a thread
                                    advances together                               */
+    int32_t persistent;         /* kpm_moments_batched only: 1 = all steps in one
+                                   cooperative launch (a team of workgroups per
+                                   structure, barrier per step); 0 = one launch
+                                   per step                                        */
 } tbk_kpm_config;
 
 /* Bytes of device workspace kpm_moments needs for (h, R, M, precision) with the
@@ -226,7 +230,10 @@ tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b
  * [n_rows][R] in the caller's stacked atom order.  The workspace size depends
  * on the structures' sizes and is queried with kpm_workspace_size_batched
  * (which reads h->seg_rows and synchronises `stream`).  Launch shapes as in
- * kpm_moments_config (xcd_remap and rows_per_thread are not used here).
+ * kpm_moments_config (xcd_remap and rows_per_thread are not used here); with
+ * cfg->persistent = 1 all M - 1 steps run in one cooperative launch (DEVICE if a
+ * team barrier times out; UNSUPPORTED with more structures than co-resident
+ * workgroups).
  * Errors as kpm_moments; SPECTRUM if any structure's moments leave [-mu_0, mu_0].
  */
 tbk_status kpm_workspace_size_batched(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,

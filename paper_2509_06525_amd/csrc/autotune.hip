@@ -62,6 +62,7 @@ void load_file_cache() {
     while (std::fgets(line, sizeof line, f)) {
         char key[512];
         tbk_tune_result r{};
+        r.config.persistent = 0;
         if (std::sscanf(line, "%511s %d %d %d %d %d %d %lf", key, &r.slice, &r.config.vectors_per_thread,
                         &r.config.tiles_per_block, &r.config.nontemporal, &r.config.xcd_remap,
                         &r.config.rows_per_thread, &r.ms_per_step) == 8) {
@@ -236,6 +237,7 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
                             c.rows_per_thread = rpt;
                             c.nontemporal = nt;
                             c.xcd_remap = xr;
+                            c.persistent = 0;
                             double ms = 0.0;
                             st = time_shape(*hp, c, R, steps, precision, a, b, rbuf.as<void>(),
                                             mubuf.as<double>(), s, &ms);

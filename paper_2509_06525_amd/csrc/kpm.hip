@@ -406,6 +406,7 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.nontemporal = 1;
     c.xcd_remap = 0;
     c.rows_per_thread = 1;
+    c.persistent = 0;
     (void)h;
     return c;
 }
@@ -438,6 +439,7 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     TBK_CHECK(pl.cfg.xcd_remap == 0 || pl.cfg.xcd_remap == 1, TBK_ERR_INVALID_ARG, "xcd_remap must be 0/1");
     TBK_CHECK(pl.cfg.rows_per_thread == 1 || pl.cfg.rows_per_thread == 2, TBK_ERR_INVALID_ARG,
               "rows_per_thread must be 1 or 2");
+    TBK_CHECK(pl.cfg.persistent == 0 || pl.cfg.persistent == 1, TBK_ERR_INVALID_ARG, "persistent must be 0/1");
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;
@@ -558,5 +560,6 @@ extern "C" tbk_status kpm_moments_config(const tbk_ham *h, const double *a, cons
     if (st != TBK_OK) return st;
     st = check_moment_args(h, pl, a, b, r, work, work_bytes, mu);
     if (st != TBK_OK) return st;
+    TBK_CHECK(pl.cfg.persistent == 0, TBK_ERR_INVALID_ARG, "the persistent launch is for kpm_moments_batched");
     return run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream));
 }

@@ -10,6 +10,7 @@
 // reproducible), giving mu[s][v][n].
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.hpp"
@@ -21,6 +22,18 @@ namespace tbk {
 namespace {
 
 constexpr size_t kSegPartialBudget = 256ull << 20;
+constexpr int kPersistPerCU = 4;
+
+// Poll limit of the persistent team barrier (about 2^26 polls of ~100 cycles,
+// seconds); TBKPM_BARRIER_SPIN_LIMIT overrides it (tests force a timeout).
+int64_t barrier_spin_limit() {
+    const char *e = std::getenv("TBKPM_BARRIER_SPIN_LIMIT");
+    if (e) {
+        const long long v = std::atoll(e);
+        if (v >= 1) return v;
+    }
+    return (int64_t)1 << 26;
+}
 
 // tile_row0[t], tile_seg[t] for the tiles of segment s (one block per segment).
 __global__ void k_tile_table(const int64_t *__restrict__ seg_rows, const int64_t *__restrict__ tile_off, int32_t rpb,
@@ -53,12 +66,11 @@ template <class VT> struct SegStep {
     int32_t tiles_per_block;
 };
 
-// One step for every segment: block b handles tiles_per_block consecutive tiles
-// of the table, one partial per tile.  Rows past the end of a tile's segment are
-// clamped to the segment's last row for their loads and masked for the rest.
+// One row of tile t for this thread: T_{n+1} of the row and its overlap with
+// r added to acc.  Rows past the end of the tile's segment are clamped to the
+// segment's last row for their loads and masked for the rest.
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, int W>
-__global__ __launch_bounds__(kThreads) void k_cheb_step_seg(SegStep<VT> a) {
-    constexpr int RPB = kThreads / L;
+__device__ __forceinline__ void seg_tile_row(const SegStep<VT> &a, int64_t t, double (&acc)[VPT]) {
     constexpr int KU = W > 0 ? W : 4;
     const int lr = threadIdx.x / L;
     const int vs = threadIdx.x % L;
@@ -66,73 +78,168 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_seg(SegStep<VT> a) {
     const int Rp = a.Rp;
     const int64_t smask = ((int64_t)1 << a.log2_slice) - 1;
     const int64_t stride = smask + 1;
+    const int sg = a.tile_seg[t];
+    const int64_t row_end = a.seg_rows[sg + 1];
+    const int64_t iu = a.tile_row0[t] + lr;
+    const bool ok = iu < row_end;
+    const int64_t i = min(iu, row_end - 1);
+    const int64_t off = 2 * (i * Rp + voff);
+    const int64_t sl = i >> a.log2_slice;
+    const int64_t p0 = a.ptr[sl], p1 = a.ptr[sl + 1];
+    const int64_t base = p0 + (i & smask);
+    const int w = W > 0 ? W : (int)((p1 - p0) >> a.log2_slice);
+    const VT c1 = a.c1[sg];
+    Pack<VT, VPT> pv, rv;
+    VT dg = 0;
+    if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(a.tprev + off);
+    rv = load_pack<NT, VT, VPT>(a.r + off);
+    if constexpr (DIAG) dg = (a.onsite ? ld<NT>(a.onsite + i) : (VT)0) - a.shift[sg];
+    Pack<VT, VPT> y;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) { y.re[q] = 0; y.im[q] = 0; }
+    for (int k0 = 0; k0 < w; k0 += KU) {
+        int32_t c[KU];
+        VT h[KU];
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+            if constexpr (W > 0) {
+                c[k] = ld<NT>(a.col + base + k * stride);
+                h[k] = ld<NT>(a.val + base + k * stride);
+            } else {
+                const int kk = min(k0 + k, w - 1);
+                c[k] = ld<NT>(a.col + base + kk * stride);
+                h[k] = (k0 + k < w) ? ld<NT>(a.val + base + kk * stride) : (VT)0;
+            }
+        }
+        Pack<VT, VPT> x[KU];
+#pragma unroll
+        for (int k = 0; k < KU; ++k) x[k] = load_pack<false, VT, VPT>(a.tcur + 2 * ((int64_t)c[k] * Rp + voff));
+#pragma unroll
+        for (int k = 0; k < KU; ++k)
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) { y.re[q] += h[k] * x[k].re[q]; y.im[q] += h[k] * x[k].im[q]; }
+    }
+    if constexpr (DIAG) {
+        Pack<VT, VPT> x = load_pack<false, VT, VPT>(a.tcur + off);
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) { y.re[q] += dg * x.re[q]; y.im[q] += dg * x.im[q]; }
+    }
+    Pack<VT, VPT> o;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+        if constexpr (FIRST) { o.re[q] = c1 * y.re[q]; o.im[q] = c1 * y.im[q]; }
+        else { o.re[q] = c1 * y.re[q] - pv.re[q]; o.im[q] = c1 * y.im[q] - pv.im[q]; }
+    }
+    if (ok) {
+        store_pack<NT, VT, VPT>(a.tnext + off, o);
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            acc[q] += (double)rv.re[q] * (double)o.re[q] + (double)rv.im[q] * (double)o.im[q];
+    }
+}
+
+// One step for every segment: block b handles tiles_per_block consecutive
+// tiles of the table and writes one partial per tile.
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, int W>
+__global__ __launch_bounds__(kThreads) void k_cheb_step_seg(SegStep<VT> a) {
     const int64_t t0 = (int64_t)blockIdx.x * a.tiles_per_block;
     const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
     for (int64_t t = t0; t < t1; ++t) {
-        const int sg = a.tile_seg[t];
-        const int64_t row_end = a.seg_rows[sg + 1];
-        const int64_t iu = a.tile_row0[t] + lr;
-        const bool ok = iu < row_end;
-        const int64_t i = min(iu, row_end - 1);
-        const int64_t off = 2 * (i * Rp + voff);
-        const int64_t sl = i >> a.log2_slice;
-        const int64_t p0 = a.ptr[sl], p1 = a.ptr[sl + 1];
-        const int64_t base = p0 + (i & smask);
-        const int w = W > 0 ? W : (int)((p1 - p0) >> a.log2_slice);
-        const VT c1 = a.c1[sg];
-        Pack<VT, VPT> pv, rv;
-        VT dg = 0;
-        if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(a.tprev + off);
-        rv = load_pack<NT, VT, VPT>(a.r + off);
-        if constexpr (DIAG) dg = (a.onsite ? ld<NT>(a.onsite + i) : (VT)0) - a.shift[sg];
-        Pack<VT, VPT> y;
+        double acc[VPT];
 #pragma unroll
-        for (int q = 0; q < VPT; ++q) { y.re[q] = 0; y.im[q] = 0; }
-        for (int k0 = 0; k0 < w; k0 += KU) {
-            int32_t c[KU];
-            VT h[KU];
-#pragma unroll
-            for (int k = 0; k < KU; ++k) {
-                if constexpr (W > 0) {
-                    c[k] = ld<NT>(a.col + base + k * stride);
-                    h[k] = ld<NT>(a.val + base + k * stride);
-                } else {
-                    const int kk = min(k0 + k, w - 1);
-                    c[k] = ld<NT>(a.col + base + kk * stride);
-                    h[k] = (k0 + k < w) ? ld<NT>(a.val + base + kk * stride) : (VT)0;
-                }
-            }
-            Pack<VT, VPT> x[KU];
-#pragma unroll
-            for (int k = 0; k < KU; ++k) x[k] = load_pack<false, VT, VPT>(a.tcur + 2 * ((int64_t)c[k] * Rp + voff));
-#pragma unroll
-            for (int k = 0; k < KU; ++k)
-#pragma unroll
-                for (int q = 0; q < VPT; ++q) { y.re[q] += h[k] * x[k].re[q]; y.im[q] += h[k] * x[k].im[q]; }
-        }
-        if constexpr (DIAG) {
-            Pack<VT, VPT> x = load_pack<false, VT, VPT>(a.tcur + off);
-#pragma unroll
-            for (int q = 0; q < VPT; ++q) { y.re[q] += dg * x.re[q]; y.im[q] += dg * x.im[q]; }
-        }
-        Pack<VT, VPT> o;
-#pragma unroll
-        for (int q = 0; q < VPT; ++q) {
-            if constexpr (FIRST) { o.re[q] = c1 * y.re[q]; o.im[q] = c1 * y.im[q]; }
-            else { o.re[q] = c1 * y.re[q] - pv.re[q]; o.im[q] = c1 * y.im[q] - pv.im[q]; }
+        for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
+        seg_tile_row<VT, L, VPT, FIRST, DIAG, NT, W>(a, t, acc);
+        block_reduce_store<L, VPT>(acc, a.partial, t);
+        __syncthreads();   // the reduction's LDS is reused by the next tile
+    }
+}
+
+// Persistent form: one launch runs all M - 1 steps.  Structure s is served by
+// a team of workgroups [boff[s], boff[s+1]); each member owns a contiguous
+// range of the structure's tiles and writes one partial per step
+// (bpart[n][block][v]).  After each step the team meets at a barrier: a
+// monotone counter per structure in global memory, incremented once per
+// member and step, with agent-scope fences on both sides.  The wait is
+// bounded: past `spin_limit` polls, or when another block has raised the
+// abort flag, the block raises the flag and leaves, so every wave exits.
+struct PersistArgs {
+    const int32_t *block_seg;   // [G] structure of each workgroup
+    const int64_t *boff;        // [n_seg + 1] team block ranges
+    const int64_t *tile_off;    // [n_seg + 1] tile ranges
+    double *bpart;              // [M][G][Rp]
+    uint32_t *bar;              // [n_seg] step counters (zero at launch)
+    int32_t *abort_flag;        // 0 at launch
+    int32_t M;
+    int64_t spin_limit;
+};
+
+template <class VT> struct PersistBufs {
+    VT *r_int, *TA, *TB;
+    const VT *c1f, *c1;
+};
+
+template <class VT, int L, int VPT, bool DIAG, bool NT, int W>
+__global__ __launch_bounds__(kThreads) void k_cheb_persistent(SegStep<VT> a, PersistBufs<VT> bufs, PersistArgs pa) {
+    __shared__ int32_t s_abort;
+    const int64_t b = blockIdx.x;
+    const int sg = pa.block_seg[b];
+    const int64_t k = pa.boff[sg + 1] - pa.boff[sg], j = b - pa.boff[sg];
+    const int64_t T0 = pa.tile_off[sg], Ts = pa.tile_off[sg + 1] - T0;
+    const int64_t t0 = T0 + (Ts * j) / k, t1 = T0 + (Ts * (j + 1)) / k;
+    const int64_t G = gridDim.x;
+    for (int n = 1; n < pa.M; ++n) {
+        SegStep<VT> st = a;
+        if (n == 1) { st.tcur = bufs.r_int; st.tprev = nullptr; st.tnext = bufs.TB; st.c1 = bufs.c1f; }
+        else if (n == 2) { st.tcur = bufs.TB; st.tprev = bufs.r_int; st.tnext = bufs.TA; st.c1 = bufs.c1; }
+        else {
+            VT *cur = (n & 1) ? bufs.TA : bufs.TB;
+            VT *old = (n & 1) ? bufs.TB : bufs.TA;
+            st.tcur = cur; st.tprev = old; st.tnext = old; st.c1 = bufs.c1;
         }
         double acc[VPT];
 #pragma unroll
         for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
-        if (ok) {
-            store_pack<NT, VT, VPT>(a.tnext + off, o);
-#pragma unroll
-            for (int q = 0; q < VPT; ++q)
-                acc[q] = (double)rv.re[q] * (double)o.re[q] + (double)rv.im[q] * (double)o.im[q];
+        for (int64_t t = t0; t < t1; ++t) {
+            if (n == 1) seg_tile_row<VT, L, VPT, true, DIAG, NT, W>(st, t, acc);
+            else seg_tile_row<VT, L, VPT, false, DIAG, NT, W>(st, t, acc);
         }
-        block_reduce_store<L, VPT>(acc, a.partial, t);
-        __syncthreads();   // the reduction's LDS is reused by the next tile
+        block_reduce_store<L, VPT>(acc, pa.bpart + ((int64_t)n * G) * a.Rp, b);
+        if (n + 1 == pa.M) break;
+        // team barrier
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_abort = 0;
+            __threadfence();
+            atomicAdd(&pa.bar[sg], 1u);
+            const uint32_t target = (uint32_t)((int64_t)n * k);
+            int64_t spins = 0;
+            while (__hip_atomic_load(&pa.bar[sg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spins > pa.spin_limit ||
+                    __hip_atomic_load(pa.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    atomicOr(pa.abort_flag, 1);
+                    s_abort = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __threadfence();
+        }
+        __syncthreads();
+        if (s_abort) return;
     }
+}
+
+// mu[s][v][n] = sum over the team blocks of s of bpart[n][b][v], in block
+// order; grid = (n_seg, ceil(M / 64)), one thread per (moment, vector).
+__global__ void k_reduce_persistent(const double *__restrict__ bpart, int64_t G, const int64_t *__restrict__ boff,
+                                    int32_t Rp, int32_t R, int32_t M, double *__restrict__ mu) {
+    const int s = blockIdx.x;
+    const int idx = R + blockIdx.y * blockDim.x + threadIdx.x;     // moments n >= 1
+    if (idx >= M * R) return;
+    const int n = idx / R, v = idx % R;
+    double acc = 0.0;
+    for (int64_t b = boff[s]; b < boff[s + 1]; ++b) acc += bpart[((int64_t)n * G + b) * Rp + v];
+    mu[((int64_t)s * R + v) * M + n] = acc;
 }
 
 // r_int[i][v] = r[perm[i]][v] (v < R, zero for padded vectors) and the tile
@@ -202,6 +309,12 @@ struct SegPlan {
     std::vector<int64_t> seg_rows;   // host copy
     std::vector<int64_t> tile_off;   // host [n_seg + 1]
     int K = 1;
+    // persistent launch
+    bool persistent = false;
+    int64_t Gp = 0;                  // workgroups of the persistent launch
+    std::vector<int64_t> boff;       // [n_seg + 1] team block ranges
+    std::vector<int32_t> block_seg;  // [Gp]
+    size_t off_bpart = 0, off_boff = 0, off_bseg = 0, off_bar = 0;
     size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_row0 = 0, off_tseg = 0, off_toff = 0,
            off_c1f = 0, off_c1 = 0, off_shift = 0, off_flag = 0, total = 0;
 };
@@ -245,6 +358,43 @@ tbk_status make_seg_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precisi
     sp.off_shift = sp.off_c1 + a256(ve * sp.n_seg);
     sp.off_flag = sp.off_shift + a256(ve * sp.n_seg);
     sp.total = sp.off_flag + 256;
+    sp.persistent = sp.base.cfg.persistent != 0;
+    if (sp.persistent) {
+        int dev = 0, cus = 0;
+        TBK_HIP(hipGetDevice(&dev));
+        TBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        // four co-resident 256-thread workgroups per CU (checked against the
+        // kernel's occupancy before the launch; the cooperative launch also
+        // refuses a grid that cannot be resident at once)
+        const int64_t gmax = (int64_t)cus * kPersistPerCU;
+        sp.Gp = std::min<int64_t>(gmax, std::max<int64_t>(sp.n_tiles, sp.n_seg));
+        TBK_CHECK(sp.n_seg <= sp.Gp, TBK_ERR_UNSUPPORTED,
+                  "persistent launch needs one workgroup per structure (%d structures, %lld workgroups)", sp.n_seg,
+                  (long long)sp.Gp);
+        // team sizes proportional to tiles, at least one each
+        sp.boff.assign(sp.n_seg + 1, 0);
+        std::vector<int64_t> ks(sp.n_seg);
+        int64_t used = 0;
+        for (int g = 0; g < sp.n_seg; ++g) {
+            const int64_t Ts = sp.tile_off[g + 1] - sp.tile_off[g];
+            ks[g] = 1 + ((sp.Gp - sp.n_seg) * Ts) / std::max<int64_t>(sp.n_tiles, 1);
+            ks[g] = std::min<int64_t>(ks[g], Ts);
+            used += ks[g];
+        }
+        sp.Gp = used;
+        sp.block_seg.resize(sp.Gp);
+        for (int g = 0; g < sp.n_seg; ++g) {
+            sp.boff[g + 1] = sp.boff[g] + ks[g];
+            for (int64_t b = sp.boff[g]; b < sp.boff[g + 1]; ++b) sp.block_seg[b] = g;
+        }
+        const size_t bpart = (size_t)M * sp.Gp * sp.base.Rp * sizeof(double);
+        TBK_CHECK(bpart <= (4ull << 30), TBK_ERR_UNSUPPORTED, "persistent partials would need %zu bytes", bpart);
+        sp.off_bpart = sp.total;
+        sp.off_boff = sp.off_bpart + a256(bpart);
+        sp.off_bseg = sp.off_boff + a256(sizeof(int64_t) * (sp.n_seg + 1));
+        sp.off_bar = sp.off_bseg + a256(sizeof(int32_t) * sp.Gp);
+        sp.total = sp.off_bar + a256(sizeof(uint32_t) * sp.n_seg + 64);
+    }
     return TBK_OK;
 }
 
@@ -311,6 +461,49 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
     st.log2_slice = sp.base.log2_slice;
     st.Rp = Rp;
     st.tiles_per_block = sp.base.cfg.tiles_per_block;
+    if (sp.persistent) {
+        // moment 0 from the tile partials of |r|^2
+        {
+            dim3 grid(ns, 1);
+            k_reduce_seg<<<grid, kThreads, 0, s>>>(part, T, toff, Rp, R, M, 0, mu);
+            TBK_HIP(hipGetLastError());
+        }
+        double *bpart = reinterpret_cast<double *>(w + sp.off_bpart);
+        int64_t *boff = reinterpret_cast<int64_t *>(w + sp.off_boff);
+        int32_t *bseg = reinterpret_cast<int32_t *>(w + sp.off_bseg);
+        uint32_t *bar = reinterpret_cast<uint32_t *>(w + sp.off_bar);
+        int32_t *abort_flag = reinterpret_cast<int32_t *>(bar + ns);
+        TBK_HIP(hipMemcpyAsync(boff, sp.boff.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s));
+        TBK_HIP(hipMemcpyAsync(bseg, sp.block_seg.data(), sizeof(int32_t) * sp.Gp, hipMemcpyHostToDevice, s));
+        TBK_HIP(hipMemsetAsync(bar, 0, sizeof(uint32_t) * ns + 64, s));
+        PersistBufs<VT> bufs{r_int, TA, TB, c1f, c1};
+        PersistArgs pa{bseg, boff, toff, bpart, bar, abort_flag, M, barrier_spin_limit()};
+        void *args[] = {&st, &bufs, &pa};
+        const bool w3 = sp.base.uniform_width == 3;
+        const void *fn;
+        if (sp.base.cfg.nontemporal)
+            fn = diag ? (w3 ? (const void *)k_cheb_persistent<VT, L, VPT, true, true, 3>
+                            : (const void *)k_cheb_persistent<VT, L, VPT, true, true, 0>)
+                      : (w3 ? (const void *)k_cheb_persistent<VT, L, VPT, false, true, 3>
+                            : (const void *)k_cheb_persistent<VT, L, VPT, false, true, 0>);
+        else
+            fn = diag ? (w3 ? (const void *)k_cheb_persistent<VT, L, VPT, true, false, 3>
+                            : (const void *)k_cheb_persistent<VT, L, VPT, true, false, 0>)
+                      : (w3 ? (const void *)k_cheb_persistent<VT, L, VPT, false, false, 3>
+                            : (const void *)k_cheb_persistent<VT, L, VPT, false, false, 0>);
+        int occ = 0;
+        TBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, 0));
+        TBK_CHECK(occ >= kPersistPerCU, TBK_ERR_UNSUPPORTED, "persistent kernel fits %d workgroups per CU, needs %d",
+                  occ, kPersistPerCU);
+        TBK_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)sp.Gp), dim3(kThreads), args, 0, s));
+        dim3 rg(ns, (unsigned)ceil_div((int64_t)(M - 1) * R, 256));
+        k_reduce_persistent<<<rg, 256, 0, s>>>(bpart, sp.Gp, boff, Rp, R, M, mu);
+        TBK_HIP(hipGetLastError());
+        int32_t habort = 0;
+        TBK_HIP(hipMemcpyAsync(&habort, abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TBK_HIP(hipStreamSynchronize(s));
+        TBK_CHECK(habort == 0, TBK_ERR_DEVICE, "persistent recurrence: a team barrier timed out");
+    } else {
     const unsigned G = (unsigned)ceil_div(T, sp.base.cfg.tiles_per_block);
     const int K = sp.K;
     auto reduce = [&](int n0, int count) {
@@ -343,6 +536,7 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
     }
     reduce(batch0, M - batch0);
     TBK_HIP(hipGetLastError());
+    }
     TBK_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     const int64_t rows = (int64_t)ns * R;
     k_guard_seg<<<(unsigned)ceil_div(rows * M, 256), 256, 0, s>>>(mu, rows, M, flag);

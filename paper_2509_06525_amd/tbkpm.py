@@ -65,7 +65,7 @@ class MlpModel(ctypes.Structure):
 class KpmConfig(ctypes.Structure):
     _fields_ = [("vectors_per_thread", ctypes.c_int32), ("tiles_per_block", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("rows_per_thread", ctypes.c_int32)]
+                ("rows_per_thread", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,8 +76,9 @@ class TuneResult(ctypes.Structure):
                 ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
-def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1):
-    return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread)
+def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1,
+                persistent=0):
+    return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread, persistent)
 
 
 def lib():

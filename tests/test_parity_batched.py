@@ -58,14 +58,14 @@ def test_batched_builder_per_structure(fmt, slice):
 
 
 @pytest.mark.parametrize("R", [1, 3, 8])
-@pytest.mark.parametrize("tpb,nt", [(1, 1), (3, 0), (2, 1)])
-def test_batched_fp64_moments_per_structure(R, tpb, nt):
+@pytest.mark.parametrize("tpb,nt,persistent", [(1, 1, 0), (3, 0, 0), (2, 1, 0), (1, 1, 1), (1, 0, 1)])
+def test_batched_fp64_moments_per_structure(R, tpb, nt, persistent):
     sheets, pos, sp, seg, boxes = make_batch()
     H = build(pos, sp, seg, boxes, "sell_f64", 16)
     a, b = H.scales()
     M = 64
     r = synth.random_phase(pos.shape[0], R, 11)
-    cfg = tbkpm.make_config(1, tpb, nt, 0, 1)
+    cfg = tbkpm.make_config(1, tpb, nt, 0, 1, persistent)
     mu = tbkpm.kpm_moments_batched(H, a, b, G.to_dev(r), M, "f64", config=cfg).cpu().numpy()
     assert mu.shape == (len(sheets), R, M)
     for k, s in enumerate(sheets):
@@ -87,14 +87,15 @@ def test_batched_equals_single_structure_calls():
         assert np.abs(mu_b[k] - mu1).max() <= 1e-12 * s.n
 
 
-def test_batched_c32_dos():
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_batched_c32_dos(persistent):
     sheets, pos, sp, seg, boxes = make_batch([(30, 26, 0.05), (11, 19, 0.07), (45, 40, 0.02)])
     H = build(pos, sp, seg, boxes, "sell_f32", 64)
     a, b = H.scales()
     M = 256
     r = synth.random_phase(pos.shape[0], 8, 13, np.complex64)
     mu = tbkpm.kpm_moments_batched(H, a, b, G.to_dev(r), M, "c32",
-                                   config=tbkpm.make_config(2, 2, 1, 0, 1)).cpu().numpy()
+                                   config=tbkpm.make_config(2, 2, 1, 0, 1, persistent)).cpu().numpy()
     for k, s in enumerate(sheets):
         csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
         mu_o, _ = O.kpm_moments(csr, a[k], b[k], r[seg[k]:seg[k + 1]].astype(np.complex128), M)
@@ -121,3 +122,32 @@ def test_batched_errors():
     with pytest.raises(tbkpm.TBKError) as e:
         tbkpm.kpm_moments_batched(H, a, b, G.to_dev(synth.random_phase(pos.shape[0], 1, 1)), 128, "f64")
     assert e.value.name == "SPECTRUM"
+
+
+def test_persistent_equals_launch_per_step():
+    sheets, pos, sp, seg, boxes = make_batch()
+    H = build(pos, sp, seg, boxes, "sell_f32", 64)
+    a, b = H.scales()
+    r = G.to_dev(synth.random_phase(pos.shape[0], 4, 21, np.complex64))
+    m0 = tbkpm.kpm_moments_batched(H, a, b, r, 200, "c32", config=tbkpm.make_config(2, 1, 1, 0, 1, 0))
+    m1 = tbkpm.kpm_moments_batched(H, a, b, r, 200, "c32", config=tbkpm.make_config(2, 1, 1, 0, 1, 1))
+    m2 = tbkpm.kpm_moments_batched(H, a, b, r, 200, "c32", config=tbkpm.make_config(2, 1, 1, 0, 1, 1))
+    n = np.diff(seg)[:, None, None]
+    assert (np.abs((m0 - m1).cpu().numpy()) <= 1e-12 * n).all()
+    torch.testing.assert_close(m1, m2, rtol=0, atol=0)          # bitwise reproducible
+
+
+def test_persistent_barrier_timeout_is_reported(monkeypatch):
+    """A host-forced poll limit of 1 makes the team barriers give up: the call
+    returns DEVICE and every workgroup exits (no hang); the next call works."""
+    sheets, pos, sp, seg, boxes = make_batch()
+    H = build(pos, sp, seg, boxes, "sell_f64", 32)
+    a, b = H.scales()
+    r = G.to_dev(synth.random_phase(pos.shape[0], 1, 5))
+    monkeypatch.setenv("TBKPM_BARRIER_SPIN_LIMIT", "1")
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.kpm_moments_batched(H, a, b, r, 400, "f64", config=tbkpm.make_config(1, 1, 1, 0, 1, 1))
+    assert e.value.name == "DEVICE"
+    monkeypatch.delenv("TBKPM_BARRIER_SPIN_LIMIT")
+    mu = tbkpm.kpm_moments_batched(H, a, b, r, 40, "f64", config=tbkpm.make_config(1, 1, 1, 0, 1, 1))
+    assert torch.isfinite(mu).all()
