@@ -185,6 +185,10 @@ typedef struct {
                                    cooperative launch (a team of workgroups per
                                    structure, barrier per step); 0 = one launch
                                    per step                                        */
+    int32_t doubling;           /* kpm_moments only: 1 = two moments per step from
+                                   mu_2k = 2<T_k|T_k> - mu_0 and
+                                   mu_2k-1 = 2 Re<T_k|T_k-1> - mu_1 (exact for
+                                   Hermitian H; M/2 steps and no read of r)        */
 } tbk_kpm_config;
 
 /* Bytes of device workspace kpm_moments needs for (h, R, M, precision) with the

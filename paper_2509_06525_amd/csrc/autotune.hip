@@ -63,6 +63,7 @@ void load_file_cache() {
         char key[512];
         tbk_tune_result r{};
         r.config.persistent = 0;
+        r.config.doubling = 0;
         if (std::sscanf(line, "%511s %d %d %d %d %d %d %lf", key, &r.slice, &r.config.vectors_per_thread,
                         &r.config.tiles_per_block, &r.config.nontemporal, &r.config.xcd_remap,
                         &r.config.rows_per_thread, &r.ms_per_step) == 8) {
@@ -238,6 +239,7 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
                             c.nontemporal = nt;
                             c.xcd_remap = xr;
                             c.persistent = 0;
+                            c.doubling = 0;
                             double ms = 0.0;
                             st = time_shape(*hp, c, R, steps, precision, a, b, rbuf.as<void>(),
                                             mubuf.as<double>(), s, &ms);

@@ -49,7 +49,7 @@ template <class VT> struct StepScalars {
 // Rows past the end are clamped to the last row for their loads (always in
 // bounds) and neither stored nor counted; entries past a slice's width are
 // clamped to its last entry and weighted by zero.
-template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int RPT, int W>
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int RPT, int W, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_cheb_step(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, const VT *__restrict__ val,
     const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
@@ -67,9 +67,10 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
     const int voff = vs * VPT;
     const int64_t last = a.n_rows - 1;
 
-    double acc[VPT];
+    constexpr int NA = DBL ? 2 * VPT : VPT;   // sums per thread
+    double acc[NA];
 #pragma unroll
-    for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
 
     for (int64_t t = t0; t < t1; t += RPT) {
         int64_t i[RPT], base[RPT], off[RPT];
@@ -101,7 +102,9 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
             if constexpr (!FIRST) pv[u] = load_pack<NT, VT, VPT>(tprev + off[u]);
-            rv[u] = load_pack<NT, VT, VPT>(r + off[u]);
+            // direct form: the start vector; doubling form: the row's own T_n
+            if constexpr (DBL) rv[u] = load_pack<false, VT, VPT>(tcur + off[u]);
+            else rv[u] = load_pack<NT, VT, VPT>(r + off[u]);
             if constexpr (DIAG) dg[u] = (onsite ? ld<NT>(onsite + i[u]) : (VT)0) - a.shift;
         }
         Pack<VT, VPT> y[RPT];
@@ -173,16 +176,24 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
             if (ok[u]) {
                 store_pack<NT, VT, VPT>(tnext + off[u], o);
 #pragma unroll
-                for (int q = 0; q < VPT; ++q)
-                    acc[q] += (double)rv[u].re[q] * (double)o.re[q] + (double)rv[u].im[q] * (double)o.im[q];
+                for (int q = 0; q < VPT; ++q) {
+                    const double cr = (double)rv[u].re[q] * (double)o.re[q] + (double)rv[u].im[q] * (double)o.im[q];
+                    if constexpr (DBL) {
+                        acc[q] += (double)o.re[q] * (double)o.re[q] + (double)o.im[q] * (double)o.im[q];
+                        acc[VPT + q] += cr;
+                    } else {
+                        acc[q] += cr;
+                    }
+                }
             }
         }
     }
-    block_reduce_store<L, VPT>(acc, partial, lb);
+    block_reduce_store<L, NA>(acc, partial, lb);
 }
 
-// r_int[i][v] = r[perm[i]][v] (v < R), 0 for padded vectors; block partials of |r|^2.
-template <class VT, int L, int VPT>
+// r_int[i][v] = r[perm[i]][v] (v < R), 0 for padded vectors; block partials of
+// |r|^2 (in the doubling layout, each followed by VPT zeros).
+template <class VT, int L, int VPT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, const int32_t *__restrict__ perm,
                                                       int64_t n_rows, int32_t R, int32_t Rp,
                                                       VT *__restrict__ r_int, double *__restrict__ partial) {
@@ -204,7 +215,33 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
             acc[q] += (double)re * (double)re + (double)im * (double)im;
         }
     }
-    block_reduce_store<L, VPT>(acc, partial, blockIdx.x);
+    if constexpr (DBL) {
+        double acc2[2 * VPT];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) { acc2[q] = acc[q]; acc2[VPT + q] = 0.0; }
+        block_reduce_store<L, 2 * VPT>(acc2, partial, blockIdx.x);
+    } else {
+        block_reduce_store<L, VPT>(acc, partial, blockIdx.x);
+    }
+}
+
+// Doubling identities for a Hermitian Ht (T_m T_n = (T_{m+n} + T_{|m-n|})/2):
+// with a[v][k] = <T_k|T_k> and b[v][k] = Re <T_k|T_{k-1}> (k = 1..K; a[v][0] = mu_0),
+//   mu_0 = a[v][0], mu_1 = b[v][1], mu_{2k} = 2 a[v][k] - mu_0, mu_{2k-1} = 2 b[v][k] - mu_1.
+// raw is [Rv][K+1] over virtual vectors v' = (v / VPT) 2 VPT + (v % VPT) (+ VPT for b).
+__global__ void k_doubling_combine(const double *__restrict__ raw, int32_t K, int32_t VPT, int32_t R, int32_t M,
+                                   double *__restrict__ mu) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)R * M) return;
+    const int v = (int)(idx / M), m = (int)(idx % M);
+    const int va = (v / VPT) * 2 * VPT + (v % VPT), vb = va + VPT;
+    const double *a = raw + (int64_t)va * (K + 1), *b = raw + (int64_t)vb * (K + 1);
+    double out;
+    if (m == 0) out = a[0];
+    else if (m == 1) out = b[1];
+    else if ((m & 1) == 0) out = 2.0 * a[m / 2] - a[0];
+    else out = 2.0 * b[(m + 1) / 2] - b[1];
+    mu[(int64_t)v * M + m] = out;
 }
 
 // First level: l1[n0 + k][v][c] = sum of partial[k][b][v] over b in chunk c.
@@ -278,14 +315,20 @@ template <class VT> struct StepPtrs {
     double *partial;
 };
 
-template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W>
-void launch_step_w(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W, bool DBL>
+void launch_step_d(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
     if (pl.cfg.rows_per_thread == 2)
-        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 2, W><<<(unsigned)pl.G, kThreads, 0, s>>>(
+        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 2, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
             p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
     else
-        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 1, W><<<(unsigned)pl.G, kThreads, 0, s>>>(
+        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 1, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
             p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+}
+
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W>
+void launch_step_w(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
+    if (pl.cfg.doubling) launch_step_d<VT, L, VPT, FIRST, DIAG, NT, TIS, W, true>(pl, s, p, a);
+    else launch_step_d<VT, L, VPT, FIRST, DIAG, NT, TIS, W, false>(pl, s, p, a);
 }
 
 // Slices of one common width 3 (nearest-neighbour honeycomb) take a fully
@@ -325,20 +368,24 @@ void launch_reduce(const KpmPlan &pl, int n0, int count, int R, double *part, do
     k_reduce_l1<<<grid, kThreads, 0, s>>>(part, pl.G, pl.Rp, R, n0, pl.n_chunks, l1);
 }
 
-template <class VT, int L, int VPT>
-tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
-                       int32_t M, char *work, double *mu, hipStream_t s) {
+template <class VT, int L, int VPT, bool DBL>
+tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
+                         int32_t M, char *work, double *mu, hipStream_t s) {
     VT *r_int = reinterpret_cast<VT *>(work + pl.off_r);
     VT *TA = reinterpret_cast<VT *>(work + pl.off_a);
     VT *TB = reinterpret_cast<VT *>(work + pl.off_b);
     double *part = reinterpret_cast<double *>(work + pl.off_part);
     double *l1 = reinterpret_cast<double *>(work + pl.off_l1);
+    double *raw = reinterpret_cast<double *>(work + pl.off_raw);
     int32_t *flag = reinterpret_cast<int32_t *>(work + pl.off_flag);
-    const int64_t pstride = pl.G * pl.Rp;
+    const int Rv = pl.Rv;           // partial sums per block (per step)
+    const int Mr = pl.Mr;           // reduced rows: moments (direct) or steps + 1 (doubling)
+    const int Rout = DBL ? Rv : R;  // sums kept after the reduction
+    const int64_t pstride = pl.G * Rv;
     const int K = pl.reduce_every;
 
-    // moment 0 goes through the same partial slots as the steps (slot 0 of the first batch)
-    k_prepare<VT, L, VPT><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp, r_int, part);
+    // row 0 goes through the same partial slots as the steps (slot 0 of the first batch)
+    k_prepare<VT, L, VPT, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp, r_int, part);
     TBK_HIP(hipGetLastError());
 
     StepPtrs<VT> sp{};
@@ -356,11 +403,15 @@ tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, 
     sa.xcd_remap = pl.cfg.xcd_remap;
     sa.shift = (VT)b;
     const bool diag = h->has_onsite || b != 0.0;
+    auto reduce = [&](int n0, int count) {
+        dim3 grid(pl.n_chunks, count);
+        k_reduce_l1<<<grid, kThreads, 0, s>>>(part, pl.G, Rv, Rout, n0, pl.n_chunks, l1);
+    };
 
-    int batch0 = 0;   // first moment index of the pending batch
-    for (int n = 1; n < M; ++n) {
+    int batch0 = 0;   // first row index of the pending batch
+    for (int n = 1; n < Mr; ++n) {
         if (n - batch0 == K) {
-            launch_reduce(pl, batch0, K, R, part, l1, s);
+            reduce(batch0, K);
             batch0 = n;
         }
         sp.partial = part + (int64_t)(n - batch0) * pstride;
@@ -375,10 +426,16 @@ tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, 
         }
         launch_step<VT, L, VPT>(pl, n == 1, diag, s, sp, sa);
     }
-    launch_reduce(pl, batch0, M - batch0, R, part, l1, s);
+    reduce(batch0, Mr - batch0);
     TBK_HIP(hipGetLastError());
     const int64_t nm = (int64_t)R * M;
-    k_reduce_l2<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(l1, R, M, pl.n_chunks, mu);
+    if constexpr (DBL) {
+        k_reduce_l2<<<(unsigned)ceil_div((int64_t)Rv * Mr, 256), 256, 0, s>>>(l1, Rv, Mr, pl.n_chunks, raw);
+        TBK_HIP(hipGetLastError());
+        k_doubling_combine<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(raw, Mr - 1, VPT, R, M, mu);
+    } else {
+        k_reduce_l2<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(l1, R, M, pl.n_chunks, mu);
+    }
     TBK_HIP(hipGetLastError());
     TBK_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     k_guard<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(mu, R, M, flag);
@@ -389,6 +446,13 @@ tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, 
     TBK_CHECK(hflag == 0, TBK_ERR_SPECTRUM,
               "a moment exceeds mu_0: the scale a = %g, shift b = %g do not bound the spectrum", a, b);
     return TBK_OK;
+}
+
+template <class VT, int L, int VPT>
+tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
+                       int32_t M, char *work, double *mu, hipStream_t s) {
+    if (pl.cfg.doubling) return run_moments_t<VT, L, VPT, true>(h, pl, a, b, r, R, M, work, mu, s);
+    return run_moments_t<VT, L, VPT, false>(h, pl, a, b, r, R, M, work, mu, s);
 }
 
 }  // namespace
@@ -407,6 +471,7 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.xcd_remap = 0;
     c.rows_per_thread = 1;
     c.persistent = 0;
+    c.doubling = 0;
     (void)h;
     return c;
 }
@@ -440,6 +505,7 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     TBK_CHECK(pl.cfg.rows_per_thread == 1 || pl.cfg.rows_per_thread == 2, TBK_ERR_INVALID_ARG,
               "rows_per_thread must be 1 or 2");
     TBK_CHECK(pl.cfg.persistent == 0 || pl.cfg.persistent == 1, TBK_ERR_INVALID_ARG, "persistent must be 0/1");
+    TBK_CHECK(pl.cfg.doubling == 0 || pl.cfg.doubling == 1, TBK_ERR_INVALID_ARG, "doubling must be 0/1");
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;
@@ -458,8 +524,11 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
                            ? h->max_degree : 0;
     pl.n_chunks = (int)ceil_div(G, kReduceChunk);
     TBK_CHECK(pl.n_chunks < 65536, TBK_ERR_UNSUPPORTED, "too many blocks");
-    const size_t per_step = (size_t)G * pl.Rp * sizeof(double);
-    pl.reduce_every = (int)std::max<size_t>(1, std::min<size_t>({kPartialBudget / per_step, (size_t)64, (size_t)M}));
+    pl.Rv = pl.cfg.doubling ? 2 * pl.Rp : pl.Rp;
+    pl.Mr = pl.cfg.doubling ? M / 2 + 1 : M;
+    const int Rout = pl.cfg.doubling ? pl.Rv : R;
+    const size_t per_step = (size_t)G * pl.Rv * sizeof(double);
+    pl.reduce_every = (int)std::max<size_t>(1, std::min<size_t>({kPartialBudget / per_step, (size_t)64, (size_t)pl.Mr}));
     TBK_CHECK(pl.reduce_every < 65536, TBK_ERR_UNSUPPORTED, "reduction grid too large");
     pl.vec_bytes = align256((size_t)h->n_rows * pl.Rp * 2 * pl.elem);
     pl.off_r = 0;
@@ -468,7 +537,8 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     pl.off_part = pl.off_b + pl.vec_bytes;
     // k_prepare writes one partial per block of its own grid (<= G blocks)
     pl.off_l1 = pl.off_part + align256((size_t)pl.reduce_every * per_step);
-    pl.off_flag = pl.off_l1 + align256((size_t)M * R * pl.n_chunks * sizeof(double));
+    pl.off_raw = pl.off_l1 + align256((size_t)pl.Mr * Rout * pl.n_chunks * sizeof(double));
+    pl.off_flag = pl.off_raw + align256((size_t)pl.Mr * Rout * sizeof(double));
     pl.total = pl.off_flag + 256;
     return TBK_OK;
 }

@@ -9,11 +9,13 @@ namespace tbk {
 struct KpmPlan {
     tbk_kpm_config cfg{};
     int Rp = 1, L = 1, VPT = 1, log2_slice = 0, n_chunks = 1, reduce_every = 1;
+    int Rv = 1;                 // block partials per step (2 Rp with the doubling identities)
+    int Mr = 1;                 // reduced rows: M, or M / 2 + 1 with the doubling identities
     int64_t n_tiles = 0, G = 0;
     bool tile_is_slice = false;
     int uniform_width = 0;      // > 0 when every slice stores this many entries per row
     size_t elem = 0, vec_bytes = 0;
-    size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_flag = 0, total = 0;
+    size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0, total = 0;
 };
 
 int pad_vectors(int R);

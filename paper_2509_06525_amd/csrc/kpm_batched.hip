@@ -326,6 +326,7 @@ tbk_status make_seg_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precisi
     TBK_CHECK(h->seg_rows != nullptr, TBK_ERR_INVALID_ARG, "h->seg_rows is NULL");
     tbk_status st = make_plan(h, R, M, precision, cfg, sp.base);
     if (st != TBK_OK) return st;
+    TBK_CHECK(sp.base.cfg.doubling == 0, TBK_ERR_UNSUPPORTED, "the doubling identities are not offered for stacked structures");
     sp.n_seg = h->n_seg;
     sp.seg_rows.resize(sp.n_seg + 1);
     TBK_HIP(hipMemcpyAsync(sp.seg_rows.data(), h->seg_rows, sizeof(int64_t) * (sp.n_seg + 1), hipMemcpyDeviceToHost,

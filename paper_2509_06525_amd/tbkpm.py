@@ -65,7 +65,8 @@ class MlpModel(ctypes.Structure):
 class KpmConfig(ctypes.Structure):
     _fields_ = [("vectors_per_thread", ctypes.c_int32), ("tiles_per_block", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("rows_per_thread", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("rows_per_thread", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("doubling", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,8 +78,16 @@ class TuneResult(ctypes.Structure):
 
 
 def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1,
-                persistent=0):
-    return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread, persistent)
+                persistent=0, doubling=0):
+    return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread, persistent,
+                     doubling)
+
+
+def with_doubling(cfg, on=1):
+    """A copy of a launch shape with the doubling identities switched on or off."""
+    d = cfg.as_dict()
+    d["doubling"] = int(on)
+    return KpmConfig(**d)
 
 
 def lib():

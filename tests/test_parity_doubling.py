@@ -1,0 +1,104 @@
+"""GPU parity of the two-moments-per-step recurrence (doubling identities).
+
+For a Hermitian scaled Hamiltonian the product rule of the Chebyshev
+polynomials gives mu_2k = 2<T_k|T_k> - mu_0 and mu_2k-1 = 2 Re<T_k|T_k-1> - mu_1
+(Weisse et al., Rev. Mod. Phys. 78, 275 (2006), Sec. II.B).  The GPU computes
+the moments this way in M/2 steps; the oracle computes every moment directly
+as <r|T_n r>, so the comparison pins the identities as well as the kernels.
+FP64: |mu - mu_oracle| <= 1e-10 N; complex float: DOS relative L2 <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_mu(s, a, b, r, M):
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    return O.kpm_moments(csr, a, b, r.astype(np.complex128), M)[0]
+
+
+def _dbl(vpt=1, tpb=2, nt=1, xr=0, rpt=1):
+    return tbkpm.make_config(vpt, tpb, nt, xr, rpt, 0, 1)
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 97, 128])
+@pytest.mark.parametrize("R", [1, 3, 8])
+@pytest.mark.parametrize("fmt,slice", [("sell_f64", 32), ("csr_f64", 1)])
+def test_fp64_doubling_matches_direct_oracle(M, R, fmt, slice):
+    s = synth.graphene_sheet(23, 17, 0.06, 29)          # 1564 rows: ragged tail
+    H = G.build(s, fmt=fmt, slice=slice)
+    a, b = H.scale()
+    r = synth.random_phase(s.n, R, 31)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), M, "f64", config=_dbl()).cpu().numpy()
+    assert mu.shape == (R, M)
+    assert np.abs(mu - _oracle_mu(s, a, b, r, M)).max() <= 1e-10 * s.n
+
+
+@pytest.mark.parametrize("tpb,nt,xr,rpt", [(1, 1, 0, 1), (3, 0, 1, 2), (4, 1, 1, 2)])
+def test_fp64_doubling_every_shape(tpb, nt, xr, rpt):
+    s = synth.graphene_sheet(19, 13, 0.15, 77)          # irregular widths
+    H = G.build(s, fmt="sell_f64", slice=64)
+    a, b = H.scale()
+    r = synth.random_phase(s.n, 4, 4)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=_dbl(1, tpb, nt, xr, rpt)).cpu().numpy()
+    assert np.abs(mu - _oracle_mu(s, a, b, r, 61)).max() <= 1e-10 * s.n
+
+
+def test_fp64_doubling_onsite_and_shift():
+    s = synth.hbn_stripes(20, 18, stripe_cells=4, sigma=0.03, seed=6)
+    H = G.build(s, fmt="sell_f64", slice=16)
+    a, b = H.scale()
+    assert b != 0.0
+    r = synth.random_phase(s.n, 4, 8)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 128, "f64", config=_dbl()).cpu().numpy()
+    assert np.abs(mu - _oracle_mu(s, a, b, r, 128)).max() <= 1e-10 * s.n
+
+
+@pytest.mark.parametrize("R,vpt", [(1, 1), (2, 2), (5, 1), (16, 2), (32, 2)])
+def test_c32_doubling_dos_within_1e_4(R, vpt):
+    s = synth.graphene_sheet(31, 29, 0.05, 41)
+    H = G.build(s, fmt="sell_f32", slice=64)
+    a, b = H.scale()
+    M = 300
+    r = synth.random_phase(s.n, R, 3, np.complex64)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), M, "c32", config=_dbl(vpt)).cpu().numpy()
+    mu_o = _oracle_mu(s, a, b, r, M)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mu.mean(0), a, b, E), O.kpm_dos(mu_o.mean(0), a, b, E)) <= 1e-4
+    assert np.abs(mu - mu_o).max() <= 1e-4 * s.n
+
+
+def test_doubling_isolated_rows_closed_form():
+    """Degree-0 rows: mu_n = sum_i cos(n arccos x_i), x_i = (eps_i - b) / a."""
+    pos = np.array([[1.0, 1.0, 1.0], [10.0, 1.0, 1.0], [1.0, 10.0, 1.0]])
+    s = synth.Structure(pos=pos, species=np.array([0, 1, 2], np.int32), box=np.array([0., 0., 0.]),
+                        periodic=np.array([0, 0, 0], np.int32), onsite=synth.ONSITE_EV,
+                        t_pair=synth.T_PAIR_EV)
+    H = G.build(s, fmt="sell_f64", slice=4)
+    a, b = 3.0, 0.1
+    r = synth.random_phase(3, 2, 5)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 41, "f64", config=_dbl()).cpu().numpy()
+    x = (synth.ONSITE_EV - b) / a
+    expect = np.cos(np.arange(41)[:, None] * np.arccos(x)[None, :]).sum(1)
+    np.testing.assert_allclose(mu, np.broadcast_to(expect, (2, 41)), atol=1e-12)
+
+
+def test_doubling_guard_and_batched_rejection():
+    s = synth.graphene_sheet(10, 10, 0.05, 4)
+    H = G.build(s, fmt="sell_f64", slice=64)
+    a, b = H.scale()
+    r = G.to_dev(synth.random_phase(s.n, 1, 2))
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.kpm_moments(H, 0.5 * a, b, r, 128, config=_dbl())
+    assert e.value.name == "SPECTRUM"
+    Hb = tbkpm.build_hamiltonian_batched(G.to_dev(s.pos), G.to_dev(s.species), np.array([0, s.n]), [s.box],
+                                         (1, 1, 0), [0.0], [[-2.7]], fmt="sell_f64", slice=32)
+    ab, bb = Hb.scales()
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.kpm_moments_batched(Hb, ab, bb, r, 16, "f64", config=_dbl())
+    assert e.value.name == "UNSUPPORTED"
