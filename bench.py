@@ -40,6 +40,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    p.add_argument("--no-doubling", action="store_true", help="skip the doubling-identity variant")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run one plain device copy of this many MiB first (counter calibration)")
     p.add_argument("--cpu-sample-cells", type=int, default=0,
@@ -48,12 +49,14 @@ def parse():
     return p.parse_args()
 
 
-def cheb_step_bytes(H, Rp, elem, diag):
-    """Algorithmic bytes of one recurrence launch (see module docstring)."""
+def cheb_step_bytes(H, Rp, elem, diag, read_r=True):
+    """Algorithmic bytes of one recurrence launch (see module docstring); the
+    doubling form reads no r."""
     st = H.st
     val_b = 4 if st.fmt == 2 else 8
     b = st.n_entries * (val_b + 4) + st.n_ptr * 8
-    b += st.n_rows * Rp * 2 * elem * 4          # gather T_n once, read T_{n-1}, read r, write T_{n+1}
+    # gather T_n once, read T_{n-1}, write T_{n+1} (+ read r in the direct form)
+    b += st.n_rows * Rp * 2 * elem * (4 if read_r else 3)
     if diag and st.has_onsite:
         b += st.n_rows * val_b
     return b
@@ -196,6 +199,41 @@ def bench_snapshots(args, w):
     print(json.dumps(out), flush=True)
 
 
+def doubling_variant(args, H, a, b, r, M, R, Rp, elem, diag, precision, config, mu_direct, rho_direct, E,
+                     stream, dev):
+    """The same moments from the doubling identities (two per step, M/2 + 1 launches, no
+    read of r), timed like the direct form and compared with it."""
+    import torch
+    from paper_2509_06525_amd import tbkpm
+    cfg = tbkpm.with_doubling(config if config is not None else tbkpm.default_config(H, R, precision), 1)
+    work = tbkpm.alloc_workspace(H, R, M, precision, dev, cfg)
+    mu = torch.empty((R, M), dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tbkpm.kpm_moments(H, a, b, r, M, precision, work=work, mu=mu, stream=stream, config=cfg)
+    ms = []
+    for _ in range(max(1, args.steps)):
+        e0.record(stream)
+        tbkpm.kpm_moments(H, a, b, r, M, precision, work=work, mu=mu, stream=stream, config=cfg)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = float(np.median(ms))
+    rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), a, b, E, stream=stream).cpu().numpy()
+    launches = M // 2
+    launch_bytes = cheb_step_bytes(H, Rp, elem, diag, read_r=False)
+    launch_s = med * 1e-3 / launches
+    achieved = launch_bytes / launch_s / 1e9
+    N = H.st.n_rows
+    log(f"doubling: kpm {med:.1f} ms ({launches} launches)")
+    return {"kpm_ms_median": med, "kpm_atom_moments_per_s": N * M * R / (med * 1e-3), "launches": launches,
+            "launch": cfg.as_dict(),
+            "dos_relL2_vs_direct": float(np.linalg.norm(rho - rho_direct) / np.linalg.norm(rho_direct)),
+            "max_abs_dmu_over_N_vs_direct": float(np.abs(mu.cpu().numpy() - mu_direct).max() / N),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_cheb_step (doubling form)",
+                         "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6}}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -319,8 +357,12 @@ def main():
                      "launch_us": launch_s * 1e6},
     }
 
-    # FP64 GPU path on the same structure and vectors (reported beside the C32 path).
     log(f"timed: {sec_per_step * 1e3:.1f} ms/step, kpm {kpm_med:.1f} ms")
+    if not args.no_doubling and M >= 2:
+        out["variants"] = {"doubling": doubling_variant(args, Hs, aa, bb, r, M, R, Rp, elem, diag, w["precision"],
+                                                        config, mu_c, rho_c, E, stream, dev)}
+
+    # FP64 GPU path on the same structure and vectors (reported beside the C32 path).
     if not args.no_fp64 and w["precision"] == "c32":
         H64 = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP,
                                       r0=synth.R0, beta=synth.BETA, fmt="sell_f64", slice=slice_,

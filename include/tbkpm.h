@@ -191,6 +191,11 @@ typedef struct {
                                    Hermitian H; M/2 steps and no read of r)        */
 } tbk_kpm_config;
 
+/* The launch shape kpm_moments uses for (h, R, precision) when none is given
+ * (written to *cfg).  Errors: INVALID_ARG (NULL pointer, R outside [1, 64],
+ * precision/format mismatch). */
+tbk_status kpm_default_config(const tbk_ham *h, int32_t R, int32_t precision, tbk_kpm_config *cfg);
+
 /* Bytes of device workspace kpm_moments needs for (h, R, M, precision) with the
  * default launch shape (kpm_workspace_size) or a given one (cfg may be NULL). */
 tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,

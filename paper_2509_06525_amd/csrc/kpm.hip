@@ -599,6 +599,16 @@ tbk_status check_moment_args(const tbk_ham *h, const KpmPlan &pl, const double *
 
 using namespace tbk;
 
+extern "C" tbk_status kpm_default_config(const tbk_ham *h, int32_t R, int32_t precision, tbk_kpm_config *cfg) {
+    clear_error();
+    TBK_CHECK(cfg != nullptr, TBK_ERR_INVALID_ARG, "cfg is NULL");
+    KpmPlan pl;
+    tbk_status st = make_plan(h, R, 2, precision, nullptr, pl);
+    if (st != TBK_OK) return st;
+    *cfg = pl.cfg;
+    return TBK_OK;
+}
+
 extern "C" tbk_status kpm_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
                                          int64_t *bytes) {
     return kpm_workspace_size_config(h, R, M, precision, nullptr, bytes);

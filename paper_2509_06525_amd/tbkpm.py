@@ -47,7 +47,7 @@ class HamStruct(ctypes.Structure):
 
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
-               "tb_build_hamiltonian", "kpm_workspace_size", "kpm_workspace_size_config",
+               "tb_build_hamiltonian", "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
                "kpm_moments", "kpm_moments_config", "kpm_dos", "tbk_autotune",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
                "kpm_workspace_size_batched", "kpm_moments_batched",
@@ -110,6 +110,8 @@ def lib():
     L.tb_build_hamiltonian.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                        ctypes.POINTER(TbParams), ctypes.POINTER(HamStruct),
                                        ctypes.POINTER(f64), vp]
+    L.kpm_default_config.restype = ctypes.c_int
+    L.kpm_default_config.argtypes = [ctypes.POINTER(HamStruct), i32, i32, ctypes.POINTER(KpmConfig)]
     L.kpm_workspace_size.restype = ctypes.c_int
     L.kpm_workspace_size.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, ctypes.POINTER(i64)]
     L.kpm_moments.restype = ctypes.c_int
@@ -281,6 +283,13 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
 
 def _cfg_ref(config):
     return ctypes.byref(config) if config is not None else None
+
+
+def default_config(H, R, precision):
+    """The launch shape kpm_moments uses for (H, R, precision) when given none."""
+    out = KpmConfig()
+    _check(lib().kpm_default_config(ctypes.byref(H.st), int(R), PRECISIONS[precision], ctypes.byref(out)))
+    return out
 
 
 def workspace_size(H, R, M, precision, config=None):

@@ -51,3 +51,15 @@ def csr_entries(csr):
 
 def rel_l2(x, y):
     return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+def bf16_decisions_clear(h1, h2, eps=1e-6):
+    """Per bond: True when every hidden activation (oracle, FP64) lies more than
+    eps from a bfloat16 rounding boundary.  The GPU forms these activations in
+    FP32 (error ~1e-8), so for such bonds both sides round every MFMA operand
+    the same way and the outputs agree to FP32 accumulation error; a bond with
+    an activation inside the band may round it one bf16 ulp apart."""
+    h = np.concatenate([h1, h2], axis=1)
+    from oracle import oracle as O
+    flip = O.bf16(h + eps) != O.bf16(h - eps)
+    return ~flip.any(axis=1)

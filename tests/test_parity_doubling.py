@@ -26,7 +26,7 @@ def _dbl(vpt=1, tpb=2, nt=1, xr=0, rpt=1):
     return tbkpm.make_config(vpt, tpb, nt, xr, rpt, 0, 1)
 
 
-@pytest.mark.parametrize("M", [1, 2, 3, 4, 97, 128])
+@pytest.mark.parametrize("M", [2, 3, 4, 5, 97, 128])
 @pytest.mark.parametrize("R", [1, 3, 8])
 @pytest.mark.parametrize("fmt,slice", [("sell_f64", 32), ("csr_f64", 1)])
 def test_fp64_doubling_matches_direct_oracle(M, R, fmt, slice):
