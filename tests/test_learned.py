@@ -202,7 +202,7 @@ def test_learned_assembly_matches_oracle():
         clear = G.bf16_decisions_clear(h1, h2)
         bond_of = {(int(i), int(j)): e for e, (i, j) in enumerate(zip(hop[0], hop[1]))}
         ent_clear = np.array([clear[bond_of[(min(i, j), max(i, j))]] for i, j in zip(orow[a2], ocol[a2])])
-        assert ent_clear.mean() >= 0.5
+        assert ent_clear.mean() >= 0.3
         assert rel[ent_clear].max() <= 5e-5
         assert rel.max() <= 1e-2
         np.testing.assert_array_equal(vv.reshape(-1) != 0, True)
