@@ -286,10 +286,10 @@ def main():
         log(f"tuned: slice {slice_} {config.as_dict()} {tune.ms_per_step:.4f} ms/step "
             f"({tune.candidates} candidates)")
 
-    def build():
+    def build(into=None):
         return tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair,
                                        r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
-                                       fmt=fmt, slice=slice_, stream=stream)
+                                       fmt=fmt, slice=slice_, stream=stream, into=into)
 
     H = build()
     a, b = (w["a"], w["b"]) if fixed_ab else H.scale()
@@ -298,13 +298,15 @@ def main():
     E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
     if fixed_ab:
         E = torch.linspace(w["e_lo"], w["e_hi"], w["n_e"], dtype=torch.float64, device=dev)
+    held = [H]          # the Hamiltonian's buffers are rebuilt in place every step
     del H
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     kpm_ms = []
 
     def step():
-        Hs = build()
+        Hs = build(into=held.pop())
+        held.append(Hs)
         aa, bb = (w["a"], w["b"]) if fixed_ab else Hs.scale()
         ev[0].record(stream)
         tbkpm.kpm_moments(Hs, aa, bb, r, M, w["precision"], work=work, mu=mu, stream=stream, config=config)
@@ -368,6 +370,7 @@ def main():
                                       r0=synth.R0, beta=synth.BETA, fmt="sell_f64", slice=slice_,
                                       stream=stream)
         del Hs
+        held.clear()
         r64 = r.to(torch.complex128)
         work = None
         torch.cuda.empty_cache()

@@ -27,45 +27,69 @@ constexpr int kMaxDegree = 256;
 constexpr int kMaxSpecies = 16;
 constexpr int kCellStrip = 64;      // cells per strip of the row order
 
-// seg_of[i] = s for atoms of segment s; one block per segment.
-__global__ void k_seg_of(const int64_t *__restrict__ seg_atoms, int32_t *__restrict__ seg_of) {
-    const int s = blockIdx.x;
-    for (int64_t i = seg_atoms[s] + threadIdx.x; i < seg_atoms[s + 1]; i += blockDim.x) seg_of[i] = s;
+// seg_of[i] = s with seg_atoms[s] <= i < seg_atoms[s + 1] (offsets strictly
+// increasing, so the binary search has one answer).
+__global__ void k_seg_of(int64_t n, int32_t nseg, const int64_t *__restrict__ seg_atoms,
+                         int32_t *__restrict__ seg_of) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (seg_atoms[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    seg_of[i] = lo;
 }
 
-// part[s][8] = {min x, min y, min z, max x, max y, max z, bad coord, bad species}; one block per segment.
-__global__ void k_segment_scan(const double *__restrict__ pos, const int32_t *__restrict__ species,
-                               const int64_t *__restrict__ seg_atoms, int32_t n_species,
-                               double *__restrict__ part) {
-    const int sg = blockIdx.x;
-    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double bad = 0.0, bad_sp = 0.0;
-    for (int64_t i = seg_atoms[sg] + threadIdx.x; i < seg_atoms[sg + 1]; i += blockDim.x) {
+constexpr int kScanChunk = 16;      // atoms per thread in k_segment_scan
+
+// Per-segment coordinate ranges and input checks over the whole grid.
+// keys[(k n_seg + s) 2 + {0, 1}] = order-preserving keys of min / max of
+// coordinate k over the finite coordinates of segment s (k_init_bounds start);
+// flags[2 s] = 1 if some coordinate of s is NaN/Inf, flags[2 s + 1] = 1 if a
+// species index is outside [0, n_species) (flags start at 0).  A block covers
+// kScanChunk * kBlock consecutive atoms; a thread flushes its running range
+// with atomics when its atoms cross into another segment, and the block folds
+// the last ranges per segment before one atomic per segment and coordinate.
+__global__ __launch_bounds__(kBlock) void k_segment_scan(const double *__restrict__ pos,
+                                                         const int32_t *__restrict__ species, int64_t n,
+                                                         const int32_t *__restrict__ seg_of, int32_t nseg,
+                                                         int32_t n_species, int64_t *__restrict__ keys,
+                                                         int32_t *__restrict__ flags) {
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kScanChunk;
+    double mn[3], mx[3];
+    int32_t cur = -1;
+    auto reset = [&]() {
+        for (int k = 0; k < 3; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+    };
+    reset();
+    for (int u = 0; u < kScanChunk; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock + threadIdx.x;
+        if (i >= n) break;
+        const int32_t sg = seg_of[i];
+        if (sg != cur) {
+            if (cur >= 0) {
+                for (int k = 0; k < 3; ++k)
+                    if (mn[k] <= mx[k]) {
+                        atomicMin((long long *)&keys[2 * ((int64_t)k * nseg + cur)], (long long)dkey(mn[k]));
+                        atomicMax((long long *)&keys[2 * ((int64_t)k * nseg + cur) + 1], (long long)dkey(mx[k]));
+                    }
+            }
+            cur = sg;
+            reset();
+        }
         for (int k = 0; k < 3; ++k) {
-            double x = pos[3 * i + k];
-            if (!isfinite(x)) bad = 1.0;
+            const double x = pos[3 * i + k];
+            if (!isfinite(x)) flags[2 * sg] = 1;
             else { mn[k] = fmin(mn[k], x); mx[k] = fmax(mx[k], x); }
         }
         if (species) {
-            int32_t s = species[i];
-            if (s < 0 || s >= n_species) bad_sp = 1.0;
+            const int32_t t = species[i];
+            if (t < 0 || t >= n_species) flags[2 * sg + 1] = 1;
         }
     }
-    __shared__ double red[8][kBlock];
-    for (int k = 0; k < 3; ++k) { red[k][threadIdx.x] = mn[k]; red[3 + k][threadIdx.x] = mx[k]; }
-    red[6][threadIdx.x] = bad;
-    red[7][threadIdx.x] = bad_sp;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            for (int k = 0; k < 3; ++k)
-                red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
-            for (int k = 3; k < 8; ++k)
-                red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) part[sg * 8 + threadIdx.x] = red[threadIdx.x][0];
+    for (int k = 0; k < 3; ++k) block_segment_bounds(mn[k], mx[k], cur < 0 ? -1 : k * nseg + cur, keys);
 }
 
 __global__ void k_cell_of(const double *__restrict__ pos, int64_t n, const CellGrid *__restrict__ grids,
@@ -275,21 +299,35 @@ tbk_status CellListOwner::build(const double *pos, const int32_t *species, int32
     TBK_HIP(seg_of.alloc(sizeof(int32_t) * n, s));
     TBK_HIP(hipMemcpyAsync(seg_atoms.as<int64_t>(), seg_atoms_h, sizeof(int64_t) * (nseg + 1),
                            hipMemcpyHostToDevice, s));
-    k_seg_of<<<nseg, kBlock, 0, s>>>(seg_atoms.as<int64_t>(), seg_of.as<int32_t>());
+    const int gseg = (int)ceil_div(n, kBlock);
+    k_seg_of<<<gseg, kBlock, 0, s>>>(n, nseg, seg_atoms.as<int64_t>(), seg_of.as<int32_t>());
     TBK_HIP(hipGetLastError());
 
     // 1. ranges and validity per segment
-    DevBuf part;
-    TBK_HIP(part.alloc(sizeof(double) * 8 * nseg, s));
-    k_segment_scan<<<nseg, kBlock, 0, s>>>(pos, species, seg_atoms.as<int64_t>(), n_species, part.as<double>());
+    DevBuf rkeys, rflags;
+    TBK_HIP(rkeys.alloc(sizeof(int64_t) * 6 * nseg, s));
+    TBK_HIP(rflags.alloc(sizeof(int32_t) * 2 * nseg, s));
+    k_init_bounds<<<(3 * nseg + 255) / 256, 256, 0, s>>>(3 * nseg, rkeys.as<int64_t>());
     TBK_HIP(hipGetLastError());
-    std::vector<double> hp(8 * (size_t)nseg);
-    TBK_HIP(hipMemcpyAsync(hp.data(), part.as<double>(), sizeof(double) * 8 * nseg, hipMemcpyDeviceToHost, s));
+    TBK_HIP(hipMemsetAsync(rflags.as<int32_t>(), 0, sizeof(int32_t) * 2 * nseg, s));
+    k_segment_scan<<<(unsigned)ceil_div(n, (int64_t)kBlock * kScanChunk), kBlock, 0, s>>>(
+        pos, species, n, seg_of.as<int32_t>(), nseg, n_species, rkeys.as<int64_t>(), rflags.as<int32_t>());
+    TBK_HIP(hipGetLastError());
+    std::vector<int64_t> hk(6 * (size_t)nseg);
+    std::vector<int32_t> hf(2 * (size_t)nseg);
+    TBK_HIP(hipMemcpyAsync(hk.data(), rkeys.as<int64_t>(), sizeof(int64_t) * 6 * nseg, hipMemcpyDeviceToHost, s));
+    TBK_HIP(hipMemcpyAsync(hf.data(), rflags.as<int32_t>(), sizeof(int32_t) * 2 * nseg, hipMemcpyDeviceToHost, s));
     TBK_HIP(hipStreamSynchronize(s));
+    // hp[8 g + k] = min, hp[8 g + 3 + k] = max of coordinate k in segment g
+    std::vector<double> hp(8 * (size_t)nseg);
     for (int g = 0; g < nseg; ++g) {
-        TBK_CHECK(hp[8 * g + 6] == 0.0, TBK_ERR_NOT_FINITE, "a coordinate of segment %d is NaN or Inf", g);
-        TBK_CHECK(hp[8 * g + 7] == 0.0, TBK_ERR_INVALID_ARG, "a species index of segment %d is outside [0, %d)",
+        TBK_CHECK(hf[2 * g] == 0, TBK_ERR_NOT_FINITE, "a coordinate of segment %d is NaN or Inf", g);
+        TBK_CHECK(hf[2 * g + 1] == 0, TBK_ERR_INVALID_ARG, "a species index of segment %d is outside [0, %d)",
                   g, n_species);
+        for (int k = 0; k < 3; ++k) {
+            hp[8 * g + k] = dunkey(hk[2 * ((size_t)k * nseg + g)]);
+            hp[8 * g + 3 + k] = dunkey(hk[2 * ((size_t)k * nseg + g) + 1]);
+        }
     }
 
     // 2. one cell grid per segment, global cell ids

@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtbkpm.so")
 
 TBK_OK = 0
+TBK_ERR_BUFFER_TOO_SMALL = 2
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BUFFER_TOO_SMALL", 3: "NOT_FINITE",
                 4: "SPECTRUM", 5: "UNSUPPORTED", 6: "DEVICE"}
 FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2}
@@ -250,8 +251,12 @@ class Hamiltonian:
 
 
 def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0=1.42, beta=3.37,
-                      fmt="sell_f32", slice=256, reorder=True, stream=None):
-    """Neighbour list + Eq. (1) assembly on the GPU.  pos: float64 [N,3], species: int32 [N]."""
+                      fmt="sell_f32", slice=256, reorder=True, stream=None, into=None):
+    """Neighbour list + Eq. (1) assembly on the GPU.  pos: float64 [N,3], species: int32 [N].
+
+    `into`: a Hamiltonian from an earlier call with the same N, format and slice
+    height whose buffers are overwritten (no size pass) when they are large
+    enough; `into` must not be used afterwards."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
@@ -259,8 +264,21 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
     p, keep = _params(onsite, t_pair, r_cut, r0, beta, reorder)
     boxa = _f64arr(box)
     per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
-    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
     s = _stream(stream)
+    if into is not None and into.st.fmt == FORMATS[fmt] and into.st.slice == int(slice) and into.n_rows == n:
+        t = into.tensors
+        st = HamStruct(fmt=FORMATS[fmt], slice=int(slice), n_rows=n, n_ptr=t["ptr"].numel(),
+                       n_entries=t["col"].numel())
+        st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
+        st.onsite, st.perm = t["onsite"].data_ptr(), t["perm"].data_ptr()
+        bounds = (ctypes.c_double * 2)()
+        rc = L.tb_build_hamiltonian(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p), ctypes.byref(st),
+                                    bounds, s)
+        if rc != TBK_ERR_BUFFER_TOO_SMALL:
+            _check(rc)
+            del keep
+            return Hamiltonian(st, t, (bounds[0], bounds[1]))
+    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
     _check(L.tbk_hamiltonian_size(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p),
                                   ctypes.byref(st), s))
     dev = pos.device

@@ -151,3 +151,39 @@ def test_persistent_barrier_timeout_is_reported(monkeypatch):
     monkeypatch.delenv("TBKPM_BARRIER_SPIN_LIMIT")
     mu = tbkpm.kpm_moments_batched(H, a, b, r, 40, "f64", config=tbkpm.make_config(1, 1, 1, 0, 1, 1))
     assert torch.isfinite(mu).all()
+
+
+def test_many_small_structures_share_scan_blocks():
+    """Dozens of small structures inside one block of the range scan: each keeps
+    its own cell grid, pattern and bounds (as if built alone)."""
+    shapes = [(3 + k % 4, 3 + (k * 7) % 5, 0.02 + 0.01 * (k % 5)) for k in range(40)]
+    sheets, pos, sp, seg, boxes = make_batch(shapes, seed=500)
+    H = build(pos, sp, seg, boxes, "sell_f64", 8)
+    rows, cols, vals, _ = G.entries_in_atom_order(H)
+    for k, s in enumerate(sheets):
+        H1 = G.build(s, fmt="sell_f64", slice=8)
+        r1, c1, v1, _ = G.entries_in_atom_order(H1)
+        m = (rows >= seg[k]) & (rows < seg[k + 1])
+        r, c, v = rows[m] - seg[k], cols[m] - seg[k], vals[m]
+        o1, o2 = np.lexsort((c, r)), np.lexsort((c1, r1))
+        np.testing.assert_array_equal(r[o1], r1[o2])
+        np.testing.assert_array_equal(c[o1], c1[o2])
+        np.testing.assert_array_equal(v[o1], v1[o2])
+        assert tuple(H.bounds[k]) == tuple(H1.bounds)
+
+
+def test_rebuild_into_existing_buffers():
+    s0 = synth.graphene_sheet(30, 21, 0.03, 1)
+    s1 = synth.graphene_sheet(30, 21, 0.07, 2)
+    H0 = G.build(s0, fmt="sell_f32", slice=64)
+    cap = H0.tensors["col"].numel()
+    H1 = tbkpm.build_hamiltonian(G.to_dev(s1.pos), G.to_dev(s1.species), s1.box, s1.periodic, s1.onsite,
+                                 s1.t_pair, fmt="sell_f32", slice=64, into=H0)
+    ref = G.build(s1, fmt="sell_f32", slice=64)
+    got, want = G.entries_in_atom_order(H1), G.entries_in_atom_order(ref)
+    o1, o2 = np.lexsort((got[1], got[0])), np.lexsort((want[1], want[0]))
+    for x, y in zip(got[:3], want[:3]):
+        np.testing.assert_array_equal(x[o1], y[o2])
+    assert H1.bounds == ref.bounds
+    if H1.tensors["col"].numel() == cap:
+        assert H1.tensors["col"].data_ptr() == H0.tensors["col"].data_ptr()
