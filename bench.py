@@ -14,6 +14,7 @@ stream, against the 8 TB/s HBM3E peak.  `cpu_baseline` times the serial FP64
 oracle (one core) on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -41,6 +42,8 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     p.add_argument("--no-doubling", action="store_true", help="skip the doubling-identity variant")
+    p.add_argument("--retune", action="store_true",
+                   help="tune afresh instead of starting from the shipped MI355X tuning table")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="run one plain device copy of this many MiB first (counter calibration)")
     p.add_argument("--cpu-sample-cells", type=int, default=0,
@@ -60,6 +63,49 @@ def cheb_step_bytes(H, Rp, elem, diag, read_r=True):
     if diag and st.has_onsite:
         b += st.n_rows * val_b
     return b
+
+
+def kernel_source_hash():
+    """Hash of the recurrence kernel's sources (a stored counter profile is valid only for these)."""
+    h = hashlib.sha256()
+    for f in ("kpm.hip", "kpm.hpp", "kpm_dev.hpp"):
+        with open(os.path.join(ROOT, "paper_2509_06525_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload, kernel, slice_, launch):
+    """HBM bytes per launch of `kernel` from the counter profile stored for `workload`
+    (FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration), or None when
+    the kernel's sources or the launch shape differ from the profiled ones."""
+    path = os.path.join(ROOT, "profiles", f"k_cheb_step_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("record "):
+                parts = dict(kv.split("=", 1) for kv in line.split()[1:])
+                rec[parts["kernel"]] = parts
+    r = rec.get(kernel)
+    if r is None or r["sources"] != kernel_source_hash() or int(r["slice"]) != slice_:
+        return None
+    if r["launch"] != ",".join(f"{k}:{v}" for k, v in sorted(launch.items())):
+        return None
+    return float(r["traffic_bytes"])
+
+
+def use_shipped_tuning():
+    """Point the autotuner's cache at a copy of the shipped MI355X tuning table."""
+    if os.environ.get("TBKPM_AUTOTUNE_CACHE"):
+        return
+    import shutil
+    import tempfile
+    src = os.path.join(ROOT, "paper_2509_06525_amd", "tuned_gfx950.txt")
+    fd, dst = tempfile.mkstemp(prefix="tbkpm_tune_", suffix=".txt")
+    os.close(fd)
+    shutil.copyfile(src, dst)
+    os.environ["TBKPM_AUTOTUNE_CACHE"] = dst
 
 
 def cpu_baseline(w, cells):
@@ -230,7 +276,9 @@ def doubling_variant(args, H, a, b, r, M, R, Rp, elem, diag, precision, config, 
             "dos_relL2_vs_direct": float(np.linalg.norm(rho - rho_direct) / np.linalg.norm(rho_direct)),
             "max_abs_dmu_over_N_vs_direct": float(np.abs(mu.cpu().numpy() - mu_direct).max() / N),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_cheb_step (doubling form)",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": profiled_traffic(args.workload, "doubling", H.st.slice, cfg.as_dict()),
+                         "kernel": "k_cheb_step (doubling form)",
                          "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6}}
 
 
@@ -278,6 +326,8 @@ def main():
     config = None
     tune = None
     if fmt != "csr_f64" and not args.no_tune:
+        if not args.retune:
+            use_shipped_tuning()
         log("autotuning slice height and launch shape")
         tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, R, w["precision"],
                               r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, stream=stream)
@@ -336,6 +386,7 @@ def main():
     launch_bytes = cheb_step_bytes(Hs, Rp, elem, diag)
     kpm_med = float(np.median(kpm_ms))
     launch_s = kpm_med * 1e-3 / (M - 1)
+    launch_cfg = config if config is not None else tbkpm.default_config(Hs, R, w["precision"])
     achieved = launch_bytes / launch_s / 1e9
     mu_c = mu.cpu().numpy().copy()
     rho_c = rho.cpu().numpy()
@@ -354,7 +405,8 @@ def main():
                                              "candidates": tune.candidates},
         "kpm_atom_moments_per_s": N * M * R / (kpm_med * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(args.workload, "direct", slice_, launch_cfg.as_dict()),
                      "kernel": "k_cheb_step", "bytes_per_launch": launch_bytes,
                      "launch_us": launch_s * 1e6},
     }
