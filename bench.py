@@ -193,8 +193,7 @@ def bench_snapshots(args, w):
     log(f"launch shapes (ms/step): {timing}; using {best}")
     work = torch.empty(tbkpm.workspace_size_batched(H, R, M, "c32", cfg, stream), dtype=torch.uint8, device=dev)
     mu = torch.empty((len(snaps), R, M), dtype=torch.float64, device=dev)
-    grids = [torch.linspace(bb - 0.99 * aa, bb + 0.99 * aa, 2001, dtype=torch.float64, device=dev)
-             for aa, bb in zip(a, b)]
+    u = torch.linspace(-0.99, 0.99, 2001, dtype=torch.float64, device=dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     kpm_ms = []
 
@@ -205,8 +204,10 @@ def bench_snapshots(args, w):
         tbkpm.kpm_moments_batched(Hs, aa, bb, r, M, "c32", work=work, mu=mu, config=cfg, stream=stream)
         ev[1].record(stream)
         mbar = mu.mean(1)
-        rhos = [tbkpm.kpm_dos(mbar[k].contiguous(), aa[k], bb[k], grids[k], stream=stream)
-                for k in range(len(snaps))]
+        # each snapshot's own grid [b - 0.99 a, b + 0.99 a]
+        grid = (torch.tensor(bb, dtype=torch.float64, device=dev)[:, None]
+                + torch.tensor(aa, dtype=torch.float64, device=dev)[:, None] * u[None, :]).contiguous()
+        rhos = tbkpm.kpm_dos_batched(mbar, aa, bb, grid, stream=stream)
         return Hs, rhos
 
     log(f"{len(snaps)} snapshots, N={N} M={M} R={R}: warmup {args.warmup}, timed {args.steps}")

@@ -407,6 +407,17 @@ tbk_status tb_build_hamiltonian_learned(const double *pos, const int32_t *specie
 tbk_status kpm_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
                    const double *E, int32_t nE, double *rho, void *stream);
 
+/* kpm_dos for n_struct structures in one launch (stacked snapshots):
+ *   mu  device double [n_struct][M] (each already averaged over vectors),
+ *   a, b host double [n_struct] (scale > 0 and shift of each structure),
+ *   E   device double [n_struct][nE] (each structure's own grid),
+ *   rho device double [n_struct][nE].
+ * Errors: as kpm_dos, INVALID_ARG for n_struct outside [1, 65535].  Copies a
+ * and b to the device and synchronises `stream` before returning. */
+tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_struct, const double *a,
+                           const double *b, int32_t kernel, const double *E, int32_t nE,
+                           double *rho, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

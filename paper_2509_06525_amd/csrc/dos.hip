@@ -1,8 +1,10 @@
 // Jackson-damped DOS reconstruction, Eq. (4), on the GPU (FP64).
 //
-// One thread per energy: x = (E - b)/a, Chebyshev polynomials T_n(x) by their
-// three-term recurrence, damping factors g_n of the Jackson kernel computed from
-// their closed form, rho = [g_0 mu_0 + 2 sum g_n mu_n T_n(x)] / (a pi sqrt(1 - x^2)).
+// x = (E - b)/a, rho = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(x)] / (a pi sqrt(1 - x^2)),
+// T_n(x) by the three-term recurrence, g_n of the Jackson kernel from its closed
+// form.  A block serves 256 energies of one structure: the weights
+// c_n = g_n mu_n (times 2 for n >= 1) are formed 256 at a time in LDS, one per
+// thread, and every thread then runs the recurrence of its energy over them.
 #include <cmath>
 
 #include "common.hpp"
@@ -10,29 +12,60 @@
 namespace tbk {
 namespace {
 
-__global__ void k_dos(const double *__restrict__ mu, int32_t M, double a, double b, int32_t kernel,
-                      const double *__restrict__ E, int32_t nE, double *__restrict__ rho) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nE) return;
-    const double x = (E[e] - b) / a;
-    if (!(fabs(x) < 1.0)) { rho[e] = 0.0; return; }
+constexpr int kDosThreads = 256;
+
+// grid = (ceil(nE / 256), n_struct); structure s reads mu + s * M, its scale
+// and shift (ab[s], ab[n_struct + s], or a0, b0 when ab is NULL),
+// E + s * e_stride and writes rho + s * nE.
+__global__ __launch_bounds__(kDosThreads) void k_dos(const double *__restrict__ mu, int32_t M, double a0, double b0,
+                                                     const double *__restrict__ ab, int32_t kernel,
+                                                     const double *__restrict__ E, int64_t e_stride, int32_t nE,
+                                                     double *__restrict__ rho) {
+    __shared__ double c[kDosThreads];
+    const int s = blockIdx.y;
+    const int e = blockIdx.x * kDosThreads + threadIdx.x;
+    const double *m = mu + (int64_t)s * M;
+    const double as = ab ? ab[s] : a0, bs = ab ? ab[gridDim.y + s] : b0;
+    const double x = e < nE ? (E[(int64_t)s * e_stride + e] - bs) / as : 0.0;
+    const bool inside = fabs(x) < 1.0;
     const double q = M_PI / (M + 1.0);
     const double cot_q = cos(q) / sin(q);
-    double s = mu[0];                       // g_0 = 1 for both kernels
-    double tm = 1.0, tn = x;
-    for (int n = 1; n < M; ++n) {
-        double g = 1.0;
-        if (kernel == 0) {
-            double sn, cn;
-            sincos(q * n, &sn, &cn);
-            g = ((M - n + 1.0) * cn + sn * cot_q) / (M + 1.0);
+    double acc = 0.0, tm = 0.0, tn = 0.0;   // T_{n-1}, T_n of this thread's energy
+    for (int n0 = 0; n0 < M; n0 += kDosThreads) {
+        const int n = n0 + threadIdx.x;
+        double w = 0.0;
+        if (n < M) {
+            double g = 1.0;
+            if (kernel == 0) {
+                double sn, cn;
+                sincos(q * n, &sn, &cn);
+                g = ((M - n + 1.0) * cn + sn * cot_q) / (M + 1.0);
+            }
+            w = (n == 0 ? 1.0 : 2.0) * g * m[n];
         }
-        s += 2.0 * g * mu[n] * tn;
-        const double tp = 2.0 * x * tn - tm;
-        tm = tn;
-        tn = tp;
+        __syncthreads();
+        c[threadIdx.x] = w;
+        __syncthreads();
+        const int cnt = min(kDosThreads, M - n0);
+        for (int k = 0; k < cnt; ++k) {
+            const int nn = n0 + k;
+            double t;
+            if (nn == 0) t = 1.0;
+            else if (nn == 1) t = x;
+            else t = 2.0 * x * tn - tm;
+            acc += c[k] * t;
+            tm = tn;
+            tn = t;
+        }
     }
-    rho[e] = s / (a * M_PI * sqrt(1.0 - x * x));
+    if (e < nE) rho[(int64_t)s * nE + e] = inside ? acc / (as * M_PI * sqrt(1.0 - x * x)) : 0.0;
+}
+
+tbk_status check_dos(int32_t M, int32_t nE, int32_t kernel) {
+    TBK_CHECK(M >= 1, TBK_ERR_INVALID_ARG, "M = %d < 1", M);
+    TBK_CHECK(nE >= 0, TBK_ERR_INVALID_ARG, "nE = %d < 0", nE);
+    TBK_CHECK(kernel == 0 || kernel == 1, TBK_ERR_INVALID_ARG, "kernel must be 0 (Jackson) or 1 (none)");
+    return TBK_OK;
 }
 
 }  // namespace
@@ -43,15 +76,42 @@ using namespace tbk;
 extern "C" tbk_status kpm_dos(const double *mu, int32_t M, double a, double b, int32_t kernel, const double *E,
                               int32_t nE, double *rho, void *stream) {
     clear_error();
-    TBK_CHECK(M >= 1, TBK_ERR_INVALID_ARG, "M = %d < 1", M);
-    TBK_CHECK(nE >= 0, TBK_ERR_INVALID_ARG, "nE = %d < 0", nE);
-    TBK_CHECK(kernel == 0 || kernel == 1, TBK_ERR_INVALID_ARG, "kernel must be 0 (Jackson) or 1 (none)");
+    tbk_status st = check_dos(M, nE, kernel);
+    if (st != TBK_OK) return st;
     TBK_CHECK(std::isfinite(a) && std::isfinite(b), TBK_ERR_NOT_FINITE, "a or b is not finite");
     TBK_CHECK(a > 0, TBK_ERR_INVALID_ARG, "a = %g must be positive", a);
     if (nE == 0) return TBK_OK;
     TBK_CHECK(mu && E && rho, TBK_ERR_INVALID_ARG, "NULL argument");
     hipStream_t s = as_stream(stream);
-    k_dos<<<(nE + 255) / 256, 256, 0, s>>>(mu, M, a, b, kernel, E, nE, rho);
+    k_dos<<<dim3((unsigned)ceil_div(nE, kDosThreads), 1), kDosThreads, 0, s>>>(mu, M, a, b, nullptr, kernel, E, 0,
+                                                                               nE, rho);
     TBK_HIP(hipGetLastError());
+    return TBK_OK;
+}
+
+extern "C" tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_struct, const double *a,
+                                      const double *b, int32_t kernel, const double *E, int32_t nE, double *rho,
+                                      void *stream) {
+    clear_error();
+    tbk_status st = check_dos(M, nE, kernel);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(n_struct >= 1 && n_struct <= 65535, TBK_ERR_INVALID_ARG, "n_struct = %d outside [1, 65535]",
+              n_struct);
+    TBK_CHECK(a && b, TBK_ERR_INVALID_ARG, "a or b is NULL");
+    for (int i = 0; i < n_struct; ++i) {
+        TBK_CHECK(std::isfinite(a[i]) && std::isfinite(b[i]), TBK_ERR_NOT_FINITE, "a or b of structure %d", i);
+        TBK_CHECK(a[i] > 0, TBK_ERR_INVALID_ARG, "a[%d] = %g must be positive", i, a[i]);
+    }
+    if (nE == 0) return TBK_OK;
+    TBK_CHECK(mu && E && rho, TBK_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    DevBuf ab;
+    TBK_HIP(ab.alloc(2 * sizeof(double) * n_struct, s));
+    TBK_HIP(hipMemcpyAsync(ab.as<double>(), a, sizeof(double) * n_struct, hipMemcpyHostToDevice, s));
+    TBK_HIP(hipMemcpyAsync(ab.as<double>() + n_struct, b, sizeof(double) * n_struct, hipMemcpyHostToDevice, s));
+    k_dos<<<dim3((unsigned)ceil_div(nE, kDosThreads), (unsigned)n_struct), kDosThreads, 0, s>>>(
+        mu, M, 0.0, 0.0, ab.as<double>(), kernel, E, nE, nE, rho);
+    TBK_HIP(hipGetLastError());
+    TBK_HIP(hipStreamSynchronize(s));    // the caller's a and b must outlive the transfer
     return TBK_OK;
 }

@@ -22,7 +22,7 @@ namespace tbk {
 namespace {
 
 constexpr size_t kSegPartialBudget = 256ull << 20;
-constexpr int kPersistPerCU = 4;
+constexpr int kPersistMaxPerCU = 8;   // co-resident workgroups per CU planned for
 
 // Poll limit of the persistent team barrier (about 2^26 polls of ~100 cycles,
 // seconds); TBKPM_BARRIER_SPIN_LIMIT overrides it (tests force a timeout).
@@ -319,6 +319,31 @@ struct SegPlan {
            off_c1f = 0, off_c1 = 0, off_shift = 0, off_flag = 0, total = 0;
 };
 
+// Teams of the persistent launch: at most gmax workgroups, one team per
+// structure with at least one member, sizes proportional to tile counts.
+tbk_status partition_teams(SegPlan &sp, int64_t gmax) {
+    int64_t G = std::min<int64_t>(gmax, std::max<int64_t>(sp.n_tiles, sp.n_seg));
+    TBK_CHECK(sp.n_seg <= G, TBK_ERR_UNSUPPORTED,
+              "persistent launch needs one workgroup per structure (%d structures, %lld workgroups)", sp.n_seg,
+              (long long)G);
+    sp.boff.assign(sp.n_seg + 1, 0);
+    std::vector<int64_t> ks(sp.n_seg);
+    int64_t used = 0;
+    for (int g = 0; g < sp.n_seg; ++g) {
+        const int64_t Ts = sp.tile_off[g + 1] - sp.tile_off[g];
+        ks[g] = 1 + ((G - sp.n_seg) * Ts) / std::max<int64_t>(sp.n_tiles, 1);
+        ks[g] = std::min<int64_t>(ks[g], Ts);
+        used += ks[g];
+    }
+    sp.Gp = used;
+    sp.block_seg.resize(sp.Gp);
+    for (int g = 0; g < sp.n_seg; ++g) {
+        sp.boff[g + 1] = sp.boff[g] + ks[g];
+        for (int64_t b = sp.boff[g]; b < sp.boff[g + 1]; ++b) sp.block_seg[b] = g;
+    }
+    return TBK_OK;
+}
+
 tbk_status make_seg_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
                          hipStream_t s, SegPlan &sp) {
     TBK_CHECK(h != nullptr, TBK_ERR_INVALID_ARG, "h is NULL");
@@ -364,30 +389,11 @@ tbk_status make_seg_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precisi
         int dev = 0, cus = 0;
         TBK_HIP(hipGetDevice(&dev));
         TBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        // four co-resident 256-thread workgroups per CU (checked against the
-        // kernel's occupancy before the launch; the cooperative launch also
-        // refuses a grid that cannot be resident at once)
-        const int64_t gmax = (int64_t)cus * kPersistPerCU;
-        sp.Gp = std::min<int64_t>(gmax, std::max<int64_t>(sp.n_tiles, sp.n_seg));
-        TBK_CHECK(sp.n_seg <= sp.Gp, TBK_ERR_UNSUPPORTED,
-                  "persistent launch needs one workgroup per structure (%d structures, %lld workgroups)", sp.n_seg,
-                  (long long)sp.Gp);
-        // team sizes proportional to tiles, at least one each
-        sp.boff.assign(sp.n_seg + 1, 0);
-        std::vector<int64_t> ks(sp.n_seg);
-        int64_t used = 0;
-        for (int g = 0; g < sp.n_seg; ++g) {
-            const int64_t Ts = sp.tile_off[g + 1] - sp.tile_off[g];
-            ks[g] = 1 + ((sp.Gp - sp.n_seg) * Ts) / std::max<int64_t>(sp.n_tiles, 1);
-            ks[g] = std::min<int64_t>(ks[g], Ts);
-            used += ks[g];
-        }
-        sp.Gp = used;
-        sp.block_seg.resize(sp.Gp);
-        for (int g = 0; g < sp.n_seg; ++g) {
-            sp.boff[g + 1] = sp.boff[g] + ks[g];
-            for (int64_t b = sp.boff[g]; b < sp.boff[g + 1]; ++b) sp.block_seg[b] = g;
-        }
+        // up to eight co-resident 256-thread workgroups per CU; the launch
+        // re-partitions for what the kernel's occupancy allows (the
+        // cooperative launch also refuses a grid that cannot be resident)
+        st = partition_teams(sp, (int64_t)cus * kPersistMaxPerCU);
+        if (st != TBK_OK) return st;
         const size_t bpart = (size_t)M * sp.Gp * sp.base.Rp * sizeof(double);
         TBK_CHECK(bpart <= (4ull << 30), TBK_ERR_UNSUPPORTED, "persistent partials would need %zu bytes", bpart);
         sp.off_bpart = sp.total;
@@ -474,8 +480,6 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
         int32_t *bseg = reinterpret_cast<int32_t *>(w + sp.off_bseg);
         uint32_t *bar = reinterpret_cast<uint32_t *>(w + sp.off_bar);
         int32_t *abort_flag = reinterpret_cast<int32_t *>(bar + ns);
-        TBK_HIP(hipMemcpyAsync(boff, sp.boff.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s));
-        TBK_HIP(hipMemcpyAsync(bseg, sp.block_seg.data(), sizeof(int32_t) * sp.Gp, hipMemcpyHostToDevice, s));
         TBK_HIP(hipMemsetAsync(bar, 0, sizeof(uint32_t) * ns + 64, s));
         PersistBufs<VT> bufs{r_int, TA, TB, c1f, c1};
         PersistArgs pa{bseg, boff, toff, bpart, bar, abort_flag, M, barrier_spin_limit()};
@@ -492,13 +496,22 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
                             : (const void *)k_cheb_persistent<VT, L, VPT, true, false, 0>)
                       : (w3 ? (const void *)k_cheb_persistent<VT, L, VPT, false, false, 3>
                             : (const void *)k_cheb_persistent<VT, L, VPT, false, false, 0>);
-        int occ = 0;
+        int occ = 0, dev = 0, cus = 0;
         TBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, 0));
-        TBK_CHECK(occ >= kPersistPerCU, TBK_ERR_UNSUPPORTED, "persistent kernel fits %d workgroups per CU, needs %d",
-                  occ, kPersistPerCU);
-        TBK_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)sp.Gp), dim3(kThreads), args, 0, s));
+        TBK_CHECK(occ >= 1, TBK_ERR_UNSUPPORTED, "the persistent kernel does not fit on a CU");
+        TBK_HIP(hipGetDevice(&dev));
+        TBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        // the workspace was laid out for kPersistMaxPerCU workgroups per CU; fewer fit in the same space
+        SegPlan tp = sp;
+        tbk_status pst = partition_teams(tp, (int64_t)cus * std::min(occ, kPersistMaxPerCU));
+        if (pst != TBK_OK) return pst;
+        TBK_CHECK(tp.Gp <= sp.Gp, TBK_ERR_DEVICE, "persistent team layout exceeds its workspace");
+        TBK_HIP(hipMemcpyAsync(boff, tp.boff.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s));
+        TBK_HIP(hipMemcpyAsync(bseg, tp.block_seg.data(), sizeof(int32_t) * tp.Gp, hipMemcpyHostToDevice, s));
+        TBK_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)tp.Gp), dim3(kThreads), args, 0, s));
         dim3 rg(ns, (unsigned)ceil_div((int64_t)(M - 1) * R, 256));
-        k_reduce_persistent<<<rg, 256, 0, s>>>(bpart, sp.Gp, boff, Rp, R, M, mu);
+        k_reduce_persistent<<<rg, 256, 0, s>>>(bpart, tp.Gp, boff, Rp, R, M, mu);
+        TBK_HIP(hipStreamSynchronize(s));    // the host team tables must outlive their transfers
         TBK_HIP(hipGetLastError());
         int32_t habort = 0;
         TBK_HIP(hipMemcpyAsync(&habort, abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));

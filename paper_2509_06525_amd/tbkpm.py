@@ -49,7 +49,7 @@ class HamStruct(ctypes.Structure):
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
                "tb_build_hamiltonian", "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_dos", "tbk_autotune",
+               "kpm_moments", "kpm_moments_config", "kpm_dos", "kpm_dos_batched", "tbk_autotune",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -173,6 +173,8 @@ def lib():
                                                ctypes.POINTER(f64), vp, i64, ctypes.POINTER(i64), vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
+    L.kpm_dos_batched.restype = ctypes.c_int
+    L.kpm_dos_batched.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64), i32, vp, i32, vp, vp]
     _LIB = L
     return L
 
@@ -352,6 +354,18 @@ def kpm_dos(mu, a, b, E, kernel=0, stream=None):
     rho = torch.empty_like(E)
     _check(lib().kpm_dos(_ptr(mu), mu.numel(), float(a), float(b), int(kernel), _ptr(E), E.numel(),
                          _ptr(rho), _stream(stream)))
+    return rho
+
+
+def kpm_dos_batched(mu, a, b, E, kernel=0, stream=None):
+    """DOS of every structure: mu [S, M] (vector-averaged), a, b [S] (host), E [S, nE] -> rho [S, nE]."""
+    mu = _dev(mu, torch.float64)
+    E = _dev(E, torch.float64)
+    S, M = mu.shape
+    assert E.dim() == 2 and E.shape[0] == S
+    rho = torch.empty_like(E)
+    _check(lib().kpm_dos_batched(_ptr(mu), M, S, _f64arr(a), _f64arr(b), int(kernel), _ptr(E), E.shape[1],
+                                 _ptr(rho), _stream(stream)))
     return rho
 
 

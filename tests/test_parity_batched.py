@@ -187,3 +187,20 @@ def test_rebuild_into_existing_buffers():
     assert H1.bounds == ref.bounds
     if H1.tensors["col"].numel() == cap:
         assert H1.tensors["col"].data_ptr() == H0.tensors["col"].data_ptr()
+
+
+@pytest.mark.parametrize("M,nE,kernel", [(1, 5, 0), (256, 2001, 0), (1000, 257, 1), (300, 1, 0)])
+def test_batched_dos_matches_oracle(M, nE, kernel):
+    rng = np.random.default_rng(M + nE)
+    S = 5
+    mu = rng.normal(size=(S, M)) * np.exp(-np.arange(M) / 50.0)
+    mu[:, 0] = rng.uniform(50, 200, size=S)
+    a = rng.uniform(3.0, 12.0, size=S)
+    b = rng.uniform(-1.0, 1.0, size=S)
+    E = np.stack([np.linspace(b[k] - 1.1 * a[k], b[k] + 1.1 * a[k], nE) for k in range(S)])
+    rho = tbkpm.kpm_dos_batched(G.to_dev(mu), a, b, G.to_dev(E), kernel=kernel).cpu().numpy()
+    for k in range(S):
+        ro = O.kpm_dos(mu[k], a[k], b[k], E[k], kernel=kernel)
+        np.testing.assert_allclose(rho[k], ro, rtol=1e-11, atol=1e-12 * np.abs(ro).max())
+        single = tbkpm.kpm_dos(G.to_dev(mu[k]), a[k], b[k], G.to_dev(E[k]), kernel=kernel).cpu().numpy()
+        np.testing.assert_array_equal(single, rho[k])
