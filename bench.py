@@ -11,7 +11,9 @@ launch (Hamiltonian values, columns and slice offsets once; per vector row one
 gather of T_n, one read of T_{n-1} and of r, one write of T_{n+1}; onsite when
 used) over its average launch time measured with HIP events on the library's
 stream, against the 8 TB/s HBM3E peak.  `cpu_baseline` times the serial FP64
-oracle (one core) on a bounded sample of the same workload.
+oracle (one core) on a bounded sample of the same workload.  `variants` reports,
+each under its own label, the same moments computed with the doubling
+identities and, when all stored hoppings are equal, without reading them.
 """
 import argparse
 import hashlib
@@ -52,12 +54,12 @@ def parse():
     return p.parse_args()
 
 
-def cheb_step_bytes(H, Rp, elem, diag, read_r=True):
+def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True):
     """Algorithmic bytes of one recurrence launch (see module docstring); the
-    doubling form reads no r."""
+    doubling form reads no r, the uniform-values form no stored hoppings."""
     st = H.st
     val_b = 4 if st.fmt == 2 else 8
-    b = st.n_entries * (val_b + 4) + st.n_ptr * 8
+    b = st.n_entries * ((val_b if read_values else 0) + 4) + st.n_ptr * 8
     # gather T_n once, read T_{n-1}, write T_{n+1} (+ read r in the direct form)
     b += st.n_rows * Rp * 2 * elem * (4 if read_r else 3)
     if diag and st.has_onsite:
@@ -246,13 +248,15 @@ def bench_snapshots(args, w):
     print(json.dumps(out), flush=True)
 
 
-def doubling_variant(args, H, a, b, r, M, R, Rp, elem, diag, precision, config, mu_direct, rho_direct, E,
-                     stream, dev):
-    """The same moments from the doubling identities (two per step, M/2 + 1 launches, no
-    read of r), timed like the direct form and compared with it."""
+def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision, config, mu_direct, rho_direct,
+                E, stream, dev):
+    """The same moments with some launch-shape fields changed (doubling identities:
+    two moments per step, M/2 launches, no read of r; uniform values: the stored
+    hoppings are not read), timed like the direct form and compared with it."""
     import torch
     from paper_2509_06525_amd import tbkpm
-    cfg = tbkpm.with_doubling(config if config is not None else tbkpm.default_config(H, R, precision), 1)
+    base = config if config is not None else tbkpm.default_config(H, R, precision)
+    cfg = tbkpm.with_fields(base, **fields)
     work = tbkpm.alloc_workspace(H, R, M, precision, dev, cfg)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -266,20 +270,21 @@ def doubling_variant(args, H, a, b, r, M, R, Rp, elem, diag, precision, config, 
         ms.append(e0.elapsed_time(e1))
     med = float(np.median(ms))
     rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), a, b, E, stream=stream).cpu().numpy()
-    launches = M // 2
-    launch_bytes = cheb_step_bytes(H, Rp, elem, diag, read_r=False)
+    dbl = bool(cfg.doubling)
+    launches = M // 2 if dbl else M - 1
+    launch_bytes = cheb_step_bytes(H, Rp, elem, diag, read_r=not dbl, read_values=not cfg.uniform_values)
     launch_s = med * 1e-3 / launches
     achieved = launch_bytes / launch_s / 1e9
     N = H.st.n_rows
-    log(f"doubling: kpm {med:.1f} ms ({launches} launches)")
+    log(f"{label}: kpm {med:.1f} ms ({launches} launches)")
     return {"kpm_ms_median": med, "kpm_atom_moments_per_s": N * M * R / (med * 1e-3), "launches": launches,
             "launch": cfg.as_dict(),
             "dos_relL2_vs_direct": float(np.linalg.norm(rho - rho_direct) / np.linalg.norm(rho_direct)),
             "max_abs_dmu_over_N_vs_direct": float(np.abs(mu.cpu().numpy() - mu_direct).max() / N),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": profiled_traffic(args.workload, "doubling", H.st.slice, cfg.as_dict()),
-                         "kernel": "k_cheb_step (doubling form)",
+                         "traffic": profiled_traffic(args.workload, label, H.st.slice, cfg.as_dict()),
+                         "kernel": f"k_cheb_step ({label})",
                          "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6}}
 
 
@@ -413,9 +418,17 @@ def main():
     }
 
     log(f"timed: {sec_per_step * 1e3:.1f} ms/step, kpm {kpm_med:.1f} ms")
+    variants = []
     if not args.no_doubling and M >= 2:
-        out["variants"] = {"doubling": doubling_variant(args, Hs, aa, bb, r, M, R, Rp, elem, diag, w["precision"],
-                                                        config, mu_c, rho_c, E, stream, dev)}
+        variants.append(("doubling", {"doubling": 1}))
+    if Hs.st.uniform_hop:
+        variants.append(("uniform_values", {"uniform_values": 1}))
+        if not args.no_doubling and M >= 2:
+            variants.append(("doubling_uniform_values", {"doubling": 1, "uniform_values": 1}))
+    if variants:
+        out["variants"] = {label: kpm_variant(args, label, fields, Hs, aa, bb, r, M, R, Rp, elem, diag,
+                                              w["precision"], config, mu_c, rho_c, E, stream, dev)
+                           for label, fields in variants}
 
     # FP64 GPU path on the same structure and vectors (reported beside the C32 path).
     if not args.no_fp64 and w["precision"] == "c32":

@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 1
+#define TBK_ABI_VERSION 2
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -104,6 +104,10 @@ typedef struct {
     int64_t *seg_rows;     /* device int64 [n_seg+1]: rows of system s are
                               [seg_rows[s], seg_rows[s+1]); may be NULL when
                               n_seg == 1                                       */
+    int32_t uniform_hop;   /* out (build): 1 when every stored off-diagonal
+                              value equals hop_value (e.g. a pristine lattice
+                              in SELL_F32); 0 otherwise and for learned H      */
+    double hop_value;      /* out (build): that value, as stored (eV)         */
 } tbk_ham;
 
 /*
@@ -189,6 +193,10 @@ typedef struct {
                                    mu_2k = 2<T_k|T_k> - mu_0 and
                                    mu_2k-1 = 2 Re<T_k|T_k-1> - mu_1 (exact for
                                    Hermitian H; M/2 steps and no read of r)        */
+    int32_t uniform_values;     /* kpm_moments only: 1 = do not read the stored
+                                   off-diagonal values, use h->hop_value (needs
+                                   h->uniform_hop = 1; same results bit for bit,
+                                   4 or 8 B less per stored entry)                */
 } tbk_kpm_config;
 
 /* The launch shape kpm_moments uses for (h, R, precision) when none is given

@@ -64,6 +64,7 @@ void load_file_cache() {
         tbk_tune_result r{};
         r.config.persistent = 0;
         r.config.doubling = 0;
+        r.config.uniform_values = 0;
         if (std::sscanf(line, "%511s %d %d %d %d %d %d %lf", key, &r.slice, &r.config.vectors_per_thread,
                         &r.config.tiles_per_block, &r.config.nontemporal, &r.config.xcd_remap,
                         &r.config.rows_per_thread, &r.ms_per_step) == 8) {
@@ -240,6 +241,7 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
                             c.xcd_remap = xr;
                             c.persistent = 0;
                             c.doubling = 0;
+                            c.uniform_values = 0;
                             double ms = 0.0;
                             st = time_shape(*hp, c, R, steps, precision, a, b, rbuf.as<void>(),
                                             mubuf.as<double>(), s, &ms);

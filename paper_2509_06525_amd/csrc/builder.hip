@@ -173,9 +173,10 @@ __global__ void k_fill(CellList cl, const double *__restrict__ pos, const int32_
                        const SpeciesTable *__restrict__ tab, const int32_t *__restrict__ perm,
                        const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                        int32_t *__restrict__ col, V *__restrict__ val, V *__restrict__ onsite,
-                       int64_t *__restrict__ bound_keys) {
+                       int64_t *__restrict__ bound_keys, int64_t *__restrict__ val_keys) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
+    double vlo = INFINITY, vhi = -INFINITY;   // range of the stored hoppings
     int32_t sg = -1;
     if (r < n) {
         const int64_t s = r / slice, lane = r - s * slice;
@@ -192,6 +193,8 @@ __global__ void k_fill(CellList cl, const double *__restrict__ pos, const int32_
                 col[base + (int64_t)k * slice] = iperm[j];
                 val[base + (int64_t)k * slice] = (V)t;
             }
+            vlo = fmin(vlo, (double)(V)t);
+            vhi = fmax(vhi, (double)(V)t);
             asum += fabs(t);
             ++k;
         });
@@ -219,6 +222,7 @@ __global__ void k_fill(CellList cl, const double *__restrict__ pos, const int32_
         hi = eps + asum;
     }
     block_segment_bounds(lo, hi, sg, bound_keys);
+    block_segment_bounds(vlo, vhi, vlo <= vhi ? 0 : -1, val_keys);
 }
 
 template <class T>
@@ -485,6 +489,8 @@ tbk_status HamPlan::fill(const double *pos, const int32_t *species, int64_t n, c
     }
     DevBuf dtab, keys;
     TBK_HIP(dtab.alloc(sizeof(SpeciesTable), s));
+    st = init_bound_keys(vkeys, 1, s);
+    if (st != TBK_OK) return st;
     TBK_HIP(hipMemcpyAsync(dtab.as<void>(), &tab, sizeof(SpeciesTable), hipMemcpyHostToDevice, s));
     st = init_bound_keys(keys, nseg, s);
     if (st != TBK_OK) return st;
@@ -495,12 +501,14 @@ tbk_status HamPlan::fill(const double *pos, const int32_t *species, int64_t n, c
         k_fill<float><<<gn, kBlock, 0, s>>>(cells.view, pos, species, n, slice, p->r_cut, p->r0, p->beta,
                                             p->n_species, dtab.as<SpeciesTable>(), perm.as<int32_t>(),
                                             iperm.as<int32_t>(), h->ptr, h->col, static_cast<float *>(h->val),
-                                            static_cast<float *>(h->onsite), keys.as<int64_t>());
+                                            static_cast<float *>(h->onsite), keys.as<int64_t>(),
+                                            vkeys.as<int64_t>());
     } else {
         k_fill<double><<<gn, kBlock, 0, s>>>(cells.view, pos, species, n, slice, p->r_cut, p->r0, p->beta,
                                              p->n_species, dtab.as<SpeciesTable>(), perm.as<int32_t>(),
                                              iperm.as<int32_t>(), h->ptr, h->col, static_cast<double *>(h->val),
-                                             static_cast<double *>(h->onsite), keys.as<int64_t>());
+                                             static_cast<double *>(h->onsite), keys.as<int64_t>(),
+                                             vkeys.as<int64_t>());
     }
     TBK_HIP(hipGetLastError());
     return finish(keys, n, p, h, bounds, s);
@@ -510,13 +518,23 @@ tbk_status HamPlan::finish(DevBuf &keys, int64_t n, const tbk_tb_params *p, tbk_
                            hipStream_t s) {
     const int nseg = cells.n_seg;
     std::vector<int64_t> hk(2 * (size_t)nseg);
+    int64_t vk[2] = {0, 0};
     TBK_HIP(hipMemcpyAsync(hk.data(), keys.as<int64_t>(), sizeof(int64_t) * 2 * nseg, hipMemcpyDeviceToHost, s));
+    if (vkeys.as<int64_t>())
+        TBK_HIP(hipMemcpyAsync(vk, vkeys.as<int64_t>(), sizeof vk, hipMemcpyDeviceToHost, s));
     if (h->seg_rows)
         TBK_HIP(hipMemcpyAsync(h->seg_rows, cells.seg_atoms.as<int64_t>(), sizeof(int64_t) * (nseg + 1),
                                hipMemcpyDeviceToDevice, s));
     TBK_HIP(hipStreamSynchronize(s));
     decode_bounds(hk, nseg, bounds);
     set_sizes(n, p, h);
+    // uniform hoppings: every stored value (as stored) equal, at least one entry
+    h->uniform_hop = 0;
+    h->hop_value = 0.0;
+    if (vkeys.as<int64_t>() && vk[0] == vk[1] && dunkey(vk[0]) <= dunkey(vk[1])) {
+        h->uniform_hop = 1;
+        h->hop_value = dunkey(vk[0]);
+    }
     return TBK_OK;
 }
 

@@ -63,6 +63,7 @@ tbk_status init_bound_keys(DevBuf &keys, int nseg, hipStream_t s);
 struct HamPlan {
     CellListOwner cells;
     DevBuf perm, iperm, deg, ptr;
+    DevBuf vkeys;    // range of the stored hoppings (plain assembly only)
     int64_t n_slices = 0, n_entries = 0, n_bonds = 0;
     int32_t max_degree = 0;
     int32_t slice = 1;

@@ -39,6 +39,8 @@ template <class VT> struct StepScalars {
     int32_t xcd_remap;
     VT c1;                   // 2/a (1/a on the first step)
     VT shift;                // b
+    VT hop;                  // the one off-diagonal value when `uniform`
+    int32_t uniform;         // 1: values are not read, every real entry is `hop`
 };
 
 // One recurrence step.  Each thread handles RPT rows (from RPT consecutive
@@ -124,7 +126,8 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
                 for (int k = 0; k < KU; ++k) {
                     if constexpr (W > 0) {
                         c[u][k] = ld<NT>(col + base[u] + k * stride);
-                        h[u][k] = ld<NT>(val + base[u] + k * stride);
+                        if (a.uniform) h[u][k] = c[u][k] == (int32_t)i[u] ? (VT)0 : a.hop;   // padding: own row
+                        else h[u][k] = ld<NT>(val + base[u] + k * stride);
                     } else {
                         // w[u] >= 1 here unless the whole slice is empty; then read the
                         // row's own diagonal position (entry 0 of a neighbouring slice
@@ -132,7 +135,9 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
                         const int kk = min(k0 + k, w[u] - 1);
                         if (kk >= 0) {
                             c[u][k] = ld<NT>(col + base[u] + kk * stride);
-                            h[u][k] = (k0 + k < w[u]) ? ld<NT>(val + base[u] + kk * stride) : (VT)0;
+                            if (k0 + k >= w[u]) h[u][k] = 0;
+                            else if (a.uniform) h[u][k] = c[u][k] == (int32_t)i[u] ? (VT)0 : a.hop;
+                            else h[u][k] = ld<NT>(val + base[u] + kk * stride);
                         } else {
                             c[u][k] = (int32_t)i[u];
                             h[u][k] = 0;
@@ -402,6 +407,8 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     sa.tiles_per_block = pl.cfg.tiles_per_block;
     sa.xcd_remap = pl.cfg.xcd_remap;
     sa.shift = (VT)b;
+    sa.hop = (VT)h->hop_value;
+    sa.uniform = pl.cfg.uniform_values;
     const bool diag = h->has_onsite || b != 0.0;
     auto reduce = [&](int n0, int count) {
         dim3 grid(pl.n_chunks, count);
@@ -472,6 +479,7 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.rows_per_thread = 1;
     c.persistent = 0;
     c.doubling = 0;
+    c.uniform_values = 0;
     (void)h;
     return c;
 }
@@ -506,6 +514,10 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
               "rows_per_thread must be 1 or 2");
     TBK_CHECK(pl.cfg.persistent == 0 || pl.cfg.persistent == 1, TBK_ERR_INVALID_ARG, "persistent must be 0/1");
     TBK_CHECK(pl.cfg.doubling == 0 || pl.cfg.doubling == 1, TBK_ERR_INVALID_ARG, "doubling must be 0/1");
+    TBK_CHECK(pl.cfg.uniform_values == 0 || pl.cfg.uniform_values == 1, TBK_ERR_INVALID_ARG,
+              "uniform_values must be 0/1");
+    TBK_CHECK(pl.cfg.uniform_values == 0 || h->uniform_hop == 1, TBK_ERR_INVALID_ARG,
+              "uniform_values needs a Hamiltonian whose stored hoppings are all equal (h->uniform_hop)");
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;

@@ -851,5 +851,6 @@ extern "C" tbk_status tb_build_hamiltonian_learned(const double *pos, const int3
                                                    static_cast<const double *>(h->onsite), h->perm,
                                                    plan.cells.view.seg_of, l2, keys.as<int64_t>());
     TBK_HIP(hipGetLastError());
+    plan.vkeys.release();    // the plain values' range no longer describes the learned ones
     return plan.finish(keys, n, p, h, spec_bounds, s);
 }

@@ -43,7 +43,7 @@ class HamStruct(ctypes.Structure):
                 ("n_seg", ctypes.c_int32),
                 ("ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("onsite", ctypes.c_void_p), ("perm", ctypes.c_void_p),
-                ("seg_rows", ctypes.c_void_p)]
+                ("seg_rows", ctypes.c_void_p), ("uniform_hop", ctypes.c_int32), ("hop_value", ctypes.c_double)]
 
 
 _LIB = None
@@ -67,7 +67,7 @@ class KpmConfig(ctypes.Structure):
     _fields_ = [("vectors_per_thread", ctypes.c_int32), ("tiles_per_block", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("doubling", ctypes.c_int32)]
+                ("doubling", ctypes.c_int32), ("uniform_values", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,15 +79,20 @@ class TuneResult(ctypes.Structure):
 
 
 def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1,
-                persistent=0, doubling=0):
+                persistent=0, doubling=0, uniform_values=0):
     return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread, persistent,
-                     doubling)
+                     doubling, uniform_values)
 
 
 def with_doubling(cfg, on=1):
     """A copy of a launch shape with the doubling identities switched on or off."""
+    return with_fields(cfg, doubling=int(on))
+
+
+def with_fields(cfg, **fields):
+    """A copy of a launch shape with some fields replaced."""
     d = cfg.as_dict()
-    d["doubling"] = int(on)
+    d.update(fields)
     return KpmConfig(**d)
 
 

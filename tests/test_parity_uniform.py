@@ -1,0 +1,74 @@
+"""GPU parity of the uniform-hopping form of the recurrence.
+
+When every stored off-diagonal value is the same number (a pristine lattice in
+SELL-F32: all hoppings are t(r0) = t_pair, stored as one float), the builder
+flags it and the recurrence can use that one value instead of reading the
+stored ones.  The products are then the same numbers in the same order, so the
+moments equal those of the stored-value path bit for bit, and both match the
+oracle to the complex-float bar.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(s, R, M, fields, slice=64, precision="c32"):
+    H = G.build(s, fmt="sell_f32", slice=slice)
+    a, b = H.scale()
+    r = G.to_dev(synth.random_phase(s.n, R, 5, np.complex64))
+    base = tbkpm.make_config(2 if R >= 2 else 1, 2, 1, 0, 1)
+    m0 = tbkpm.kpm_moments(H, a, b, r, M, precision, config=base).cpu().numpy()
+    m1 = tbkpm.kpm_moments(H, a, b, r, M, precision, config=tbkpm.with_fields(base, **fields)).cpu().numpy()
+    return H, a, b, m0, m1
+
+
+@pytest.mark.parametrize("R", [1, 4])
+@pytest.mark.parametrize("slice", [1, 16, 256])
+def test_pristine_uniform_values_bitwise(R, slice):
+    s = synth.graphene_sheet(37, 23)          # 3404 rows: ragged tail
+    H, a, b, m0, m1 = _pair(s, R, 200, {"uniform_values": 1}, slice=slice)
+    assert H.st.uniform_hop == 1
+    assert H.st.hop_value == float(np.float32(-2.7))
+    np.testing.assert_array_equal(m1, m0)
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    r = synth.random_phase(s.n, R, 5, np.complex64)
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 200)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(m1.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+
+
+def test_uniform_values_with_padding_rows():
+    """Open y boundary: edge rows have degree 2 (a padding entry with the row's own column)."""
+    s0 = synth.graphene_sheet(20, 9)
+    s = synth.Structure(pos=s0.pos, species=s0.species, box=s0.box,
+                        periodic=np.array([1, 0, 0], np.int32), onsite=s0.onsite, t_pair=s0.t_pair)
+    H, a, b, m0, m1 = _pair(s, 2, 120, {"uniform_values": 1}, slice=32)
+    assert H.st.uniform_hop == 1
+    assert H.st.n_bonds < 3 * s.n // 2           # some rows have fewer than 3 neighbours
+    np.testing.assert_array_equal(m1, m0)
+
+
+def test_uniform_values_with_doubling():
+    s = synth.graphene_sheet(29, 31)
+    H, a, b, m0, m1 = _pair(s, 1, 301, {"uniform_values": 1, "doubling": 1})
+    _, _, _, _, m2 = _pair(s, 1, 301, {"doubling": 1})
+    np.testing.assert_array_equal(m1, m2)
+    assert np.abs(m1 - m0).max() <= 1e-4 * s.n
+
+
+def test_non_uniform_hamiltonians_are_flagged_and_refused():
+    s = synth.graphene_sheet(12, 10, 0.05, 3)     # displaced: hoppings differ
+    H = G.build(s, fmt="sell_f32", slice=32)
+    assert H.st.uniform_hop == 0
+    r = G.to_dev(synth.random_phase(s.n, 1, 2, np.complex64))
+    a, b = H.scale()
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.kpm_moments(H, a, b, r, 16, "c32", config=tbkpm.make_config(1, 2, 1, 0, 1, 0, 0, 1))
+    assert e.value.name == "INVALID_ARG"
+    st = synth.hbn_stripes(12, 9, stripe_cells=3, sigma=0.0, seed=5)
+    assert G.build(st, fmt="sell_f32", slice=32).st.uniform_hop == 0   # several pair types
