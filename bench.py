@@ -249,14 +249,21 @@ def bench_snapshots(args, w):
 
 
 def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision, config, mu_direct, rho_direct,
-                E, stream, dev):
-    """The same moments with some launch-shape fields changed (doubling identities:
+                E, stream, dev, tune=None):
+    """The same moments in another form of the recurrence (doubling identities:
     two moments per step, M/2 launches, no read of r; uniform values: the stored
-    hoppings are not read), timed like the direct form and compared with it."""
+    hoppings are not read), timed like the direct form and compared with it.
+    `tune` (slice, config) is the form's own tuned shape; H is rebuilt when its
+    slice height differs."""
     import torch
     from paper_2509_06525_amd import tbkpm
-    base = config if config is not None else tbkpm.default_config(H, R, precision)
-    cfg = tbkpm.with_fields(base, **fields)
+    if tune is not None:
+        slice_v, cfg = tune
+        if slice_v != H.st.slice:
+            H = args.rebuild(slice_v)
+    else:
+        base = config if config is not None else tbkpm.default_config(H, R, precision)
+        cfg = tbkpm.with_fields(base, **fields)
     work = tbkpm.alloc_workspace(H, R, M, precision, dev, cfg)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -426,9 +433,18 @@ def main():
         if not args.no_doubling and M >= 2:
             variants.append(("doubling_uniform_values", {"doubling": 1, "uniform_values": 1}))
     if variants:
-        out["variants"] = {label: kpm_variant(args, label, fields, Hs, aa, bb, r, M, R, Rp, elem, diag,
-                                              w["precision"], config, mu_c, rho_c, E, stream, dev)
-                           for label, fields in variants}
+        args.rebuild = lambda sl: tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair,
+                                                          r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                                          fmt=fmt, slice=sl, stream=stream)
+        out["variants"] = {}
+        for label, fields in variants:
+            vt = None
+            if tune is not None:
+                t = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, R, w["precision"],
+                                   r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, stream=stream, **fields)
+                vt = (t.slice, t.config)
+            out["variants"][label] = kpm_variant(args, label, fields, Hs, aa, bb, r, M, R, Rp, elem, diag,
+                                                 w["precision"], config, mu_c, rho_c, E, stream, dev, vt)
 
     # FP64 GPU path on the same structure and vectors (reported beside the C32 path).
     if not args.no_fp64 and w["precision"] == "c32":

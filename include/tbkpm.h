@@ -291,6 +291,17 @@ tbk_status tbk_autotune(const double *pos, const int32_t *species, int64_t n,
                         const tbk_tb_params *p, int32_t fmt, int32_t R, int32_t precision,
                         int32_t steps, tbk_tune_result *out, void *stream);
 
+/* tbk_autotune for one form of the recurrence: `form` gives the fields
+ * doubling and uniform_values (the other fields are ignored; NULL = the
+ * direct form); the returned config carries them.  The cache key includes the
+ * form.  Extra error: INVALID_ARG when uniform_values = 1 and the structure's
+ * hoppings are not all equal at some candidate slice height. */
+tbk_status tbk_autotune_form(const double *pos, const int32_t *species, int64_t n,
+                             const double box[3], const int32_t periodic[3],
+                             const tbk_tb_params *p, int32_t fmt, int32_t R, int32_t precision,
+                             int32_t steps, const tbk_kpm_config *form, tbk_tune_result *out,
+                             void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Learned hoppings (radial descriptor + per-bond MLP)                       */
 /* ------------------------------------------------------------------------ */

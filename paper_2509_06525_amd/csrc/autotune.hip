@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -69,6 +70,8 @@ void load_file_cache() {
                         &r.config.tiles_per_block, &r.config.nontemporal, &r.config.xcd_remap,
                         &r.config.rows_per_thread, &r.ms_per_step) == 8) {
             r.from_cache = 1;
+            r.config.doubling = std::strstr(key, "/dbl1") ? 1 : 0;
+            r.config.uniform_values = std::strstr(key, "/uv1") ? 1 : 0;
             g_cache[Key{key}] = r;
         }
     }
@@ -87,12 +90,12 @@ void append_file_cache(const Key &k, const tbk_tune_result &r) {
 }
 
 Key make_key(int device, const char *arch, int64_t n, int32_t R, int32_t precision, int32_t fmt,
-             const tbk_ham &h0) {
+             const tbk_ham &h0, int32_t doubling, int32_t uniform_values) {
     int lg = 0;
     while (((int64_t)1 << (lg + 1)) <= n) ++lg;
     char buf[512];
-    std::snprintf(buf, sizeof buf, "%s/dev%d/n2^%d/R%d/p%d/f%d/deg%d/ons%d", arch, device, lg, R, precision, fmt,
-                  h0.max_degree, h0.has_onsite);
+    std::snprintf(buf, sizeof buf, "%s/dev%d/n2^%d/R%d/p%d/f%d/deg%d/ons%d%s%s", arch, device, lg, R, precision,
+                  fmt, h0.max_degree, h0.has_onsite, doubling ? "/dbl1" : "", uniform_values ? "/uv1" : "");
     return Key{buf};
 }
 
@@ -127,7 +130,7 @@ tbk_status build_tune_ham(const double *pos, const int32_t *species, int64_t n, 
 tbk_status time_shape(const tbk_ham &h, const tbk_kpm_config &cfg, int32_t R, int32_t steps, int32_t precision,
                       double a, double b, const void *r, double *mu, hipStream_t s, double *ms_out) {
     KpmPlan pl;
-    const int M = steps + 1;
+    const int M = cfg.doubling ? 2 * steps + 1 : steps + 1;   // `steps` launches either way
     tbk_status st = make_plan(&h, R, M, precision, &cfg, pl);
     if (st != TBK_OK) return st;
     DevBuf work;
@@ -157,10 +160,12 @@ tbk_status time_shape(const tbk_ham &h, const tbk_kpm_config &cfg, int32_t R, in
 
 using namespace tbk;
 
-extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, int64_t n, const double box[3],
-                                   const int32_t periodic[3], const tbk_tb_params *p, int32_t fmt, int32_t R,
-                                   int32_t precision, int32_t steps, tbk_tune_result *out, void *stream) {
-    clear_error();
+namespace {
+
+tbk_status autotune_impl(const double *pos, const int32_t *species, int64_t n, const double box[3],
+                         const int32_t periodic[3], const tbk_tb_params *p, int32_t fmt, int32_t R,
+                         int32_t precision, int32_t steps, int32_t doubling, int32_t uniform_values,
+                         tbk_tune_result *out, void *stream) {
     TBK_CHECK(out != nullptr, TBK_ERR_INVALID_ARG, "out is NULL");
     TBK_CHECK(R >= 1 && R <= 64, TBK_ERR_INVALID_ARG, "R = %d outside [1, 64]", R);
     TBK_CHECK(steps >= 1 && steps <= 1000, TBK_ERR_INVALID_ARG, "steps = %d outside [1, 1000]", steps);
@@ -181,11 +186,15 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
     TBK_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     TBK_HIP(hipGetDeviceProperties(&prop, dev));
-    const Key key = make_key(dev, prop.gcnArchName, n, R, precision, fmt, t0.h);
+    const Key key = make_key(dev, prop.gcnArchName, n, R, precision, fmt, t0.h, doubling, uniform_values);
+    TBK_CHECK(uniform_values == 0 || t0.h.uniform_hop == 1, TBK_ERR_INVALID_ARG,
+              "uniform_values: the structure's hoppings are not all equal");
 
     tbk_tune_result best{};
     best.slice = rpb1;
     best.config = default_config(&t0.h, R, precision);
+    best.config.doubling = doubling;
+    best.config.uniform_values = uniform_values;
     best.ms_per_step = -1.0;
     const char *env = std::getenv("TBKPM_AUTOTUNE");
     if (env && std::string(env) == "0") {
@@ -207,7 +216,7 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
     const size_t elem = precision == TBK_PREC_C32 ? sizeof(float) : sizeof(double);
     DevBuf rbuf, mubuf;
     TBK_HIP(rbuf.alloc((size_t)n * R * 2 * elem, s));
-    TBK_HIP(mubuf.alloc(sizeof(double) * R * (steps + 1), s));
+    TBK_HIP(mubuf.alloc(sizeof(double) * R * (2 * steps + 1), s));
     const int64_t nv = n * R;
     if (precision == TBK_PREC_C32)
         k_tune_vectors<float><<<(unsigned)ceil_div(nv, 256), 256, 0, s>>>(rbuf.as<float>(), n, R);
@@ -227,6 +236,8 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
                 st = build_tune_ham(pos, species, n, box, periodic, p, fmt, slice, th, bb, s);
                 if (st != TBK_OK) return st;
                 hp = &th.h;
+                TBK_CHECK(uniform_values == 0 || th.h.uniform_hop == 1, TBK_ERR_INVALID_ARG,
+                          "uniform_values: the hoppings are not all equal at slice %d", slice);
             }
             for (int tpb : {1, 2, 4})
                 for (int rpt : {1, 2}) {
@@ -240,8 +251,8 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
                             c.nontemporal = nt;
                             c.xcd_remap = xr;
                             c.persistent = 0;
-                            c.doubling = 0;
-                            c.uniform_values = 0;
+                            c.doubling = doubling;
+                            c.uniform_values = uniform_values;
                             double ms = 0.0;
                             st = time_shape(*hp, c, R, steps, precision, a, b, rbuf.as<void>(),
                                             mubuf.as<double>(), s, &ms);
@@ -266,4 +277,24 @@ extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, in
     }
     *out = best;
     return TBK_OK;
+}
+
+}  // namespace
+
+extern "C" tbk_status tbk_autotune(const double *pos, const int32_t *species, int64_t n, const double box[3],
+                                   const int32_t periodic[3], const tbk_tb_params *p, int32_t fmt, int32_t R,
+                                   int32_t precision, int32_t steps, tbk_tune_result *out, void *stream) {
+    clear_error();
+    return autotune_impl(pos, species, n, box, periodic, p, fmt, R, precision, steps, 0, 0, out, stream);
+}
+
+extern "C" tbk_status tbk_autotune_form(const double *pos, const int32_t *species, int64_t n, const double box[3],
+                                        const int32_t periodic[3], const tbk_tb_params *p, int32_t fmt, int32_t R,
+                                        int32_t precision, int32_t steps, const tbk_kpm_config *form,
+                                        tbk_tune_result *out, void *stream) {
+    clear_error();
+    const int32_t dbl = form ? form->doubling : 0, uv = form ? form->uniform_values : 0;
+    TBK_CHECK(dbl == 0 || dbl == 1, TBK_ERR_INVALID_ARG, "form->doubling must be 0/1");
+    TBK_CHECK(uv == 0 || uv == 1, TBK_ERR_INVALID_ARG, "form->uniform_values must be 0/1");
+    return autotune_impl(pos, species, n, box, periodic, p, fmt, R, precision, steps, dbl, uv, out, stream);
 }

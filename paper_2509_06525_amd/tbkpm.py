@@ -49,7 +49,7 @@ class HamStruct(ctypes.Structure):
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
                "tb_build_hamiltonian", "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_dos", "kpm_dos_batched", "tbk_autotune",
+               "kpm_moments", "kpm_moments_config", "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -132,6 +132,10 @@ def lib():
     L.tbk_autotune.restype = ctypes.c_int
     L.tbk_autotune.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(TbParams),
                                i32, i32, i32, i32, ctypes.POINTER(TuneResult), vp]
+    L.tbk_autotune_form.restype = ctypes.c_int
+    L.tbk_autotune_form.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                    ctypes.POINTER(TbParams), i32, i32, i32, i32, ctypes.POINTER(KpmConfig),
+                                    ctypes.POINTER(TuneResult), vp]
     L.tbk_hamiltonian_size_batched.restype = ctypes.c_int
     L.tbk_hamiltonian_size_batched.argtypes = [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
                                                ctypes.POINTER(i32), ctypes.POINTER(TbParams),
@@ -375,8 +379,9 @@ def kpm_dos_batched(mu, a, b, E, kernel=0, stream=None):
 
 
 def autotune(pos, species, box, periodic, onsite, t_pair, R, precision="c32", r_cut=2.0, r0=1.42,
-             beta=3.37, reorder=True, steps=8, stream=None):
-    """Fastest (slice, launch shape) for this structure and R; returns a TuneResult."""
+             beta=3.37, reorder=True, steps=8, stream=None, doubling=0, uniform_values=0):
+    """Fastest (slice, launch shape) for this structure, R and form of the
+    recurrence (doubling identities, uniform values); returns a TuneResult."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
@@ -385,9 +390,10 @@ def autotune(pos, species, box, periodic, onsite, t_pair, R, precision="c32", r_
     per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
     out = TuneResult()
     fmt = "sell_f32" if precision == "c32" else "sell_f64"
-    _check(L.tbk_autotune(_ptr(pos), _ptr(species), pos.shape[0], boxa, per, ctypes.byref(p),
-                          FORMATS[fmt], int(R), PRECISIONS[precision], int(steps), ctypes.byref(out),
-                          _stream(stream)))
+    form = make_config(doubling=int(doubling), uniform_values=int(uniform_values))
+    _check(L.tbk_autotune_form(_ptr(pos), _ptr(species), pos.shape[0], boxa, per, ctypes.byref(p),
+                               FORMATS[fmt], int(R), PRECISIONS[precision], int(steps), ctypes.byref(form),
+                               ctypes.byref(out), _stream(stream)))
     del keep
     return out
 
