@@ -183,8 +183,10 @@ typedef struct {
     int32_t tiles_per_block;    /* >= 1: consecutive tiles one workgroup handles    */
     int32_t nontemporal;        /* 1: streamed arrays use non-temporal loads/stores */
     int32_t xcd_remap;          /* 1: each XCD sweeps a contiguous eighth of rows   */
-    int32_t rows_per_thread;    /* 1 or 2: rows (from consecutive tiles) a thread
-                                   advances together                               */
+    int32_t rows_per_thread;    /* 1, 2 or 4: rows (from consecutive tiles) a
+                                   thread advances together; 4 takes effect with
+                                   one vector per thread row on width-3 slices and
+                                   runs as 2 elsewhere                             */
     int32_t persistent;         /* kpm_moments_batched only: 1 = all steps in one
                                    cooperative launch (a team of workgroups per
                                    structure, barrier per step); 0 = one launch

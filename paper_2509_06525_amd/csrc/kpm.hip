@@ -320,9 +320,18 @@ template <class VT> struct StepPtrs {
     double *partial;
 };
 
+// rows_per_thread 4 is instantiated for one vector per row on width-3 slices
+// (the latency-bound case: 44-56 B per row); elsewhere it runs as 2.
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W, bool DBL>
 void launch_step_d(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
-    if (pl.cfg.rows_per_thread == 2)
+    if constexpr (L == 1 && VPT == 1 && W == 3) {
+        if (pl.cfg.rows_per_thread == 4) {
+            k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 4, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
+                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+            return;
+        }
+    }
+    if (pl.cfg.rows_per_thread >= 2)
         k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 2, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
             p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
     else
@@ -510,8 +519,8 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
               "tiles_per_block = %d outside [1, 2^20]", pl.cfg.tiles_per_block);
     TBK_CHECK(pl.cfg.nontemporal == 0 || pl.cfg.nontemporal == 1, TBK_ERR_INVALID_ARG, "nontemporal must be 0/1");
     TBK_CHECK(pl.cfg.xcd_remap == 0 || pl.cfg.xcd_remap == 1, TBK_ERR_INVALID_ARG, "xcd_remap must be 0/1");
-    TBK_CHECK(pl.cfg.rows_per_thread == 1 || pl.cfg.rows_per_thread == 2, TBK_ERR_INVALID_ARG,
-              "rows_per_thread must be 1 or 2");
+    TBK_CHECK(pl.cfg.rows_per_thread == 1 || pl.cfg.rows_per_thread == 2 || pl.cfg.rows_per_thread == 4,
+              TBK_ERR_INVALID_ARG, "rows_per_thread must be 1, 2 or 4");
     TBK_CHECK(pl.cfg.persistent == 0 || pl.cfg.persistent == 1, TBK_ERR_INVALID_ARG, "persistent must be 0/1");
     TBK_CHECK(pl.cfg.doubling == 0 || pl.cfg.doubling == 1, TBK_ERR_INVALID_ARG, "doubling must be 0/1");
     TBK_CHECK(pl.cfg.uniform_values == 0 || pl.cfg.uniform_values == 1, TBK_ERR_INVALID_ARG,

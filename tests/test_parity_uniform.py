@@ -72,3 +72,27 @@ def test_non_uniform_hamiltonians_are_flagged_and_refused():
     assert e.value.name == "INVALID_ARG"
     st = synth.hbn_stripes(12, 9, stripe_cells=3, sigma=0.0, seed=5)
     assert G.build(st, fmt="sell_f32", slice=32).st.uniform_hop == 0   # several pair types
+
+
+@pytest.mark.parametrize("tpb", [4, 8, 5])
+@pytest.mark.parametrize("fields", [{}, {"doubling": 1}, {"uniform_values": 1}, {"doubling": 1, "uniform_values": 1}])
+def test_four_rows_per_thread(tpb, fields):
+    """rows_per_thread = 4 (one vector, width-3 slices): same T_n as one row per
+    thread, moments to FP64 rounding; FP64 path against the oracle."""
+    s = synth.graphene_sheet(37, 23)              # 3404 rows: 13.3 tiles of 256
+    H = G.build(s, fmt="sell_f32", slice=256)
+    a, b = H.scale()
+    r = G.to_dev(synth.random_phase(s.n, 1, 8, np.complex64))
+    m1 = tbkpm.kpm_moments(H, a, b, r, 150, "c32", config=tbkpm.make_config(1, tpb, 1, 0, 1, **fields))
+    m4 = tbkpm.kpm_moments(H, a, b, r, 150, "c32", config=tbkpm.make_config(1, tpb, 1, 0, 4, **fields))
+    assert np.abs((m4 - m1).cpu().numpy()).max() <= 1e-12 * s.n
+    if "uniform_values" not in fields:
+        s64 = synth.graphene_sheet(19, 13, 0.03, 4)
+        H64 = G.build(s64, fmt="sell_f64", slice=256)
+        a, b = H64.scale()
+        r64 = synth.random_phase(s64.n, 1, 9)
+        mu = tbkpm.kpm_moments(H64, a, b, G.to_dev(r64), 77, "f64",
+                               config=tbkpm.make_config(1, tpb, 0, 1, 4, **fields)).cpu().numpy()
+        csr, _ = O.hamiltonian(s64.pos, s64.species, s64.box, s64.periodic, s64.onsite, s64.t_pair)
+        mo, _ = O.kpm_moments(csr, a, b, r64, 77)
+        assert np.abs(mu - mo).max() <= 1e-10 * s64.n
