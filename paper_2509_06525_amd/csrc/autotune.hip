@@ -241,7 +241,7 @@ tbk_status autotune_impl(const double *pos, const int32_t *species, int64_t n, c
             }
             for (int tpb : {1, 2, 4, 8})
                 for (int rpt : {1, 2, 4}) {
-                    if (rpt > tpb || (tpb == 8 && rpt < 4)) continue;
+                    if (rpt > tpb) continue;
                     if (rpt == 4 && (Rp / vpt != 1 || hp->max_degree != 3)) continue;   // see rows_per_thread
                     for (int nt : {0, 1})
                         for (int xr : {0, 1}) {
