@@ -90,7 +90,7 @@ def profiled_traffic(workload, kernel, slice_, launch):
                 parts = dict(kv.split("=", 1) for kv in line.split()[1:])
                 rec[parts["kernel"]] = parts
     r = rec.get(kernel)
-    if r is None or r["sources"] != kernel_source_hash() or int(r["slice"]) != slice_:
+    if r is None or r["sources"] != kernel_source_hash() or int(r["slice"]) != int(slice_):
         return None
     if r["launch"] != ",".join(f"{k}:{v}" for k, v in sorted(launch.items())):
         return None
@@ -285,7 +285,7 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
     N = H.st.n_rows
     log(f"{label}: kpm {med:.1f} ms ({launches} launches)")
     return {"kpm_ms_median": med, "kpm_atom_moments_per_s": N * M * R / (med * 1e-3), "launches": launches,
-            "launch": cfg.as_dict(),
+            "slice": H.st.slice, "launch": cfg.as_dict(),
             "dos_relL2_vs_direct": float(np.linalg.norm(rho - rho_direct) / np.linalg.norm(rho_direct)),
             "max_abs_dmu_over_N_vs_direct": float(np.abs(mu.cpu().numpy() - mu_direct).max() / N),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
