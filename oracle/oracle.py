@@ -63,6 +63,10 @@ def _lib():
     L.orc_target_scale.argtypes = [_i64, _i32p, _i32p, _f64p, _i32, _f64, _f64, _f64p]
     L.orc_adamw_step.restype = None
     L.orc_adamw_step.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _f64, _f64, _f64, _f64, _f64]
+    L.orc_splitmix64.restype = ctypes.c_uint64
+    L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.orc_random_phase.restype = None
+    L.orc_random_phase.argtypes = [_i64, _i32, ctypes.c_uint64, _f64p, _f64p]
     _LIB = L
     return L
 
@@ -225,6 +229,19 @@ def target_scale(pairs, v, kappa, z0):
     _lib().orc_target_scale(pi.shape[0], pi, pj, _c(v, np.float64).reshape(-1), v.shape[1],
                             float(kappa), float(z0), out)
     return out
+
+
+def splitmix64(seed, k):
+    """Output number k of SplitMix64 started at state `seed`."""
+    return int(_lib().orc_splitmix64(int(seed) & (2**64 - 1), int(k)))
+
+
+def random_phase(n, R, seed):
+    """complex128 [n, R] counter-based random phases exp(2 pi i u(seed, i R + v))."""
+    re = np.empty(n * R)
+    im = np.empty(n * R)
+    _lib().orc_random_phase(n, R, int(seed) & (2**64 - 1), re, im)
+    return (re + 1j * im).reshape(n, R)
 
 
 def mlp_forward(X, prm, bf16_ops=True, keep=False):

@@ -6,7 +6,8 @@
  * of Eq. (1), the kernel-polynomial (Chebyshev) moments over random-phase
  * vectors, Jackson damping and the DOS of Eq. (4); plus, for the learned-hopping
  * variant, the Chebyshev radial descriptor of Eq. (2), a per-bond MLP forward and
- * analytic backward with BF16 operand rounding, and one AdamW step.
+ * analytic backward with BF16 operand rounding, and one AdamW step; and the
+ * counter-based random-phase generator the GPU can use instead of stored phases.
  *
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
  * load this file.  It shares no code, header or constant generator with the HIP
@@ -346,6 +347,43 @@ int orc_kpm_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
     }
     free(g);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Seeded random phases (counter-based): output k of SplitMix64.              */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Output number k (k = 0, 1, ...) of SplitMix64 started at state `seed`
+ * (Steele, Lea & Flood, OOPSLA 2014; Vigna's reference splitmix64.c): the state
+ * advances by the odd constant 0x9e3779b97f4a7c15 before each output, and each
+ * output is the state after k + 1 advances passed through the mixing function
+ * z ^= z >> 30; z *= 0xbf58476d1ce4e5b9; z ^= z >> 27; z *= 0x94d049bb133111eb;
+ * z ^= z >> 31 (arithmetic mod 2^64).
+ */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+/*
+ * Random-phase vectors r[i][v] = exp(i phi), phi = 2 pi u, u = (x >> 11) 2^-53
+ * with x = output number i R + v of the generator above (i = atom, v = vector).
+ * re/im are [n][R].
+ */
+void orc_random_phase(int64_t n, int32_t R, uint64_t seed, double *re, double *im)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t v = 0; v < R; ++v) {
+            uint64_t x = orc_splitmix64(seed, (uint64_t)i * (uint64_t)R + (uint64_t)v);
+            double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+            double phi = 2.0 * ORC_PI * u;
+            re[i * R + v] = cos(phi);
+            im[i * R + v] = sin(phi);
+        }
 }
 
 /* ------------------------------------------------------------------------- */
