@@ -242,6 +242,24 @@ tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b
                               void *work, int64_t work_bytes, double *mu, void *stream);
 
 /*
+ * kpm_moments_config with the random-phase start vectors (Sec. 2.4) generated
+ * on the device instead of read from an [n_rows][R] array:
+ *   r[i][v] = exp(i phi), phi = 2 pi (x >> 11) 2^-53, x = output number
+ *   i R + v of SplitMix64 started at state `seed` (Steele, Lea & Flood 2014),
+ * with i the caller's atom index (so the phases do not depend on the row order
+ * the builder chose).  Same workspace and errors as kpm_moments_config.
+ */
+tbk_status kpm_moments_seeded(const tbk_ham *h, const double *a, const double *b, uint64_t seed,
+                              int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                              void *work, int64_t work_bytes, double *mu, void *stream);
+
+/* The phases kpm_moments_seeded uses, written out: r device c128 (precision
+ * 0) or c64 (precision 1) [n][R], caller-allocated.  Asynchronous on `stream`.
+ * Errors: INVALID_ARG (n < 0, R outside [1, 64], bad precision, r NULL). */
+tbk_status tbk_random_phase(uint64_t seed, int64_t n, int32_t R, int32_t precision, void *r,
+                            void *stream);
+
+/*
  * Moments of every structure of a stacked Hamiltonian (tb_build_hamiltonian_
  * batched) in one recurrence launch per step: structure s is scaled by its own
  * a[s] > 0, b[s] (host double [n_seg]) and mu is device double

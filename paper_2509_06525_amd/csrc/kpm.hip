@@ -196,12 +196,26 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
     block_reduce_store<L, NA>(acc, partial, lb);
 }
 
+// Counter-based random phase exp(i phi) of output k of SplitMix64 started at
+// `seed` (Steele, Lea & Flood 2014): phi = 2 pi (x >> 11) 2^-53.
+__device__ __forceinline__ void seeded_phase(uint64_t seed, uint64_t k, double &c, double &s) {
+    uint64_t z = seed + (k + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    const double phi = 6.283185307179586 * ((double)(z >> 11) * 0x1p-53);
+    sincos(phi, &s, &c);
+}
+
 // r_int[i][v] = r[perm[i]][v] (v < R), 0 for padded vectors; block partials of
-// |r|^2 (in the doubling layout, each followed by VPT zeros).
+// |r|^2 (in the doubling layout, each followed by VPT zeros).  With `seeded`
+// the phases are generated for atom perm[i] (output perm[i] R + v) instead of
+// being read from r.
 template <class VT, int L, int VPT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, const int32_t *__restrict__ perm,
-                                                      int64_t n_rows, int32_t R, int32_t Rp,
-                                                      VT *__restrict__ r_int, double *__restrict__ partial) {
+                                                      int64_t n_rows, int32_t R, int32_t Rp, int32_t seeded,
+                                                      uint64_t seed, VT *__restrict__ r_int,
+                                                      double *__restrict__ partial) {
     constexpr int RPB = kThreads / L;
     const int lr = threadIdx.x / L;
     const int vs = threadIdx.x % L;
@@ -214,7 +228,17 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
         for (int q = 0; q < VPT; ++q) {
             const int v = vs * VPT + q;
             VT re = 0, im = 0;
-            if (v < R) { re = r[2 * (src * R + v)]; im = r[2 * (src * R + v) + 1]; }
+            if (v < R) {
+                if (seeded) {
+                    double c, sn;
+                    seeded_phase(seed, (uint64_t)src * (uint64_t)R + (uint64_t)v, c, sn);
+                    re = (VT)c;
+                    im = (VT)sn;
+                } else {
+                    re = r[2 * (src * R + v)];
+                    im = r[2 * (src * R + v) + 1];
+                }
+            }
             r_int[2 * (i * Rp + v)] = re;
             r_int[2 * (i * Rp + v) + 1] = im;
             acc[q] += (double)re * (double)re + (double)im * (double)im;
@@ -399,7 +423,8 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     const int K = pl.reduce_every;
 
     // row 0 goes through the same partial slots as the steps (slot 0 of the first batch)
-    k_prepare<VT, L, VPT, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp, r_int, part);
+    k_prepare<VT, L, VPT, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp,
+                                                                    pl.seeded ? 1 : 0, pl.seed, r_int, part);
     TBK_HIP(hipGetLastError());
 
     StepPtrs<VT> sp{};
@@ -603,9 +628,20 @@ tbk_status run_plan(const tbk_ham *h, const KpmPlan &pl, double a, double b, con
     return fail(TBK_ERR_UNSUPPORTED, "no kernel for R = %d", R);
 }
 
+// r[i][v] = the seeded phase of output i R + v (caller's atom order).
+template <class VT>
+__global__ void k_random_phase(uint64_t seed, int64_t n, int32_t R, VT *__restrict__ r) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * R) return;
+    double c, sn;
+    seeded_phase(seed, (uint64_t)idx, c, sn);
+    r[2 * idx] = (VT)c;
+    r[2 * idx + 1] = (VT)sn;
+}
+
 tbk_status check_moment_args(const tbk_ham *h, const KpmPlan &pl, const double *a, const double *b,
                              const void *r, void *work, int64_t work_bytes, double *mu) {
-    TBK_CHECK(a && b && r && work && mu, TBK_ERR_INVALID_ARG, "NULL argument");
+    TBK_CHECK(a && b && (r || pl.seeded) && work && mu, TBK_ERR_INVALID_ARG, "NULL argument");
     TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "stacked systems go through kpm_moments_batched");
     TBK_CHECK(std::isfinite(a[0]) && std::isfinite(b[0]), TBK_ERR_NOT_FINITE, "a or b is not finite");
     TBK_CHECK(a[0] > 0, TBK_ERR_INVALID_ARG, "a = %g must be positive", a[0]);
@@ -663,4 +699,34 @@ extern "C" tbk_status kpm_moments_config(const tbk_ham *h, const double *a, cons
     if (st != TBK_OK) return st;
     TBK_CHECK(pl.cfg.persistent == 0, TBK_ERR_INVALID_ARG, "the persistent launch is for kpm_moments_batched");
     return run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream));
+}
+
+extern "C" tbk_status kpm_moments_seeded(const tbk_ham *h, const double *a, const double *b, uint64_t seed,
+                                         int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                                         void *work, int64_t work_bytes, double *mu, void *stream) {
+    clear_error();
+    KpmPlan pl;
+    tbk_status st = make_plan(h, R, M, precision, cfg, pl);
+    if (st != TBK_OK) return st;
+    pl.seeded = true;
+    pl.seed = seed;
+    st = check_moment_args(h, pl, a, b, nullptr, work, work_bytes, mu);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(pl.cfg.persistent == 0, TBK_ERR_INVALID_ARG, "the persistent launch is for kpm_moments_batched");
+    return run_plan(h, pl, a[0], b[0], nullptr, R, M, precision, static_cast<char *>(work), mu, as_stream(stream));
+}
+
+extern "C" tbk_status tbk_random_phase(uint64_t seed, int64_t n, int32_t R, int32_t precision, void *r,
+                                       void *stream) {
+    clear_error();
+    TBK_CHECK(n >= 0 && R >= 1 && R <= 64, TBK_ERR_INVALID_ARG, "n = %lld, R = %d", (long long)n, R);
+    TBK_CHECK(precision == TBK_PREC_F64 || precision == TBK_PREC_C32, TBK_ERR_INVALID_ARG, "bad precision");
+    if (n == 0) return TBK_OK;
+    TBK_CHECK(r != nullptr, TBK_ERR_INVALID_ARG, "r is NULL");
+    hipStream_t s = as_stream(stream);
+    const unsigned g = (unsigned)ceil_div(n * R, 256);
+    if (precision == TBK_PREC_F64) k_random_phase<double><<<g, 256, 0, s>>>(seed, n, R, static_cast<double *>(r));
+    else k_random_phase<float><<<g, 256, 0, s>>>(seed, n, R, static_cast<float *>(r));
+    TBK_HIP(hipGetLastError());
+    return TBK_OK;
 }

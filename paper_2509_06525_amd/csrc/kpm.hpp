@@ -16,6 +16,8 @@ struct KpmPlan {
     int uniform_width = 0;      // > 0 when every slice stores this many entries per row
     size_t elem = 0, vec_bytes = 0;
     size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0, total = 0;
+    bool seeded = false;        // start vectors generated on the device from `seed`
+    uint64_t seed = 0;
 };
 
 int pad_vectors(int R);

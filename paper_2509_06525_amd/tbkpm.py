@@ -49,7 +49,7 @@ class HamStruct(ctypes.Structure):
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
                "tb_build_hamiltonian", "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
+               "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase", "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -180,6 +180,11 @@ def lib():
                                                ctypes.POINTER(i32), ctypes.POINTER(TbParams),
                                                ctypes.POINTER(MlpModel), ctypes.POINTER(HamStruct),
                                                ctypes.POINTER(f64), vp, i64, ctypes.POINTER(i64), vp]
+    L.kpm_moments_seeded.restype = ctypes.c_int
+    L.kpm_moments_seeded.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                     ctypes.c_uint64, i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+    L.tbk_random_phase.restype = ctypes.c_int
+    L.tbk_random_phase.argtypes = [ctypes.c_uint64, i64, i32, i32, vp, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     L.kpm_dos_batched.restype = ctypes.c_int
@@ -353,6 +358,30 @@ def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, 
     bv = (ctypes.c_double * 1)(float(b))
     _check(L.kpm_moments_config(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
                                 _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
+    return mu
+
+
+def random_phase(seed, n, R, precision="c32", device="cuda", stream=None):
+    """Counter-based random phases [n, R] (complex64 for c32, complex128 for f64) on the device."""
+    dt = torch.complex64 if precision == "c32" else torch.complex128
+    r = torch.empty((n, R), dtype=dt, device=device)
+    _check(lib().tbk_random_phase(int(seed) & (2**64 - 1), int(n), int(R), PRECISIONS[precision], _ptr(r),
+                                  _stream(stream)))
+    return r
+
+
+def kpm_moments_seeded(H, a, b, seed, R, M, precision="c32", work=None, mu=None, stream=None, config=None):
+    """kpm_moments with the random-phase start vectors generated on the device from `seed`."""
+    L = lib()
+    dev = H.tensors["ptr"].device
+    if work is None:
+        work = alloc_workspace(H, R, M, precision, dev, config)
+    if mu is None:
+        mu = torch.empty((R, M), dtype=torch.float64, device=dev)
+    av, bv = (ctypes.c_double * 1)(float(a)), (ctypes.c_double * 1)(float(b))
+    _check(L.kpm_moments_seeded(ctypes.byref(H.st), av, bv, int(seed) & (2**64 - 1), int(R), int(M),
+                                PRECISIONS[precision], _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu),
+                                _stream(stream)))
     return mu
 
 
