@@ -63,6 +63,15 @@ def _lib():
     L.orc_target_scale.argtypes = [_i64, _i32p, _i32p, _f64p, _i32, _f64, _f64, _f64p]
     L.orc_adamw_step.restype = None
     L.orc_adamw_step.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _f64, _f64, _f64, _f64, _f64]
+    L.orc_velocity_values.restype = None
+    L.orc_velocity_values.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _i32p, _i32, _f64p]
+    L.orc_evolve.restype = ctypes.c_int
+    L.orc_evolve.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64, _f64, _f64, _i32, _c128p]
+    L.orc_vac_moments.restype = ctypes.c_int
+    L.orc_vac_moments.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _f64, _f64, _c128p, _i32, _i32,
+                                  _i32, _f64, _i32, _f64p]
+    L.orc_vac_sigma.restype = ctypes.c_int
+    L.orc_vac_sigma.argtypes = [_f64p, _i32, _i32, _f64, _f64, _f64, _i32, _f64p, _i32, _f64p]
     L.orc_splitmix64.restype = ctypes.c_uint64
     L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     L.orc_random_phase.restype = None
@@ -229,6 +238,54 @@ def target_scale(pairs, v, kappa, z0):
     _lib().orc_target_scale(pi.shape[0], pi, pj, _c(v, np.float64).reshape(-1), v.shape[1],
                             float(kappa), float(z0), out)
     return out
+
+
+HBAR_EV_FS = 0.6582119569
+
+
+def velocity_values(csr, pos, box, periodic, axis=0):
+    """vx[q] = H_ij (x_j - x_i) / hbar per CSR entry (V = i vx), Angstrom / fs."""
+    vx = np.empty(csr.col.shape[0])
+    _lib().orc_velocity_values(csr.n, csr.row_ptr, csr.col, csr.val, _c(pos, np.float64).reshape(-1),
+                               _c(box, np.float64), _c(periodic, np.int32), int(axis), vx)
+    return vx
+
+
+def evolve(csr, a, b, dt, n_cheb, psi):
+    """exp(-i H dt / hbar) psi (dt in fs) by a Chebyshev-Bessel series of n_cheb terms."""
+    out = _c(psi, np.complex128).copy()
+    rc = _lib().orc_evolve(csr.n, csr.row_ptr, csr.col, csr.val, csr.diag, float(a), float(b), float(dt),
+                           int(n_cheb), out)
+    if rc != 0:
+        raise OracleError("orc_evolve: invalid argument")
+    return out
+
+
+def vac_moments(csr, vx, a, b, r, M, n_t, dt, n_cheb):
+    """nu [n_t][R][M] = Re <phi_L(t_j)| T_m(Ht) V |phi_R(t_j)> for start vectors r [N][R]."""
+    r = _c(r, np.complex128)
+    if r.ndim == 1:
+        r = r.reshape(-1, 1)
+    n, R = r.shape
+    nu = np.empty((n_t, R, M))
+    rc = _lib().orc_vac_moments(n, csr.row_ptr, csr.col, csr.val, csr.diag, _c(vx, np.float64), float(a),
+                                float(b), r.reshape(-1), R, M, n_t, float(dt), int(n_cheb), nu.reshape(-1))
+    if rc != 0:
+        raise OracleError("orc_vac_moments: invalid argument")
+    return nu
+
+
+def vac_sigma(nu, a, b, dt, E, kernel=0):
+    """Running time integral s [n_t][nE] of the KPM-reconstructed correlation (nu [n_t][M])."""
+    nu = _c(nu, np.float64)
+    n_t, M = nu.shape
+    E = _c(E, np.float64)
+    s = np.empty((n_t, E.shape[0]))
+    rc = _lib().orc_vac_sigma(nu.reshape(-1), M, n_t, float(dt), float(a), float(b), int(kernel), E,
+                              E.shape[0], s.reshape(-1))
+    if rc != 0:
+        raise OracleError("orc_vac_sigma: invalid argument")
+    return s
 
 
 def splitmix64(seed, k):

@@ -7,7 +7,9 @@
  * vectors, Jackson damping and the DOS of Eq. (4); plus, for the learned-hopping
  * variant, the Chebyshev radial descriptor of Eq. (2), a per-bond MLP forward and
  * analytic backward with BF16 operand rounding, and one AdamW step; and the
- * counter-based random-phase generator the GPU can use instead of stored phases.
+ * counter-based random-phase generator the GPU can use instead of stored phases;
+ * and the velocity-autocorrelation conductivity of Eq. (3) (velocity operator,
+ * Chebyshev time evolution, correlation moments, running time integral).
  *
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
  * load this file.  It shares no code, header or constant generator with the HIP
@@ -24,6 +26,7 @@
  * Every routine is serial and allocation-light; errors are reported by a
  * negative return value, never by aborting.
  */
+#define _DEFAULT_SOURCE 1   /* jn() (Bessel functions of the first kind) from libm */
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
@@ -578,4 +581,163 @@ void orc_target_scale(int64_t npairs, const int32_t *pi, const int32_t *pj,
 {
     for (int64_t p = 0; p < npairs; ++p)
         s[p] = 1.0 + kappa * (v[(int64_t)pi[p] * nk] + v[(int64_t)pj[p] * nk] - 2.0 * z0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Velocity autocorrelation, Eq. (3): velocity operator, time evolution, the  */
+/* correlation moments and the running conductivity integral.                 */
+/* ------------------------------------------------------------------------- */
+
+#define ORC_HBAR 0.6582119569 /* reduced Planck constant, eV fs (CODATA 2018) */
+
+/*
+ * Velocity operator along `axis`, V = (i / hbar) [H, X]: in the site basis
+ * V_ij = (i / hbar) H_ij (x_j - x_i), the displacement taken with the
+ * minimum-image convention (the bond the hopping belongs to), and V_ii = 0.
+ * Stored as the real coefficient vx[q] = H_ij (x_j - x_i) / hbar of each CSR
+ * entry q = (i, j), so that (V psi)_i = i sum_q vx[q] psi_j (Angstrom / fs).
+ */
+void orc_velocity_values(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                         const double *pos, const double box[3], const int32_t periodic[3],
+                         int32_t axis, double *vx)
+{
+    double d[3];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+            orc_displacement(pos, i, col[q], box, periodic, d);
+            vx[q] = val[q] * d[axis] / ORC_HBAR;
+        }
+}
+
+/* y = V x, (V x)_i = i sum_q vx[q] x_col[q]. */
+static void orc_apply_velocity(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *vx,
+                               const double complex *x, double complex *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double complex s = 0.0;
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) s += vx[q] * x[col[q]];
+        y[i] = I * s;
+    }
+}
+
+/*
+ * psi <- exp(-i H dt / hbar) psi (dt in fs) by the Chebyshev expansion of the
+ * propagator on the scaled spectrum H = a Htilde + b:
+ *   exp(-i H dt/hbar) = exp(-i b dt/hbar) sum_k (2 - delta_k0) (-i)^k J_k(a dt/hbar) T_k(Htilde),
+ * truncated after n_cheb terms; J_k is the C library's Bessel function jn.
+ * Returns 0, -1 on a bad argument, -2 when out of memory.
+ */
+int orc_evolve(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+               const double *diag, double a, double b, double dt, int32_t n_cheb, double complex *psi)
+{
+    if (n <= 0 || !(a > 0.0) || n_cheb < 1) return -1;
+    double complex *t0 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t1 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t2 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *acc = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    if (!t0 || !t1 || !t2 || !acc) { free(t0); free(t1); free(t2); free(acc); return -2; }
+    const double z = a * dt / ORC_HBAR;
+    const double complex phase = cexp(-I * b * dt / ORC_HBAR);
+    double complex ik = 1.0;                                    /* (-i)^k */
+    for (int64_t i = 0; i < n; ++i) { t0[i] = psi[i]; acc[i] = jn(0, z) * t0[i]; }
+    if (n_cheb > 1) {
+        orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t0, t1);
+        ik = -I;
+        double complex c = 2.0 * ik * jn(1, z);
+        for (int64_t i = 0; i < n; ++i) acc[i] += c * t1[i];
+    }
+    for (int32_t k = 2; k < n_cheb; ++k) {
+        orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t1, t2);
+        for (int64_t i = 0; i < n; ++i) t2[i] = 2.0 * t2[i] - t0[i];
+        ik *= -I;
+        double complex c = 2.0 * ik * jn(k, z);
+        for (int64_t i = 0; i < n; ++i) acc[i] += c * t2[i];
+        double complex *tmp = t0; t0 = t1; t1 = t2; t2 = tmp;
+    }
+    for (int64_t i = 0; i < n; ++i) psi[i] = phase * acc[i];
+    free(t0); free(t1); free(t2); free(acc);
+    return 0;
+}
+
+/*
+ * Correlation moments of Eq. (3) with the random-phase trace (Sec. 2.4).  For
+ * each start vector phi_v (r, interleaved [n][R]):
+ *   phi_R(0) = phi, phi_L(0) = V phi, and for time step j = 0..n_t-1
+ *     nu[j][v][m] = Re <phi_L(t_j)| T_m(Htilde) V |phi_R(t_j)>,  m = 0..M-1,
+ *     then phi_R <- U phi_R and phi_L <- U phi_L, U = exp(-i H dt/hbar) (orc_evolve).
+ * With phi_R(t) = U(t) phi and phi_L(t) = U(t) V phi the bracket is
+ * <phi| V U(t)^+ T_m V U(t) |phi>, whose trace over phi is
+ * Tr[T_m(Htilde) V(t) V] with V(t) = U(t)^+ V U(t); the real part is the
+ * T_m-moment of Tr[delta(E - H) Re(V V(t))].
+ * Returns 0, -1 on a bad argument, -2 when out of memory.
+ */
+int orc_vac_moments(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                    const double *diag, const double *vx, double a, double b,
+                    const double complex *r, int32_t R, int32_t M, int32_t n_t, double dt,
+                    int32_t n_cheb, double *nu)
+{
+    if (n <= 0 || R < 1 || M < 1 || n_t < 1 || !(a > 0.0) || n_cheb < 1) return -1;
+    size_t bytes = sizeof(double complex) * (size_t)n;
+    double complex *pr = malloc(bytes), *pl = malloc(bytes), *w = malloc(bytes);
+    double complex *t0 = malloc(bytes), *t1 = malloc(bytes), *t2 = malloc(bytes);
+    if (!pr || !pl || !w || !t0 || !t1 || !t2) {
+        free(pr); free(pl); free(w); free(t0); free(t1); free(t2);
+        return -2;
+    }
+    int rc = 0;
+    for (int32_t v = 0; v < R && rc == 0; ++v) {
+        for (int64_t i = 0; i < n; ++i) pr[i] = r[i * R + v];
+        orc_apply_velocity(n, row_ptr, col, vx, pr, pl);
+        for (int32_t j = 0; j < n_t && rc == 0; ++j) {
+            double *out = nu + ((int64_t)j * R + v) * M;
+            orc_apply_velocity(n, row_ptr, col, vx, pr, w);
+            /* <phi_L| T_m w>, T_0 = w */
+            for (int64_t i = 0; i < n; ++i) t0[i] = w[i];
+            out[0] = creal(orc_dot(n, pl, t0));
+            if (M > 1) {
+                orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t0, t1);
+                out[1] = creal(orc_dot(n, pl, t1));
+            }
+            for (int32_t m = 2; m < M; ++m) {
+                orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t1, t2);
+                for (int64_t i = 0; i < n; ++i) t2[i] = 2.0 * t2[i] - t0[i];
+                out[m] = creal(orc_dot(n, pl, t2));
+                double complex *tmp = t0; t0 = t1; t1 = t2; t2 = tmp;
+            }
+            if (j + 1 < n_t) {
+                rc = orc_evolve(n, row_ptr, col, val, diag, a, b, dt, n_cheb, pr);
+                if (rc == 0) rc = orc_evolve(n, row_ptr, col, val, diag, a, b, dt, n_cheb, pl);
+            }
+        }
+    }
+    free(pr); free(pl); free(w); free(t0); free(t1); free(t2);
+    return rc;
+}
+
+/*
+ * Running conductivity of Eq. (3) without its prefactor 2 e^2 / Omega:
+ *   C_j(E) = the KPM reconstruction (orc_kpm_dos, same kernel) of the moments
+ *            nu[j][m] (already averaged over vectors) at correlation time t_j = j dt,
+ *   s[j][e] = integral_0^{t_j} C(E, tau) dtau by the trapezoidal rule over the
+ *            samples (s[0] = 0).
+ * Units: (Angstrom / fs)^2 per eV times fs.  Returns 0 or -1.
+ */
+int orc_vac_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a, double b,
+                  int32_t kernel, const double *E, int32_t nE, double *s)
+{
+    if (n_t < 1 || nE < 0) return -1;
+    double *cprev = malloc(sizeof(double) * (size_t)(nE > 0 ? nE : 1));
+    double *cj = malloc(sizeof(double) * (size_t)(nE > 0 ? nE : 1));
+    if (!cprev || !cj) { free(cprev); free(cj); return -2; }
+    int rc = orc_kpm_dos(nu, M, a, b, kernel, E, nE, cprev);
+    for (int32_t e = 0; e < nE; ++e) s[e] = 0.0;
+    for (int32_t j = 1; j < n_t && rc == 0; ++j) {
+        rc = orc_kpm_dos(nu + (int64_t)j * M, M, a, b, kernel, E, nE, cj);
+        for (int32_t e = 0; e < nE; ++e) {
+            s[(int64_t)j * nE + e] = s[(int64_t)(j - 1) * nE + e] + 0.5 * dt * (cprev[e] + cj[e]);
+            cprev[e] = cj[e];
+        }
+    }
+    free(cprev); free(cj);
+    return rc;
 }
