@@ -457,6 +457,69 @@ tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_struct, const 
                            const double *b, int32_t kernel, const double *E, int32_t nE,
                            double *rho, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Velocity autocorrelation conductivity, Eq. (3)                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Velocity operator along `axis` (0, 1, 2 = x, y, z), V = (i / hbar)[H, X],
+ * in the layout of a built Hamiltonian h (single structure):
+ *   vx[q] = H_q (x_col - x_row) / hbar  for every stored entry q (0 on padding),
+ * the displacement between the two atoms taken with the minimum-image
+ * convention (the bond of the hopping), hbar = 0.6582119569 eV fs, so that
+ * (V psi)_i = i sum_q vx[q] psi_col(q) in Angstrom / fs.
+ *   pos  device double [n_rows][3] (the positions h was built from, caller's
+ *        atom order); box, periodic: host, as for tb_build_hamiltonian.
+ *   vx   device, same type as h->val, >= h->n_entries elements.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (NULL, axis, box), UNSUPPORTED
+ * (stacked structures).
+ */
+tbk_status tb_build_velocity(const double *pos, const double box[3], const int32_t periodic[3],
+                             int32_t axis, const tbk_ham *h, void *vx, void *stream);
+
+/* Terms of the Chebyshev-Bessel series of exp(-i H dt / hbar) used when
+ * lsqt_vac_moments gets n_cheb <= 0: the first k past z = a dt / hbar with
+ * |J_k(z)| < 1e-15, plus one.  -1 on a bad argument. */
+int32_t lsqt_chebyshev_terms(double a, double dt);
+
+/* Bytes of device workspace lsqt_vac_moments needs (recurrence workspace of
+ * kpm_workspace_size_config plus six [n_rows][R_pad] vectors). */
+tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
+                               const tbk_kpm_config *cfg, int64_t *bytes);
+
+/*
+ * Correlation moments of Eq. (3) with the random-phase trace of Sec. 2.4:
+ *   phi_R(0) = r_v, phi_L(0) = V r_v; for j = 0 .. n_t - 1 (t_j = j dt fs)
+ *     nu[j][v][m] = Re <phi_L(t_j)| T_m(Ht) V |phi_R(t_j)>,  m = 0 .. M-1,
+ *     then phi_R, phi_L <- exp(-i H dt / hbar) (.) by the Chebyshev-Bessel
+ *     series exp(-i b dt/hbar) sum_k (2 - delta_k0) (-i)^k J_k(a dt/hbar) T_k(Ht)
+ *     with n_cheb terms (<= 0: lsqt_chebyshev_terms).
+ * Summed over a complete basis, nu[j][.][m] is the T_m moment of
+ * Tr[delta(E - H) Re(V V(t_j))]; lsqt_sigma turns nu into sigma(E, t).
+ *   r    device c128|c64 [n_rows][R] start vectors, caller's atom order;
+ *   vx   from tb_build_velocity; cfg: launch shape of the recurrence (NULL =
+ *        default; doubling must be 0);
+ *   nu   device double [n_t][R][M].
+ * Synchronises `stream`.  Errors: as kpm_moments_config; INVALID_ARG (dt <= 0,
+ * n_t outside [1, 10^6], doubling); SPECTRUM when a moment is not finite.
+ */
+tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double a, double b, const void *r,
+                            int32_t R, int32_t M, int32_t n_t, double dt, int32_t n_cheb,
+                            int32_t precision, const tbk_kpm_config *cfg, void *work,
+                            int64_t work_bytes, double *nu, void *stream);
+
+/*
+ * Running conductivity of Eq. (3) without the prefactor 2 e^2 / Omega:
+ *   C_j(E) = [g_0 nu_0 + 2 sum g_m nu_m T_m(x)] / (a pi sqrt(1 - x^2)) of
+ *            nu[j] (the kpm_dos reconstruction, same kernels),
+ *   sigma[j][e] = trapezoidal integral of C over t_0 .. t_j (sigma[0] = 0).
+ *   nu device double [n_t][M] (averaged over vectors); E device [nE];
+ *   sigma device double [n_t][nE], in (Angstrom/fs)^2 fs / eV.
+ * Errors: as kpm_dos; INVALID_ARG (n_t outside [1, 65535], dt <= 0).
+ */
+tbk_status lsqt_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a, double b,
+                      int32_t kernel, const double *E, int32_t nE, double *sigma, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,21 @@ __global__ __launch_bounds__(kDosThreads) void k_dos(const double *__restrict__ 
     if (e < nE) rho[(int64_t)s * nE + e] = inside ? acc / (as * M_PI * sqrt(1.0 - x * x)) : 0.0;
 }
 
+// In place over sigma [n_t][nE] holding the correlation C_j(E): the running
+// trapezoidal integral s_0 = 0, s_j = s_{j-1} + dt/2 (C_{j-1} + C_j).
+__global__ void k_cumtrapz(double *__restrict__ sigma, int32_t n_t, int32_t nE, double dt) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nE) return;
+    double prev = sigma[e], run = 0.0;
+    sigma[e] = 0.0;
+    for (int32_t j = 1; j < n_t; ++j) {
+        const double cj = sigma[(int64_t)j * nE + e];
+        run += 0.5 * dt * (prev + cj);
+        sigma[(int64_t)j * nE + e] = run;
+        prev = cj;
+    }
+}
+
 tbk_status check_dos(int32_t M, int32_t nE, int32_t kernel) {
     TBK_CHECK(M >= 1, TBK_ERR_INVALID_ARG, "M = %d < 1", M);
     TBK_CHECK(nE >= 0, TBK_ERR_INVALID_ARG, "nE = %d < 0", nE);
@@ -113,5 +128,24 @@ extern "C" tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_str
         mu, M, 0.0, 0.0, ab.as<double>(), kernel, E, nE, nE, rho);
     TBK_HIP(hipGetLastError());
     TBK_HIP(hipStreamSynchronize(s));    // the caller's a and b must outlive the transfer
+    return TBK_OK;
+}
+
+extern "C" tbk_status lsqt_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a, double b,
+                                 int32_t kernel, const double *E, int32_t nE, double *sigma, void *stream) {
+    clear_error();
+    tbk_status st = check_dos(M, nE, kernel);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(n_t >= 1 && n_t <= 65535, TBK_ERR_INVALID_ARG, "n_t = %d outside [1, 65535]", n_t);
+    TBK_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(dt), TBK_ERR_NOT_FINITE,
+              "a, b or dt is not finite");
+    TBK_CHECK(a > 0 && dt > 0, TBK_ERR_INVALID_ARG, "a and dt must be positive");
+    if (nE == 0) return TBK_OK;
+    TBK_CHECK(nu && E && sigma, TBK_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    k_dos<<<dim3((unsigned)ceil_div(nE, kDosThreads), (unsigned)n_t), kDosThreads, 0, s>>>(
+        nu, M, a, b, nullptr, kernel, E, 0, nE, sigma);
+    k_cumtrapz<<<(unsigned)ceil_div(nE, 256), 256, 0, s>>>(sigma, n_t, nE, dt);
+    TBK_HIP(hipGetLastError());
     return TBK_OK;
 }

@@ -254,6 +254,29 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
     }
 }
 
+// Block partials of Re <left|start> per vector slot (slot 0 of the first batch
+// in the pair form of the recurrence); both vectors in row order, [rows][Rp].
+template <class VT, int L, int VPT>
+__global__ __launch_bounds__(kThreads) void k_pair_overlap(const VT *__restrict__ left,
+                                                           const VT *__restrict__ start, int64_t n_rows,
+                                                           int32_t Rp, double *__restrict__ partial) {
+    constexpr int RPB = kThreads / L;
+    const int lr = threadIdx.x / L;
+    const int vs = threadIdx.x % L;
+    double acc[VPT];
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RPB + lr; i < n_rows; i += (int64_t)gridDim.x * RPB) {
+        const int64_t off = 2 * (i * Rp + vs * VPT);
+        const Pack<VT, VPT> l = load_pack<false, VT, VPT>(left + off);
+        const Pack<VT, VPT> t = load_pack<false, VT, VPT>(start + off);
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            acc[q] += (double)l.re[q] * (double)t.re[q] + (double)l.im[q] * (double)t.im[q];
+    }
+    block_reduce_store<L, VPT>(acc, partial, blockIdx.x);
+}
+
 // Doubling identities for a Hermitian Ht (T_m T_n = (T_{m+n} + T_{|m-n|})/2):
 // with a[v][k] = <T_k|T_k> and b[v][k] = Re <T_k|T_{k-1}> (k = 1..K; a[v][0] = mu_0),
 //   mu_0 = a[v][0], mu_1 = b[v][1], mu_{2k} = 2 a[v][k] - mu_0, mu_{2k-1} = 2 b[v][k] - mu_1.
@@ -406,9 +429,12 @@ void launch_reduce(const KpmPlan &pl, int n0, int count, int R, double *part, do
     k_reduce_l1<<<grid, kThreads, 0, s>>>(part, pl.G, pl.Rp, R, n0, pl.n_chunks, l1);
 }
 
+// start/left (row order, [rows][Rp], both non-NULL) select the pair form:
+// T_0 = start and mu_n = Re <left|T_n>, without the spectrum guard.
 template <class VT, int L, int VPT, bool DBL>
 tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
-                         int32_t M, char *work, double *mu, hipStream_t s) {
+                         int32_t M, char *work, double *mu, hipStream_t s, const VT *start, const VT *left) {
+    const bool pair = left != nullptr;
     VT *r_int = reinterpret_cast<VT *>(work + pl.off_r);
     VT *TA = reinterpret_cast<VT *>(work + pl.off_a);
     VT *TB = reinterpret_cast<VT *>(work + pl.off_b);
@@ -423,16 +449,20 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     const int K = pl.reduce_every;
 
     // row 0 goes through the same partial slots as the steps (slot 0 of the first batch)
-    k_prepare<VT, L, VPT, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp,
-                                                                    pl.seeded ? 1 : 0, pl.seed, r_int, part);
+    if (pair)
+        k_pair_overlap<VT, L, VPT><<<(unsigned)pl.G, kThreads, 0, s>>>(left, start, h->n_rows, pl.Rp, part);
+    else
+        k_prepare<VT, L, VPT, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp,
+                                                                        pl.seeded ? 1 : 0, pl.seed, r_int, part);
     TBK_HIP(hipGetLastError());
+    const VT *t0 = pair ? start : r_int;
 
     StepPtrs<VT> sp{};
     sp.ptr = h->ptr;
     sp.col = h->col;
     sp.val = static_cast<const VT *>(h->val);
     sp.onsite = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
-    sp.r = r_int;
+    sp.r = pair ? left : r_int;
     StepScalars<VT> sa{};
     sa.n_rows = h->n_rows;
     sa.n_tiles = pl.n_tiles;
@@ -457,9 +487,9 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
         }
         sp.partial = part + (int64_t)(n - batch0) * pstride;
         if (n == 1) {            // T_1 = Ht T_0 into TB
-            sp.tcur = r_int; sp.tprev = nullptr; sp.tnext = TB; sa.c1 = (VT)(1.0 / a);
+            sp.tcur = t0; sp.tprev = nullptr; sp.tnext = TB; sa.c1 = (VT)(1.0 / a);
         } else if (n == 2) {     // T_2 = 2 Ht T_1 - T_0 into TA
-            sp.tcur = TB; sp.tprev = r_int; sp.tnext = TA; sa.c1 = (VT)(2.0 / a);
+            sp.tcur = TB; sp.tprev = t0; sp.tnext = TA; sa.c1 = (VT)(2.0 / a);
         } else {                 // T_n overwrites T_{n-2} in place
             VT *cur = (n & 1) ? TA : TB;
             VT *old = (n & 1) ? TB : TA;
@@ -478,6 +508,7 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
         k_reduce_l2<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(l1, R, M, pl.n_chunks, mu);
     }
     TBK_HIP(hipGetLastError());
+    if (pair) return TBK_OK;     // no guard: |mu_n| <= mu_0 holds only for left = start
     TBK_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     k_guard<<<(unsigned)ceil_div(nm, 256), 256, 0, s>>>(mu, R, M, flag);
     TBK_HIP(hipGetLastError());
@@ -491,9 +522,9 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
 
 template <class VT, int L, int VPT>
 tbk_status run_moments(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
-                       int32_t M, char *work, double *mu, hipStream_t s) {
-    if (pl.cfg.doubling) return run_moments_t<VT, L, VPT, true>(h, pl, a, b, r, R, M, work, mu, s);
-    return run_moments_t<VT, L, VPT, false>(h, pl, a, b, r, R, M, work, mu, s);
+                       int32_t M, char *work, double *mu, hipStream_t s, const VT *start, const VT *left) {
+    if (pl.cfg.doubling) return run_moments_t<VT, L, VPT, true>(h, pl, a, b, r, R, M, work, mu, s, start, left);
+    return run_moments_t<VT, L, VPT, false>(h, pl, a, b, r, R, M, work, mu, s, start, left);
 }
 
 }  // namespace
@@ -590,38 +621,41 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
 }
 
 tbk_status run_plan(const tbk_ham *h, const KpmPlan &pl, double a, double b, const void *r, int32_t R,
-                    int32_t M, int32_t precision, char *w, double *mu, hipStream_t s) {
+                    int32_t M, int32_t precision, char *w, double *mu, hipStream_t s, const void *start,
+                    const void *left) {
+    const double *sd = static_cast<const double *>(start), *ld_ = static_cast<const double *>(left);
+    const float *sf = static_cast<const float *>(start), *lf = static_cast<const float *>(left);
     if (precision == TBK_PREC_F64) {
         const double *rr = static_cast<const double *>(r);
         switch (pl.L) {
-        case 1: return run_moments<double, 1, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-        case 2: return run_moments<double, 2, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-        case 4: return run_moments<double, 4, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-        case 8: return run_moments<double, 8, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-        case 16: return run_moments<double, 16, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-        case 32: return run_moments<double, 32, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-        case 64: return run_moments<double, 64, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+        case 1: return run_moments<double, 1, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
+        case 2: return run_moments<double, 2, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
+        case 4: return run_moments<double, 4, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
+        case 8: return run_moments<double, 8, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
+        case 16: return run_moments<double, 16, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
+        case 32: return run_moments<double, 32, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
+        case 64: return run_moments<double, 64, 1>(h, pl, a, b, rr, R, M, w, mu, s, sd, ld_);
         }
     } else {
         const float *rr = static_cast<const float *>(r);
         if (pl.VPT == 1) {
             switch (pl.L) {
-            case 1: return run_moments<float, 1, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 2: return run_moments<float, 2, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 4: return run_moments<float, 4, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 8: return run_moments<float, 8, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 16: return run_moments<float, 16, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 32: return run_moments<float, 32, 1>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 64: return run_moments<float, 64, 1>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 1: return run_moments<float, 1, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 2: return run_moments<float, 2, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 4: return run_moments<float, 4, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 8: return run_moments<float, 8, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 16: return run_moments<float, 16, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 32: return run_moments<float, 32, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 64: return run_moments<float, 64, 1>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
             }
         } else {
             switch (pl.L) {
-            case 1: return run_moments<float, 1, 2>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 2: return run_moments<float, 2, 2>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 4: return run_moments<float, 4, 2>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 8: return run_moments<float, 8, 2>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 16: return run_moments<float, 16, 2>(h, pl, a, b, rr, R, M, w, mu, s);
-            case 32: return run_moments<float, 32, 2>(h, pl, a, b, rr, R, M, w, mu, s);
+            case 1: return run_moments<float, 1, 2>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 2: return run_moments<float, 2, 2>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 4: return run_moments<float, 4, 2>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 8: return run_moments<float, 8, 2>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 16: return run_moments<float, 16, 2>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
+            case 32: return run_moments<float, 32, 2>(h, pl, a, b, rr, R, M, w, mu, s, sf, lf);
             }
         }
     }
@@ -698,7 +732,8 @@ extern "C" tbk_status kpm_moments_config(const tbk_ham *h, const double *a, cons
     st = check_moment_args(h, pl, a, b, r, work, work_bytes, mu);
     if (st != TBK_OK) return st;
     TBK_CHECK(pl.cfg.persistent == 0, TBK_ERR_INVALID_ARG, "the persistent launch is for kpm_moments_batched");
-    return run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream));
+    return run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream),
+                    nullptr, nullptr);
 }
 
 extern "C" tbk_status kpm_moments_seeded(const tbk_ham *h, const double *a, const double *b, uint64_t seed,
@@ -713,7 +748,8 @@ extern "C" tbk_status kpm_moments_seeded(const tbk_ham *h, const double *a, cons
     st = check_moment_args(h, pl, a, b, nullptr, work, work_bytes, mu);
     if (st != TBK_OK) return st;
     TBK_CHECK(pl.cfg.persistent == 0, TBK_ERR_INVALID_ARG, "the persistent launch is for kpm_moments_batched");
-    return run_plan(h, pl, a[0], b[0], nullptr, R, M, precision, static_cast<char *>(work), mu, as_stream(stream));
+    return run_plan(h, pl, a[0], b[0], nullptr, R, M, precision, static_cast<char *>(work), mu, as_stream(stream),
+                    nullptr, nullptr);
 }
 
 extern "C" tbk_status tbk_random_phase(uint64_t seed, int64_t n, int32_t R, int32_t precision, void *r,

@@ -26,7 +26,11 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
                      KpmPlan &pl);
 tbk_status check_moment_args(const tbk_ham *h, const KpmPlan &pl, const double *a, const double *b,
                              const void *r, void *work, int64_t work_bytes, double *mu);
+// r: start vectors in the caller's order (or NULL with pl.seeded).  With start
+// and left (row order, [rows][Rp], device) the pair form runs instead:
+// T_0 = start, mu_n = Re <left|T_n(Ht) start>, no spectrum guard.
 tbk_status run_plan(const tbk_ham *h, const KpmPlan &pl, double a, double b, const void *r, int32_t R,
-                    int32_t M, int32_t precision, char *w, double *mu, hipStream_t s);
+                    int32_t M, int32_t precision, char *w, double *mu, hipStream_t s,
+                    const void *start = nullptr, const void *left = nullptr);
 
 }  // namespace tbk

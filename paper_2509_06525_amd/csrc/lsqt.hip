@@ -1,0 +1,337 @@
+// Velocity autocorrelation (VAC) conductivity of Eq. (3) on the GPU.
+//
+//   sigma(E, t) = (2 e^2 / Omega) int_0^t Tr[delta(E - H) Re(V V(tau))] dtau,
+//
+// with V = (i / hbar)[H, X] and V(tau) = U(tau)^+ V U(tau), U = exp(-i H tau / hbar).
+// The trace is estimated with random-phase vectors phi (Sec. 2.4):
+//   phi_R(0) = phi, phi_L(0) = V phi; at each time step t_j = j dt
+//     nu_m(t_j) = Re <phi_L(t_j)| T_m(Ht) V |phi_R(t_j)>     (pair form of the recurrence)
+//   then phi_R, phi_L <- U(dt) (.), U(dt) by its Chebyshev-Bessel series
+//     exp(-i H dt/hbar) = exp(-i b dt/hbar) sum_k (2 - delta_k0) (-i)^k J_k(a dt/hbar) T_k(Ht).
+// delta(E - H) is the KPM expansion of the DOS, so the correlation at t_j is the
+// DOS reconstruction of nu(t_j); the running time integral is the trapezoidal
+// rule over the samples (lsqt_sigma in dos.hip).
+//
+// All vectors live in the builder's row order, [rows][R_pad] interleaved
+// complex, like the recurrence's.  The kernels here are plain SELL sweeps with
+// one thread per (row, vector); the M-1 recurrence steps per time step, which
+// dominate, run in the tuned recurrence kernel.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "kpm.hpp"
+
+namespace tbk {
+namespace {
+
+constexpr double kHbar = 0.6582119569;   // eV fs
+constexpr int kLsqtThreads = 256;
+
+struct SellView {
+    const int64_t *ptr;
+    const int32_t *col;
+    int32_t log2_slice;
+};
+
+__device__ __forceinline__ void row_range(const SellView &h, int64_t i, int64_t &base, int32_t &w,
+                                          int64_t &stride) {
+    const int64_t sl = i >> h.log2_slice;
+    stride = (int64_t)1 << h.log2_slice;
+    const int64_t p0 = h.ptr[sl], p1 = h.ptr[sl + 1];
+    base = p0 + (i & (stride - 1));
+    w = (int32_t)((p1 - p0) >> h.log2_slice);
+}
+
+// vx[q] = val[q] (x_j - x_i) / hbar for the stored entry q = (row i, column j),
+// minimum-image displacement along `axis` between the rows' atoms; 0 on padding.
+template <class V>
+__global__ void k_velocity(SellView h, const V *__restrict__ val, const int32_t *__restrict__ perm,
+                           const double *__restrict__ pos, int64_t n, double L, int32_t periodic, int32_t axis,
+                           V *__restrict__ vx) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t base, stride;
+    int32_t w;
+    row_range(h, r, base, w, stride);
+    const double xi = pos[3 * (int64_t)perm[r] + axis];
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = base + k * stride;
+        const int32_t c = h.col[q];
+        if (c == (int32_t)r) { vx[q] = (V)0; continue; }    // padding (no atom bonds to itself)
+        double d = __dsub_rn(pos[3 * (int64_t)perm[c] + axis], xi);
+        if (periodic) d = __dsub_rn(d, __dmul_rn(L, rint(__ddiv_rn(d, L))));
+        vx[q] = (V)__ddiv_rn(__dmul_rn((double)val[q], d), kHbar);
+    }
+}
+
+// out[i][v] = r[perm[i]][v] for v < R, 0 for the padded vectors.
+template <class VT>
+__global__ void k_permute_in(const VT *__restrict__ r, const int32_t *__restrict__ perm, int64_t n, int32_t R,
+                             int32_t Rp, VT *__restrict__ out) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * Rp) return;
+    const int64_t i = idx / Rp;
+    const int v = (int)(idx % Rp);
+    VT re = 0, im = 0;
+    if (v < R) {
+        const int64_t src = 2 * ((int64_t)perm[i] * R + v);
+        re = r[src];
+        im = r[src + 1];
+    }
+    out[2 * idx] = re;
+    out[2 * idx + 1] = im;
+}
+
+// y = V x, (V x)_i = i sum_q vx[q] x_col[q].
+template <class VT>
+__global__ void k_apply_velocity(SellView h, const VT *__restrict__ vx, const VT *__restrict__ x, int64_t n,
+                                 int32_t Rp, VT *__restrict__ y) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * Rp) return;
+    const int64_t i = idx / Rp;
+    const int v = (int)(idx % Rp);
+    int64_t base, stride;
+    int32_t w;
+    row_range(h, i, base, w, stride);
+    VT sr = 0, si = 0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = base + k * stride;
+        const VT c = vx[q];
+        const int64_t xo = 2 * ((int64_t)h.col[q] * Rp + v);
+        sr += c * x[xo];
+        si += c * x[xo + 1];
+    }
+    y[2 * idx] = -si;
+    y[2 * idx + 1] = sr;
+}
+
+// One term of the propagator series: tnext = c1 (H - b) tcur - tprev (tprev
+// absent on the first term), then acc += (cr + i ci) tnext.  tnext may alias
+// tprev (each element reads its own old value before writing).
+template <class VT, bool FIRST>
+__global__ void k_evolve_term(SellView h, const VT *__restrict__ val, const VT *__restrict__ onsite, VT shift,
+                              VT c1, const VT *__restrict__ tcur, const VT *tprev, VT *tnext, VT *__restrict__ acc,
+                              double cr, double ci, int64_t n, int32_t Rp) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * Rp) return;
+    const int64_t i = idx / Rp;
+    const int v = (int)(idx % Rp);
+    int64_t base, stride;
+    int32_t w;
+    row_range(h, i, base, w, stride);
+    const VT d = (onsite ? onsite[i] : (VT)0) - shift;
+    VT yr = d * tcur[2 * idx], yi = d * tcur[2 * idx + 1];
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = base + k * stride;
+        const VT hv = val[q];
+        const int64_t xo = 2 * ((int64_t)h.col[q] * Rp + v);
+        yr += hv * tcur[xo];
+        yi += hv * tcur[xo + 1];
+    }
+    VT tr = c1 * yr, ti = c1 * yi;
+    if (!FIRST) {
+        tr -= tprev[2 * idx];
+        ti -= tprev[2 * idx + 1];
+    }
+    tnext[2 * idx] = tr;
+    tnext[2 * idx + 1] = ti;
+    acc[2 * idx] += (VT)(cr * (double)tr - ci * (double)ti);
+    acc[2 * idx + 1] += (VT)(cr * (double)ti + ci * (double)tr);
+}
+
+// y = (cr + i ci) x
+template <class VT>
+__global__ void k_cscale(const VT *__restrict__ x, double cr, double ci, int64_t m, VT *__restrict__ y) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= m) return;
+    const double xr = x[2 * idx], xi = x[2 * idx + 1];
+    y[2 * idx] = (VT)(cr * xr - ci * xi);
+    y[2 * idx + 1] = (VT)(cr * xi + ci * xr);
+}
+
+__global__ void k_all_finite(const double *__restrict__ x, int64_t m, int32_t *__restrict__ flag) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < m && !isfinite(x[idx])) *flag = 1;
+}
+
+int32_t log2_of(int32_t v) {
+    int32_t l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Terms of the Chebyshev-Bessel series of exp(-i H dt/hbar): the first k past
+// z = a dt/hbar with |J_k(z)| below 1e-15 (J_k decays faster than geometrically there).
+int32_t default_terms(double z) {
+    int32_t k = 1;
+    while (k < 100000 && !(k > z && std::fabs(::jn(k, z)) < 1e-15)) ++k;
+    return k + 1;
+}
+
+struct LsqtLayout {
+    KpmPlan pl;
+    size_t vec = 0, off_vec = 0, total = 0;   // six vectors after the recurrence workspace
+};
+
+tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                       LsqtLayout &ly) {
+    tbk_status st = make_plan(h, R, M, precision, cfg, ly.pl);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(ly.pl.cfg.doubling == 0, TBK_ERR_INVALID_ARG,
+              "the doubling identities need the same left and right vectors; VAC moments use the direct form");
+    TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "VAC conductivity takes one structure");
+    TBK_CHECK(h->fmt != TBK_CSR_F64 || h->slice == 1, TBK_ERR_INVALID_ARG, "CSR needs slice 1");
+    const size_t elem = precision == TBK_PREC_C32 ? sizeof(float) : sizeof(double);
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    ly.vec = a256((size_t)h->n_rows * ly.pl.Rp * 2 * elem);
+    ly.off_vec = a256(ly.pl.total);
+    ly.total = ly.off_vec + 6 * ly.vec;
+    return TBK_OK;
+}
+
+template <class VT>
+tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT *r, int32_t R, int32_t M,
+                   int32_t n_t, double dt, int32_t n_cheb, int32_t precision, const LsqtLayout &ly, char *work,
+                   double *nu, hipStream_t s) {
+    const KpmPlan &pl = ly.pl;
+    const int32_t Rp = pl.Rp;
+    const int64_t n = h->n_rows;
+    VT *v[6];
+    for (int k = 0; k < 6; ++k) v[k] = reinterpret_cast<VT *>(work + ly.off_vec + k * ly.vec);
+    VT *phiR = v[0], *phiL = v[1], *wv = v[2], *e1 = v[3], *e2 = v[4], *acc = v[5];
+    const SellView sv{h->ptr, h->col, log2_of(h->fmt == TBK_CSR_F64 ? 1 : h->slice)};
+    const VT *val = static_cast<const VT *>(h->val);
+    const VT *ons = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
+    const int64_t nv = n * Rp;
+    const unsigned g = (unsigned)ceil_div(nv, kLsqtThreads);
+
+    // series coefficients of U(dt)
+    const double z = a * dt / kHbar;
+    std::vector<double> cre(n_cheb), cim(n_cheb);
+    for (int32_t k = 0; k < n_cheb; ++k) {
+        const double jk = (k == 0 ? 1.0 : 2.0) * ::jn(k, z);
+        // (-i)^k: 1, -i, -1, i
+        const int q = k & 3;
+        cre[k] = q == 0 ? jk : (q == 2 ? -jk : 0.0);
+        cim[k] = q == 1 ? -jk : (q == 3 ? jk : 0.0);
+    }
+    const double pr = std::cos(b * dt / kHbar), pi = -std::sin(b * dt / kHbar);   // exp(-i b dt / hbar)
+
+    auto evolve = [&](VT *psi) -> tbk_status {
+        k_cscale<VT><<<g, kLsqtThreads, 0, s>>>(psi, cre[0], cim[0], nv, acc);
+        if (n_cheb > 1)
+            k_evolve_term<VT, true><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, (VT)(1.0 / a), psi, nullptr,
+                                                                e1, acc, cre[1], cim[1], n, Rp);
+        for (int32_t k = 2; k < n_cheb; ++k) {
+            const VT *tcur = (k & 1) ? e2 : e1;
+            const VT *tprev = k == 2 ? psi : ((k & 1) ? e1 : e2);
+            VT *tnext = (k & 1) ? e1 : e2;
+            k_evolve_term<VT, false><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, (VT)(2.0 / a), tcur, tprev,
+                                                                 tnext, acc, cre[k], cim[k], n, Rp);
+        }
+        k_cscale<VT><<<g, kLsqtThreads, 0, s>>>(acc, pr, pi, nv, psi);
+        TBK_HIP(hipGetLastError());
+        return TBK_OK;
+    };
+
+    k_permute_in<VT><<<g, kLsqtThreads, 0, s>>>(r, h->perm, n, R, Rp, phiR);
+    k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, phiR, n, Rp, phiL);
+    TBK_HIP(hipGetLastError());
+    for (int32_t j = 0; j < n_t; ++j) {
+        k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, phiR, n, Rp, wv);
+        TBK_HIP(hipGetLastError());
+        tbk_status st = run_plan(h, pl, a, b, nullptr, R, M, precision, work, nu + (int64_t)j * R * M, s, wv, phiL);
+        if (st != TBK_OK) return st;
+        if (j + 1 < n_t) {
+            st = evolve(phiR);
+            if (st != TBK_OK) return st;
+            st = evolve(phiL);
+            if (st != TBK_OK) return st;
+        }
+    }
+    DevBuf flag;
+    TBK_HIP(flag.alloc(sizeof(int32_t), s));
+    TBK_HIP(hipMemsetAsync(flag.as<int32_t>(), 0, sizeof(int32_t), s));
+    const int64_t m = (int64_t)n_t * R * M;
+    k_all_finite<<<(unsigned)ceil_div(m, 256), 256, 0, s>>>(nu, m, flag.as<int32_t>());
+    TBK_HIP(hipGetLastError());
+    int32_t hf = 0;
+    TBK_HIP(hipMemcpyAsync(&hf, flag.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TBK_HIP(hipStreamSynchronize(s));
+    TBK_CHECK(hf == 0, TBK_ERR_SPECTRUM, "a correlation moment is not finite: (a, b) does not bound the spectrum");
+    return TBK_OK;
+}
+
+}  // namespace
+}  // namespace tbk
+
+using namespace tbk;
+
+extern "C" int32_t lsqt_chebyshev_terms(double a, double dt) {
+    if (!(a > 0.0) || !(dt >= 0.0) || !std::isfinite(a * dt)) return -1;
+    return default_terms(a * dt / kHbar);
+}
+
+extern "C" tbk_status tb_build_velocity(const double *pos, const double box[3], const int32_t periodic[3],
+                                        int32_t axis, const tbk_ham *h, void *vx, void *stream) {
+    clear_error();
+    TBK_CHECK(pos && box && periodic && h && vx, TBK_ERR_INVALID_ARG, "NULL argument");
+    TBK_CHECK(axis >= 0 && axis <= 2, TBK_ERR_INVALID_ARG, "axis = %d not in {0, 1, 2}", axis);
+    TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "the velocity operator is built for one structure");
+    TBK_CHECK(h->ptr && h->col && h->val && h->perm, TBK_ERR_INVALID_ARG, "a Hamiltonian array is NULL");
+    TBK_CHECK(!periodic[axis] || (std::isfinite(box[axis]) && box[axis] > 0), TBK_ERR_INVALID_ARG,
+              "periodic length along axis %d must be positive", axis);
+    if (h->n_rows == 0) return TBK_OK;
+    hipStream_t s = as_stream(stream);
+    const SellView sv{h->ptr, h->col, log2_of(h->fmt == TBK_CSR_F64 ? 1 : h->slice)};
+    const unsigned g = (unsigned)ceil_div(h->n_rows, kLsqtThreads);
+    if (h->fmt == TBK_SELL_F32)
+        k_velocity<float><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const float *>(h->val), h->perm, pos,
+                                                     h->n_rows, box[axis], periodic[axis], axis,
+                                                     static_cast<float *>(vx));
+    else
+        k_velocity<double><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const double *>(h->val), h->perm, pos,
+                                                      h->n_rows, box[axis], periodic[axis], axis,
+                                                      static_cast<double *>(vx));
+    TBK_HIP(hipGetLastError());
+    return TBK_OK;
+}
+
+extern "C" tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
+                                          const tbk_kpm_config *cfg, int64_t *bytes) {
+    clear_error();
+    TBK_CHECK(bytes != nullptr, TBK_ERR_INVALID_ARG, "bytes is NULL");
+    LsqtLayout ly;
+    tbk_status st = make_layout(h, R, M, precision, cfg, ly);
+    if (st != TBK_OK) return st;
+    *bytes = (int64_t)ly.total;
+    return TBK_OK;
+}
+
+extern "C" tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double a, double b, const void *r,
+                                       int32_t R, int32_t M, int32_t n_t, double dt, int32_t n_cheb,
+                                       int32_t precision, const tbk_kpm_config *cfg, void *work,
+                                       int64_t work_bytes, double *nu, void *stream) {
+    clear_error();
+    TBK_CHECK(h && vx && r && work && nu, TBK_ERR_INVALID_ARG, "NULL argument");
+    TBK_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(dt), TBK_ERR_NOT_FINITE,
+              "a, b or dt is not finite");
+    TBK_CHECK(a > 0 && dt > 0, TBK_ERR_INVALID_ARG, "a = %g and dt = %g must be positive", a, dt);
+    TBK_CHECK(n_t >= 1 && n_t <= 1000000, TBK_ERR_INVALID_ARG, "n_t = %d outside [1, 10^6]", n_t);
+    if (n_cheb <= 0) n_cheb = default_terms(a * dt / kHbar);
+    TBK_CHECK(n_cheb <= 100000, TBK_ERR_INVALID_ARG, "n_cheb = %d too large", n_cheb);
+    LsqtLayout ly;
+    tbk_status st = make_layout(h, R, M, precision, cfg, ly);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(work_bytes >= (int64_t)ly.total, TBK_ERR_BUFFER_TOO_SMALL, "work has %lld bytes, needs %lld",
+              (long long)work_bytes, (long long)ly.total);
+    TBK_CHECK(((uintptr_t)work & 255) == 0, TBK_ERR_INVALID_ARG, "work is not 256-byte aligned");
+    hipStream_t s = as_stream(stream);
+    char *w = static_cast<char *>(work);
+    if (precision == TBK_PREC_C32)
+        return run_vac<float>(h, static_cast<const float *>(vx), a, b, static_cast<const float *>(r), R, M, n_t, dt,
+                              n_cheb, precision, ly, w, nu, s);
+    return run_vac<double>(h, static_cast<const double *>(vx), a, b, static_cast<const double *>(r), R, M, n_t, dt,
+                           n_cheb, precision, ly, w, nu, s);
+}

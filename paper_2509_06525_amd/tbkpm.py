@@ -47,14 +47,18 @@ class HamStruct(ctypes.Structure):
 
 
 _LIB = None
-ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version", "tbk_hamiltonian_size",
-               "tb_build_hamiltonian", "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase", "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
+ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
+               "tbk_hamiltonian_size", "tb_build_hamiltonian",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
+               "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
+               "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
                "kpm_workspace_size_batched", "kpm_moments_batched",
+               "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
                "tbk_coordination_target", "tbk_mlp_forward", "tbk_mlp_workspace_size",
-               "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned")
+               "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned",
+               "tb_build_velocity", "lsqt_chebyshev_terms", "lsqt_workspace_size", "lsqt_vac_moments",
+               "lsqt_sigma")
 
 
 class MlpModel(ctypes.Structure):
@@ -185,6 +189,19 @@ def lib():
                                      ctypes.c_uint64, i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
     L.tbk_random_phase.restype = ctypes.c_int
     L.tbk_random_phase.argtypes = [ctypes.c_uint64, i64, i32, i32, vp, vp]
+    L.tb_build_velocity.restype = ctypes.c_int
+    L.tb_build_velocity.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i32), i32, ctypes.POINTER(HamStruct),
+                                    vp, vp]
+    L.lsqt_chebyshev_terms.restype = i32
+    L.lsqt_chebyshev_terms.argtypes = [f64, f64]
+    L.lsqt_workspace_size.restype = ctypes.c_int
+    L.lsqt_workspace_size.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, ctypes.POINTER(KpmConfig),
+                                      ctypes.POINTER(i64)]
+    L.lsqt_vac_moments.restype = ctypes.c_int
+    L.lsqt_vac_moments.argtypes = [ctypes.POINTER(HamStruct), vp, f64, f64, vp, i32, i32, i32, f64, i32, i32,
+                                   ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+    L.lsqt_sigma.restype = ctypes.c_int
+    L.lsqt_sigma.argtypes = [vp, i32, i32, f64, f64, f64, i32, vp, i32, vp, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     L.kpm_dos_batched.restype = ctypes.c_int
@@ -671,3 +688,55 @@ def build_hamiltonian_learned(pos, species, seg_atoms, boxes, periodic, onsite, 
     if with_bond_y:
         H.bond_y = y[:nb_out.value]
     return H
+
+
+# --------------------------------------------------------------------------
+# Velocity autocorrelation conductivity (Eq. (3))
+# --------------------------------------------------------------------------
+
+def build_velocity(H, pos, box, periodic, axis=0, stream=None):
+    """vx [n_entries] (type of H's values): V = i vx in H's layout, Angstrom / fs."""
+    pos = _dev(pos, torch.float64)
+    vx = torch.empty_like(H.tensors["val"])
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    _check(lib().tb_build_velocity(_ptr(pos), _f64arr(box), per, int(axis), ctypes.byref(H.st), _ptr(vx),
+                                   _stream(stream)))
+    return vx
+
+
+def chebyshev_terms(a, dt):
+    """Terms of the propagator series lsqt_vac_moments uses by default."""
+    return int(lib().lsqt_chebyshev_terms(float(a), float(dt)))
+
+
+def vac_moments(H, vx, a, b, r, M, n_t, dt, n_cheb=0, precision=None, config=None, work=None, stream=None):
+    """nu [n_t][R][M] (float64, device): Re <phi_L(t_j)| T_m(Ht) V |phi_R(t_j)> for start vectors r [N, R]."""
+    L = lib()
+    if precision is None:
+        precision = "c32" if r.dtype == torch.complex64 else "f64"
+    want = torch.complex64 if precision == "c32" else torch.complex128
+    r = _dev(r, want)
+    if r.dim() == 1:
+        r = r.reshape(-1, 1)
+    R = r.shape[1]
+    if work is None:
+        nbytes = ctypes.c_int64(0)
+        _check(L.lsqt_workspace_size(ctypes.byref(H.st), R, int(M), PRECISIONS[precision], _cfg_ref(config),
+                                     ctypes.byref(nbytes)))
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=r.device)
+    nu = torch.empty((int(n_t), R, int(M)), dtype=torch.float64, device=r.device)
+    _check(L.lsqt_vac_moments(ctypes.byref(H.st), _ptr(vx), float(a), float(b), _ptr(r), R, int(M), int(n_t),
+                              float(dt), int(n_cheb), PRECISIONS[precision], _cfg_ref(config), _ptr(work),
+                              work.numel(), _ptr(nu), _stream(stream)))
+    return nu
+
+
+def vac_sigma(nu, a, b, dt, E, kernel=0, stream=None):
+    """Running conductivity integral [n_t][nE] from vector-averaged moments nu [n_t][M]."""
+    nu = _dev(nu, torch.float64)
+    E = _dev(E, torch.float64)
+    n_t, M = nu.shape
+    sig = torch.empty((n_t, E.numel()), dtype=torch.float64, device=E.device)
+    _check(lib().lsqt_sigma(_ptr(nu), M, n_t, float(dt), float(a), float(b), int(kernel), _ptr(E), E.numel(),
+                            _ptr(sig), _stream(stream)))
+    return sig

@@ -21,12 +21,14 @@ def build(s, fmt="sell_f64", slice=64, reorder=True, r_cut=synth.R_HOP):
                                    r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice, reorder=reorder)
 
 
-def entries_in_atom_order(H):
-    """(rows, cols, vals, onsite) of the stored non-padding entries, mapped back to atom indices."""
+def entries_in_atom_order(H, values=None):
+    """(rows, cols, vals, onsite) of the stored non-padding entries, mapped back to atom indices.
+    `values` (a tensor in H's entry layout, e.g. velocity coefficients) replaces H's values."""
     t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
     n = H.n_rows
     C = 1 if H.fmt == tbkpm.FORMATS["csr_f64"] else H.st.slice
     ptr, col, val, perm = t["ptr"], t["col"], t["val"].astype(np.float64), t["perm"]
+    other = None if values is None else values.cpu().numpy().astype(np.float64)
     rows, cols, vals = [], [], []
     for s in range(ptr.shape[0] - 1):
         w = (ptr[s + 1] - ptr[s]) // C
@@ -38,7 +40,8 @@ def entries_in_atom_order(H):
                 q = ptr[s] + k * C + lane
                 if col[q] == i and val[q] == 0.0:
                     continue        # padding
-                rows.append(perm[i]); cols.append(perm[col[q]]); vals.append(val[q])
+                rows.append(perm[i]); cols.append(perm[col[q]])
+                vals.append(val[q] if other is None else other[q])
     onsite = np.empty(n)
     onsite[perm] = t["onsite"].astype(np.float64)
     return np.array(rows), np.array(cols), np.array(vals), onsite
