@@ -295,6 +295,82 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
                          "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6}}
 
 
+def bench_vac(args, w):
+    """Velocity-autocorrelation conductivity (Eq. (3)) on one structure: per step the
+    Hamiltonian and velocity operator are built, the correlation moments of n_t
+    propagation steps computed (M - 1 recurrence launches, two Chebyshev-Bessel
+    propagations and one velocity product per time step) and sigma(E, t) formed."""
+    import torch
+    from paper_2509_06525_amd import synth, tbkpm
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    M, R, n_t, dt = w["M"], w["R"], w["n_t"], w["dt"]
+    log(f"generating {args.workload}")
+    s = synth.make_structure(args.workload)
+    N = s.n
+    pos = torch.from_numpy(s.pos).to(dev)
+    sp = torch.from_numpy(s.species).to(dev)
+    r = torch.from_numpy(synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
+    held = []
+
+    def build():
+        H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP, r0=synth.R0,
+                                    beta=synth.BETA, fmt=w["fmt"], slice=args.slice, stream=stream,
+                                    into=held.pop() if held else None)
+        held.append(H)
+        return H
+
+    H = build()
+    a, b = H.scale()
+    n_cheb = tbkpm.chebyshev_terms(a, dt)
+    E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
+
+    def step():
+        Hs = build()
+        aa, bb = Hs.scale()
+        vx = tbkpm.build_velocity(Hs, pos, s.box, s.periodic, 0, stream=stream)
+        nu = tbkpm.vac_moments(Hs, vx, aa, bb, r, M, n_t, dt, n_cheb, "c32", stream=stream)
+        sig = tbkpm.vac_sigma(nu.mean(1).contiguous(), aa, bb, dt, E, stream=stream)
+        return Hs, sig
+
+    log(f"N={N} M={M} R={R} n_t={n_t} dt={dt} fs, {n_cheb} propagator terms: warmup {args.warmup}, "
+        f"timed {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Hs, sig = step()
+        torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    st = Hs.st
+    Rp = 1
+    while Rp < R:
+        Rp *= 2
+    hb = st.n_entries * 8 + st.n_ptr * 8                # values + columns (4 + 4 B), slice offsets
+    rec = hb + N * Rp * 8 * 4                           # recurrence launch (pair form: left vector for r)
+    prop = hb + N * Rp * 8 * 5                          # propagator term: T_k gather, T_{k-1}, T_{k+1}, acc r/w
+    vel = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 2
+    per_t = (M - 1) * rec + 2 * (n_cheb - 1) * prop + vel
+    total = n_t * per_t
+    achieved = total / sec / 1e9
+    out = {
+        "metric": "VAC atom*moments*timesteps/s", "value": N * M * R * n_t / sec,
+        "unit": "atom*moments*timesteps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": N, "moments": M, "vectors": R, "time_steps": n_t,
+                   "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"], "slice": args.slice,
+                   "precision": "c32", "a_eV": a, "b_eV": b},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole VAC step (k_cheb_step pair form, k_evolve_term, k_apply_velocity)",
+                     "bytes_per_step": total},
+        "sigma_max": float(sig[-1].abs().max()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -313,6 +389,8 @@ def main():
     w = dict(synth.WORKLOADS[args.workload])
     if w["kind"] == "snapshots":
         return bench_snapshots(args, w)
+    if w.get("vac"):
+        return bench_vac(args, w)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()

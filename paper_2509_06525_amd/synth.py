@@ -154,6 +154,10 @@ WORKLOADS = {
                                    train_seed=4004),
     "graphene_pristine_100M": dict(kind="sheet", nx=5000, ny=5000, sigma=0.0, M=1000, R=1,
                                    fmt="sell_f32", precision="c32", seed=1004),
+    # velocity autocorrelation: 200 propagation steps of 0.1 fs (20 fs of correlation time)
+    "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
+                                    fmt="sell_f32", precision="c32", seed=1005, vac=True,
+                                    n_t=200, dt=0.1),
 }
 VECTOR_SEED_OFFSET = 1000   # vector seed = structure seed + 1000
 
