@@ -312,10 +312,18 @@ def bench_vac(args, w):
     sp = torch.from_numpy(s.species).to(dev)
     r = torch.from_numpy(synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
     held = []
+    slice_, config = args.slice, None
+    if not args.no_tune:
+        if not args.retune:
+            use_shipped_tuning()
+        tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, R, "c32", r_cut=synth.R_HOP,
+                              r0=synth.R0, beta=synth.BETA, stream=stream)
+        slice_, config = tune.slice, tune.config
+        log(f"tuned: slice {slice_} {config.as_dict()}")
 
     def build():
         H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP, r0=synth.R0,
-                                    beta=synth.BETA, fmt=w["fmt"], slice=args.slice, stream=stream,
+                                    beta=synth.BETA, fmt=w["fmt"], slice=slice_, stream=stream,
                                     into=held.pop() if held else None)
         held.append(H)
         return H
@@ -329,7 +337,7 @@ def bench_vac(args, w):
         Hs = build()
         aa, bb = Hs.scale()
         vx = tbkpm.build_velocity(Hs, pos, s.box, s.periodic, 0, stream=stream)
-        nu = tbkpm.vac_moments(Hs, vx, aa, bb, r, M, n_t, dt, n_cheb, "c32", stream=stream)
+        nu = tbkpm.vac_moments(Hs, vx, aa, bb, r, M, n_t, dt, n_cheb, "c32", config=config, stream=stream)
         sig = tbkpm.vac_sigma(nu.mean(1).contiguous(), aa, bb, dt, E, stream=stream)
         return Hs, sig
 
@@ -360,8 +368,9 @@ def bench_vac(args, w):
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "moments": M, "vectors": R, "time_steps": n_t,
-                   "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"], "slice": args.slice,
-                   "precision": "c32", "a_eV": a, "b_eV": b},
+                   "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"], "slice": slice_,
+                   "precision": "c32", "a_eV": a, "b_eV": b,
+                   "launch": None if config is None else config.as_dict()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "whole VAC step (k_cheb_step pair form, k_evolve_term, k_apply_velocity)",
