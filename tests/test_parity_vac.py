@@ -110,3 +110,30 @@ def test_vac_errors():
         tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 3)
     assert e.value.name == "INVALID_ARG"
     assert tbkpm.chebyshev_terms(-1.0, 0.1) == -1
+
+
+def test_fullsize_vac_first_steps_against_oracle():
+    """The 1M-atom VAC workload in the benchmark's launch shape: its first two time
+    steps (one propagation) of all M moments against the oracle (complex-float bar:
+    1e-4 of the largest moment; running integral within 1e-4 relative L2)."""
+    w = synth.WORKLOADS["graphene_thermal_1M_vac"]
+    s = synth.make_structure("graphene_thermal_1M_vac")
+    print(f"[fullsize-vac] N={s.n} M={w['M']} n_t=2", flush=True)
+    pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
+    tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, w["R"], "c32")
+    H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32", slice=tune.slice)
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    lo, hi = O.gershgorin(csr)
+    a, b = 1.01 * (hi - lo) / 2, (hi + lo) / 2
+    r = synth.random_phase(s.n, w["R"], w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)
+    vx = tbkpm.build_velocity(H, pos, s.box, s.periodic, 0)
+    nc = tbkpm.chebyshev_terms(a, w["dt"])
+    nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), w["M"], 2, w["dt"], nc, "c32", config=tune.config)
+    nu = nu.cpu().numpy()
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0)
+    nuo = O.vac_moments(csr, vo, a, b, r.astype(np.complex128), w["M"], 2, w["dt"], nc)
+    assert np.abs(nu - nuo).max() <= 1e-4 * np.abs(nuo).max()
+    E = synth.energy_grid(a, b)
+    sig = O.vac_sigma(nu.mean(1), a, b, w["dt"], E)
+    sigo = O.vac_sigma(nuo.mean(1), a, b, w["dt"], E)
+    assert G.rel_l2(sig[1], sigo[1]) <= 1e-4
