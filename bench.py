@@ -54,12 +54,14 @@ def parse():
     return p.parse_args()
 
 
-def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True):
+def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True, compact=False):
     """Algorithmic bytes of one recurrence launch (see module docstring); the
-    doubling form reads no r, the uniform-values form no stored hoppings."""
+    doubling form reads no r, the uniform-values form no stored hoppings, the
+    compact-column form 2-byte column offsets (the few entries whose offset
+    escapes 16 bits also read their 4-byte column; not counted)."""
     st = H.st
     val_b = 4 if st.fmt == 2 else 8
-    b = st.n_entries * ((val_b if read_values else 0) + 4) + st.n_ptr * 8
+    b = st.n_entries * ((val_b if read_values else 0) + (2 if compact else 4)) + st.n_ptr * 8
     # gather T_n once, read T_{n-1}, write T_{n+1} (+ read r in the direct form)
     b += st.n_rows * Rp * 2 * elem * (4 if read_r else 3)
     if diag and st.has_onsite:
@@ -279,7 +281,8 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
     rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), a, b, E, stream=stream).cpu().numpy()
     dbl = bool(cfg.doubling)
     launches = M // 2 if dbl else M - 1
-    launch_bytes = cheb_step_bytes(H, Rp, elem, diag, read_r=not dbl, read_values=not cfg.uniform_values)
+    launch_bytes = cheb_step_bytes(H, Rp, elem, diag, read_r=not dbl, read_values=not cfg.uniform_values,
+                                   compact=bool(cfg.compact_columns))
     launch_s = med * 1e-3 / launches
     achieved = launch_bytes / launch_s / 1e9
     N = H.st.n_rows
@@ -483,10 +486,10 @@ def main():
         Rp *= 2
     elem = 4 if w["precision"] == "c32" else 8
     diag = Hs.st.has_onsite or bb != 0.0
-    launch_bytes = cheb_step_bytes(Hs, Rp, elem, diag)
+    launch_cfg = config if config is not None else tbkpm.default_config(Hs, R, w["precision"])
+    launch_bytes = cheb_step_bytes(Hs, Rp, elem, diag, compact=bool(launch_cfg.compact_columns))
     kpm_med = float(np.median(kpm_ms))
     launch_s = kpm_med * 1e-3 / (M - 1)
-    launch_cfg = config if config is not None else tbkpm.default_config(Hs, R, w["precision"])
     achieved = launch_bytes / launch_s / 1e9
     mu_c = mu.cpu().numpy().copy()
     rho_c = rho.cpu().numpy()

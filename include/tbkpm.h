@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 2
+#define TBK_ABI_VERSION 3
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -108,6 +108,12 @@ typedef struct {
                               value equals hop_value (e.g. a pristine lattice
                               in SELL_F32); 0 otherwise and for learned H      */
     double hop_value;      /* out (build): that value, as stored (eV)         */
+    int16_t *col16;        /* optional device int16 [n_entries] (NULL = none):
+                              column minus row of each stored entry, or -32768
+                              where that does not fit in 16 bits (col holds
+                              every column); filled by tb_build_hamiltonian
+                              when non-NULL, read by the recurrence with
+                              compact_columns = 1                              */
 } tbk_ham;
 
 /*
@@ -199,6 +205,10 @@ typedef struct {
                                    off-diagonal values, use h->hop_value (needs
                                    h->uniform_hop = 1; same results bit for bit,
                                    4 or 8 B less per stored entry)                */
+    int32_t compact_columns;    /* kpm_moments only: 1 = read the 16-bit column
+                                   offsets h->col16 (needs them) and col only
+                                   where an offset does not fit: 2 B less per
+                                   stored entry, same results bit for bit         */
 } tbk_kpm_config;
 
 /* The launch shape kpm_moments uses for (h, R, precision) when none is given

@@ -66,9 +66,13 @@ void load_file_cache() {
         r.config.persistent = 0;
         r.config.doubling = 0;
         r.config.uniform_values = 0;
-        if (std::sscanf(line, "%511s %d %d %d %d %d %d %lf", key, &r.slice, &r.config.vectors_per_thread,
-                        &r.config.tiles_per_block, &r.config.nontemporal, &r.config.xcd_remap,
-                        &r.config.rows_per_thread, &r.ms_per_step) == 8) {
+        int compact = 0;
+        const int got = std::sscanf(line, "%511s %d %d %d %d %d %d %lf %d", key, &r.slice,
+                                    &r.config.vectors_per_thread, &r.config.tiles_per_block,
+                                    &r.config.nontemporal, &r.config.xcd_remap, &r.config.rows_per_thread,
+                                    &r.ms_per_step, &compact);
+        if (got == 8 || got == 9) {
+            r.config.compact_columns = got == 9 ? compact : 0;
             r.from_cache = 1;
             r.config.doubling = std::strstr(key, "/dbl1") ? 1 : 0;
             r.config.uniform_values = std::strstr(key, "/uv1") ? 1 : 0;
@@ -83,9 +87,9 @@ void append_file_cache(const Key &k, const tbk_tune_result &r) {
     if (path.empty()) return;
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", k.text.c_str(), r.slice, r.config.vectors_per_thread,
+    std::fprintf(f, "%s %d %d %d %d %d %d %.6f %d\n", k.text.c_str(), r.slice, r.config.vectors_per_thread,
                  r.config.tiles_per_block, r.config.nontemporal, r.config.xcd_remap, r.config.rows_per_thread,
-                 r.ms_per_step);
+                 r.ms_per_step, r.config.compact_columns);
     std::fclose(f);
 }
 
@@ -102,7 +106,7 @@ Key make_key(int device, const char *arch, int64_t n, int32_t R, int32_t precisi
 // Owns the device arrays of one Hamiltonian built for tuning.
 struct TuneHam {
     tbk_ham h{};
-    DevBuf ptr, col, val, onsite, perm;
+    DevBuf ptr, col, col16, val, onsite, perm;
 };
 
 tbk_status build_tune_ham(const double *pos, const int32_t *species, int64_t n, const double box[3],
@@ -119,6 +123,8 @@ tbk_status build_tune_ham(const double *pos, const int32_t *species, int64_t n, 
     TBK_HIP(t.val.alloc(vb * std::max<int64_t>(t.h.n_entries, 1), s));
     TBK_HIP(t.onsite.alloc(vb * n, s));
     TBK_HIP(t.perm.alloc(sizeof(int32_t) * n, s));
+    TBK_HIP(t.col16.alloc(sizeof(int16_t) * std::max<int64_t>(t.h.n_entries, 1), s));
+    t.h.col16 = t.col16.as<int16_t>();
     t.h.ptr = t.ptr.as<int64_t>();
     t.h.col = t.col.as<int32_t>();
     t.h.val = t.val.as<void>();
@@ -244,8 +250,10 @@ tbk_status autotune_impl(const double *pos, const int32_t *species, int64_t n, c
                     if (rpt > tpb) continue;
                     if (rpt == 4 && (Rp / vpt != 1 || hp->max_degree != 3)) continue;   // see rows_per_thread
                     for (int nt : {0, 1})
-                        for (int xr : {0, 1}) {
+                        for (int xr : {0, 1})
+                        for (int cc : {0, 1}) {
                             tbk_kpm_config c{};
+                            c.compact_columns = cc;
                             c.vectors_per_thread = vpt;
                             c.tiles_per_block = tpb;
                             c.rows_per_thread = rpt;

@@ -173,7 +173,8 @@ __global__ void k_fill(CellList cl, const double *__restrict__ pos, const int32_
                        const SpeciesTable *__restrict__ tab, const int32_t *__restrict__ perm,
                        const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                        int32_t *__restrict__ col, V *__restrict__ val, V *__restrict__ onsite,
-                       int64_t *__restrict__ bound_keys, int64_t *__restrict__ val_keys) {
+                       int64_t *__restrict__ bound_keys, int64_t *__restrict__ val_keys,
+                       int16_t *__restrict__ col16) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     double vlo = INFINITY, vhi = -INFINITY;   // range of the stored hoppings
@@ -215,6 +216,12 @@ __global__ void k_fill(CellList cl, const double *__restrict__ pos, const int32_
             }
             col[base + (int64_t)(b + 1) * slice] = c;
             val[base + (int64_t)(b + 1) * slice] = v;
+        }
+        if (col16) {    // 16-bit column offsets (escape -32768: read col)
+            for (int32_t q = 0; q < w; ++q) {
+                const int64_t d = (int64_t)col[base + (int64_t)q * slice] - r;
+                col16[base + (int64_t)q * slice] = (d >= -32767 && d <= 32767) ? (int16_t)d : (int16_t)-32768;
+            }
         }
         double eps = tab->onsite[si];
         onsite[r] = (V)eps;
@@ -502,13 +509,13 @@ tbk_status HamPlan::fill(const double *pos, const int32_t *species, int64_t n, c
                                             p->n_species, dtab.as<SpeciesTable>(), perm.as<int32_t>(),
                                             iperm.as<int32_t>(), h->ptr, h->col, static_cast<float *>(h->val),
                                             static_cast<float *>(h->onsite), keys.as<int64_t>(),
-                                            vkeys.as<int64_t>());
+                                            vkeys.as<int64_t>(), h->col16);
     } else {
         k_fill<double><<<gn, kBlock, 0, s>>>(cells.view, pos, species, n, slice, p->r_cut, p->r0, p->beta,
                                              p->n_species, dtab.as<SpeciesTable>(), perm.as<int32_t>(),
                                              iperm.as<int32_t>(), h->ptr, h->col, static_cast<double *>(h->val),
                                              static_cast<double *>(h->onsite), keys.as<int64_t>(),
-                                             vkeys.as<int64_t>());
+                                             vkeys.as<int64_t>(), h->col16);
     }
     TBK_HIP(hipGetLastError());
     return finish(keys, n, p, h, bounds, s);

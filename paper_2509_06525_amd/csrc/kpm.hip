@@ -41,6 +41,7 @@ template <class VT> struct StepScalars {
     VT shift;                // b
     VT hop;                  // the one off-diagonal value when `uniform`
     int32_t uniform;         // 1: values are not read, every real entry is `hop`
+    int32_t compact;         // 1: columns from the 16-bit offsets (col where they escape)
 };
 
 // One recurrence step.  Each thread handles RPT rows (from RPT consecutive
@@ -53,9 +54,9 @@ template <class VT> struct StepScalars {
 // clamped to its last entry and weighted by zero.
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int RPT, int W, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_cheb_step(
-    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, const VT *__restrict__ val,
-    const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
-    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a) {
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, const int16_t *__restrict__ col16,
+    const VT *__restrict__ val, const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev,
+    VT *tnext, const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a) {
     constexpr int RPB = kThreads / L;   // rows per tile
     constexpr int KU = W > 0 ? W : 4;   // entries per batch of loads
     const int lr = threadIdx.x / L;
@@ -125,7 +126,12 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
 #pragma unroll
                 for (int k = 0; k < KU; ++k) {
                     if constexpr (W > 0) {
-                        c[u][k] = ld<NT>(col + base[u] + k * stride);
+                        if (a.compact) {
+                            const int16_t d = ld<NT>(col16 + base[u] + k * stride);
+                            c[u][k] = d == -32768 ? ld<NT>(col + base[u] + k * stride) : (int32_t)i[u] + d;
+                        } else {
+                            c[u][k] = ld<NT>(col + base[u] + k * stride);
+                        }
                         if (a.uniform) h[u][k] = c[u][k] == (int32_t)i[u] ? (VT)0 : a.hop;   // padding: own row
                         else h[u][k] = ld<NT>(val + base[u] + k * stride);
                     } else {
@@ -134,7 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
                         // is never read: kk is clamped below 0 -> use the row itself).
                         const int kk = min(k0 + k, w[u] - 1);
                         if (kk >= 0) {
-                            c[u][k] = ld<NT>(col + base[u] + kk * stride);
+                            if (a.compact) {
+                                const int16_t d = ld<NT>(col16 + base[u] + kk * stride);
+                                c[u][k] = d == -32768 ? ld<NT>(col + base[u] + kk * stride) : (int32_t)i[u] + d;
+                            } else {
+                                c[u][k] = ld<NT>(col + base[u] + kk * stride);
+                            }
                             if (k0 + k >= w[u]) h[u][k] = 0;
                             else if (a.uniform) h[u][k] = c[u][k] == (int32_t)i[u] ? (VT)0 : a.hop;
                             else h[u][k] = ld<NT>(val + base[u] + kk * stride);
@@ -358,6 +369,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 template <class VT> struct StepPtrs {
     const int64_t *ptr;
     const int32_t *col;
+    const int16_t *col16;
     const VT *val;
     const VT *onsite;
     const VT *tcur;
@@ -374,16 +386,16 @@ void launch_step_d(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, cons
     if constexpr (L == 1 && VPT == 1 && W == 3) {
         if (pl.cfg.rows_per_thread == 4) {
             k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 4, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
-                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+                p.ptr, p.col, p.col16, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
             return;
         }
     }
     if (pl.cfg.rows_per_thread >= 2)
         k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 2, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
-            p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+            p.ptr, p.col, p.col16, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
     else
         k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 1, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
-            p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
+            p.ptr, p.col, p.col16, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
 }
 
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W>
@@ -460,6 +472,7 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     StepPtrs<VT> sp{};
     sp.ptr = h->ptr;
     sp.col = h->col;
+    sp.col16 = h->col16;
     sp.val = static_cast<const VT *>(h->val);
     sp.onsite = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
     sp.r = pair ? left : r_int;
@@ -473,6 +486,7 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     sa.shift = (VT)b;
     sa.hop = (VT)h->hop_value;
     sa.uniform = pl.cfg.uniform_values;
+    sa.compact = pl.cfg.compact_columns;
     const bool diag = h->has_onsite || b != 0.0;
     auto reduce = [&](int n0, int count) {
         dim3 grid(pl.n_chunks, count);
@@ -545,6 +559,7 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.persistent = 0;
     c.doubling = 0;
     c.uniform_values = 0;
+    c.compact_columns = 0;
     (void)h;
     return c;
 }
@@ -583,6 +598,10 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
               "uniform_values must be 0/1");
     TBK_CHECK(pl.cfg.uniform_values == 0 || h->uniform_hop == 1, TBK_ERR_INVALID_ARG,
               "uniform_values needs a Hamiltonian whose stored hoppings are all equal (h->uniform_hop)");
+    TBK_CHECK(pl.cfg.compact_columns == 0 || pl.cfg.compact_columns == 1, TBK_ERR_INVALID_ARG,
+              "compact_columns must be 0/1");
+    TBK_CHECK(pl.cfg.compact_columns == 0 || h->col16 != nullptr, TBK_ERR_INVALID_ARG,
+              "compact_columns needs the 16-bit column offsets h->col16");
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;

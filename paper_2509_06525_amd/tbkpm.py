@@ -43,7 +43,8 @@ class HamStruct(ctypes.Structure):
                 ("n_seg", ctypes.c_int32),
                 ("ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("onsite", ctypes.c_void_p), ("perm", ctypes.c_void_p),
-                ("seg_rows", ctypes.c_void_p), ("uniform_hop", ctypes.c_int32), ("hop_value", ctypes.c_double)]
+                ("seg_rows", ctypes.c_void_p), ("uniform_hop", ctypes.c_int32), ("hop_value", ctypes.c_double),
+                ("col16", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -71,7 +72,8 @@ class KpmConfig(ctypes.Structure):
     _fields_ = [("vectors_per_thread", ctypes.c_int32), ("tiles_per_block", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("doubling", ctypes.c_int32), ("uniform_values", ctypes.c_int32)]
+                ("doubling", ctypes.c_int32), ("uniform_values", ctypes.c_int32),
+                ("compact_columns", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,9 +85,9 @@ class TuneResult(ctypes.Structure):
 
 
 def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1,
-                persistent=0, doubling=0, uniform_values=0):
+                persistent=0, doubling=0, uniform_values=0, compact_columns=0):
     return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread, persistent,
-                     doubling, uniform_values)
+                     doubling, uniform_values, compact_columns)
 
 
 def with_doubling(cfg, on=1):
@@ -303,7 +305,7 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
         st = HamStruct(fmt=FORMATS[fmt], slice=int(slice), n_rows=n, n_ptr=t["ptr"].numel(),
                        n_entries=t["col"].numel())
         st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
-        st.onsite, st.perm = t["onsite"].data_ptr(), t["perm"].data_ptr()
+        st.onsite, st.perm, st.col16 = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["col16"].data_ptr()
         bounds = (ctypes.c_double * 2)()
         rc = L.tb_build_hamiltonian(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p), ctypes.byref(st),
                                     bounds, s)
@@ -322,9 +324,10 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
         "val": torch.empty(max(st.n_entries, 1), dtype=vdt, device=dev),
         "onsite": torch.empty(n, dtype=vdt, device=dev),
         "perm": torch.empty(n, dtype=torch.int32, device=dev),
+        "col16": torch.empty(max(st.n_entries, 1), dtype=torch.int16, device=dev),
     }
     st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
-    st.onsite, st.perm = t["onsite"].data_ptr(), t["perm"].data_ptr()
+    st.onsite, st.perm, st.col16 = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["col16"].data_ptr()
     bounds = (ctypes.c_double * 2)()
     _check(L.tb_build_hamiltonian(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p),
                                   ctypes.byref(st), bounds, s))

@@ -9,6 +9,7 @@ oracle to the complex-float bar.
 """
 import numpy as np
 import pytest
+import torch
 
 from oracle import oracle as O
 from paper_2509_06525_amd import synth, tbkpm
@@ -96,3 +97,34 @@ def test_four_rows_per_thread(tpb, fields):
         csr, _ = O.hamiltonian(s64.pos, s64.species, s64.box, s64.periodic, s64.onsite, s64.t_pair)
         mo, _ = O.kpm_moments(csr, a, b, r64, 77)
         assert np.abs(mu - mo).max() <= 1e-10 * s64.n
+
+
+@pytest.mark.parametrize("fmt,slice", [("sell_f32", 64), ("sell_f64", 256), ("csr_f64", 1)])
+@pytest.mark.parametrize("fields", [{}, {"doubling": 1}])
+def test_compact_columns_bitwise(fmt, slice, fields):
+    """16-bit column offsets give the same moments bit for bit; a 160 x 110 cell sheet
+    (70,400 rows) has periodic-wrap bonds whose offsets escape 16 bits."""
+    s = synth.graphene_sheet(160, 110, 0.04, 12)
+    H = G.build(s, fmt=fmt, slice=slice)
+    col = H.tensors["col"].cpu().numpy().astype(np.int64)
+    c16 = H.tensors["col16"].cpu().numpy()
+    assert (c16[: H.st.n_entries] == -32768).any()          # some offsets escape
+    a, b = H.scale()
+    prec = "c32" if fmt == "sell_f32" else "f64"
+    cdt = np.complex64 if prec == "c32" else np.complex128
+    r = G.to_dev(synth.random_phase(s.n, 2, 3, cdt))
+    m0 = tbkpm.kpm_moments(H, a, b, r, 64, prec, config=tbkpm.make_config(1, 2, 1, 0, 1, **fields))
+    m1 = tbkpm.kpm_moments(H, a, b, r, 64, prec,
+                           config=tbkpm.make_config(1, 2, 1, 0, 1, compact_columns=1, **fields))
+    torch.testing.assert_close(m1, m0, rtol=0, atol=0)
+    # offsets decode to the stored columns
+    rows = np.empty(H.st.n_entries, np.int64)
+    ptr = H.tensors["ptr"].cpu().numpy()
+    C = 1 if fmt == "csr_f64" else slice
+    for sl in range(ptr.shape[0] - 1):
+        w = (ptr[sl + 1] - ptr[sl]) // C
+        for k in range(w):
+            rows[ptr[sl] + k * C: ptr[sl] + (k + 1) * C] = sl * C + np.arange(C)
+    ok = c16[: H.st.n_entries] != -32768
+    np.testing.assert_array_equal(rows[ok] + c16[: H.st.n_entries][ok], col[: H.st.n_entries][ok])
+    assert np.all(np.abs(col[: H.st.n_entries][~ok] - rows[~ok]) > 32767)
