@@ -9,7 +9,8 @@
  * analytic backward with BF16 operand rounding, and one AdamW step; and the
  * counter-based random-phase generator the GPU can use instead of stored phases;
  * and the velocity-autocorrelation conductivity of Eq. (3) (velocity operator,
- * Chebyshev time evolution, correlation moments, running time integral).
+ * Chebyshev time evolution, correlation moments, running time integral); and
+ * the s, p Slater-Koster orbital Hamiltonian of the multi-orbital models.
  *
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
  * load this file.  It shares no code, header or constant generator with the HIP
@@ -740,4 +741,79 @@ int orc_vac_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a,
     }
     free(cprev); free(cj);
     return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multi-orbital Slater-Koster Hamiltonian (s, px, py, pz per atom).          */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Two-centre block <a_i|H|b_j> of a bond with direction cosines c = (l, m, n)
+ * (from atom i to atom j) and radial factor f, orbitals a, b in (s, x, y, z)
+ * (Slater & Koster, Phys. Rev. 94, 1498 (1954), Table I, s and p rows):
+ *   ss = V_ss_sigma,  s p_b = c_b V_sp_sigma,  p_a s = -c_a V_sp_sigma,
+ *   p_a p_b = c_a c_b V_pp_sigma + (delta_ab - c_a c_b) V_pp_pi,
+ * all times f.  v = {V_ss_sigma, V_sp_sigma, V_pp_sigma, V_pp_pi}.
+ */
+static void orc_sk_block(const double c[3], double f, const double v[4], double B[4][4])
+{
+    B[0][0] = f * v[0];
+    for (int b = 0; b < 3; ++b) {
+        B[0][b + 1] = f * c[b] * v[1];
+        B[b + 1][0] = -f * c[b] * v[1];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            B[a + 1][b + 1] = f * (c[a] * c[b] * v[2] + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * v[3]);
+}
+
+/*
+ * Orbital Hamiltonian of one species with s and p orbitals: orbital index
+ * 4 i + a (a = s, x, y, z).  For every pair {i, j} of orc_neighbor_pairs the
+ * bond vector d = x_j - x_i (minimum image), r = |d|, f = exp(-beta (r/r0 - 1))
+ * give H[4i+a][4j+b] = B(d/r, f)[a][b] and H[4j+b][4i+a] = the same number
+ * (B(-c) = B(c)^T, so H is symmetric).  Onsite diag(e_s, e_p, e_p, e_p).
+ * CSR of the 4n x 4n off-diagonal part (row_ptr [4n+1], col/val [32 npairs],
+ * columns ascending); diag [4n].  Returns 0, -2 when out of memory.
+ */
+int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int32_t periodic[3],
+                    int64_t npairs, const int32_t *pi, const int32_t *pj, const double v[4],
+                    double e_s, double e_p, double r0, double beta,
+                    int64_t *row_ptr, int32_t *col, double *val, double *diag)
+{
+    const int64_t nr = 4 * n;
+    int64_t *deg = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    if (!deg) return -2;
+    for (int64_t p = 0; p < npairs; ++p) { deg[pi[p]]++; deg[pj[p]]++; }
+    row_ptr[0] = 0;
+    for (int64_t r = 0; r < nr; ++r) row_ptr[r + 1] = row_ptr[r] + 4 * deg[r / 4];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nr > 0 ? nr : 1));
+    if (!fill) { free(deg); return -2; }
+    for (int64_t r = 0; r < nr; ++r) fill[r] = row_ptr[r];
+    for (int64_t p = 0; p < npairs; ++p) {
+        int32_t i = pi[p], j = pj[p];
+        double d[3], B[4][4], c[3];
+        double r = orc_displacement(pos, i, j, box, periodic, d);
+        for (int k = 0; k < 3; ++k) c[k] = d[k] / r;
+        orc_sk_block(c, exp(-beta * (r / r0 - 1.0)), v, B);
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                int64_t q = fill[4 * (int64_t)i + a]++;
+                col[q] = 4 * j + b; val[q] = B[a][b];
+                q = fill[4 * (int64_t)j + b]++;
+                col[q] = 4 * i + a; val[q] = B[a][b];
+            }
+    }
+    /* sort each row by column (values travel with their columns) */
+    for (int64_t r = 0; r < nr; ++r)
+        for (int64_t q = row_ptr[r] + 1; q < row_ptr[r + 1]; ++q) {
+            int32_t cq = col[q];
+            double vq = val[q];
+            int64_t t = q - 1;
+            while (t >= row_ptr[r] && col[t] > cq) { col[t + 1] = col[t]; val[t + 1] = val[t]; --t; }
+            col[t + 1] = cq; val[t + 1] = vq;
+        }
+    for (int64_t r = 0; r < nr; ++r) diag[r] = (r % 4 == 0) ? e_s : e_p;
+    free(deg); free(fill);
+    return 0;
 }

@@ -1,0 +1,64 @@
+"""Pins of the oracle's s, p Slater-Koster orbital Hamiltonian.
+
+* a dimer along z has the textbook block: ss sigma, sp sigma on s-p_z only, pp
+  sigma on p_z-p_z, pp pi on p_x-p_x and p_y-p_y;
+* the Hamiltonian is rotation covariant: rotating the structure by Q turns each
+  atom-pair block B into D B D^T with D = diag(1, Q) (s is a scalar, p a vector);
+  a wrong sign or a swapped direction cosine breaks this;
+* for a flat sheet the p_z orbitals decouple (sigma-pi separation) and their
+  block is exactly the one-orbital Hamiltonian with t_pair = V_pp_pi;
+* H is symmetric and its onsite part is diag(e_s, e_p, e_p, e_p).
+"""
+import numpy as np
+import scipy.spatial.transform
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth
+
+V = np.array([-5.7, 5.4, 6.2, -2.7])        # V_ss_sigma, V_sp_sigma, V_pp_sigma, V_pp_pi (eV)
+ES, EP = -7.3, 0.0
+OPEN = np.array([0, 0, 0], np.int32)
+
+
+def test_dimer_along_z():
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.42]])
+    csr, _ = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V, ES, EP)
+    H = csr.dense()
+    vss, vsp, vpps, vppp = V
+    want = np.array([[vss, 0, 0, vsp], [0, vppp, 0, 0], [0, 0, vppp, 0], [-vsp, 0, 0, vpps]])
+    np.testing.assert_allclose(H[0:4, 4:8], want, atol=1e-15)
+    np.testing.assert_allclose(H[4:8, 0:4], want.T, atol=1e-15)
+    np.testing.assert_allclose(np.diag(H), [ES, EP, EP, EP] * 2)
+
+
+def test_rotation_covariance():
+    s = synth.graphene_sheet(2, 2, 0.15, 5)
+    pos = s.pos - s.pos.mean(0)
+    Q = scipy.spatial.transform.Rotation.from_euler("zyx", [0.7, -0.4, 1.1]).as_matrix()
+    h1, pairs = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V, ES, EP)
+    h2, _ = O.sk_hamiltonian(pos @ Q.T, np.zeros(3), OPEN, V, ES, EP, pairs=pairs)
+    D = np.eye(4)
+    D[1:, 1:] = Q
+    Dn = np.kron(np.eye(s.n), D)
+    np.testing.assert_allclose(h2.dense(), Dn @ h1.dense() @ Dn.T, atol=1e-12)
+    assert np.abs(h1.dense()).max() > 1.0
+
+
+def test_flat_sheet_pz_block_is_the_one_orbital_hamiltonian():
+    s = synth.graphene_sheet(4, 5)                  # pristine, all atoms at the same z
+    sk, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V, ES, EP)
+    H = sk.dense()
+    z = np.arange(s.n) * 4 + 3
+    others = np.setdiff1d(np.arange(4 * s.n), z)
+    assert np.abs(H[np.ix_(z, others)]).max() == 0.0
+    h1, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, [EP], [[V[3]]])
+    np.testing.assert_allclose(H[np.ix_(z, z)], h1.dense(), rtol=0, atol=1e-15)
+
+
+def test_symmetric_with_periodic_images():
+    s = synth.graphene_sheet(3, 3, 0.08, 2)
+    sk, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V, ES, EP)
+    H = sk.dense()
+    np.testing.assert_array_equal(H, H.T)
+    assert abs(np.trace(H) - s.n * (ES + 3 * EP)) < 1e-12
+    assert np.all(np.diff(sk.row_ptr) == 12)          # 3 neighbours x 4 orbitals per row
