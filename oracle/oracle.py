@@ -64,7 +64,7 @@ def _lib():
     L.orc_adamw_step.restype = None
     L.orc_adamw_step.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _f64, _f64, _f64, _f64, _f64]
     L.orc_velocity_values.restype = None
-    L.orc_velocity_values.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _i32p, _i32, _f64p]
+    L.orc_velocity_values.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _i32p, _i32, _i32, _f64p]
     L.orc_evolve.restype = ctypes.c_int
     L.orc_evolve.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64, _f64, _f64, _i32, _c128p]
     L.orc_vac_moments.restype = ctypes.c_int
@@ -246,11 +246,12 @@ def target_scale(pairs, v, kappa, z0):
 HBAR_EV_FS = 0.6582119569
 
 
-def velocity_values(csr, pos, box, periodic, axis=0):
-    """vx[q] = H_ij (x_j - x_i) / hbar per CSR entry (V = i vx), Angstrom / fs."""
+def velocity_values(csr, pos, box, periodic, axis=0, n_orb=1):
+    """vx[q] = H_ij (x_j - x_i) / hbar per CSR entry (V = i vx), Angstrom / fs; with
+    n_orb orbitals per atom the positions are those of the orbitals' atoms."""
     vx = np.empty(csr.col.shape[0])
     _lib().orc_velocity_values(csr.n, csr.row_ptr, csr.col, csr.val, _c(pos, np.float64).reshape(-1),
-                               _c(box, np.float64), _c(periodic, np.int32), int(axis), vx)
+                               _c(box, np.float64), _c(periodic, np.int32), int(axis), int(n_orb), vx)
     return vx
 
 

@@ -597,15 +597,18 @@ void orc_target_scale(int64_t npairs, const int32_t *pi, const int32_t *pj,
  * minimum-image convention (the bond the hopping belongs to), and V_ii = 0.
  * Stored as the real coefficient vx[q] = H_ij (x_j - x_i) / hbar of each CSR
  * entry q = (i, j), so that (V psi)_i = i sum_q vx[q] psi_j (Angstrom / fs).
+ * With n_orb orbitals per atom (orbital index = n_orb atom + a), x is the
+ * position of the orbital's atom.
  */
 void orc_velocity_values(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                          const double *pos, const double box[3], const int32_t periodic[3],
-                         int32_t axis, double *vx)
+                         int32_t axis, int32_t n_orb, double *vx)
 {
+    /* n rows = n_orb orbitals per atom; an orbital sits at its atom's position */
     double d[3];
     for (int64_t i = 0; i < n; ++i)
         for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
-            orc_displacement(pos, i, col[q], box, periodic, d);
+            orc_displacement(pos, i / n_orb, col[q] / n_orb, box, periodic, d);
             vx[q] = val[q] * d[axis] / ORC_HBAR;
         }
 }

@@ -62,3 +62,17 @@ def test_symmetric_with_periodic_images():
     np.testing.assert_array_equal(H, H.T)
     assert abs(np.trace(H) - s.n * (ES + 3 * EP)) < 1e-12
     assert np.all(np.diff(sk.row_ptr) == 12)          # 3 neighbours x 4 orbitals per row
+
+
+def test_orbital_velocity_is_commutator_with_atom_positions():
+    """V = (i/hbar)[H, X] with X = diag(x of each orbital's atom), on an open flake."""
+    s = synth.graphene_sheet(2, 2, 0.1, 8)
+    csr, _ = O.sk_hamiltonian(s.pos, np.zeros(3), OPEN, V, ES, EP)
+    vx = O.velocity_values(csr, s.pos, np.zeros(3), OPEN, 0, n_orb=4)
+    Vd = np.zeros((csr.n, csr.n), complex)
+    for i in range(csr.n):
+        for q in range(csr.row_ptr[i], csr.row_ptr[i + 1]):
+            Vd[i, csr.col[q]] += 1j * vx[q]
+    H = csr.dense()
+    X = np.diag(np.repeat(s.pos[:, 0], 4))
+    np.testing.assert_allclose(Vd, 1j / O.HBAR_EV_FS * (H @ X - X @ H), atol=1e-12)
