@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 3
+#define TBK_ABI_VERSION 4
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -114,6 +114,9 @@ typedef struct {
                               every column); filled by tb_build_hamiltonian
                               when non-NULL, read by the recurrence with
                               compact_columns = 1                              */
+    int32_t n_orb;         /* out (build): orbitals per atom, 1 for the one-
+                              orbital builders, 4 for tb_build_hamiltonian_sk;
+                              perm[row] / n_orb is the caller's atom           */
 } tbk_ham;
 
 /*
@@ -468,6 +471,46 @@ tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_struct, const 
                            double *rho, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Multi-orbital Slater-Koster Hamiltonian (s, px, py, pz per atom)          */
+/* ------------------------------------------------------------------------ */
+
+/* Two-centre parameters of one species (Sec. 3: Slater-Koster blocks formed
+ * from bond directions; Slater & Koster, Phys. Rev. 94, 1498 (1954), Table I,
+ * s and p rows).  Every integral is scaled by f(r) = exp(-beta (r/r0 - 1)) for
+ * r < r_cut. */
+typedef struct {
+    double r_cut, r0, beta;     /* cutoff and reference length (Angstrom), decay */
+    double e_s, e_p;            /* onsite energies (eV)                            */
+    double v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi;   /* at r0 (eV)          */
+    int32_t reorder;            /* 1 = atom rows in cell-list order (as
+                                   tbk_tb_params.reorder)                          */
+} tbk_sk_params;
+
+/*
+ * Orbital Hamiltonian with s, px, py, pz on every atom: row 4 r + a (a = s, x,
+ * y, z) for atom row r; for a bond with direction cosines c (from i to j,
+ * minimum image) and f = f(r):
+ *   <s|s> = f V_ss_sigma, <s_i|p_j,b> = f c_b V_sp_sigma, <p_i,a|s_j> = -f c_a V_sp_sigma,
+ *   <p_i,a|p_j,b> = f [c_a c_b V_pp_sigma + (delta_ab - c_a c_b) V_pp_pi];
+ * onsite diag(e_s, e_p, e_p, e_p).  Stored as a SELL/CSR matrix of 4 n rows
+ * (entry 4 q + b of an orbital row: q-th neighbour in cell-list order, its
+ * orbital b; columns not sorted), so kpm_moments, kpm_dos and the VAC calls
+ * take it as is.  perm[4 r + a] = 4 atom + a (the caller's orbital order);
+ * n_orb = 4; spec_bounds: host double[2], row Gershgorin bounds.
+ *   species device int32 [n] (all 0: one species); other arguments as for
+ *   tbk_hamiltonian_size / tb_build_hamiltonian.
+ * Errors: as tb_build_hamiltonian; NOT_FINITE for a non-finite parameter.
+ * Both calls synchronise `stream`.
+ */
+tbk_status tbk_hamiltonian_size_sk(const double *pos, const int32_t *species, int64_t n,
+                                   const double box[3], const int32_t periodic[3],
+                                   const tbk_sk_params *sk, tbk_ham *h, void *stream);
+tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, int64_t n,
+                                   const double box[3], const int32_t periodic[3],
+                                   const tbk_sk_params *sk, tbk_ham *h, double spec_bounds[2],
+                                   void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Velocity autocorrelation conductivity, Eq. (3)                            */
 /* ------------------------------------------------------------------------ */
 
@@ -475,7 +518,7 @@ tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_struct, const 
  * Velocity operator along `axis` (0, 1, 2 = x, y, z), V = (i / hbar)[H, X],
  * in the layout of a built Hamiltonian h (single structure):
  *   vx[q] = H_q (x_col - x_row) / hbar  for every stored entry q (0 on padding),
- * the displacement between the two atoms taken with the minimum-image
+ * the displacement between the two atoms (perm[row] / h->n_orb) taken with the minimum-image
  * convention (the bond of the hopping), hbar = 0.6582119569 eV fs, so that
  * (V psi)_i = i sum_q vx[q] psi_col(q) in Angstrom / fs.
  *   pos  device double [n_rows][3] (the positions h was built from, caller's

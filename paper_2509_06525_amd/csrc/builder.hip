@@ -481,6 +481,7 @@ void HamPlan::set_sizes(int64_t n, const tbk_tb_params *p, tbk_ham *h) const {
     h->max_degree = max_degree;
     h->has_onsite = any_onsite(p);
     h->n_seg = cells.n_seg;
+    h->n_orb = 1;
     if (h->fmt == TBK_CSR_F64) h->slice = 1;
 }
 

@@ -46,7 +46,7 @@ __device__ __forceinline__ void row_range(const SellView &h, int64_t i, int64_t 
 // vx[q] = val[q] (x_j - x_i) / hbar for the stored entry q = (row i, column j),
 // minimum-image displacement along `axis` between the rows' atoms; 0 on padding.
 template <class V>
-__global__ void k_velocity(SellView h, const V *__restrict__ val, const int32_t *__restrict__ perm,
+__global__ void k_velocity(SellView h, const V *__restrict__ val, const int32_t *__restrict__ perm, int32_t n_orb,
                            const double *__restrict__ pos, int64_t n, double L, int32_t periodic, int32_t axis,
                            V *__restrict__ vx) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -54,12 +54,12 @@ __global__ void k_velocity(SellView h, const V *__restrict__ val, const int32_t 
     int64_t base, stride;
     int32_t w;
     row_range(h, r, base, w, stride);
-    const double xi = pos[3 * (int64_t)perm[r] + axis];
+    const double xi = pos[3 * (int64_t)(perm[r] / n_orb) + axis];
     for (int32_t k = 0; k < w; ++k) {
         const int64_t q = base + k * stride;
         const int32_t c = h.col[q];
         if (c == (int32_t)r) { vx[q] = (V)0; continue; }    // padding (no atom bonds to itself)
-        double d = __dsub_rn(pos[3 * (int64_t)perm[c] + axis], xi);
+        double d = __dsub_rn(pos[3 * (int64_t)(perm[c] / n_orb) + axis], xi);
         if (periodic) d = __dsub_rn(d, __dmul_rn(L, rint(__ddiv_rn(d, L))));
         vx[q] = (V)__ddiv_rn(__dmul_rn((double)val[q], d), kHbar);
     }
@@ -286,12 +286,13 @@ extern "C" tbk_status tb_build_velocity(const double *pos, const double box[3], 
     hipStream_t s = as_stream(stream);
     const SellView sv{h->ptr, h->col, log2_of(h->fmt == TBK_CSR_F64 ? 1 : h->slice)};
     const unsigned g = (unsigned)ceil_div(h->n_rows, kLsqtThreads);
+    const int32_t n_orb = h->n_orb >= 1 ? h->n_orb : 1;
     if (h->fmt == TBK_SELL_F32)
-        k_velocity<float><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const float *>(h->val), h->perm, pos,
+        k_velocity<float><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const float *>(h->val), h->perm, n_orb, pos,
                                                      h->n_rows, box[axis], periodic[axis], axis,
                                                      static_cast<float *>(vx));
     else
-        k_velocity<double><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const double *>(h->val), h->perm, pos,
+        k_velocity<double><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const double *>(h->val), h->perm, n_orb, pos,
                                                       h->n_rows, box[axis], periodic[axis], axis,
                                                       static_cast<double *>(vx));
     TBK_HIP(hipGetLastError());

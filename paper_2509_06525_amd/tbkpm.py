@@ -44,13 +44,14 @@ class HamStruct(ctypes.Structure):
                 ("ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("onsite", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("seg_rows", ctypes.c_void_p), ("uniform_hop", ctypes.c_int32), ("hop_value", ctypes.c_double),
-                ("col16", ctypes.c_void_p)]
+                ("col16", ctypes.c_void_p), ("n_orb", ctypes.c_int32)]
 
 
 _LIB = None
 ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_hamiltonian_size", "tb_build_hamiltonian",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
+               "tbk_hamiltonian_size_sk", "tb_build_hamiltonian_sk",
                "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
                "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
                "kpm_workspace_size_batched", "kpm_moments_batched",
@@ -60,6 +61,13 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned",
                "tb_build_velocity", "lsqt_chebyshev_terms", "lsqt_workspace_size", "lsqt_vac_moments",
                "lsqt_sigma")
+
+
+class SkParams(ctypes.Structure):
+    _fields_ = [("r_cut", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double),
+                ("e_s", ctypes.c_double), ("e_p", ctypes.c_double),
+                ("v_ss_sigma", ctypes.c_double), ("v_sp_sigma", ctypes.c_double),
+                ("v_pp_sigma", ctypes.c_double), ("v_pp_pi", ctypes.c_double), ("reorder", ctypes.c_int32)]
 
 
 class MlpModel(ctypes.Structure):
@@ -204,6 +212,13 @@ def lib():
                                    ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
     L.lsqt_sigma.restype = ctypes.c_int
     L.lsqt_sigma.argtypes = [vp, i32, i32, f64, f64, f64, i32, vp, i32, vp, vp]
+    L.tbk_hamiltonian_size_sk.restype = ctypes.c_int
+    L.tbk_hamiltonian_size_sk.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                          ctypes.POINTER(SkParams), ctypes.POINTER(HamStruct), vp]
+    L.tb_build_hamiltonian_sk.restype = ctypes.c_int
+    L.tb_build_hamiltonian_sk.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                          ctypes.POINTER(SkParams), ctypes.POINTER(HamStruct),
+                                          ctypes.POINTER(f64), vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
     L.kpm_dos_batched.restype = ctypes.c_int
@@ -332,6 +347,38 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
     _check(L.tb_build_hamiltonian(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(p),
                                   ctypes.byref(st), bounds, s))
     del keep
+    return Hamiltonian(st, t, (bounds[0], bounds[1]))
+
+
+def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi, e_s, e_p,
+                         r_cut=2.0, r0=1.42, beta=3.37, fmt="sell_f32", slice=256, reorder=True, stream=None):
+    """s, p Slater-Koster orbital Hamiltonian (4 rows per atom) on the GPU."""
+    L = lib()
+    pos = _dev(pos, torch.float64)
+    species = _dev(species, torch.int32)
+    n = pos.shape[0]
+    sk = SkParams(float(r_cut), float(r0), float(beta), float(e_s), float(e_p), float(v_ss_sigma),
+                  float(v_sp_sigma), float(v_pp_sigma), float(v_pp_pi), int(bool(reorder)))
+    boxa = _f64arr(box)
+    per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
+    s = _stream(stream)
+    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
+    _check(L.tbk_hamiltonian_size_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk), ctypes.byref(st), s))
+    dev = pos.device
+    vdt = torch.float32 if fmt == "sell_f32" else torch.float64
+    t = {
+        "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
+        "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),
+        "val": torch.empty(max(st.n_entries, 1), dtype=vdt, device=dev),
+        "onsite": torch.empty(st.n_rows, dtype=vdt, device=dev),
+        "perm": torch.empty(st.n_rows, dtype=torch.int32, device=dev),
+        "col16": torch.empty(max(st.n_entries, 1), dtype=torch.int16, device=dev),
+    }
+    st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
+    st.onsite, st.perm, st.col16 = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["col16"].data_ptr()
+    bounds = (ctypes.c_double * 2)()
+    _check(L.tb_build_hamiltonian_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk), ctypes.byref(st),
+                                     bounds, s))
     return Hamiltonian(st, t, (bounds[0], bounds[1]))
 
 
