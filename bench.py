@@ -298,6 +298,99 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
                          "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6}}
 
 
+def bench_sk(args, w):
+    """DOS step on the s, p Slater-Koster orbital Hamiltonian (4 rows per atom): build +
+    moments + DOS per step, the recurrence rated like the one-orbital workloads, the
+    doubling form as a variant, the oracle on a bounded sample as the CPU baseline."""
+    import torch
+    from paper_2509_06525_amd import synth, tbkpm
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    M, R = w["M"], w["R"]
+    log(f"generating {args.workload}")
+    s = synth.make_structure(args.workload)
+    N = s.n
+    pos = torch.from_numpy(s.pos).to(dev)
+    sp = torch.from_numpy(s.species).to(dev)
+    r = torch.from_numpy(synth.random_phase(4 * N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
+
+    def build(fmt="sell_f32", slice_=64):
+        return tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
+                                          r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice_,
+                                          stream=stream)
+
+    H = build()
+    a, b = H.scale()
+    cfg = tbkpm.default_config(H, R, "c32")
+    work = tbkpm.alloc_workspace(H, R, M, "c32", dev, cfg)
+    mu = torch.empty((R, M), dtype=torch.float64, device=dev)
+    E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    kpm_ms = []
+    del H
+
+    def step():
+        Hs = build()
+        aa, bb = Hs.scale()
+        ev[0].record(stream)
+        tbkpm.kpm_moments(Hs, aa, bb, r, M, "c32", work=work, mu=mu, stream=stream, config=cfg)
+        ev[1].record(stream)
+        rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream)
+        return Hs, aa, bb, rho
+
+    log(f"N={N} atoms, {4 * N} orbitals, M={M} R={R}: warmup {args.warmup}, timed {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Hs, aa, bb, rho = step()
+        torch.cuda.synchronize()
+        kpm_ms.append(ev[0].elapsed_time(ev[1]))
+    sec = (time.perf_counter() - t0) / args.steps
+    Rp = 1
+    while Rp < R:
+        Rp *= 2
+    diag = Hs.st.has_onsite or bb != 0.0
+    launch_bytes = cheb_step_bytes(Hs, Rp, 4, diag)
+    kmed = float(np.median(kpm_ms))
+    launch_s = kmed * 1e-3 / (M - 1)
+    achieved = launch_bytes / launch_s / 1e9
+    mu_c, rho_c = mu.cpu().numpy().copy(), rho.cpu().numpy()
+    nr = 4 * N
+    out = {
+        "metric": "KPM orbital*moments/s", "value": nr * M * R / sec, "unit": "orbital*moments/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": N, "n_orbitals": nr, "moments": M, "vectors": R,
+                   "format": "sell_f32", "slice": 64, "precision": "c32", "a_eV": aa, "b_eV": bb,
+                   "launch": cfg.as_dict()},
+        "kpm_ms_median": kmed,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_cheb_step",
+                     "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6},
+    }
+    if not args.no_doubling:
+        out["variants"] = {"doubling": kpm_variant(args, "doubling", {"doubling": 1}, Hs, aa, bb, r, M, R, Rp, 4,
+                                                   diag, "c32", cfg, mu_c, rho_c, E, stream, dev)}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (16.0 * M * R))))
+        ss = synth.graphene_sheet(cells, cells, w["sigma"], w["seed"])
+        rs = synth.random_phase(4 * ss.n, R, w["seed"] + synth.VECTOR_SEED_OFFSET)
+        t0 = time.perf_counter()
+        csr, _ = O.sk_hamiltonian(ss.pos, ss.box, ss.periodic, synth.SK_V, synth.SK_ES, synth.SK_EP)
+        lo, hi = O.gershgorin(csr)
+        sa, sb = 1.01 * (hi - lo) / 2, (hi + lo) / 2
+        mo, _ = O.kpm_moments(csr, sa, sb, rs, M)
+        O.kpm_dos(mo.mean(0), sa, sb, synth.energy_grid(sa, sb))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 4 * ss.n * M * R / dt, "unit": "orbital*moments/s", "cores": 1,
+                               "kind": "oracle", "seconds": dt,
+                               "sample": f"{cells}x{cells}-cell sheet, {4 * ss.n} orbitals, M={M}, R={R}: full path"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_vac(args, w):
     """Velocity-autocorrelation conductivity (Eq. (3)) on one structure: per step the
     Hamiltonian and velocity operator are built, the correlation moments of n_t
@@ -403,6 +496,8 @@ def main():
         return bench_snapshots(args, w)
     if w.get("vac"):
         return bench_vac(args, w)
+    if w.get("sk"):
+        return bench_sk(args, w)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()

@@ -154,12 +154,21 @@ WORKLOADS = {
                                    train_seed=4004),
     "graphene_pristine_100M": dict(kind="sheet", nx=5000, ny=5000, sigma=0.0, M=1000, R=1,
                                    fmt="sell_f32", precision="c32", seed=1004),
+    # s, p Slater-Koster orbital Hamiltonian (4 orbitals per atom: 4,000,000 rows)
+    "graphene_sp3_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=3000, R=16,
+                                    fmt="sell_f32", precision="c32", seed=1006, sk=True),
     # velocity autocorrelation: 200 propagation steps of 0.1 fs (20 fs of correlation time)
     "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
                                     fmt="sell_f32", precision="c32", seed=1005, vac=True,
                                     n_t=200, dt=0.1),
 }
 VECTOR_SEED_OFFSET = 1000   # vector seed = structure seed + 1000
+
+# Synthetic s, p Slater-Koster parameters of carbon (eV at R0): V_ss_sigma, V_sp_sigma,
+# V_pp_sigma, V_pp_pi, and onsite e_s, e_p.  Round stand-ins of the magnitudes of
+# published sp3 carbon sets, not a fit.
+SK_V = (-5.7, 5.4, 6.2, -2.7)
+SK_ES, SK_EP = -7.3, 0.0
 
 
 def make_structure(name):
