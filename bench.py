@@ -321,7 +321,20 @@ def bench_sk(args, w):
 
     H = build()
     a, b = H.scale()
-    cfg = tbkpm.default_config(H, R, "c32")
+    # launch shape: the tuner builds one-orbital Hamiltonians, so time a few shapes here
+    shapes = [tbkpm.make_config(v, t, nt, xr, 1) for v in (1, 2) for t in (1, 2, 4) for nt in (0, 1)
+              for xr in (0, 1)]
+    times = []
+    for c in shapes:
+        tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tbkpm.kpm_moments(H, a, b, r, 33, "c32", config=c, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    cfg = shapes[int(np.argmin(times))]
+    log(f"launch shape {cfg.as_dict()} ({min(times) / 32:.3f} ms/step of {len(shapes)} timed)")
     work = tbkpm.alloc_workspace(H, R, M, "c32", dev, cfg)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)

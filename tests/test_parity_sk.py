@@ -96,3 +96,18 @@ def test_sk_errors():
         tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *V, ES, EP,
                                    fmt="sell_f64", slice=3)
     assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("vpt,tpb,nt,xr", [(1, 1, 1, 0), (2, 2, 0, 1), (2, 4, 1, 1)])
+def test_sk_uniform_width_12_shapes(vpt, tpb, nt, xr):
+    """Pristine periodic sheet: every orbital row has 12 entries (the unrolled width-12 path)."""
+    s = synth.graphene_sheet(11, 10, 0.0, 1)
+    csr = oracle_csr(s)
+    H = build(s, "sell_f32", 64)
+    assert H.st.max_degree == 12 and H.st.n_entries == 12 * 4 * s.n
+    a, b = H.scale()
+    r = synth.random_phase(4 * s.n, 8, 3, np.complex64)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 200, "c32", config=tbkpm.make_config(vpt, tpb, nt, xr, 1))
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 200)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mu.cpu().numpy().mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
