@@ -27,7 +27,8 @@ def entries_in_atom_order(H, values=None):
     t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
     n = H.n_rows
     C = 1 if H.fmt == tbkpm.FORMATS["csr_f64"] else H.st.slice
-    ptr, col, val, perm = t["ptr"], t["col"], t["val"].astype(np.float64), t["perm"]
+    with np.errstate(invalid="ignore"):      # lanes past the last row of the last slice are never written
+        ptr, col, val, perm = t["ptr"], t["col"], t["val"].astype(np.float64), t["perm"]
     other = None if values is None else values.cpu().numpy().astype(np.float64)
     rows, cols, vals = [], [], []
     for s in range(ptr.shape[0] - 1):
