@@ -383,11 +383,6 @@ template <class VT> struct StepPtrs {
 // (the latency-bound case: 44-56 B per row); elsewhere it runs as 2.
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS, int W, bool DBL>
 void launch_step_d(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
-    if constexpr (W == 12) {   // one row per thread: twelve entries in flight already
-        k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 1, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
-            p.ptr, p.col, p.col16, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);
-        return;
-    }
     if constexpr (L == 1 && VPT == 1 && W == 3) {
         if (pl.cfg.rows_per_thread == 4) {
             k_cheb_step<VT, L, VPT, FIRST, DIAG, NT, TIS, 4, W, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(
@@ -409,13 +404,13 @@ void launch_step_w(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, cons
     else launch_step_d<VT, L, VPT, FIRST, DIAG, NT, TIS, W, false>(pl, s, p, a);
 }
 
-// Slices of one common width take a fully unrolled kernel: 3 (nearest-neighbour
-// honeycomb, one orbital) or 12 (the same with s, p orbitals: 3 neighbours x 4);
-// any other width pattern the general one.
+// Slices of one common width 3 (nearest-neighbour honeycomb) take a fully
+// unrolled kernel; any other width pattern the general one (batches of four
+// entries: an unrolled width-12 variant for s, p orbitals measured slower,
+// its registers cut the occupancy).
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool TIS>
 void launch_step_rpt(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
     if (pl.uniform_width == 3) launch_step_w<VT, L, VPT, FIRST, DIAG, NT, TIS, 3>(pl, s, p, a);
-    else if (pl.uniform_width == 12) launch_step_w<VT, L, VPT, FIRST, DIAG, NT, TIS, 12>(pl, s, p, a);
     else launch_step_w<VT, L, VPT, FIRST, DIAG, NT, TIS, 0>(pl, s, p, a);
 }
 
