@@ -60,8 +60,9 @@ def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True, compact=Fa
     compact-column form 2-byte column offsets (the few entries whose offset
     escapes 16 bits also read their 4-byte column; not counted)."""
     st = H.st
-    val_b = 4 if st.fmt == 2 else 8
-    b = st.n_entries * ((val_b if read_values else 0) + (2 if compact else 4)) + st.n_ptr * 8
+    val_b = 4 if st.fmt in (2, 4) else 8
+    per_value = 16 if st.fmt in (3, 4) else 1          # 4x4 blocks of the orbital formats
+    b = st.n_entries * ((per_value * val_b if read_values else 0) + (2 if compact else 4)) + st.n_ptr * 8
     # gather T_n once, read T_{n-1}, write T_{n+1} (+ read r in the direct form)
     b += st.n_rows * Rp * 2 * elem * (4 if read_r else 3)
     if diag and st.has_onsite:
@@ -314,27 +315,30 @@ def bench_sk(args, w):
     sp = torch.from_numpy(s.species).to(dev)
     r = torch.from_numpy(synth.random_phase(4 * N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
 
-    def build(fmt="sell_f32", slice_=64):
+    def build(fmt=w["fmt"], slice_=64):
         return tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
                                           r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice_,
                                           stream=stream)
 
+    def pick_shape(H, a, b):
+        # the tuner builds one-orbital Hamiltonians, so time a few shapes here
+        shapes = [tbkpm.make_config(v, t, nt, xr, 1) for v in (1, 2) for t in (1, 2, 4) for nt in (0, 1)
+                  for xr in (0, 1)]
+        times = []
+        for c in shapes:
+            tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            tbkpm.kpm_moments(H, a, b, r, 33, "c32", config=c, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return shapes[int(np.argmin(times))], min(times) / 32
+
     H = build()
     a, b = H.scale()
-    # launch shape: the tuner builds one-orbital Hamiltonians, so time a few shapes here
-    shapes = [tbkpm.make_config(v, t, nt, xr, 1) for v in (1, 2) for t in (1, 2, 4) for nt in (0, 1)
-              for xr in (0, 1)]
-    times = []
-    for c in shapes:
-        tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        tbkpm.kpm_moments(H, a, b, r, 33, "c32", config=c, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    cfg = shapes[int(np.argmin(times))]
-    log(f"launch shape {cfg.as_dict()} ({min(times) / 32:.3f} ms/step of {len(shapes)} timed)")
+    cfg, ms = pick_shape(H, a, b)
+    log(f"{w['fmt']}: launch shape {cfg.as_dict()} ({ms:.3f} ms/step)")
     work = tbkpm.alloc_workspace(H, R, M, "c32", dev, cfg)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
@@ -376,16 +380,36 @@ def bench_sk(args, w):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "n_orbitals": nr, "moments": M, "vectors": R,
-                   "format": "sell_f32", "slice": 64, "precision": "c32", "a_eV": aa, "b_eV": bb,
+                   "format": w["fmt"], "slice": 64, "precision": "c32", "a_eV": aa, "b_eV": bb,
                    "launch": cfg.as_dict()},
         "kpm_ms_median": kmed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_cheb_step",
                      "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6},
     }
+    # the same Hamiltonian as a scalar SELL matrix (12 columns and values per orbital row)
+    Hsc = build("sell_f32", 64)
+    cfg_s, _ = pick_shape(Hsc, aa, bb)
+    ws = tbkpm.alloc_workspace(Hsc, R, M, "c32", dev, cfg_s)
+    ms_s = []
+    for _ in range(max(1, args.steps)):
+        ev[0].record(stream)
+        tbkpm.kpm_moments(Hsc, aa, bb, r, M, "c32", work=ws, mu=mu, stream=stream, config=cfg_s)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms_s.append(ev[0].elapsed_time(ev[1]))
+    med_s = float(np.median(ms_s))
+    sb = cheb_step_bytes(Hsc, Rp, 4, diag)
+    out["variants"] = {"scalar_sell": {
+        "kpm_ms_median": med_s, "launch": cfg_s.as_dict(),
+        "max_abs_dmu_over_rows_vs_block": float(np.abs(mu.cpu().numpy() - mu_c).max() / nr),
+        "roofline": {"bound": "hbm", "achieved": sb / (med_s * 1e-3 / (M - 1)) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": sb / (med_s * 1e-3 / (M - 1)) / 1e9 / HBM_PEAK_GBS,
+                     "bytes_per_launch": sb, "kernel": "k_cheb_step (scalar SELL)"}}}
+    del Hsc, ws
     if not args.no_doubling:
-        out["variants"] = {"doubling": kpm_variant(args, "doubling", {"doubling": 1}, Hs, aa, bb, r, M, R, Rp, 4,
-                                                   diag, "c32", cfg, mu_c, rho_c, E, stream, dev)}
+        out["variants"]["doubling"] = kpm_variant(args, "doubling", {"doubling": 1}, Hs, aa, bb, r, M, R, Rp, 4,
+                                                  diag, "c32", cfg, mu_c, rho_c, E, stream, dev)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (16.0 * M * R))))

@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 4
+#define TBK_ABI_VERSION 5
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -64,7 +64,13 @@ int32_t tbk_abi_version(void);
 typedef enum {
     TBK_CSR_F64 = 0,   /* CSR, double values: entries of row i at [ptr[i], ptr[i+1]) */
     TBK_SELL_F64 = 1,  /* SELL, double values                                          */
-    TBK_SELL_F32 = 2   /* SELL, float values (for the complex-float recurrence)         */
+    TBK_SELL_F32 = 2,  /* SELL, float values (for the complex-float recurrence)         */
+    TBK_BSELL4_F64 = 3, /* block SELL over atoms, four orbitals per atom, double 4x4 blocks
+                           (tb_build_hamiltonian_sk only): ptr [n_slices+1] over atom
+                           slices of `slice` atoms; col [n_entries] neighbour atom row of
+                           each block (own row on padding); val [16 n_entries], block q
+                           row-major at 16 q (zero on padding); n_rows = 4 atoms      */
+    TBK_BSELL4_F32 = 4  /* the same with float blocks (complex-float recurrence)        */
 } tbk_format;
 
 /* Distance-scaled hopping model of Eq. (1):

@@ -29,20 +29,6 @@ namespace {
 constexpr int kReduceChunk = 2048;                 // partials per first-level reduction block
 constexpr size_t kPartialBudget = 256ull << 20;    // bytes of block partials kept between reductions
 
-// Per-launch scalars of a step (pointers go as separate restrict parameters).
-template <class VT> struct StepScalars {
-    int64_t n_rows;
-    int64_t n_tiles;
-    int32_t log2_slice;
-    int32_t Rp;              // padded vector count = L * VPT
-    int32_t tiles_per_block;
-    int32_t xcd_remap;
-    VT c1;                   // 2/a (1/a on the first step)
-    VT shift;                // b
-    VT hop;                  // the one off-diagonal value when `uniform`
-    int32_t uniform;         // 1: values are not read, every real entry is `hop`
-    int32_t compact;         // 1: columns from the 16-bit offsets (col where they escape)
-};
 
 // One recurrence step.  Each thread handles RPT rows (from RPT consecutive
 // tiles of its block).  All loads of a row group are issued before any is
@@ -365,19 +351,6 @@ int log2_exact(int x) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Pointers of one step launch.
-template <class VT> struct StepPtrs {
-    const int64_t *ptr;
-    const int32_t *col;
-    const int16_t *col16;
-    const VT *val;
-    const VT *onsite;
-    const VT *tcur;
-    const VT *tprev;
-    VT *tnext;
-    const VT *r;
-    double *partial;
-};
 
 // rows_per_thread 4 is instantiated for one vector per row on width-3 slices
 // (the latency-bound case: 44-56 B per row); elsewhere it runs as 2.
@@ -511,7 +484,12 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
             VT *old = (n & 1) ? TB : TA;
             sp.tcur = cur; sp.tprev = old; sp.tnext = old;
         }
-        launch_step<VT, L, VPT>(pl, n == 1, diag, s, sp, sa);
+        if (pl.block) {
+            tbk_status st = launch_step_block<VT>(pl, n == 1, diag, s, sp, sa);
+            if (st != TBK_OK) return st;
+        } else {
+            launch_step<VT, L, VPT>(pl, n == 1, diag, s, sp, sa);
+        }
     }
     reduce(batch0, Mr - batch0);
     TBK_HIP(hipGetLastError());
@@ -575,10 +553,15 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     TBK_CHECK(precision == TBK_PREC_F64 || precision == TBK_PREC_C32, TBK_ERR_INVALID_ARG,
               "unknown precision %d", precision);
     if (precision == TBK_PREC_F64)
-        TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64, TBK_ERR_INVALID_ARG,
+        TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_BSELL4_F64, TBK_ERR_INVALID_ARG,
                   "FP64 recurrence needs a double-valued Hamiltonian");
     else
-        TBK_CHECK(h->fmt == TBK_SELL_F32, TBK_ERR_INVALID_ARG, "C32 recurrence needs a float SELL Hamiltonian");
+        TBK_CHECK(h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32, TBK_ERR_INVALID_ARG,
+                  "C32 recurrence needs a float SELL Hamiltonian");
+    pl.block = h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32;
+    if (pl.block)
+        TBK_CHECK(h->n_orb == 4 && h->n_rows % 4 == 0, TBK_ERR_INVALID_ARG,
+                  "a block Hamiltonian has four orbital rows per atom");
     const int slice = h->fmt == TBK_CSR_F64 ? 1 : h->slice;
     pl.log2_slice = log2_exact(slice);
     TBK_CHECK(pl.log2_slice >= 0, TBK_ERR_INVALID_ARG, "slice %d is not a power of two", slice);
@@ -604,6 +587,8 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
               "compact_columns must be 0/1");
     TBK_CHECK(pl.cfg.compact_columns == 0 || h->col16 != nullptr, TBK_ERR_INVALID_ARG,
               "compact_columns needs the 16-bit column offsets h->col16");
+    TBK_CHECK(!pl.block || (pl.cfg.uniform_values == 0 && pl.cfg.compact_columns == 0), TBK_ERR_INVALID_ARG,
+              "uniform_values and compact_columns are not offered for block Hamiltonians");
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;
@@ -618,7 +603,7 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     pl.tile_is_slice = (slice == rpb);
     // every slice stores the same number of entries per row
     const int64_t n_slices = ceil_div(h->n_rows, slice);
-    pl.uniform_width = (h->max_degree > 0 && h->n_entries == n_slices * slice * (int64_t)h->max_degree)
+    pl.uniform_width = (!pl.block && h->max_degree > 0 && h->n_entries == n_slices * slice * (int64_t)h->max_degree)
                            ? h->max_degree : 0;
     pl.n_chunks = (int)ceil_div(G, kReduceChunk);
     TBK_CHECK(pl.n_chunks < 65536, TBK_ERR_UNSUPPORTED, "too many blocks");

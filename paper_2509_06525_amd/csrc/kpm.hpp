@@ -16,9 +16,46 @@ struct KpmPlan {
     int uniform_width = 0;      // > 0 when every slice stores this many entries per row
     size_t elem = 0, vec_bytes = 0;
     size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0, total = 0;
+    bool block = false;         // 4x4 block Hamiltonian (kpm_block.hip)
     bool seeded = false;        // start vectors generated on the device from `seed`
     uint64_t seed = 0;
 };
+
+// Per-launch scalars of a step (pointers go as separate restrict parameters).
+template <class VT> struct StepScalars {
+    int64_t n_rows;
+    int64_t n_tiles;
+    int32_t log2_slice;
+    int32_t Rp;              // padded vector count = L * VPT
+    int32_t tiles_per_block;
+    int32_t xcd_remap;
+    VT c1;                   // 2/a (1/a on the first step)
+    VT shift;                // b
+    VT hop;                  // the one off-diagonal value when `uniform`
+    int32_t uniform;         // 1: values are not read, every real entry is `hop`
+    int32_t compact;         // 1: columns from the 16-bit offsets (col where they escape)
+};
+
+// Pointers of one step launch.
+template <class VT> struct StepPtrs {
+    const int64_t *ptr;
+    const int32_t *col;
+    const int16_t *col16;
+    const VT *val;
+    const VT *onsite;
+    const VT *tcur;
+    const VT *tprev;
+    VT *tnext;
+    const VT *r;
+    double *partial;
+};
+
+// One recurrence step on a block Hamiltonian (four orbitals per atom, 4x4
+// blocks; kpm_block.hip): the same contract as the one-orbital step kernel,
+// rows = orbital rows, sa.n_rows = orbital rows, slices over atoms.
+template <class VT>
+tbk_status launch_step_block(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,
+                             const StepScalars<VT> &a);
 
 int pad_vectors(int R);
 tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision);

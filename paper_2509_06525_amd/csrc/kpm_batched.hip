@@ -352,6 +352,7 @@ tbk_status make_seg_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precisi
     tbk_status st = make_plan(h, R, M, precision, cfg, sp.base);
     if (st != TBK_OK) return st;
     TBK_CHECK(sp.base.cfg.doubling == 0, TBK_ERR_UNSUPPORTED, "the doubling identities are not offered for stacked structures");
+    TBK_CHECK(!sp.base.block, TBK_ERR_UNSUPPORTED, "block Hamiltonians are not offered for stacked structures");
     TBK_CHECK(sp.base.cfg.uniform_values == 0 && sp.base.cfg.compact_columns == 0, TBK_ERR_UNSUPPORTED,
               "uniform_values and compact_columns are not offered for stacked structures");
     sp.n_seg = h->n_seg;

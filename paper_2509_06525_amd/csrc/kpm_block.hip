@@ -1,0 +1,224 @@
+// Chebyshev recurrence step on a block Hamiltonian: four orbitals (s, px, py,
+// pz) per atom, one 4x4 block per bond (the Slater-Koster blocks of the
+// multi-orbital models), stored as a sliced ELL over atoms:
+//   ptr[s]            first block of atom slice s (slice = h->slice atoms),
+//   col[q]            neighbour atom row of block q (own row on padding),
+//   val[16 q + 4a+b]  <orbital a of the row atom| H |orbital b of col[q]>.
+// Vectors keep the one-orbital layout over orbital rows 4 i + a, [rows][R_pad].
+//
+// A thread owns one orbital row (4 i + a) and VPT vectors, like the
+// one-orbital kernel.  Per neighbour block it reads the block's column (shared
+// by the four rows of the atom: one address per atom in a wavefront), its row
+// a of four values (one 16 B or 32 B load), and the four orbital rows of the
+// neighbour's T_n, which are contiguous.  Against the scalar expansion of the
+// same matrix (12 columns and 12 values per orbital row) this reads a quarter
+// of the column bytes and issues a quarter of the column loads.
+#include "common.hpp"
+#include "kpm.hpp"
+#include "kpm_dev.hpp"
+
+namespace tbk {
+namespace {
+
+template <class VT> struct Row4;
+template <> struct Row4<float> { typedef f4v T; };
+template <> struct Row4<double> { typedef d2v T; };
+
+// Row a of a block: four values.
+template <bool NT, class VT>
+__device__ __forceinline__ void load_row4(const VT *p, VT (&h)[4]) {
+    if constexpr (sizeof(VT) == 4) {
+        const f4v v = ld<NT>(reinterpret_cast<const f4v *>(p));
+        h[0] = v.x; h[1] = v.y; h[2] = v.z; h[3] = v.w;
+    } else {
+        const d2v v0 = ld<NT>(reinterpret_cast<const d2v *>(p));
+        const d2v v1 = ld<NT>(reinterpret_cast<const d2v *>(p) + 1);
+        h[0] = v0.x; h[1] = v0.y; h[2] = v1.x; h[3] = v1.y;
+    }
+}
+
+// KB neighbour blocks are loaded before any is used (three: the honeycomb's
+// nearest neighbours in one batch); blocks past the atom's width are clamped
+// to its last block and weighted by zero.
+template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
+__global__ __launch_bounds__(kThreads) void k_cheb_step_blk(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
+    const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
+    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a) {
+    constexpr int RPB = kThreads / L;   // orbital rows per tile
+    constexpr int KB = 3;
+    const int lr = threadIdx.x / L;
+    const int vs = threadIdx.x % L;
+    const int64_t lb = logical_block(a.xcd_remap);
+    const int64_t t0 = lb * a.tiles_per_block;
+    const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
+    const int64_t smask = ((int64_t)1 << a.log2_slice) - 1;
+    const int64_t stride = smask + 1;
+    const int Rp = a.Rp;
+    const int voff = vs * VPT;
+    const int64_t last = a.n_rows - 1;
+
+    constexpr int NA = DBL ? 2 * VPT : VPT;
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t iu = t * RPB + lr;
+        const bool ok = iu <= last;
+        const int64_t i = min(iu, last);            // orbital row
+        const int64_t at = i >> 2;                   // atom row
+        const int orb = (int)(i & 3);
+        const int64_t off = 2 * (i * Rp + voff);
+        const int64_t sl = at >> a.log2_slice;
+        const int64_t p0 = ptr[sl], p1 = ptr[sl + 1];
+        const int64_t base = p0 + (at & smask);
+        const int w = (int)((p1 - p0) >> a.log2_slice);
+
+        Pack<VT, VPT> pv, rv;
+        VT dg = 0;
+        if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(tprev + off);
+        if constexpr (DBL) rv = load_pack<false, VT, VPT>(tcur + off);
+        else rv = load_pack<NT, VT, VPT>(r + off);
+        if constexpr (DIAG) dg = (onsite ? ld<NT>(onsite + i) : (VT)0) - a.shift;
+
+        Pack<VT, VPT> y;
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) { y.re[q] = 0; y.im[q] = 0; }
+        for (int k0 = 0; k0 < w; k0 += KB) {
+            int32_t c[KB];
+            VT h[KB][4];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int kk = min(k0 + k, w - 1);
+                const int64_t q = base + (int64_t)kk * stride;
+                c[k] = ld<NT>(bcol + q);
+                load_row4<NT, VT>(bval + 16 * q + 4 * orb, h[k]);
+                if (k0 + k >= w) { h[k][0] = 0; h[k][1] = 0; h[k][2] = 0; h[k][3] = 0; }
+            }
+            Pack<VT, VPT> x[KB][4];
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    x[k][b] = load_pack<false, VT, VPT>(tcur + 2 * ((4 * (int64_t)c[k] + b) * Rp + voff));
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) {
+                        y.re[q] += h[k][b] * x[k][b].re[q];
+                        y.im[q] += h[k][b] * x[k][b].im[q];
+                    }
+        }
+        if constexpr (DIAG) {
+            const Pack<VT, VPT> x = load_pack<false, VT, VPT>(tcur + off);
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) { y.re[q] += dg * x.re[q]; y.im[q] += dg * x.im[q]; }
+        }
+        Pack<VT, VPT> o;
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            if constexpr (FIRST) {
+                o.re[q] = a.c1 * y.re[q];
+                o.im[q] = a.c1 * y.im[q];
+            } else {
+                o.re[q] = a.c1 * y.re[q] - pv.re[q];
+                o.im[q] = a.c1 * y.im[q] - pv.im[q];
+            }
+        }
+        if (ok) {
+            store_pack<NT, VT, VPT>(tnext + off, o);
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {
+                const double cr = (double)rv.re[q] * (double)o.re[q] + (double)rv.im[q] * (double)o.im[q];
+                if constexpr (DBL) {
+                    acc[q] += (double)o.re[q] * (double)o.re[q] + (double)o.im[q] * (double)o.im[q];
+                    acc[VPT + q] += cr;
+                } else {
+                    acc[q] += cr;
+                }
+            }
+        }
+    }
+    block_reduce_store<L, NA>(acc, partial, lb);
+}
+
+template <class VT, int L, int VPT, bool FIRST, bool DIAG>
+void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
+    const unsigned G = (unsigned)pl.G;
+#define TBK_BLK(NT, DBL)                                                                                    \
+    k_cheb_step_blk<VT, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(p.ptr, p.col, p.val, p.onsite, \
+                                                                            p.tcur, p.tprev, p.tnext, p.r,  \
+                                                                            p.partial, a)
+    if (pl.cfg.nontemporal) {
+        if (pl.cfg.doubling) TBK_BLK(true, true);
+        else TBK_BLK(true, false);
+    } else {
+        if (pl.cfg.doubling) TBK_BLK(false, true);
+        else TBK_BLK(false, false);
+    }
+#undef TBK_BLK
+}
+
+template <class VT, int L, int VPT>
+void launch_lv(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,
+               const StepScalars<VT> &a) {
+    if (first) {
+        if (diag) launch_fd<VT, L, VPT, true, true>(pl, s, p, a);
+        else launch_fd<VT, L, VPT, true, false>(pl, s, p, a);
+    } else {
+        if (diag) launch_fd<VT, L, VPT, false, true>(pl, s, p, a);
+        else launch_fd<VT, L, VPT, false, false>(pl, s, p, a);
+    }
+}
+
+}  // namespace
+
+template <class VT>
+tbk_status launch_step_block(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,
+                             const StepScalars<VT> &a) {
+    if constexpr (sizeof(VT) == 8) {
+        switch (pl.L) {
+        case 1: launch_lv<VT, 1, 1>(pl, first, diag, s, p, a); break;
+        case 2: launch_lv<VT, 2, 1>(pl, first, diag, s, p, a); break;
+        case 4: launch_lv<VT, 4, 1>(pl, first, diag, s, p, a); break;
+        case 8: launch_lv<VT, 8, 1>(pl, first, diag, s, p, a); break;
+        case 16: launch_lv<VT, 16, 1>(pl, first, diag, s, p, a); break;
+        case 32: launch_lv<VT, 32, 1>(pl, first, diag, s, p, a); break;
+        case 64: launch_lv<VT, 64, 1>(pl, first, diag, s, p, a); break;
+        default: return fail(TBK_ERR_UNSUPPORTED, "no block kernel for L = %d", pl.L);
+        }
+    } else if (pl.VPT == 1) {
+        switch (pl.L) {
+        case 1: launch_lv<VT, 1, 1>(pl, first, diag, s, p, a); break;
+        case 2: launch_lv<VT, 2, 1>(pl, first, diag, s, p, a); break;
+        case 4: launch_lv<VT, 4, 1>(pl, first, diag, s, p, a); break;
+        case 8: launch_lv<VT, 8, 1>(pl, first, diag, s, p, a); break;
+        case 16: launch_lv<VT, 16, 1>(pl, first, diag, s, p, a); break;
+        case 32: launch_lv<VT, 32, 1>(pl, first, diag, s, p, a); break;
+        case 64: launch_lv<VT, 64, 1>(pl, first, diag, s, p, a); break;
+        default: return fail(TBK_ERR_UNSUPPORTED, "no block kernel for L = %d", pl.L);
+        }
+    } else {
+        switch (pl.L) {
+        case 1: launch_lv<VT, 1, 2>(pl, first, diag, s, p, a); break;
+        case 2: launch_lv<VT, 2, 2>(pl, first, diag, s, p, a); break;
+        case 4: launch_lv<VT, 4, 2>(pl, first, diag, s, p, a); break;
+        case 8: launch_lv<VT, 8, 2>(pl, first, diag, s, p, a); break;
+        case 16: launch_lv<VT, 16, 2>(pl, first, diag, s, p, a); break;
+        case 32: launch_lv<VT, 32, 2>(pl, first, diag, s, p, a); break;
+        default: return fail(TBK_ERR_UNSUPPORTED, "no block kernel for L = %d", pl.L);
+        }
+    }
+    TBK_HIP(hipGetLastError());
+    return TBK_OK;
+}
+
+template tbk_status launch_step_block<float>(const KpmPlan &, bool, bool, hipStream_t, const StepPtrs<float> &,
+                                             const StepScalars<float> &);
+template tbk_status launch_step_block<double>(const KpmPlan &, bool, bool, hipStream_t, const StepPtrs<double> &,
+                                              const StepScalars<double> &);
+
+}  // namespace tbk

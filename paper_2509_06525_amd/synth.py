@@ -156,7 +156,7 @@ WORKLOADS = {
                                    fmt="sell_f32", precision="c32", seed=1004),
     # s, p Slater-Koster orbital Hamiltonian (4 orbitals per atom: 4,000,000 rows)
     "graphene_sp3_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=3000, R=16,
-                                    fmt="sell_f32", precision="c32", seed=1006, sk=True),
+                                    fmt="bsell4_f32", precision="c32", seed=1006, sk=True),
     # velocity autocorrelation: 200 propagation steps of 0.1 fs (20 fs of correlation time)
     "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
                                     fmt="sell_f32", precision="c32", seed=1005, vac=True,

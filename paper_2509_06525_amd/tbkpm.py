@@ -17,7 +17,7 @@ TBK_OK = 0
 TBK_ERR_BUFFER_TOO_SMALL = 2
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BUFFER_TOO_SMALL", 3: "NOT_FINITE",
                 4: "SPECTRUM", 5: "UNSUPPORTED", 6: "DEVICE"}
-FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2}
+FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2, "bsell4_f64": 3, "bsell4_f32": 4}
 PRECISIONS = {"f64": 0, "c32": 1}
 
 
@@ -365,11 +365,12 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
     _check(L.tbk_hamiltonian_size_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk), ctypes.byref(st), s))
     dev = pos.device
-    vdt = torch.float32 if fmt == "sell_f32" else torch.float64
+    vdt = torch.float32 if fmt in ("sell_f32", "bsell4_f32") else torch.float64
+    per_entry = 16 if fmt.startswith("bsell4") else 1        # 4x4 blocks
     t = {
         "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
         "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),
-        "val": torch.empty(max(st.n_entries, 1), dtype=vdt, device=dev),
+        "val": torch.empty(max(per_entry * st.n_entries, 1), dtype=vdt, device=dev),
         "onsite": torch.empty(st.n_rows, dtype=vdt, device=dev),
         "perm": torch.empty(st.n_rows, dtype=torch.int32, device=dev),
         "col16": torch.empty(max(st.n_entries, 1), dtype=torch.int16, device=dev),

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_error_text_without_gpu(lib):
-    assert lib.tbk_abi_version() == 4
+    assert lib.tbk_abi_version() == 5
     assert lib.tbk_last_error() == b""
 
 

@@ -111,3 +111,91 @@ def test_sk_uniform_width_12_shapes(vpt, tpb, nt, xr):
     mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 200)
     E = synth.energy_grid(a, b)
     assert G.rel_l2(O.kpm_dos(mu.cpu().numpy().mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+
+
+def block_entries(H):
+    """(rows, cols, vals, onsite) in the caller's orbital order from a block Hamiltonian."""
+    t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
+    n_at = H.n_rows // 4
+    C = H.st.slice
+    ptr, col, perm = t["ptr"], t["col"], t["perm"]
+    val = t["val"].astype(np.float64).reshape(-1, 4, 4)
+    rows, cols, vals = [], [], []
+    for sl in range(ptr.shape[0] - 1):
+        w = (ptr[sl + 1] - ptr[sl]) // C
+        for lane in range(C):
+            r = sl * C + lane
+            if r >= n_at:
+                break
+            for k in range(w):
+                q = ptr[sl] + k * C + lane
+                c = col[q]
+                if c == r and not val[q].any():
+                    continue                     # padding block
+                for a in range(4):
+                    for b in range(4):
+                        rows.append(perm[4 * r + a]); cols.append(perm[4 * c + b]); vals.append(val[q, a, b])
+    onsite = np.empty(H.n_rows)
+    onsite[perm] = t["onsite"].astype(np.float64)
+    return np.array(rows), np.array(cols), np.array(vals), onsite
+
+
+@pytest.mark.parametrize("fmt,slice", [("bsell4_f64", 16), ("bsell4_f32", 32), ("bsell4_f64", 1)])
+def test_block_builder_matches_oracle(fmt, slice):
+    s = synth.graphene_sheet(9, 7, 0.08, 21)
+    H = build(s, fmt, slice)
+    assert H.st.n_rows == 4 * s.n and H.st.n_orb == 4 and H.st.max_degree == 3
+    csr = oracle_csr(s)
+    rows, cols, vals, onsite = block_entries(H)
+    orow, ocol, oval = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_array_equal(rows[o1], orow[o2])
+    np.testing.assert_array_equal(cols[o1], ocol[o2])
+    tol = 1e-6 if fmt.endswith("f32") else 2e-15
+    np.testing.assert_allclose(vals[o1], oval[o2], rtol=tol, atol=tol * np.abs(oval).max())
+    lo, hi = O.gershgorin(csr)
+    assert H.bounds[0] == pytest.approx(lo, rel=1e-12)
+    assert H.bounds[1] == pytest.approx(hi, rel=1e-12)
+
+
+@pytest.mark.parametrize("R,tpb,nt,xr,dbl", [(1, 1, 1, 0, 0), (3, 2, 0, 1, 0), (16, 2, 1, 0, 1), (64, 1, 1, 1, 0)])
+def test_block_fp64_moments(R, tpb, nt, xr, dbl):
+    s = synth.graphene_sheet(13, 11, 0.06, 4)        # 2288 orbital rows: ragged tiles
+    csr = oracle_csr(s)
+    H = build(s, "bsell4_f64", 32)
+    a, b = H.scale()
+    r = synth.random_phase(4 * s.n, R, 7)
+    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r, 61)
+    assert np.abs(mu - mo).max() <= 1e-10 * 4 * s.n
+
+
+@pytest.mark.parametrize("R,vpt", [(2, 2), (16, 2), (8, 1), (32, 2)])
+def test_block_c32_dos_and_scalar_agreement(R, vpt):
+    s = synth.graphene_sheet(12, 10, 0.05, 8)
+    csr = oracle_csr(s)
+    Hb = build(s, "bsell4_f32", 64)
+    Hs = build(s, "sell_f32", 64)
+    a, b = Hb.scale()
+    r = synth.random_phase(4 * s.n, R, 3, np.complex64)
+    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1)
+    mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
+    ms = tbkpm.kpm_moments(Hs, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 256)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mb.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+    assert np.abs(mb - ms).max() <= 1e-4 * 4 * s.n
+
+
+def test_block_rejections():
+    s = synth.graphene_sheet(5, 4, 0.03, 1)
+    H = build(s, "bsell4_f64", 8)
+    a, b = H.scale()
+    r = G.to_dev(synth.random_phase(4 * s.n, 1, 2))
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
+    assert e.value.name == "UNSUPPORTED"
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.kpm_moments(H, a, b, r, 16, "f64", config=tbkpm.make_config(1, 2, 1, 0, 1, uniform_values=1))
+    assert e.value.name == "INVALID_ARG"
