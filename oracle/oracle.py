@@ -73,7 +73,7 @@ def _lib():
     L.orc_vac_sigma.restype = ctypes.c_int
     L.orc_vac_sigma.argtypes = [_f64p, _i32, _i32, _f64, _f64, _f64, _i32, _f64p, _i32, _f64p]
     L.orc_assemble_sk.restype = ctypes.c_int
-    L.orc_assemble_sk.argtypes = [_i64, _f64p, _f64p, _i32p, _i64, _i32p, _i32p, _f64p, _f64, _f64, _f64, _f64,
+    L.orc_assemble_sk.argtypes = [_i64, _f64p, _f64p, _i32p, _i64, _i32p, _i32p, _i32, _f64p, _f64p, _f64, _f64,
                                   _i64p, _i32p, _f64p, _f64p]
     L.orc_splitmix64.restype = ctypes.c_uint64
     L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -292,22 +292,27 @@ def vac_sigma(nu, a, b, dt, E, kernel=0):
     return s
 
 
-def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None):
-    """s, p Slater-Koster orbital Hamiltonian (orbital 4 i + a, a = s, x, y, z) as a CSR of
-    size 4N; v = (V_ss_sigma, V_sp_sigma, V_pp_sigma, V_pp_pi) at r0.  Returns (csr, pairs)."""
+def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None, e_d=0.0):
+    """Slater-Koster orbital Hamiltonian as a CSR: v holds 4 integrals (s, p: orbital 4 i + a,
+    a = s, x, y, z) or 10 (s, p, d: orbital 9 i + a, then dxy, dyz, dzx, dx2-y2, d3z2-r2)
+    at r0.  Returns (csr, pairs)."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     if pairs is None:
         pairs = neighbor_pairs(pos, box, periodic, r_cut)
     pi, pj, _ = pairs
+    v = np.asarray(v, np.float64)
+    norb = 4 if v.size == 4 else 9
+    v10 = np.zeros(10)
+    v10[: v.size] = v
     n = pos.shape[0]
     npairs = pi.shape[0]
-    row_ptr = np.empty(4 * n + 1, np.int64)
-    col = np.empty(32 * npairs, np.int32)
-    val = np.empty(32 * npairs)
-    diag = np.empty(4 * n)
+    row_ptr = np.empty(norb * n + 1, np.int64)
+    col = np.empty(2 * norb * norb * npairs, np.int32)
+    val = np.empty(2 * norb * norb * npairs)
+    diag = np.empty(norb * n)
     rc = _lib().orc_assemble_sk(n, _c(pos, np.float64).reshape(-1), _c(box, np.float64), _c(periodic, np.int32),
-                                npairs, pi, pj, _c(v, np.float64), float(e_s), float(e_p), float(r0), float(beta),
-                                row_ptr, col, val, diag)
+                                npairs, pi, pj, norb, v10, np.array([e_s, e_p, e_d], np.float64), float(r0),
+                                float(beta), row_ptr, col, val, diag)
     if rc != 0:
         raise OracleError("orc_assemble_sk failed")
     return CSR(row_ptr, col, val, diag), pairs

@@ -10,7 +10,8 @@
  * counter-based random-phase generator the GPU can use instead of stored phases;
  * and the velocity-autocorrelation conductivity of Eq. (3) (velocity operator,
  * Chebyshev time evolution, correlation moments, running time integral); and
- * the s, p Slater-Koster orbital Hamiltonian of the multi-orbital models.
+ * the s, p (and s, p, d) Slater-Koster orbital Hamiltonian of the multi-orbital
+ * models.
  *
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
  * load this file.  It shares no code, header or constant generator with the HIP
@@ -747,64 +748,133 @@ int orc_vac_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Multi-orbital Slater-Koster Hamiltonian (s, px, py, pz per atom).          */
+/* Multi-orbital Slater-Koster Hamiltonian (s, p or s, p, d per atom).        */
 /* ------------------------------------------------------------------------- */
 
 /*
- * Two-centre block <a_i|H|b_j> of a bond with direction cosines c = (l, m, n)
- * (from atom i to atom j) and radial factor f, orbitals a, b in (s, x, y, z)
- * (Slater & Koster, Phys. Rev. 94, 1498 (1954), Table I, s and p rows):
- *   ss = V_ss_sigma,  s p_b = c_b V_sp_sigma,  p_a s = -c_a V_sp_sigma,
- *   p_a p_b = c_a c_b V_pp_sigma + (delta_ab - c_a c_b) V_pp_pi,
- * all times f.  v = {V_ss_sigma, V_sp_sigma, V_pp_sigma, V_pp_pi}.
+ * Two-centre block E[a][b] = <a_i|H|b_j> / f of a bond with direction cosines
+ * c = (l, m, n) from atom i to atom j, orbitals in the order
+ *   s, px, py, pz, dxy, dyz, dzx, dx2-y2, d3z2-r2
+ * (Slater & Koster, Phys. Rev. 94, 1498 (1954), Table I), from the ten
+ * integrals v = {ss_sigma, sp_sigma, pp_sigma, pp_pi, sd_sigma, pd_sigma,
+ * pd_pi, dd_sigma, dd_pi, dd_delta}.  The table gives the blocks with the
+ * lower angular momentum first; the others follow from Hermiticity and parity,
+ * E[b][a](c) = E[a][b](-c) = (-1)^(l_a + l_b) E[a][b](c).
  */
-static void orc_sk_block(const double c[3], double f, const double v[4], double B[4][4])
+static void orc_sk_table(const double c[3], const double v[10], double E[9][9])
 {
-    B[0][0] = f * v[0];
-    for (int b = 0; b < 3; ++b) {
-        B[0][b + 1] = f * c[b] * v[1];
-        B[b + 1][0] = -f * c[b] * v[1];
-    }
-    for (int a = 0; a < 3; ++a)
+    const double l = c[0], m = c[1], n = c[2], s3 = sqrt(3.0);
+    const double l2 = l * l, m2 = m * m, n2 = n * n;
+    const double ss = v[0], sp = v[1], pps = v[2], ppp = v[3], sd = v[4], pds = v[5], pdp = v[6];
+    const double dds = v[7], ddp = v[8], ddd = v[9];
+    double sdrow[5], pd[3][5], dd[5][5];
+    for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b) E[a][b] = 0.0;
+    /* s-s, s-p, p-p */
+    E[0][0] = ss;
+    for (int a = 0; a < 3; ++a) {
+        E[0][1 + a] = c[a] * sp;
         for (int b = 0; b < 3; ++b)
-            B[a + 1][b + 1] = f * (c[a] * c[b] * v[2] + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * v[3]);
+            E[1 + a][1 + b] = c[a] * c[b] * pps + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * ppp;
+    }
+    /* s-d */
+    sdrow[0] = s3 * l * m * sd;
+    sdrow[1] = s3 * m * n * sd;
+    sdrow[2] = s3 * n * l * sd;
+    sdrow[3] = 0.5 * s3 * (l2 - m2) * sd;
+    sdrow[4] = (n2 - 0.5 * (l2 + m2)) * sd;
+    /* p-d */
+    pd[0][0] = s3 * l2 * m * pds + m * (1.0 - 2.0 * l2) * pdp;
+    pd[0][1] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
+    pd[0][2] = s3 * l2 * n * pds + n * (1.0 - 2.0 * l2) * pdp;
+    pd[0][3] = 0.5 * s3 * l * (l2 - m2) * pds + l * (1.0 - l2 + m2) * pdp;
+    pd[0][4] = l * (n2 - 0.5 * (l2 + m2)) * pds - s3 * l * n2 * pdp;
+    pd[1][0] = s3 * m2 * l * pds + l * (1.0 - 2.0 * m2) * pdp;
+    pd[1][1] = s3 * m2 * n * pds + n * (1.0 - 2.0 * m2) * pdp;
+    pd[1][2] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
+    pd[1][3] = 0.5 * s3 * m * (l2 - m2) * pds - m * (1.0 + l2 - m2) * pdp;
+    pd[1][4] = m * (n2 - 0.5 * (l2 + m2)) * pds - s3 * m * n2 * pdp;
+    pd[2][0] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
+    pd[2][1] = s3 * n2 * m * pds + m * (1.0 - 2.0 * n2) * pdp;
+    pd[2][2] = s3 * n2 * l * pds + l * (1.0 - 2.0 * n2) * pdp;
+    pd[2][3] = 0.5 * s3 * n * (l2 - m2) * pds - n * (l2 - m2) * pdp;
+    pd[2][4] = n * (n2 - 0.5 * (l2 + m2)) * pds + s3 * n * (l2 + m2) * pdp;
+    /* d-d (symmetric in the two d orbitals) */
+    dd[0][0] = 3.0 * l2 * m2 * dds + (l2 + m2 - 4.0 * l2 * m2) * ddp + (n2 + l2 * m2) * ddd;
+    dd[1][1] = 3.0 * m2 * n2 * dds + (m2 + n2 - 4.0 * m2 * n2) * ddp + (l2 + m2 * n2) * ddd;
+    dd[2][2] = 3.0 * n2 * l2 * dds + (n2 + l2 - 4.0 * n2 * l2) * ddp + (m2 + n2 * l2) * ddd;
+    dd[0][1] = 3.0 * l * m2 * n * dds + l * n * (1.0 - 4.0 * m2) * ddp + l * n * (m2 - 1.0) * ddd;
+    dd[0][2] = 3.0 * l2 * m * n * dds + m * n * (1.0 - 4.0 * l2) * ddp + m * n * (l2 - 1.0) * ddd;
+    dd[1][2] = 3.0 * l * m * n2 * dds + l * m * (1.0 - 4.0 * n2) * ddp + l * m * (n2 - 1.0) * ddd;
+    dd[0][3] = 1.5 * l * m * (l2 - m2) * dds + 2.0 * l * m * (m2 - l2) * ddp + 0.5 * l * m * (l2 - m2) * ddd;
+    dd[1][3] = 1.5 * m * n * (l2 - m2) * dds - m * n * (1.0 + 2.0 * (l2 - m2)) * ddp
+             + m * n * (1.0 + 0.5 * (l2 - m2)) * ddd;
+    dd[2][3] = 1.5 * n * l * (l2 - m2) * dds + n * l * (1.0 - 2.0 * (l2 - m2)) * ddp
+             - n * l * (1.0 - 0.5 * (l2 - m2)) * ddd;
+    dd[0][4] = s3 * (l * m * (n2 - 0.5 * (l2 + m2)) * dds - 2.0 * l * m * n2 * ddp + 0.5 * l * m * (1.0 + n2) * ddd);
+    dd[1][4] = s3 * (m * n * (n2 - 0.5 * (l2 + m2)) * dds + m * n * (l2 + m2 - n2) * ddp
+                     - 0.5 * m * n * (l2 + m2) * ddd);
+    dd[2][4] = s3 * (l * n * (n2 - 0.5 * (l2 + m2)) * dds + l * n * (l2 + m2 - n2) * ddp
+                     - 0.5 * l * n * (l2 + m2) * ddd);
+    dd[3][3] = 0.75 * (l2 - m2) * (l2 - m2) * dds + (l2 + m2 - (l2 - m2) * (l2 - m2)) * ddp
+             + (n2 + 0.25 * (l2 - m2) * (l2 - m2)) * ddd;
+    dd[3][4] = s3 * (0.5 * (l2 - m2) * (n2 - 0.5 * (l2 + m2)) * dds + n2 * (m2 - l2) * ddp
+                     + 0.25 * (1.0 + n2) * (l2 - m2) * ddd);
+    dd[4][4] = (n2 - 0.5 * (l2 + m2)) * (n2 - 0.5 * (l2 + m2)) * dds + 3.0 * n2 * (l2 + m2) * ddp
+             + 0.75 * (l2 + m2) * (l2 + m2) * ddd;
+    for (int a = 0; a < 5; ++a) {
+        E[0][4 + a] = sdrow[a];
+        for (int b = 0; b < 3; ++b) E[1 + b][4 + a] = pd[b][a];
+        for (int b = a; b < 5; ++b) E[4 + a][4 + b] = dd[a][b];
+    }
+    /* lower blocks by parity: E[b][a] = (-1)^(l_a + l_b) E[a][b] */
+    static const int lq[9] = {0, 1, 1, 1, 2, 2, 2, 2, 2};
+    for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b)
+            if (lq[b] > lq[a] || (lq[b] == lq[a] && b > a))
+                E[b][a] = ((lq[a] + lq[b]) & 1) ? -E[a][b] : E[a][b];
 }
 
 /*
- * Orbital Hamiltonian of one species with s and p orbitals: orbital index
- * 4 i + a (a = s, x, y, z).  For every pair {i, j} of orc_neighbor_pairs the
- * bond vector d = x_j - x_i (minimum image), r = |d|, f = exp(-beta (r/r0 - 1))
- * give H[4i+a][4j+b] = B(d/r, f)[a][b] and H[4j+b][4i+a] = the same number
- * (B(-c) = B(c)^T, so H is symmetric).  Onsite diag(e_s, e_p, e_p, e_p).
- * CSR of the 4n x 4n off-diagonal part (row_ptr [4n+1], col/val [32 npairs],
- * columns ascending); diag [4n].  Returns 0, -2 when out of memory.
+ * Orbital Hamiltonian of one species with norb = 4 (s, p) or 9 (s, p, d)
+ * orbitals per atom: orbital index norb i + a.  For every pair {i, j} of
+ * orc_neighbor_pairs the bond vector d = x_j - x_i (minimum image), r = |d|,
+ * f = exp(-beta (r/r0 - 1)) give H[norb i + a][norb j + b] = f E(d/r)[a][b]
+ * and H[norb j + b][norb i + a] = the same number (E(-c) = E(c)^T).  v holds
+ * the ten integrals of orc_sk_table at r0 (only the first four enter when
+ * norb = 4); onsite e = {e_s, e_p, e_d}.  CSR of the off-diagonal part
+ * (row_ptr [norb n + 1], col/val [2 norb^2 npairs], columns ascending);
+ * diag [norb n].  Returns 0, -1 on a bad norb, -2 when out of memory.
  */
 int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int32_t periodic[3],
-                    int64_t npairs, const int32_t *pi, const int32_t *pj, const double v[4],
-                    double e_s, double e_p, double r0, double beta,
+                    int64_t npairs, const int32_t *pi, const int32_t *pj, int32_t norb, const double v[10],
+                    const double e[3], double r0, double beta,
                     int64_t *row_ptr, int32_t *col, double *val, double *diag)
 {
-    const int64_t nr = 4 * n;
+    if (norb != 4 && norb != 9) return -1;
+    const int64_t nr = norb * n;
     int64_t *deg = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
     if (!deg) return -2;
     for (int64_t p = 0; p < npairs; ++p) { deg[pi[p]]++; deg[pj[p]]++; }
     row_ptr[0] = 0;
-    for (int64_t r = 0; r < nr; ++r) row_ptr[r + 1] = row_ptr[r] + 4 * deg[r / 4];
+    for (int64_t r = 0; r < nr; ++r) row_ptr[r + 1] = row_ptr[r] + norb * deg[r / norb];
     int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nr > 0 ? nr : 1));
     if (!fill) { free(deg); return -2; }
     for (int64_t r = 0; r < nr; ++r) fill[r] = row_ptr[r];
     for (int64_t p = 0; p < npairs; ++p) {
         int32_t i = pi[p], j = pj[p];
-        double d[3], B[4][4], c[3];
+        double d[3], E[9][9], c[3];
         double r = orc_displacement(pos, i, j, box, periodic, d);
         for (int k = 0; k < 3; ++k) c[k] = d[k] / r;
-        orc_sk_block(c, exp(-beta * (r / r0 - 1.0)), v, B);
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) {
-                int64_t q = fill[4 * (int64_t)i + a]++;
-                col[q] = 4 * j + b; val[q] = B[a][b];
-                q = fill[4 * (int64_t)j + b]++;
-                col[q] = 4 * i + a; val[q] = B[a][b];
+        orc_sk_table(c, v, E);
+        double f = exp(-beta * (r / r0 - 1.0));
+        for (int a = 0; a < norb; ++a)
+            for (int b = 0; b < norb; ++b) {
+                double h = f * E[a][b];
+                int64_t q = fill[norb * (int64_t)i + a]++;
+                col[q] = norb * j + b; val[q] = h;
+                q = fill[norb * (int64_t)j + b]++;
+                col[q] = norb * i + a; val[q] = h;
             }
     }
     /* sort each row by column (values travel with their columns) */
@@ -816,7 +886,10 @@ int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int
             while (t >= row_ptr[r] && col[t] > cq) { col[t + 1] = col[t]; val[t + 1] = val[t]; --t; }
             col[t + 1] = cq; val[t + 1] = vq;
         }
-    for (int64_t r = 0; r < nr; ++r) diag[r] = (r % 4 == 0) ? e_s : e_p;
+    for (int64_t r = 0; r < nr; ++r) {
+        int a = (int)(r % norb);
+        diag[r] = a == 0 ? e[0] : (a < 4 ? e[1] : e[2]);
+    }
     free(deg); free(fill);
     return 0;
 }

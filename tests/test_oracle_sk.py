@@ -76,3 +76,76 @@ def test_orbital_velocity_is_commutator_with_atom_positions():
     H = csr.dense()
     X = np.diag(np.repeat(s.pos[:, 0], 4))
     np.testing.assert_allclose(Vd, 1j / O.HBAR_EV_FS * (H @ X - X @ H), atol=1e-12)
+
+
+# s, p, d: V_ss_s, V_sp_s, V_pp_s, V_pp_p, V_sd_s, V_pd_s, V_pd_p, V_dd_s, V_dd_p, V_dd_d
+V10 = np.array([-5.7, 5.4, 6.2, -2.7, -3.1, -2.4, 1.6, -1.9, 1.3, -0.4])
+ED = 4.0
+
+
+def d_harmonics(x):
+    """Real d orbitals of the Slater-Koster table at unit vectors x [k][3]."""
+    a, b, c = x[:, 0], x[:, 1], x[:, 2]
+    s3 = np.sqrt(3.0)
+    return np.stack([s3 * a * b, s3 * b * c, s3 * c * a, 0.5 * s3 * (a * a - b * b), c * c - 0.5 * (a * a + b * b)],
+                    axis=1)
+
+
+def d_rotation(Q):
+    """D2 with d(Q x) = D2 d(x) for every unit x (least squares over many directions)."""
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(400, 3))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    A, B = d_harmonics(x), d_harmonics(x @ Q.T)
+    D2T, *_ = np.linalg.lstsq(A, B, rcond=None)
+    assert np.abs(A @ D2T - B).max() < 1e-12          # the five functions span an invariant space
+    return D2T.T
+
+
+def test_spd_dimer_along_z():
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.42]])
+    csr, _ = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V10, ES, EP, e_d=ED)
+    H = csr.dense()[0:9, 9:18]
+    ss, sp, pps, ppp, sd, pds, pdp, dds, ddp, ddd = V10
+    want = np.zeros((9, 9))
+    want[0, 0], want[0, 3], want[0, 8] = ss, sp, sd
+    want[3, 0], want[8, 0] = -sp, sd
+    want[1, 1] = want[2, 2] = ppp
+    want[3, 3] = pps
+    want[3, 8], want[8, 3] = pds, -pds
+    want[1, 6], want[6, 1] = pdp, -pdp            # px - dzx
+    want[2, 5], want[5, 2] = pdp, -pdp            # py - dyz
+    want[8, 8] = dds
+    want[5, 5] = want[6, 6] = ddp
+    want[4, 4] = want[7, 7] = ddd
+    np.testing.assert_allclose(H, want, atol=1e-14)
+    np.testing.assert_allclose(np.diag(csr.dense())[:9], [ES, EP, EP, EP, ED, ED, ED, ED, ED])
+
+
+def test_spd_rotation_covariance():
+    s = synth.graphene_sheet(2, 2, 0.2, 6)
+    pos = s.pos - s.pos.mean(0)
+    Q = scipy.spatial.transform.Rotation.from_euler("zyx", [-0.3, 0.9, 2.1]).as_matrix()
+    h1, pairs = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V10, ES, EP, e_d=ED)
+    h2, _ = O.sk_hamiltonian(pos @ Q.T, np.zeros(3), OPEN, V10, ES, EP, e_d=ED, pairs=pairs)
+    D = np.zeros((9, 9))
+    D[0, 0] = 1.0
+    D[1:4, 1:4] = Q
+    D[4:9, 4:9] = d_rotation(Q)
+    Dn = np.kron(np.eye(s.n), D)
+    np.testing.assert_allclose(h2.dense(), Dn @ h1.dense() @ Dn.T, atol=1e-12)
+
+
+def test_spd_mirror_parity_and_sp_restriction():
+    s = synth.graphene_sheet(3, 4)                  # flat: z -> -z is a symmetry
+    h9, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED)
+    H = h9.dense()
+    odd = np.array([3, 5, 6])                       # pz, dyz, dzx
+    even = np.setdiff1d(np.arange(9), odd)
+    oi = (np.arange(s.n)[:, None] * 9 + odd).ravel()
+    ei = (np.arange(s.n)[:, None] * 9 + even).ravel()
+    assert np.abs(H[np.ix_(oi, ei)]).max() < 1e-14
+    np.testing.assert_array_equal(H, H.T)
+    h4, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10[:4], ES, EP)
+    sp = (np.arange(s.n)[:, None] * 9 + np.arange(4)).ravel()
+    np.testing.assert_allclose(H[np.ix_(sp, sp)], h4.dense(), atol=1e-15)
