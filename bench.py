@@ -61,7 +61,7 @@ def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True, compact=Fa
     escapes 16 bits also read their 4-byte column; not counted)."""
     st = H.st
     val_b = 4 if st.fmt in (2, 4) else 8
-    per_value = 16 if st.fmt in (3, 4) else 1          # 4x4 blocks of the orbital formats
+    per_value = st.n_orb * st.n_orb if st.fmt in (3, 4) else 1      # n_orb x n_orb blocks
     b = st.n_entries * ((per_value * val_b if read_values else 0) + (2 if compact else 4)) + st.n_ptr * 8
     # gather T_n once, read T_{n-1}, write T_{n+1} (+ read r in the direct form)
     b += st.n_rows * Rp * 2 * elem * (4 if read_r else 3)

@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 5
+#define TBK_ABI_VERSION 6
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -65,11 +65,12 @@ typedef enum {
     TBK_CSR_F64 = 0,   /* CSR, double values: entries of row i at [ptr[i], ptr[i+1]) */
     TBK_SELL_F64 = 1,  /* SELL, double values                                          */
     TBK_SELL_F32 = 2,  /* SELL, float values (for the complex-float recurrence)         */
-    TBK_BSELL4_F64 = 3, /* block SELL over atoms, four orbitals per atom, double 4x4 blocks
-                           (tb_build_hamiltonian_sk only): ptr [n_slices+1] over atom
-                           slices of `slice` atoms; col [n_entries] neighbour atom row of
-                           each block (own row on padding); val [16 n_entries], block q
-                           row-major at 16 q (zero on padding); n_rows = 4 atoms      */
+    TBK_BSELL4_F64 = 3, /* block SELL over atoms, n_orb = 4 or 9 orbitals per atom, double
+                           n_orb x n_orb blocks (tb_build_hamiltonian_sk only): ptr
+                           [n_slices+1] over atom slices of `slice` atoms; col [n_entries]
+                           neighbour atom row of each block (own row on padding); val
+                           [n_orb^2 n_entries], block q row-major at n_orb^2 q (zero on
+                           padding); n_rows = n_orb atoms                              */
     TBK_BSELL4_F32 = 4  /* the same with float blocks (complex-float recurrence)        */
 } tbk_format;
 
@@ -477,36 +478,44 @@ tbk_status kpm_dos_batched(const double *mu, int32_t M, int32_t n_struct, const 
                            double *rho, void *stream);
 
 /* ------------------------------------------------------------------------ */
-/* Multi-orbital Slater-Koster Hamiltonian (s, px, py, pz per atom)          */
+/* Multi-orbital Slater-Koster Hamiltonian (s, p or s, p, d per atom)        */
 /* ------------------------------------------------------------------------ */
 
 /* Two-centre parameters of one species (Sec. 3: Slater-Koster blocks formed
  * from bond directions; Slater & Koster, Phys. Rev. 94, 1498 (1954), Table I,
- * s and p rows).  Every integral is scaled by f(r) = exp(-beta (r/r0 - 1)) for
- * r < r_cut. */
+ * s, p and d rows).  Every integral is scaled by f(r) = exp(-beta (r/r0 - 1))
+ * for r < r_cut. */
 typedef struct {
     double r_cut, r0, beta;     /* cutoff and reference length (Angstrom), decay */
     double e_s, e_p;            /* onsite energies (eV)                            */
     double v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi;   /* at r0 (eV)          */
     int32_t reorder;            /* 1 = atom rows in cell-list order (as
                                    tbk_tb_params.reorder)                          */
+    int32_t orbitals;           /* 4 = s, px, py, pz; 9 = those and dxy, dyz, dzx,
+                                   dx2-y2, d3z2-r2                                 */
+    double e_d;                 /* d onsite energy (eV), orbitals = 9             */
+    double v_sd_sigma, v_pd_sigma, v_pd_pi;                /* at r0 (eV),          */
+    double v_dd_sigma, v_dd_pi, v_dd_delta;                /* orbitals = 9         */
 } tbk_sk_params;
 
 /*
- * Orbital Hamiltonian with s, px, py, pz on every atom: row 4 r + a (a = s, x,
- * y, z) for atom row r; for a bond with direction cosines c (from i to j,
- * minimum image) and f = f(r):
+ * Orbital Hamiltonian with N = sk->orbitals orbitals on every atom: row N r + a
+ * (a = s, x, y, z, then the five d for N = 9) for atom row r; for a bond with
+ * direction cosines c (from i to j, minimum image) and f = f(r):
  *   <s|s> = f V_ss_sigma, <s_i|p_j,b> = f c_b V_sp_sigma, <p_i,a|s_j> = -f c_a V_sp_sigma,
- *   <p_i,a|p_j,b> = f [c_a c_b V_pp_sigma + (delta_ab - c_a c_b) V_pp_pi];
- * onsite diag(e_s, e_p, e_p, e_p).  Stored as a SELL/CSR matrix of 4 n rows
- * (entry 4 q + b of an orbital row: q-th neighbour in cell-list order, its
- * orbital b; columns not sorted), so kpm_moments, kpm_dos and the VAC calls
- * take it as is.  perm[4 r + a] = 4 atom + a (the caller's orbital order);
- * n_orb = 4; spec_bounds: host double[2], row Gershgorin bounds.
+ *   <p_i,a|p_j,b> = f [c_a c_b V_pp_sigma + (delta_ab - c_a c_b) V_pp_pi],
+ * and with N = 9 the s-d, p-d and d-d entries of the same table (blocks with
+ * the lower angular momentum on the row side as tabulated, the others by
+ * <b_i|a_j> = (-1)^(l_a + l_b) <a_i|b_j>); onsite diag(e_s, e_p x3, e_d x5).
+ * Stored as a SELL/CSR matrix of N n rows (entry N q + b of an orbital row:
+ * q-th neighbour in cell-list order, its orbital b; columns not sorted), so
+ * kpm_moments, kpm_dos and the VAC calls take it as is, or in the block
+ * format (h->fmt = TBK_BSELL4_*).  perm[N r + a] = N atom + a (the caller's
+ * orbital order); n_orb = N; spec_bounds: host double[2], row Gershgorin bounds.
  *   species device int32 [n] (all 0: one species); other arguments as for
  *   tbk_hamiltonian_size / tb_build_hamiltonian.
- * Errors: as tb_build_hamiltonian; NOT_FINITE for a non-finite parameter.
- * Both calls synchronise `stream`.
+ * Errors: as tb_build_hamiltonian; NOT_FINITE for a non-finite parameter;
+ * INVALID_ARG for orbitals other than 4 and 9.  Both calls synchronise `stream`.
  */
 tbk_status tbk_hamiltonian_size_sk(const double *pos, const int32_t *species, int64_t n,
                                    const double box[3], const int32_t periodic[3],

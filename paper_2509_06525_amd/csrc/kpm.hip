@@ -559,9 +559,11 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
         TBK_CHECK(h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32, TBK_ERR_INVALID_ARG,
                   "C32 recurrence needs a float SELL Hamiltonian");
     pl.block = h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32;
-    if (pl.block)
-        TBK_CHECK(h->n_orb == 4 && h->n_rows % 4 == 0, TBK_ERR_INVALID_ARG,
-                  "a block Hamiltonian has four orbital rows per atom");
+    if (pl.block) {
+        TBK_CHECK((h->n_orb == 4 || h->n_orb == 9) && h->n_rows % h->n_orb == 0, TBK_ERR_INVALID_ARG,
+                  "a block Hamiltonian has 4 or 9 orbital rows per atom (n_orb = %d)", h->n_orb);
+        pl.norb = h->n_orb;
+    }
     const int slice = h->fmt == TBK_CSR_F64 ? 1 : h->slice;
     pl.log2_slice = log2_exact(slice);
     TBK_CHECK(pl.log2_slice >= 0, TBK_ERR_INVALID_ARG, "slice %d is not a power of two", slice);

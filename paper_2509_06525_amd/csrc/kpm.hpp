@@ -16,7 +16,8 @@ struct KpmPlan {
     int uniform_width = 0;      // > 0 when every slice stores this many entries per row
     size_t elem = 0, vec_bytes = 0;
     size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0, total = 0;
-    bool block = false;         // 4x4 block Hamiltonian (kpm_block.hip)
+    bool block = false;         // block Hamiltonian (kpm_block.hip)
+    int norb = 1;               // orbitals per atom of a block Hamiltonian (4 or 9)
     bool seeded = false;        // start vectors generated on the device from `seed`
     uint64_t seed = 0;
 };
@@ -50,8 +51,8 @@ template <class VT> struct StepPtrs {
     double *partial;
 };
 
-// One recurrence step on a block Hamiltonian (four orbitals per atom, 4x4
-// blocks; kpm_block.hip): the same contract as the one-orbital step kernel,
+// One recurrence step on a block Hamiltonian (pl.norb = 4 or 9 orbitals per
+// atom, norb x norb blocks; kpm_block.hip): the same contract as the one-orbital step kernel,
 // rows = orbital rows, sa.n_rows = orbital rows, slices over atoms.
 template <class VT>
 tbk_status launch_step_block(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,

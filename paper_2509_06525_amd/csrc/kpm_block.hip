@@ -1,18 +1,19 @@
-// Chebyshev recurrence step on a block Hamiltonian: four orbitals (s, px, py,
-// pz) per atom, one 4x4 block per bond (the Slater-Koster blocks of the
-// multi-orbital models), stored as a sliced ELL over atoms:
-//   ptr[s]            first block of atom slice s (slice = h->slice atoms),
-//   col[q]            neighbour atom row of block q (own row on padding),
-//   val[16 q + 4a+b]  <orbital a of the row atom| H |orbital b of col[q]>.
-// Vectors keep the one-orbital layout over orbital rows 4 i + a, [rows][R_pad].
+// Chebyshev recurrence step on a block Hamiltonian: NORB orbitals per atom
+// (4: s, px, py, pz; 9: s, p and the five d), one NORB x NORB block per bond
+// (the Slater-Koster blocks of the multi-orbital models), stored as a sliced
+// ELL over atoms:
+//   ptr[s]                      first block of atom slice s (slice = h->slice atoms),
+//   col[q]                      neighbour atom row of block q (own row on padding),
+//   val[NORB^2 q + NORB a + b]  <orbital a of the row atom| H |orbital b of col[q]>.
+// Vectors keep the one-orbital layout over orbital rows NORB i + a, [rows][R_pad].
 //
-// A thread owns one orbital row (4 i + a) and VPT vectors, like the
+// A thread owns one orbital row (NORB i + a) and VPT vectors, like the
 // one-orbital kernel.  Per neighbour block it reads the block's column (shared
-// by the four rows of the atom: one address per atom in a wavefront), its row
-// a of four values (one 16 B or 32 B load), and the four orbital rows of the
-// neighbour's T_n, which are contiguous.  Against the scalar expansion of the
-// same matrix (12 columns and 12 values per orbital row) this reads a quarter
-// of the column bytes and issues a quarter of the column loads.
+// by the NORB rows of the atom: one address per atom in a wavefront), its row
+// a of NORB values (one 16 B or 32 B load for NORB = 4), and the NORB orbital
+// rows of the neighbour's T_n, which are contiguous.  Against the scalar
+// expansion of the same matrix (NORB columns and NORB values per neighbour and
+// orbital row) this reads 1/NORB of the column bytes and column loads.
 #include "common.hpp"
 #include "kpm.hpp"
 #include "kpm_dev.hpp"
@@ -20,14 +21,14 @@
 namespace tbk {
 namespace {
 
-template <class VT> struct Row4;
-template <> struct Row4<float> { typedef f4v T; };
-template <> struct Row4<double> { typedef d2v T; };
-
-// Row a of a block: four values.
-template <bool NT, class VT>
-__device__ __forceinline__ void load_row4(const VT *p, VT (&h)[4]) {
-    if constexpr (sizeof(VT) == 4) {
+// Row a of a block: NORB values (vector loads for NORB = 4, whose rows are
+// 16 B or 32 B aligned; scalar loads for NORB = 9).
+template <int NORB, bool NT, class VT>
+__device__ __forceinline__ void load_row(const VT *p, VT (&h)[NORB]) {
+    if constexpr (NORB != 4) {
+#pragma unroll
+        for (int b = 0; b < NORB; ++b) h[b] = ld<NT>(p + b);
+    } else if constexpr (sizeof(VT) == 4) {
         const f4v v = ld<NT>(reinterpret_cast<const f4v *>(p));
         h[0] = v.x; h[1] = v.y; h[2] = v.z; h[3] = v.w;
     } else {
@@ -40,7 +41,7 @@ __device__ __forceinline__ void load_row4(const VT *p, VT (&h)[4]) {
 // KB neighbour blocks are loaded before any is used (three: the honeycomb's
 // nearest neighbours in one batch); blocks past the atom's width are clamped
 // to its last block and weighted by zero.
-template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
+template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_cheb_step_blk(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
     const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
@@ -67,8 +68,8 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_blk(
         const int64_t iu = t * RPB + lr;
         const bool ok = iu <= last;
         const int64_t i = min(iu, last);            // orbital row
-        const int64_t at = i >> 2;                   // atom row
-        const int orb = (int)(i & 3);
+        const int64_t at = i / NORB;                 // atom row
+        const int orb = (int)(i - at * NORB);
         const int64_t off = 2 * (i * Rp + voff);
         const int64_t sl = at >> a.log2_slice;
         const int64_t p0 = ptr[sl], p1 = ptr[sl + 1];
@@ -87,25 +88,28 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_blk(
         for (int q = 0; q < VPT; ++q) { y.re[q] = 0; y.im[q] = 0; }
         for (int k0 = 0; k0 < w; k0 += KB) {
             int32_t c[KB];
-            VT h[KB][4];
+            VT h[KB][NORB];
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
                 const int kk = min(k0 + k, w - 1);
                 const int64_t q = base + (int64_t)kk * stride;
                 c[k] = ld<NT>(bcol + q);
-                load_row4<NT, VT>(bval + 16 * q + 4 * orb, h[k]);
-                if (k0 + k >= w) { h[k][0] = 0; h[k][1] = 0; h[k][2] = 0; h[k][3] = 0; }
+                load_row<NORB, NT, VT>(bval + (int64_t)NORB * NORB * q + NORB * orb, h[k]);
+                if (k0 + k >= w) {
+#pragma unroll
+                    for (int b = 0; b < NORB; ++b) h[k][b] = 0;
+                }
             }
-            Pack<VT, VPT> x[KB][4];
+            Pack<VT, VPT> x[KB][NORB];
 #pragma unroll
             for (int k = 0; k < KB; ++k)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    x[k][b] = load_pack<false, VT, VPT>(tcur + 2 * ((4 * (int64_t)c[k] + b) * Rp + voff));
+                for (int b = 0; b < NORB; ++b)
+                    x[k][b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c[k] + b) * Rp + voff));
 #pragma unroll
             for (int k = 0; k < KB; ++k)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < NORB; ++b)
 #pragma unroll
                     for (int q = 0; q < VPT; ++q) {
                         y.re[q] += h[k][b] * x[k][b].re[q];
@@ -145,13 +149,12 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_blk(
     block_reduce_store<L, NA>(acc, partial, lb);
 }
 
-template <class VT, int L, int VPT, bool FIRST, bool DIAG>
+template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG>
 void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
     const unsigned G = (unsigned)pl.G;
 #define TBK_BLK(NT, DBL)                                                                                    \
-    k_cheb_step_blk<VT, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(p.ptr, p.col, p.val, p.onsite, \
-                                                                            p.tcur, p.tprev, p.tnext, p.r,  \
-                                                                            p.partial, a)
+    k_cheb_step_blk<VT, NORB, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(                         \
+        p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a)
     if (pl.cfg.nontemporal) {
         if (pl.cfg.doubling) TBK_BLK(true, true);
         else TBK_BLK(true, false);
@@ -162,16 +165,23 @@ void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const St
 #undef TBK_BLK
 }
 
+template <class VT, int NORB, int L, int VPT>
+void launch_fdv(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,
+                const StepScalars<VT> &a) {
+    if (first) {
+        if (diag) launch_fd<VT, NORB, L, VPT, true, true>(pl, s, p, a);
+        else launch_fd<VT, NORB, L, VPT, true, false>(pl, s, p, a);
+    } else {
+        if (diag) launch_fd<VT, NORB, L, VPT, false, true>(pl, s, p, a);
+        else launch_fd<VT, NORB, L, VPT, false, false>(pl, s, p, a);
+    }
+}
+
 template <class VT, int L, int VPT>
 void launch_lv(const KpmPlan &pl, bool first, bool diag, hipStream_t s, const StepPtrs<VT> &p,
                const StepScalars<VT> &a) {
-    if (first) {
-        if (diag) launch_fd<VT, L, VPT, true, true>(pl, s, p, a);
-        else launch_fd<VT, L, VPT, true, false>(pl, s, p, a);
-    } else {
-        if (diag) launch_fd<VT, L, VPT, false, true>(pl, s, p, a);
-        else launch_fd<VT, L, VPT, false, false>(pl, s, p, a);
-    }
+    if (pl.norb == 9) launch_fdv<VT, 9, L, VPT>(pl, first, diag, s, p, a);
+    else launch_fdv<VT, 4, L, VPT>(pl, first, diag, s, p, a);
 }
 
 }  // namespace

@@ -1,18 +1,17 @@
-// Multi-orbital Slater-Koster Hamiltonian (s, px, py, pz per atom) on the GPU.
+// Multi-orbital Slater-Koster Hamiltonian (s, p or s, p, d per atom) on the GPU.
 //
 // The paper's models attach several orbitals to each atom and form every
 // atom-pair block from two-centre integrals and the bond direction (the SK
-// conversion P_lambda(r_ij) of Sec. 3).  Here the s and p rows of the
-// Slater-Koster table (Phys. Rev. 94, 1498 (1954), Table I) with one radial
-// factor f(r) = exp(-beta (r/r0 - 1)) for every integral:
-//   <s_i|s_j> = f V_ss_sigma, <s_i|p_j,b> = f c_b V_sp_sigma, <p_i,a|s_j> = -f c_a V_sp_sigma,
-//   <p_i,a|p_j,b> = f [c_a c_b V_pp_sigma + (delta_ab - c_a c_b) V_pp_pi],
-// c = bond direction cosines from i to j (minimum image).
+// conversion P_lambda(r_ij) of Sec. 3).  Here the Slater-Koster table (Phys.
+// Rev. 94, 1498 (1954), Table I) for s, p and d orbitals with one radial factor
+// f(r) = exp(-beta (r/r0 - 1)) for every integral; c = bond direction cosines
+// from i to j (minimum image); orbitals s, px, py, pz (and dxy, dyz, dzx,
+// dx2-y2, d3z2-r2).
 //
-// The orbital Hamiltonian (row 4 r + a for atom row r, orbital a = s, x, y, z)
+// The orbital Hamiltonian (row NORB r + a for atom row r, NORB = 4 or 9)
 // is stored either as an ordinary SELL matrix with 4 N rows (the recurrence,
 // the DOS and the VAC path run on it unchanged) or as a block SELL over atoms
-// with one 4x4 block per bond (a quarter of the column traffic; the block
+// with one NORB x NORB block per bond (one column per block; the block
 // recurrence kernel in kpm_block.hip).  The neighbour search, the atom row
 // order and the atom degrees come from the one-orbital builder's plan.
 #include <hipcub/hipcub.hpp>
@@ -26,48 +25,109 @@
 namespace tbk {
 namespace {
 
-// entries[s] = C * max over the orbital rows of slice s of 4 * deg(atom row).
-__global__ void k_sk_width(int64_t n_orb_rows, int32_t slice, int64_t n_slices, const int32_t *__restrict__ deg,
-                           int64_t *__restrict__ entries) {
+// entries[s] = C * max over the orbital rows of slice s of norb * deg(atom row).
+__global__ void k_sk_width(int64_t n_orb_rows, int32_t norb, int32_t slice, int64_t n_slices,
+                           const int32_t *__restrict__ deg, int64_t *__restrict__ entries) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n_slices) return;
     int32_t w = 0;
     const int64_t r1 = min((s + 1) * (int64_t)slice, n_orb_rows);
-    for (int64_t R = s * (int64_t)slice; R < r1; ++R) w = max(w, 4 * deg[R >> 2]);
+    for (int64_t R = s * (int64_t)slice; R < r1; ++R) w = max(w, norb * deg[R / norb]);
     entries[s] = (int64_t)slice * w;
 }
 
-// perm_orb[4 r + a] = 4 perm[r] + a
-__global__ void k_sk_perm(int64_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ perm_orb) {
+// perm_orb[norb r + a] = norb perm[r] + a
+__global__ void k_sk_perm(int64_t n, int32_t norb, const int32_t *__restrict__ perm,
+                          int32_t *__restrict__ perm_orb) {
     const int64_t R = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (R >= 4 * n) return;
-    perm_orb[R] = 4 * perm[R >> 2] + (int32_t)(R & 3);
+    if (R >= norb * n) return;
+    perm_orb[R] = norb * perm[R / norb] + (int32_t)(R % norb);
 }
 
 struct SkValues {
-    double r0, beta, e_s, e_p;
-    double v[4];   // V_ss_sigma, V_sp_sigma, V_pp_sigma, V_pp_pi at r0
+    double r0, beta, e_s, e_p, e_d;
+    // at r0: ss_sigma, sp_sigma, pp_sigma, pp_pi, sd_sigma, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta
+    double v[10];
 };
 
-// The 4x4 block of a bond of length r and vector (dx, dy, dz) from the row atom.
-__device__ __forceinline__ void sk_block(const SkValues &sk, double r, double dx, double dy, double dz,
-                                         double (&B)[4][4]) {
-    const double c[3] = {dx / r, dy / r, dz / r};
-    const double f = exp(-sk.beta * (r / sk.r0 - 1.0));
-    B[0][0] = f * sk.v[0];
-    for (int b = 0; b < 3; ++b) {
-        B[0][b + 1] = f * c[b] * sk.v[1];
-        B[b + 1][0] = -f * c[b] * sk.v[1];
+// The Slater-Koster table: E[a][b] = <a_i|H|b_j> / f for direction cosines
+// (l, m, n) from i to j; rows with the lower angular momentum first, the other
+// blocks from E[b][a] = (-1)^(l_a + l_b) E[a][b].  Only the first NORB rows and
+// columns are formed.
+template <int NORB>
+__device__ __forceinline__ void sk_table(const double *v, double l, double m, double n, double (&E)[NORB][NORB]) {
+    const double s3 = 1.7320508075688772;
+    const double l2 = l * l, m2 = m * m, n2 = n * n;
+    const double c[3] = {l, m, n};
+    E[0][0] = v[0];
+    for (int a = 0; a < 3; ++a) {
+        E[0][1 + a] = c[a] * v[1];
+        E[1 + a][0] = -c[a] * v[1];
+        for (int b = 0; b < 3; ++b) E[1 + a][1 + b] = c[a] * c[b] * v[2] + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * v[3];
     }
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            B[a + 1][b + 1] = f * (c[a] * c[b] * sk.v[2] + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * sk.v[3]);
+    if constexpr (NORB == 9) {
+        const double sd = v[4], pds = v[5], pdp = v[6], dds = v[7], ddp = v[8], ddd = v[9];
+        const double q = n2 - 0.5 * (l2 + m2), dlm = l2 - m2;
+        const double sdr[5] = {s3 * l * m * sd, s3 * m * n * sd, s3 * n * l * sd, 0.5 * s3 * dlm * sd, q * sd};
+        const double pd[3][5] = {
+            {s3 * l2 * m * pds + m * (1.0 - 2.0 * l2) * pdp, s3 * l * m * n * pds - 2.0 * l * m * n * pdp,
+             s3 * l2 * n * pds + n * (1.0 - 2.0 * l2) * pdp, 0.5 * s3 * l * dlm * pds + l * (1.0 - dlm) * pdp,
+             l * q * pds - s3 * l * n2 * pdp},
+            {s3 * m2 * l * pds + l * (1.0 - 2.0 * m2) * pdp, s3 * m2 * n * pds + n * (1.0 - 2.0 * m2) * pdp,
+             s3 * l * m * n * pds - 2.0 * l * m * n * pdp, 0.5 * s3 * m * dlm * pds - m * (1.0 + dlm) * pdp,
+             m * q * pds - s3 * m * n2 * pdp},
+            {s3 * l * m * n * pds - 2.0 * l * m * n * pdp, s3 * n2 * m * pds + m * (1.0 - 2.0 * n2) * pdp,
+             s3 * n2 * l * pds + l * (1.0 - 2.0 * n2) * pdp, 0.5 * s3 * n * dlm * pds - n * dlm * pdp,
+             n * q * pds + s3 * n * (l2 + m2) * pdp}};
+        double dd[5][5];
+        dd[0][0] = 3.0 * l2 * m2 * dds + (l2 + m2 - 4.0 * l2 * m2) * ddp + (n2 + l2 * m2) * ddd;
+        dd[1][1] = 3.0 * m2 * n2 * dds + (m2 + n2 - 4.0 * m2 * n2) * ddp + (l2 + m2 * n2) * ddd;
+        dd[2][2] = 3.0 * n2 * l2 * dds + (n2 + l2 - 4.0 * n2 * l2) * ddp + (m2 + n2 * l2) * ddd;
+        dd[0][1] = 3.0 * l * m2 * n * dds + l * n * (1.0 - 4.0 * m2) * ddp + l * n * (m2 - 1.0) * ddd;
+        dd[0][2] = 3.0 * l2 * m * n * dds + m * n * (1.0 - 4.0 * l2) * ddp + m * n * (l2 - 1.0) * ddd;
+        dd[1][2] = 3.0 * l * m * n2 * dds + l * m * (1.0 - 4.0 * n2) * ddp + l * m * (n2 - 1.0) * ddd;
+        dd[0][3] = 1.5 * l * m * dlm * dds - 2.0 * l * m * dlm * ddp + 0.5 * l * m * dlm * ddd;
+        dd[1][3] = 1.5 * m * n * dlm * dds - m * n * (1.0 + 2.0 * dlm) * ddp + m * n * (1.0 + 0.5 * dlm) * ddd;
+        dd[2][3] = 1.5 * n * l * dlm * dds + n * l * (1.0 - 2.0 * dlm) * ddp - n * l * (1.0 - 0.5 * dlm) * ddd;
+        dd[0][4] = s3 * (l * m * q * dds - 2.0 * l * m * n2 * ddp + 0.5 * l * m * (1.0 + n2) * ddd);
+        dd[1][4] = s3 * (m * n * q * dds + m * n * (l2 + m2 - n2) * ddp - 0.5 * m * n * (l2 + m2) * ddd);
+        dd[2][4] = s3 * (l * n * q * dds + l * n * (l2 + m2 - n2) * ddp - 0.5 * l * n * (l2 + m2) * ddd);
+        dd[3][3] = 0.75 * dlm * dlm * dds + (l2 + m2 - dlm * dlm) * ddp + (n2 + 0.25 * dlm * dlm) * ddd;
+        dd[3][4] = s3 * (0.5 * dlm * q * dds - n2 * dlm * ddp + 0.25 * (1.0 + n2) * dlm * ddd);
+        dd[4][4] = q * q * dds + 3.0 * n2 * (l2 + m2) * ddp + 0.75 * (l2 + m2) * (l2 + m2) * ddd;
+        for (int a = 0; a < 5; ++a) {
+            E[0][4 + a] = sdr[a];
+            E[4 + a][0] = sdr[a];                      // d-s: even
+            for (int b = 0; b < 3; ++b) {
+                E[1 + b][4 + a] = pd[b][a];
+                E[4 + a][1 + b] = -pd[b][a];           // d-p: odd
+            }
+            for (int b = a; b < 5; ++b) {
+                E[4 + a][4 + b] = dd[a][b];
+                E[4 + b][4 + a] = dd[a][b];
+            }
+        }
+    }
 }
 
-// One atom row r per thread: its four orbital rows, entry 4 q + b for the q-th
-// neighbour (cell-list order) and its orbital b; padding (own row, value 0)
-// up to the slice width; onsite; row Gershgorin bounds; 16-bit offsets.
-template <class V>
+// The NORB x NORB block of a bond of length r and vector (dx, dy, dz) from the row atom.
+template <int NORB>
+__device__ __forceinline__ void sk_block(const SkValues &sk, double r, double dx, double dy, double dz,
+                                         double (&B)[NORB][NORB]) {
+    sk_table<NORB>(sk.v, dx / r, dy / r, dz / r, B);
+    const double f = exp(-sk.beta * (r / sk.r0 - 1.0));
+    for (int a = 0; a < NORB; ++a)
+        for (int b = 0; b < NORB; ++b) B[a][b] *= f;
+}
+
+__device__ __forceinline__ double sk_onsite(const SkValues &sk, int a) {
+    return a == 0 ? sk.e_s : (a < 4 ? sk.e_p : sk.e_d);
+}
+
+// One atom row r per thread: its NORB orbital rows, entry NORB q + b for the
+// q-th neighbour (cell-list order) and its orbital b; padding (own row, value
+// 0) up to the slice width; onsite; row Gershgorin bounds; 16-bit offsets.
+template <class V, int NORB>
 __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n, int32_t slice,
                           int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                           const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
@@ -76,24 +136,25 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     if (r < n) {
-        int64_t base[4];
-        int32_t w[4];
-        for (int a = 0; a < 4; ++a) {
-            const int64_t R = 4 * r + a;
+        int64_t base[NORB];
+        int32_t w[NORB];
+        for (int a = 0; a < NORB; ++a) {
+            const int64_t R = NORB * r + a;
             const int64_t sl = R >> log2_slice;
             base[a] = ptr[sl] + (R & (slice - 1));
             w[a] = (int32_t)((ptr[sl + 1] - ptr[sl]) >> log2_slice);
         }
         const int32_t i = perm[r];
-        double asum[4] = {0.0, 0.0, 0.0, 0.0};
+        double asum[NORB];
+        for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[4][4];
-            sk_block(sk, rij, dx, dy, dz, B);
-            const int32_t cj = 4 * iperm[j];
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) {
-                    const int32_t k = 4 * q + b;
+            double B[NORB][NORB];
+            sk_block<NORB>(sk, rij, dx, dy, dz, B);
+            const int32_t cj = NORB * iperm[j];
+            for (int a = 0; a < NORB; ++a)
+                for (int b = 0; b < NORB; ++b) {
+                    const int32_t k = NORB * q + b;
                     if (k < w[a]) {
                         col[base[a] + (int64_t)k * slice] = cj + b;
                         val[base[a] + (int64_t)k * slice] = (V)B[a][b];
@@ -102,9 +163,9 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
                 }
             ++q;
         });
-        for (int a = 0; a < 4; ++a) {
-            const int64_t R = 4 * r + a;
-            for (int32_t k = 4 * q; k < w[a]; ++k) {
+        for (int a = 0; a < NORB; ++a) {
+            const int64_t R = NORB * r + a;
+            for (int32_t k = NORB * q; k < w[a]; ++k) {
                 col[base[a] + (int64_t)k * slice] = (int32_t)R;
                 val[base[a] + (int64_t)k * slice] = (V)0;
             }
@@ -114,7 +175,7 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
                     col16[base[a] + (int64_t)k * slice] =
                         (d >= -32767 && d <= 32767) ? (int16_t)d : (int16_t)-32768;
                 }
-            const double e = a == 0 ? sk.e_s : sk.e_p;
+            const double e = sk_onsite(sk, a);
             onsite[R] = (V)e;
             lo = fmin(lo, e - asum[a]);
             hi = fmax(hi, e + asum[a]);
@@ -124,14 +185,15 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
 }
 
 // Block form: one atom row r per thread; block q (q-th neighbour, cell-list
-// order) at slot base + q C of the atom slice, its 16 values row-major at
-// 16 (base + q C); padding blocks (own row, zero) up to the slice width.
-template <class V>
+// order) at slot base + q C of the atom slice, its NORB^2 values row-major at
+// NORB^2 (base + q C); padding blocks (own row, zero) up to the slice width.
+template <class V, int NORB>
 __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64_t n, int32_t slice,
                               int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                               const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                               int32_t *__restrict__ bcol, V *__restrict__ bval, V *__restrict__ onsite,
                               int64_t *__restrict__ bound_keys) {
+    constexpr int NB = NORB * NORB;
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     if (r < n) {
@@ -139,29 +201,30 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
         const int64_t base = ptr[sl] + (r & (slice - 1));
         const int32_t w = (int32_t)((ptr[sl + 1] - ptr[sl]) >> log2_slice);
         const int32_t i = perm[r];
-        double asum[4] = {0.0, 0.0, 0.0, 0.0};
+        double asum[NORB];
+        for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[4][4];
-            sk_block(sk, rij, dx, dy, dz, B);
+            double B[NORB][NORB];
+            sk_block<NORB>(sk, rij, dx, dy, dz, B);
             if (q < w) {
                 const int64_t slot = base + (int64_t)q * slice;
                 bcol[slot] = iperm[j];
-                for (int a = 0; a < 4; ++a)
-                    for (int b = 0; b < 4; ++b) bval[16 * slot + 4 * a + b] = (V)B[a][b];
+                for (int a = 0; a < NORB; ++a)
+                    for (int b = 0; b < NORB; ++b) bval[NB * slot + NORB * a + b] = (V)B[a][b];
             }
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) asum[a] += fabs(B[a][b]);
+            for (int a = 0; a < NORB; ++a)
+                for (int b = 0; b < NORB; ++b) asum[a] += fabs(B[a][b]);
             ++q;
         });
         for (int32_t k = q; k < w; ++k) {
             const int64_t slot = base + (int64_t)k * slice;
             bcol[slot] = (int32_t)r;
-            for (int e = 0; e < 16; ++e) bval[16 * slot + e] = (V)0;
+            for (int e = 0; e < NB; ++e) bval[NB * slot + e] = (V)0;
         }
-        for (int a = 0; a < 4; ++a) {
-            const double e = a == 0 ? sk.e_s : sk.e_p;
-            onsite[4 * r + a] = (V)e;
+        for (int a = 0; a < NORB; ++a) {
+            const double e = sk_onsite(sk, a);
+            onsite[NORB * r + a] = (V)e;
             lo = fmin(lo, e - asum[a]);
             hi = fmax(hi, e + asum[a]);
         }
@@ -173,8 +236,11 @@ bool is_block(int32_t fmt) { return fmt == TBK_BSELL4_F64 || fmt == TBK_BSELL4_F
 
 tbk_status check_sk(const tbk_sk_params *sk) {
     TBK_CHECK(sk != nullptr, TBK_ERR_INVALID_ARG, "sk params are NULL");
-    const double x[9] = {sk->r_cut, sk->r0, sk->beta, sk->e_s, sk->e_p,
-                         sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi};
+    TBK_CHECK(sk->orbitals == 4 || sk->orbitals == 9, TBK_ERR_INVALID_ARG,
+              "orbitals = %d (4 = s, p; 9 = s, p, d)", sk->orbitals);
+    const double x[16] = {sk->r_cut, sk->r0, sk->beta, sk->e_s, sk->e_p, sk->e_d,
+                          sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi, sk->v_sd_sigma,
+                          sk->v_pd_sigma, sk->v_pd_pi, sk->v_dd_sigma, sk->v_dd_pi, sk->v_dd_delta};
     for (double v : x) TBK_CHECK(std::isfinite(v), TBK_ERR_NOT_FINITE, "an SK parameter is not finite");
     return TBK_OK;
 }
@@ -186,8 +252,8 @@ tbk_status atom_plan(const double *pos, const int32_t *species, int64_t n, const
     tbk_status st = check_sk(sk);
     if (st != TBK_OK) return st;
     TBK_CHECK(box != nullptr, TBK_ERR_INVALID_ARG, "box is NULL");
-    TBK_CHECK(n >= 1 && 4 * n < (int64_t)INT32_MAX, TBK_ERR_INVALID_ARG, "4 n = %lld orbital rows out of range",
-              (long long)(4 * n));
+    TBK_CHECK(n >= 1 && sk->orbitals * n < (int64_t)INT32_MAX, TBK_ERR_INVALID_ARG,
+              "%lld orbital rows out of range", (long long)(sk->orbitals * n));
     const double onsite0 = 0.0, t0 = 1.0;
     tbk_tb_params p{};
     p.r_cut = sk->r_cut;
@@ -207,14 +273,14 @@ struct SkLayout {
     DevBuf ptr;
 };
 
-tbk_status sk_layout(const HamPlan &plan, int64_t n, int32_t slice, SkLayout &ly, hipStream_t s) {
-    const int64_t nr = 4 * n;
+tbk_status sk_layout(const HamPlan &plan, int64_t n, int32_t norb, int32_t slice, SkLayout &ly, hipStream_t s) {
+    const int64_t nr = norb * n;
     ly.n_slices = ceil_div(nr, slice);
     DevBuf entries;
     TBK_HIP(entries.alloc(sizeof(int64_t) * (ly.n_slices + 1), s));
     TBK_HIP(ly.ptr.alloc(sizeof(int64_t) * (ly.n_slices + 1), s));
     TBK_HIP(hipMemsetAsync(entries.as<int64_t>() + ly.n_slices, 0, sizeof(int64_t), s));
-    k_sk_width<<<(unsigned)ceil_div(ly.n_slices, kBlock), kBlock, 0, s>>>(nr, slice, ly.n_slices,
+    k_sk_width<<<(unsigned)ceil_div(ly.n_slices, kBlock), kBlock, 0, s>>>(nr, norb, slice, ly.n_slices,
                                                                            plan.deg.as<int32_t>(),
                                                                            entries.as<int64_t>());
     TBK_HIP(hipGetLastError());
@@ -229,7 +295,7 @@ tbk_status sk_layout(const HamPlan &plan, int64_t n, int32_t slice, SkLayout &ly
     TBK_HIP(hipMemcpyAsync(&total, ly.ptr.as<int64_t>() + ly.n_slices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     TBK_HIP(hipStreamSynchronize(s));
     ly.n_entries = total;
-    ly.max_w = 4 * plan.max_degree;
+    ly.max_w = norb * plan.max_degree;
     return TBK_OK;
 }
 
@@ -240,7 +306,8 @@ int32_t log2i(int32_t v) {
 }
 
 tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, const tbk_sk_params *sk, tbk_ham *h) {
-    h->n_rows = 4 * n;
+    const int32_t norb = sk->orbitals;
+    h->n_rows = norb * n;
     if (is_block(h->fmt)) {      // blocks over atom slices
         h->n_ptr = plan.n_slices + 1;
         h->n_entries = plan.n_entries;
@@ -251,12 +318,28 @@ tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, cons
         h->max_degree = ly.max_w;
     }
     h->n_bonds = plan.n_bonds;
-    h->has_onsite = (sk->e_s != 0.0 || sk->e_p != 0.0) ? 1 : 0;
+    h->has_onsite = (sk->e_s != 0.0 || sk->e_p != 0.0 || (norb == 9 && sk->e_d != 0.0)) ? 1 : 0;
     h->n_seg = 1;
-    h->n_orb = 4;
+    h->n_orb = norb;
     h->uniform_hop = 0;
     h->hop_value = 0.0;
     return TBK_OK;
+}
+
+template <class V, int NORB>
+void launch_fill(const HamPlan &plan, const double *pos, int64_t n, int32_t slice, double r_cut, const SkValues &v,
+                 tbk_ham *h, int64_t *keys, hipStream_t s) {
+    const unsigned g = (unsigned)ceil_div(n, kBlock);
+    if (is_block(h->fmt))
+        k_fill_sk_blk<V, NORB><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), r_cut, v,
+                                                    plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr,
+                                                    h->col, static_cast<V *>(h->val), static_cast<V *>(h->onsite),
+                                                    keys);
+    else
+        k_fill_sk<V, NORB><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), r_cut, v,
+                                                plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr, h->col,
+                                                static_cast<V *>(h->val), static_cast<V *>(h->onsite), h->col16,
+                                                keys);
 }
 
 }  // namespace
@@ -280,7 +363,7 @@ extern "C" tbk_status tbk_hamiltonian_size_sk(const double *pos, const int32_t *
     if (st != TBK_OK) return st;
     SkLayout ly;
     if (!is_block(h->fmt)) {
-        st = sk_layout(plan, n, slice, ly, s);
+        st = sk_layout(plan, n, sk->orbitals, slice, ly, s);
         if (st != TBK_OK) return st;
     }
     if (h->fmt == TBK_CSR_F64) h->slice = 1;
@@ -303,50 +386,39 @@ extern "C" tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *
     const bool blk = is_block(h->fmt);
     tbk_status st = atom_plan(pos, species, n, box, periodic, sk, blk ? slice : 1, plan, s);
     if (st != TBK_OK) return st;
+    const int32_t norb = sk->orbitals;
     SkLayout ly;
     if (blk) {
         ly.n_slices = plan.n_slices;
         ly.n_entries = plan.n_entries;
     } else {
-        st = sk_layout(plan, n, slice, ly, s);
+        st = sk_layout(plan, n, norb, slice, ly, s);
         if (st != TBK_OK) return st;
     }
-    TBK_CHECK(h->n_rows >= 4 * n && h->n_ptr >= ly.n_slices + 1 && h->n_entries >= ly.n_entries,
+    TBK_CHECK(h->n_rows >= norb * n && h->n_ptr >= ly.n_slices + 1 && h->n_entries >= ly.n_entries,
               TBK_ERR_BUFFER_TOO_SMALL, "buffers sized for n_rows=%lld n_ptr=%lld n_entries=%lld; need %lld, %lld, %lld",
-              (long long)h->n_rows, (long long)h->n_ptr, (long long)h->n_entries, (long long)(4 * n),
+              (long long)h->n_rows, (long long)h->n_ptr, (long long)h->n_entries, (long long)(norb * n),
               (long long)(ly.n_slices + 1), (long long)ly.n_entries);
     TBK_CHECK(h->ptr && h->col && h->val && h->onsite && h->perm, TBK_ERR_INVALID_ARG,
               "a Hamiltonian array pointer is NULL");
     TBK_HIP(hipMemcpyAsync(h->ptr, blk ? plan.ptr.as<int64_t>() : ly.ptr.as<int64_t>(),
                            sizeof(int64_t) * (ly.n_slices + 1), hipMemcpyDeviceToDevice, s));
-    k_sk_perm<<<(unsigned)ceil_div(4 * n, kBlock), kBlock, 0, s>>>(n, plan.perm.as<int32_t>(), h->perm);
+    k_sk_perm<<<(unsigned)ceil_div(norb * n, kBlock), kBlock, 0, s>>>(n, norb, plan.perm.as<int32_t>(), h->perm);
     TBK_HIP(hipGetLastError());
     DevBuf keys;
     st = init_bound_keys(keys, 1, s);
     if (st != TBK_OK) return st;
-    SkValues v{sk->r0, sk->beta, sk->e_s, sk->e_p, {sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi}};
-    const unsigned g = (unsigned)ceil_div(n, kBlock);
-    if (blk) {
-        if (h->fmt == TBK_BSELL4_F32)
-            k_fill_sk_blk<float><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), sk->r_cut, v,
-                                                      plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr,
-                                                      h->col, static_cast<float *>(h->val),
-                                                      static_cast<float *>(h->onsite), keys.as<int64_t>());
-        else
-            k_fill_sk_blk<double><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), sk->r_cut, v,
-                                                       plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr,
-                                                       h->col, static_cast<double *>(h->val),
-                                                       static_cast<double *>(h->onsite), keys.as<int64_t>());
-    } else if (h->fmt == TBK_SELL_F32)
-        k_fill_sk<float><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), sk->r_cut, v,
-                                              plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr, h->col,
-                                              static_cast<float *>(h->val), static_cast<float *>(h->onsite),
-                                              h->col16, keys.as<int64_t>());
-    else
-        k_fill_sk<double><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), sk->r_cut, v,
-                                               plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr, h->col,
-                                               static_cast<double *>(h->val), static_cast<double *>(h->onsite),
-                                               h->col16, keys.as<int64_t>());
+    SkValues v{sk->r0, sk->beta, sk->e_s, sk->e_p, sk->e_d,
+               {sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi, sk->v_sd_sigma, sk->v_pd_sigma,
+                sk->v_pd_pi, sk->v_dd_sigma, sk->v_dd_pi, sk->v_dd_delta}};
+    const bool f32 = h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32;
+    if (norb == 4) {
+        if (f32) launch_fill<float, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
+        else launch_fill<double, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
+    } else {
+        if (f32) launch_fill<float, 9>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
+        else launch_fill<double, 9>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
+    }
     TBK_HIP(hipGetLastError());
     std::vector<int64_t> hk(2);
     TBK_HIP(hipMemcpyAsync(hk.data(), keys.as<int64_t>(), sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s));

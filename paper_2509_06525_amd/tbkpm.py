@@ -67,7 +67,10 @@ class SkParams(ctypes.Structure):
     _fields_ = [("r_cut", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double),
                 ("e_s", ctypes.c_double), ("e_p", ctypes.c_double),
                 ("v_ss_sigma", ctypes.c_double), ("v_sp_sigma", ctypes.c_double),
-                ("v_pp_sigma", ctypes.c_double), ("v_pp_pi", ctypes.c_double), ("reorder", ctypes.c_int32)]
+                ("v_pp_sigma", ctypes.c_double), ("v_pp_pi", ctypes.c_double), ("reorder", ctypes.c_int32),
+                ("orbitals", ctypes.c_int32), ("e_d", ctypes.c_double),
+                ("v_sd_sigma", ctypes.c_double), ("v_pd_sigma", ctypes.c_double), ("v_pd_pi", ctypes.c_double),
+                ("v_dd_sigma", ctypes.c_double), ("v_dd_pi", ctypes.c_double), ("v_dd_delta", ctypes.c_double)]
 
 
 class MlpModel(ctypes.Structure):
@@ -351,14 +354,21 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
 
 
 def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi, e_s, e_p,
-                         r_cut=2.0, r0=1.42, beta=3.37, fmt="sell_f32", slice=256, reorder=True, stream=None):
-    """s, p Slater-Koster orbital Hamiltonian (4 rows per atom) on the GPU."""
+                         r_cut=2.0, r0=1.42, beta=3.37, fmt="sell_f32", slice=256, reorder=True, stream=None,
+                         d=None, e_d=0.0):
+    """Slater-Koster orbital Hamiltonian on the GPU: s, p (4 rows per atom), or
+    s, p, d (9 rows per atom) when d = (v_sd_sigma, v_pd_sigma, v_pd_pi,
+    v_dd_sigma, v_dd_pi, v_dd_delta) is given."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
     n = pos.shape[0]
+    dv = [0.0] * 6 if d is None else [float(x) for x in d]
+    if len(dv) != 6:
+        raise ValueError("d takes six integrals: sd_sigma, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta")
+    norb = 4 if d is None else 9
     sk = SkParams(float(r_cut), float(r0), float(beta), float(e_s), float(e_p), float(v_ss_sigma),
-                  float(v_sp_sigma), float(v_pp_sigma), float(v_pp_pi), int(bool(reorder)))
+                  float(v_sp_sigma), float(v_pp_sigma), float(v_pp_pi), int(bool(reorder)), norb, float(e_d), *dv)
     boxa = _f64arr(box)
     per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
     s = _stream(stream)
@@ -366,7 +376,7 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     _check(L.tbk_hamiltonian_size_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk), ctypes.byref(st), s))
     dev = pos.device
     vdt = torch.float32 if fmt in ("sell_f32", "bsell4_f32") else torch.float64
-    per_entry = 16 if fmt.startswith("bsell4") else 1        # 4x4 blocks
+    per_entry = norb * norb if fmt.startswith("bsell4") else 1        # norb x norb blocks
     t = {
         "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
         "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),

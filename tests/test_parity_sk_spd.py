@@ -1,0 +1,154 @@
+"""GPU parity of the s, p, d Slater-Koster orbital Hamiltonian (nine orbital
+rows per atom) in the scalar and the block format, and of the DOS and VAC
+paths on it.
+
+Builder: the same (orbital row, orbital column) pattern as the oracle, values
+within 2e-15 (FP64 storage) or 1e-6 (FP32 storage) relative to the largest;
+onsite; Gershgorin bounds.  FP64 moments within 1e-10 of the row count;
+complex float DOS within 1e-4 relative L2; block and scalar moments within
+1e-4 of the row count of each other; VAC moments FP64 within 1e-10 of the
+largest.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+V = (-5.7, 5.4, 6.2, -2.7)
+D = (-3.1, -2.4, 1.3, -1.9, 1.05, -0.21)     # sd_sigma, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta
+V10 = V + D
+ES, EP, ED = -7.3, 0.0, 6.5
+
+
+def build(s, fmt, slice, reorder=True):
+    return tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *V, ES, EP,
+                                      fmt=fmt, slice=slice, reorder=reorder, d=D, e_d=ED)
+
+
+def oracle_csr(s):
+    return O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED)[0]
+
+
+def block_entries(H):
+    """(rows, cols, vals, onsite) in the caller's orbital order from a block Hamiltonian."""
+    t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
+    no = H.st.n_orb
+    n_at = H.n_rows // no
+    C = H.st.slice
+    ptr, col, perm = t["ptr"], t["col"], t["perm"]
+    with np.errstate(invalid="ignore"):      # lanes past the last atom of the last slice are never written
+        val = t["val"][: no * no * H.st.n_entries].astype(np.float64).reshape(-1, no, no)
+    rows, cols, vals = [], [], []
+    for sl in range(ptr.shape[0] - 1):
+        w = (ptr[sl + 1] - ptr[sl]) // C
+        for lane in range(C):
+            r = sl * C + lane
+            if r >= n_at:
+                break
+            for k in range(w):
+                q = ptr[sl] + k * C + lane
+                c = col[q]
+                if c == r and not val[q].any():
+                    continue                     # padding block
+                rr = perm[no * r + np.arange(no)]
+                cc = perm[no * c + np.arange(no)]
+                rows.append(np.repeat(rr, no)); cols.append(np.tile(cc, no)); vals.append(val[q].reshape(-1))
+    onsite = np.empty(H.n_rows)
+    onsite[perm] = t["onsite"].astype(np.float64)
+    return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), onsite
+
+
+@pytest.mark.parametrize("fmt,slice", [("sell_f64", 16), ("sell_f32", 64), ("csr_f64", 1),
+                                       ("bsell4_f64", 16), ("bsell4_f32", 32), ("bsell4_f64", 1)])
+@pytest.mark.parametrize("reorder", [True, False])
+def test_spd_builder_matches_oracle(fmt, slice, reorder):
+    s = synth.graphene_sheet(7, 6, 0.08, 31)
+    H = build(s, fmt, slice, reorder)
+    assert H.st.n_rows == 9 * s.n and H.st.n_orb == 9
+    csr = oracle_csr(s)
+    if fmt.startswith("bsell4"):
+        assert H.st.max_degree == 3
+        rows, cols, vals, onsite = block_entries(H)
+    else:
+        assert H.st.max_degree == 27
+        rows, cols, vals, onsite = G.entries_in_atom_order(H)
+    orow, ocol, oval = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_array_equal(rows[o1], orow[o2])
+    np.testing.assert_array_equal(cols[o1], ocol[o2])
+    tol = 1e-6 if fmt.endswith("f32") else 2e-15
+    np.testing.assert_allclose(vals[o1], oval[o2], rtol=tol, atol=tol * np.abs(oval).max())
+    odiag = csr.diag.astype(np.float32).astype(np.float64) if fmt.endswith("f32") else csr.diag
+    np.testing.assert_array_equal(onsite, odiag)
+    lo, hi = O.gershgorin(csr)
+    assert H.bounds[0] == pytest.approx(lo, rel=1e-12)
+    assert H.bounds[1] == pytest.approx(hi, rel=1e-12)
+
+
+@pytest.mark.parametrize("fmt,R,tpb,nt,xr,dbl", [("sell_f64", 1, 2, 1, 0, 0), ("bsell4_f64", 1, 1, 1, 0, 0),
+                                                  ("bsell4_f64", 3, 2, 0, 1, 0), ("bsell4_f64", 16, 2, 1, 0, 1),
+                                                  ("sell_f64", 4, 1, 1, 1, 1)])
+def test_spd_fp64_moments(fmt, R, tpb, nt, xr, dbl):
+    s = synth.graphene_sheet(9, 7, 0.06, 4)          # 2268 orbital rows: ragged tiles
+    csr = oracle_csr(s)
+    H = build(s, fmt, 32)
+    a, b = H.scale()
+    r = synth.random_phase(9 * s.n, R, 7)
+    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r, 61)
+    assert np.abs(mu - mo).max() <= 1e-10 * 9 * s.n
+
+
+@pytest.mark.parametrize("R,vpt", [(2, 2), (16, 2), (8, 1)])
+def test_spd_c32_dos_block_and_scalar(R, vpt):
+    s = synth.graphene_sheet(8, 7, 0.05, 8)
+    csr = oracle_csr(s)
+    Hb = build(s, "bsell4_f32", 64)
+    Hs = build(s, "sell_f32", 64)
+    a, b = Hb.scale()
+    r = synth.random_phase(9 * s.n, R, 3, np.complex64)
+    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1)
+    mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
+    ms = tbkpm.kpm_moments(Hs, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 256)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mb.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+    assert np.abs(mb - ms).max() <= 1e-4 * 9 * s.n
+
+
+def test_spd_vac_moments_match_oracle():
+    s = synth.graphene_sheet(5, 4, 0.07, 9)
+    csr = oracle_csr(s)
+    H = build(s, "sell_f64", 16)
+    a, b = H.scale()
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
+    rows, cols, vals, _ = G.entries_in_atom_order(H, vx)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0, n_orb=9)
+    orow, ocol, _ = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_allclose(vals[o1], vo[o2], rtol=1e-14, atol=1e-14 * np.abs(vo).max())
+    r = synth.random_phase(9 * s.n, 2, 5)
+    M, n_t, dt = 40, 3, 0.3
+    nc = tbkpm.chebyshev_terms(a, dt)
+    nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt).cpu().numpy()
+    nuo = O.vac_moments(csr, vo, a, b, r, M, n_t, dt, nc)
+    assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()
+
+
+def test_spd_orbital_count_rejected():
+    s = synth.graphene_sheet(3, 3)
+    pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
+    sk = tbkpm.SkParams(2.0, 1.42, 3.37, ES, EP, *V, 1, 5, ED, *D)
+    st = tbkpm.HamStruct(fmt=tbkpm.FORMATS["sell_f64"], slice=8)
+    boxa = (ctypes.c_double * 3)(*[float(x) for x in s.box])
+    per = (ctypes.c_int32 * 3)(*[int(x) for x in s.periodic])
+    rc = tbkpm.lib().tbk_hamiltonian_size_sk(pos.data_ptr(), sp.data_ptr(), s.n, boxa, per, ctypes.byref(sk),
+                                             ctypes.byref(st), None)
+    assert rc == 1                               # TBK_ERR_INVALID_ARG
