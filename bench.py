@@ -300,30 +300,36 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
 
 
 def bench_sk(args, w):
-    """DOS step on the s, p Slater-Koster orbital Hamiltonian (4 rows per atom): build +
-    moments + DOS per step, the recurrence rated like the one-orbital workloads, the
-    doubling form as a variant, the oracle on a bounded sample as the CPU baseline."""
+    """DOS step on the Slater-Koster orbital Hamiltonian (s, p: 4 rows per atom; s, p, d:
+    9): build + moments + DOS per step, the recurrence rated like the one-orbital
+    workloads, the doubling form as a variant, the oracle on a bounded sample as the CPU
+    baseline."""
     import torch
     from paper_2509_06525_amd import synth, tbkpm
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     M, R = w["M"], w["R"]
+    norb = w.get("orbitals", 4)
+    dint = synth.SK_D if norb == 9 else None
     log(f"generating {args.workload}")
     s = synth.make_structure(args.workload)
     N = s.n
     pos = torch.from_numpy(s.pos).to(dev)
     sp = torch.from_numpy(s.species).to(dev)
-    r = torch.from_numpy(synth.random_phase(4 * N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
+    r = torch.from_numpy(synth.random_phase(norb * N, R, w["seed"] + synth.VECTOR_SEED_OFFSET,
+                                            np.complex64)).to(dev)
 
     def build(fmt=w["fmt"], slice_=64):
         return tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
                                           r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice_,
-                                          stream=stream)
+                                          stream=stream, d=dint, e_d=synth.SK_ED)
 
     def pick_shape(H, a, b):
-        # the tuner builds one-orbital Hamiltonians, so time a few shapes here
-        shapes = [tbkpm.make_config(v, t, nt, xr, 1) for v in (1, 2) for t in (1, 2, 4) for nt in (0, 1)
-                  for xr in (0, 1)]
+        # the tuner builds one-orbital Hamiltonians, so time a few shapes here (both forms
+        # of the block kernel: a thread per orbital row, a thread per atom)
+        forms = (0, 1) if H.fmt in (tbkpm.FORMATS["bsell4_f32"], tbkpm.FORMATS["bsell4_f64"]) else (0,)
+        shapes = [tbkpm.make_config(v, t, nt, xr, 1, atom_rows=at) for at in forms for v in (1, 2)
+                  for t in (1, 2, 4) for nt in (0, 1) for xr in (0, 1)]
         times = []
         for c in shapes:
             tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
@@ -333,11 +339,14 @@ def bench_sk(args, w):
             e1.record(stream)
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
-        return shapes[int(np.argmin(times))], min(times) / 32
+        best = {}
+        for c, t in zip(shapes, times):
+            best[c.atom_rows] = min(best.get(c.atom_rows, float("inf")), t / 32)
+        return shapes[int(np.argmin(times))], min(times) / 32, best
 
     H = build()
     a, b = H.scale()
-    cfg, ms = pick_shape(H, a, b)
+    cfg, ms, form_ms = pick_shape(H, a, b)
     log(f"{w['fmt']}: launch shape {cfg.as_dict()} ({ms:.3f} ms/step)")
     work = tbkpm.alloc_workspace(H, R, M, "c32", dev, cfg)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
@@ -355,7 +364,7 @@ def bench_sk(args, w):
         rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream)
         return Hs, aa, bb, rho
 
-    log(f"N={N} atoms, {4 * N} orbitals, M={M} R={R}: warmup {args.warmup}, timed {args.steps}")
+    log(f"N={N} atoms, {norb * N} orbitals, M={M} R={R}: warmup {args.warmup}, timed {args.steps}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -374,22 +383,25 @@ def bench_sk(args, w):
     launch_s = kmed * 1e-3 / (M - 1)
     achieved = launch_bytes / launch_s / 1e9
     mu_c, rho_c = mu.cpu().numpy().copy(), rho.cpu().numpy()
-    nr = 4 * N
+    nr = norb * N
     out = {
         "metric": "KPM orbital*moments/s", "value": nr * M * R / sec, "unit": "orbital*moments/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "n_orbitals": nr, "moments": M, "vectors": R,
-                   "format": w["fmt"], "slice": 64, "precision": "c32", "a_eV": aa, "b_eV": bb,
+                   "orbitals_per_atom": norb, "format": w["fmt"], "slice": 64, "precision": "c32",
+                   "a_eV": aa, "b_eV": bb,
                    "launch": cfg.as_dict()},
         "kpm_ms_median": kmed,
+        "shape_search_ms_per_launch": {("atom_form" if k else "orbital_row_form"): v for k, v in form_ms.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_cheb_step",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cheb_step_atom" if cfg.atom_rows else "k_cheb_step_blk",
                      "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6},
     }
-    # the same Hamiltonian as a scalar SELL matrix (12 columns and values per orbital row)
+    # the same Hamiltonian as a scalar SELL matrix (3 norb columns and values per orbital row)
     Hsc = build("sell_f32", 64)
-    cfg_s, _ = pick_shape(Hsc, aa, bb)
+    cfg_s, _, _ = pick_shape(Hsc, aa, bb)
     ws = tbkpm.alloc_workspace(Hsc, R, M, "c32", dev, cfg_s)
     ms_s = []
     for _ in range(max(1, args.steps)):
@@ -412,19 +424,21 @@ def bench_sk(args, w):
                                                   diag, "c32", cfg, mu_c, rho_c, E, stream, dev)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
-        cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (16.0 * M * R))))
+        cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (norb * norb * M * R))))
         ss = synth.graphene_sheet(cells, cells, w["sigma"], w["seed"])
-        rs = synth.random_phase(4 * ss.n, R, w["seed"] + synth.VECTOR_SEED_OFFSET)
+        rs = synth.random_phase(norb * ss.n, R, w["seed"] + synth.VECTOR_SEED_OFFSET)
         t0 = time.perf_counter()
-        csr, _ = O.sk_hamiltonian(ss.pos, ss.box, ss.periodic, synth.SK_V, synth.SK_ES, synth.SK_EP)
+        vs = synth.SK_V + (synth.SK_D if norb == 9 else ())
+        csr, _ = O.sk_hamiltonian(ss.pos, ss.box, ss.periodic, vs, synth.SK_ES, synth.SK_EP, e_d=synth.SK_ED)
         lo, hi = O.gershgorin(csr)
         sa, sb = 1.01 * (hi - lo) / 2, (hi + lo) / 2
         mo, _ = O.kpm_moments(csr, sa, sb, rs, M)
         O.kpm_dos(mo.mean(0), sa, sb, synth.energy_grid(sa, sb))
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": 4 * ss.n * M * R / dt, "unit": "orbital*moments/s", "cores": 1,
+        out["cpu_baseline"] = {"value": norb * ss.n * M * R / dt, "unit": "orbital*moments/s", "cores": 1,
                                "kind": "oracle", "seconds": dt,
-                               "sample": f"{cells}x{cells}-cell sheet, {4 * ss.n} orbitals, M={M}, R={R}: full path"}
+                               "sample": f"{cells}x{cells}-cell sheet, {norb * ss.n} orbitals, M={M}, R={R}: "
+                                         "full path"}
     print(json.dumps(out), flush=True)
 
 

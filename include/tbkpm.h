@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 6
+#define TBK_ABI_VERSION 7
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -219,6 +219,11 @@ typedef struct {
                                    offsets h->col16 (needs them) and col only
                                    where an offset does not fit: 2 B less per
                                    stored entry, same results bit for bit         */
+    int32_t atom_rows;          /* block Hamiltonians (TBK_BSELL4_*) only: 1 = a
+                                   thread owns every orbital row of one atom, so a
+                                   neighbour's orbital rows of T_n are gathered
+                                   once per atom; 0 = a thread per orbital row.
+                                   Ignored for the other formats                 */
 } tbk_kpm_config;
 
 /* The launch shape kpm_moments uses for (h, R, precision) when none is given

@@ -540,7 +540,7 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.doubling = 0;
     c.uniform_values = 0;
     c.compact_columns = 0;
-    (void)h;
+    c.atom_rows = (h && (h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32)) ? 1 : 0;
     return c;
 }
 
@@ -591,10 +591,14 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
               "compact_columns needs the 16-bit column offsets h->col16");
     TBK_CHECK(!pl.block || (pl.cfg.uniform_values == 0 && pl.cfg.compact_columns == 0), TBK_ERR_INVALID_ARG,
               "uniform_values and compact_columns are not offered for block Hamiltonians");
+    TBK_CHECK(pl.cfg.atom_rows == 0 || pl.cfg.atom_rows == 1, TBK_ERR_INVALID_ARG, "atom_rows must be 0/1");
+    if (!pl.block) pl.cfg.atom_rows = 0;
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;
-    pl.n_tiles = (h->n_rows + rpb - 1) / rpb;
+    // tiles of rpb orbital rows, or of rpb atoms in the atom form of the block kernel
+    const int64_t tiled = pl.cfg.atom_rows ? h->n_rows / pl.norb : h->n_rows;
+    pl.n_tiles = (tiled + rpb - 1) / rpb;
     int64_t G = (pl.n_tiles + pl.cfg.tiles_per_block - 1) / pl.cfg.tiles_per_block;
     if (pl.cfg.xcd_remap) {
         // round up to a multiple of the XCD count; the extra blocks own no tile

@@ -157,6 +157,9 @@ WORKLOADS = {
     # s, p Slater-Koster orbital Hamiltonian (4 orbitals per atom: 4,000,000 rows)
     "graphene_sp3_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=3000, R=16,
                                     fmt="bsell4_f32", precision="c32", seed=1006, sk=True),
+    # s, p, d Slater-Koster orbital Hamiltonian (9 orbitals per atom: 9,000,000 rows)
+    "graphene_spd_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=16,
+                                    fmt="bsell4_f32", precision="c32", seed=1007, sk=True, orbitals=9),
     # velocity autocorrelation: 200 propagation steps of 0.1 fs (20 fs of correlation time)
     "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
                                     fmt="sell_f32", precision="c32", seed=1005, vac=True,
@@ -169,6 +172,11 @@ VECTOR_SEED_OFFSET = 1000   # vector seed = structure seed + 1000
 # published sp3 carbon sets, not a fit.
 SK_V = (-5.7, 5.4, 6.2, -2.7)
 SK_ES, SK_EP = -7.3, 0.0
+# d-orbital integrals at r0 (sd_sigma, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta) and the d
+# onsite energy of the synthetic nine-orbital model: magnitudes and signs of typical s, p, d
+# tight-binding sets, not fitted to any material
+SK_D = (-3.1, -2.4, 1.3, -1.9, 1.05, -0.21)
+SK_ED = 6.5
 
 
 def make_structure(name):

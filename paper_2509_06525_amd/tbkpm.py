@@ -84,7 +84,7 @@ class KpmConfig(ctypes.Structure):
                 ("nontemporal", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("doubling", ctypes.c_int32), ("uniform_values", ctypes.c_int32),
-                ("compact_columns", ctypes.c_int32)]
+                ("compact_columns", ctypes.c_int32), ("atom_rows", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,9 +96,9 @@ class TuneResult(ctypes.Structure):
 
 
 def make_config(vectors_per_thread=1, tiles_per_block=2, nontemporal=1, xcd_remap=0, rows_per_thread=1,
-                persistent=0, doubling=0, uniform_values=0, compact_columns=0):
+                persistent=0, doubling=0, uniform_values=0, compact_columns=0, atom_rows=0):
     return KpmConfig(vectors_per_thread, tiles_per_block, nontemporal, xcd_remap, rows_per_thread, persistent,
-                     doubling, uniform_values, compact_columns)
+                     doubling, uniform_values, compact_columns, atom_rows)
 
 
 def with_doubling(cfg, on=1):

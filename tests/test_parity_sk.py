@@ -159,34 +159,44 @@ def test_block_builder_matches_oracle(fmt, slice):
     assert H.bounds[1] == pytest.approx(hi, rel=1e-12)
 
 
+@pytest.mark.parametrize("atom", [0, 1])
 @pytest.mark.parametrize("R,tpb,nt,xr,dbl", [(1, 1, 1, 0, 0), (3, 2, 0, 1, 0), (16, 2, 1, 0, 1), (64, 1, 1, 1, 0)])
-def test_block_fp64_moments(R, tpb, nt, xr, dbl):
+def test_block_fp64_moments(R, tpb, nt, xr, dbl, atom):
     s = synth.graphene_sheet(13, 11, 0.06, 4)        # 2288 orbital rows: ragged tiles
     csr = oracle_csr(s)
     H = build(s, "bsell4_f64", 32)
     a, b = H.scale()
     r = synth.random_phase(4 * s.n, R, 7)
-    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl)
+    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=atom)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r, 61)
     assert np.abs(mu - mo).max() <= 1e-10 * 4 * s.n
 
 
+@pytest.mark.parametrize("atom", [0, 1])
 @pytest.mark.parametrize("R,vpt", [(2, 2), (16, 2), (8, 1), (32, 2)])
-def test_block_c32_dos_and_scalar_agreement(R, vpt):
+def test_block_c32_dos_and_scalar_agreement(R, vpt, atom):
     s = synth.graphene_sheet(12, 10, 0.05, 8)
     csr = oracle_csr(s)
     Hb = build(s, "bsell4_f32", 64)
     Hs = build(s, "sell_f32", 64)
     a, b = Hb.scale()
     r = synth.random_phase(4 * s.n, R, 3, np.complex64)
-    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1)
+    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1, atom_rows=atom)
     mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
     ms = tbkpm.kpm_moments(Hs, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 256)
     E = synth.energy_grid(a, b)
     assert G.rel_l2(O.kpm_dos(mb.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
     assert np.abs(mb - ms).max() <= 1e-4 * 4 * s.n
+
+
+def test_block_default_shape_is_atom_form():
+    s = synth.graphene_sheet(5, 4, 0.03, 1)
+    H = build(s, "bsell4_f32", 8)
+    assert tbkpm.default_config(H, 8, "c32").atom_rows == 1
+    Hs = build(s, "sell_f32", 8)
+    assert tbkpm.default_config(Hs, 8, "c32").atom_rows == 0
 
 
 def test_block_rejections():

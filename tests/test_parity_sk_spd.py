@@ -91,30 +91,37 @@ def test_spd_builder_matches_oracle(fmt, slice, reorder):
     assert H.bounds[1] == pytest.approx(hi, rel=1e-12)
 
 
-@pytest.mark.parametrize("fmt,R,tpb,nt,xr,dbl", [("sell_f64", 1, 2, 1, 0, 0), ("bsell4_f64", 1, 1, 1, 0, 0),
-                                                  ("bsell4_f64", 3, 2, 0, 1, 0), ("bsell4_f64", 16, 2, 1, 0, 1),
-                                                  ("sell_f64", 4, 1, 1, 1, 1)])
-def test_spd_fp64_moments(fmt, R, tpb, nt, xr, dbl):
+@pytest.mark.parametrize("fmt,R,tpb,nt,xr,dbl,atom", [("sell_f64", 1, 2, 1, 0, 0, 0),
+                                                       ("bsell4_f64", 1, 1, 1, 0, 0, 0),
+                                                       ("bsell4_f64", 1, 1, 1, 0, 0, 1),
+                                                       ("bsell4_f64", 3, 2, 0, 1, 0, 0),
+                                                       ("bsell4_f64", 3, 2, 0, 1, 0, 1),
+                                                       ("bsell4_f64", 16, 2, 1, 0, 1, 0),
+                                                       ("bsell4_f64", 16, 2, 1, 0, 1, 1),
+                                                       ("bsell4_f64", 64, 1, 1, 1, 0, 1),
+                                                       ("sell_f64", 4, 1, 1, 1, 1, 0)])
+def test_spd_fp64_moments(fmt, R, tpb, nt, xr, dbl, atom):
     s = synth.graphene_sheet(9, 7, 0.06, 4)          # 2268 orbital rows: ragged tiles
     csr = oracle_csr(s)
     H = build(s, fmt, 32)
     a, b = H.scale()
     r = synth.random_phase(9 * s.n, R, 7)
-    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl)
+    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=atom)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r, 61)
     assert np.abs(mu - mo).max() <= 1e-10 * 9 * s.n
 
 
+@pytest.mark.parametrize("atom", [0, 1])
 @pytest.mark.parametrize("R,vpt", [(2, 2), (16, 2), (8, 1)])
-def test_spd_c32_dos_block_and_scalar(R, vpt):
+def test_spd_c32_dos_block_and_scalar(R, vpt, atom):
     s = synth.graphene_sheet(8, 7, 0.05, 8)
     csr = oracle_csr(s)
     Hb = build(s, "bsell4_f32", 64)
     Hs = build(s, "sell_f32", 64)
     a, b = Hb.scale()
     r = synth.random_phase(9 * s.n, R, 3, np.complex64)
-    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1)
+    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1, atom_rows=atom)
     mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
     ms = tbkpm.kpm_moments(Hs, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 256)
