@@ -543,16 +543,8 @@ def main():
     from paper_2509_06525_amd import synth, tbkpm
 
     w = dict(synth.WORKLOADS[args.workload])
-    if w["kind"] == "snapshots":
-        return bench_snapshots(args, w)
-    if w.get("vac"):
-        return bench_vac(args, w)
-    if w.get("sk"):
-        return bench_sk(args, w)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -560,6 +552,14 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
         del src, dst
+    if w["kind"] == "snapshots":
+        return bench_snapshots(args, w)
+    if w.get("vac"):
+        return bench_vac(args, w)
+    if w.get("sk"):
+        return bench_sk(args, w)
+    stream = torch.cuda.current_stream()
+
     log(f"generating {args.workload}")
     s = synth.make_structure(args.workload)
     N, M, R = s.n, w["M"], w["R"]
