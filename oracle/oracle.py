@@ -73,6 +73,10 @@ def _lib():
     L.orc_vac_sigma.restype = ctypes.c_int
     L.orc_vac_sigma.argtypes = [_f64p, _i32, _i32, _f64, _f64, _f64, _i32, _f64p, _i32, _f64p]
     L.orc_assemble_sk.restype = ctypes.c_int
+    L.orc_integrated_dos.restype = ctypes.c_int
+    L.orc_integrated_dos.argtypes = [_f64p, _i32, _f64, _f64, _i32, _f64p, _i32, _f64p]
+    L.orc_mobility.restype = ctypes.c_int
+    L.orc_mobility.argtypes = [_f64p, _i32, _i32, _i32, _f64p, _f64, _f64p, _f64p, _f64p]
     L.orc_assemble_sk.argtypes = [_i64, _f64p, _f64p, _i32p, _i64, _i32p, _i32p, _i32, _f64p, _f64p, _f64, _f64,
                                   _i64p, _i32p, _f64p, _f64p]
     L.orc_splitmix64.restype = ctypes.c_uint64
@@ -290,6 +294,28 @@ def vac_sigma(nu, a, b, dt, E, kernel=0):
     if rc != 0:
         raise OracleError("orc_vac_sigma: invalid argument")
     return s
+
+
+def integrated_dos(mu, a, b, E, kernel=0):
+    """N(E): states below E of the kernel-damped expansion (closed form), whole system."""
+    mu = _c(mu, np.float64)
+    E = _c(E, np.float64)
+    N = np.empty(E.shape[0])
+    if _lib().orc_integrated_dos(mu, mu.shape[0], float(a), float(b), int(kernel), E, E.shape[0], N) != 0:
+        raise OracleError("orc_integrated_dos: invalid argument")
+    return N
+
+
+def mobility(sigma, N, n_ref):
+    """Frame-averaged semiclassical conductivity, carriers and mobility (cm^2/(V s)):
+    sigma [F][n_t][nE] running conductivities, N [F][nE] integrated DOS of each frame."""
+    sigma = _c(sigma, np.float64)
+    N = _c(N, np.float64)
+    F, n_t, nE = sigma.shape
+    ssc, car, mob = np.empty(nE), np.empty(nE), np.empty(nE)
+    if _lib().orc_mobility(sigma.reshape(-1), F, n_t, nE, N.reshape(-1), float(n_ref), ssc, car, mob) != 0:
+        raise OracleError("orc_mobility: invalid argument")
+    return ssc, car, mob
 
 
 def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None, e_d=0.0):

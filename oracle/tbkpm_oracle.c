@@ -11,7 +11,8 @@
  * and the velocity-autocorrelation conductivity of Eq. (3) (velocity operator,
  * Chebyshev time evolution, correlation moments, running time integral); and
  * the s, p (and s, p, d) Slater-Koster orbital Hamiltonian of the multi-orbital
- * models.
+ * models; and the transport post-processing (integrated DOS, frame averages,
+ * semiclassical conductivity and mobility).
  *
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
  * load this file.  It shares no code, header or constant generator with the HIP
@@ -745,6 +746,80 @@ int orc_vac_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a,
     }
     free(cprev); free(cj);
     return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Transport post-processing: integrated DOS, frame averages, mobility.       */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Integrated DOS N(E) = integral of rho(E') dE' from the bottom of the spectrum
+ * to E, for the kernel-damped expansion of orc_kpm_dos, in closed form: with
+ * x = (E - b)/a = cos(theta),
+ *   integral_{-1}^{x} T_0(y) / (pi sqrt(1 - y^2)) dy = 1 - theta / pi,
+ *   integral_{-1}^{x} T_n(y) / (pi sqrt(1 - y^2)) dy = -sin(n theta) / (n pi),  n >= 1,
+ * so N = g_0 mu_0 (1 - theta/pi) - (2/pi) sum_{n>=1} g_n mu_n sin(n theta) / n;
+ * N = 0 for x <= -1 and g_0 mu_0 for x >= 1.  States of the whole system (no
+ * spin factor), as orc_kpm_dos.  Returns 0, -1 on a bad argument.
+ */
+int orc_integrated_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
+                       const double *E, int32_t nE, double *N)
+{
+    if (M < 1 || !(a > 0.0) || (kernel != 0 && kernel != 1) || nE < 0) return -1;
+    double *g = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!g) return -2;
+    if (kernel == 0) orc_jackson(M, g);
+    else for (int32_t k = 0; k < M; ++k) g[k] = 1.0;
+    for (int32_t e = 0; e < nE; ++e) {
+        double x = (E[e] - b) / a;
+        if (x <= -1.0) { N[e] = 0.0; continue; }
+        if (x >= 1.0) { N[e] = g[0] * mu[0]; continue; }
+        double theta = acos(x);
+        double s = g[0] * mu[0] * (1.0 - theta / ORC_PI);
+        for (int32_t k = 1; k < M; ++k)
+            s -= 2.0 / ORC_PI * g[k] * mu[k] * sin(k * theta) / k;
+        N[e] = s;
+    }
+    free(g);
+    return 0;
+}
+
+/*
+ * Frame averages and mobility (Sec. 2.4: results of several MD frames are
+ * averaged; Sec. 3: mobility against carrier concentration).
+ *   sigma [F][n_t][nE]  running conductivity of each frame (orc_vac_sigma units),
+ *   N     [F][nE]       integrated DOS of each frame (orc_integrated_dos),
+ *   n_ref               integrated DOS at charge neutrality (states),
+ * out:
+ *   sigma_sc[e] = max over j of (1/F) sum_f sigma[f][j][e]   (semiclassical
+ *                 conductivity: the plateau of the frame-averaged running value),
+ *   carriers[e] = (1/F) sum_f N[f][e] - n_ref                 (carriers, states),
+ *   mobility[e] = 0.1 sigma_sc[e] / |carriers[e]|             (cm^2 / (V s)).
+ * The factor: sigma = (2 e^2 / A) sigma_sc and n = 2 carriers / A (spin 2, area A
+ * in Angstrom^2), so mu = sigma / (e n) = e sigma_sc / carriers, and
+ * e Angstrom^2 / (eV fs) = Angstrom^2 / (V fs) = 1e-16 cm^2 / (1e-15 V s).
+ * mobility = NaN where carriers = 0.  Returns 0, -1 on a bad argument.
+ */
+int orc_mobility(const double *sigma, int32_t F, int32_t n_t, int32_t nE, const double *N, double n_ref,
+                 double *sigma_sc, double *carriers, double *mobility)
+{
+    if (F < 1 || n_t < 1 || nE < 0) return -1;
+    for (int32_t e = 0; e < nE; ++e) {
+        double best = -INFINITY;
+        for (int32_t j = 0; j < n_t; ++j) {
+            double m = 0.0;
+            for (int32_t f = 0; f < F; ++f) m += sigma[((int64_t)f * n_t + j) * nE + e];
+            m /= F;
+            if (m > best) best = m;
+        }
+        double nb = 0.0;
+        for (int32_t f = 0; f < F; ++f) nb += N[(int64_t)f * nE + e];
+        nb = nb / F - n_ref;
+        sigma_sc[e] = best;
+        carriers[e] = nb;
+        mobility[e] = nb != 0.0 ? 0.1 * best / fabs(nb) : NAN;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
