@@ -443,59 +443,84 @@ def bench_sk(args, w):
 
 
 def bench_vac(args, w):
-    """Velocity-autocorrelation conductivity (Eq. (3)) on one structure: per step the
-    Hamiltonian and velocity operator are built, the correlation moments of n_t
-    propagation steps computed (M - 1 recurrence launches, two Chebyshev-Bessel
-    propagations and one velocity product per time step) and sigma(E, t) formed."""
+    """Velocity-autocorrelation conductivity (Eq. (3)): per step and frame the Hamiltonian
+    and velocity operator are built, the correlation moments of n_t propagation steps
+    computed (M - 1 recurrence launches, two Chebyshev-Bessel propagations and one
+    velocity product per time step) and sigma(E, t) formed.  A multi-frame workload also
+    computes each frame's DOS moments and integrated DOS and, over the frames, the
+    averaged plateau conductivity, carriers and mobility (Sec. 2.4, Sec. 3)."""
     import torch
     from paper_2509_06525_amd import synth, tbkpm
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     M, R, n_t, dt = w["M"], w["R"], w["n_t"], w["dt"]
+    F = w.get("frames", 1)
     log(f"generating {args.workload}")
-    s = synth.make_structure(args.workload)
+    frames = synth.make_frames(args.workload) if F > 1 else [synth.make_structure(args.workload)]
+    s = frames[0]
     N = s.n
-    pos = torch.from_numpy(s.pos).to(dev)
+    pos = [torch.from_numpy(fr.pos).to(dev) for fr in frames]
     sp = torch.from_numpy(s.species).to(dev)
     r = torch.from_numpy(synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
     held = []
-    slice_, config = args.slice, None
+    slice_, config, config_dos = args.slice, None, None
     if not args.no_tune:
         if not args.retune:
             use_shipped_tuning()
-        tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, R, "c32", r_cut=synth.R_HOP,
+        tune = tbkpm.autotune(pos[0], sp, s.box, s.periodic, s.onsite, s.t_pair, R, "c32", r_cut=synth.R_HOP,
                               r0=synth.R0, beta=synth.BETA, stream=stream)
         slice_, config = tune.slice, tune.config
         log(f"tuned: slice {slice_} {config.as_dict()}")
 
-    def build():
-        H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP, r0=synth.R0,
-                                    beta=synth.BETA, fmt=w["fmt"], slice=slice_, stream=stream,
+    def build(f):
+        H = tbkpm.build_hamiltonian(pos[f], sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP,
+                                    r0=synth.R0, beta=synth.BETA, fmt=w["fmt"], slice=slice_, stream=stream,
                                     into=held.pop() if held else None)
         held.append(H)
         return H
 
-    H = build()
-    a, b = H.scale()
-    n_cheb = tbkpm.chebyshev_terms(a, dt)
-    E = torch.linspace(b - 0.99 * a, b + 0.99 * a, 2001, dtype=torch.float64, device=dev)
+    scales = []
+    for f in range(F):
+        scales.append(build(f).scale())
+    a, b = scales[0]
+    n_cheb = tbkpm.chebyshev_terms(max(x[0] for x in scales), dt)
+    lo = max(bb - 0.99 * aa for aa, bb in scales)
+    hi = min(bb + 0.99 * aa for aa, bb in scales)
+    E = torch.linspace(lo, hi, 2001, dtype=torch.float64, device=dev)
+    if F > 1:
+        R_dos = w["R_dos"]
+        r_dos = torch.from_numpy(synth.random_phase(N, R_dos, w["seed"] + 1 + synth.VECTOR_SEED_OFFSET,
+                                                    np.complex64)).to(dev)
+        if not args.no_tune:
+            config_dos = tbkpm.autotune(pos[0], sp, s.box, s.periodic, s.onsite, s.t_pair, R_dos, "c32",
+                                        r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, stream=stream).config
+        sig_all = torch.empty((F, n_t, E.numel()), dtype=torch.float64, device=dev)
+        n_all = torch.empty((F, E.numel()), dtype=torch.float64, device=dev)
 
     def step():
-        Hs = build()
-        aa, bb = Hs.scale()
-        vx = tbkpm.build_velocity(Hs, pos, s.box, s.periodic, 0, stream=stream)
-        nu = tbkpm.vac_moments(Hs, vx, aa, bb, r, M, n_t, dt, n_cheb, "c32", config=config, stream=stream)
-        sig = tbkpm.vac_sigma(nu.mean(1).contiguous(), aa, bb, dt, E, stream=stream)
-        return Hs, sig
+        res = None
+        for f in range(F):
+            Hs = build(f)
+            aa, bb = Hs.scale()
+            vx = tbkpm.build_velocity(Hs, pos[f], s.box, s.periodic, 0, stream=stream)
+            nu = tbkpm.vac_moments(Hs, vx, aa, bb, r, M, n_t, dt, n_cheb, "c32", config=config, stream=stream)
+            sig = tbkpm.vac_sigma(nu.mean(1).contiguous(), aa, bb, dt, E, stream=stream)
+            if F > 1:
+                sig_all[f].copy_(sig)
+                mu = tbkpm.kpm_moments(Hs, aa, bb, r_dos, M, "c32", stream=stream, config=config_dos)
+                n_all[f].copy_(tbkpm.integrated_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream))
+        if F > 1:
+            res = tbkpm.mobility(sig_all, n_all, 0.5 * N, stream=stream)
+        return Hs, sig, res
 
-    log(f"N={N} M={M} R={R} n_t={n_t} dt={dt} fs, {n_cheb} propagator terms: warmup {args.warmup}, "
-        f"timed {args.steps}")
+    log(f"N={N} x {F} frames, M={M} R={R} n_t={n_t} dt={dt} fs, {n_cheb} propagator terms: "
+        f"warmup {args.warmup}, timed {args.steps}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        Hs, sig = step()
+        Hs, sig, res = step()
         torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / args.steps
     st = Hs.st
@@ -507,16 +532,16 @@ def bench_vac(args, w):
     prop = hb + N * Rp * 8 * 5                          # propagator term: T_k gather, T_{k-1}, T_{k+1}, acc r/w
     vel = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 2
     per_t = (M - 1) * rec + 2 * (n_cheb - 1) * prop + vel
-    total = n_t * per_t
+    total = F * n_t * per_t
     achieved = total / sec / 1e9
     out = {
-        "metric": "VAC atom*moments*timesteps/s", "value": N * M * R * n_t / sec,
+        "metric": "VAC atom*moments*timesteps/s", "value": F * N * M * R * n_t / sec,
         "unit": "atom*moments*timesteps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "n_atoms": N, "moments": M, "vectors": R, "time_steps": n_t,
-                   "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"], "slice": slice_,
-                   "precision": "c32", "a_eV": a, "b_eV": b,
+        "config": {"workload": args.workload, "n_atoms": N, "frames": F, "moments": M, "vectors": R,
+                   "time_steps": n_t, "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"],
+                   "slice": slice_, "precision": "c32", "a_eV": a, "b_eV": b,
                    "launch": None if config is None else config.as_dict()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -524,6 +549,21 @@ def bench_vac(args, w):
                      "bytes_per_step": total},
         "sigma_max": float(sig[-1].abs().max()),
     }
+    if F > 1:
+        # carriers per cm^2 (spin 2, sheet area) and the mobility at a few concentrations
+        area = float(s.box[0] * s.box[1])
+        ssc, car, mob = (x.cpu().numpy() for x in res)
+        conc = 2.0 * car / area * 1e16
+        Eh = E.cpu().numpy()
+        pts = {}
+        for n_cm2 in (1e12, 5e12, 1e13):
+            for sign, lab in ((1.0, "electrons"), (-1.0, "holes")):
+                k = int(np.argmin(np.abs(conc - sign * n_cm2)))
+                pts[f"{lab}_{n_cm2:.0e}"] = {"E_eV": float(Eh[k]), "n_cm2": float(conc[k]),
+                                             "mobility_cm2_Vs": float(mob[k])}
+        out["mobility"] = {"n_ref_states": 0.5 * N, "area_A2": area, "points": pts,
+                           "dos_vectors": w["R_dos"],
+                           "dos_launch": None if config_dos is None else config_dos.as_dict()}
     print(json.dumps(out), flush=True)
 
 

@@ -593,6 +593,48 @@ tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double a, double b
 tbk_status lsqt_sigma(const double *nu, int32_t M, int32_t n_t, double dt, double a, double b,
                       int32_t kernel, const double *E, int32_t nE, double *sigma, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Transport post-processing: integrated DOS, frames, mobility               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Integrated DOS (states below E) of the kernel-damped expansion of kpm_dos,
+ * in closed form: with x = (E - b)/a = cos(theta),
+ *   N(E) = g_0 mu_0 (1 - theta/pi) - (2/pi) sum_{n=1}^{M-1} g_n mu_n sin(n theta) / n,
+ * N = 0 for x <= -1 and g_0 mu_0 for x >= 1 (the integral of each T_n against
+ * the Chebyshev weight; no energy grid, so no states are lost at the band
+ * edges).  States of the whole system without the spin factor, as kpm_dos;
+ * N(E) - N(E_neutral) counts the carriers behind the concentration axis of the
+ * mobility curve (Sec. 3).
+ *   mu device double [M]; E device double [nE]; N device double [nE].
+ * Asynchronous on `stream`.  Errors: as kpm_dos.
+ */
+tbk_status kpm_integrated_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
+                              const double *E, int32_t nE, double *N, void *stream);
+
+/*
+ * Frame average and mobility (Sec. 2.4: LSQT results of several MD frames are
+ * averaged; Sec. 3: mobility against carrier concentration):
+ *   sigma    device double [n_frames][n_t][nE]: lsqt_sigma of each frame on
+ *            one common energy grid,
+ *   N        device double [n_frames][nE]: kpm_integrated_dos of each frame on
+ *            the same grid,
+ *   n_ref    states below the charge-neutrality point (e.g. half the orbitals
+ *            of a half-filled band),
+ * out (device double [nE] each):
+ *   sigma_sc[e] = max over j of the frame mean of sigma[.][j][e] (the plateau
+ *                 of the running conductivity: the semiclassical value),
+ *   carriers[e] = frame mean of N[.][e] - n_ref,
+ *   mobility[e] = 0.1 sigma_sc[e] / |carriers[e]| in cm^2 / (V s), NaN where
+ *                 carriers[e] = 0.
+ * The factor 0.1: with sigma = (2 e^2 / A) sigma_sc and n = 2 carriers / A
+ * (spin 2, area A), mu = sigma / (e n) = e sigma_sc / carriers, and
+ * e Angstrom^2 / (eV fs) = 0.1 cm^2 / (V s); area and spin cancel.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (counts, NULL), NOT_FINITE (n_ref).
+ */
+tbk_status lsqt_mobility(const double *sigma, int32_t n_frames, int32_t n_t, int32_t nE, const double *N,
+                         double n_ref, double *sigma_sc, double *carriers, double *mobility, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -164,6 +164,11 @@ WORKLOADS = {
     "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
                                     fmt="sell_f32", precision="c32", seed=1005, vac=True,
                                     n_t=200, dt=0.1),
+    # four thermal frames of a 1 M-atom sheet (seeds 1010..1013): VAC conductivity and integrated
+    # DOS of each frame, frame average, carriers and mobility
+    "graphene_mobility_frames_1M": dict(kind="frames", frames=4, nx=500, ny=500, sigma=0.05, M=1000, R=1,
+                                        R_dos=16, fmt="sell_f32", precision="c32", seed=1010, vac=True,
+                                        n_t=200, dt=0.1),
 }
 VECTOR_SEED_OFFSET = 1000   # vector seed = structure seed + 1000
 
@@ -185,7 +190,16 @@ def make_structure(name):
         return graphene_sheet(w["nx"], w["ny"], w["sigma"], w["seed"])
     if w["kind"] == "stripes":
         return hbn_stripes(w["nx"], w["ny"], 50, w["sigma"], w["seed"])
+    if w["kind"] == "frames":
+        return graphene_sheet(w["nx"], w["ny"], w["sigma"], w["seed"])
     raise ValueError("use snapshot_set for the snapshot workload")
+
+
+def make_frames(name):
+    """The frames of a multi-frame workload: the same sheet with independent
+    displacements (seeds seed, seed + 1, ...)."""
+    w = WORKLOADS[name]
+    return [graphene_sheet(w["nx"], w["ny"], w["sigma"], w["seed"] + f) for f in range(w.get("frames", 1))]
 
 
 # ---------------------------------------------------------------------------

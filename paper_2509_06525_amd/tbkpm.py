@@ -60,7 +60,7 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_coordination_target", "tbk_mlp_forward", "tbk_mlp_workspace_size",
                "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned",
                "tb_build_velocity", "lsqt_chebyshev_terms", "lsqt_workspace_size", "lsqt_vac_moments",
-               "lsqt_sigma")
+               "lsqt_sigma", "kpm_integrated_dos", "lsqt_mobility")
 
 
 class SkParams(ctypes.Structure):
@@ -215,6 +215,10 @@ def lib():
                                    ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
     L.lsqt_sigma.restype = ctypes.c_int
     L.lsqt_sigma.argtypes = [vp, i32, i32, f64, f64, f64, i32, vp, i32, vp, vp]
+    L.kpm_integrated_dos.restype = ctypes.c_int
+    L.kpm_integrated_dos.argtypes = [vp, i32, f64, f64, i32, vp, i32, vp, vp]
+    L.lsqt_mobility.restype = ctypes.c_int
+    L.lsqt_mobility.argtypes = [vp, i32, i32, i32, vp, f64, vp, vp, vp, vp]
     L.tbk_hamiltonian_size_sk.restype = ctypes.c_int
     L.tbk_hamiltonian_size_sk.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                           ctypes.POINTER(SkParams), ctypes.POINTER(HamStruct), vp]
@@ -790,6 +794,30 @@ def vac_moments(H, vx, a, b, r, M, n_t, dt, n_cheb=0, precision=None, config=Non
                               float(dt), int(n_cheb), PRECISIONS[precision], _cfg_ref(config), _ptr(work),
                               work.numel(), _ptr(nu), _stream(stream)))
     return nu
+
+
+def integrated_dos(mu, a, b, E, kernel=0, stream=None):
+    """States below each energy of E (float64, device) from vector-averaged moments mu [M]."""
+    mu = _dev(mu, torch.float64)
+    E = _dev(E, torch.float64)
+    N = torch.empty(E.numel(), dtype=torch.float64, device=E.device)
+    _check(lib().kpm_integrated_dos(_ptr(mu), mu.numel(), float(a), float(b), int(kernel), _ptr(E), E.numel(),
+                                    _ptr(N), _stream(stream)))
+    return N
+
+
+def mobility(sigma, N, n_ref, stream=None):
+    """Frame-averaged plateau conductivity, carriers and mobility (cm^2/(V s)) from
+    sigma [F][n_t][nE] and integrated DOS N [F][nE] on one energy grid."""
+    sigma = _dev(sigma, torch.float64)
+    N = _dev(N, torch.float64)
+    F, n_t, nE = sigma.shape
+    if tuple(N.shape) != (F, nE):
+        raise ValueError(f"N has shape {tuple(N.shape)}, expected {(F, nE)}")
+    out = [torch.empty(nE, dtype=torch.float64, device=sigma.device) for _ in range(3)]
+    _check(lib().lsqt_mobility(_ptr(sigma), F, n_t, nE, _ptr(N), float(n_ref), _ptr(out[0]), _ptr(out[1]),
+                               _ptr(out[2]), _stream(stream)))
+    return tuple(out)
 
 
 def vac_sigma(nu, a, b, dt, E, kernel=0, stream=None):
