@@ -541,11 +541,15 @@ tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, in
  * the displacement between the two atoms (perm[row] / h->n_orb) taken with the minimum-image
  * convention (the bond of the hopping), hbar = 0.6582119569 eV fs, so that
  * (V psi)_i = i sum_q vx[q] psi_col(q) in Angstrom / fs.
- *   pos  device double [n_rows][3] (the positions h was built from, caller's
+ * For a block Hamiltonian (TBK_BSELL4_*) every value of block q is scaled by
+ * the displacement between the row atom and col[q] (the orbitals sit on their
+ * atom): vx has the layout of h->val, n_orb^2 values per block.
+ *   pos  device double [atoms][3] (the positions h was built from, caller's
  *        atom order); box, periodic: host, as for tb_build_hamiltonian.
- *   vx   device, same type as h->val, >= h->n_entries elements.
- * Asynchronous on `stream`.  Errors: INVALID_ARG (NULL, axis, box), UNSUPPORTED
- * (stacked structures).
+ *   vx   device, same type as h->val, as many elements as h->val holds
+ *        (h->n_entries, or n_orb^2 h->n_entries for blocks).
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (NULL, axis, box, format),
+ * UNSUPPORTED (stacked structures).
  */
 tbk_status tb_build_velocity(const double *pos, const double box[3], const int32_t periodic[3],
                              int32_t axis, const tbk_ham *h, void *vx, void *stream);
@@ -570,8 +574,8 @@ tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t p
  * Summed over a complete basis, nu[j][.][m] is the T_m moment of
  * Tr[delta(E - H) Re(V V(t_j))]; lsqt_sigma turns nu into sigma(E, t).
  *   r    device c128|c64 [n_rows][R] start vectors, caller's atom order;
- *   vx   from tb_build_velocity; cfg: launch shape of the recurrence (NULL =
- *        default; doubling must be 0);
+ *   vx   from tb_build_velocity (scalar or block layout, as h); cfg: launch
+ *        shape of the recurrence (NULL = default; doubling must be 0);
  *   nu   device double [n_t][R][M].
  * Synchronises `stream`.  Errors: as kpm_moments_config; INVALID_ARG (dt <= 0,
  * n_t outside [1, 10^6], doubling); SPECTRUM when a moment is not finite.

@@ -14,8 +14,9 @@
 //
 // All vectors live in the builder's row order, [rows][R_pad] interleaved
 // complex, like the recurrence's.  The kernels here are plain SELL sweeps with
-// one thread per (row, vector); the M-1 recurrence steps per time step, which
-// dominate, run in the tuned recurrence kernel.
+// one thread per (row, vector) (for block Hamiltonians: per (orbital row,
+// vector), over the atom's blocks); the M-1 recurrence steps per time step,
+// which dominate, run in the tuned recurrence kernel.
 #include <cmath>
 #include <vector>
 
@@ -65,6 +66,33 @@ __global__ void k_velocity(SellView h, const V *__restrict__ val, const int32_t 
     }
 }
 
+// Block form: one atom row r per thread; every value of block q (neighbour
+// atom col[q]) is scaled by the atoms' displacement (x_j - x_i) / hbar (the
+// orbitals sit on their atom); padding blocks (col = own row) stay 0.
+template <class V>
+__global__ void k_velocity_blk(SellView h, const V *__restrict__ val, const int32_t *__restrict__ perm, int32_t norb,
+                               const double *__restrict__ pos, int64_t n_atoms, double L, int32_t periodic,
+                               int32_t axis, V *__restrict__ vx) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n_atoms) return;
+    int64_t base, stride;
+    int32_t w;
+    row_range(h, r, base, w, stride);
+    const int32_t nb = norb * norb;
+    const double xi = pos[3 * (int64_t)(perm[norb * r] / norb) + axis];
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = base + k * stride;
+        const int32_t c = h.col[q];
+        double d = 0.0;
+        if (c != (int32_t)r) {
+            d = __dsub_rn(pos[3 * (int64_t)(perm[(int64_t)norb * c] / norb) + axis], xi);
+            if (periodic) d = __dsub_rn(d, __dmul_rn(L, rint(__ddiv_rn(d, L))));
+        }
+        for (int32_t e = 0; e < nb; ++e)
+            vx[nb * q + e] = (V)__ddiv_rn(__dmul_rn((double)val[nb * q + e], d), kHbar);
+    }
+}
+
 // out[i][v] = r[perm[i]][v] for v < R, 0 for the padded vectors.
 template <class VT>
 __global__ void k_permute_in(const VT *__restrict__ r, const int32_t *__restrict__ perm, int64_t n, int32_t R,
@@ -104,6 +132,69 @@ __global__ void k_apply_velocity(SellView h, const VT *__restrict__ vx, const VT
     }
     y[2 * idx] = -si;
     y[2 * idx + 1] = sr;
+}
+
+// (A x)_i for orbital row i of a block matrix (values a, norb x norb blocks
+// over atom slices), vector v: sum over the atom's blocks and the neighbour's
+// orbitals.
+template <class VT>
+__device__ __forceinline__ void block_row_product(const SellView &h, int32_t norb, const VT *__restrict__ a,
+                                                  const VT *__restrict__ x, int64_t i, int v, int32_t Rp, VT &sr,
+                                                  VT &si) {
+    const int64_t at = i / norb;
+    const int32_t orb = (int32_t)(i - at * norb);
+    const int32_t nb = norb * norb;
+    int64_t base, stride;
+    int32_t w;
+    row_range(h, at, base, w, stride);
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = base + k * stride;
+        const int64_t c0 = (int64_t)norb * h.col[q];
+        const VT *ar = a + nb * q + norb * orb;
+        for (int32_t b = 0; b < norb; ++b) {
+            const VT hv = ar[b];
+            const int64_t xo = 2 * ((c0 + b) * Rp + v);
+            sr += hv * x[xo];
+            si += hv * x[xo + 1];
+        }
+    }
+}
+
+// y = V x on a block velocity operator.
+template <class VT>
+__global__ void k_apply_velocity_blk(SellView h, int32_t norb, const VT *__restrict__ vx, const VT *__restrict__ x,
+                                     int64_t n, int32_t Rp, VT *__restrict__ y) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * Rp) return;
+    const int64_t i = idx / Rp;
+    const int v = (int)(idx % Rp);
+    VT sr = 0, si = 0;
+    block_row_product(h, norb, vx, x, i, v, Rp, sr, si);
+    y[2 * idx] = -si;
+    y[2 * idx + 1] = sr;
+}
+
+// One term of the propagator series on a block Hamiltonian (as k_evolve_term).
+template <class VT, bool FIRST>
+__global__ void k_evolve_term_blk(SellView h, int32_t norb, const VT *__restrict__ val, const VT *__restrict__ onsite,
+                                  VT shift, VT c1, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
+                                  VT *__restrict__ acc, double cr, double ci, int64_t n, int32_t Rp) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * Rp) return;
+    const int64_t i = idx / Rp;
+    const int v = (int)(idx % Rp);
+    const VT d = (onsite ? onsite[i] : (VT)0) - shift;
+    VT yr = d * tcur[2 * idx], yi = d * tcur[2 * idx + 1];
+    block_row_product(h, norb, val, tcur, i, v, Rp, yr, yi);
+    VT tr = c1 * yr, ti = c1 * yi;
+    if (!FIRST) {
+        tr -= tprev[2 * idx];
+        ti -= tprev[2 * idx + 1];
+    }
+    tnext[2 * idx] = tr;
+    tnext[2 * idx + 1] = ti;
+    acc[2 * idx] += (VT)(cr * (double)tr - ci * (double)ti);
+    acc[2 * idx + 1] += (VT)(cr * (double)ti + ci * (double)tr);
 }
 
 // One term of the propagator series: tnext = c1 (H - b) tcur - tprev (tprev
@@ -181,7 +272,6 @@ tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision
     TBK_CHECK(ly.pl.cfg.doubling == 0, TBK_ERR_INVALID_ARG,
               "the doubling identities need the same left and right vectors; VAC moments use the direct form");
     TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "VAC conductivity takes one structure");
-    TBK_CHECK(!ly.pl.block, TBK_ERR_UNSUPPORTED, "VAC conductivity takes scalar (SELL/CSR) Hamiltonians");
     TBK_CHECK(h->fmt != TBK_CSR_F64 || h->slice == 1, TBK_ERR_INVALID_ARG, "CSR needs slice 1");
     const size_t elem = precision == TBK_PREC_C32 ? sizeof(float) : sizeof(double);
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -219,17 +309,38 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
     }
     const double pr = std::cos(b * dt / kHbar), pi = -std::sin(b * dt / kHbar);   // exp(-i b dt / hbar)
 
+    const bool blk = pl.block;
+    const int32_t norb = pl.norb;
+    auto term = [&](bool first, VT c1, const VT *tcur, const VT *tprev, VT *tnext, int32_t k) {
+        if (blk) {
+            if (first)
+                k_evolve_term_blk<VT, true><<<g, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
+                                                                        tnext, acc, cre[k], cim[k], n, Rp);
+            else
+                k_evolve_term_blk<VT, false><<<g, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
+                                                                         tnext, acc, cre[k], cim[k], n, Rp);
+        } else {
+            if (first)
+                k_evolve_term<VT, true><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext, acc,
+                                                                    cre[k], cim[k], n, Rp);
+            else
+                k_evolve_term<VT, false><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext,
+                                                                     acc, cre[k], cim[k], n, Rp);
+        }
+    };
+    auto apply_v = [&](const VT *x, VT *y) {
+        if (blk) k_apply_velocity_blk<VT><<<g, kLsqtThreads, 0, s>>>(sv, norb, vx, x, n, Rp, y);
+        else k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, x, n, Rp, y);
+    };
+
     auto evolve = [&](VT *psi) -> tbk_status {
         k_cscale<VT><<<g, kLsqtThreads, 0, s>>>(psi, cre[0], cim[0], nv, acc);
-        if (n_cheb > 1)
-            k_evolve_term<VT, true><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, (VT)(1.0 / a), psi, nullptr,
-                                                                e1, acc, cre[1], cim[1], n, Rp);
+        if (n_cheb > 1) term(true, (VT)(1.0 / a), psi, nullptr, e1, 1);
         for (int32_t k = 2; k < n_cheb; ++k) {
             const VT *tcur = (k & 1) ? e2 : e1;
             const VT *tprev = k == 2 ? psi : ((k & 1) ? e1 : e2);
             VT *tnext = (k & 1) ? e1 : e2;
-            k_evolve_term<VT, false><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, (VT)(2.0 / a), tcur, tprev,
-                                                                 tnext, acc, cre[k], cim[k], n, Rp);
+            term(false, (VT)(2.0 / a), tcur, tprev, tnext, k);
         }
         k_cscale<VT><<<g, kLsqtThreads, 0, s>>>(acc, pr, pi, nv, psi);
         TBK_HIP(hipGetLastError());
@@ -237,10 +348,10 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
     };
 
     k_permute_in<VT><<<g, kLsqtThreads, 0, s>>>(r, h->perm, n, R, Rp, phiR);
-    k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, phiR, n, Rp, phiL);
+    apply_v(phiR, phiL);
     TBK_HIP(hipGetLastError());
     for (int32_t j = 0; j < n_t; ++j) {
-        k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, phiR, n, Rp, wv);
+        apply_v(phiR, wv);
         TBK_HIP(hipGetLastError());
         tbk_status st = run_plan(h, pl, a, b, nullptr, R, M, precision, work, nu + (int64_t)j * R * M, s, wv, phiL);
         if (st != TBK_OK) return st;
@@ -280,8 +391,12 @@ extern "C" tbk_status tb_build_velocity(const double *pos, const double box[3], 
     TBK_CHECK(pos && box && periodic && h && vx, TBK_ERR_INVALID_ARG, "NULL argument");
     TBK_CHECK(axis >= 0 && axis <= 2, TBK_ERR_INVALID_ARG, "axis = %d not in {0, 1, 2}", axis);
     TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "the velocity operator is built for one structure");
-    TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_SELL_F32, TBK_ERR_UNSUPPORTED,
-              "the velocity operator is built for scalar (SELL/CSR) Hamiltonians");
+    TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_SELL_F32 ||
+                  h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32,
+              TBK_ERR_INVALID_ARG, "unknown format %d", h->fmt);
+    const bool blk = h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32;
+    TBK_CHECK(!blk || ((h->n_orb == 4 || h->n_orb == 9) && h->n_rows % h->n_orb == 0), TBK_ERR_INVALID_ARG,
+              "a block Hamiltonian has 4 or 9 orbital rows per atom (n_orb = %d)", h->n_orb);
     TBK_CHECK(h->ptr && h->col && h->val && h->perm, TBK_ERR_INVALID_ARG, "a Hamiltonian array is NULL");
     TBK_CHECK(!periodic[axis] || (std::isfinite(box[axis]) && box[axis] > 0), TBK_ERR_INVALID_ARG,
               "periodic length along axis %d must be positive", axis);
@@ -290,7 +405,18 @@ extern "C" tbk_status tb_build_velocity(const double *pos, const double box[3], 
     const SellView sv{h->ptr, h->col, log2_of(h->fmt == TBK_CSR_F64 ? 1 : h->slice)};
     const unsigned g = (unsigned)ceil_div(h->n_rows, kLsqtThreads);
     const int32_t n_orb = h->n_orb >= 1 ? h->n_orb : 1;
-    if (h->fmt == TBK_SELL_F32)
+    if (blk) {
+        const int64_t na = h->n_rows / n_orb;
+        const unsigned ga = (unsigned)ceil_div(na, kLsqtThreads);
+        if (h->fmt == TBK_BSELL4_F32)
+            k_velocity_blk<float><<<ga, kLsqtThreads, 0, s>>>(sv, static_cast<const float *>(h->val), h->perm, n_orb,
+                                                              pos, na, box[axis], periodic[axis], axis,
+                                                              static_cast<float *>(vx));
+        else
+            k_velocity_blk<double><<<ga, kLsqtThreads, 0, s>>>(sv, static_cast<const double *>(h->val), h->perm,
+                                                               n_orb, pos, na, box[axis], periodic[axis], axis,
+                                                               static_cast<double *>(vx));
+    } else if (h->fmt == TBK_SELL_F32)
         k_velocity<float><<<g, kLsqtThreads, 0, s>>>(sv, static_cast<const float *>(h->val), h->perm, n_orb, pos,
                                                      h->n_rows, box[axis], periodic[axis], axis,
                                                      static_cast<float *>(vx));

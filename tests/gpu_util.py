@@ -48,6 +48,39 @@ def entries_in_atom_order(H, values=None):
     return np.array(rows), np.array(cols), np.array(vals), onsite
 
 
+def block_entries(H, values=None):
+    """(rows, cols, vals, onsite) in the caller's orbital order from a block Hamiltonian;
+    `values` (a tensor in H's block value layout, e.g. velocity coefficients) replaces H's values."""
+    t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
+    no = H.st.n_orb
+    n_at = H.n_rows // no
+    C = H.st.slice
+    ptr, col, perm = t["ptr"], t["col"], t["perm"]
+    nv = no * no * H.st.n_entries
+    with np.errstate(invalid="ignore"):      # lanes past the last atom of the last slice are never written
+        val = t["val"][:nv].astype(np.float64).reshape(-1, no, no)
+        other = None if values is None else values.cpu().numpy()[:nv].astype(np.float64).reshape(-1, no, no)
+    rows, cols, vals = [], [], []
+    for sl in range(ptr.shape[0] - 1):
+        w = (ptr[sl + 1] - ptr[sl]) // C
+        for lane in range(C):
+            r = sl * C + lane
+            if r >= n_at:
+                break
+            for k in range(w):
+                q = ptr[sl] + k * C + lane
+                c = col[q]
+                if c == r and not val[q].any():
+                    continue                     # padding block
+                rr = perm[no * r + np.arange(no)]
+                cc = perm[no * c + np.arange(no)]
+                rows.append(np.repeat(rr, no)); cols.append(np.tile(cc, no))
+                vals.append((val[q] if other is None else other[q]).reshape(-1))
+    onsite = np.empty(H.n_rows)
+    onsite[perm] = t["onsite"].astype(np.float64)
+    return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), onsite
+
+
 def csr_entries(csr):
     rows = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
     return rows, csr.col.astype(np.int64), csr.val

@@ -113,41 +113,13 @@ def test_sk_uniform_width_12_shapes(vpt, tpb, nt, xr):
     assert G.rel_l2(O.kpm_dos(mu.cpu().numpy().mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
 
 
-def block_entries(H):
-    """(rows, cols, vals, onsite) in the caller's orbital order from a block Hamiltonian."""
-    t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
-    n_at = H.n_rows // 4
-    C = H.st.slice
-    ptr, col, perm = t["ptr"], t["col"], t["perm"]
-    with np.errstate(invalid="ignore"):      # lanes past the last atom of the last slice are never written
-        val = t["val"].astype(np.float64).reshape(-1, 4, 4)
-    rows, cols, vals = [], [], []
-    for sl in range(ptr.shape[0] - 1):
-        w = (ptr[sl + 1] - ptr[sl]) // C
-        for lane in range(C):
-            r = sl * C + lane
-            if r >= n_at:
-                break
-            for k in range(w):
-                q = ptr[sl] + k * C + lane
-                c = col[q]
-                if c == r and not val[q].any():
-                    continue                     # padding block
-                for a in range(4):
-                    for b in range(4):
-                        rows.append(perm[4 * r + a]); cols.append(perm[4 * c + b]); vals.append(val[q, a, b])
-    onsite = np.empty(H.n_rows)
-    onsite[perm] = t["onsite"].astype(np.float64)
-    return np.array(rows), np.array(cols), np.array(vals), onsite
-
-
 @pytest.mark.parametrize("fmt,slice", [("bsell4_f64", 16), ("bsell4_f32", 32), ("bsell4_f64", 1)])
 def test_block_builder_matches_oracle(fmt, slice):
     s = synth.graphene_sheet(9, 7, 0.08, 21)
     H = build(s, fmt, slice)
     assert H.st.n_rows == 4 * s.n and H.st.n_orb == 4 and H.st.max_degree == 3
     csr = oracle_csr(s)
-    rows, cols, vals, onsite = block_entries(H)
+    rows, cols, vals, onsite = G.block_entries(H)
     orow, ocol, oval = G.csr_entries(csr)
     o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
     np.testing.assert_array_equal(rows[o1], orow[o2])
@@ -205,8 +177,26 @@ def test_block_rejections():
     a, b = H.scale()
     r = G.to_dev(synth.random_phase(4 * s.n, 1, 2))
     with pytest.raises(tbkpm.TBKError) as e:
-        tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
-    assert e.value.name == "UNSUPPORTED"
-    with pytest.raises(tbkpm.TBKError) as e:
         tbkpm.kpm_moments(H, a, b, r, 16, "f64", config=tbkpm.make_config(1, 2, 1, 0, 1, uniform_values=1))
     assert e.value.name == "INVALID_ARG"
+
+
+@pytest.mark.parametrize("atom", [0, 1])
+def test_block_vac_moments_match_oracle(atom):
+    s = synth.graphene_sheet(6, 5, 0.07, 9)
+    csr = oracle_csr(s)
+    H = build(s, "bsell4_f64", 16)
+    a, b = H.scale()
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 1)
+    rows, cols, vals, _ = G.block_entries(H, vx)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 1, n_orb=4)
+    orow, ocol, _ = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_allclose(vals[o1], vo[o2], rtol=1e-15, atol=1e-15 * np.abs(vo).max())
+    r = synth.random_phase(4 * s.n, 2, 5)
+    M, n_t, dt = 40, 3, 0.3
+    nc = tbkpm.chebyshev_terms(a, dt)
+    cfg = tbkpm.make_config(1, 2, 1, 0, 1, atom_rows=atom)
+    nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, config=cfg).cpu().numpy()
+    nuo = O.vac_moments(csr, vo, a, b, r, M, n_t, dt, nc)
+    assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()

@@ -35,35 +35,6 @@ def oracle_csr(s):
     return O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED)[0]
 
 
-def block_entries(H):
-    """(rows, cols, vals, onsite) in the caller's orbital order from a block Hamiltonian."""
-    t = {k: v.cpu().numpy() for k, v in H.tensors.items()}
-    no = H.st.n_orb
-    n_at = H.n_rows // no
-    C = H.st.slice
-    ptr, col, perm = t["ptr"], t["col"], t["perm"]
-    with np.errstate(invalid="ignore"):      # lanes past the last atom of the last slice are never written
-        val = t["val"][: no * no * H.st.n_entries].astype(np.float64).reshape(-1, no, no)
-    rows, cols, vals = [], [], []
-    for sl in range(ptr.shape[0] - 1):
-        w = (ptr[sl + 1] - ptr[sl]) // C
-        for lane in range(C):
-            r = sl * C + lane
-            if r >= n_at:
-                break
-            for k in range(w):
-                q = ptr[sl] + k * C + lane
-                c = col[q]
-                if c == r and not val[q].any():
-                    continue                     # padding block
-                rr = perm[no * r + np.arange(no)]
-                cc = perm[no * c + np.arange(no)]
-                rows.append(np.repeat(rr, no)); cols.append(np.tile(cc, no)); vals.append(val[q].reshape(-1))
-    onsite = np.empty(H.n_rows)
-    onsite[perm] = t["onsite"].astype(np.float64)
-    return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), onsite
-
-
 @pytest.mark.parametrize("fmt,slice", [("sell_f64", 16), ("sell_f32", 64), ("csr_f64", 1),
                                        ("bsell4_f64", 16), ("bsell4_f32", 32), ("bsell4_f64", 1)])
 @pytest.mark.parametrize("reorder", [True, False])
@@ -74,7 +45,7 @@ def test_spd_builder_matches_oracle(fmt, slice, reorder):
     csr = oracle_csr(s)
     if fmt.startswith("bsell4"):
         assert H.st.max_degree == 3
-        rows, cols, vals, onsite = block_entries(H)
+        rows, cols, vals, onsite = G.block_entries(H)
     else:
         assert H.st.max_degree == 27
         rows, cols, vals, onsite = G.entries_in_atom_order(H)
@@ -159,3 +130,50 @@ def test_spd_orbital_count_rejected():
     rc = tbkpm.lib().tbk_hamiltonian_size_sk(pos.data_ptr(), sp.data_ptr(), s.n, boxa, per, ctypes.byref(sk),
                                              ctypes.byref(st), None)
     assert rc == 1                               # TBK_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("fmt,slice,axis", [("bsell4_f64", 16, 0), ("bsell4_f64", 1, 1), ("bsell4_f32", 32, 0)])
+def test_spd_block_velocity_matches_oracle(fmt, slice, axis):
+    s = synth.graphene_sheet(5, 4, 0.07, 9)
+    H = build(s, fmt, slice)
+    csr = oracle_csr(s)
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, axis)
+    rows, cols, vals, _ = G.block_entries(H, vx)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, axis, n_orb=9)
+    orow, ocol, _ = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_array_equal(cols[o1], ocol[o2])
+    tol = 1e-6 if fmt.endswith("f32") else 1e-15
+    np.testing.assert_allclose(vals[o1], vo[o2], rtol=tol, atol=tol * np.abs(vo).max())
+
+
+@pytest.mark.parametrize("atom", [0, 1])
+def test_spd_block_vac_moments_match_oracle(atom):
+    s = synth.graphene_sheet(5, 4, 0.07, 9)
+    csr = oracle_csr(s)
+    H = build(s, "bsell4_f64", 16)
+    a, b = H.scale()
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0, n_orb=9)
+    r = synth.random_phase(9 * s.n, 2, 5)
+    M, n_t, dt = 40, 3, 0.3
+    nc = tbkpm.chebyshev_terms(a, dt)
+    cfg = tbkpm.make_config(1, 2, 1, 0, 1, atom_rows=atom)
+    nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, config=cfg).cpu().numpy()
+    nuo = O.vac_moments(csr, vo, a, b, r, M, n_t, dt, nc)
+    assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()
+
+
+def test_spd_block_and_scalar_c32_vac_agree():
+    s = synth.graphene_sheet(8, 7, 0.05, 12)
+    Hb = build(s, "bsell4_f32", 64)
+    Hs = build(s, "sell_f32", 64)
+    a, b = Hb.scale()
+    pos = G.to_dev(s.pos)
+    vb = tbkpm.build_velocity(Hb, pos, s.box, s.periodic, 0)
+    vs = tbkpm.build_velocity(Hs, pos, s.box, s.periodic, 0)
+    r = G.to_dev(synth.random_phase(9 * s.n, 4, 6, np.complex64))
+    M, n_t, dt = 64, 4, 0.5
+    nb = tbkpm.vac_moments(Hb, vb, a, b, r, M, n_t, dt).cpu().numpy()
+    ns = tbkpm.vac_moments(Hs, vs, a, b, r, M, n_t, dt).cpu().numpy()
+    assert np.abs(nb - ns).max() <= 1e-4 * np.abs(ns).max()
