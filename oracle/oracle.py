@@ -77,8 +77,8 @@ def _lib():
     L.orc_integrated_dos.argtypes = [_f64p, _i32, _f64, _f64, _i32, _f64p, _i32, _f64p]
     L.orc_mobility.restype = ctypes.c_int
     L.orc_mobility.argtypes = [_f64p, _i32, _i32, _i32, _f64p, _f64, _f64p, _f64p, _f64p]
-    L.orc_assemble_sk.argtypes = [_i64, _f64p, _f64p, _i32p, _i64, _i32p, _i32p, _i32, _f64p, _f64p, _f64, _f64,
-                                  _i64p, _i32p, _f64p, _f64p]
+    L.orc_assemble_sk.argtypes = [_i64, _f64p, _f64p, _i32p, _i64, _i32p, _i32p, _i32, _f64p, ctypes.c_void_p,
+                                  _f64p, _f64, _f64, _i64p, _i32p, _f64p, _f64p]
     L.orc_splitmix64.restype = ctypes.c_uint64
     L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     L.orc_random_phase.restype = None
@@ -318,10 +318,12 @@ def mobility(sigma, N, n_ref):
     return ssc, car, mob
 
 
-def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None, e_d=0.0):
+def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None, e_d=0.0,
+                   scale=None):
     """Slater-Koster orbital Hamiltonian as a CSR: v holds 4 integrals (s, p: orbital 4 i + a,
     a = s, x, y, z) or 10 (s, p, d: orbital 9 i + a, then dxy, dyz, dzx, dx2-y2, d3z2-r2)
-    at r0.  Returns (csr, pairs)."""
+    at r0; scale [npairs][len(v)] (optional) multiplies each pair's integrals (learned form).
+    Returns (csr, pairs)."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     if pairs is None:
         pairs = neighbor_pairs(pos, box, periodic, r_cut)
@@ -336,9 +338,15 @@ def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.3
     col = np.empty(2 * norb * norb * npairs, np.int32)
     val = np.empty(2 * norb * norb * npairs)
     diag = np.empty(norb * n)
+    sc = None
+    if scale is not None:
+        scale = np.asarray(scale, np.float64).reshape(npairs, -1)
+        sc = np.ones((npairs, 10))
+        sc[:, : scale.shape[1]] = scale
     rc = _lib().orc_assemble_sk(n, _c(pos, np.float64).reshape(-1), _c(box, np.float64), _c(periodic, np.int32),
-                                npairs, pi, pj, norb, v10, np.array([e_s, e_p, e_d], np.float64), float(r0),
-                                float(beta), row_ptr, col, val, diag)
+                                npairs, pi, pj, norb, v10, None if sc is None else sc.ctypes.data,
+                                np.array([e_s, e_p, e_d], np.float64), float(r0), float(beta), row_ptr, col, val,
+                                diag)
     if rc != 0:
         raise OracleError("orc_assemble_sk failed")
     return CSR(row_ptr, col, val, diag), pairs

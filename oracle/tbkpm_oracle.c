@@ -917,13 +917,17 @@ static void orc_sk_table(const double c[3], const double v[10], double E[9][9])
  * f = exp(-beta (r/r0 - 1)) give H[norb i + a][norb j + b] = f E(d/r)[a][b]
  * and H[norb j + b][norb i + a] = the same number (E(-c) = E(c)^T).  v holds
  * the ten integrals of orc_sk_table at r0 (only the first four enter when
- * norb = 4); onsite e = {e_s, e_p, e_d}.  CSR of the off-diagonal part
- * (row_ptr [norb n + 1], col/val [2 norb^2 npairs], columns ascending);
- * diag [norb n].  Returns 0, -1 on a bad norb, -2 when out of memory.
+ * norb = 4); onsite e = {e_s, e_p, e_d}.  With scale (NULL = none, else
+ * [npairs][10]) pair p uses the integrals v[l] scale[p][l] instead of v[l]:
+ * the learned form of Eq. (2), where each bond's two-centre integrals are
+ * network outputs (here v[l] (1 + y_l) with y_l the output of network l), the
+ * angular factors unchanged.  CSR of the off-diagonal part (row_ptr
+ * [norb n + 1], col/val [2 norb^2 npairs], columns ascending); diag [norb n].
+ * Returns 0, -1 on a bad norb, -2 when out of memory.
  */
 int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int32_t periodic[3],
                     int64_t npairs, const int32_t *pi, const int32_t *pj, int32_t norb, const double v[10],
-                    const double e[3], double r0, double beta,
+                    const double *scale, const double e[3], double r0, double beta,
                     int64_t *row_ptr, int32_t *col, double *val, double *diag)
 {
     if (norb != 4 && norb != 9) return -1;
@@ -941,7 +945,9 @@ int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int
         double d[3], E[9][9], c[3];
         double r = orc_displacement(pos, i, j, box, periodic, d);
         for (int k = 0; k < 3; ++k) c[k] = d[k] / r;
-        orc_sk_table(c, v, E);
+        double vp[10];
+        for (int l = 0; l < 10; ++l) vp[l] = scale ? v[l] * scale[10 * p + l] : v[l];
+        orc_sk_table(c, vp, E);
         double f = exp(-beta * (r / r0 - 1.0));
         for (int a = 0; a < norb; ++a)
             for (int b = 0; b < norb; ++b) {

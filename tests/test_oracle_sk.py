@@ -149,3 +149,57 @@ def test_spd_mirror_parity_and_sp_restriction():
     h4, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10[:4], ES, EP)
     sp = (np.arange(s.n)[:, None] * 9 + np.arange(4)).ravel()
     np.testing.assert_allclose(H[np.ix_(sp, sp)], h4.dense(), atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Learned form of Eq. (2): per-bond scales of the two-centre integrals
+# ---------------------------------------------------------------------------
+
+def test_unit_scales_reproduce_the_plain_table():
+    s = synth.graphene_sheet(3, 2, 0.1, 7)
+    plain, pairs = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED)
+    ones, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED, pairs=pairs,
+                               scale=np.ones((pairs[0].shape[0], 10)))
+    np.testing.assert_array_equal(plain.val, ones.val)
+    np.testing.assert_array_equal(plain.col, ones.col)
+
+
+def test_scaled_spd_dimer_puts_each_scale_on_its_integral():
+    """Dimer along z: each textbook entry carries the scale of its own integral (a swapped
+    integral index moves a scale onto the wrong entries)."""
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.42]])
+    sc = np.array([1.5, 0.5, 2.0, 0.25, 3.0, 0.75, 1.25, 0.6, 1.8, 2.5])
+    csr, _ = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V10, ES, EP, e_d=ED, scale=sc[None, :])
+    H = csr.dense()[0:9, 9:18]
+    ss, sp, pps, ppp, sd, pds, pdp, dds, ddp, ddd = V10 * sc
+    want = np.zeros((9, 9))
+    want[0, 0], want[0, 3], want[0, 8] = ss, sp, sd
+    want[3, 0], want[8, 0] = -sp, sd
+    want[1, 1] = want[2, 2] = ppp
+    want[3, 3] = pps
+    want[3, 8], want[8, 3] = pds, -pds
+    want[1, 6], want[6, 1] = pdp, -pdp
+    want[2, 5], want[5, 2] = pdp, -pdp
+    want[8, 8] = dds
+    want[5, 5] = want[6, 6] = ddp
+    want[4, 4] = want[7, 7] = ddd
+    np.testing.assert_allclose(H, want, atol=1e-14)
+    np.testing.assert_allclose(np.diag(csr.dense())[:9], [ES, EP, EP, EP, ED, ED, ED, ED, ED])
+
+
+def test_per_pair_scales_keep_h_symmetric_and_linear():
+    """Distinct scales on every pair: H stays symmetric (both entries of a pair scaled
+    alike), and H is the sum over integrals of the one-integral Hamiltonians with the
+    same per-pair scales (the scales enter linearly, one per integral)."""
+    s = synth.graphene_sheet(3, 3, 0.12, 2)
+    pairs = O.neighbor_pairs(s.pos, s.box, s.periodic, 2.0)
+    rng = np.random.default_rng(1)
+    sc = rng.uniform(0.5, 1.5, (pairs[0].shape[0], 10))
+    H = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, 0.0, 0.0, pairs=pairs, scale=sc)[0].dense()
+    np.testing.assert_allclose(H, H.T, atol=1e-14)
+    total = np.zeros_like(H)
+    for lam in range(10):
+        v1 = np.zeros(10)
+        v1[lam] = V10[lam]
+        total += O.sk_hamiltonian(s.pos, s.box, s.periodic, v1, 0.0, 0.0, pairs=pairs, scale=sc)[0].dense()
+    np.testing.assert_allclose(H, total, atol=1e-13)
