@@ -81,6 +81,27 @@ def block_entries(H, values=None):
     return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), onsite
 
 
+def oracle_ab(csr, margin=1.01):
+    """(a, b) from the oracle's Gershgorin bounds of csr: the scale a parity test gives
+    both sides (the GPU's own bounds are tested against the same oracle bounds)."""
+    from oracle import oracle as O
+    lo, hi = O.gershgorin(csr)
+    return margin * (hi - lo) / 2.0, (hi + lo) / 2.0
+
+
+def oracle_ab_of(s, margin=1.01):
+    """oracle_ab of the one-orbital Hamiltonian of structure s."""
+    from oracle import oracle as O
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    return oracle_ab(csr, margin)
+
+
+def oracle_scales(structures, margin=1.01):
+    """Lists (a, b) of oracle_ab_of over stacked structures."""
+    ab = [oracle_ab_of(s, margin) for s in structures]
+    return [x[0] for x in ab], [x[1] for x in ab]
+
+
 def csr_entries(csr):
     rows = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
     return rows, csr.col.astype(np.int64), csr.val

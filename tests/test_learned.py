@@ -68,21 +68,27 @@ def test_descriptor_and_bonds_match_oracle():
         np.testing.assert_allclose(br[m], hop[2], rtol=1e-15)
 
 
+def oracle_moments(ss):
+    """Mean and standard deviation of the oracle's raw bond features over the structures."""
+    raw = np.concatenate([O.bond_features(oracle_parts(s)[1], oracle_parts(s)[0], synth.R_DESC) for s in ss])
+    return raw.mean(0), raw.std(0)
+
+
 def test_features_moments_and_targets_match_oracle():
     ss = sheets_small()
     pos, sp, seg, boxes, v, b = gpu_parts(ss)
+    mean_o, std_o = oracle_moments(ss)
     mean, std = tbkpm.feature_moments(b, v, synth.R_DESC)
-    X = bf16_bits_to_float(tbkpm.bond_features(b, v, mean, std, synth.R_DESC))
+    np.testing.assert_allclose(mean, mean_o, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(std, std_o, rtol=1e-8, atol=1e-12)
+    # both sides standardise with the oracle's moments
+    X = bf16_bits_to_float(tbkpm.bond_features(b, v, mean_o, std_o, synth.R_DESC))
     y = tbkpm.coordination_target(b, v, synth.COORD_KAPPA, synth.COORD_Z0).cpu().numpy()
-    raw, Xo, yo = [], [], []
+    Xo, yo = [], []
     for s in ss:
         vo, hop = oracle_parts(s)
-        raw.append(O.bond_features(hop, vo, synth.R_DESC))
-        Xo.append(O.bf16(O.bond_features(hop, vo, synth.R_DESC, mean, std)))
+        Xo.append(O.bf16(O.bond_features(hop, vo, synth.R_DESC, mean_o, std_o)))
         yo.append(O.target_scale(hop, vo, synth.COORD_KAPPA, synth.COORD_Z0) - 1.0)
-    raw = np.concatenate(raw)
-    np.testing.assert_allclose(mean, raw.mean(0), rtol=1e-10, atol=1e-12)
-    np.testing.assert_allclose(std, raw.std(0), rtol=1e-8, atol=1e-12)
     Xo = np.concatenate(Xo)
     mism = X != Xo
     assert mism.mean() <= 1e-4
@@ -177,7 +183,7 @@ def test_learned_assembly_matches_oracle():
     ss = sheets_small()
     p = synth.init_mlp_params(21, out_scale=1.0)
     pos, sp, seg, boxes, v, b = gpu_parts(ss)
-    mean, std = tbkpm.feature_moments(b, v, synth.R_DESC)
+    mean, std = oracle_moments(ss)
     H = tbkpm.build_hamiltonian_learned(G.to_dev(pos), G.to_dev(sp), seg, boxes, PER, [0.0], [[-2.7]],
                                         G.to_dev(p), mean, std, fmt="sell_f64", slice=32, with_bond_y=True)
     rows, cols, vals, _ = G.entries_in_atom_order(H)

@@ -62,7 +62,7 @@ def test_batched_builder_per_structure(fmt, slice):
 def test_batched_fp64_moments_per_structure(R, tpb, nt, persistent):
     sheets, pos, sp, seg, boxes = make_batch()
     H = build(pos, sp, seg, boxes, "sell_f64", 16)
-    a, b = H.scales()
+    a, b = G.oracle_scales(sheets)
     M = 64
     r = synth.random_phase(pos.shape[0], R, 11)
     cfg = tbkpm.make_config(1, tpb, nt, 0, 1, persistent)
@@ -91,7 +91,7 @@ def test_batched_equals_single_structure_calls():
 def test_batched_c32_dos(persistent):
     sheets, pos, sp, seg, boxes = make_batch([(30, 26, 0.05), (11, 19, 0.07), (45, 40, 0.02)])
     H = build(pos, sp, seg, boxes, "sell_f32", 64)
-    a, b = H.scales()
+    a, b = G.oracle_scales(sheets)
     M = 256
     r = synth.random_phase(pos.shape[0], 8, 13, np.complex64)
     mu = tbkpm.kpm_moments_batched(H, a, b, G.to_dev(r), M, "c32",

@@ -32,7 +32,7 @@ def _dbl(vpt=1, tpb=2, nt=1, xr=0, rpt=1):
 def test_fp64_doubling_matches_direct_oracle(M, R, fmt, slice):
     s = synth.graphene_sheet(23, 17, 0.06, 29)          # 1564 rows: ragged tail
     H = G.build(s, fmt=fmt, slice=slice)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     r = synth.random_phase(s.n, R, 31)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), M, "f64", config=_dbl()).cpu().numpy()
     assert mu.shape == (R, M)
@@ -43,7 +43,7 @@ def test_fp64_doubling_matches_direct_oracle(M, R, fmt, slice):
 def test_fp64_doubling_every_shape(tpb, nt, xr, rpt):
     s = synth.graphene_sheet(19, 13, 0.15, 77)          # irregular widths
     H = G.build(s, fmt="sell_f64", slice=64)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     r = synth.random_phase(s.n, 4, 4)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=_dbl(1, tpb, nt, xr, rpt)).cpu().numpy()
     assert np.abs(mu - _oracle_mu(s, a, b, r, 61)).max() <= 1e-10 * s.n
@@ -52,7 +52,7 @@ def test_fp64_doubling_every_shape(tpb, nt, xr, rpt):
 def test_fp64_doubling_onsite_and_shift():
     s = synth.hbn_stripes(20, 18, stripe_cells=4, sigma=0.03, seed=6)
     H = G.build(s, fmt="sell_f64", slice=16)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     assert b != 0.0
     r = synth.random_phase(s.n, 4, 8)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 128, "f64", config=_dbl()).cpu().numpy()
@@ -63,7 +63,7 @@ def test_fp64_doubling_onsite_and_shift():
 def test_c32_doubling_dos_within_1e_4(R, vpt):
     s = synth.graphene_sheet(31, 29, 0.05, 41)
     H = G.build(s, fmt="sell_f32", slice=64)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     M = 300
     r = synth.random_phase(s.n, R, 3, np.complex64)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), M, "c32", config=_dbl(vpt)).cpu().numpy()
@@ -91,7 +91,7 @@ def test_doubling_isolated_rows_closed_form():
 def test_doubling_guard_and_batched_rejection():
     s = synth.graphene_sheet(10, 10, 0.05, 4)
     H = G.build(s, fmt="sell_f64", slice=64)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     r = G.to_dev(synth.random_phase(s.n, 1, 2))
     with pytest.raises(tbkpm.TBKError) as e:
         tbkpm.kpm_moments(H, 0.5 * a, b, r, 128, config=_dbl())

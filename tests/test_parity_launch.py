@@ -33,7 +33,7 @@ def test_fp64_every_shape_matches_oracle(sigma, slice, R):
     H = G.build(s, fmt="sell_f64", slice=slice)
     if sigma == 0.15:
         assert H.st.max_degree > 3                         # irregular widths
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     M = 48
     r = synth.random_phase(s.n, R, 4)
     mu_o = _oracle_mu(s, a, b, r, M)
@@ -51,7 +51,7 @@ def test_fp64_every_shape_matches_oracle(sigma, slice, R):
 def test_c32_shapes_agree(R, vpt):
     s = synth.hbn_stripes(22, 15, stripe_cells=5, sigma=0.12, seed=3)
     H = G.build(s, fmt="sell_f32", slice=16)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     M = 64
     r = synth.random_phase(s.n, R, 9, np.complex64)
     mu_o = _oracle_mu(s, a, b, r, M)
@@ -75,7 +75,7 @@ def test_autotune_choice_is_valid_and_cached(tmp_path, monkeypatch):
     assert again.from_cache == 1 and again.slice == res.slice
     H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32",
                                 slice=res.slice)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     r = synth.random_phase(s.n, 4, 2, np.complex64)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 100, "c32", config=res.config).cpu().numpy()
     mu_o = _oracle_mu(s, a, b, r, 100)

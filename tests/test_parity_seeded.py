@@ -35,7 +35,7 @@ def test_phases_match_oracle(n, R):
 def test_seeded_fp64_moments_match_oracle(fields, R):
     s = synth.graphene_sheet(23, 17, 0.06, 29)
     H = G.build(s, fmt="sell_f64", slice=32)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     cfg = tbkpm.make_config(1, 2, 1, 0, 1, **fields)
     mu = tbkpm.kpm_moments_seeded(H, a, b, SEED, R, 97, "f64", config=cfg).cpu().numpy()
     csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
@@ -50,7 +50,7 @@ def test_seeded_fp64_moments_match_oracle(fields, R):
 def test_seeded_c32_dos_and_row_order():
     s = synth.hbn_stripes(20, 18, stripe_cells=4, sigma=0.03, seed=6)
     H = G.build(s, fmt="sell_f32", slice=64)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     mu = tbkpm.kpm_moments_seeded(H, a, b, SEED, 8, 256, "c32").cpu().numpy()
     csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
     mo, _ = O.kpm_moments(csr, a, b, O.random_phase(s.n, 8, SEED), 256)

@@ -54,7 +54,7 @@ def test_sk_fp64_moments_and_c32_dos(R):
     s = synth.graphene_sheet(13, 11, 0.06, 4)
     csr = oracle_csr(s)
     H = build(s, "sell_f64", 32)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     r = synth.random_phase(4 * s.n, R, 7)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 96, "f64").cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r, 96)
@@ -71,7 +71,7 @@ def test_sk_vac_moments_match_oracle():
     s = synth.graphene_sheet(6, 5, 0.07, 9)
     csr = oracle_csr(s)
     H = build(s, "sell_f64", 16)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 1)
     rows, cols, vals, _ = G.entries_in_atom_order(H, vx)
     vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 1, n_orb=4)
@@ -105,7 +105,7 @@ def test_sk_uniform_width_12_shapes(vpt, tpb, nt, xr):
     csr = oracle_csr(s)
     H = build(s, "sell_f32", 64)
     assert H.st.max_degree == 12 and H.st.n_entries == 12 * 64 * (-(-4 * s.n // 64))   # slices of 64 rows
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     r = synth.random_phase(4 * s.n, 8, 3, np.complex64)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 200, "c32", config=tbkpm.make_config(vpt, tpb, nt, xr, 1))
     mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 200)
@@ -137,7 +137,7 @@ def test_block_fp64_moments(R, tpb, nt, xr, dbl, atom):
     s = synth.graphene_sheet(13, 11, 0.06, 4)        # 2288 orbital rows: ragged tiles
     csr = oracle_csr(s)
     H = build(s, "bsell4_f64", 32)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     r = synth.random_phase(4 * s.n, R, 7)
     cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=atom)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
@@ -152,7 +152,7 @@ def test_block_c32_dos_and_scalar_agreement(R, vpt, atom):
     csr = oracle_csr(s)
     Hb = build(s, "bsell4_f32", 64)
     Hs = build(s, "sell_f32", 64)
-    a, b = Hb.scale()
+    a, b = G.oracle_ab(csr)
     r = synth.random_phase(4 * s.n, R, 3, np.complex64)
     cfg = tbkpm.make_config(vpt, 2, 1, 0, 1, atom_rows=atom)
     mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
@@ -186,7 +186,7 @@ def test_block_vac_moments_match_oracle(atom):
     s = synth.graphene_sheet(6, 5, 0.07, 9)
     csr = oracle_csr(s)
     H = build(s, "bsell4_f64", 16)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 1)
     rows, cols, vals, _ = G.block_entries(H, vx)
     vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 1, n_orb=4)

@@ -75,7 +75,7 @@ def test_spd_fp64_moments(fmt, R, tpb, nt, xr, dbl, atom):
     s = synth.graphene_sheet(9, 7, 0.06, 4)          # 2268 orbital rows: ragged tiles
     csr = oracle_csr(s)
     H = build(s, fmt, 32)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     r = synth.random_phase(9 * s.n, R, 7)
     cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=atom)
     mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
@@ -90,7 +90,7 @@ def test_spd_c32_dos_block_and_scalar(R, vpt, atom):
     csr = oracle_csr(s)
     Hb = build(s, "bsell4_f32", 64)
     Hs = build(s, "sell_f32", 64)
-    a, b = Hb.scale()
+    a, b = G.oracle_ab(csr)
     r = synth.random_phase(9 * s.n, R, 3, np.complex64)
     cfg = tbkpm.make_config(vpt, 2, 1, 0, 1, atom_rows=atom)
     mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
@@ -105,7 +105,7 @@ def test_spd_vac_moments_match_oracle():
     s = synth.graphene_sheet(5, 4, 0.07, 9)
     csr = oracle_csr(s)
     H = build(s, "sell_f64", 16)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
     rows, cols, vals, _ = G.entries_in_atom_order(H, vx)
     vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0, n_orb=9)
@@ -152,7 +152,7 @@ def test_spd_block_vac_moments_match_oracle(atom):
     s = synth.graphene_sheet(5, 4, 0.07, 9)
     csr = oracle_csr(s)
     H = build(s, "bsell4_f64", 16)
-    a, b = H.scale()
+    a, b = G.oracle_ab(csr)
     vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
     vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0, n_orb=9)
     r = synth.random_phase(9 * s.n, 2, 5)

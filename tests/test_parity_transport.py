@@ -67,9 +67,8 @@ def test_multi_frame_workflow_matches_oracle():
     rd = synth.random_phase(n, R_dos, 10)
     Hs, scales = [], []
     for s in frames:
-        H = G.build(s, fmt="sell_f64", slice=16)
-        Hs.append(H)
-        scales.append(H.scale())
+        Hs.append(G.build(s, fmt="sell_f64", slice=16))
+        scales.append(G.oracle_ab_of(s))
     lo = max(b - 0.99 * a for a, b in scales)
     hi = min(b + 0.99 * a for a, b in scales)
     E = np.linspace(lo, hi, 301)

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 def _pair(s, R, M, fields, slice=64, precision="c32"):
     H = G.build(s, fmt="sell_f32", slice=slice)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     r = G.to_dev(synth.random_phase(s.n, R, 5, np.complex64))
     base = tbkpm.make_config(2 if R >= 2 else 1, 2, 1, 0, 1)
     m0 = tbkpm.kpm_moments(H, a, b, r, M, precision, config=base).cpu().numpy()
@@ -67,7 +67,7 @@ def test_non_uniform_hamiltonians_are_flagged_and_refused():
     H = G.build(s, fmt="sell_f32", slice=32)
     assert H.st.uniform_hop == 0
     r = G.to_dev(synth.random_phase(s.n, 1, 2, np.complex64))
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     with pytest.raises(tbkpm.TBKError) as e:
         tbkpm.kpm_moments(H, a, b, r, 16, "c32", config=tbkpm.make_config(1, 2, 1, 0, 1, 0, 0, 1))
     assert e.value.name == "INVALID_ARG"
@@ -82,7 +82,7 @@ def test_four_rows_per_thread(tpb, fields):
     thread, moments to FP64 rounding; FP64 path against the oracle."""
     s = synth.graphene_sheet(37, 23)              # 3404 rows: 13.3 tiles of 256
     H = G.build(s, fmt="sell_f32", slice=256)
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     r = G.to_dev(synth.random_phase(s.n, 1, 8, np.complex64))
     m1 = tbkpm.kpm_moments(H, a, b, r, 150, "c32", config=tbkpm.make_config(1, tpb, 1, 0, 1, **fields))
     m4 = tbkpm.kpm_moments(H, a, b, r, 150, "c32", config=tbkpm.make_config(1, tpb, 1, 0, 4, **fields))
@@ -90,7 +90,7 @@ def test_four_rows_per_thread(tpb, fields):
     if "uniform_values" not in fields:
         s64 = synth.graphene_sheet(19, 13, 0.03, 4)
         H64 = G.build(s64, fmt="sell_f64", slice=256)
-        a, b = H64.scale()
+        a, b = G.oracle_ab_of(s64)
         r64 = synth.random_phase(s64.n, 1, 9)
         mu = tbkpm.kpm_moments(H64, a, b, G.to_dev(r64), 77, "f64",
                                config=tbkpm.make_config(1, tpb, 0, 1, 4, **fields)).cpu().numpy()
@@ -109,7 +109,7 @@ def test_compact_columns_bitwise(fmt, slice, fields):
     col = H.tensors["col"].cpu().numpy().astype(np.int64)
     c16 = H.tensors["col16"].cpu().numpy()
     assert (c16[: H.st.n_entries] == -32768).any()          # some offsets escape
-    a, b = H.scale()
+    a, b = G.oracle_ab_of(s)
     prec = "c32" if fmt == "sell_f32" else "f64"
     cdt = np.complex64 if prec == "c32" else np.complex128
     r = G.to_dev(synth.random_phase(s.n, 2, 3, cdt))
