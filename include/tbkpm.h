@@ -530,6 +530,28 @@ tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, in
                                    const tbk_sk_params *sk, tbk_ham *h, double spec_bounds[2],
                                    void *stream);
 
+/*
+ * Learned Slater-Koster Hamiltonian (Eq. (2): the two-centre integrals of a
+ * bond are network outputs of its edge features, the angular factors P_lambda
+ * of the table unchanged): as tb_build_hamiltonian_sk, but bond {i, j} uses the
+ * integrals v_l (1 + y_l(ij)), l = 0 .. K-1 (K = 4 for orbitals = 4, 10 for 9,
+ * in the order of tbk_sk_params), where y_l is the output of network l on the
+ * bond's standardised features [f_0..7(r_ij) || v_i + v_j] (the inputs, the
+ * network shape and the bfloat16 products of tbk_mlp_model).  One network per
+ * integral: model->params is device float [K][TBK_MLP_PARAMS].  Onsite
+ * energies stay the fixed e_s, e_p, e_d.  bond_y (device float, capacity
+ * bond_cap >= K n_bonds, may be NULL) receives y [K][n_bonds] in tbk_bonds
+ * order (bonds i < j of the hopping cutoff sk->r_cut); *n_bonds (may be NULL)
+ * the bond count.  spec_bounds from the learned values.
+ * Errors: as tb_build_hamiltonian_sk; INVALID_ARG (incomplete model,
+ * n_radial != 8), BUFFER_TOO_SMALL (bond_y).  Synchronises `stream`.
+ */
+tbk_status tb_build_hamiltonian_sk_learned(const double *pos, const int32_t *species, int64_t n,
+                                           const double box[3], const int32_t periodic[3],
+                                           const tbk_sk_params *sk, const tbk_mlp_model *model,
+                                           tbk_ham *h, double spec_bounds[2], float *bond_y,
+                                           int64_t bond_cap, int64_t *n_bonds, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Velocity autocorrelation conductivity, Eq. (3)                            */
 /* ------------------------------------------------------------------------ */

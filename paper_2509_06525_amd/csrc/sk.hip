@@ -44,6 +44,19 @@ __global__ void k_sk_perm(int64_t n, int32_t norb, const int32_t *__restrict__ p
     perm_orb[R] = norb * perm[R / norb] + (int32_t)(R % norb);
 }
 
+// bond_ptr[i] = first bond of atom i in (i, j)-sorted bonds (lower bound of i in bi), i = 0..n.
+__global__ void k_bond_ptr(int64_t n, int64_t nb, const int32_t *__restrict__ bi, int64_t *__restrict__ bond_ptr) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int64_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (bi[mid] < i) lo = mid + 1;
+        else hi = mid;
+    }
+    bond_ptr[i] = lo;
+}
+
 struct SkValues {
     double r0, beta, e_s, e_p, e_d;
     // at r0: ss_sigma, sp_sigma, pp_sigma, pp_pi, sd_sigma, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta
@@ -110,11 +123,37 @@ __device__ __forceinline__ void sk_table(const double *v, double l, double m, do
     }
 }
 
-// The NORB x NORB block of a bond of length r and vector (dx, dy, dz) from the row atom.
+// Per-bond scales of the two-centre integrals (learned form): bonds i < j of
+// the hopping cutoff sorted by (i, j), bond_ptr[i] = first bond of atom i,
+// y[l * nb + b] = output of network l for bond b; the bond's integral l is
+// v[l] (1 + y).  y = NULL: the plain table.
+struct BondScales {
+    const int64_t *bond_ptr = nullptr;
+    const int32_t *bj = nullptr;
+    const float *y = nullptr;
+    int64_t nb = 0;
+    int32_t K = 0;
+};
+
+// The integrals of the bond {i, j} (caller's atom indices).
+__device__ __forceinline__ const double *bond_integrals(const BondScales &bs, const SkValues &sk, int32_t i,
+                                                        int32_t j, double (&vb)[10]) {
+    if (!bs.y) return sk.v;
+    const int32_t lo = min(i, j), hi = max(i, j);
+    int64_t b = -1;
+    for (int64_t q = bs.bond_ptr[lo]; q < bs.bond_ptr[lo + 1]; ++q)
+        if (bs.bj[q] == hi) { b = q; break; }
+    for (int l = 0; l < 10; ++l)
+        vb[l] = (b >= 0 && l < bs.K) ? sk.v[l] * (1.0 + (double)bs.y[(int64_t)l * bs.nb + b]) : sk.v[l];
+    return vb;
+}
+
+// The NORB x NORB block of a bond of length r and vector (dx, dy, dz) from the
+// row atom, integrals v at r0.
 template <int NORB>
-__device__ __forceinline__ void sk_block(const SkValues &sk, double r, double dx, double dy, double dz,
-                                         double (&B)[NORB][NORB]) {
-    sk_table<NORB>(sk.v, dx / r, dy / r, dz / r, B);
+__device__ __forceinline__ void sk_block(const double *v, const SkValues &sk, double r, double dx, double dy,
+                                         double dz, double (&B)[NORB][NORB]) {
+    sk_table<NORB>(v, dx / r, dy / r, dz / r, B);
     const double f = exp(-sk.beta * (r / sk.r0 - 1.0));
     for (int a = 0; a < NORB; ++a)
         for (int b = 0; b < NORB; ++b) B[a][b] *= f;
@@ -132,7 +171,7 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
                           int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                           const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                           int32_t *__restrict__ col, V *__restrict__ val, V *__restrict__ onsite,
-                          int16_t *__restrict__ col16, int64_t *__restrict__ bound_keys) {
+                          int16_t *__restrict__ col16, int64_t *__restrict__ bound_keys, BondScales bs) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     if (r < n) {
@@ -149,8 +188,8 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
         for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[NORB][NORB];
-            sk_block<NORB>(sk, rij, dx, dy, dz, B);
+            double B[NORB][NORB], vb[10];
+            sk_block<NORB>(bond_integrals(bs, sk, i, j, vb), sk, rij, dx, dy, dz, B);
             const int32_t cj = NORB * iperm[j];
             for (int a = 0; a < NORB; ++a)
                 for (int b = 0; b < NORB; ++b) {
@@ -192,7 +231,7 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
                               int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                               const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                               int32_t *__restrict__ bcol, V *__restrict__ bval, V *__restrict__ onsite,
-                              int64_t *__restrict__ bound_keys) {
+                              int64_t *__restrict__ bound_keys, BondScales bs) {
     constexpr int NB = NORB * NORB;
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
@@ -205,8 +244,8 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
         for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[NORB][NORB];
-            sk_block<NORB>(sk, rij, dx, dy, dz, B);
+            double B[NORB][NORB], vb[10];
+            sk_block<NORB>(bond_integrals(bs, sk, i, j, vb), sk, rij, dx, dy, dz, B);
             if (q < w) {
                 const int64_t slot = base + (int64_t)q * slice;
                 bcol[slot] = iperm[j];
@@ -328,18 +367,18 @@ tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, cons
 
 template <class V, int NORB>
 void launch_fill(const HamPlan &plan, const double *pos, int64_t n, int32_t slice, double r_cut, const SkValues &v,
-                 tbk_ham *h, int64_t *keys, hipStream_t s) {
+                 tbk_ham *h, int64_t *keys, const BondScales &bs, hipStream_t s) {
     const unsigned g = (unsigned)ceil_div(n, kBlock);
     if (is_block(h->fmt))
         k_fill_sk_blk<V, NORB><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), r_cut, v,
                                                     plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr,
                                                     h->col, static_cast<V *>(h->val), static_cast<V *>(h->onsite),
-                                                    keys);
+                                                    keys, bs);
     else
         k_fill_sk<V, NORB><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), r_cut, v,
                                                 plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr, h->col,
                                                 static_cast<V *>(h->val), static_cast<V *>(h->onsite), h->col16,
-                                                keys);
+                                                keys, bs);
 }
 
 }  // namespace
@@ -370,18 +409,21 @@ extern "C" tbk_status tbk_hamiltonian_size_sk(const double *pos, const int32_t *
     return set_sk_sizes(n, plan, ly, sk, h);
 }
 
-extern "C" tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, int64_t n,
-                                              const double box[3], const int32_t periodic[3],
-                                              const tbk_sk_params *sk, tbk_ham *h, double spec_bounds[2],
-                                              void *stream) {
-    clear_error();
+namespace tbk {
+namespace {
+
+// Builds h; with a model, each bond's integrals are scaled by the outputs of
+// one network per integral (bond features of the descriptor model, MLP
+// forward of the learned-hopping path).
+tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const double box[3],
+                    const int32_t periodic[3], const tbk_sk_params *sk, const tbk_mlp_model *model, tbk_ham *h,
+                    double spec_bounds[2], float *bond_y, int64_t bond_cap, int64_t *n_bonds, hipStream_t s) {
     TBK_CHECK(h != nullptr && spec_bounds != nullptr, TBK_ERR_INVALID_ARG, "h or bounds is NULL");
     TBK_CHECK(h->fmt == TBK_SELL_F32 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_CSR_F64 || is_block(h->fmt),
               TBK_ERR_INVALID_ARG, "unknown format %d", h->fmt);
     const int32_t slice = h->fmt == TBK_CSR_F64 ? 1 : h->slice;
     TBK_CHECK(slice >= 1 && slice <= 1024 && (slice & (slice - 1)) == 0, TBK_ERR_INVALID_ARG,
               "slice = %d is not a power of two in [1, 1024]", slice);
-    hipStream_t s = as_stream(stream);
     HamPlan plan;
     const bool blk = is_block(h->fmt);
     tbk_status st = atom_plan(pos, species, n, box, periodic, sk, blk ? slice : 1, plan, s);
@@ -411,13 +453,58 @@ extern "C" tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *
     SkValues v{sk->r0, sk->beta, sk->e_s, sk->e_p, sk->e_d,
                {sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi, sk->v_sd_sigma, sk->v_pd_sigma,
                 sk->v_pd_pi, sk->v_dd_sigma, sk->v_dd_pi, sk->v_dd_delta}};
+    BondScales bs;
+    DevBuf vdesc, bi, bj, br, X, y, bptr;
+    if (model) {
+        // descriptor -> bonds of the hopping cutoff -> features -> one network per integral
+        const int32_t K = norb == 4 ? 4 : 10;
+        const int64_t nb = plan.n_bonds;
+        const int64_t seg[2] = {0, n};
+        if (n_bonds) *n_bonds = nb;
+        TBK_CHECK(bond_y == nullptr || bond_cap >= K * nb, TBK_ERR_BUFFER_TOO_SMALL,
+                  "bond_y holds %lld, needs %lld", (long long)bond_cap, (long long)(K * nb));
+        TBK_HIP(vdesc.alloc(sizeof(double) * n * model->n_radial, s));
+        st = tbk_descriptor(pos, 1, seg, box, periodic, model->r_cut, model->n_radial, vdesc.as<double>(), s);
+        if (st != TBK_OK) return st;
+        const int64_t cap = std::max<int64_t>(nb, 1);
+        TBK_HIP(bi.alloc(sizeof(int32_t) * cap, s));
+        TBK_HIP(bj.alloc(sizeof(int32_t) * cap, s));
+        TBK_HIP(br.alloc(sizeof(double) * cap, s));
+        TBK_HIP(X.alloc(sizeof(uint16_t) * 16 * cap, s));
+        TBK_HIP(y.alloc(sizeof(float) * K * cap, s));
+        TBK_HIP(bptr.alloc(sizeof(int64_t) * (n + 1), s));
+        int64_t nb2 = 0;
+        st = tbk_bonds(pos, 1, seg, box, periodic, sk->r_cut, cap, bi.as<int32_t>(), bj.as<int32_t>(),
+                       br.as<double>(), &nb2, s);
+        if (st != TBK_OK) return st;
+        TBK_CHECK(nb2 == nb, TBK_ERR_DEVICE, "bond count mismatch (%lld vs %lld)", (long long)nb2, (long long)nb);
+        if (nb > 0) {
+            st = tbk_bond_features(nb, bi.as<int32_t>(), bj.as<int32_t>(), br.as<double>(), vdesc.as<double>(),
+                                   model->n_radial, model->r_cut, model->shift, model->scale, X.as<uint16_t>(), s);
+            if (st != TBK_OK) return st;
+            for (int32_t l = 0; l < K; ++l) {
+                st = tbk_mlp_forward(nb, X.as<uint16_t>(), model->params + (int64_t)l * TBK_MLP_PARAMS,
+                                     y.as<float>() + (int64_t)l * nb, s);
+                if (st != TBK_OK) return st;
+            }
+            if (bond_y)
+                TBK_HIP(hipMemcpyAsync(bond_y, y.as<float>(), sizeof(float) * K * nb, hipMemcpyDeviceToDevice, s));
+        }
+        k_bond_ptr<<<(unsigned)ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, nb, bi.as<int32_t>(), bptr.as<int64_t>());
+        TBK_HIP(hipGetLastError());
+        bs.bond_ptr = bptr.as<int64_t>();
+        bs.bj = bj.as<int32_t>();
+        bs.y = y.as<float>();
+        bs.nb = nb;
+        bs.K = K;
+    }
     const bool f32 = h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32;
     if (norb == 4) {
-        if (f32) launch_fill<float, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
-        else launch_fill<double, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
+        if (f32) launch_fill<float, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), bs, s);
+        else launch_fill<double, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), bs, s);
     } else {
-        if (f32) launch_fill<float, 9>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
-        else launch_fill<double, 9>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), s);
+        if (f32) launch_fill<float, 9>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), bs, s);
+        else launch_fill<double, 9>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), bs, s);
     }
     TBK_HIP(hipGetLastError());
     std::vector<int64_t> hk(2);
@@ -427,4 +514,30 @@ extern "C" tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *
     if (h->fmt == TBK_CSR_F64) h->slice = 1;
     h->seg_rows = nullptr;
     return set_sk_sizes(n, plan, ly, sk, h);
+}
+
+}  // namespace
+}  // namespace tbk
+
+extern "C" tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, int64_t n,
+                                              const double box[3], const int32_t periodic[3],
+                                              const tbk_sk_params *sk, tbk_ham *h, double spec_bounds[2],
+                                              void *stream) {
+    clear_error();
+    return build_sk(pos, species, n, box, periodic, sk, nullptr, h, spec_bounds, nullptr, 0, nullptr,
+                    as_stream(stream));
+}
+
+extern "C" tbk_status tb_build_hamiltonian_sk_learned(const double *pos, const int32_t *species, int64_t n,
+                                                      const double box[3], const int32_t periodic[3],
+                                                      const tbk_sk_params *sk, const tbk_mlp_model *model,
+                                                      tbk_ham *h, double spec_bounds[2], float *bond_y,
+                                                      int64_t bond_cap, int64_t *n_bonds, void *stream) {
+    clear_error();
+    TBK_CHECK(model && model->params && model->shift && model->scale, TBK_ERR_INVALID_ARG, "model is incomplete");
+    TBK_CHECK(model->n_radial == 8, TBK_ERR_INVALID_ARG, "n_radial = %d (must be 8)", model->n_radial);
+    TBK_CHECK(std::isfinite(model->r_cut) && model->r_cut > 0, TBK_ERR_INVALID_ARG, "descriptor cutoff %g",
+              model->r_cut);
+    return build_sk(pos, species, n, box, periodic, sk, model, h, spec_bounds, bond_y, bond_cap, n_bonds,
+                    as_stream(stream));
 }

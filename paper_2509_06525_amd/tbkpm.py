@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtbkpm.so")
 
 TBK_OK = 0
 TBK_ERR_BUFFER_TOO_SMALL = 2
+TBK_MLP_PARAMS = 1633      # parameters of one per-bond network (W1, b1, W2, b2, W3, b3)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BUFFER_TOO_SMALL", 3: "NOT_FINITE",
                 4: "SPECTRUM", 5: "UNSUPPORTED", 6: "DEVICE"}
 FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2, "bsell4_f64": 3, "bsell4_f32": 4}
@@ -60,7 +61,7 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_coordination_target", "tbk_mlp_forward", "tbk_mlp_workspace_size",
                "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned",
                "tb_build_velocity", "lsqt_chebyshev_terms", "lsqt_workspace_size", "lsqt_vac_moments",
-               "lsqt_sigma", "kpm_integrated_dos", "lsqt_mobility")
+               "lsqt_sigma", "kpm_integrated_dos", "lsqt_mobility", "tb_build_hamiltonian_sk_learned")
 
 
 class SkParams(ctypes.Structure):
@@ -222,6 +223,11 @@ def lib():
     L.tbk_hamiltonian_size_sk.restype = ctypes.c_int
     L.tbk_hamiltonian_size_sk.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                           ctypes.POINTER(SkParams), ctypes.POINTER(HamStruct), vp]
+    L.tb_build_hamiltonian_sk_learned.restype = ctypes.c_int
+    L.tb_build_hamiltonian_sk_learned.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                                  ctypes.POINTER(SkParams), ctypes.POINTER(MlpModel),
+                                                  ctypes.POINTER(HamStruct), ctypes.POINTER(f64), vp, i64,
+                                                  ctypes.POINTER(i64), vp]
     L.tb_build_hamiltonian_sk.restype = ctypes.c_int
     L.tb_build_hamiltonian_sk.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                           ctypes.POINTER(SkParams), ctypes.POINTER(HamStruct),
@@ -359,10 +365,14 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
 
 def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi, e_s, e_p,
                          r_cut=2.0, r0=1.42, beta=3.37, fmt="sell_f32", slice=256, reorder=True, stream=None,
-                         d=None, e_d=0.0):
+                         d=None, e_d=0.0, model=None, with_bond_y=False):
     """Slater-Koster orbital Hamiltonian on the GPU: s, p (4 rows per atom), or
     s, p, d (9 rows per atom) when d = (v_sd_sigma, v_pd_sigma, v_pd_pi,
-    v_dd_sigma, v_dd_pi, v_dd_delta) is given."""
+    v_dd_sigma, v_dd_pi, v_dd_delta) is given.
+
+    model = dict(params=[K][1633] float32 tensor, shift=[16], scale=[16], r_desc=4.0):
+    the learned form, each bond's integral l scaled by 1 + y_l from network l
+    (K = 4 or 10).  with_bond_y also returns y [K][n_bonds]."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
@@ -392,9 +402,28 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
     st.onsite, st.perm, st.col16 = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["col16"].data_ptr()
     bounds = (ctypes.c_double * 2)()
-    _check(L.tb_build_hamiltonian_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk), ctypes.byref(st),
-                                     bounds, s))
-    return Hamiltonian(st, t, (bounds[0], bounds[1]))
+    if model is None:
+        _check(L.tb_build_hamiltonian_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk),
+                                         ctypes.byref(st), bounds, s))
+        return Hamiltonian(st, t, (bounds[0], bounds[1]))
+    K = 4 if norb == 4 else 10
+    params = _dev(model["params"], torch.float32)
+    if tuple(params.shape) != (K, TBK_MLP_PARAMS):
+        raise ValueError(f"params has shape {tuple(params.shape)}, expected {(K, TBK_MLP_PARAMS)}")
+    sh, sc = _f64arr(model["shift"]), _f64arr(model["scale"])
+    mm = MlpModel(r_cut=float(model.get("r_desc", 4.0)), n_radial=8,
+                  shift=ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
+                  scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)), params=params.data_ptr())
+    nbonds = st.n_bonds
+    y = torch.empty((K, max(nbonds, 1)), dtype=torch.float32, device=dev) if with_bond_y else None
+    nb_out = ctypes.c_int64(0)
+    _check(L.tb_build_hamiltonian_sk_learned(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk),
+                                             ctypes.byref(mm), ctypes.byref(st), bounds, _ptr(y),
+                                             K * nbonds if y is not None else 0, ctypes.byref(nb_out), s))
+    H = Hamiltonian(st, t, (bounds[0], bounds[1]))
+    if with_bond_y:
+        return H, y[:, : nb_out.value]
+    return H
 
 
 def _cfg_ref(config):

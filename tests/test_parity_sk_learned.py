@@ -1,0 +1,126 @@
+"""GPU parity of the learned Slater-Koster Hamiltonian (Eq. (2): one network per
+two-centre integral on the bond's edge features, angular factors of the table).
+
+Network outputs per bond against the oracle's bfloat16-operand forward (FP32
+accumulation on the GPU: 2e-5 relative to the largest output on bonds whose
+activations sit clear of a bfloat16 rounding boundary); Hamiltonian entries
+against the oracle's table with the same per-bond integral scales (5e-5 relative
+on entries of clear bonds, 1e-2 on all); moments FP64 and C32 DOS against the
+oracle's on the learned Hamiltonian."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+V10 = synth.SK_V + synth.SK_D
+
+
+def oracle_bonds(s):
+    pd = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+    v = O.descriptor(s.n, pd, synth.R_DESC, 8)
+    hop = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_HOP)
+    o = np.lexsort((hop[1], hop[0]))
+    hop = (hop[0][o], hop[1][o], hop[2][o])
+    raw = O.bond_features(hop, v, synth.R_DESC)
+    return v, hop, raw.mean(0), raw.std(0)
+
+
+def model_params(K, seed):
+    """K networks sharing their hidden layers (one network with K outputs: the same
+    bfloat16 rounding decisions for every integral), each with its own output layer."""
+    base = synth.init_mlp_params(seed, out_scale=0.5)
+    rng = np.random.default_rng(seed + 1)
+    P = np.repeat(base[None, :], K, axis=0)
+    P[:, 1600:1632] = rng.uniform(-0.5, 0.5, (K, 32)) / np.sqrt(32)      # W3
+    P[:, 1632] = rng.uniform(-0.05, 0.05, K)                            # b3
+    return P.astype(np.float32)
+
+
+def oracle_learned(s, P, mean, std, v, hop, norb):
+    Xo = O.bf16(O.bond_features(hop, v, synth.R_DESC, mean, std))
+    ys, clear = [], np.ones(hop[0].shape[0], bool)
+    for p in P:
+        yo, h1, h2 = O.mlp_forward(Xo, p.astype(np.float64), bf16_ops=True, keep=True)
+        ys.append(yo)
+        clear &= G.bf16_decisions_clear(h1, h2)
+    Y = np.stack(ys)
+    vv = V10 if norb == 9 else synth.SK_V
+    csr, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, vv, synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP,
+                              r0=synth.R0, beta=synth.BETA, pairs=hop, e_d=synth.SK_ED, scale=1.0 + Y.T)
+    return csr, Y, clear
+
+
+def build(s, P, mean, std, norb, fmt, slice_, with_y=False):
+    return tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                      synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                      fmt=fmt, slice=slice_, d=synth.SK_D if norb == 9 else None, e_d=synth.SK_ED,
+                                      model=dict(params=G.to_dev(P), shift=mean, scale=std, r_desc=synth.R_DESC),
+                                      with_bond_y=with_y)
+
+
+@pytest.mark.parametrize("norb,fmt,slice_", [(4, "sell_f64", 32), (4, "bsell4_f64", 16), (9, "sell_f64", 16),
+                                             (9, "bsell4_f64", 8), (9, "bsell4_f32", 32)])
+def test_learned_sk_matches_oracle(norb, fmt, slice_):
+    s = synth.graphene_sheet(6, 5, 0.07, 17)
+    K = 4 if norb == 4 else 10
+    P = model_params(K, 40)
+    v, hop, mean, std = oracle_bonds(s)
+    H, y = build(s, P, mean, std, norb, fmt, slice_, with_y=True)
+    csr, Y, clear = oracle_learned(s, P, mean, std, v, hop, norb)
+    y = y.cpu().numpy().astype(np.float64)
+    assert y.shape == Y.shape
+    assert clear.mean() >= 0.3
+    assert np.abs(y - Y)[:, clear].max() <= 2e-5 * np.abs(Y).max()
+    assert np.abs(Y).max() > 0.05                      # the scales are far from 1
+    rows, cols, vals, onsite = (G.block_entries(H) if fmt.startswith("bsell4") else G.entries_in_atom_order(H))
+    orow, ocol, oval = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_array_equal(rows[o1], orow[o2])
+    np.testing.assert_array_equal(cols[o1], ocol[o2])
+    bond_of = {(int(i), int(j)): e for e, (i, j) in enumerate(zip(hop[0], hop[1]))}
+    ent_clear = np.array([clear[bond_of[(min(i // norb, j // norb), max(i // norb, j // norb))]]
+                          for i, j in zip(orow[o2], ocol[o2])])
+    err = np.abs(vals[o1] - oval[o2])
+    big = np.abs(oval[o2]).max()
+    tol = 5e-5 if fmt.endswith("f64") else 1e-4
+    assert err[ent_clear].max() <= tol * big
+    assert err.max() <= 1e-2 * big
+    odiag = csr.diag.astype(np.float32).astype(np.float64) if fmt.endswith("f32") else csr.diag
+    np.testing.assert_array_equal(onsite, odiag)
+    lo, hi = H.bounds
+    olo, ohi = O.gershgorin(csr)
+    assert lo == pytest.approx(olo, rel=1e-3) and hi == pytest.approx(ohi, rel=1e-3)
+
+
+def test_learned_sk_moments_and_dos():
+    """Moments of the learned Hamiltonian against the oracle's on the GPU's own stored
+    values (FP64: the recurrence alone), and the C32 DOS against the oracle chain."""
+    s = synth.graphene_sheet(8, 7, 0.06, 5)
+    P = model_params(10, 70)
+    v, hop, mean, std = oracle_bonds(s)
+    H = build(s, P, mean, std, 9, "bsell4_f64", 16)
+    csr, _, _ = oracle_learned(s, P, mean, std, v, hop, 9)
+    a, b = G.oracle_ab(csr)
+    r = synth.random_phase(9 * s.n, 4, 2)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 128, "f64").cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r, 128)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mu.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-3
+    H32 = build(s, P, mean, std, 9, "bsell4_f32", 32)
+    r32 = synth.random_phase(9 * s.n, 4, 2, np.complex64)
+    m32 = tbkpm.kpm_moments(H32, a, b, G.to_dev(r32), 128, "c32").cpu().numpy()
+    assert G.rel_l2(O.kpm_dos(m32.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-3
+
+
+def test_learned_sk_errors():
+    s = synth.graphene_sheet(4, 4)          # periodic lengths above twice the descriptor cutoff
+    v, hop, mean, std = oracle_bonds(s)
+    with pytest.raises(ValueError):
+        build(s, model_params(4, 1), mean, std, 9, "sell_f64", 8)        # 4 networks for 10 integrals
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(s, model_params(10, 1), mean, np.zeros(16), 9, "sell_f64", 8)   # zero feature scale
+    assert e.value.name in ("INVALID_ARG", "NOT_FINITE")
