@@ -422,6 +422,41 @@ def bench_sk(args, w):
     if not args.no_doubling:
         out["variants"]["doubling"] = kpm_variant(args, "doubling", {"doubling": 1}, Hs, aa, bb, r, M, R, Rp, 4,
                                                   diag, "c32", cfg, mu_c, rho_c, E, stream, dev)
+    # learned form of Eq. (2): one network per two-centre integral on the bond's edge features
+    # (seeded weights, shared hidden layers; the assembly cost does not depend on their values)
+    K = 4 if norb == 4 else 10
+    rng = np.random.default_rng(w["seed"])
+    P = np.repeat(synth.init_mlp_params(w["seed"], out_scale=0.5)[None, :], K, axis=0)
+    P[:, 1600:1632] = rng.uniform(-0.5, 0.5, (K, 32)) / math.sqrt(32)
+    model = dict(params=torch.from_numpy(P.astype(np.float32)).to(dev), shift=np.zeros(16),
+                 scale=np.concatenate([np.full(8, 0.3), np.full(8, 1.5)]), r_desc=synth.R_DESC)
+    del Hs
+    times = {"plain": [], "learned": []}
+    for _ in range(max(2, args.steps)):
+        for lab in ("plain", "learned"):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Hx = tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
+                                            r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=w["fmt"], slice=64,
+                                            stream=stream, d=dint, e_d=synth.SK_ED,
+                                            model=model if lab == "learned" else None)
+            torch.cuda.synchronize()
+            times[lab].append((time.perf_counter() - t1) * 1e3)
+            nbonds = Hx.st.n_bonds
+            del Hx
+    Hl = tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
+                                    r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=w["fmt"], slice=64,
+                                    stream=stream, d=dint, e_d=synth.SK_ED, model=model)
+    la, lb = Hl.scale()
+    ev[0].record(stream)
+    tbkpm.kpm_moments(Hl, la, lb, r, M, "c32", work=work, mu=mu, stream=stream, config=cfg)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    out["variants"]["learned_sk"] = {
+        "networks": K, "bonds": int(nbonds), "build_ms_median": float(np.median(times["learned"])),
+        "plain_build_ms_median": float(np.median(times["plain"])), "kpm_ms": ev[0].elapsed_time(ev[1]),
+        "a_eV": la, "b_eV": lb}
+    del Hl
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (norb * norb * M * R))))

@@ -210,6 +210,9 @@ MLP_SHAPES = ((32, 16), (32,), (32, 32), (32,), (32,), (1,))   # W1, b1, W2, b2,
 MLP_N_PARAMS = 1633
 COORD_KAPPA = 0.25          # strength of the coordination correction of the target hoppings
 COORD_Z0 = 4.7357           # pristine coordination sum_j f_c(r_ij) within 4.0 A (rounded)
+# per-integral strengths of the coordination correction of the learned Slater-Koster
+# workload's target (ss_sigma, sp_sigma, pp_sigma, pp_pi, then the six d integrals)
+SK_COORD_KAPPA = (0.25, -0.15, 0.2, 0.3, 0.1, -0.2, 0.15, 0.25, -0.1, 0.05)
 
 
 def init_mlp_params(seed, out_scale=0.1):

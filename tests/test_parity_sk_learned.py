@@ -124,3 +124,56 @@ def test_learned_sk_errors():
     with pytest.raises(tbkpm.TBKError) as e:
         build(s, model_params(10, 1), mean, np.zeros(16), 9, "sell_f64", 8)   # zero feature scale
     assert e.value.name in ("INVALID_ARG", "NOT_FINITE")
+
+
+def test_trained_sk_networks_beat_the_plain_table():
+    """One network per s, p integral trained on the GPU (coordination-corrected targets
+    with a different strength per integral); on a held-out sheet the DOS of the learned
+    Hamiltonian is closer to the oracle DOS of the target Hamiltonian than the plain
+    table's, and within 1e-2."""
+    import torch
+    K = 4
+    kap = synth.SK_COORD_KAPPA[:K]
+    snaps = synth.snapshot_set(16, 4004, n_min=1000, n_max=6000)
+    pos, sp, seg, boxes = synth.stack(snaps)
+    pd = G.to_dev(pos)
+    per = (1, 1, 0)
+    v = tbkpm.descriptor(pd, seg, boxes, per, synth.R_DESC, 8)
+    b = tbkpm.bonds(pd, seg, boxes, per, synth.R_HOP)
+    mean, std = tbkpm.feature_moments(b, v, synth.R_DESC)
+    std = [max(x, 1e-6) for x in std]
+    X = tbkpm.bond_features(b, v, mean, std, synth.R_DESC)
+    P = []
+    for l in range(K):
+        y = tbkpm.coordination_target(b, v, kap[l], synth.COORD_Z0)
+        tr = tbkpm.MlpTrainer(G.to_dev(synth.init_mlp_params(60 + l)))
+        hist = tr.train(X, y, epochs=120, batch=2048, lr=2e-3, wd=1e-5)
+        assert hist[-1] < 0.05 * hist[0], (l, hist[0], hist[-1])
+        P.append(tr.params)
+    P = torch.stack(P).contiguous()
+    s = synth.graphene_sheet(20, 12, 0.06, 999)
+    Hl = tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                    synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                    fmt="bsell4_f32", slice=32,
+                                    model=dict(params=P, shift=mean, scale=std, r_desc=synth.R_DESC))
+    Hp = tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                    synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                    fmt="bsell4_f32", slice=32)
+    vo, hop, _, _ = oracle_bonds(s)
+    sc = np.stack([O.target_scale(hop, vo, kap[l], synth.COORD_Z0) for l in range(K)], axis=1)
+    csr_t, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, synth.SK_V, synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP,
+                                r0=synth.R0, beta=synth.BETA, pairs=hop, scale=sc)
+    a, b_ = G.oracle_ab(csr_t, 1.05)
+    M, R = 512, 8
+    r = synth.random_phase(4 * s.n, R, 5, np.complex64)
+    mo, _ = O.kpm_moments(csr_t, a, b_, r.astype(np.complex128), M)
+    E = synth.energy_grid(a, b_)
+    rho_t = O.kpm_dos(mo.mean(0), a, b_, E)
+    rd = G.to_dev(r)
+    ml = tbkpm.kpm_moments(Hl, a, b_, rd, M, "c32").cpu().numpy()
+    mp = tbkpm.kpm_moments(Hp, a, b_, rd, M, "c32").cpu().numpy()
+    err_l = G.rel_l2(O.kpm_dos(ml.mean(0), a, b_, E), rho_t)
+    err_p = G.rel_l2(O.kpm_dos(mp.mean(0), a, b_, E), rho_t)
+    print(f"[learned sk] err_learned={err_l:.3e} err_plain={err_p:.3e}", flush=True)
+    assert err_l <= 1e-2
+    assert err_l < 0.5 * err_p
