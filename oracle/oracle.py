@@ -78,7 +78,8 @@ def _lib():
     L.orc_mobility.restype = ctypes.c_int
     L.orc_mobility.argtypes = [_f64p, _i32, _i32, _i32, _f64p, _f64, _f64p, _f64p, _f64p]
     L.orc_assemble_sk.argtypes = [_i64, _f64p, _f64p, _i32p, _i64, _i32p, _i32p, _i32, _f64p, ctypes.c_void_p,
-                                  _f64p, _f64, _f64, _i64p, _i32p, _f64p, _f64p]
+                                  _f64p, ctypes.c_void_p, _i32, ctypes.c_void_p, ctypes.c_void_p, _f64, _f64,
+                                  _i64p, _i32p, _f64p, _f64p]
     L.orc_splitmix64.restype = ctypes.c_uint64
     L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     L.orc_random_phase.restype = None
@@ -319,10 +320,12 @@ def mobility(sigma, N, n_ref):
 
 
 def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None, e_d=0.0,
-                   scale=None):
+                   scale=None, species=None, pair_v=None, species_e=None):
     """Slater-Koster orbital Hamiltonian as a CSR: v holds 4 integrals (s, p: orbital 4 i + a,
     a = s, x, y, z) or 10 (s, p, d: orbital 9 i + a, then dxy, dyz, dzx, dx2-y2, d3z2-r2)
     at r0; scale [npairs][len(v)] (optional) multiplies each pair's integrals (learned form).
+    Several species: species [n], pair_v [ns][ns][len(v)] (ordered pair, lower angular
+    momentum on the first species), species_e [ns][3] replace v and e_s, e_p, e_d.
     Returns (csr, pairs)."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     if pairs is None:
@@ -330,6 +333,8 @@ def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.3
     pi, pj, _ = pairs
     v = np.asarray(v, np.float64)
     norb = 4 if v.size == 4 else 9
+    if pair_v is not None:
+        norb = 4 if np.asarray(pair_v).shape[2] == 4 else 9
     v10 = np.zeros(10)
     v10[: v.size] = v
     n = pos.shape[0]
@@ -343,10 +348,21 @@ def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.3
         scale = np.asarray(scale, np.float64).reshape(npairs, -1)
         sc = np.ones((npairs, 10))
         sc[:, : scale.shape[1]] = scale
+    sp_a = pv = se = None
+    ns = 0
+    if pair_v is not None:
+        pv0 = np.asarray(pair_v, np.float64)
+        ns = pv0.shape[0]
+        pv = np.zeros((ns, ns, 10))
+        pv[:, :, : pv0.shape[2]] = pv0
+        se = np.ascontiguousarray(np.asarray(species_e, np.float64).reshape(ns, 3))
+        sp_a = np.ascontiguousarray(np.asarray(species, np.int32))
     rc = _lib().orc_assemble_sk(n, _c(pos, np.float64).reshape(-1), _c(box, np.float64), _c(periodic, np.int32),
                                 npairs, pi, pj, norb, v10, None if sc is None else sc.ctypes.data,
-                                np.array([e_s, e_p, e_d], np.float64), float(r0), float(beta), row_ptr, col, val,
-                                diag)
+                                np.array([e_s, e_p, e_d], np.float64),
+                                None if sp_a is None else sp_a.ctypes.data, ns,
+                                None if pv is None else pv.ctypes.data, None if se is None else se.ctypes.data,
+                                float(r0), float(beta), row_ptr, col, val, diag)
     if rc != 0:
         raise OracleError("orc_assemble_sk failed")
     return CSR(row_ptr, col, val, diag), pairs

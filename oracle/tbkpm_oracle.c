@@ -836,6 +836,8 @@ int orc_mobility(const double *sigma, int32_t F, int32_t n_t, int32_t nE, const 
  * lower angular momentum first; the others follow from Hermiticity and parity,
  * E[b][a](c) = E[a][b](-c) = (-1)^(l_a + l_b) E[a][b](c).
  */
+static const int lq[9] = {0, 1, 1, 1, 2, 2, 2, 2, 2};   /* angular momentum of each orbital */
+
 static void orc_sk_table(const double c[3], const double v[10], double E[9][9])
 {
     const double l = c[0], m = c[1], n = c[2], s3 = sqrt(3.0);
@@ -903,11 +905,27 @@ static void orc_sk_table(const double c[3], const double v[10], double E[9][9])
         for (int b = a; b < 5; ++b) E[4 + a][4 + b] = dd[a][b];
     }
     /* lower blocks by parity: E[b][a] = (-1)^(l_a + l_b) E[a][b] */
-    static const int lq[9] = {0, 1, 1, 1, 2, 2, 2, 2, 2};
     for (int a = 0; a < 9; ++a)
         for (int b = 0; b < 9; ++b)
             if (lq[b] > lq[a] || (lq[b] == lq[a] && b > a))
                 E[b][a] = ((lq[a] + lq[b]) & 1) ? -E[a][b] : E[a][b];
+}
+
+/*
+ * Block of a bond between atoms of species A (row) and B (column): the blocks
+ * with l_a <= l_b from the integrals v_ab of the ordered pair (A, B) (for a
+ * mixed integral the lower angular momentum sits on A), the blocks with
+ * l_a > l_b from those of (B, A): <a_i|H|b_j> = <b_j|H|a_i> is the table's
+ * block of the reversed bond, (-1)^(l_a + l_b) times its entry at c.
+ */
+static void orc_sk_table_pair(const double c[3], const double v_ab[10], const double v_ba[10], double E[9][9])
+{
+    double Eb[9][9];
+    orc_sk_table(c, v_ab, E);
+    orc_sk_table(c, v_ba, Eb);
+    for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b)
+            if (lq[a] > lq[b]) E[a][b] = Eb[a][b];
 }
 
 /*
@@ -921,13 +939,18 @@ static void orc_sk_table(const double c[3], const double v[10], double E[9][9])
  * [npairs][10]) pair p uses the integrals v[l] scale[p][l] instead of v[l]:
  * the learned form of Eq. (2), where each bond's two-centre integrals are
  * network outputs (here v[l] (1 + y_l) with y_l the output of network l), the
- * angular factors unchanged.  CSR of the off-diagonal part (row_ptr
- * [norb n + 1], col/val [2 norb^2 npairs], columns ascending); diag [norb n].
+ * angular factors unchanged.  Several species (pair_v != NULL): atom i has
+ * species[i] in [0, n_species); a bond i -> j uses pair_v[(s_i n_species +
+ * s_j) 10 + l] for the blocks with l_a <= l_b and those of (s_j, s_i) for the
+ * others (orc_sk_table_pair); onsite energies species_e[3 s_i + shell]; v and
+ * e are then unused.  CSR of the off-diagonal part (row_ptr [norb n + 1],
+ * col/val [2 norb^2 npairs], columns ascending); diag [norb n].
  * Returns 0, -1 on a bad norb, -2 when out of memory.
  */
 int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int32_t periodic[3],
                     int64_t npairs, const int32_t *pi, const int32_t *pj, int32_t norb, const double v[10],
-                    const double *scale, const double e[3], double r0, double beta,
+                    const double *scale, const double e[3], const int32_t *species, int32_t n_species,
+                    const double *pair_v, const double *species_e, double r0, double beta,
                     int64_t *row_ptr, int32_t *col, double *val, double *diag)
 {
     if (norb != 4 && norb != 9) return -1;
@@ -945,9 +968,14 @@ int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int
         double d[3], E[9][9], c[3];
         double r = orc_displacement(pos, i, j, box, periodic, d);
         for (int k = 0; k < 3; ++k) c[k] = d[k] / r;
-        double vp[10];
-        for (int l = 0; l < 10; ++l) vp[l] = scale ? v[l] * scale[10 * p + l] : v[l];
-        orc_sk_table(c, vp, E);
+        double vab[10], vba[10];
+        const double *tab = pair_v ? pair_v + 10 * ((int64_t)species[i] * n_species + species[j]) : v;
+        const double *tba = pair_v ? pair_v + 10 * ((int64_t)species[j] * n_species + species[i]) : v;
+        for (int l = 0; l < 10; ++l) {
+            vab[l] = scale ? tab[l] * scale[10 * p + l] : tab[l];
+            vba[l] = scale ? tba[l] * scale[10 * p + l] : tba[l];
+        }
+        orc_sk_table_pair(c, vab, vba, E);
         double f = exp(-beta * (r / r0 - 1.0));
         for (int a = 0; a < norb; ++a)
             for (int b = 0; b < norb; ++b) {
@@ -969,7 +997,8 @@ int orc_assemble_sk(int64_t n, const double *pos, const double box[3], const int
         }
     for (int64_t r = 0; r < nr; ++r) {
         int a = (int)(r % norb);
-        diag[r] = a == 0 ? e[0] : (a < 4 ? e[1] : e[2]);
+        const double *es = pair_v ? species_e + 3 * (int64_t)species[r / norb] : e;
+        diag[r] = a == 0 ? es[0] : (a < 4 ? es[1] : es[2]);
     }
     free(deg); free(fill);
     return 0;

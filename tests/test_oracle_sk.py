@@ -10,6 +10,7 @@
 * H is symmetric and its onsite part is diag(e_s, e_p, e_p, e_p).
 """
 import numpy as np
+import pytest
 import scipy.spatial.transform
 
 from oracle import oracle as O
@@ -203,3 +204,63 @@ def test_per_pair_scales_keep_h_symmetric_and_linear():
         v1[lam] = V10[lam]
         total += O.sk_hamiltonian(s.pos, s.box, s.periodic, v1, 0.0, 0.0, pairs=pairs, scale=sc)[0].dense()
     np.testing.assert_allclose(H, total, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Several species: integrals per ordered species pair, onsite energies per species
+# ---------------------------------------------------------------------------
+
+def species_tables(ns, seed, norb=9):
+    """Random pair tables with the same-l integrals (ss, pp, dd) symmetric in the pair."""
+    rng = np.random.default_rng(seed)
+    K = 4 if norb == 4 else 10
+    pv = rng.uniform(-6.0, 6.0, (ns, ns, K))
+    for l in (0, 2, 3, 7, 8, 9)[: 3 if K == 4 else 6]:
+        pv[:, :, l] = 0.5 * (pv[:, :, l] + pv[:, :, l].T)
+    se = rng.uniform(-8.0, 8.0, (ns, 3))
+    return pv, se
+
+
+def test_hetero_dimer_along_z():
+    """A (row) - B dimer along z: s_A-pz_B carries V_sp of (A, B), pz_A-s_B minus V_sp of
+    (B, A); s-d and p-d likewise with their parities; onsite per species."""
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.42]])
+    pv, se = species_tables(2, 3)
+    csr, _ = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V10, 0.0, 0.0, species=np.array([0, 1]), pair_v=pv,
+                              species_e=se)
+    H = csr.dense()
+    B = H[0:9, 9:18]
+    ab, ba = pv[0, 1], pv[1, 0]
+    assert B[0, 0] == pytest.approx(ab[0])
+    assert B[0, 3] == pytest.approx(ab[1]) and B[3, 0] == pytest.approx(-ba[1])
+    assert B[0, 8] == pytest.approx(ab[4]) and B[8, 0] == pytest.approx(ba[4])
+    assert B[3, 8] == pytest.approx(ab[5]) and B[8, 3] == pytest.approx(-ba[5])
+    assert B[1, 6] == pytest.approx(ab[6]) and B[6, 1] == pytest.approx(-ba[6])
+    assert B[3, 3] == pytest.approx(ab[2]) and B[1, 1] == pytest.approx(ab[3])
+    assert B[8, 8] == pytest.approx(ab[7]) and B[5, 5] == pytest.approx(ab[8]) and B[4, 4] == pytest.approx(ab[9])
+    np.testing.assert_allclose(H, H.T, atol=1e-14)
+    np.testing.assert_allclose(np.diag(H), np.concatenate([se[k][[0, 1, 1, 1, 2, 2, 2, 2, 2]] for k in (0, 1)]))
+
+
+def test_species_relabelling_and_single_species_limit():
+    s = synth.hbn_stripes(6, 4, stripe_cells=2, sigma=0.1, seed=3)
+    pairs = O.neighbor_pairs(s.pos, s.box, s.periodic, 2.0)
+    pv, se = species_tables(3, 8)
+    H = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, 0.0, 0.0, pairs=pairs, species=s.species, pair_v=pv,
+                         species_e=se)[0].dense()
+    np.testing.assert_allclose(H, H.T, atol=1e-13)
+    perm = np.array([2, 0, 1])                   # species k becomes perm[k]
+    pv2 = np.empty_like(pv)
+    se2 = np.empty_like(se)
+    for a in range(3):
+        se2[perm[a]] = se[a]
+        for b in range(3):
+            pv2[perm[a], perm[b]] = pv[a, b]
+    H2 = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, 0.0, 0.0, pairs=pairs, species=perm[s.species],
+                          pair_v=pv2, species_e=se2)[0].dense()
+    np.testing.assert_array_equal(H, H2)
+    one = np.broadcast_to(np.asarray(V10), (3, 3, 10))
+    H1 = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED, pairs=pairs, species=s.species,
+                          pair_v=one, species_e=np.tile([ES, EP, ED], (3, 1)))[0].dense()
+    H0 = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED, pairs=pairs)[0].dense()
+    np.testing.assert_array_equal(H1, H0)
