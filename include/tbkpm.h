@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 7
+#define TBK_ABI_VERSION 8
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -501,6 +501,21 @@ typedef struct {
     double e_d;                 /* d onsite energy (eV), orbitals = 9             */
     double v_sd_sigma, v_pd_sigma, v_pd_pi;                /* at r0 (eV),          */
     double v_dd_sigma, v_dd_pi, v_dd_delta;                /* orbitals = 9         */
+    /* Several species (pair_v != NULL; the single-species integrals and onsite
+     * energies above are then unused):
+     *   n_species  in [1, 16]; species[i] (device, the builder's argument) in
+     *              [0, n_species);
+     *   pair_v     host double [n_species][n_species][10]: the ten integrals
+     *              (order as above) of the ordered species pair (A, B); a mixed
+     *              integral (sp, sd, pd) has the lower angular momentum on A, and
+     *              the equal-l integrals (ss, pp, dd) must not depend on the order;
+     *   species_e  host double [n_species][3]: e_s, e_p, e_d of each species.
+     * A bond i -> j takes the blocks with l_a <= l_b from (s_i, s_j) and the
+     * others from (s_j, s_i), by <b_i|H|a_j> = (-1)^(l_a + l_b) of the reversed
+     * bond's entry. */
+    int32_t n_species;
+    const double *pair_v;
+    const double *species_e;
 } tbk_sk_params;
 
 /*

@@ -61,37 +61,68 @@ struct SkValues {
     double r0, beta, e_s, e_p, e_d;
     // at r0: ss_sigma, sp_sigma, pp_sigma, pp_pi, sd_sigma, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta
     double v[10];
+    // several species (pv != NULL): integrals pv[(s_i ns + s_j) 10 + l] of the ordered
+    // species pair, onsite energies se[3 s + shell], species of the caller's atoms
+    const double *pv = nullptr;
+    const double *se = nullptr;
+    const int32_t *species = nullptr;
+    int32_t ns = 1;
 };
 
+// The s-d row and the p-d block of the table for integrals v.
+__device__ __forceinline__ void sk_sd_pd(const double *v, double l, double m, double n, double (&sdr)[5],
+                                         double (&pd)[3][5]) {
+    const double s3 = 1.7320508075688772;
+    const double l2 = l * l, m2 = m * m, n2 = n * n;
+    const double sd = v[4], pds = v[5], pdp = v[6];
+    const double q = n2 - 0.5 * (l2 + m2), dlm = l2 - m2;
+    sdr[0] = s3 * l * m * sd;
+    sdr[1] = s3 * m * n * sd;
+    sdr[2] = s3 * n * l * sd;
+    sdr[3] = 0.5 * s3 * dlm * sd;
+    sdr[4] = q * sd;
+    pd[0][0] = s3 * l2 * m * pds + m * (1.0 - 2.0 * l2) * pdp;
+    pd[0][1] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
+    pd[0][2] = s3 * l2 * n * pds + n * (1.0 - 2.0 * l2) * pdp;
+    pd[0][3] = 0.5 * s3 * l * dlm * pds + l * (1.0 - dlm) * pdp;
+    pd[0][4] = l * q * pds - s3 * l * n2 * pdp;
+    pd[1][0] = s3 * m2 * l * pds + l * (1.0 - 2.0 * m2) * pdp;
+    pd[1][1] = s3 * m2 * n * pds + n * (1.0 - 2.0 * m2) * pdp;
+    pd[1][2] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
+    pd[1][3] = 0.5 * s3 * m * dlm * pds - m * (1.0 + dlm) * pdp;
+    pd[1][4] = m * q * pds - s3 * m * n2 * pdp;
+    pd[2][0] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
+    pd[2][1] = s3 * n2 * m * pds + m * (1.0 - 2.0 * n2) * pdp;
+    pd[2][2] = s3 * n2 * l * pds + l * (1.0 - 2.0 * n2) * pdp;
+    pd[2][3] = 0.5 * s3 * n * dlm * pds - n * dlm * pdp;
+    pd[2][4] = n * q * pds + s3 * n * (l2 + m2) * pdp;
+}
+
 // The Slater-Koster table: E[a][b] = <a_i|H|b_j> / f for direction cosines
-// (l, m, n) from i to j; rows with the lower angular momentum first, the other
-// blocks from E[b][a] = (-1)^(l_a + l_b) E[a][b].  Only the first NORB rows and
-// columns are formed.
+// (l, m, n) from i to j.  The blocks with the lower angular momentum on the row
+// side (and the equal-l blocks) come from the integrals vu of the ordered
+// species pair (row, column), the others from the reversed pair's vl by
+// E[b][a] = (-1)^(l_a + l_b) E'[a][b] (E' formed with vl; vl = vu for one
+// species).  Only the first NORB rows and columns are formed.
 template <int NORB>
-__device__ __forceinline__ void sk_table(const double *v, double l, double m, double n, double (&E)[NORB][NORB]) {
+__device__ __forceinline__ void sk_table(const double *vu, const double *vl, double l, double m, double n,
+                                         double (&E)[NORB][NORB]) {
+    const double *v = vu;
     const double s3 = 1.7320508075688772;
     const double l2 = l * l, m2 = m * m, n2 = n * n;
     const double c[3] = {l, m, n};
     E[0][0] = v[0];
     for (int a = 0; a < 3; ++a) {
         E[0][1 + a] = c[a] * v[1];
-        E[1 + a][0] = -c[a] * v[1];
+        E[1 + a][0] = -c[a] * vl[1];
         for (int b = 0; b < 3; ++b) E[1 + a][1 + b] = c[a] * c[b] * v[2] + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * v[3];
     }
     if constexpr (NORB == 9) {
-        const double sd = v[4], pds = v[5], pdp = v[6], dds = v[7], ddp = v[8], ddd = v[9];
+        const double dds = v[7], ddp = v[8], ddd = v[9];
         const double q = n2 - 0.5 * (l2 + m2), dlm = l2 - m2;
-        const double sdr[5] = {s3 * l * m * sd, s3 * m * n * sd, s3 * n * l * sd, 0.5 * s3 * dlm * sd, q * sd};
-        const double pd[3][5] = {
-            {s3 * l2 * m * pds + m * (1.0 - 2.0 * l2) * pdp, s3 * l * m * n * pds - 2.0 * l * m * n * pdp,
-             s3 * l2 * n * pds + n * (1.0 - 2.0 * l2) * pdp, 0.5 * s3 * l * dlm * pds + l * (1.0 - dlm) * pdp,
-             l * q * pds - s3 * l * n2 * pdp},
-            {s3 * m2 * l * pds + l * (1.0 - 2.0 * m2) * pdp, s3 * m2 * n * pds + n * (1.0 - 2.0 * m2) * pdp,
-             s3 * l * m * n * pds - 2.0 * l * m * n * pdp, 0.5 * s3 * m * dlm * pds - m * (1.0 + dlm) * pdp,
-             m * q * pds - s3 * m * n2 * pdp},
-            {s3 * l * m * n * pds - 2.0 * l * m * n * pdp, s3 * n2 * m * pds + m * (1.0 - 2.0 * n2) * pdp,
-             s3 * n2 * l * pds + l * (1.0 - 2.0 * n2) * pdp, 0.5 * s3 * n * dlm * pds - n * dlm * pdp,
-             n * q * pds + s3 * n * (l2 + m2) * pdp}};
+        double sdr[5], pd[3][5], sdl[5], pdl[3][5];
+        sk_sd_pd(vu, l, m, n, sdr, pd);
+        sk_sd_pd(vl, l, m, n, sdl, pdl);
         double dd[5][5];
         dd[0][0] = 3.0 * l2 * m2 * dds + (l2 + m2 - 4.0 * l2 * m2) * ddp + (n2 + l2 * m2) * ddd;
         dd[1][1] = 3.0 * m2 * n2 * dds + (m2 + n2 - 4.0 * m2 * n2) * ddp + (l2 + m2 * n2) * ddd;
@@ -110,10 +141,10 @@ __device__ __forceinline__ void sk_table(const double *v, double l, double m, do
         dd[4][4] = q * q * dds + 3.0 * n2 * (l2 + m2) * ddp + 0.75 * (l2 + m2) * (l2 + m2) * ddd;
         for (int a = 0; a < 5; ++a) {
             E[0][4 + a] = sdr[a];
-            E[4 + a][0] = sdr[a];                      // d-s: even
+            E[4 + a][0] = sdl[a];                      // d-s: even
             for (int b = 0; b < 3; ++b) {
                 E[1 + b][4 + a] = pd[b][a];
-                E[4 + a][1 + b] = -pd[b][a];           // d-p: odd
+                E[4 + a][1 + b] = -pdl[b][a];          // d-p: odd
             }
             for (int b = a; b < 5; ++b) {
                 E[4 + a][4 + b] = dd[a][b];
@@ -135,32 +166,48 @@ struct BondScales {
     int32_t K = 0;
 };
 
-// The integrals of the bond {i, j} (caller's atom indices).
-__device__ __forceinline__ const double *bond_integrals(const BondScales &bs, const SkValues &sk, int32_t i,
-                                                        int32_t j, double (&vb)[10]) {
-    if (!bs.y) return sk.v;
+// The integrals of the bond i -> j (caller's atom indices): vu of the ordered
+// species pair (s_i, s_j) and vl of (s_j, s_i), times the bond's learned scales.
+__device__ __forceinline__ void bond_integrals(const BondScales &bs, const SkValues &sk, int32_t i, int32_t j,
+                                               const double *&vu, const double *&vl, double (&bu)[10],
+                                               double (&bl)[10]) {
+    vu = sk.v;
+    vl = sk.v;
+    if (sk.pv) {
+        const int32_t si = sk.species[i], sj = sk.species[j];
+        vu = sk.pv + 10 * ((int64_t)si * sk.ns + sj);
+        vl = sk.pv + 10 * ((int64_t)sj * sk.ns + si);
+    }
+    if (!bs.y) return;
     const int32_t lo = min(i, j), hi = max(i, j);
     int64_t b = -1;
     for (int64_t q = bs.bond_ptr[lo]; q < bs.bond_ptr[lo + 1]; ++q)
         if (bs.bj[q] == hi) { b = q; break; }
-    for (int l = 0; l < 10; ++l)
-        vb[l] = (b >= 0 && l < bs.K) ? sk.v[l] * (1.0 + (double)bs.y[(int64_t)l * bs.nb + b]) : sk.v[l];
-    return vb;
+    for (int l = 0; l < 10; ++l) {
+        const double f = (b >= 0 && l < bs.K) ? 1.0 + (double)bs.y[(int64_t)l * bs.nb + b] : 1.0;
+        bu[l] = vu[l] * f;
+        bl[l] = vl[l] * f;
+    }
+    vu = bu;
+    vl = bl;
 }
 
 // The NORB x NORB block of a bond of length r and vector (dx, dy, dz) from the
-// row atom, integrals v at r0.
+// row atom, integrals vu, vl (sk_table) at r0.
 template <int NORB>
-__device__ __forceinline__ void sk_block(const double *v, const SkValues &sk, double r, double dx, double dy,
-                                         double dz, double (&B)[NORB][NORB]) {
-    sk_table<NORB>(v, dx / r, dy / r, dz / r, B);
+__device__ __forceinline__ void sk_block(const double *vu, const double *vl, const SkValues &sk, double r, double dx,
+                                         double dy, double dz, double (&B)[NORB][NORB]) {
+    sk_table<NORB>(vu, vl, dx / r, dy / r, dz / r, B);
     const double f = exp(-sk.beta * (r / sk.r0 - 1.0));
     for (int a = 0; a < NORB; ++a)
         for (int b = 0; b < NORB; ++b) B[a][b] *= f;
 }
 
-__device__ __forceinline__ double sk_onsite(const SkValues &sk, int a) {
-    return a == 0 ? sk.e_s : (a < 4 ? sk.e_p : sk.e_d);
+// Onsite energy of orbital a on atom i (caller's index).
+__device__ __forceinline__ double sk_onsite(const SkValues &sk, int32_t i, int a) {
+    const int sh = a == 0 ? 0 : (a < 4 ? 1 : 2);
+    if (sk.pv) return sk.se[3 * sk.species[i] + sh];
+    return sh == 0 ? sk.e_s : (sh == 1 ? sk.e_p : sk.e_d);
 }
 
 // One atom row r per thread: its NORB orbital rows, entry NORB q + b for the
@@ -188,8 +235,10 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
         for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[NORB][NORB], vb[10];
-            sk_block<NORB>(bond_integrals(bs, sk, i, j, vb), sk, rij, dx, dy, dz, B);
+            double B[NORB][NORB], bu[10], bl[10];
+            const double *vu, *vl;
+            bond_integrals(bs, sk, i, j, vu, vl, bu, bl);
+            sk_block<NORB>(vu, vl, sk, rij, dx, dy, dz, B);
             const int32_t cj = NORB * iperm[j];
             for (int a = 0; a < NORB; ++a)
                 for (int b = 0; b < NORB; ++b) {
@@ -214,7 +263,7 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
                     col16[base[a] + (int64_t)k * slice] =
                         (d >= -32767 && d <= 32767) ? (int16_t)d : (int16_t)-32768;
                 }
-            const double e = sk_onsite(sk, a);
+            const double e = sk_onsite(sk, i, a);
             onsite[R] = (V)e;
             lo = fmin(lo, e - asum[a]);
             hi = fmax(hi, e + asum[a]);
@@ -244,8 +293,10 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
         for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[NORB][NORB], vb[10];
-            sk_block<NORB>(bond_integrals(bs, sk, i, j, vb), sk, rij, dx, dy, dz, B);
+            double B[NORB][NORB], bu[10], bl[10];
+            const double *vu, *vl;
+            bond_integrals(bs, sk, i, j, vu, vl, bu, bl);
+            sk_block<NORB>(vu, vl, sk, rij, dx, dy, dz, B);
             if (q < w) {
                 const int64_t slot = base + (int64_t)q * slice;
                 bcol[slot] = iperm[j];
@@ -262,7 +313,7 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
             for (int e = 0; e < NB; ++e) bval[NB * slot + e] = (V)0;
         }
         for (int a = 0; a < NORB; ++a) {
-            const double e = sk_onsite(sk, a);
+            const double e = sk_onsite(sk, i, a);
             onsite[NORB * r + a] = (V)e;
             lo = fmin(lo, e - asum[a]);
             hi = fmax(hi, e + asum[a]);
@@ -281,8 +332,27 @@ tbk_status check_sk(const tbk_sk_params *sk) {
                           sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi, sk->v_sd_sigma,
                           sk->v_pd_sigma, sk->v_pd_pi, sk->v_dd_sigma, sk->v_dd_pi, sk->v_dd_delta};
     for (double v : x) TBK_CHECK(std::isfinite(v), TBK_ERR_NOT_FINITE, "an SK parameter is not finite");
+    if (!sk->pair_v) return TBK_OK;
+    const int32_t ns = sk->n_species;
+    TBK_CHECK(ns >= 1 && ns <= 16, TBK_ERR_INVALID_ARG, "n_species = %d outside [1, 16]", ns);
+    TBK_CHECK(sk->species_e != nullptr, TBK_ERR_INVALID_ARG, "species_e is NULL");
+    for (int64_t k = 0; k < (int64_t)ns * ns * 10; ++k)
+        TBK_CHECK(std::isfinite(sk->pair_v[k]), TBK_ERR_NOT_FINITE, "pair_v[%lld] is not finite", (long long)k);
+    for (int64_t k = 0; k < 3 * (int64_t)ns; ++k)
+        TBK_CHECK(std::isfinite(sk->species_e[k]), TBK_ERR_NOT_FINITE, "species_e[%lld] is not finite",
+                  (long long)k);
+    // equal-l integrals (ss, pp, dd) do not depend on the order of the pair
+    static const int same_l[6] = {0, 2, 3, 7, 8, 9};
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int l : same_l)
+                TBK_CHECK(sk->pair_v[10 * (a * ns + b) + l] == sk->pair_v[10 * (b * ns + a) + l], TBK_ERR_INVALID_ARG,
+                          "pair_v[%d][%d][%d] differs from pair_v[%d][%d][%d] (an equal-l integral)", a, b, l, b, a,
+                          l);
     return TBK_OK;
 }
+
+int32_t species_count(const tbk_sk_params *sk) { return sk->pair_v ? sk->n_species : 1; }
 
 // One-orbital plan of the atoms (cell list, row order, atom degrees) for the SK builder.
 tbk_status atom_plan(const double *pos, const int32_t *species, int64_t n, const double box[3],
@@ -293,15 +363,17 @@ tbk_status atom_plan(const double *pos, const int32_t *species, int64_t n, const
     TBK_CHECK(box != nullptr, TBK_ERR_INVALID_ARG, "box is NULL");
     TBK_CHECK(n >= 1 && sk->orbitals * n < (int64_t)INT32_MAX, TBK_ERR_INVALID_ARG,
               "%lld orbital rows out of range", (long long)(sk->orbitals * n));
-    const double onsite0 = 0.0, t0 = 1.0;
+    // the one-orbital plan validates the species indices against n_species
+    const int32_t ns = species_count(sk);
+    std::vector<double> onsite0(ns, 0.0), t0((size_t)ns * ns, 1.0);
     tbk_tb_params p{};
     p.r_cut = sk->r_cut;
     p.r0 = sk->r0;
     p.beta = sk->beta;
-    p.n_species = 1;
+    p.n_species = ns;
     p.reorder = sk->reorder;
-    p.onsite = &onsite0;
-    p.t_pair = &t0;
+    p.onsite = onsite0.data();
+    p.t_pair = t0.data();
     const int64_t seg[2] = {0, n};
     return plan.run(pos, species, n, 1, seg, box, periodic, &p, TBK_SELL_F64, atom_slice, s);
 }
@@ -358,6 +430,11 @@ tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, cons
     }
     h->n_bonds = plan.n_bonds;
     h->has_onsite = (sk->e_s != 0.0 || sk->e_p != 0.0 || (norb == 9 && sk->e_d != 0.0)) ? 1 : 0;
+    if (sk->pair_v) {
+        h->has_onsite = 0;
+        for (int64_t k = 0; k < 3 * (int64_t)sk->n_species; ++k)
+            if ((k % 3 < 2 || norb == 9) && sk->species_e[k] != 0.0) h->has_onsite = 1;
+    }
     h->n_seg = 1;
     h->n_orb = norb;
     h->uniform_hop = 0;
@@ -453,6 +530,18 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
     SkValues v{sk->r0, sk->beta, sk->e_s, sk->e_p, sk->e_d,
                {sk->v_ss_sigma, sk->v_sp_sigma, sk->v_pp_sigma, sk->v_pp_pi, sk->v_sd_sigma, sk->v_pd_sigma,
                 sk->v_pd_pi, sk->v_dd_sigma, sk->v_dd_pi, sk->v_dd_delta}};
+    DevBuf dpv, dse;
+    if (sk->pair_v) {
+        const int32_t ns = sk->n_species;
+        TBK_HIP(dpv.alloc(sizeof(double) * 10 * ns * ns, s));
+        TBK_HIP(dse.alloc(sizeof(double) * 3 * ns, s));
+        TBK_HIP(hipMemcpyAsync(dpv.as<double>(), sk->pair_v, sizeof(double) * 10 * ns * ns, hipMemcpyHostToDevice, s));
+        TBK_HIP(hipMemcpyAsync(dse.as<double>(), sk->species_e, sizeof(double) * 3 * ns, hipMemcpyHostToDevice, s));
+        v.pv = dpv.as<double>();
+        v.se = dse.as<double>();
+        v.species = species;
+        v.ns = ns;
+    }
     BondScales bs;
     DevBuf vdesc, bi, bj, br, X, y, bptr;
     if (model) {

@@ -71,7 +71,9 @@ class SkParams(ctypes.Structure):
                 ("v_pp_sigma", ctypes.c_double), ("v_pp_pi", ctypes.c_double), ("reorder", ctypes.c_int32),
                 ("orbitals", ctypes.c_int32), ("e_d", ctypes.c_double),
                 ("v_sd_sigma", ctypes.c_double), ("v_pd_sigma", ctypes.c_double), ("v_pd_pi", ctypes.c_double),
-                ("v_dd_sigma", ctypes.c_double), ("v_dd_pi", ctypes.c_double), ("v_dd_delta", ctypes.c_double)]
+                ("v_dd_sigma", ctypes.c_double), ("v_dd_pi", ctypes.c_double), ("v_dd_delta", ctypes.c_double),
+                ("n_species", ctypes.c_int32), ("pair_v", ctypes.POINTER(ctypes.c_double)),
+                ("species_e", ctypes.POINTER(ctypes.c_double))]
 
 
 class MlpModel(ctypes.Structure):
@@ -365,14 +367,19 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
 
 def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi, e_s, e_p,
                          r_cut=2.0, r0=1.42, beta=3.37, fmt="sell_f32", slice=256, reorder=True, stream=None,
-                         d=None, e_d=0.0, model=None, with_bond_y=False):
+                         d=None, e_d=0.0, model=None, with_bond_y=False, pair_v=None, species_e=None):
     """Slater-Koster orbital Hamiltonian on the GPU: s, p (4 rows per atom), or
     s, p, d (9 rows per atom) when d = (v_sd_sigma, v_pd_sigma, v_pd_pi,
     v_dd_sigma, v_dd_pi, v_dd_delta) is given.
 
     model = dict(params=[K][1633] float32 tensor, shift=[16], scale=[16], r_desc=4.0):
     the learned form, each bond's integral l scaled by 1 + y_l from network l
-    (K = 4 or 10).  with_bond_y also returns y [K][n_bonds]."""
+    (K = 4 or 10).  with_bond_y also returns y [K][n_bonds].
+
+    pair_v [ns][ns][K], species_e [ns][3]: several species (species indices in
+    `species`), integrals per ordered species pair (lower angular momentum on
+    the first species), onsite energies per species; the single-species
+    integrals and onsite energies are then unused."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
@@ -383,6 +390,20 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     norb = 4 if d is None else 9
     sk = SkParams(float(r_cut), float(r0), float(beta), float(e_s), float(e_p), float(v_ss_sigma),
                   float(v_sp_sigma), float(v_pp_sigma), float(v_pp_pi), int(bool(reorder)), norb, float(e_d), *dv)
+    keep = None
+    if pair_v is not None:
+        import numpy as np
+        pv0 = np.asarray(pair_v, np.float64)
+        ns = pv0.shape[0]
+        if pv0.shape != (ns, ns, 4 if norb == 4 else 10):
+            raise ValueError(f"pair_v has shape {pv0.shape}, expected ({ns}, {ns}, {4 if norb == 4 else 10})")
+        pv = np.zeros((ns, ns, 10))
+        pv[:, :, : pv0.shape[2]] = pv0
+        se = np.asarray(species_e, np.float64).reshape(ns, 3)
+        keep = (_f64arr(pv.reshape(-1)), _f64arr(se.reshape(-1)))
+        sk.n_species = ns
+        sk.pair_v = ctypes.cast(keep[0], ctypes.POINTER(ctypes.c_double))
+        sk.species_e = ctypes.cast(keep[1], ctypes.POINTER(ctypes.c_double))
     boxa = _f64arr(box)
     per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
     s = _stream(stream)

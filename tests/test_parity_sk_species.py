@@ -1,0 +1,131 @@
+"""GPU parity of the Slater-Koster Hamiltonian with several species (integrals per
+ordered species pair, onsite energies per species) on h-BN/graphene stripes:
+pattern exact, values within 2e-15 (FP64) / 1e-6 (FP32) relative to the largest,
+onsite exact (after FP32 rounding), Gershgorin bounds; FP64 moments within 1e-10
+of the row count; the learned scales on top of the species tables; argument
+errors."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def tables(ns, K, seed):
+    rng = np.random.default_rng(seed)
+    pv = rng.uniform(-6.0, 6.0, (ns, ns, K))
+    for l in (0, 2, 3, 7, 8, 9)[: 3 if K == 4 else 6]:
+        pv[:, :, l] = 0.5 * (pv[:, :, l] + pv[:, :, l].T)
+    return pv, rng.uniform(-8.0, 8.0, (ns, 3))
+
+
+def build(s, norb, fmt, slice_, pv, se, model=None, with_y=False):
+    return tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                      synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                      fmt=fmt, slice=slice_, d=synth.SK_D if norb == 9 else None, e_d=synth.SK_ED,
+                                      pair_v=pv, species_e=se, model=model, with_bond_y=with_y)
+
+
+def oracle_csr(s, norb, pv, se, pairs=None, scale=None):
+    return O.sk_hamiltonian(s.pos, s.box, s.periodic, np.zeros(4 if norb == 4 else 10), 0.0, 0.0,
+                            r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, pairs=pairs, scale=scale,
+                            species=s.species, pair_v=pv, species_e=se)[0]
+
+
+def compare(H, csr, fmt, norb):
+    rows, cols, vals, onsite = G.block_entries(H) if fmt.startswith("bsell4") else G.entries_in_atom_order(H)
+    orow, ocol, oval = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_array_equal(rows[o1], orow[o2])
+    np.testing.assert_array_equal(cols[o1], ocol[o2])
+    return vals[o1], oval[o2], onsite
+
+
+@pytest.mark.parametrize("norb,fmt,slice_", [(4, "sell_f64", 16), (4, "bsell4_f64", 16), (9, "sell_f32", 64),
+                                             (9, "bsell4_f64", 8), (9, "bsell4_f32", 32), (4, "csr_f64", 1)])
+def test_species_builder_matches_oracle(norb, fmt, slice_):
+    s = synth.hbn_stripes(10, 6, stripe_cells=2, sigma=0.08, seed=4)
+    assert set(np.unique(s.species)) == {0, 1, 2}
+    K = 4 if norb == 4 else 10
+    pv, se = tables(3, K, 11)
+    H = build(s, norb, fmt, slice_, pv, se)
+    csr = oracle_csr(s, norb, pv, se)
+    v, ov, onsite = compare(H, csr, fmt, norb)
+    tol = 1e-6 if fmt.endswith("f32") else 2e-15
+    np.testing.assert_allclose(v, ov, rtol=tol, atol=tol * np.abs(ov).max())
+    odiag = csr.diag.astype(np.float32).astype(np.float64) if fmt.endswith("f32") else csr.diag
+    np.testing.assert_array_equal(onsite, odiag)
+    lo, hi = O.gershgorin(csr)
+    assert H.bounds[0] == pytest.approx(lo, rel=1e-6) and H.bounds[1] == pytest.approx(hi, rel=1e-6)
+
+
+@pytest.mark.parametrize("atom", [0, 1])
+def test_species_fp64_moments(atom):
+    s = synth.hbn_stripes(9, 7, stripe_cells=3, sigma=0.05, seed=8)
+    pv, se = tables(3, 10, 2)
+    H = build(s, 9, "bsell4_f64", 16, pv, se)
+    csr = oracle_csr(s, 9, pv, se)
+    a, b = G.oracle_ab(csr)
+    r = synth.random_phase(9 * s.n, 3, 4)
+    cfg = tbkpm.make_config(1, 2, 1, 0, 1, atom_rows=atom)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r, 61)
+    assert np.abs(mu - mo).max() <= 1e-10 * 9 * s.n
+
+
+def test_species_with_learned_scales():
+    s = synth.hbn_stripes(8, 5, stripe_cells=2, sigma=0.07, seed=6)
+    pv, se = tables(3, 4, 9)
+    pd = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+    vo = O.descriptor(s.n, pd, synth.R_DESC, 8)
+    hop = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_HOP)
+    o = np.lexsort((hop[1], hop[0]))
+    hop = (hop[0][o], hop[1][o], hop[2][o])
+    raw = O.bond_features(hop, vo, synth.R_DESC)
+    mean, std = raw.mean(0), raw.std(0)
+    base = synth.init_mlp_params(3, out_scale=0.5)
+    rng = np.random.default_rng(4)
+    P = np.repeat(base[None, :], 4, axis=0)
+    P[:, 1600:1632] = rng.uniform(-0.5, 0.5, (4, 32)) / np.sqrt(32)
+    P = P.astype(np.float32)
+    H, y = build(s, 4, "bsell4_f64", 16, pv, se,
+                 model=dict(params=G.to_dev(P), shift=mean, scale=std, r_desc=synth.R_DESC), with_y=True)
+    Xo = O.bf16(O.bond_features(hop, vo, synth.R_DESC, mean, std))
+    Y, clear = [], None
+    for p in P:
+        yo, h1, h2 = O.mlp_forward(Xo, p.astype(np.float64), bf16_ops=True, keep=True)
+        Y.append(yo)
+        clear = G.bf16_decisions_clear(h1, h2)
+    Y = np.stack(Y)
+    csr = oracle_csr(s, 4, pv, se, pairs=hop, scale=1.0 + Y.T)
+    v, ov, _ = compare(H, csr, "bsell4_f64", 4)
+    assert clear.mean() >= 0.3
+    orow, ocol, _ = G.csr_entries(csr)
+    o2 = np.lexsort((ocol, orow))
+    bond_of = {(int(i), int(j)): e for e, (i, j) in enumerate(zip(hop[0], hop[1]))}
+    ent_clear = np.array([clear[bond_of[(min(i // 4, j // 4), max(i // 4, j // 4))]]
+                          for i, j in zip(orow[o2], ocol[o2])])
+    err = np.abs(v - ov)
+    assert err[ent_clear].max() <= 5e-5 * np.abs(ov).max()
+    assert err.max() <= 1e-2 * np.abs(ov).max()
+
+
+def test_species_errors():
+    s = synth.hbn_stripes(6, 4, stripe_cells=2, sigma=0.0, seed=1)
+    pv, se = tables(3, 4, 1)
+    bad = pv.copy()
+    bad[0, 1, 2] += 1.0                                   # pp_sigma of (0, 1) differs from (1, 0)
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(s, 4, "sell_f64", 8, bad, se)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(s, 4, "sell_f64", 8, pv[:2, :2], se[:2])      # species 2 outside two species
+    assert e.value.name == "INVALID_ARG"
+    nan = pv.copy()
+    nan[2, 2, 0] = np.nan
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(s, 4, "sell_f64", 8, nan, se)
+    assert e.value.name == "NOT_FINITE"
