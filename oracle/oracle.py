@@ -319,14 +319,24 @@ def mobility(sigma, N, n_ref):
     return ssc, car, mob
 
 
+def node_features(v, shift, scale):
+    """Onsite-network inputs of Eq. (2) (the node feature v_i): [(v_i - shift) / scale || 0 x 8],
+    rounded to bfloat16 (16 inputs, as the bond network's)."""
+    v = np.asarray(v, np.float64)
+    X = np.zeros((v.shape[0], 16))
+    X[:, :8] = (v - np.asarray(shift, np.float64)) / np.asarray(scale, np.float64)
+    return bf16(X)
+
+
 def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.37, pairs=None, e_d=0.0,
-                   scale=None, species=None, pair_v=None, species_e=None):
+                   scale=None, species=None, pair_v=None, species_e=None, onsite_add=None):
     """Slater-Koster orbital Hamiltonian as a CSR: v holds 4 integrals (s, p: orbital 4 i + a,
     a = s, x, y, z) or 10 (s, p, d: orbital 9 i + a, then dxy, dyz, dzx, dx2-y2, d3z2-r2)
     at r0; scale [npairs][len(v)] (optional) multiplies each pair's integrals (learned form).
     Several species: species [n], pair_v [ns][ns][len(v)] (ordered pair, lower angular
     momentum on the first species), species_e [ns][3] replace v and e_s, e_p, e_d.
-    Returns (csr, pairs)."""
+    onsite_add [n][3] (optional): added to the onsite energy of each atom's s, p, d shell
+    (the onsite network of Eq. (2)).  Returns (csr, pairs)."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     if pairs is None:
         pairs = neighbor_pairs(pos, box, periodic, r_cut)
@@ -365,6 +375,10 @@ def sk_hamiltonian(pos, box, periodic, v, e_s, e_p, r_cut=2.0, r0=1.42, beta=3.3
                                 float(r0), float(beta), row_ptr, col, val, diag)
     if rc != 0:
         raise OracleError("orc_assemble_sk failed")
+    if onsite_add is not None:
+        add = np.asarray(onsite_add, np.float64).reshape(n, 3)
+        shell = np.array([0, 1, 1, 1, 2, 2, 2, 2, 2])[:norb]
+        diag = diag + add[:, shell].reshape(-1)
     return CSR(row_ptr, col, val, diag), pairs
 
 

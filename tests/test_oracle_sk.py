@@ -264,3 +264,18 @@ def test_species_relabelling_and_single_species_limit():
                           pair_v=one, species_e=np.tile([ES, EP, ED], (3, 1)))[0].dense()
     H0 = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, ES, EP, e_d=ED, pairs=pairs)[0].dense()
     np.testing.assert_array_equal(H1, H0)
+
+
+def test_onsite_addition_and_node_features():
+    """The onsite network's output is added per atom and shell; its inputs are the
+    standardised node features in the first eight slots, bfloat16-rounded."""
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.42]])
+    add = np.array([[0.5, -0.25, 1.0], [0.125, 0.75, -2.0]])
+    csr, _ = O.sk_hamiltonian(pos, np.zeros(3), OPEN, V10, ES, EP, e_d=ED, onsite_add=add)
+    np.testing.assert_array_equal(np.diag(csr.dense())[:9], [ES + 0.5] + [EP - 0.25] * 3 + [ED + 1.0] * 5)
+    np.testing.assert_array_equal(np.diag(csr.dense())[9:], [ES + 0.125] + [EP + 0.75] * 3 + [ED - 2.0] * 5)
+    v = np.array([[1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0]])
+    X = O.node_features(v, np.full(8, 1.0), np.full(8, 2.0))
+    np.testing.assert_array_equal(X[0, :8], (v[0] - 1.0) / 2.0)        # exact in bfloat16
+    np.testing.assert_array_equal(X[0, 8:], 0.0)
+    assert O.node_features(np.array([[1.0 + 2 ** -12] + [0.0] * 7]), np.zeros(8), np.ones(8))[0, 0] == 1.0
