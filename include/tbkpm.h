@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 8
+#define TBK_ABI_VERSION 9
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -394,6 +394,14 @@ tbk_status tbk_bond_features(int64_t nb, const int32_t *bi, const int32_t *bj, c
                              const double *v, int32_t n_radial, double r_cut, const double *shift,
                              const double *scale, uint16_t *X, void *stream);
 
+/* Onsite-network inputs of Eq. (2) (the node feature v_i of each atom):
+ * X[i] = bfloat16 bits of [(v_i - shift) / scale || 0 x 8] (16 values, the
+ * bond network's input width), one rounding from double.  v device double
+ * [n][n_radial] (tbk_descriptor); shift, scale host [8]; X device uint16
+ * [n][16].  Errors: UNSUPPORTED (n_radial != 8), INVALID_ARG. */
+tbk_status tbk_node_features(int64_t n, const double *v, int32_t n_radial, const double *shift,
+                             const double *scale, uint16_t *X, void *stream);
+
 /* Mean and standard deviation (host double [16] each) of the unstandardised
  * bond features over nb bonds (FP64, fixed summation order); used as the
  * fixed feature shift and scale of a model.  Synchronises `stream`. */
@@ -545,6 +553,20 @@ tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, in
                                    const tbk_sk_params *sk, tbk_ham *h, double spec_bounds[2],
                                    void *stream);
 
+/* Onsite network of Eq. (2): the onsite energy of shell l (s, p, d) on an atom
+ * of species a is e_{a,l} + y_{a,l}, y_{a,l} the output of network (a, l) on
+ * the atom's node features (tbk_node_features of its descriptor v_i at cutoff
+ * r_cut; the shape and bfloat16 products of tbk_mlp_model).
+ *   params device float [n_species][n_shells][TBK_MLP_PARAMS], n_shells = 2
+ *   for orbitals = 4, 3 for 9; n_species as in tbk_sk_params (1 without
+ *   pair_v). */
+typedef struct {
+    double r_cut;          /* descriptor cutoff (A)              */
+    const double *shift;   /* host [8] node-feature shifts       */
+    const double *scale;   /* host [8] node-feature scales       */
+    const float *params;   /* device, see above                  */
+} tbk_onsite_model;
+
 /*
  * Learned Slater-Koster Hamiltonian (Eq. (2): the two-centre integrals of a
  * bond are network outputs of its edge features, the angular factors P_lambda
@@ -553,8 +575,9 @@ tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, in
  * in the order of tbk_sk_params), where y_l is the output of network l on the
  * bond's standardised features [f_0..7(r_ij) || v_i + v_j] (the inputs, the
  * network shape and the bfloat16 products of tbk_mlp_model).  One network per
- * integral: model->params is device float [K][TBK_MLP_PARAMS].  Onsite
- * energies stay the fixed e_s, e_p, e_d.  bond_y (device float, capacity
+ * integral: model->params is device float [K][TBK_MLP_PARAMS].  With onsite
+ * (may be NULL) the onsite energies are those of tbk_onsite_model; model may
+ * be NULL when onsite is given (fixed two-centre integrals).  bond_y (device float, capacity
  * bond_cap >= K n_bonds, may be NULL) receives y [K][n_bonds] in tbk_bonds
  * order (bonds i < j of the hopping cutoff sk->r_cut); *n_bonds (may be NULL)
  * the bond count.  spec_bounds from the learned values.
@@ -564,8 +587,9 @@ tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *species, in
 tbk_status tb_build_hamiltonian_sk_learned(const double *pos, const int32_t *species, int64_t n,
                                            const double box[3], const int32_t periodic[3],
                                            const tbk_sk_params *sk, const tbk_mlp_model *model,
-                                           tbk_ham *h, double spec_bounds[2], float *bond_y,
-                                           int64_t bond_cap, int64_t *n_bonds, void *stream);
+                                           const tbk_onsite_model *onsite, tbk_ham *h,
+                                           double spec_bounds[2], float *bond_y, int64_t bond_cap,
+                                           int64_t *n_bonds, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Velocity autocorrelation conductivity, Eq. (3)                            */

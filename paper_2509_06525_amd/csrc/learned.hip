@@ -159,6 +159,14 @@ __global__ void k_bond_features(int64_t nb, const int32_t *__restrict__ bi, cons
     for (int k = 0; k < kNI; ++k) X[b * kNI + k] = d2bf(x[k]);
 }
 
+// Onsite-network inputs: X[i] = bf16([(v_i - shift) / scale || 0 x 8]).
+__global__ void k_node_features(int64_t n, const double *__restrict__ v, FeatNorm fn, uint16_t *__restrict__ X) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < kNR; ++k) X[i * kNI + k] = d2bf((v[i * kNR + k] - fn.shift[k]) / fn.inv_scale[k]);
+    for (int k = kNR; k < kNI; ++k) X[i * kNI + k] = 0;
+}
+
 // Per-block partial sums of each standardisation-free feature and its square
 // (for the fixed feature shift/scale taken from training data): part[block][2][16].
 __global__ void k_feature_moments(int64_t nb, const int32_t *__restrict__ bi, const int32_t *__restrict__ bj,
@@ -585,6 +593,26 @@ static tbk_status bonds_impl(const double *pos, int64_t n, int32_t nseg, const i
 }  // namespace tbk
 
 using namespace tbk;
+
+extern "C" tbk_status tbk_node_features(int64_t n, const double *v, int32_t n_radial, const double *shift,
+                                        const double *scale, uint16_t *X, void *stream) {
+    clear_error();
+    TBK_CHECK(n_radial == kNR, TBK_ERR_UNSUPPORTED, "features need %d radial functions", kNR);
+    TBK_CHECK(n >= 0 && shift && scale, TBK_ERR_INVALID_ARG, "bad arguments");
+    FeatNorm fn{};
+    for (int k = 0; k < kNR; ++k) {
+        TBK_CHECK(scale[k] != 0.0 && std::isfinite(scale[k]) && std::isfinite(shift[k]), TBK_ERR_INVALID_ARG,
+                  "node feature %d: shift/scale invalid", k);
+        fn.shift[k] = shift[k];
+        fn.inv_scale[k] = scale[k];        // this kernel divides by the scale itself
+    }
+    if (n == 0) return TBK_OK;
+    TBK_CHECK(v && X, TBK_ERR_INVALID_ARG, "NULL array");
+    hipStream_t s = as_stream(stream);
+    k_node_features<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(n, v, fn, X);
+    TBK_HIP(hipGetLastError());
+    return TBK_OK;
+}
 
 extern "C" tbk_status tbk_descriptor(const double *pos, int32_t n_seg, const int64_t *seg_atoms, const double *boxes,
                                      const int32_t periodic[3], double r_cut, int32_t n_radial, double *v,

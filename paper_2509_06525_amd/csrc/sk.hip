@@ -67,6 +67,10 @@ struct SkValues {
     const double *se = nullptr;
     const int32_t *species = nullptr;
     int32_t ns = 1;
+    // onsite network (yon != NULL): yon[(s_i n_sh + shell) n_atoms + i] added to the onsite energy
+    const float *yon = nullptr;
+    int64_t n_atoms = 0;
+    int32_t n_sh = 0;
 };
 
 // The s-d row and the p-d block of the table for integrals v.
@@ -206,8 +210,9 @@ __device__ __forceinline__ void sk_block(const double *vu, const double *vl, con
 // Onsite energy of orbital a on atom i (caller's index).
 __device__ __forceinline__ double sk_onsite(const SkValues &sk, int32_t i, int a) {
     const int sh = a == 0 ? 0 : (a < 4 ? 1 : 2);
-    if (sk.pv) return sk.se[3 * sk.species[i] + sh];
-    return sh == 0 ? sk.e_s : (sh == 1 ? sk.e_p : sk.e_d);
+    const double e = sk.pv ? sk.se[3 * sk.species[i] + sh] : (sh == 0 ? sk.e_s : (sh == 1 ? sk.e_p : sk.e_d));
+    if (!sk.yon) return e;
+    return e + (double)sk.yon[((int64_t)sk.species[i] * sk.n_sh + sh) * sk.n_atoms + i];
 }
 
 // One atom row r per thread: its NORB orbital rows, entry NORB q + b for the
@@ -416,7 +421,8 @@ int32_t log2i(int32_t v) {
     return l;
 }
 
-tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, const tbk_sk_params *sk, tbk_ham *h) {
+tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, const tbk_sk_params *sk, tbk_ham *h,
+                        bool learned_onsite = false) {
     const int32_t norb = sk->orbitals;
     h->n_rows = norb * n;
     if (is_block(h->fmt)) {      // blocks over atom slices
@@ -435,6 +441,7 @@ tbk_status set_sk_sizes(int64_t n, const HamPlan &plan, const SkLayout &ly, cons
         for (int64_t k = 0; k < 3 * (int64_t)sk->n_species; ++k)
             if ((k % 3 < 2 || norb == 9) && sk->species_e[k] != 0.0) h->has_onsite = 1;
     }
+    if (learned_onsite) h->has_onsite = 1;
     h->n_seg = 1;
     h->n_orb = norb;
     h->uniform_hop = 0;
@@ -493,8 +500,9 @@ namespace {
 // one network per integral (bond features of the descriptor model, MLP
 // forward of the learned-hopping path).
 tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const double box[3],
-                    const int32_t periodic[3], const tbk_sk_params *sk, const tbk_mlp_model *model, tbk_ham *h,
-                    double spec_bounds[2], float *bond_y, int64_t bond_cap, int64_t *n_bonds, hipStream_t s) {
+                    const int32_t periodic[3], const tbk_sk_params *sk, const tbk_mlp_model *model,
+                    const tbk_onsite_model *onsite, tbk_ham *h, double spec_bounds[2], float *bond_y,
+                    int64_t bond_cap, int64_t *n_bonds, hipStream_t s) {
     TBK_CHECK(h != nullptr && spec_bounds != nullptr, TBK_ERR_INVALID_ARG, "h or bounds is NULL");
     TBK_CHECK(h->fmt == TBK_SELL_F32 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_CSR_F64 || is_block(h->fmt),
               TBK_ERR_INVALID_ARG, "unknown format %d", h->fmt);
@@ -541,6 +549,28 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
         v.se = dse.as<double>();
         v.species = species;
         v.ns = ns;
+    }
+    DevBuf von, Xn, yon;
+    if (onsite) {
+        // node features -> one network per (species, shell)
+        const int32_t ns = species_count(sk), nsh = norb == 4 ? 2 : 3;
+        const int64_t seg[2] = {0, n};
+        TBK_HIP(von.alloc(sizeof(double) * n * 8, s));
+        TBK_HIP(Xn.alloc(sizeof(uint16_t) * 16 * n, s));
+        TBK_HIP(yon.alloc(sizeof(float) * ns * nsh * n, s));
+        st = tbk_descriptor(pos, 1, seg, box, periodic, onsite->r_cut, 8, von.as<double>(), s);
+        if (st != TBK_OK) return st;
+        st = tbk_node_features(n, von.as<double>(), 8, onsite->shift, onsite->scale, Xn.as<uint16_t>(), s);
+        if (st != TBK_OK) return st;
+        for (int32_t q = 0; q < ns * nsh; ++q) {
+            st = tbk_mlp_forward(n, Xn.as<uint16_t>(), onsite->params + (int64_t)q * TBK_MLP_PARAMS,
+                                 yon.as<float>() + (int64_t)q * n, s);
+            if (st != TBK_OK) return st;
+        }
+        v.yon = yon.as<float>();
+        v.n_atoms = n;
+        v.n_sh = nsh;
+        v.species = species;
     }
     BondScales bs;
     DevBuf vdesc, bi, bj, br, X, y, bptr;
@@ -602,7 +632,7 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
     decode_bounds(hk, 1, spec_bounds);
     if (h->fmt == TBK_CSR_F64) h->slice = 1;
     h->seg_rows = nullptr;
-    return set_sk_sizes(n, plan, ly, sk, h);
+    return set_sk_sizes(n, plan, ly, sk, h, onsite != nullptr);
 }
 
 }  // namespace
@@ -613,20 +643,30 @@ extern "C" tbk_status tb_build_hamiltonian_sk(const double *pos, const int32_t *
                                               const tbk_sk_params *sk, tbk_ham *h, double spec_bounds[2],
                                               void *stream) {
     clear_error();
-    return build_sk(pos, species, n, box, periodic, sk, nullptr, h, spec_bounds, nullptr, 0, nullptr,
+    return build_sk(pos, species, n, box, periodic, sk, nullptr, nullptr, h, spec_bounds, nullptr, 0, nullptr,
                     as_stream(stream));
 }
 
 extern "C" tbk_status tb_build_hamiltonian_sk_learned(const double *pos, const int32_t *species, int64_t n,
                                                       const double box[3], const int32_t periodic[3],
                                                       const tbk_sk_params *sk, const tbk_mlp_model *model,
-                                                      tbk_ham *h, double spec_bounds[2], float *bond_y,
-                                                      int64_t bond_cap, int64_t *n_bonds, void *stream) {
+                                                      const tbk_onsite_model *onsite, tbk_ham *h,
+                                                      double spec_bounds[2], float *bond_y, int64_t bond_cap,
+                                                      int64_t *n_bonds, void *stream) {
     clear_error();
-    TBK_CHECK(model && model->params && model->shift && model->scale, TBK_ERR_INVALID_ARG, "model is incomplete");
-    TBK_CHECK(model->n_radial == 8, TBK_ERR_INVALID_ARG, "n_radial = %d (must be 8)", model->n_radial);
-    TBK_CHECK(std::isfinite(model->r_cut) && model->r_cut > 0, TBK_ERR_INVALID_ARG, "descriptor cutoff %g",
-              model->r_cut);
-    return build_sk(pos, species, n, box, periodic, sk, model, h, spec_bounds, bond_y, bond_cap, n_bonds,
+    TBK_CHECK(model || onsite, TBK_ERR_INVALID_ARG, "neither a bond model nor an onsite model");
+    if (model) {
+        TBK_CHECK(model->params && model->shift && model->scale, TBK_ERR_INVALID_ARG, "model is incomplete");
+        TBK_CHECK(model->n_radial == 8, TBK_ERR_INVALID_ARG, "n_radial = %d (must be 8)", model->n_radial);
+        TBK_CHECK(std::isfinite(model->r_cut) && model->r_cut > 0, TBK_ERR_INVALID_ARG, "descriptor cutoff %g",
+                  model->r_cut);
+    }
+    if (onsite) {
+        TBK_CHECK(onsite->params && onsite->shift && onsite->scale, TBK_ERR_INVALID_ARG,
+                  "onsite model is incomplete");
+        TBK_CHECK(std::isfinite(onsite->r_cut) && onsite->r_cut > 0, TBK_ERR_INVALID_ARG,
+                  "onsite descriptor cutoff %g", onsite->r_cut);
+    }
+    return build_sk(pos, species, n, box, periodic, sk, model, onsite, h, spec_bounds, bond_y, bond_cap, n_bonds,
                     as_stream(stream));
 }

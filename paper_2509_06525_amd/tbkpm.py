@@ -61,7 +61,8 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_coordination_target", "tbk_mlp_forward", "tbk_mlp_workspace_size",
                "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned",
                "tb_build_velocity", "lsqt_chebyshev_terms", "lsqt_workspace_size", "lsqt_vac_moments",
-               "lsqt_sigma", "kpm_integrated_dos", "lsqt_mobility", "tb_build_hamiltonian_sk_learned")
+               "lsqt_sigma", "kpm_integrated_dos", "lsqt_mobility", "tb_build_hamiltonian_sk_learned",
+               "tbk_node_features")
 
 
 class SkParams(ctypes.Structure):
@@ -80,6 +81,11 @@ class MlpModel(ctypes.Structure):
     _fields_ = [("r_cut", ctypes.c_double), ("n_radial", ctypes.c_int32),
                 ("shift", ctypes.POINTER(ctypes.c_double)), ("scale", ctypes.POINTER(ctypes.c_double)),
                 ("params", ctypes.c_void_p)]
+
+
+class OnsiteModel(ctypes.Structure):
+    _fields_ = [("r_cut", ctypes.c_double), ("shift", ctypes.POINTER(ctypes.c_double)),
+                ("scale", ctypes.POINTER(ctypes.c_double)), ("params", ctypes.c_void_p)]
 
 
 class KpmConfig(ctypes.Structure):
@@ -228,8 +234,10 @@ def lib():
     L.tb_build_hamiltonian_sk_learned.restype = ctypes.c_int
     L.tb_build_hamiltonian_sk_learned.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                                   ctypes.POINTER(SkParams), ctypes.POINTER(MlpModel),
-                                                  ctypes.POINTER(HamStruct), ctypes.POINTER(f64), vp, i64,
-                                                  ctypes.POINTER(i64), vp]
+                                                  ctypes.POINTER(OnsiteModel), ctypes.POINTER(HamStruct),
+                                                  ctypes.POINTER(f64), vp, i64, ctypes.POINTER(i64), vp]
+    L.tbk_node_features.restype = ctypes.c_int
+    L.tbk_node_features.argtypes = [i64, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(f64), vp, vp]
     L.tb_build_hamiltonian_sk.restype = ctypes.c_int
     L.tb_build_hamiltonian_sk.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32),
                                           ctypes.POINTER(SkParams), ctypes.POINTER(HamStruct),
@@ -367,7 +375,8 @@ def build_hamiltonian(pos, species, box, periodic, onsite, t_pair, r_cut=2.0, r0
 
 def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_pp_sigma, v_pp_pi, e_s, e_p,
                          r_cut=2.0, r0=1.42, beta=3.37, fmt="sell_f32", slice=256, reorder=True, stream=None,
-                         d=None, e_d=0.0, model=None, with_bond_y=False, pair_v=None, species_e=None):
+                         d=None, e_d=0.0, model=None, with_bond_y=False, pair_v=None, species_e=None,
+                         onsite_model=None):
     """Slater-Koster orbital Hamiltonian on the GPU: s, p (4 rows per atom), or
     s, p, d (9 rows per atom) when d = (v_sd_sigma, v_pd_sigma, v_pd_pi,
     v_dd_sigma, v_dd_pi, v_dd_delta) is given.
@@ -379,7 +388,11 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     pair_v [ns][ns][K], species_e [ns][3]: several species (species indices in
     `species`), integrals per ordered species pair (lower angular momentum on
     the first species), onsite energies per species; the single-species
-    integrals and onsite energies are then unused."""
+    integrals and onsite energies are then unused.
+
+    onsite_model = dict(params=[ns][n_shells][1633] float32 tensor, shift=[8], scale=[8],
+    r_desc=4.0): onsite energies e + y from one network per species and shell
+    (n_shells = 2 for s, p, 3 for s, p, d)."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
@@ -423,24 +436,40 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
     st.onsite, st.perm, st.col16 = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["col16"].data_ptr()
     bounds = (ctypes.c_double * 2)()
-    if model is None:
+    if model is None and onsite_model is None:
         _check(L.tb_build_hamiltonian_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk),
                                          ctypes.byref(st), bounds, s))
         return Hamiltonian(st, t, (bounds[0], bounds[1]))
     K = 4 if norb == 4 else 10
-    params = _dev(model["params"], torch.float32)
-    if tuple(params.shape) != (K, TBK_MLP_PARAMS):
-        raise ValueError(f"params has shape {tuple(params.shape)}, expected {(K, TBK_MLP_PARAMS)}")
-    sh, sc = _f64arr(model["shift"]), _f64arr(model["scale"])
-    mm = MlpModel(r_cut=float(model.get("r_desc", 4.0)), n_radial=8,
-                  shift=ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
-                  scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)), params=params.data_ptr())
+    mm = None
+    if model is not None:
+        params = _dev(model["params"], torch.float32)
+        if tuple(params.shape) != (K, TBK_MLP_PARAMS):
+            raise ValueError(f"params has shape {tuple(params.shape)}, expected {(K, TBK_MLP_PARAMS)}")
+        sh, sc = _f64arr(model["shift"]), _f64arr(model["scale"])
+        mm = MlpModel(r_cut=float(model.get("r_desc", 4.0)), n_radial=8,
+                      shift=ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
+                      scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)), params=params.data_ptr())
+    om = None
+    if onsite_model is not None:
+        ns = 1 if pair_v is None else sk.n_species
+        op = _dev(onsite_model["params"], torch.float32)
+        want = (ns, 2 if norb == 4 else 3, TBK_MLP_PARAMS)
+        if tuple(op.shape) != want:
+            raise ValueError(f"onsite params have shape {tuple(op.shape)}, expected {want}")
+        osh, osc = _f64arr(onsite_model["shift"]), _f64arr(onsite_model["scale"])
+        om = OnsiteModel(r_cut=float(onsite_model.get("r_desc", 4.0)),
+                         shift=ctypes.cast(osh, ctypes.POINTER(ctypes.c_double)),
+                         scale=ctypes.cast(osc, ctypes.POINTER(ctypes.c_double)), params=op.data_ptr())
+    if mm is None:
+        with_bond_y = False
     nbonds = st.n_bonds
     y = torch.empty((K, max(nbonds, 1)), dtype=torch.float32, device=dev) if with_bond_y else None
     nb_out = ctypes.c_int64(0)
     _check(L.tb_build_hamiltonian_sk_learned(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk),
-                                             ctypes.byref(mm), ctypes.byref(st), bounds, _ptr(y),
-                                             K * nbonds if y is not None else 0, ctypes.byref(nb_out), s))
+                                             None if mm is None else ctypes.byref(mm),
+                                             None if om is None else ctypes.byref(om), ctypes.byref(st), bounds,
+                                             _ptr(y), K * nbonds if y is not None else 0, ctypes.byref(nb_out), s))
     H = Hamiltonian(st, t, (bounds[0], bounds[1]))
     if with_bond_y:
         return H, y[:, : nb_out.value]
@@ -844,6 +873,15 @@ def vac_moments(H, vx, a, b, r, M, n_t, dt, n_cheb=0, precision=None, config=Non
                               float(dt), int(n_cheb), PRECISIONS[precision], _cfg_ref(config), _ptr(work),
                               work.numel(), _ptr(nu), _stream(stream)))
     return nu
+
+
+def node_features(v, shift, scale, stream=None):
+    """Onsite-network inputs (bf16 bits, int16 [n][16]) of node features v [n][8]."""
+    v = _dev(v, torch.float64)
+    X = torch.empty((v.shape[0], 16), dtype=torch.int16, device=v.device)
+    _check(lib().tbk_node_features(v.shape[0], _ptr(v), 8, _f64arr(shift), _f64arr(scale), _ptr(X),
+                                   _stream(stream)))
+    return X
 
 
 def integrated_dos(mu, a, b, E, kernel=0, stream=None):

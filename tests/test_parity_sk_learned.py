@@ -177,3 +177,77 @@ def test_trained_sk_networks_beat_the_plain_table():
     print(f"[learned sk] err_learned={err_l:.3e} err_plain={err_p:.3e}", flush=True)
     assert err_l <= 1e-2
     assert err_l < 0.5 * err_p
+
+
+def onsite_params(ns, nsh, seed):
+    """ns x nsh onsite networks sharing their hidden layers (same bf16 decisions)."""
+    base = synth.init_mlp_params(seed, out_scale=0.5)
+    rng = np.random.default_rng(seed + 1)
+    P = np.repeat(base[None, None, :], ns * nsh, axis=0).reshape(ns, nsh, -1).copy()
+    P[:, :, 1600:1632] = rng.uniform(-1.0, 1.0, (ns, nsh, 32)) / np.sqrt(32)
+    P[:, :, 1632] = rng.uniform(-0.2, 0.2, (ns, nsh))
+    return P.astype(np.float32)
+
+
+def test_node_features_match_oracle():
+    s = synth.graphene_sheet(7, 6, 0.08, 3)
+    pd = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+    vo = O.descriptor(s.n, pd, synth.R_DESC, 8)
+    mean, std = vo.mean(0), vo.std(0)
+    X = tbkpm.node_features(G.to_dev(vo), mean, std).cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    X = X.view(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(X, O.node_features(vo, mean, std))
+
+
+@pytest.mark.parametrize("norb,fmt,multi", [(4, "bsell4_f64", False), (9, "sell_f64", False),
+                                            (9, "bsell4_f32", True), (4, "sell_f64", True)])
+def test_onsite_network_matches_oracle(norb, fmt, multi):
+    s = (synth.hbn_stripes(8, 6, stripe_cells=2, sigma=0.07, seed=2) if multi
+         else synth.graphene_sheet(8, 6, 0.07, 2))
+    ns, nsh = (3 if multi else 1), (2 if norb == 4 else 3)
+    pv = se = None
+    if multi:
+        rng = np.random.default_rng(5)
+        K = 4 if norb == 4 else 10
+        pv = rng.uniform(-6.0, 6.0, (3, 3, K))
+        for l in (0, 2, 3, 7, 8, 9)[: 3 if K == 4 else 6]:
+            pv[:, :, l] = 0.5 * (pv[:, :, l] + pv[:, :, l].T)
+        se = rng.uniform(-8.0, 8.0, (3, 3))
+    pd = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+    vo = O.descriptor(s.n, pd, synth.R_DESC, 8)
+    mean, std = vo.mean(0), vo.std(0)
+    P = onsite_params(ns, nsh, 30)
+    X = O.node_features(vo, mean, std)
+    add = np.zeros((s.n, 3))
+    clear = None
+    for a in range(ns):
+        for l in range(nsh):
+            y, h1, h2 = O.mlp_forward(X, P[a, l].astype(np.float64), bf16_ops=True, keep=True)
+            sel = s.species == a
+            add[sel, l] = y[sel]
+            clear = G.bf16_decisions_clear(h1, h2)
+    vv = (synth.SK_V + synth.SK_D) if norb == 9 else synth.SK_V
+    csr, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, vv, synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP,
+                              r0=synth.R0, beta=synth.BETA, e_d=synth.SK_ED, onsite_add=add,
+                              species=s.species if multi else None, pair_v=pv, species_e=se)
+    H = tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                   synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                   fmt=fmt, slice=16, d=synth.SK_D if norb == 9 else None, e_d=synth.SK_ED,
+                                   pair_v=pv, species_e=se,
+                                   onsite_model=dict(params=G.to_dev(P), shift=mean, scale=std,
+                                                     r_desc=synth.R_DESC))
+    assert H.st.has_onsite == 1
+    rows, cols, vals, onsite = G.block_entries(H) if fmt.startswith("bsell4") else G.entries_in_atom_order(H)
+    orow, ocol, oval = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    np.testing.assert_array_equal(cols[o1], ocol[o2])
+    tol = 1e-6 if fmt.endswith("f32") else 2e-15
+    np.testing.assert_allclose(vals[o1], oval[o2], rtol=tol, atol=tol * np.abs(oval).max())
+    atom_clear = np.repeat(clear, norb)
+    assert atom_clear.mean() >= 0.3
+    d = np.abs(onsite - csr.diag)
+    scale_e = np.abs(csr.diag).max()
+    assert d[atom_clear].max() <= 2e-5 * np.abs(add).max() + (1e-6 * scale_e if fmt.endswith("f32") else 0.0)
+    assert d.max() <= 1e-2 * np.abs(add).max() + 1e-6 * scale_e
+    lo, hi = O.gershgorin(csr)
+    assert H.bounds[0] == pytest.approx(lo, rel=1e-3) and H.bounds[1] == pytest.approx(hi, rel=1e-3)
