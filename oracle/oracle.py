@@ -50,7 +50,8 @@ def _lib():
     L.orc_radial.restype = None
     L.orc_radial.argtypes = [_f64, _f64, _i32, _f64p]
     L.orc_descriptor.restype = None
-    L.orc_descriptor.argtypes = [_i64, _i64, _i32p, _i32p, _f64p, _f64, _i32, _f64p]
+    L.orc_descriptor.argtypes = [_i64, _i64, _i32p, _i32p, _f64p, _f64, _i32, ctypes.c_void_p, _i32,
+                                 ctypes.c_void_p, _f64p]
     L.orc_bf16.restype = _f64
     L.orc_bf16.argtypes = [_f64]
     L.orc_mlp_forward.restype = None
@@ -58,7 +59,8 @@ def _lib():
     L.orc_mlp_loss_grad.restype = _f64
     L.orc_mlp_loss_grad.argtypes = [_i64, _f64p, _f64p, ctypes.c_void_p, _f64p, _i32, _f64p]
     L.orc_bond_features.restype = None
-    L.orc_bond_features.argtypes = [_i64, _i32p, _i32p, _f64p, _f64p, _f64, _i32, _f64p, _f64p, _f64p]
+    L.orc_bond_features.argtypes = [_i64, _i32p, _i32p, _f64p, _f64p, _f64, _i32, ctypes.c_void_p, _i32,
+                                    ctypes.c_void_p, _f64p, _f64p, _f64p]
     L.orc_target_scale.restype = None
     L.orc_target_scale.argtypes = [_i64, _i32p, _i32p, _f64p, _i32, _f64, _f64, _f64p]
     L.orc_adamw_step.restype = None
@@ -211,10 +213,23 @@ def radial(r, rc, nk=8):
     return f
 
 
-def descriptor(n, pairs, rc, nk=8):
+def _species_cnk(species, cnk, nk):
+    if cnk is None:
+        return None, 0, None
+    c = np.ascontiguousarray(np.asarray(cnk, np.float64))
+    ns = c.shape[0]
+    assert c.shape == (ns, ns, nk, nk)
+    return np.ascontiguousarray(np.asarray(species, np.int32)), ns, c
+
+
+def descriptor(n, pairs, rc, nk=8, species=None, cnk=None):
+    """Node features v [n][nk] = sum_j C(r_ij); cnk [ns][ns][nk][nk] per species pair
+    (None: identity)."""
     pi, pj, d = pairs
     v = np.empty((n, nk))
-    _lib().orc_descriptor(n, pi.shape[0], pi, pj, d, float(rc), nk, v.reshape(-1))
+    sp, ns, c = _species_cnk(species, cnk, nk)
+    _lib().orc_descriptor(n, pi.shape[0], pi, pj, d, float(rc), nk, None if sp is None else sp.ctypes.data, ns,
+                          None if c is None else c.ctypes.data, v.reshape(-1))
     return v
 
 
@@ -227,14 +242,17 @@ def bf16(x):
 N_PARAMS = 1633
 
 
-def bond_features(pairs, v, rc, shift=None, scale=None):
-    """[npairs][2 nk] MLP inputs [f(r_ij) || v_i + v_j], standardised by (shift, scale)."""
+def bond_features(pairs, v, rc, shift=None, scale=None, species=None, cnk=None):
+    """[npairs][2 nk] MLP inputs [C(r_ij) || v_i + v_j], standardised by (shift, scale);
+    C = f without cnk."""
     pi, pj, d = pairs
     nk = v.shape[1]
     shift = np.zeros(2 * nk) if shift is None else _c(shift, np.float64)
     scale = np.ones(2 * nk) if scale is None else _c(scale, np.float64)
     X = np.empty((pi.shape[0], 2 * nk))
+    sp, ns, c = _species_cnk(species, cnk, nk)
     _lib().orc_bond_features(pi.shape[0], pi, pj, d, _c(v, np.float64).reshape(-1), float(rc), nk,
+                             None if sp is None else sp.ctypes.data, ns, None if c is None else c.ctypes.data,
                              shift, scale, X.reshape(-1))
     return X
 

@@ -419,16 +419,41 @@ void orc_radial(double r, double rc, int32_t nk, double *f)
     }
 }
 
-/* Node feature v_i = sum_{j in N(i)} f(r_ij) (Eq. (2) with the identity c_nk),
- * from the pair list of a descriptor cutoff: v [n][nk]. */
-void orc_descriptor(int64_t n, int64_t npairs, const int32_t *pi, const int32_t *pj,
-                    const double *dist, double rc, int32_t nk, double *v)
+/* Bond descriptor of Eq. (2): C_n(r) = sum_k c_nk f_k(r) with the coefficients
+ * c [nk][nk] of the bond's species pair, or C_n = f_n (c = NULL: identity). */
+static void orc_bond_basis(double r, double rc, int32_t nk, const double *c, double *C)
 {
     double f[64];
+    orc_radial(r, rc, nk, f);
+    for (int32_t a = 0; a < nk; ++a) {
+        if (!c) { C[a] = f[a]; continue; }
+        double s = 0.0;
+        for (int32_t k = 0; k < nk; ++k) s += c[a * nk + k] * f[k];
+        C[a] = s;
+    }
+}
+
+/* Coefficients of the species pair of atoms i and j: cnk [ns][ns][nk][nk]
+ * (NULL: identity for every pair). */
+static const double *orc_pair_cnk(const double *cnk, const int32_t *species, int32_t ns, int32_t nk,
+                                  int32_t i, int32_t j)
+{
+    if (!cnk) return NULL;
+    return cnk + ((int64_t)species[i] * ns + species[j]) * nk * nk;
+}
+
+/* Node feature v_i = sum_{j in N(i)} C(r_ij) (Eq. (2)), from the pair list of a
+ * descriptor cutoff: v [n][nk].  cnk [ns][ns][nk][nk] (symmetric in the species
+ * pair) and species [n], or cnk = NULL for the identity c_nk. */
+void orc_descriptor(int64_t n, int64_t npairs, const int32_t *pi, const int32_t *pj,
+                    const double *dist, double rc, int32_t nk, const int32_t *species, int32_t ns,
+                    const double *cnk, double *v)
+{
+    double C[64];
     for (int64_t i = 0; i < n * nk; ++i) v[i] = 0.0;
     for (int64_t p = 0; p < npairs; ++p) {
-        orc_radial(dist[p], rc, nk, f);
-        for (int32_t k = 0; k < nk; ++k) { v[(int64_t)pi[p] * nk + k] += f[k]; v[(int64_t)pj[p] * nk + k] += f[k]; }
+        orc_bond_basis(dist[p], rc, nk, orc_pair_cnk(cnk, species, ns, nk, pi[p], pj[p]), C);
+        for (int32_t k = 0; k < nk; ++k) { v[(int64_t)pi[p] * nk + k] += C[k]; v[(int64_t)pj[p] * nk + k] += C[k]; }
     }
 }
 
@@ -555,18 +580,21 @@ void orc_adamw_step(int64_t n, double *p, const double *g, double *m, double *v,
 
 /*
  * Per-bond MLP input of the learned model: for pair p = {i, j},
- *   x_p = [f_0..f_{nk-1}(r_ij) || v_i + v_j]      (2 nk values, symmetric in i, j)
+ *   x_p = [C_0..C_{nk-1}(r_ij) || v_i + v_j]      (2 nk values, symmetric in i, j)
+ * with C the bond descriptor of the pair's species (orc_bond_basis; f itself
+ * when cnk = NULL)
  * followed by the fixed standardisation x <- (x - shift) / scale per feature.
  * X is [npairs][2 nk].
  */
 void orc_bond_features(int64_t npairs, const int32_t *pi, const int32_t *pj,
                        const double *dist, const double *v, double rc, int32_t nk,
+                       const int32_t *species, int32_t ns, const double *cnk,
                        const double *shift, const double *scale, double *X)
 {
     double f[64];
     for (int64_t p = 0; p < npairs; ++p) {
         double *x = X + p * 2 * nk;
-        orc_radial(dist[p], rc, nk, f);
+        orc_bond_basis(dist[p], rc, nk, orc_pair_cnk(cnk, species, ns, nk, pi[p], pj[p]), f);
         for (int32_t k = 0; k < nk; ++k) x[k] = f[k];
         for (int32_t k = 0; k < nk; ++k) x[nk + k] = v[(int64_t)pi[p] * nk + k] + v[(int64_t)pj[p] * nk + k];
         for (int32_t k = 0; k < 2 * nk; ++k) x[k] = (x[k] - shift[k]) / scale[k];

@@ -142,3 +142,41 @@ def test_adamw_matches_torch():
         tp.grad = torch.tensor(grads[t], dtype=torch.float64)
         opt.step()
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Species-dependent descriptor coefficients c_nk of Eq. (2)
+# ---------------------------------------------------------------------------
+
+def _stripes():
+    s = synth.hbn_stripes(6, 4, stripe_cells=2, sigma=0.1, seed=3)
+    return s, O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+
+
+def test_identity_coefficients_reproduce_the_plain_descriptor():
+    s, pd = _stripes()
+    eye = np.broadcast_to(np.eye(8), (3, 3, 8, 8))
+    np.testing.assert_array_equal(O.descriptor(s.n, pd, synth.R_DESC, 8, s.species, eye),
+                                  O.descriptor(s.n, pd, synth.R_DESC, 8))
+    np.testing.assert_array_equal(O.bond_features(pd, np.ones((s.n, 8)), synth.R_DESC, species=s.species, cnk=eye),
+                                  O.bond_features(pd, np.ones((s.n, 8)), synth.R_DESC))
+
+
+def test_coefficients_against_brute_force():
+    """Pair by pair: C(r) = c[s_i][s_j] f(r), summed onto both atoms; bond features
+    carry C of the bond's own species pair."""
+    s, pd = _stripes()
+    rng = np.random.default_rng(2)
+    c = rng.normal(size=(3, 3, 8, 8))
+    c = 0.5 * (c + c.transpose(1, 0, 2, 3))              # symmetric in the species pair
+    v = np.zeros((s.n, 8))
+    C = []
+    for i, j, r in zip(*pd):
+        g = c[s.species[i], s.species[j]] @ O.radial(r, synth.R_DESC)
+        v[i] += g
+        v[j] += g
+        C.append(g)
+    np.testing.assert_allclose(O.descriptor(s.n, pd, synth.R_DESC, 8, s.species, c), v, rtol=1e-13, atol=1e-13)
+    X = O.bond_features(pd, v, synth.R_DESC, species=s.species, cnk=c)
+    np.testing.assert_allclose(X[:, :8], np.array(C), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(X[:, 8:], v[pd[0]] + v[pd[1]], rtol=1e-14)
