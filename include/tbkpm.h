@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 9
+#define TBK_ABI_VERSION 10
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -370,6 +370,13 @@ typedef struct {
     const double *shift;   /* host [16] feature shifts                    */
     const double *scale;   /* host [16] feature scales (non-zero)         */
     const float *params;   /* device [1633] MLP parameters                */
+    int32_t n_species;     /* with c_nk: species count                    */
+    const double *c_nk;    /* host [n_species][n_species][8][8] descriptor
+                              coefficients per species pair (symmetric in
+                              the pair), or NULL for the identity: the bond
+                              descriptor C_n(r) = sum_k c_nk f_k(r) replaces
+                              f in the node and the bond features (Eq. (2));
+                              taken by tb_build_hamiltonian_sk_learned only */
 } tbk_mlp_model;
 
 #define TBK_MLP_PARAMS 1633
@@ -388,11 +395,31 @@ tbk_status tbk_bonds(const double *pos, int32_t n_seg, const int64_t *seg_atoms,
                      const double *boxes, const int32_t periodic[3], double r_cut, int64_t cap,
                      int32_t *bi, int32_t *bj, double *br, int64_t *n_bonds, void *stream);
 
+/* tbk_descriptor with descriptor coefficients per species pair (Eq. (2)):
+ * v_i = sum_j C(r_ij), C_n(r) = sum_k c_nk[s_i][s_j][n][k] f_k(r).
+ * species device int32 [n] in [0, n_species); c_nk host double
+ * [n_species][n_species][n_radial][n_radial], symmetric in the species pair.
+ * Errors: as tbk_descriptor; INVALID_ARG (species, asymmetric c_nk),
+ * NOT_FINITE.  Synchronises `stream`. */
+tbk_status tbk_descriptor_species(const double *pos, const int32_t *species, int32_t n_seg,
+                                  const int64_t *seg_atoms, const double *boxes,
+                                  const int32_t periodic[3], double r_cut, int32_t n_radial,
+                                  int32_t n_species, const double *c_nk, double *v, void *stream);
+
 /* Standardised MLP inputs X [nb][16] as bfloat16 bits (device uint16), one
  * rounding from double.  shift, scale: host [16]. */
 tbk_status tbk_bond_features(int64_t nb, const int32_t *bi, const int32_t *bj, const double *br,
                              const double *v, int32_t n_radial, double r_cut, const double *shift,
                              const double *scale, uint16_t *X, void *stream);
+
+/* tbk_bond_features with the bond descriptor C(r_ij) of the bond's species
+ * pair in place of f(r_ij) (same c_nk as tbk_descriptor_species).
+ * Synchronises `stream`. */
+tbk_status tbk_bond_features_species(int64_t nb, const int32_t *bi, const int32_t *bj,
+                                     const double *br, const int32_t *species, const double *v,
+                                     int32_t n_radial, double r_cut, int32_t n_species,
+                                     const double *c_nk, const double *shift, const double *scale,
+                                     uint16_t *X, void *stream);
 
 /* Onsite-network inputs of Eq. (2) (the node feature v_i of each atom):
  * X[i] = bfloat16 bits of [(v_i - shift) / scale || 0 x 8] (16 values, the
@@ -565,6 +592,8 @@ typedef struct {
     const double *shift;   /* host [8] node-feature shifts       */
     const double *scale;   /* host [8] node-feature scales       */
     const float *params;   /* device, see above                  */
+    int32_t n_species;     /* with c_nk, as in tbk_mlp_model     */
+    const double *c_nk;    /* host, as in tbk_mlp_model, or NULL */
 } tbk_onsite_model;
 
 /*

@@ -92,15 +92,35 @@ __device__ __forceinline__ void radial(double r, double rc, int nk, double *f) {
 // Descriptor, bonds, features, synthetic targets
 // ------------------------------------------------------------------------
 
+// Bond descriptor of Eq. (2): C_n(r) = sum_k c[n][k] f_k(r) with the
+// coefficients c [nk][nk] of the bond's species pair, or f itself (c = NULL).
+__device__ __forceinline__ void bond_basis(double r, double rc, int nk, const double *__restrict__ c, double *C) {
+    double f[16];
+    radial(r, rc, nk, f);
+    for (int a = 0; a < nk; ++a) {
+        if (!c) { C[a] = f[a]; continue; }
+        double s = 0.0;
+        for (int k = 0; k < nk; ++k) s += c[a * nk + k] * f[k];
+        C[a] = s;
+    }
+}
+
+// Coefficients of the species pair (s_i, s_j): cnk [ns][ns][nk][nk], or NULL.
+__device__ __forceinline__ const double *pair_cnk(const double *__restrict__ cnk, const int32_t *__restrict__ species,
+                                                  int32_t ns, int nk, int32_t i, int32_t j) {
+    return cnk ? cnk + ((int64_t)species[i] * ns + species[j]) * nk * nk : nullptr;
+}
+
 __global__ void k_descriptor(CellList cl, const double *__restrict__ pos, int64_t n, double rc, int32_t nk,
+                             const int32_t *__restrict__ species, int32_t ns, const double *__restrict__ cnk,
                              double *__restrict__ v) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc[16];
     for (int k = 0; k < nk; ++k) acc[k] = 0.0;
-    for_each_neighbor(cl, pos, (int32_t)i, rc, [&](int32_t, double r, double, double, double) {
+    for_each_neighbor(cl, pos, (int32_t)i, rc, [&](int32_t j, double r, double, double, double) {
         double f[16];
-        radial(r, rc, nk, f);
+        bond_basis(r, rc, nk, pair_cnk(cnk, species, ns, nk, (int32_t)i, j), f);
         for (int k = 0; k < nk; ++k) acc[k] += f[k];
     });
     for (int k = 0; k < nk; ++k) v[i * nk + k] = acc[k];
@@ -143,19 +163,22 @@ struct FeatNorm {
 
 // Standardised bond feature k of bond (i, j, r) in double.
 __device__ __forceinline__ void bond_features(double r, const double *__restrict__ vi, const double *__restrict__ vj,
-                                              double rc, const FeatNorm &fn, double *x) {
-    radial(r, rc, kNR, x);
+                                              double rc, const FeatNorm &fn, double *x,
+                                              const double *__restrict__ c = nullptr) {
+    bond_basis(r, rc, kNR, c, x);
     for (int k = 0; k < kNR; ++k) x[kNR + k] = vi[k] + vj[k];
     for (int k = 0; k < kNI; ++k) x[k] = (x[k] - fn.shift[k]) * fn.inv_scale[k];
 }
 
 __global__ void k_bond_features(int64_t nb, const int32_t *__restrict__ bi, const int32_t *__restrict__ bj,
                                 const double *__restrict__ br, const double *__restrict__ v, double rc, FeatNorm fn,
+                                const int32_t *__restrict__ species, int32_t ns, const double *__restrict__ cnk,
                                 uint16_t *__restrict__ X) {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb) return;
     double x[kNI];
-    bond_features(br[b], v + (int64_t)bi[b] * kNR, v + (int64_t)bj[b] * kNR, rc, fn, x);
+    bond_features(br[b], v + (int64_t)bi[b] * kNR, v + (int64_t)bj[b] * kNR, rc, fn, x,
+                  pair_cnk(cnk, species, ns, kNR, bi[b], bj[b]));
     for (int k = 0; k < kNI; ++k) X[b * kNI + k] = d2bf(x[k]);
 }
 
@@ -524,6 +547,8 @@ int mlp_grid(int64_t nb) {
 
 tbk_status check_model(const tbk_mlp_model *mdl) {
     TBK_CHECK(mdl != nullptr && mdl->params && mdl->shift && mdl->scale, TBK_ERR_INVALID_ARG, "model is NULL");
+    TBK_CHECK(mdl->c_nk == nullptr, TBK_ERR_UNSUPPORTED,
+              "descriptor coefficients per species pair are taken by the Slater-Koster builder only");
     TBK_CHECK(mdl->n_radial == kNR, TBK_ERR_UNSUPPORTED, "the bond MLP takes %d radial functions", kNR);
     TBK_CHECK(std::isfinite(mdl->r_cut) && mdl->r_cut > 0, TBK_ERR_INVALID_ARG, "descriptor cutoff must be positive");
     for (int k = 0; k < kNI; ++k) {
@@ -545,14 +570,17 @@ FeatNorm make_norm(const double *shift, const double *scale) {
 // Descriptor of every atom: cell list at the descriptor cutoff, then sums.
 static tbk_status descriptor_impl(const double *pos, int64_t n, int32_t nseg, const int64_t *seg_atoms,
                                   const double *boxes, const int32_t periodic[3], double rc, int32_t nk, double *v,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int32_t *species = nullptr, int32_t ns = 1,
+                                  const double *cnk_dev = nullptr) {
     TBK_CHECK(nk >= 1 && nk <= 16, TBK_ERR_INVALID_ARG, "n_radial = %d outside [1, 16]", nk);
     TBK_CHECK(std::isfinite(rc) && rc > 0, TBK_ERR_INVALID_ARG, "descriptor cutoff must be positive");
     TBK_CHECK(v != nullptr, TBK_ERR_INVALID_ARG, "v is NULL");
     CellListOwner cells;
-    tbk_status st = cells.build(pos, nullptr, 1, n, nseg, seg_atoms, boxes, periodic, rc, s);
+    // with coefficients per species pair the cell list also validates the species indices
+    tbk_status st = cells.build(pos, cnk_dev ? species : nullptr, cnk_dev ? ns : 1, n, nseg, seg_atoms, boxes,
+                                periodic, rc, s);
     if (st != TBK_OK) return st;
-    k_descriptor<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(cells.view, pos, n, rc, nk, v);
+    k_descriptor<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(cells.view, pos, n, rc, nk, species, ns, cnk_dev, v);
     TBK_HIP(hipGetLastError());
     return TBK_OK;
 }
@@ -648,8 +676,78 @@ extern "C" tbk_status tbk_bond_features(int64_t nb, const int32_t *bi, const int
     if (nb == 0) return TBK_OK;
     TBK_CHECK(bi && bj && br && v && X, TBK_ERR_INVALID_ARG, "NULL array");
     hipStream_t s = as_stream(stream);
-    k_bond_features<<<(unsigned)ceil_div(nb, 256), 256, 0, s>>>(nb, bi, bj, br, v, r_cut, make_norm(shift, scale), X);
+    k_bond_features<<<(unsigned)ceil_div(nb, 256), 256, 0, s>>>(nb, bi, bj, br, v, r_cut, make_norm(shift, scale),
+                                                                 nullptr, 1, nullptr, X);
     TBK_HIP(hipGetLastError());
+    return TBK_OK;
+}
+
+namespace tbk {
+namespace {
+
+// Coefficients per species pair: host [ns][ns][nk][nk], finite, symmetric in the pair.
+tbk_status check_cnk(int32_t ns, int32_t nk, const double *cnk) {
+    TBK_CHECK(ns >= 1 && ns <= 16, TBK_ERR_INVALID_ARG, "n_species = %d outside [1, 16]", ns);
+    TBK_CHECK(cnk != nullptr, TBK_ERR_INVALID_ARG, "c_nk is NULL");
+    const int64_t blk = (int64_t)nk * nk;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int64_t q = 0; q < blk; ++q) {
+                const double x = cnk[(a * ns + b) * blk + q];
+                TBK_CHECK(std::isfinite(x), TBK_ERR_NOT_FINITE, "c_nk[%d][%d] is not finite", a, b);
+                TBK_CHECK(x == cnk[(b * ns + a) * blk + q], TBK_ERR_INVALID_ARG,
+                          "c_nk[%d][%d] differs from c_nk[%d][%d] (must be symmetric in the pair)", a, b, b, a);
+            }
+    return TBK_OK;
+}
+
+}  // namespace
+}  // namespace tbk
+
+extern "C" tbk_status tbk_descriptor_species(const double *pos, const int32_t *species, int32_t n_seg,
+                                             const int64_t *seg_atoms, const double *boxes,
+                                             const int32_t periodic[3], double r_cut, int32_t n_radial,
+                                             int32_t n_species, const double *c_nk, double *v, void *stream) {
+    clear_error();
+    TBK_CHECK(seg_atoms && n_seg >= 1 && species, TBK_ERR_INVALID_ARG, "bad segment table or species");
+    TBK_CHECK(n_radial >= 1 && n_radial <= 16, TBK_ERR_INVALID_ARG, "n_radial = %d outside [1, 16]", n_radial);
+    tbk_status st = check_cnk(n_species, n_radial, c_nk);
+    if (st != TBK_OK) return st;
+    hipStream_t s = as_stream(stream);
+    const size_t bytes = sizeof(double) * n_species * n_species * n_radial * n_radial;
+    DevBuf c;
+    TBK_HIP(c.alloc(bytes, s));
+    TBK_HIP(hipMemcpyAsync(c.as<double>(), c_nk, bytes, hipMemcpyHostToDevice, s));
+    st = descriptor_impl(pos, seg_atoms[n_seg], n_seg, seg_atoms, boxes, periodic, r_cut, n_radial, v, s, species,
+                         n_species, c.as<double>());
+    if (st != TBK_OK) return st;
+    TBK_HIP(hipStreamSynchronize(s));      // the caller's c_nk must outlive the transfer
+    return TBK_OK;
+}
+
+extern "C" tbk_status tbk_bond_features_species(int64_t nb, const int32_t *bi, const int32_t *bj, const double *br,
+                                                const int32_t *species, const double *v, int32_t n_radial,
+                                                double r_cut, int32_t n_species, const double *c_nk,
+                                                const double *shift, const double *scale, uint16_t *X,
+                                                void *stream) {
+    clear_error();
+    TBK_CHECK(n_radial == kNR, TBK_ERR_UNSUPPORTED, "features need %d radial functions", kNR);
+    TBK_CHECK(nb >= 0 && shift && scale && species, TBK_ERR_INVALID_ARG, "bad arguments");
+    for (int k = 0; k < kNI; ++k) TBK_CHECK(scale[k] != 0.0 && std::isfinite(scale[k]) && std::isfinite(shift[k]),
+                                             TBK_ERR_INVALID_ARG, "bad feature normalisation %d", k);
+    tbk_status st = check_cnk(n_species, kNR, c_nk);
+    if (st != TBK_OK) return st;
+    if (nb == 0) return TBK_OK;
+    TBK_CHECK(bi && bj && br && v && X, TBK_ERR_INVALID_ARG, "NULL array");
+    hipStream_t s = as_stream(stream);
+    const size_t bytes = sizeof(double) * n_species * n_species * kNR * kNR;
+    DevBuf c;
+    TBK_HIP(c.alloc(bytes, s));
+    TBK_HIP(hipMemcpyAsync(c.as<double>(), c_nk, bytes, hipMemcpyHostToDevice, s));
+    k_bond_features<<<(unsigned)ceil_div(nb, 256), 256, 0, s>>>(nb, bi, bj, br, v, r_cut, make_norm(shift, scale),
+                                                                 species, n_species, c.as<double>(), X);
+    TBK_HIP(hipGetLastError());
+    TBK_HIP(hipStreamSynchronize(s));      // the caller's c_nk must outlive the transfer
     return TBK_OK;
 }
 

@@ -558,7 +558,9 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
         TBK_HIP(von.alloc(sizeof(double) * n * 8, s));
         TBK_HIP(Xn.alloc(sizeof(uint16_t) * 16 * n, s));
         TBK_HIP(yon.alloc(sizeof(float) * ns * nsh * n, s));
-        st = tbk_descriptor(pos, 1, seg, box, periodic, onsite->r_cut, 8, von.as<double>(), s);
+        st = onsite->c_nk ? tbk_descriptor_species(pos, species, 1, seg, box, periodic, onsite->r_cut, 8,
+                                                   onsite->n_species, onsite->c_nk, von.as<double>(), s)
+                          : tbk_descriptor(pos, 1, seg, box, periodic, onsite->r_cut, 8, von.as<double>(), s);
         if (st != TBK_OK) return st;
         st = tbk_node_features(n, von.as<double>(), 8, onsite->shift, onsite->scale, Xn.as<uint16_t>(), s);
         if (st != TBK_OK) return st;
@@ -583,7 +585,10 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
         TBK_CHECK(bond_y == nullptr || bond_cap >= K * nb, TBK_ERR_BUFFER_TOO_SMALL,
                   "bond_y holds %lld, needs %lld", (long long)bond_cap, (long long)(K * nb));
         TBK_HIP(vdesc.alloc(sizeof(double) * n * model->n_radial, s));
-        st = tbk_descriptor(pos, 1, seg, box, periodic, model->r_cut, model->n_radial, vdesc.as<double>(), s);
+        st = model->c_nk ? tbk_descriptor_species(pos, species, 1, seg, box, periodic, model->r_cut, model->n_radial,
+                                                  model->n_species, model->c_nk, vdesc.as<double>(), s)
+                         : tbk_descriptor(pos, 1, seg, box, periodic, model->r_cut, model->n_radial,
+                                          vdesc.as<double>(), s);
         if (st != TBK_OK) return st;
         const int64_t cap = std::max<int64_t>(nb, 1);
         TBK_HIP(bi.alloc(sizeof(int32_t) * cap, s));
@@ -598,8 +603,13 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
         if (st != TBK_OK) return st;
         TBK_CHECK(nb2 == nb, TBK_ERR_DEVICE, "bond count mismatch (%lld vs %lld)", (long long)nb2, (long long)nb);
         if (nb > 0) {
-            st = tbk_bond_features(nb, bi.as<int32_t>(), bj.as<int32_t>(), br.as<double>(), vdesc.as<double>(),
-                                   model->n_radial, model->r_cut, model->shift, model->scale, X.as<uint16_t>(), s);
+            st = model->c_nk
+                     ? tbk_bond_features_species(nb, bi.as<int32_t>(), bj.as<int32_t>(), br.as<double>(), species,
+                                                 vdesc.as<double>(), model->n_radial, model->r_cut, model->n_species,
+                                                 model->c_nk, model->shift, model->scale, X.as<uint16_t>(), s)
+                     : tbk_bond_features(nb, bi.as<int32_t>(), bj.as<int32_t>(), br.as<double>(), vdesc.as<double>(),
+                                         model->n_radial, model->r_cut, model->shift, model->scale,
+                                         X.as<uint16_t>(), s);
             if (st != TBK_OK) return st;
             for (int32_t l = 0; l < K; ++l) {
                 st = tbk_mlp_forward(nb, X.as<uint16_t>(), model->params + (int64_t)l * TBK_MLP_PARAMS,

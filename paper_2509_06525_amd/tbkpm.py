@@ -62,7 +62,7 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_mlp_loss_grad", "tbk_adamw_step", "tbk_mlp_train", "tb_build_hamiltonian_learned",
                "tb_build_velocity", "lsqt_chebyshev_terms", "lsqt_workspace_size", "lsqt_vac_moments",
                "lsqt_sigma", "kpm_integrated_dos", "lsqt_mobility", "tb_build_hamiltonian_sk_learned",
-               "tbk_node_features")
+               "tbk_node_features", "tbk_descriptor_species", "tbk_bond_features_species")
 
 
 class SkParams(ctypes.Structure):
@@ -80,12 +80,27 @@ class SkParams(ctypes.Structure):
 class MlpModel(ctypes.Structure):
     _fields_ = [("r_cut", ctypes.c_double), ("n_radial", ctypes.c_int32),
                 ("shift", ctypes.POINTER(ctypes.c_double)), ("scale", ctypes.POINTER(ctypes.c_double)),
-                ("params", ctypes.c_void_p)]
+                ("params", ctypes.c_void_p), ("n_species", ctypes.c_int32),
+                ("c_nk", ctypes.POINTER(ctypes.c_double))]
 
 
 class OnsiteModel(ctypes.Structure):
     _fields_ = [("r_cut", ctypes.c_double), ("shift", ctypes.POINTER(ctypes.c_double)),
-                ("scale", ctypes.POINTER(ctypes.c_double)), ("params", ctypes.c_void_p)]
+                ("scale", ctypes.POINTER(ctypes.c_double)), ("params", ctypes.c_void_p),
+                ("n_species", ctypes.c_int32), ("c_nk", ctypes.POINTER(ctypes.c_double))]
+
+
+def _cnk_arg(cnk):
+    """(n_species, host array, pointer) of descriptor coefficients [ns][ns][8][8], or (0, None, NULL)."""
+    if cnk is None:
+        return 0, None, None
+    import numpy as np
+    c = np.ascontiguousarray(np.asarray(cnk, np.float64))
+    ns = c.shape[0]
+    if c.shape != (ns, ns, 8, 8):
+        raise ValueError(f"c_nk has shape {c.shape}, expected ({ns}, {ns}, 8, 8)")
+    arr = _f64arr(c.reshape(-1))
+    return ns, arr, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
 
 
 class KpmConfig(ctypes.Structure):
@@ -186,6 +201,12 @@ def lib():
     L.tbk_bond_features.restype = ctypes.c_int
     L.tbk_bond_features.argtypes = [i64, vp, vp, vp, vp, i32, f64, ctypes.POINTER(f64), ctypes.POINTER(f64),
                                     u16p, vp]
+    L.tbk_descriptor_species.restype = ctypes.c_int
+    L.tbk_descriptor_species.argtypes = [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(i32),
+                                         f64, i32, i32, ctypes.POINTER(f64), vp, vp]
+    L.tbk_bond_features_species.restype = ctypes.c_int
+    L.tbk_bond_features_species.argtypes = [i64, vp, vp, vp, vp, vp, i32, f64, i32, ctypes.POINTER(f64),
+                                            ctypes.POINTER(f64), ctypes.POINTER(f64), u16p, vp]
     L.tbk_feature_moments.restype = ctypes.c_int
     L.tbk_feature_moments.argtypes = [i64, vp, vp, vp, vp, i32, f64, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
     L.tbk_coordination_target.restype = ctypes.c_int
@@ -447,9 +468,11 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
         if tuple(params.shape) != (K, TBK_MLP_PARAMS):
             raise ValueError(f"params has shape {tuple(params.shape)}, expected {(K, TBK_MLP_PARAMS)}")
         sh, sc = _f64arr(model["shift"]), _f64arr(model["scale"])
+        mns, marr, mcp = _cnk_arg(model.get("cnk"))
         mm = MlpModel(r_cut=float(model.get("r_desc", 4.0)), n_radial=8,
                       shift=ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
-                      scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)), params=params.data_ptr())
+                      scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)), params=params.data_ptr(),
+                      n_species=mns, c_nk=mcp)
     om = None
     if onsite_model is not None:
         ns = 1 if pair_v is None else sk.n_species
@@ -458,9 +481,11 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
         if tuple(op.shape) != want:
             raise ValueError(f"onsite params have shape {tuple(op.shape)}, expected {want}")
         osh, osc = _f64arr(onsite_model["shift"]), _f64arr(onsite_model["scale"])
+        ons, oarr, ocp = _cnk_arg(onsite_model.get("cnk"))
         om = OnsiteModel(r_cut=float(onsite_model.get("r_desc", 4.0)),
                          shift=ctypes.cast(osh, ctypes.POINTER(ctypes.c_double)),
-                         scale=ctypes.cast(osc, ctypes.POINTER(ctypes.c_double)), params=op.data_ptr())
+                         scale=ctypes.cast(osc, ctypes.POINTER(ctypes.c_double)), params=op.data_ptr(),
+                         n_species=ons, c_nk=ocp)
     if mm is None:
         with_bond_y = False
     nbonds = st.n_bonds
@@ -677,14 +702,20 @@ def _segs(seg_atoms, boxes):
     return n_seg, seg, bx
 
 
-def descriptor(pos, seg_atoms, boxes, periodic, r_cut=4.0, n_radial=8, stream=None):
-    """Node features v [N][n_radial] (float64, device)."""
+def descriptor(pos, seg_atoms, boxes, periodic, r_cut=4.0, n_radial=8, stream=None, species=None, cnk=None):
+    """Node features v [N][n_radial] (float64, device); with species (int32 device) and
+    cnk [ns][ns][8][8] the descriptor coefficients per species pair of Eq. (2)."""
     pos = _dev(pos, torch.float64)
     n_seg, seg, bx = _segs(seg_atoms, boxes)
     per = (ctypes.c_int32 * 3)(*[int(v) for v in periodic])
     v = torch.empty((pos.shape[0], n_radial), dtype=torch.float64, device=pos.device)
-    _check(lib().tbk_descriptor(_ptr(pos), n_seg, seg, bx, per, float(r_cut), int(n_radial), _ptr(v),
-                                _stream(stream)))
+    if cnk is None:
+        _check(lib().tbk_descriptor(_ptr(pos), n_seg, seg, bx, per, float(r_cut), int(n_radial), _ptr(v),
+                                    _stream(stream)))
+        return v
+    ns, arr, cp = _cnk_arg(cnk)
+    _check(lib().tbk_descriptor_species(_ptr(pos), _ptr(_dev(species, torch.int32)), n_seg, seg, bx, per,
+                                        float(r_cut), int(n_radial), ns, cp, _ptr(v), _stream(stream)))
     return v
 
 
@@ -719,13 +750,20 @@ def feature_moments(bonds_, v, r_cut=4.0, stream=None):
     return list(mean), list(std)
 
 
-def bond_features(bonds_, v, shift, scale, r_cut=4.0, stream=None):
-    """Standardised MLP inputs as bfloat16 bits: int16 tensor [nb][16]."""
+def bond_features(bonds_, v, shift, scale, r_cut=4.0, stream=None, species=None, cnk=None):
+    """Standardised MLP inputs as bfloat16 bits: int16 tensor [nb][16] (with species and
+    cnk the bond descriptor of each bond's species pair)."""
     bi, bj, br = bonds_
     nb = bi.numel()
     X = torch.empty((nb, 16), dtype=torch.int16, device=bi.device)
-    _check(lib().tbk_bond_features(nb, _ptr(bi), _ptr(bj), _ptr(br), _ptr(v), v.shape[1], float(r_cut),
-                                   _f64arr(shift), _f64arr(scale), _ptr(X), _stream(stream)))
+    if cnk is None:
+        _check(lib().tbk_bond_features(nb, _ptr(bi), _ptr(bj), _ptr(br), _ptr(v), v.shape[1], float(r_cut),
+                                       _f64arr(shift), _f64arr(scale), _ptr(X), _stream(stream)))
+        return X
+    ns, arr, cp = _cnk_arg(cnk)
+    _check(lib().tbk_bond_features_species(nb, _ptr(bi), _ptr(bj), _ptr(br), _ptr(_dev(species, torch.int32)),
+                                           _ptr(v), v.shape[1], float(r_cut), ns, cp, _f64arr(shift),
+                                           _f64arr(scale), _ptr(X), _stream(stream)))
     return X
 
 

@@ -129,3 +129,101 @@ def test_species_errors():
     with pytest.raises(tbkpm.TBKError) as e:
         build(s, 4, "sell_f64", 8, nan, se)
     assert e.value.name == "NOT_FINITE"
+
+
+def cnk_table(ns, seed):
+    rng = np.random.default_rng(seed)
+    c = np.eye(8)[None, None] + 0.3 * rng.normal(size=(ns, ns, 8, 8))
+    return 0.5 * (c + c.transpose(1, 0, 2, 3))
+
+
+def test_species_descriptor_and_features_match_oracle():
+    s = synth.hbn_stripes(8, 6, stripe_cells=2, sigma=0.08, seed=7)
+    c = cnk_table(3, 1)
+    pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
+    seg = [0, s.n]
+    v = tbkpm.descriptor(pos, seg, [s.box], s.periodic, synth.R_DESC, 8, species=sp, cnk=c).cpu().numpy()
+    pd = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+    vo = O.descriptor(s.n, pd, synth.R_DESC, 8, s.species, c)
+    np.testing.assert_allclose(v, vo, rtol=1e-12, atol=1e-12 * np.abs(vo).max())
+    b = tbkpm.bonds(pos, seg, [s.box], s.periodic, synth.R_HOP)
+    hop = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_HOP)
+    o = np.lexsort((hop[1], hop[0]))
+    hop = (hop[0][o], hop[1][o], hop[2][o])
+    raw = O.bond_features(hop, vo, synth.R_DESC, species=s.species, cnk=c)
+    mean, std = raw.mean(0), raw.std(0)
+    X = tbkpm.bond_features(b, G.to_dev(vo), mean, std, synth.R_DESC, species=sp, cnk=c)
+    X = (X.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    Xo = O.bf16(O.bond_features(hop, vo, synth.R_DESC, mean, std, species=s.species, cnk=c))
+    mism = X != Xo
+    assert mism.mean() <= 1e-3
+    if mism.any():
+        np.testing.assert_allclose(X[mism], Xo[mism], rtol=2 ** -7)
+    bad = c.copy()
+    bad[0, 1, 0, 0] += 0.5
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.descriptor(pos, seg, [s.box], s.periodic, synth.R_DESC, 8, species=sp, cnk=bad)
+    assert e.value.name == "INVALID_ARG"
+
+
+def test_learned_sk_with_species_coefficients_matches_oracle():
+    """Bond and onsite networks on descriptors with coefficients per species pair."""
+    s = synth.hbn_stripes(8, 5, stripe_cells=2, sigma=0.07, seed=6)
+    pv, se = tables(3, 4, 9)
+    c = cnk_table(3, 4)
+    pd = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_DESC)
+    vo = O.descriptor(s.n, pd, synth.R_DESC, 8, s.species, c)
+    hop = O.neighbor_pairs(s.pos, s.box, s.periodic, synth.R_HOP)
+    o = np.lexsort((hop[1], hop[0]))
+    hop = (hop[0][o], hop[1][o], hop[2][o])
+    raw = O.bond_features(hop, vo, synth.R_DESC, species=s.species, cnk=c)
+    mean, std = raw.mean(0), raw.std(0)
+    base = synth.init_mlp_params(3, out_scale=0.5)
+    rng = np.random.default_rng(4)
+    P = np.repeat(base[None, :], 4, axis=0)
+    P[:, 1600:1632] = rng.uniform(-0.5, 0.5, (4, 32)) / np.sqrt(32)
+    P = P.astype(np.float32)
+    Pon = np.repeat(base[None, None, :], 6, axis=0).reshape(3, 2, -1).copy()
+    Pon[:, :, 1600:1632] = rng.uniform(-1.0, 1.0, (3, 2, 32)) / np.sqrt(32)
+    Pon = Pon.astype(np.float32)
+    nmean, nstd = vo.mean(0), vo.std(0)
+    H = build(s, 4, "bsell4_f64", 16, pv, se,
+              model=dict(params=G.to_dev(P), shift=mean, scale=std, r_desc=synth.R_DESC, cnk=c))
+    Hon = tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                     synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                     fmt="bsell4_f64", slice=16, pair_v=pv, species_e=se,
+                                     onsite_model=dict(params=G.to_dev(Pon), shift=nmean, scale=nstd,
+                                                       r_desc=synth.R_DESC, cnk=c))
+    Xo = O.bf16(O.bond_features(hop, vo, synth.R_DESC, mean, std, species=s.species, cnk=c))
+    Y = []
+    for p in P:
+        yo, h1, h2 = O.mlp_forward(Xo, p.astype(np.float64), bf16_ops=True, keep=True)
+        Y.append(yo)
+    clear = G.bf16_decisions_clear(h1, h2)
+    Y = np.stack(Y)
+    csr = oracle_csr(s, 4, pv, se, pairs=hop, scale=1.0 + Y.T)
+    v, ov, _ = compare(H, csr, "bsell4_f64", 4)
+    orow, ocol, _ = G.csr_entries(csr)
+    o2 = np.lexsort((ocol, orow))
+    bond_of = {(int(i), int(j)): e for e, (i, j) in enumerate(zip(hop[0], hop[1]))}
+    ent_clear = np.array([clear[bond_of[(min(i // 4, j // 4), max(i // 4, j // 4))]]
+                          for i, j in zip(orow[o2], ocol[o2])])
+    assert ent_clear.mean() >= 0.2
+    err = np.abs(v - ov)
+    assert err[ent_clear].max() <= 5e-5 * np.abs(ov).max()
+    assert err.max() <= 1e-2 * np.abs(ov).max()
+    # onsite networks on the species descriptor
+    Xn = O.node_features(vo, nmean, nstd)
+    add = np.zeros((s.n, 3))
+    for a in range(3):
+        for l in range(2):
+            y, n1, n2 = O.mlp_forward(Xn, Pon[a, l].astype(np.float64), bf16_ops=True, keep=True)
+            add[s.species == a, l] = y[s.species == a]
+    nclear = np.repeat(G.bf16_decisions_clear(n1, n2), 4)
+    csr_on = O.sk_hamiltonian(s.pos, s.box, s.periodic, np.zeros(4), 0.0, 0.0, r_cut=synth.R_HOP, r0=synth.R0,
+                              beta=synth.BETA, species=s.species, pair_v=pv, species_e=se, onsite_add=add)[0]
+    _, _, _, onsite = G.block_entries(Hon)
+    d = np.abs(onsite - csr_on.diag)
+    assert nclear.mean() >= 0.3
+    assert d[nclear].max() <= 2e-5 * np.abs(add).max()
+    assert d.max() <= 1e-2 * np.abs(add).max()
