@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 10
+#define TBK_ABI_VERSION 11
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -71,7 +71,17 @@ typedef enum {
                            neighbour atom row of each block (own row on padding); val
                            [n_orb^2 n_entries], block q row-major at n_orb^2 q (zero on
                            padding); n_rows = n_orb atoms                              */
-    TBK_BSELL4_F32 = 4  /* the same with float blocks (complex-float recurrence)        */
+    TBK_BSELL4_F32 = 4, /* the same with float blocks (complex-float recurrence)        */
+    TBK_BGEOM_F64 = 5,  /* block SELL over atoms that stores each bond's displacement
+                           instead of its block (tb_build_hamiltonian_sk, one species,
+                           no networks): ptr, col as TBK_BSELL4_*; val [3 n_entries],
+                           (dx, dy, dz) from the row atom to col[q] (minimum image; zero
+                           on padding); the recurrence forms every block from it and the
+                           integrals in h->sk_geom (12 B or 24 B per bond instead of
+                           n_orb^2 values: the matrix-free form for models whose
+                           blocks do not fit in memory)                              */
+    TBK_BGEOM_F32 = 6   /* the same with float displacements (complex-float
+                           recurrence, blocks formed in float)                       */
 } tbk_format;
 
 /* Distance-scaled hopping model of Eq. (1):
@@ -122,8 +132,10 @@ typedef struct {
                               when non-NULL, read by the recurrence with
                               compact_columns = 1                              */
     int32_t n_orb;         /* out (build): orbitals per atom, 1 for the one-
-                              orbital builders, 4 for tb_build_hamiltonian_sk;
+                              orbital builders, 4 or 9 for tb_build_hamiltonian_sk;
                               perm[row] / n_orb is the caller's atom           */
+    double sk_geom[12];    /* out (build, TBK_BGEOM_*): the ten integrals of
+                              tbk_sk_params at r0, then r0 and beta            */
 } tbk_ham;
 
 /*

@@ -540,7 +540,10 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.doubling = 0;
     c.uniform_values = 0;
     c.compact_columns = 0;
-    c.atom_rows = (h && (h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32)) ? 1 : 0;
+    c.atom_rows = (h && (h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32 || h->fmt == TBK_BGEOM_F64 ||
+                         h->fmt == TBK_BGEOM_F32))
+                      ? 1
+                      : 0;
     return c;
 }
 
@@ -553,12 +556,19 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     TBK_CHECK(precision == TBK_PREC_F64 || precision == TBK_PREC_C32, TBK_ERR_INVALID_ARG,
               "unknown precision %d", precision);
     if (precision == TBK_PREC_F64)
-        TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_BSELL4_F64, TBK_ERR_INVALID_ARG,
-                  "FP64 recurrence needs a double-valued Hamiltonian");
+        TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_BSELL4_F64 ||
+                      h->fmt == TBK_BGEOM_F64,
+                  TBK_ERR_INVALID_ARG, "FP64 recurrence needs a double-valued Hamiltonian");
     else
-        TBK_CHECK(h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32, TBK_ERR_INVALID_ARG,
+        TBK_CHECK(h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32 || h->fmt == TBK_BGEOM_F32, TBK_ERR_INVALID_ARG,
                   "C32 recurrence needs a float SELL Hamiltonian");
-    pl.block = h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32;
+    pl.geom = h->fmt == TBK_BGEOM_F64 || h->fmt == TBK_BGEOM_F32;
+    pl.block = h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32 || pl.geom;
+    if (pl.geom) {
+        for (int k = 0; k < 12; ++k) pl.geom_params[k] = h->sk_geom[k];
+        TBK_CHECK(h->sk_geom[10] > 0 && std::isfinite(h->sk_geom[11]), TBK_ERR_INVALID_ARG,
+                  "sk_geom: r0 must be positive and beta finite");
+    }
     if (pl.block) {
         TBK_CHECK((h->n_orb == 4 || h->n_orb == 9) && h->n_rows % h->n_orb == 0, TBK_ERR_INVALID_ARG,
                   "a block Hamiltonian has 4 or 9 orbital rows per atom (n_orb = %d)", h->n_orb);
@@ -593,6 +603,7 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
               "uniform_values and compact_columns are not offered for block Hamiltonians");
     TBK_CHECK(pl.cfg.atom_rows == 0 || pl.cfg.atom_rows == 1, TBK_ERR_INVALID_ARG, "atom_rows must be 0/1");
     if (!pl.block) pl.cfg.atom_rows = 0;
+    if (pl.geom) pl.cfg.atom_rows = 1;     // the displacement form has a thread per atom only
     pl.VPT = pl.cfg.vectors_per_thread;
     pl.L = pl.Rp / pl.VPT;
     const int64_t rpb = kThreads / pl.L;

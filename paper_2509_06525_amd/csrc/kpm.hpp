@@ -18,6 +18,8 @@ struct KpmPlan {
     size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0, total = 0;
     bool block = false;         // block Hamiltonian (kpm_block.hip)
     int norb = 1;               // orbitals per atom of a block Hamiltonian (4 or 9)
+    bool geom = false;          // blocks formed in the step from bond displacements
+    double geom_params[12] = {};   // integrals at r0, r0, beta (h->sk_geom)
     bool seeded = false;        // start vectors generated on the device from `seed`
     uint64_t seed = 0;
 };

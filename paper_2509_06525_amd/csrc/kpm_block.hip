@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "kpm.hpp"
 #include "kpm_dev.hpp"
+#include "sk_table.hpp"
 
 namespace tbk {
 namespace {
@@ -254,12 +255,140 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
     block_reduce_store<L, NA>(acc, partial, lb);
 }
 
+// Integrals and radial law of the displacement form, in the vector type.
+template <class VT> struct GeomParams {
+    VT v[10];        // integrals at r0
+    VT inv_r0;       // 1 / r0
+    VT beta;         // decay exponent
+};
+
+// Displacement form (TBK_BGEOM_*): as the atom form, but each bond stores its
+// displacement d = x_j - x_i (3 values) instead of its block.  The block is
+// formed in registers: r = |d|, direction cosines d / r, integrals scaled by
+// f(r) = exp(-beta (r / r0 - 1)), then the Slater-Koster table in the vector
+// type.  Padding slots (d = 0) are skipped.  Per bond this reads 12 B (float)
+// instead of 4 NORB^2 B and spends about 2 NORB^2 + 150 flops forming the
+// block, which the HBM-bound step has to spare.
+template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
+__global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ geo,
+    const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
+    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a, GeomParams<VT> gp) {
+    constexpr int APB = kThreads / L;   // atoms per tile
+    const int la = threadIdx.x / L;
+    const int vs = threadIdx.x % L;
+    const int64_t lb = logical_block(a.xcd_remap);
+    const int64_t t0 = lb * a.tiles_per_block;
+    const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
+    const int64_t smask = ((int64_t)1 << a.log2_slice) - 1;
+    const int64_t stride = smask + 1;
+    const int Rp = a.Rp;
+    const int voff = vs * VPT;
+    const int64_t last = a.n_rows / NORB - 1;     // last atom row
+
+    constexpr int NA = DBL ? 2 * VPT : VPT;
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t au = t * APB + la;
+        const bool ok = au <= last;
+        const int64_t at = min(au, last);
+        const int64_t sl = at >> a.log2_slice;
+        const int64_t p0 = ptr[sl], p1 = ptr[sl + 1];
+        const int64_t base = p0 + (at & smask);
+        const int w = (int)((p1 - p0) >> a.log2_slice);
+
+        Pack<VT, VPT> y[NORB];
+#pragma unroll
+        for (int o = 0; o < NORB; ++o)
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) { y[o].re[q] = 0; y[o].im[q] = 0; }
+        for (int k = 0; k < w; ++k) {
+            const int64_t qb = base + (int64_t)k * stride;
+            const int32_t c = ld<NT>(bcol + qb);
+            const VT dx = ld<NT>(geo + 3 * qb), dy = ld<NT>(geo + 3 * qb + 1), dz = ld<NT>(geo + 3 * qb + 2);
+            const VT r2 = dx * dx + dy * dy + dz * dz;
+            if (!(r2 > (VT)0)) continue;              // padding slot
+            Pack<VT, VPT> x[NORB];
+#pragma unroll
+            for (int b = 0; b < NORB; ++b)
+                x[b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c + b) * Rp + voff));
+            const VT rr = sqrt(r2);
+            const VT inv = (VT)1 / rr;
+            const VT f = exp(-gp.beta * (rr * gp.inv_r0 - (VT)1));
+            VT vf[10];
+#pragma unroll
+            for (int l = 0; l < 10; ++l) vf[l] = gp.v[l] * f;
+            VT B[NORB][NORB];
+            sk_table<VT, NORB>(vf, vf, dx * inv, dy * inv, dz * inv, B);
+#pragma unroll
+            for (int o = 0; o < NORB; ++o)
+#pragma unroll
+                for (int b = 0; b < NORB; ++b)
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) {
+                        y[o].re[q] += B[o][b] * x[b].re[q];
+                        y[o].im[q] += B[o][b] * x[b].im[q];
+                    }
+        }
+#pragma unroll
+        for (int o = 0; o < NORB; ++o) {
+            const int64_t i = (int64_t)NORB * at + o;
+            const int64_t off = 2 * (i * Rp + voff);
+            Pack<VT, VPT> pv, rv;
+            if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(tprev + off);
+            if constexpr (DBL) rv = load_pack<false, VT, VPT>(tcur + off);
+            else rv = load_pack<NT, VT, VPT>(r + off);
+            if constexpr (DIAG) {
+                const VT dg = (onsite ? ld<NT>(onsite + i) : (VT)0) - a.shift;
+                const Pack<VT, VPT> xs = DBL ? rv : load_pack<false, VT, VPT>(tcur + off);
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) { y[o].re[q] += dg * xs.re[q]; y[o].im[q] += dg * xs.im[q]; }
+            }
+            Pack<VT, VPT> ov;
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {
+                if constexpr (FIRST) {
+                    ov.re[q] = a.c1 * y[o].re[q];
+                    ov.im[q] = a.c1 * y[o].im[q];
+                } else {
+                    ov.re[q] = a.c1 * y[o].re[q] - pv.re[q];
+                    ov.im[q] = a.c1 * y[o].im[q] - pv.im[q];
+                }
+            }
+            if (ok) {
+                store_pack<NT, VT, VPT>(tnext + off, ov);
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const double cr = (double)rv.re[q] * (double)ov.re[q] + (double)rv.im[q] * (double)ov.im[q];
+                    if constexpr (DBL) {
+                        acc[q] += (double)ov.re[q] * (double)ov.re[q] + (double)ov.im[q] * (double)ov.im[q];
+                        acc[VPT + q] += cr;
+                    } else {
+                        acc[q] += cr;
+                    }
+                }
+            }
+        }
+    }
+    block_reduce_store<L, NA>(acc, partial, lb);
+}
+
 template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG>
 void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
     const unsigned G = (unsigned)pl.G;
+    GeomParams<VT> gp;
+    for (int l = 0; l < 10; ++l) gp.v[l] = (VT)pl.geom_params[l];
+    gp.inv_r0 = pl.geom_params[10] > 0 ? (VT)(1.0 / pl.geom_params[10]) : (VT)0;
+    gp.beta = (VT)pl.geom_params[11];
 #define TBK_BLK(NT, DBL)                                                                                    \
     do {                                                                                                    \
-        if (pl.cfg.atom_rows)                                                                               \
+        if (pl.geom)                                                                                        \
+            k_cheb_step_geom<VT, NORB, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(                \
+                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a, gp);            \
+        else if (pl.cfg.atom_rows)                                                                          \
             k_cheb_step_atom<VT, NORB, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(                \
                 p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);                \
         else                                                                                                \

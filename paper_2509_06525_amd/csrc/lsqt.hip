@@ -272,6 +272,7 @@ tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision
     TBK_CHECK(ly.pl.cfg.doubling == 0, TBK_ERR_INVALID_ARG,
               "the doubling identities need the same left and right vectors; VAC moments use the direct form");
     TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "VAC conductivity takes one structure");
+    TBK_CHECK(!ly.pl.geom, TBK_ERR_UNSUPPORTED, "VAC conductivity takes stored blocks, not the displacement form");
     TBK_CHECK(h->fmt != TBK_CSR_F64 || h->slice == 1, TBK_ERR_INVALID_ARG, "CSR needs slice 1");
     const size_t elem = precision == TBK_PREC_C32 ? sizeof(float) : sizeof(double);
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -391,6 +392,8 @@ extern "C" tbk_status tb_build_velocity(const double *pos, const double box[3], 
     TBK_CHECK(pos && box && periodic && h && vx, TBK_ERR_INVALID_ARG, "NULL argument");
     TBK_CHECK(axis >= 0 && axis <= 2, TBK_ERR_INVALID_ARG, "axis = %d not in {0, 1, 2}", axis);
     TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "the velocity operator is built for one structure");
+    TBK_CHECK(h->fmt != TBK_BGEOM_F64 && h->fmt != TBK_BGEOM_F32, TBK_ERR_UNSUPPORTED,
+              "the velocity operator is built for stored values, not the displacement form");
     TBK_CHECK(h->fmt == TBK_CSR_F64 || h->fmt == TBK_SELL_F64 || h->fmt == TBK_SELL_F32 ||
                   h->fmt == TBK_BSELL4_F64 || h->fmt == TBK_BSELL4_F32,
               TBK_ERR_INVALID_ARG, "unknown format %d", h->fmt);

@@ -21,6 +21,7 @@
 
 #include "builder.hpp"
 #include "nlist.hpp"
+#include "sk_table.hpp"
 
 namespace tbk {
 namespace {
@@ -73,91 +74,6 @@ struct SkValues {
     int32_t n_sh = 0;
 };
 
-// The s-d row and the p-d block of the table for integrals v.
-__device__ __forceinline__ void sk_sd_pd(const double *v, double l, double m, double n, double (&sdr)[5],
-                                         double (&pd)[3][5]) {
-    const double s3 = 1.7320508075688772;
-    const double l2 = l * l, m2 = m * m, n2 = n * n;
-    const double sd = v[4], pds = v[5], pdp = v[6];
-    const double q = n2 - 0.5 * (l2 + m2), dlm = l2 - m2;
-    sdr[0] = s3 * l * m * sd;
-    sdr[1] = s3 * m * n * sd;
-    sdr[2] = s3 * n * l * sd;
-    sdr[3] = 0.5 * s3 * dlm * sd;
-    sdr[4] = q * sd;
-    pd[0][0] = s3 * l2 * m * pds + m * (1.0 - 2.0 * l2) * pdp;
-    pd[0][1] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
-    pd[0][2] = s3 * l2 * n * pds + n * (1.0 - 2.0 * l2) * pdp;
-    pd[0][3] = 0.5 * s3 * l * dlm * pds + l * (1.0 - dlm) * pdp;
-    pd[0][4] = l * q * pds - s3 * l * n2 * pdp;
-    pd[1][0] = s3 * m2 * l * pds + l * (1.0 - 2.0 * m2) * pdp;
-    pd[1][1] = s3 * m2 * n * pds + n * (1.0 - 2.0 * m2) * pdp;
-    pd[1][2] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
-    pd[1][3] = 0.5 * s3 * m * dlm * pds - m * (1.0 + dlm) * pdp;
-    pd[1][4] = m * q * pds - s3 * m * n2 * pdp;
-    pd[2][0] = s3 * l * m * n * pds - 2.0 * l * m * n * pdp;
-    pd[2][1] = s3 * n2 * m * pds + m * (1.0 - 2.0 * n2) * pdp;
-    pd[2][2] = s3 * n2 * l * pds + l * (1.0 - 2.0 * n2) * pdp;
-    pd[2][3] = 0.5 * s3 * n * dlm * pds - n * dlm * pdp;
-    pd[2][4] = n * q * pds + s3 * n * (l2 + m2) * pdp;
-}
-
-// The Slater-Koster table: E[a][b] = <a_i|H|b_j> / f for direction cosines
-// (l, m, n) from i to j.  The blocks with the lower angular momentum on the row
-// side (and the equal-l blocks) come from the integrals vu of the ordered
-// species pair (row, column), the others from the reversed pair's vl by
-// E[b][a] = (-1)^(l_a + l_b) E'[a][b] (E' formed with vl; vl = vu for one
-// species).  Only the first NORB rows and columns are formed.
-template <int NORB>
-__device__ __forceinline__ void sk_table(const double *vu, const double *vl, double l, double m, double n,
-                                         double (&E)[NORB][NORB]) {
-    const double *v = vu;
-    const double s3 = 1.7320508075688772;
-    const double l2 = l * l, m2 = m * m, n2 = n * n;
-    const double c[3] = {l, m, n};
-    E[0][0] = v[0];
-    for (int a = 0; a < 3; ++a) {
-        E[0][1 + a] = c[a] * v[1];
-        E[1 + a][0] = -c[a] * vl[1];
-        for (int b = 0; b < 3; ++b) E[1 + a][1 + b] = c[a] * c[b] * v[2] + ((a == b ? 1.0 : 0.0) - c[a] * c[b]) * v[3];
-    }
-    if constexpr (NORB == 9) {
-        const double dds = v[7], ddp = v[8], ddd = v[9];
-        const double q = n2 - 0.5 * (l2 + m2), dlm = l2 - m2;
-        double sdr[5], pd[3][5], sdl[5], pdl[3][5];
-        sk_sd_pd(vu, l, m, n, sdr, pd);
-        sk_sd_pd(vl, l, m, n, sdl, pdl);
-        double dd[5][5];
-        dd[0][0] = 3.0 * l2 * m2 * dds + (l2 + m2 - 4.0 * l2 * m2) * ddp + (n2 + l2 * m2) * ddd;
-        dd[1][1] = 3.0 * m2 * n2 * dds + (m2 + n2 - 4.0 * m2 * n2) * ddp + (l2 + m2 * n2) * ddd;
-        dd[2][2] = 3.0 * n2 * l2 * dds + (n2 + l2 - 4.0 * n2 * l2) * ddp + (m2 + n2 * l2) * ddd;
-        dd[0][1] = 3.0 * l * m2 * n * dds + l * n * (1.0 - 4.0 * m2) * ddp + l * n * (m2 - 1.0) * ddd;
-        dd[0][2] = 3.0 * l2 * m * n * dds + m * n * (1.0 - 4.0 * l2) * ddp + m * n * (l2 - 1.0) * ddd;
-        dd[1][2] = 3.0 * l * m * n2 * dds + l * m * (1.0 - 4.0 * n2) * ddp + l * m * (n2 - 1.0) * ddd;
-        dd[0][3] = 1.5 * l * m * dlm * dds - 2.0 * l * m * dlm * ddp + 0.5 * l * m * dlm * ddd;
-        dd[1][3] = 1.5 * m * n * dlm * dds - m * n * (1.0 + 2.0 * dlm) * ddp + m * n * (1.0 + 0.5 * dlm) * ddd;
-        dd[2][3] = 1.5 * n * l * dlm * dds + n * l * (1.0 - 2.0 * dlm) * ddp - n * l * (1.0 - 0.5 * dlm) * ddd;
-        dd[0][4] = s3 * (l * m * q * dds - 2.0 * l * m * n2 * ddp + 0.5 * l * m * (1.0 + n2) * ddd);
-        dd[1][4] = s3 * (m * n * q * dds + m * n * (l2 + m2 - n2) * ddp - 0.5 * m * n * (l2 + m2) * ddd);
-        dd[2][4] = s3 * (l * n * q * dds + l * n * (l2 + m2 - n2) * ddp - 0.5 * l * n * (l2 + m2) * ddd);
-        dd[3][3] = 0.75 * dlm * dlm * dds + (l2 + m2 - dlm * dlm) * ddp + (n2 + 0.25 * dlm * dlm) * ddd;
-        dd[3][4] = s3 * (0.5 * dlm * q * dds - n2 * dlm * ddp + 0.25 * (1.0 + n2) * dlm * ddd);
-        dd[4][4] = q * q * dds + 3.0 * n2 * (l2 + m2) * ddp + 0.75 * (l2 + m2) * (l2 + m2) * ddd;
-        for (int a = 0; a < 5; ++a) {
-            E[0][4 + a] = sdr[a];
-            E[4 + a][0] = sdl[a];                      // d-s: even
-            for (int b = 0; b < 3; ++b) {
-                E[1 + b][4 + a] = pd[b][a];
-                E[4 + a][1 + b] = -pdl[b][a];          // d-p: odd
-            }
-            for (int b = a; b < 5; ++b) {
-                E[4 + a][4 + b] = dd[a][b];
-                E[4 + b][4 + a] = dd[a][b];
-            }
-        }
-    }
-}
-
 // Per-bond scales of the two-centre integrals (learned form): bonds i < j of
 // the hopping cutoff sorted by (i, j), bond_ptr[i] = first bond of atom i,
 // y[l * nb + b] = output of network l for bond b; the bond's integral l is
@@ -201,7 +117,7 @@ __device__ __forceinline__ void bond_integrals(const BondScales &bs, const SkVal
 template <int NORB>
 __device__ __forceinline__ void sk_block(const double *vu, const double *vl, const SkValues &sk, double r, double dx,
                                          double dy, double dz, double (&B)[NORB][NORB]) {
-    sk_table<NORB>(vu, vl, dx / r, dy / r, dz / r, B);
+    sk_table<double, NORB>(vu, vl, dx / r, dy / r, dz / r, B);
     const double f = exp(-sk.beta * (r / sk.r0 - 1.0));
     for (int a = 0; a < NORB; ++a)
         for (int b = 0; b < NORB; ++b) B[a][b] *= f;
@@ -285,7 +201,7 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
                               int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                               const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                               int32_t *__restrict__ bcol, V *__restrict__ bval, V *__restrict__ onsite,
-                              int64_t *__restrict__ bound_keys, BondScales bs) {
+                              int64_t *__restrict__ bound_keys, BondScales bs, bool geom) {
     constexpr int NB = NORB * NORB;
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
@@ -305,8 +221,14 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
             if (q < w) {
                 const int64_t slot = base + (int64_t)q * slice;
                 bcol[slot] = iperm[j];
-                for (int a = 0; a < NORB; ++a)
-                    for (int b = 0; b < NORB; ++b) bval[NB * slot + NORB * a + b] = (V)B[a][b];
+                if (geom) {              // the bond's displacement instead of its block
+                    bval[3 * slot] = (V)dx;
+                    bval[3 * slot + 1] = (V)dy;
+                    bval[3 * slot + 2] = (V)dz;
+                } else {
+                    for (int a = 0; a < NORB; ++a)
+                        for (int b = 0; b < NORB; ++b) bval[NB * slot + NORB * a + b] = (V)B[a][b];
+                }
             }
             for (int a = 0; a < NORB; ++a)
                 for (int b = 0; b < NORB; ++b) asum[a] += fabs(B[a][b]);
@@ -315,7 +237,8 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
         for (int32_t k = q; k < w; ++k) {
             const int64_t slot = base + (int64_t)k * slice;
             bcol[slot] = (int32_t)r;
-            for (int e = 0; e < NB; ++e) bval[NB * slot + e] = (V)0;
+            const int ne = geom ? 3 : NB;
+            for (int e = 0; e < ne; ++e) bval[(int64_t)ne * slot + e] = (V)0;
         }
         for (int a = 0; a < NORB; ++a) {
             const double e = sk_onsite(sk, i, a);
@@ -327,7 +250,8 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
     block_segment_bounds(lo, hi, r < n ? 0 : -1, bound_keys);
 }
 
-bool is_block(int32_t fmt) { return fmt == TBK_BSELL4_F64 || fmt == TBK_BSELL4_F32; }
+bool is_geom(int32_t fmt) { return fmt == TBK_BGEOM_F64 || fmt == TBK_BGEOM_F32; }
+bool is_block(int32_t fmt) { return fmt == TBK_BSELL4_F64 || fmt == TBK_BSELL4_F32 || is_geom(fmt); }
 
 tbk_status check_sk(const tbk_sk_params *sk) {
     TBK_CHECK(sk != nullptr, TBK_ERR_INVALID_ARG, "sk params are NULL");
@@ -457,7 +381,7 @@ void launch_fill(const HamPlan &plan, const double *pos, int64_t n, int32_t slic
         k_fill_sk_blk<V, NORB><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), r_cut, v,
                                                     plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr,
                                                     h->col, static_cast<V *>(h->val), static_cast<V *>(h->onsite),
-                                                    keys, bs);
+                                                    keys, bs, is_geom(h->fmt));
     else
         k_fill_sk<V, NORB><<<g, kBlock, 0, s>>>(plan.cells.view, pos, n, slice, log2i(slice), r_cut, v,
                                                 plan.perm.as<int32_t>(), plan.iperm.as<int32_t>(), h->ptr, h->col,
@@ -627,7 +551,14 @@ tbk_status build_sk(const double *pos, const int32_t *species, int64_t n, const 
         bs.nb = nb;
         bs.K = K;
     }
-    const bool f32 = h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32;
+    const bool f32 = h->fmt == TBK_SELL_F32 || h->fmt == TBK_BSELL4_F32 || h->fmt == TBK_BGEOM_F32;
+    if (is_geom(h->fmt)) {
+        TBK_CHECK(!sk->pair_v && !model && !onsite, TBK_ERR_INVALID_ARG,
+                  "the displacement format takes one species and fixed integrals");
+        for (int l = 0; l < 10; ++l) h->sk_geom[l] = v.v[l];
+        h->sk_geom[10] = sk->r0;
+        h->sk_geom[11] = sk->beta;
+    }
     if (norb == 4) {
         if (f32) launch_fill<float, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), bs, s);
         else launch_fill<double, 4>(plan, pos, n, slice, sk->r_cut, v, h, keys.as<int64_t>(), bs, s);

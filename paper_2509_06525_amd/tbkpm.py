@@ -18,7 +18,7 @@ TBK_ERR_BUFFER_TOO_SMALL = 2
 TBK_MLP_PARAMS = 1633      # parameters of one per-bond network (W1, b1, W2, b2, W3, b3)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BUFFER_TOO_SMALL", 3: "NOT_FINITE",
                 4: "SPECTRUM", 5: "UNSUPPORTED", 6: "DEVICE"}
-FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2, "bsell4_f64": 3, "bsell4_f32": 4}
+FORMATS = {"csr_f64": 0, "sell_f64": 1, "sell_f32": 2, "bsell4_f64": 3, "bsell4_f32": 4, "bgeom_f64": 5, "bgeom_f32": 6}
 PRECISIONS = {"f64": 0, "c32": 1}
 
 
@@ -45,7 +45,7 @@ class HamStruct(ctypes.Structure):
                 ("ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("onsite", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("seg_rows", ctypes.c_void_p), ("uniform_hop", ctypes.c_int32), ("hop_value", ctypes.c_double),
-                ("col16", ctypes.c_void_p), ("n_orb", ctypes.c_int32)]
+                ("col16", ctypes.c_void_p), ("n_orb", ctypes.c_int32), ("sk_geom", ctypes.c_double * 12)]
 
 
 _LIB = None
@@ -444,8 +444,9 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
     _check(L.tbk_hamiltonian_size_sk(_ptr(pos), _ptr(species), n, boxa, per, ctypes.byref(sk), ctypes.byref(st), s))
     dev = pos.device
-    vdt = torch.float32 if fmt in ("sell_f32", "bsell4_f32") else torch.float64
-    per_entry = norb * norb if fmt.startswith("bsell4") else 1        # norb x norb blocks
+    vdt = torch.float32 if fmt in ("sell_f32", "bsell4_f32", "bgeom_f32") else torch.float64
+    # norb x norb blocks, or the bond's displacement (3 values) for the matrix-free form
+    per_entry = norb * norb if fmt.startswith("bsell4") else (3 if fmt.startswith("bgeom") else 1)
     t = {
         "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
         "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),

@@ -1,0 +1,117 @@
+"""GPU parity of the displacement (matrix-free) form of the Slater-Koster block
+Hamiltonian: each bond stores (dx, dy, dz), the recurrence forms the block.
+
+Stored displacements against the minimum-image differences of the positions
+(FP64: exact to rounding); the pattern equals the block format's; FP64 moments
+within 1e-10 of the row count against the oracle (s, p and s, p, d); complex
+float DOS within 1e-4 relative L2 and moments within 1e-4 of the row count of
+the stored-block form; the forms that need stored values are refused."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_06525_amd import synth, tbkpm
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def build(s, norb, fmt, slice_=16, model=None):
+    return tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
+                                      synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                      fmt=fmt, slice=slice_, d=synth.SK_D if norb == 9 else None, e_d=synth.SK_ED,
+                                      model=model)
+
+
+def oracle_csr(s, norb):
+    vv = (synth.SK_V + synth.SK_D) if norb == 9 else synth.SK_V
+    return O.sk_hamiltonian(s.pos, s.box, s.periodic, vv, synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP,
+                            r0=synth.R0, beta=synth.BETA, e_d=synth.SK_ED)[0]
+
+
+@pytest.mark.parametrize("norb", [4, 9])
+def test_displacements_and_pattern(norb):
+    s = synth.graphene_sheet(7, 6, 0.08, 3)
+    Hg = build(s, norb, "bgeom_f64", 16)
+    Hb = build(s, norb, "bsell4_f64", 16)
+    assert Hg.st.n_entries == Hb.st.n_entries and Hg.st.n_orb == norb
+    tg = {k: v.cpu().numpy() for k, v in Hg.tensors.items()}
+    tb = {k: v.cpu().numpy() for k, v in Hb.tensors.items()}
+    ne = Hg.st.n_entries
+    np.testing.assert_array_equal(tg["ptr"], tb["ptr"])
+    # slots of real atoms (lanes past the last atom of the last slice are never written)
+    C = Hg.st.slice
+    ptr = tg["ptr"]
+    valid = np.zeros(ne, bool)
+    for sl in range(ptr.shape[0] - 1):
+        w = (ptr[sl + 1] - ptr[sl]) // C
+        lanes = min(C, s.n - sl * C)
+        for k in range(w):
+            valid[ptr[sl] + k * C: ptr[sl] + k * C + lanes] = True
+    np.testing.assert_array_equal(tg["col"][:ne][valid], tb["col"][:ne][valid])
+    np.testing.assert_array_equal(tg["onsite"], tb["onsite"])
+    assert Hg.bounds == Hb.bounds
+    assert list(Hg.st.sk_geom)[:4] == list(synth.SK_V)
+    geo = tg["val"][: 3 * ne].reshape(ne, 3)
+    perm = tg["perm"][::norb] // norb                      # atom row -> caller's atom
+    n_at = s.n
+    col = tg["col"]
+    for sl in range(ptr.shape[0] - 1):
+        w = (ptr[sl + 1] - ptr[sl]) // C
+        for lane in range(C):
+            r = sl * C + lane
+            if r >= n_at:
+                break
+            for k in range(w):
+                q = ptr[sl] + k * C + lane
+                if col[q] == r:
+                    np.testing.assert_array_equal(geo[q], 0.0)        # padding
+                    continue
+                d = s.pos[perm[col[q]]] - s.pos[perm[r]]
+                for ax in range(3):
+                    if s.periodic[ax]:
+                        d[ax] -= s.box[ax] * np.rint(d[ax] / s.box[ax])
+                np.testing.assert_allclose(geo[q], d, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("norb,R,tpb,nt,xr,dbl", [(4, 1, 1, 1, 0, 0), (4, 3, 2, 0, 1, 0), (9, 1, 2, 1, 0, 0),
+                                                  (9, 4, 1, 1, 1, 1), (9, 16, 2, 1, 0, 0)])
+def test_geom_fp64_moments(norb, R, tpb, nt, xr, dbl):
+    s = synth.graphene_sheet(9, 7, 0.06, 4)
+    csr = oracle_csr(s, norb)
+    H = build(s, norb, "bgeom_f64", 32)
+    a, b = G.oracle_ab(csr)
+    r = synth.random_phase(norb * s.n, R, 7)
+    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=1)
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r, 61)
+    assert np.abs(mu - mo).max() <= 1e-10 * norb * s.n
+
+
+@pytest.mark.parametrize("norb,R,vpt", [(4, 8, 2), (9, 1, 1), (9, 16, 2)])
+def test_geom_c32_dos_and_stored_block_agreement(norb, R, vpt):
+    s = synth.graphene_sheet(12, 10, 0.05, 8)
+    csr = oracle_csr(s, norb)
+    Hg = build(s, norb, "bgeom_f32", 64)
+    Hb = build(s, norb, "bsell4_f32", 64)
+    a, b = G.oracle_ab(csr)
+    r = synth.random_phase(norb * s.n, R, 3, np.complex64)
+    cfg = tbkpm.make_config(vpt, 2, 1, 0, 1, atom_rows=1)
+    mg = tbkpm.kpm_moments(Hg, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
+    mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 256, "c32", config=cfg).cpu().numpy()
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 256)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mg.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+    assert np.abs(mg - mb).max() <= 1e-4 * norb * s.n
+
+
+def test_geom_refusals():
+    s = synth.graphene_sheet(5, 4, 0.03, 1)
+    H = build(s, 4, "bgeom_f64", 8)
+    with pytest.raises(tbkpm.TBKError) as e:
+        tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
+    assert e.value.name == "UNSUPPORTED"
+    P = np.repeat(synth.init_mlp_params(1)[None, :], 4, axis=0)
+    with pytest.raises(tbkpm.TBKError) as e:
+        build(s, 4, "bgeom_f64", 8, model=dict(params=G.to_dev(P), shift=np.zeros(16), scale=np.ones(16)))
+    assert e.value.name == "INVALID_ARG"
