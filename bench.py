@@ -60,8 +60,9 @@ def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True, compact=Fa
     compact-column form 2-byte column offsets (the few entries whose offset
     escapes 16 bits also read their 4-byte column; not counted)."""
     st = H.st
-    val_b = 4 if st.fmt in (2, 4) else 8
-    per_value = st.n_orb * st.n_orb if st.fmt in (3, 4) else 1      # n_orb x n_orb blocks
+    val_b = 4 if st.fmt in (2, 4, 6) else 8
+    # n_orb x n_orb blocks, or the bond's displacement (3 values) in the matrix-free form
+    per_value = st.n_orb * st.n_orb if st.fmt in (3, 4) else (3 if st.fmt in (5, 6) else 1)
     b = st.n_entries * ((per_value * val_b if read_values else 0) + (2 if compact else 4)) + st.n_ptr * 8
     # gather T_n once, read T_{n-1}, write T_{n+1} (+ read r in the direct form)
     b += st.n_rows * Rp * 2 * elem * (4 if read_r else 3)
@@ -319,17 +320,24 @@ def bench_sk(args, w):
     r = torch.from_numpy(synth.random_phase(norb * N, R, w["seed"] + synth.VECTOR_SEED_OFFSET,
                                             np.complex64)).to(dev)
 
+    r_cut = w.get("r_cut", synth.R_HOP)
+    geom = w["fmt"].startswith("bgeom")
+
     def build(fmt=w["fmt"], slice_=64):
         return tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
-                                          r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice_,
+                                          r_cut=r_cut, r0=synth.R0, beta=synth.BETA, fmt=fmt, slice=slice_,
                                           stream=stream, d=dint, e_d=synth.SK_ED)
 
     def pick_shape(H, a, b):
         # the tuner builds one-orbital Hamiltonians, so time a few shapes here (both forms
         # of the block kernel: a thread per orbital row, a thread per atom)
         forms = (0, 1) if H.fmt in (tbkpm.FORMATS["bsell4_f32"], tbkpm.FORMATS["bsell4_f64"]) else (0,)
-        shapes = [tbkpm.make_config(v, t, nt, xr, 1, atom_rows=at) for at in forms for v in (1, 2)
-                  for t in (1, 2, 4) for nt in (0, 1) for xr in (0, 1)]
+        vpts = (1, 2) if R >= 2 else (1,)
+        tpbs = (1, 2) if geom else (1, 2, 4)
+        if geom:
+            forms = (1,)
+        shapes = [tbkpm.make_config(v, t, nt, xr, 1, atom_rows=at) for at in forms for v in vpts
+                  for t in tpbs for nt in (0, 1) for xr in (0, 1)]
         times = []
         for c in shapes:
             tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
@@ -396,9 +404,51 @@ def bench_sk(args, w):
         "shape_search_ms_per_launch": {("atom_form" if k else "orbital_row_form"): v for k, v in form_ms.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cheb_step_atom" if cfg.atom_rows else "k_cheb_step_blk",
+                     "kernel": "k_cheb_step_geom" if geom else (
+                         "k_cheb_step_atom" if cfg.atom_rows else "k_cheb_step_blk"),
                      "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6},
     }
+    if geom:
+        # stored blocks of the same matrix: norb^2 floats per bond instead of three
+        blk_bytes = Hs.st.n_entries * (norb * norb * 4 + 4)
+        out["variants"] = {"stored_blocks": {
+            "bytes": blk_bytes, "displacement_form_bytes": Hs.st.n_entries * 16,
+            "note": "not run: the stored-block form of this matrix does not fit next to the vectors"
+            if blk_bytes > 200e9 else "not run"}}
+        if not args.no_doubling:
+            out["variants"]["doubling"] = kpm_variant(args, "doubling", {"doubling": 1}, Hs, aa, bb, r, M, R, Rp,
+                                                      4, diag, "c32", cfg, mu_c, rho_c, E, stream, dev)
+        del Hs
+    else:
+        sk_block_variants(args, w, out, build, pick_shape, Hs, aa, bb, r, M, R, Rp, diag, cfg, mu, mu_c, rho_c, E,
+                          ev, work, nr, norb, dint, pos, sp, s, stream, dev)
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (norb * norb * M * R))))
+        ss = synth.graphene_sheet(cells, cells, w["sigma"], w["seed"])
+        rs = synth.random_phase(norb * ss.n, R, w["seed"] + synth.VECTOR_SEED_OFFSET)
+        t0 = time.perf_counter()
+        vs = synth.SK_V + (synth.SK_D if norb == 9 else ())
+        csr, _ = O.sk_hamiltonian(ss.pos, ss.box, ss.periodic, vs, synth.SK_ES, synth.SK_EP, e_d=synth.SK_ED,
+                                  r_cut=r_cut, r0=synth.R0, beta=synth.BETA)
+        lo, hi = O.gershgorin(csr)
+        sa, sb = 1.01 * (hi - lo) / 2, (hi + lo) / 2
+        mo, _ = O.kpm_moments(csr, sa, sb, rs, M)
+        O.kpm_dos(mo.mean(0), sa, sb, synth.energy_grid(sa, sb))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": norb * ss.n * M * R / dt, "unit": "orbital*moments/s", "cores": 1,
+                               "kind": "oracle", "seconds": dt,
+                               "sample": f"{cells}x{cells}-cell sheet, {norb * ss.n} orbitals, M={M}, R={R}: "
+                                         "full path"}
+    print(json.dumps(out), flush=True)
+
+
+def sk_block_variants(args, w, out, build, pick_shape, Hs, aa, bb, r, M, R, Rp, diag, cfg, mu, mu_c, rho_c, E, ev,
+                      work, nr, norb, dint, pos, sp, s, stream, dev):
+    """Stored-block workloads: the scalar SELL expansion, the doubling form and the learned
+    assembly, each timed beside the block form."""
+    import torch
+    from paper_2509_06525_amd import synth, tbkpm
     # the same Hamiltonian as a scalar SELL matrix (3 norb columns and values per orbital row)
     Hsc = build("sell_f32", 64)
     cfg_s, _, _ = pick_shape(Hsc, aa, bb)
@@ -457,24 +507,6 @@ def bench_sk(args, w):
         "plain_build_ms_median": float(np.median(times["plain"])), "kpm_ms": ev[0].elapsed_time(ev[1]),
         "a_eV": la, "b_eV": lb}
     del Hl
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        cells = args.cpu_sample_cells or max(8, int(math.sqrt(1.5e9 / (norb * norb * M * R))))
-        ss = synth.graphene_sheet(cells, cells, w["sigma"], w["seed"])
-        rs = synth.random_phase(norb * ss.n, R, w["seed"] + synth.VECTOR_SEED_OFFSET)
-        t0 = time.perf_counter()
-        vs = synth.SK_V + (synth.SK_D if norb == 9 else ())
-        csr, _ = O.sk_hamiltonian(ss.pos, ss.box, ss.periodic, vs, synth.SK_ES, synth.SK_EP, e_d=synth.SK_ED)
-        lo, hi = O.gershgorin(csr)
-        sa, sb = 1.01 * (hi - lo) / 2, (hi + lo) / 2
-        mo, _ = O.kpm_moments(csr, sa, sb, rs, M)
-        O.kpm_dos(mo.mean(0), sa, sb, synth.energy_grid(sa, sb))
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": norb * ss.n * M * R / dt, "unit": "orbital*moments/s", "cores": 1,
-                               "kind": "oracle", "seconds": dt,
-                               "sample": f"{cells}x{cells}-cell sheet, {norb * ss.n} orbitals, M={M}, R={R}: "
-                                         "full path"}
-    print(json.dumps(out), flush=True)
 
 
 def bench_vac(args, w):

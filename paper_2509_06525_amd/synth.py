@@ -160,6 +160,10 @@ WORKLOADS = {
     # s, p, d Slater-Koster orbital Hamiltonian (9 orbitals per atom: 9,000,000 rows)
     "graphene_spd_thermal_1M": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=16,
                                     fmt="bsell4_f32", precision="c32", seed=1007, sk=True, orbitals=9),
+    # s, p, d model with a third-neighbour cutoff on 100 M atoms (900 M orbital rows), the size of
+    # the paper's largest DOS; bonds stored as displacements, blocks formed in the recurrence
+    "graphene_spd_3nn_100M": dict(kind="sheet", nx=5000, ny=5000, sigma=0.05, M=1000, R=1,
+                                  fmt="bgeom_f32", precision="c32", seed=1008, sk=True, orbitals=9, r_cut=3.0),
     # velocity autocorrelation: 200 propagation steps of 0.1 fs (20 fs of correlation time)
     "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
                                     fmt="sell_f32", precision="c32", seed=1005, vac=True,
