@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
     const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
     const int64_t smask = ((int64_t)1 << a.log2_slice) - 1;
     const int64_t stride = smask + 1;
-    const int Rp = a.Rp;
+    constexpr int Rp = L * VPT;       // padded vector count (a.Rp)
     const int voff = vs * VPT;
     const int64_t last = a.n_rows / NORB - 1;     // last atom row
 
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
     const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
     const int64_t smask = ((int64_t)1 << a.log2_slice) - 1;
     const int64_t stride = smask + 1;
-    const int Rp = a.Rp;
+    constexpr int Rp = L * VPT;       // padded vector count (a.Rp)
     const int voff = vs * VPT;
     const int64_t last = a.n_rows / NORB - 1;     // last atom row
 
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
 #pragma unroll
             for (int l = 0; l < 10; ++l) vf[l] = gp.v[l] * f;
             VT B[NORB][NORB];
-            sk_table<VT, NORB>(vf, vf, dx * inv, dy * inv, dz * inv, B);
+            sk_table<VT, NORB, true>(vf, vf, dx * inv, dy * inv, dz * inv, B);
 #pragma unroll
             for (int o = 0; o < NORB; ++o)
 #pragma unroll

@@ -42,8 +42,9 @@ __device__ __forceinline__ void sk_sd_pd(const T *v, T l, T m, T n, T (&sdr)[5],
 // side (and the equal-l blocks) come from the integrals vu of the ordered
 // species pair (row, column), the others from the reversed pair's vl by
 // E[b][a] = (-1)^(l_a + l_b) E'[a][b] (E' formed with vl; vl = vu for one
-// species).  Only the first NORB rows and columns are formed.
-template <class T, int NORB>
+// species).  Only the first NORB rows and columns are formed.  SAME: vl is
+// vu (one species), so the s-d and p-d pieces are formed once.
+template <class T, int NORB, bool SAME = false>
 __device__ __forceinline__ void sk_table(const T *vu, const T *vl, T l, T m, T n, T (&E)[NORB][NORB]) {
     const T *v = vu;
     const T s3 = T(1.7320508075688772);
@@ -60,7 +61,14 @@ __device__ __forceinline__ void sk_table(const T *vu, const T *vl, T l, T m, T n
         const T q = n2 - T(0.5) * (l2 + m2), dlm = l2 - m2;
         T sdr[5], pd[3][5], sdl[5], pdl[3][5];
         sk_sd_pd<T>(vu, l, m, n, sdr, pd);
-        sk_sd_pd<T>(vl, l, m, n, sdl, pdl);
+        if constexpr (SAME) {
+            for (int a = 0; a < 5; ++a) {
+                sdl[a] = sdr[a];
+                for (int b = 0; b < 3; ++b) pdl[b][a] = pd[b][a];
+            }
+        } else {
+            sk_sd_pd<T>(vl, l, m, n, sdl, pdl);
+        }
         T dd[5][5];
         dd[0][0] = T(3.0) * l2 * m2 * dds + (l2 + m2 - T(4.0) * l2 * m2) * ddp + (n2 + l2 * m2) * ddd;
         dd[1][1] = T(3.0) * m2 * n2 * dds + (m2 + n2 - T(4.0) * m2 * n2) * ddp + (l2 + m2 * n2) * ddd;
