@@ -143,8 +143,7 @@ def lib():
     if _LIB is not None:
         return _LIB
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2509_06525_amd/build.py "
-                           "(or __graft_entry__.build()) first")
+        raise RuntimeError(f"{LIB_PATH} is not built; run python paper_2509_06525_amd/build.py first")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.tbk_last_error.restype = ctypes.c_char_p
