@@ -536,21 +536,31 @@ def bench_vac(args, w):
     log(f"generating {args.workload}")
     frames = synth.make_frames(args.workload) if F > 1 else [synth.make_structure(args.workload)]
     s = frames[0]
+    sk = bool(w.get("sk"))
+    norb = w.get("orbitals", 4) if sk else 1
     N = s.n
+    nr = norb * N                                      # orbital rows
     pos = [torch.from_numpy(fr.pos).to(dev) for fr in frames]
     sp = torch.from_numpy(s.species).to(dev)
-    r = torch.from_numpy(synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
+    r = torch.from_numpy(synth.random_phase(nr, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
     held = []
     slice_, config, config_dos = args.slice, None, None
-    if not args.no_tune:
+    if not args.no_tune and not sk:
         if not args.retune:
             use_shipped_tuning()
         tune = tbkpm.autotune(pos[0], sp, s.box, s.periodic, s.onsite, s.t_pair, R, "c32", r_cut=synth.R_HOP,
                               r0=synth.R0, beta=synth.BETA, stream=stream)
         slice_, config = tune.slice, tune.config
         log(f"tuned: slice {slice_} {config.as_dict()}")
+    if sk:
+        slice_ = 64                                    # atom slices; the default launch shape (atom form)
 
     def build(f):
+        if sk:
+            return tbkpm.build_hamiltonian_sk(pos[f], sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP,
+                                              r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, fmt=w["fmt"],
+                                              slice=slice_, stream=stream, d=synth.SK_D if norb == 9 else None,
+                                              e_d=synth.SK_ED)
         H = tbkpm.build_hamiltonian(pos[f], sp, s.box, s.periodic, s.onsite, s.t_pair, r_cut=synth.R_HOP,
                                     r0=synth.R0, beta=synth.BETA, fmt=w["fmt"], slice=slice_, stream=stream,
                                     into=held.pop() if held else None)
@@ -605,25 +615,30 @@ def bench_vac(args, w):
     Rp = 1
     while Rp < R:
         Rp *= 2
-    hb = st.n_entries * 8 + st.n_ptr * 8                # values + columns (4 + 4 B), slice offsets
-    rec = hb + N * Rp * 8 * 4                           # recurrence launch (pair form: left vector for r)
-    prop = hb + N * Rp * 8 * 5                          # propagator term: T_k gather, T_{k-1}, T_{k+1}, acc r/w
-    vel = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 2
+    per_val = norb * norb if sk else 1
+    hb = st.n_entries * (4 * per_val + 4) + st.n_ptr * 8    # values (FP32) + columns, slice offsets
+    rec = hb + nr * Rp * 8 * 4                          # recurrence launch (pair form: left vector for r)
+    prop = hb + nr * Rp * 8 * 5                         # propagator term: T_k gather, T_{k-1}, T_{k+1}, acc r/w
+    vel = hb + nr * Rp * 8 * 2
     per_t = (M - 1) * rec + 2 * (n_cheb - 1) * prop + vel
     total = F * n_t * per_t
     achieved = total / sec / 1e9
     out = {
-        "metric": "VAC atom*moments*timesteps/s", "value": F * N * M * R * n_t / sec,
-        "unit": "atom*moments*timesteps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": "VAC atom*moments*timesteps/s" if not sk else "VAC orbital*moments*timesteps/s",
+        "value": F * nr * M * R * n_t / sec,
+        "unit": "atom*moments*timesteps/s" if not sk else "orbital*moments*timesteps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "n_atoms": N, "frames": F, "moments": M, "vectors": R,
+        "config": {"workload": args.workload, "n_atoms": N, "orbital_rows": nr, "frames": F, "moments": M,
+                   "vectors": R,
                    "time_steps": n_t, "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"],
                    "slice": slice_, "precision": "c32", "a_eV": a, "b_eV": b,
                    "launch": None if config is None else config.as_dict()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "whole VAC step (k_cheb_step pair form, k_evolve_term, k_apply_velocity)",
+                     "kernel": "whole VAC step (k_cheb_step_atom pair form, k_evolve_term_blk, "
+                               "k_apply_velocity_blk)" if sk else
+                               "whole VAC step (k_cheb_step pair form, k_evolve_term, k_apply_velocity)",
                      "bytes_per_step": total},
         "sigma_max": float(sig[-1].abs().max()),
     }

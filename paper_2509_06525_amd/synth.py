@@ -168,6 +168,10 @@ WORKLOADS = {
     "graphene_thermal_1M_vac": dict(kind="sheet", nx=500, ny=500, sigma=0.05, M=1000, R=1,
                                     fmt="sell_f32", precision="c32", seed=1005, vac=True,
                                     n_t=200, dt=0.1),
+    # velocity autocorrelation on the s, p block Hamiltonian (100,800 atoms, 403,200 orbital rows)
+    "graphene_sp3_thermal_100k_vac": dict(kind="sheet", nx=160, ny=158, sigma=0.05, M=1000, R=1,
+                                          fmt="bsell4_f32", precision="c32", seed=1009, vac=True, sk=True,
+                                          orbitals=4, n_t=200, dt=0.1),
     # four thermal frames of a 1 M-atom sheet (seeds 1010..1013): VAC conductivity and integrated
     # DOS of each frame, frame average, carriers and mobility
     "graphene_mobility_frames_1M": dict(kind="frames", frames=4, nx=500, ny=500, sigma=0.05, M=1000, R=1,
