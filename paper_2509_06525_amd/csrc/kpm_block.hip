@@ -14,10 +14,11 @@
 // rows of the neighbour's T_n, which are contiguous.  Against the scalar
 // expansion of the same matrix (NORB columns and NORB values per neighbour and
 // orbital row) this reads 1/NORB of the column bytes and column loads.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kpm.hpp"
 #include "kpm_dev.hpp"
-#include "sk_table.hpp"
 
 namespace tbk {
 namespace {
@@ -262,13 +263,65 @@ template <class VT> struct GeomParams {
     VT beta;         // decay exponent
 };
 
+// y += B x for the one-species Slater-Koster block B of a bond with direction
+// cosines c = (l, m, n) and integrals v (already scaled by f(r)), without
+// forming B: with u the d-orbital sigma vector along c (the s-d row of the table
+// divided by V_sd_sigma) and J = du/dc (u is homogeneous of degree 2, so
+// c.grad u_b = 2 u_b), the table's blocks are
+//   p-p: V_pp_pi I + (V_pp_sigma - V_pp_pi) c c^T,
+//   p-d: V_pd_sigma c u^T + V_pd_pi (J^T - 2 c u^T) / sqrt(3)    (d-p: minus its transpose),
+//   d-d: V_dd_delta I + (V_dd_sigma - V_dd_delta) u u^T + (V_dd_pi - V_dd_delta) J (I - c c^T) J^T / 3,
+// so one bond costs about 76 multiply-adds per vector component instead of the
+// NORB^2 products plus the table.
+template <class VT, int NORB>
+__device__ __forceinline__ void sk_apply(const VT (&v)[10], VT l, VT m, VT n, const VT (&x)[NORB], VT (&y)[NORB]) {
+    const VT ss = v[0], sp = v[1], pps = v[2], ppp = v[3];
+    const VT xs = x[0], xp0 = x[1], xp1 = x[2], xp2 = x[3];
+    const VT cp = l * xp0 + m * xp1 + n * xp2;
+    if constexpr (NORB == 4) {
+        y[0] += ss * xs + sp * cp;
+        const VT t = (pps - ppp) * cp - sp * xs;
+        y[1] += ppp * xp0 + l * t;
+        y[2] += ppp * xp1 + m * t;
+        y[3] += ppp * xp2 + n * t;
+    } else {
+        const VT s3 = (VT)1.7320508075688772;
+        const VT sd = v[4], pds = v[5], pdp = v[6], dds = v[7], ddp = v[8], ddd = v[9];
+        const VT u0 = s3 * l * m, u1 = s3 * m * n, u2 = s3 * n * l;
+        const VT u3 = (VT)0.5 * s3 * (l * l - m * m), u4 = n * n - (VT)0.5 * (l * l + m * m);
+        const VT xd0 = x[4], xd1 = x[5], xd2 = x[6], xd3 = x[7], xd4 = x[8];
+        const VT ud = u0 * xd0 + u1 * xd1 + u2 * xd2 + u3 * xd3 + u4 * xd4;
+        // G = J^T x_d
+        const VT gl = s3 * (m * xd0 + n * xd2 + l * xd3) - l * xd4;
+        const VT gm = s3 * (l * xd0 + n * xd1 - m * xd3) - m * xd4;
+        const VT gn = s3 * (m * xd1 + l * xd2) + (VT)2 * n * xd4;
+        const VT ud2 = (VT)2 * ud;
+        const VT pl = gl - ud2 * l, pm = gm - ud2 * m, pn = gn - ud2 * n;      // (I - c c^T) G
+        const VT k1 = pdp / s3, k2 = (ddp - ddd) / (VT)3;
+        y[0] += ss * xs + sp * cp + sd * ud;
+        const VT t = (pps - ppp) * cp + pds * ud - sp * xs;
+        y[1] += ppp * xp0 + l * t + k1 * pl;
+        y[2] += ppp * xp1 + m * t + k1 * pm;
+        y[3] += ppp * xp2 + n * t + k1 * pn;
+        // h = -k1 (x_p - c cp) + k2 (I - c c^T) G, then J h
+        const VT hl = k2 * pl - k1 * (xp0 - l * cp);
+        const VT hm = k2 * pm - k1 * (xp1 - m * cp);
+        const VT hn = k2 * pn - k1 * (xp2 - n * cp);
+        const VT w = sd * xs - pds * cp + (dds - ddd) * ud;
+        y[4] += ddd * xd0 + u0 * w + s3 * (m * hl + l * hm);
+        y[5] += ddd * xd1 + u1 * w + s3 * (n * hm + m * hn);
+        y[6] += ddd * xd2 + u2 * w + s3 * (n * hl + l * hn);
+        y[7] += ddd * xd3 + u3 * w + s3 * (l * hl - m * hm);
+        y[8] += ddd * xd4 + u4 * w + ((VT)2 * n * hn - l * hl - m * hm);
+    }
+}
+
 // Displacement form (TBK_BGEOM_*): as the atom form, but each bond stores its
 // displacement d = x_j - x_i (3 values) instead of its block.  The block is
-// formed in registers: r = |d|, direction cosines d / r, integrals scaled by
-// f(r) = exp(-beta (r / r0 - 1)), then the Slater-Koster table in the vector
-// type.  Padding slots (d = 0) are skipped.  Per bond this reads 12 B (float)
-// instead of 4 NORB^2 B and spends about 2 NORB^2 + 150 flops forming the
-// block, which the HBM-bound step has to spare.
+// applied without being formed: r = |d|, direction cosines d / r, integrals
+// scaled by f(r) = exp(-beta (r / r0 - 1)), then sk_apply in the vector type.
+// Padding slots (d = 0) are skipped.  Per bond this reads 12 B (float) instead
+// of 4 NORB^2 B.
 template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ geo,
@@ -321,53 +374,133 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
             VT vf[10];
 #pragma unroll
             for (int l = 0; l < 10; ++l) vf[l] = gp.v[l] * f;
-            VT B[NORB][NORB];
-            sk_table<VT, NORB, true>(vf, vf, dx * inv, dy * inv, dz * inv, B);
-#pragma unroll
-            for (int o = 0; o < NORB; ++o)
-#pragma unroll
-                for (int b = 0; b < NORB; ++b)
-#pragma unroll
-                    for (int q = 0; q < VPT; ++q) {
-                        y[o].re[q] += B[o][b] * x[b].re[q];
-                        y[o].im[q] += B[o][b] * x[b].im[q];
-                    }
-        }
-#pragma unroll
-        for (int o = 0; o < NORB; ++o) {
-            const int64_t i = (int64_t)NORB * at + o;
-            const int64_t off = 2 * (i * Rp + voff);
-            Pack<VT, VPT> pv, rv;
-            if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(tprev + off);
-            if constexpr (DBL) rv = load_pack<false, VT, VPT>(tcur + off);
-            else rv = load_pack<NT, VT, VPT>(r + off);
-            if constexpr (DIAG) {
-                const VT dg = (onsite ? ld<NT>(onsite + i) : (VT)0) - a.shift;
-                const Pack<VT, VPT> xs = DBL ? rv : load_pack<false, VT, VPT>(tcur + off);
-#pragma unroll
-                for (int q = 0; q < VPT; ++q) { y[o].re[q] += dg * xs.re[q]; y[o].im[q] += dg * xs.im[q]; }
-            }
-            Pack<VT, VPT> ov;
+            const VT cl = dx * inv, cm = dy * inv, cn = dz * inv;
 #pragma unroll
             for (int q = 0; q < VPT; ++q) {
-                if constexpr (FIRST) {
-                    ov.re[q] = a.c1 * y[o].re[q];
-                    ov.im[q] = a.c1 * y[o].im[q];
-                } else {
-                    ov.re[q] = a.c1 * y[o].re[q] - pv.re[q];
-                    ov.im[q] = a.c1 * y[o].im[q] - pv.im[q];
+                VT xr[NORB], xi[NORB], yr[NORB], yi[NORB];
+#pragma unroll
+                for (int b = 0; b < NORB; ++b) {
+                    xr[b] = x[b].re[q];
+                    xi[b] = x[b].im[q];
+                    yr[b] = y[b].re[q];
+                    yi[b] = y[b].im[q];
+                }
+                sk_apply<VT, NORB>(vf, cl, cm, cn, xr, yr);
+                sk_apply<VT, NORB>(vf, cl, cm, cn, xi, yi);
+#pragma unroll
+                for (int b = 0; b < NORB; ++b) {
+                    y[b].re[q] = yr[b];
+                    y[b].im[q] = yi[b];
                 }
             }
-            if (ok) {
-                store_pack<NT, VT, VPT>(tnext + off, ov);
+        }
+        if constexpr (L == 1 && VPT == 1) {
+            // one vector: the tile's rows are one contiguous range; staging its inputs and
+            // outputs through LDS turns each thread's NORB rows at a stride of NORB into
+            // coalesced accesses of the whole range (direct row stores write every line
+            // several times in part)
+            typedef std::conditional_t<sizeof(VT) == 4, f2v, d2v> C2;
+            __shared__ C2 sbuf[NORB * kThreads];
+            VT *sv = reinterpret_cast<VT *>(sbuf);
+            const int64_t row0 = (int64_t)NORB * (t * APB);
+            const int nrow = (int)min((int64_t)NORB * APB, a.n_rows - row0);
+            const int mine = NORB * la;
+            VT dg[NORB];
+            C2 pv[NORB], rv[NORB];
+            if constexpr (DIAG) {
+                for (int e = threadIdx.x; e < nrow; e += kThreads) sv[e] = onsite ? ld<NT>(onsite + row0 + e) : (VT)0;
+                __syncthreads();
+#pragma unroll
+                for (int o = 0; o < NORB; ++o) dg[o] = sv[mine + o] - a.shift;
+                __syncthreads();
+            }
+            if constexpr (!FIRST) {
+                const C2 *g = reinterpret_cast<const C2 *>(tprev) + row0;
+                for (int e = threadIdx.x; e < nrow; e += kThreads) sbuf[e] = ld<NT>(g + e);
+                __syncthreads();
+#pragma unroll
+                for (int o = 0; o < NORB; ++o) pv[o] = sbuf[mine + o];
+                __syncthreads();
+            }
+            {
+                const C2 *g = reinterpret_cast<const C2 *>(DBL ? tcur : r) + row0;
+                for (int e = threadIdx.x; e < nrow; e += kThreads) sbuf[e] = DBL ? g[e] : ld<NT>(g + e);
+                __syncthreads();
+#pragma unroll
+                for (int o = 0; o < NORB; ++o) rv[o] = sbuf[mine + o];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int o = 0; o < NORB; ++o) {
+                VT yr = y[o].re[0], yi = y[o].im[0];
+                if constexpr (DIAG) {
+                    C2 xs = rv[o];
+                    if constexpr (!DBL) xs = reinterpret_cast<const C2 *>(tcur)[(int64_t)NORB * at + o];
+                    yr += dg[o] * xs.x;
+                    yi += dg[o] * xs.y;
+                }
+                C2 ov;
+                if constexpr (FIRST) {
+                    ov.x = a.c1 * yr;
+                    ov.y = a.c1 * yi;
+                } else {
+                    ov.x = a.c1 * yr - pv[o].x;
+                    ov.y = a.c1 * yi - pv[o].y;
+                }
+                if (ok) {
+                    const double cr = (double)rv[o].x * (double)ov.x + (double)rv[o].y * (double)ov.y;
+                    if constexpr (DBL) {
+                        acc[0] += (double)ov.x * (double)ov.x + (double)ov.y * (double)ov.y;
+                        acc[1] += cr;
+                    } else {
+                        acc[0] += cr;
+                    }
+                }
+                sbuf[mine + o] = ov;
+            }
+            __syncthreads();
+            {
+                C2 *g = reinterpret_cast<C2 *>(tnext) + row0;
+                for (int e = threadIdx.x; e < nrow; e += kThreads) st<NT>(g + e, sbuf[e]);
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int o = 0; o < NORB; ++o) {
+                const int64_t i = (int64_t)NORB * at + o;
+                const int64_t off = 2 * (i * Rp + voff);
+                Pack<VT, VPT> pv, rv;
+                if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(tprev + off);
+                if constexpr (DBL) rv = load_pack<false, VT, VPT>(tcur + off);
+                else rv = load_pack<NT, VT, VPT>(r + off);
+                if constexpr (DIAG) {
+                    const VT dg = (onsite ? ld<NT>(onsite + i) : (VT)0) - a.shift;
+                    const Pack<VT, VPT> xs = DBL ? rv : load_pack<false, VT, VPT>(tcur + off);
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) { y[o].re[q] += dg * xs.re[q]; y[o].im[q] += dg * xs.im[q]; }
+                }
+                Pack<VT, VPT> ov;
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
-                    const double cr = (double)rv.re[q] * (double)ov.re[q] + (double)rv.im[q] * (double)ov.im[q];
-                    if constexpr (DBL) {
-                        acc[q] += (double)ov.re[q] * (double)ov.re[q] + (double)ov.im[q] * (double)ov.im[q];
-                        acc[VPT + q] += cr;
+                    if constexpr (FIRST) {
+                        ov.re[q] = a.c1 * y[o].re[q];
+                        ov.im[q] = a.c1 * y[o].im[q];
                     } else {
-                        acc[q] += cr;
+                        ov.re[q] = a.c1 * y[o].re[q] - pv.re[q];
+                        ov.im[q] = a.c1 * y[o].im[q] - pv.im[q];
+                    }
+                }
+                if (ok) {
+                    store_pack<NT, VT, VPT>(tnext + off, ov);
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) {
+                        const double cr = (double)rv.re[q] * (double)ov.re[q] + (double)rv.im[q] * (double)ov.im[q];
+                        if constexpr (DBL) {
+                            acc[q] += (double)ov.re[q] * (double)ov.re[q] + (double)ov.im[q] * (double)ov.im[q];
+                            acc[VPT + q] += cr;
+                        } else {
+                            acc[q] += cr;
+                        }
                     }
                 }
             }

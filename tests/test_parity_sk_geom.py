@@ -75,7 +75,8 @@ def test_displacements_and_pattern(norb):
 
 
 @pytest.mark.parametrize("norb,R,tpb,nt,xr,dbl", [(4, 1, 1, 1, 0, 0), (4, 3, 2, 0, 1, 0), (9, 1, 2, 1, 0, 0),
-                                                  (9, 4, 1, 1, 1, 1), (9, 16, 2, 1, 0, 0)])
+                                                  (9, 4, 1, 1, 1, 1), (9, 16, 2, 1, 0, 0), (9, 1, 1, 1, 0, 1),
+                                                  (4, 1, 3, 0, 1, 1)])
 def test_geom_fp64_moments(norb, R, tpb, nt, xr, dbl):
     s = synth.graphene_sheet(9, 7, 0.06, 4)
     csr = oracle_csr(s, norb)
