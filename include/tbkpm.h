@@ -214,7 +214,10 @@ typedef struct {
     int32_t rows_per_thread;    /* 1, 2 or 4: rows (from consecutive tiles) a
                                    thread advances together; 4 takes effect with
                                    one vector per thread row on width-3 slices and
-                                   runs as 2 elsewhere                             */
+                                   runs as 2 elsewhere.  Block Hamiltonians with one
+                                   vector (atom form, displacement form): staging of
+                                   each tile's rows through LDS, 1 = when the launch
+                                   has >= 2048 tiles, 2 = always, 4 = never        */
     int32_t persistent;         /* kpm_moments_batched only: 1 = all steps in one
                                    cooperative launch (a team of workgroups per
                                    structure, barrier per step); 0 = one launch

@@ -151,6 +151,89 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_blk(
     block_reduce_store<L, NA>(acc, partial, lb);
 }
 
+// Tiles from which the one-vector block kernels stage their rows by default
+// (about eight workgroups per CU; fewer leave the barriers exposed).
+constexpr int64_t kStageMinTiles = 2048;
+
+// Last part of a one-vector step for the NORB rows of each atom of a tile
+// (the thread's atom la, clamped atom row at): the tile's rows are one
+// contiguous range, so T_{n-1}, r (T_n with the doubling identities) and the
+// onsite energies are loaded, and T_{n+1} stored, through LDS as whole ranges;
+// direct row accesses at a stride of NORB write every cache line several times
+// in part.  y holds sum_q H_iq T_n(q) of the thread's rows.
+template <class VT, int NORB, bool FIRST, bool DIAG, bool NT, bool DBL>
+__device__ __forceinline__ void finish_rows_staged(const Pack<VT, 1> (&y)[NORB], const StepScalars<VT> &a, int64_t t,
+                                                   int la, int64_t at, bool ok, const VT *__restrict__ onsite,
+                                                   const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
+                                                   const VT *__restrict__ r, double (&acc)[DBL ? 2 : 1]) {
+    constexpr int APB = kThreads;
+    typedef std::conditional_t<sizeof(VT) == 4, f2v, d2v> C2;
+    __shared__ C2 sbuf[NORB * kThreads];
+    VT *sv = reinterpret_cast<VT *>(sbuf);
+    const int64_t row0 = (int64_t)NORB * (t * APB);
+    const int nrow = (int)min((int64_t)NORB * APB, a.n_rows - row0);
+    const int mine = NORB * la;
+    VT dg[NORB];
+    C2 pv[NORB], rv[NORB];
+    if constexpr (DIAG) {
+        for (int e = threadIdx.x; e < nrow; e += kThreads) sv[e] = onsite ? ld<NT>(onsite + row0 + e) : (VT)0;
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < NORB; ++o) dg[o] = sv[mine + o] - a.shift;
+        __syncthreads();
+    }
+    if constexpr (!FIRST) {
+        const C2 *g = reinterpret_cast<const C2 *>(tprev) + row0;
+        for (int e = threadIdx.x; e < nrow; e += kThreads) sbuf[e] = ld<NT>(g + e);
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < NORB; ++o) pv[o] = sbuf[mine + o];
+        __syncthreads();
+    }
+    {
+        const C2 *g = reinterpret_cast<const C2 *>(DBL ? tcur : r) + row0;
+        for (int e = threadIdx.x; e < nrow; e += kThreads) sbuf[e] = DBL ? g[e] : ld<NT>(g + e);
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < NORB; ++o) rv[o] = sbuf[mine + o];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = 0; o < NORB; ++o) {
+        VT yr = y[o].re[0], yi = y[o].im[0];
+        if constexpr (DIAG) {
+            C2 xs = rv[o];
+            if constexpr (!DBL) xs = reinterpret_cast<const C2 *>(tcur)[(int64_t)NORB * at + o];
+            yr += dg[o] * xs.x;
+            yi += dg[o] * xs.y;
+        }
+        C2 ov;
+        if constexpr (FIRST) {
+            ov.x = a.c1 * yr;
+            ov.y = a.c1 * yi;
+        } else {
+            ov.x = a.c1 * yr - pv[o].x;
+            ov.y = a.c1 * yi - pv[o].y;
+        }
+        if (ok) {
+            const double cr = (double)rv[o].x * (double)ov.x + (double)rv[o].y * (double)ov.y;
+            if constexpr (DBL) {
+                acc[0] += (double)ov.x * (double)ov.x + (double)ov.y * (double)ov.y;
+                acc[1] += cr;
+            } else {
+                acc[0] += cr;
+            }
+        }
+        sbuf[mine + o] = ov;
+    }
+    __syncthreads();
+    {
+        C2 *g = reinterpret_cast<C2 *>(tnext) + row0;
+        for (int e = threadIdx.x; e < nrow; e += kThreads) st<NT>(g + e, sbuf[e]);
+    }
+    __syncthreads();
+}
+
 // Atom form: a thread owns every orbital row of one atom (VPT vectors), so
 // each neighbour's NORB orbital rows of T_n are gathered once per atom instead
 // of once per orbital row; the block's rows are read one after the other
@@ -160,7 +243,7 @@ template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bo
 __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ bval,
     const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
-    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a) {
+    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a, int stage) {
     constexpr int APB = kThreads / L;   // atoms per tile
     const int la = threadIdx.x / L;
     const int vs = threadIdx.x % L;
@@ -213,41 +296,51 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
                     }
             }
         }
-#pragma unroll
-        for (int o = 0; o < NORB; ++o) {
-            const int64_t i = (int64_t)NORB * at + o;
-            const int64_t off = 2 * (i * Rp + voff);
-            Pack<VT, VPT> pv, rv;
-            if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(tprev + off);
-            if constexpr (DBL) rv = load_pack<false, VT, VPT>(tcur + off);
-            else rv = load_pack<NT, VT, VPT>(r + off);
-            if constexpr (DIAG) {
-                const VT dg = (onsite ? ld<NT>(onsite + i) : (VT)0) - a.shift;
-                const Pack<VT, VPT> xs = DBL ? rv : load_pack<false, VT, VPT>(tcur + off);
-#pragma unroll
-                for (int q = 0; q < VPT; ++q) { y[o].re[q] += dg * xs.re[q]; y[o].im[q] += dg * xs.im[q]; }
+        bool staged = false;
+        if constexpr (L == 1 && VPT == 1) {
+            if (stage) {
+                finish_rows_staged<VT, NORB, FIRST, DIAG, NT, DBL>(y, a, t, la, at, ok, onsite, tcur, tprev, tnext,
+                                                                  r, acc);
+                staged = true;
             }
-            Pack<VT, VPT> ov;
+        }
+        if (!staged) {
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) {
-                if constexpr (FIRST) {
-                    ov.re[q] = a.c1 * y[o].re[q];
-                    ov.im[q] = a.c1 * y[o].im[q];
-                } else {
-                    ov.re[q] = a.c1 * y[o].re[q] - pv.re[q];
-                    ov.im[q] = a.c1 * y[o].im[q] - pv.im[q];
+            for (int o = 0; o < NORB; ++o) {
+                const int64_t i = (int64_t)NORB * at + o;
+                const int64_t off = 2 * (i * Rp + voff);
+                Pack<VT, VPT> pv, rv;
+                if constexpr (!FIRST) pv = load_pack<NT, VT, VPT>(tprev + off);
+                if constexpr (DBL) rv = load_pack<false, VT, VPT>(tcur + off);
+                else rv = load_pack<NT, VT, VPT>(r + off);
+                if constexpr (DIAG) {
+                    const VT dg = (onsite ? ld<NT>(onsite + i) : (VT)0) - a.shift;
+                    const Pack<VT, VPT> xs = DBL ? rv : load_pack<false, VT, VPT>(tcur + off);
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) { y[o].re[q] += dg * xs.re[q]; y[o].im[q] += dg * xs.im[q]; }
                 }
-            }
-            if (ok) {
-                store_pack<NT, VT, VPT>(tnext + off, ov);
+                Pack<VT, VPT> ov;
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
-                    const double cr = (double)rv.re[q] * (double)ov.re[q] + (double)rv.im[q] * (double)ov.im[q];
-                    if constexpr (DBL) {
-                        acc[q] += (double)ov.re[q] * (double)ov.re[q] + (double)ov.im[q] * (double)ov.im[q];
-                        acc[VPT + q] += cr;
+                    if constexpr (FIRST) {
+                        ov.re[q] = a.c1 * y[o].re[q];
+                        ov.im[q] = a.c1 * y[o].im[q];
                     } else {
-                        acc[q] += cr;
+                        ov.re[q] = a.c1 * y[o].re[q] - pv.re[q];
+                        ov.im[q] = a.c1 * y[o].im[q] - pv.im[q];
+                    }
+                }
+                if (ok) {
+                    store_pack<NT, VT, VPT>(tnext + off, ov);
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) {
+                        const double cr = (double)rv.re[q] * (double)ov.re[q] + (double)rv.im[q] * (double)ov.im[q];
+                        if constexpr (DBL) {
+                            acc[q] += (double)ov.re[q] * (double)ov.re[q] + (double)ov.im[q] * (double)ov.im[q];
+                            acc[VPT + q] += cr;
+                        } else {
+                            acc[q] += cr;
+                        }
                     }
                 }
             }
@@ -326,7 +419,7 @@ template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bo
 __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ geo,
     const VT *__restrict__ onsite, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
-    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a, GeomParams<VT> gp) {
+    const VT *__restrict__ r, double *__restrict__ partial, StepScalars<VT> a, GeomParams<VT> gp, int stage) {
     constexpr int APB = kThreads / L;   // atoms per tile
     const int la = threadIdx.x / L;
     const int vs = threadIdx.x % L;
@@ -394,77 +487,15 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
                 }
             }
         }
+        bool staged = false;
         if constexpr (L == 1 && VPT == 1) {
-            // one vector: the tile's rows are one contiguous range; staging its inputs and
-            // outputs through LDS turns each thread's NORB rows at a stride of NORB into
-            // coalesced accesses of the whole range (direct row stores write every line
-            // several times in part)
-            typedef std::conditional_t<sizeof(VT) == 4, f2v, d2v> C2;
-            __shared__ C2 sbuf[NORB * kThreads];
-            VT *sv = reinterpret_cast<VT *>(sbuf);
-            const int64_t row0 = (int64_t)NORB * (t * APB);
-            const int nrow = (int)min((int64_t)NORB * APB, a.n_rows - row0);
-            const int mine = NORB * la;
-            VT dg[NORB];
-            C2 pv[NORB], rv[NORB];
-            if constexpr (DIAG) {
-                for (int e = threadIdx.x; e < nrow; e += kThreads) sv[e] = onsite ? ld<NT>(onsite + row0 + e) : (VT)0;
-                __syncthreads();
-#pragma unroll
-                for (int o = 0; o < NORB; ++o) dg[o] = sv[mine + o] - a.shift;
-                __syncthreads();
+            if (stage) {
+                finish_rows_staged<VT, NORB, FIRST, DIAG, NT, DBL>(y, a, t, la, at, ok, onsite, tcur, tprev, tnext,
+                                                                  r, acc);
+                staged = true;
             }
-            if constexpr (!FIRST) {
-                const C2 *g = reinterpret_cast<const C2 *>(tprev) + row0;
-                for (int e = threadIdx.x; e < nrow; e += kThreads) sbuf[e] = ld<NT>(g + e);
-                __syncthreads();
-#pragma unroll
-                for (int o = 0; o < NORB; ++o) pv[o] = sbuf[mine + o];
-                __syncthreads();
-            }
-            {
-                const C2 *g = reinterpret_cast<const C2 *>(DBL ? tcur : r) + row0;
-                for (int e = threadIdx.x; e < nrow; e += kThreads) sbuf[e] = DBL ? g[e] : ld<NT>(g + e);
-                __syncthreads();
-#pragma unroll
-                for (int o = 0; o < NORB; ++o) rv[o] = sbuf[mine + o];
-                __syncthreads();
-            }
-#pragma unroll
-            for (int o = 0; o < NORB; ++o) {
-                VT yr = y[o].re[0], yi = y[o].im[0];
-                if constexpr (DIAG) {
-                    C2 xs = rv[o];
-                    if constexpr (!DBL) xs = reinterpret_cast<const C2 *>(tcur)[(int64_t)NORB * at + o];
-                    yr += dg[o] * xs.x;
-                    yi += dg[o] * xs.y;
-                }
-                C2 ov;
-                if constexpr (FIRST) {
-                    ov.x = a.c1 * yr;
-                    ov.y = a.c1 * yi;
-                } else {
-                    ov.x = a.c1 * yr - pv[o].x;
-                    ov.y = a.c1 * yi - pv[o].y;
-                }
-                if (ok) {
-                    const double cr = (double)rv[o].x * (double)ov.x + (double)rv[o].y * (double)ov.y;
-                    if constexpr (DBL) {
-                        acc[0] += (double)ov.x * (double)ov.x + (double)ov.y * (double)ov.y;
-                        acc[1] += cr;
-                    } else {
-                        acc[0] += cr;
-                    }
-                }
-                sbuf[mine + o] = ov;
-            }
-            __syncthreads();
-            {
-                C2 *g = reinterpret_cast<C2 *>(tnext) + row0;
-                for (int e = threadIdx.x; e < nrow; e += kThreads) st<NT>(g + e, sbuf[e]);
-            }
-            __syncthreads();
-        } else {
+        }
+        if (!staged) {
 #pragma unroll
             for (int o = 0; o < NORB; ++o) {
                 const int64_t i = (int64_t)NORB * at + o;
@@ -512,6 +543,9 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
 template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG>
 void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const StepScalars<VT> &a) {
     const unsigned G = (unsigned)pl.G;
+    // one-vector row staging through LDS (rows_per_thread: 1 = when the launch is large
+    // enough to keep every CU busy between the staging barriers, 2 = always, 4 = never)
+    const int stage = pl.cfg.rows_per_thread == 2 || (pl.cfg.rows_per_thread == 1 && pl.n_tiles >= kStageMinTiles);
     GeomParams<VT> gp;
     for (int l = 0; l < 10; ++l) gp.v[l] = (VT)pl.geom_params[l];
     gp.inv_r0 = pl.geom_params[10] > 0 ? (VT)(1.0 / pl.geom_params[10]) : (VT)0;
@@ -520,10 +554,10 @@ void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const St
     do {                                                                                                    \
         if (pl.geom)                                                                                        \
             k_cheb_step_geom<VT, NORB, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(                \
-                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a, gp);            \
+                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a, gp, stage);     \
         else if (pl.cfg.atom_rows)                                                                          \
             k_cheb_step_atom<VT, NORB, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(                \
-                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);                \
+                p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a, stage);         \
         else                                                                                                \
             k_cheb_step_blk<VT, NORB, L, VPT, FIRST, DIAG, NT, DBL><<<G, kThreads, 0, s>>>(                 \
                 p.ptr, p.col, p.val, p.onsite, p.tcur, p.tprev, p.tnext, p.r, p.partial, a);                \

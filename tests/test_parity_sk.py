@@ -132,17 +132,19 @@ def test_block_builder_matches_oracle(fmt, slice):
 
 
 @pytest.mark.parametrize("atom", [0, 1])
-@pytest.mark.parametrize("R,tpb,nt,xr,dbl", [(1, 1, 1, 0, 0), (3, 2, 0, 1, 0), (16, 2, 1, 0, 1), (64, 1, 1, 1, 0)])
+@pytest.mark.parametrize("R,tpb,nt,xr,dbl", [(1, 1, 1, 0, 0), (3, 2, 0, 1, 0), (16, 2, 1, 0, 1), (64, 1, 1, 1, 0),
+                                             (1, 2, 1, 0, 1), (1, 3, 0, 1, 0)])
 def test_block_fp64_moments(R, tpb, nt, xr, dbl, atom):
     s = synth.graphene_sheet(13, 11, 0.06, 4)        # 2288 orbital rows: ragged tiles
     csr = oracle_csr(s)
     H = build(s, "bsell4_f64", 32)
     a, b = G.oracle_ab(csr)
     r = synth.random_phase(4 * s.n, R, 7)
-    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=atom)
-    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r, 61)
-    assert np.abs(mu - mo).max() <= 1e-10 * 4 * s.n
+    for rows in ((2, 4) if atom else (1,)):   # atom form, one vector: staged rows and direct
+        cfg = tbkpm.make_config(1, tpb, nt, xr, rows, doubling=dbl, atom_rows=atom)
+        mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
+        assert np.abs(mu - mo).max() <= 1e-10 * 4 * s.n
 
 
 @pytest.mark.parametrize("atom", [0, 1])
@@ -181,8 +183,9 @@ def test_block_rejections():
     assert e.value.name == "INVALID_ARG"
 
 
+@pytest.mark.parametrize("R", [1, 2])
 @pytest.mark.parametrize("atom", [0, 1])
-def test_block_vac_moments_match_oracle(atom):
+def test_block_vac_moments_match_oracle(atom, R):
     s = synth.graphene_sheet(6, 5, 0.07, 9)
     csr = oracle_csr(s)
     H = build(s, "bsell4_f64", 16)
@@ -193,10 +196,11 @@ def test_block_vac_moments_match_oracle(atom):
     orow, ocol, _ = G.csr_entries(csr)
     o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
     np.testing.assert_allclose(vals[o1], vo[o2], rtol=1e-15, atol=1e-15 * np.abs(vo).max())
-    r = synth.random_phase(4 * s.n, 2, 5)
+    r = synth.random_phase(4 * s.n, R, 5)
     M, n_t, dt = 40, 3, 0.3
     nc = tbkpm.chebyshev_terms(a, dt)
-    cfg = tbkpm.make_config(1, 2, 1, 0, 1, atom_rows=atom)
-    nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, config=cfg).cpu().numpy()
     nuo = O.vac_moments(csr, vo, a, b, r, M, n_t, dt, nc)
-    assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()
+    for rows in ((2, 4) if atom else (1,)):
+        cfg = tbkpm.make_config(1, 2, 1, 0, rows, atom_rows=atom)
+        nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, config=cfg).cpu().numpy()
+        assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()

@@ -83,10 +83,11 @@ def test_geom_fp64_moments(norb, R, tpb, nt, xr, dbl):
     H = build(s, norb, "bgeom_f64", 32)
     a, b = G.oracle_ab(csr)
     r = synth.random_phase(norb * s.n, R, 7)
-    cfg = tbkpm.make_config(1, tpb, nt, xr, 1, doubling=dbl, atom_rows=1)
-    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
     mo, _ = O.kpm_moments(csr, a, b, r, 61)
-    assert np.abs(mu - mo).max() <= 1e-10 * norb * s.n
+    for rows in (2, 4):                # one-vector rows staged through LDS, and direct
+        cfg = tbkpm.make_config(1, tpb, nt, xr, rows, doubling=dbl, atom_rows=1)
+        mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), 61, "f64", config=cfg).cpu().numpy()
+        assert np.abs(mu - mo).max() <= 1e-10 * norb * s.n
 
 
 @pytest.mark.parametrize("norb,R,vpt", [(4, 8, 2), (9, 1, 1), (9, 16, 2)])
