@@ -117,3 +117,89 @@ def test_geom_refusals():
     with pytest.raises(tbkpm.TBKError) as e:
         build(s, 4, "bgeom_f64", 8, model=dict(params=G.to_dev(P), shift=np.zeros(16), scale=np.ones(16)))
     assert e.value.name == "INVALID_ARG"
+
+
+V10 = synth.SK_V + synth.SK_D
+R3NN = 3.0                        # third-neighbour cutoff (shells at 1.42, 2.46, 2.84 A)
+
+
+@pytest.mark.parametrize("rows", [2, 4])
+def test_geom_third_neighbours_against_oracle_and_stored_blocks(rows):
+    """s, p, d with the third-neighbour cutoff: C32 DOS of the displacement form within 1e-4
+    of the oracle's, moments within 1e-4 of the row count of the stored-block form."""
+    s = synth.graphene_sheet(24, 14, 0.05, 12)
+    mk = lambda fmt: tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic,
+                                                *synth.SK_V, synth.SK_ES, synth.SK_EP, r_cut=R3NN, r0=synth.R0,
+                                                beta=synth.BETA, fmt=fmt, slice=64, d=synth.SK_D, e_d=synth.SK_ED)
+    Hg, Hb = mk("bgeom_f32"), mk("bsell4_f32")
+    assert Hg.st.max_degree >= 11
+    csr = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, synth.SK_ES, synth.SK_EP, r_cut=R3NN, r0=synth.R0,
+                           beta=synth.BETA, e_d=synth.SK_ED)[0]
+    a, b = G.oracle_ab(csr)
+    r = synth.random_phase(9 * s.n, 1, 21, np.complex64)
+    cfg = tbkpm.make_config(1, 2, 1, 0, rows, atom_rows=1)
+    mg = tbkpm.kpm_moments(Hg, a, b, G.to_dev(r), 128, "c32", config=cfg).cpu().numpy()
+    mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 128, "c32", config=cfg).cpu().numpy()
+    assert np.abs(mg - mb).max() <= 1e-4 * 9 * s.n
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 128)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mg.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+
+
+def bloch_spectrum(cell, tx, ty):
+    """Exact spectrum of the pristine s, p, d third-neighbour sheet on a torus of tx x ty copies
+    of the small periodic sheet `cell`, from the oracle's blocks of the small sheet and the
+    commensurate Bloch phases (each entry's minimum-image lattice shift)."""
+    csr = O.sk_hamiltonian(cell.pos, cell.box, cell.periodic, V10, synth.SK_ES, synth.SK_EP, r_cut=R3NN,
+                           r0=synth.R0, beta=synth.BETA, e_d=synth.SK_ED)[0]
+    nr = 9 * cell.n
+    rows = np.repeat(np.arange(nr), np.diff(csr.row_ptr))
+    cols = csr.col.astype(np.int64)
+    d = cell.pos[cols // 9] - cell.pos[rows // 9]
+    img = np.zeros_like(d)
+    for ax in range(2):                              # periodic x, y
+        img[:, ax] = -cell.box[ax] * np.rint(d[:, ax] / cell.box[ax])
+    idx = rows * nr + cols
+    eigs = []
+    kx = 2 * np.pi * np.arange(tx) / (tx * cell.box[0])
+    ky = 2 * np.pi * np.arange(ty) / (ty * cell.box[1])
+    K = np.array([(x, y) for x in kx for y in ky])
+    for s0 in range(0, K.shape[0], 100):
+        Hk = []
+        for k in K[s0:s0 + 100]:
+            ph = np.exp(1j * (img[:, 0] * k[0] + img[:, 1] * k[1])) * csr.val
+            h = (np.bincount(idx, weights=ph.real, minlength=nr * nr)
+                 + 1j * np.bincount(idx, weights=ph.imag, minlength=nr * nr)).reshape(nr, nr)
+            h[np.arange(nr), np.arange(nr)] += csr.diag
+            Hk.append(h)
+        eigs.append(np.linalg.eigvalsh(np.array(Hk)).reshape(-1))
+    return np.concatenate(eigs), csr
+
+
+def test_geom_100M_third_neighbours_against_exact_spectrum():
+    """100 M atoms (900 M orbital rows), pristine s, p, d third-neighbour sheet, displacement
+    form, the launch path of the benchmark (one vector, rows staged): moments n < 150 against
+    the exact spectrum of a 200 x 200-cell torus (walks shorter than ~164 hops do not wrap
+    it), |mu_n / N - tau_n| <= 5 / sqrt(N)."""
+    from tests import ref_numpy as ref
+    cell = synth.graphene_sheet(2, 4)                # 8.52 x 9.84 A: above twice the cutoff
+    eigs, csr = bloch_spectrum(cell, 100, 50)        # 200 x 200 unit cells
+    assert eigs.size == 9 * 4 * 200 * 200
+    a, b = G.oracle_ab(csr)                          # every atom is equivalent: the same bounds
+    Mc = 150
+    tau = ref.trace_moments_from_eigs(eigs, a, b, Mc) / eigs.size
+    s = synth.graphene_sheet(5000, 5000)
+    n = 9 * s.n
+    print(f"[fullsize] spd 3nn: N={s.n} atoms, {n} rows, M={Mc}", flush=True)
+    pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
+    H = tbkpm.build_hamiltonian_sk(pos, sp, s.box, s.periodic, *synth.SK_V, synth.SK_ES, synth.SK_EP, r_cut=R3NN,
+                                   r0=synth.R0, beta=synth.BETA, fmt="bgeom_f32", slice=64, d=synth.SK_D,
+                                   e_d=synth.SK_ED)
+    del s, pos, sp
+    assert H.st.max_degree == 12
+    cfg = tbkpm.make_config(1, 1, 0, 1, 1, atom_rows=1)
+    mu = tbkpm.kpm_moments_seeded(H, a, b, 77, 1, Mc, "c32", config=cfg).cpu().numpy()[0]
+    dev = np.abs(mu / n - tau)
+    bound = 5.0 / np.sqrt(n)
+    print(f"[fullsize] spd 3nn vs exact: max dev {dev.max():.3e} (bound {bound:.3e})", flush=True)
+    assert np.all(dev <= bound)
