@@ -451,39 +451,55 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
         for (int o = 0; o < NORB; ++o)
 #pragma unroll
             for (int q = 0; q < VPT; ++q) { y[o].re[q] = 0; y[o].im[q] = 0; }
-        for (int k = 0; k < w; ++k) {
-            const int64_t qb = base + (int64_t)k * stride;
-            const int32_t c = ld<NT>(bcol + qb);
-            const VT dx = ld<NT>(geo + 3 * qb), dy = ld<NT>(geo + 3 * qb + 1), dz = ld<NT>(geo + 3 * qb + 2);
-            const VT r2 = dx * dx + dy * dy + dz * dz;
-            if (!(r2 > (VT)0)) continue;              // padding slot
-            Pack<VT, VPT> x[NORB];
+        // two bonds per pass: both bonds' columns, displacements and neighbour rows are
+        // loaded before either block is applied (slots past the width repeat the last one
+        // and are skipped, as are padding slots, d = 0)
+        constexpr int KU = 2;
+        for (int k0 = 0; k0 < w; k0 += KU) {
+            int32_t c[KU];
+            VT dx[KU], dy[KU], dz[KU];
 #pragma unroll
-            for (int b = 0; b < NORB; ++b)
-                x[b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c + b) * Rp + voff));
-            const VT rr = sqrt(r2);
-            const VT inv = (VT)1 / rr;
-            const VT f = exp(-gp.beta * (rr * gp.inv_r0 - (VT)1));
-            VT vf[10];
+            for (int u = 0; u < KU; ++u) {
+                const int64_t qb = base + (int64_t)min(k0 + u, w - 1) * stride;
+                c[u] = ld<NT>(bcol + qb);
+                dx[u] = ld<NT>(geo + 3 * qb);
+                dy[u] = ld<NT>(geo + 3 * qb + 1);
+                dz[u] = ld<NT>(geo + 3 * qb + 2);
+            }
+            Pack<VT, VPT> x[KU][NORB];
 #pragma unroll
-            for (int l = 0; l < 10; ++l) vf[l] = gp.v[l] * f;
-            const VT cl = dx * inv, cm = dy * inv, cn = dz * inv;
+            for (int u = 0; u < KU; ++u)
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) {
-                VT xr[NORB], xi[NORB], yr[NORB], yi[NORB];
+                for (int b = 0; b < NORB; ++b)
+                    x[u][b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c[u] + b) * Rp + voff));
 #pragma unroll
-                for (int b = 0; b < NORB; ++b) {
-                    xr[b] = x[b].re[q];
-                    xi[b] = x[b].im[q];
-                    yr[b] = y[b].re[q];
-                    yi[b] = y[b].im[q];
-                }
-                sk_apply<VT, NORB>(vf, cl, cm, cn, xr, yr);
-                sk_apply<VT, NORB>(vf, cl, cm, cn, xi, yi);
+            for (int u = 0; u < KU; ++u) {
+                const VT r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+                if (k0 + u >= w || !(r2 > (VT)0)) continue;
+                const VT rr = sqrt(r2);
+                const VT inv = (VT)1 / rr;
+                const VT f = exp(-gp.beta * (rr * gp.inv_r0 - (VT)1));
+                VT vf[10];
 #pragma unroll
-                for (int b = 0; b < NORB; ++b) {
-                    y[b].re[q] = yr[b];
-                    y[b].im[q] = yi[b];
+                for (int l = 0; l < 10; ++l) vf[l] = gp.v[l] * f;
+                const VT cl = dx[u] * inv, cm = dy[u] * inv, cn = dz[u] * inv;
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    VT xr[NORB], xi[NORB], yr[NORB], yi[NORB];
+#pragma unroll
+                    for (int b = 0; b < NORB; ++b) {
+                        xr[b] = x[u][b].re[q];
+                        xi[b] = x[u][b].im[q];
+                        yr[b] = y[b].re[q];
+                        yi[b] = y[b].im[q];
+                    }
+                    sk_apply<VT, NORB>(vf, cl, cm, cn, xr, yr);
+                    sk_apply<VT, NORB>(vf, cl, cm, cn, xi, yi);
+#pragma unroll
+                    for (int b = 0; b < NORB; ++b) {
+                        y[b].re[q] = yr[b];
+                        y[b].im[q] = yi[b];
+                    }
                 }
             }
         }
