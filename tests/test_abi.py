@@ -66,3 +66,22 @@ def test_host_side_validation_without_gpu(lib):
     assert rc == 0 and out.value > 3 * 10 * 4 * 8
     rc = lib.kpm_dos(None, 0, 1.0, 0.0, 0, None, 0, None, None)
     assert rc == 1
+
+
+def test_post_processing_checks_without_gpu(lib):
+    """Integrated DOS and mobility validate on the host and treat nE = 0 as a
+    no-op that touches no pointer and no device."""
+    assert lib.kpm_integrated_dos(None, 8, 1.0, 0.0, 0, None, 0, None, None) == 0
+    assert lib.kpm_integrated_dos(None, 0, 1.0, 0.0, 0, None, 4, None, None) == 1
+    assert b"M = 0" in lib.tbk_last_error()
+    assert lib.kpm_integrated_dos(None, 8, 0.0, 0.0, 0, None, 4, None, None) == 1
+    assert b"positive" in lib.tbk_last_error()
+    assert lib.kpm_integrated_dos(None, 8, 1.0, 0.0, 2, None, 4, None, None) == 1
+    assert lib.kpm_integrated_dos(None, 8, 1.0, 0.0, 0, None, 4, None, None) == 1
+    assert b"NULL" in lib.tbk_last_error()
+    assert lib.lsqt_mobility(None, 2, 3, 0, None, 1.0, None, None, None, None) == 0
+    assert lib.lsqt_mobility(None, 0, 3, 5, None, 1.0, None, None, None, None) == 1
+    assert b"n_frames = 0" in lib.tbk_last_error()
+    assert lib.lsqt_mobility(None, 2, 3, 5, None, float("inf"), None, None, None, None) != 0
+    assert lib.lsqt_mobility(None, 2, 3, 5, None, 1.0, None, None, None, None) == 1
+    assert b"NULL" in lib.tbk_last_error()
