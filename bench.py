@@ -180,8 +180,10 @@ def bench_snapshots(args, w):
 
     H = build()
     a, b = H.scales()
-    # launch shape: one launch per step vs one persistent launch (both exact), faster kept
-    shapes = {"per_step": tbkpm.make_config(2, 2, 1, 0, 1, 0), "persistent": tbkpm.make_config(2, 1, 1, 0, 1, 1)}
+    # launch shape: one launch per step (block order plain or XCD-aware) vs one persistent
+    # launch (all exact), fastest kept
+    shapes = {"per_step": tbkpm.make_config(2, 2, 1, 0, 1, 0), "per_step_xcd": tbkpm.make_config(2, 2, 1, 1, 1, 0),
+              "persistent": tbkpm.make_config(2, 1, 1, 0, 1, 1)}
     timing = {}
     for name, cfg in shapes.items():
         try:

@@ -64,6 +64,7 @@ template <class VT> struct SegStep {
     int32_t log2_slice;
     int32_t Rp;
     int32_t tiles_per_block;
+    int32_t xcd_remap;       // grid is a multiple of the XCD count when set
 };
 
 // One row of tile t for this thread: T_{n+1} of the row and its overlap with
@@ -138,11 +139,14 @@ __device__ __forceinline__ void seg_tile_row(const SegStep<VT> &a, int64_t t, do
     }
 }
 
-// One step for every segment: block b handles tiles_per_block consecutive
-// tiles of the table and writes one partial per tile.
+// One step for every segment: logical block b handles tiles_per_block
+// consecutive tiles of the table and writes one partial per tile.  With
+// xcd_remap each XCD sweeps a contiguous range of tiles, so the neighbour rows
+// a tile gathers are mostly in that XCD's own L2; blocks past the last tile
+// (grid rounded up to the XCD count) do nothing.
 template <class VT, int L, int VPT, bool FIRST, bool DIAG, bool NT, int W>
 __global__ __launch_bounds__(kThreads) void k_cheb_step_seg(SegStep<VT> a) {
-    const int64_t t0 = (int64_t)blockIdx.x * a.tiles_per_block;
+    const int64_t t0 = logical_block(a.xcd_remap) * a.tiles_per_block;
     const int64_t t1 = min(t0 + a.tiles_per_block, a.n_tiles);
     for (int64_t t = t0; t < t1; ++t) {
         double acc[VPT];
@@ -371,7 +375,7 @@ tbk_status make_seg_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precisi
     }
     sp.n_tiles = sp.tile_off[sp.n_seg];
     const int64_t G = ceil_div(sp.n_tiles, sp.base.cfg.tiles_per_block);
-    TBK_CHECK(G < (int64_t)INT32_MAX && sp.n_tiles < (int64_t)INT32_MAX, TBK_ERR_UNSUPPORTED, "too many tiles");
+    TBK_CHECK(G + kNumXcd < (int64_t)INT32_MAX && sp.n_tiles < (int64_t)INT32_MAX, TBK_ERR_UNSUPPORTED, "too many tiles");
     const size_t per_step = (size_t)sp.n_tiles * sp.base.Rp * sizeof(double);
     sp.K = (int)std::max<size_t>(1, std::min<size_t>({kSegPartialBudget / per_step, (size_t)64, (size_t)M}));
     const size_t vb = sp.base.vec_bytes, ve = sp.base.elem;
@@ -471,6 +475,7 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
     st.log2_slice = sp.base.log2_slice;
     st.Rp = Rp;
     st.tiles_per_block = sp.base.cfg.tiles_per_block;
+    st.xcd_remap = sp.base.cfg.xcd_remap;
     if (sp.persistent) {
         // moment 0 from the tile partials of |r|^2
         {
@@ -521,7 +526,9 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
         TBK_HIP(hipStreamSynchronize(s));
         TBK_CHECK(habort == 0, TBK_ERR_DEVICE, "persistent recurrence: a team barrier timed out");
     } else {
-    const unsigned G = (unsigned)ceil_div(T, sp.base.cfg.tiles_per_block);
+    int64_t Gt = ceil_div(T, sp.base.cfg.tiles_per_block);
+    if (st.xcd_remap) Gt = ceil_div(Gt, kNumXcd) * kNumXcd;
+    const unsigned G = (unsigned)Gt;
     const int K = sp.K;
     auto reduce = [&](int n0, int count) {
         dim3 grid(ns, count);

@@ -58,14 +58,15 @@ def test_batched_builder_per_structure(fmt, slice):
 
 
 @pytest.mark.parametrize("R", [1, 3, 8])
-@pytest.mark.parametrize("tpb,nt,persistent", [(1, 1, 0), (3, 0, 0), (2, 1, 0), (1, 1, 1), (1, 0, 1)])
-def test_batched_fp64_moments_per_structure(R, tpb, nt, persistent):
+@pytest.mark.parametrize("tpb,nt,persistent,xcd", [(1, 1, 0, 0), (3, 0, 0, 0), (2, 1, 0, 0), (1, 1, 1, 0),
+                                                    (1, 0, 1, 0), (1, 1, 0, 1), (3, 0, 0, 1)])
+def test_batched_fp64_moments_per_structure(R, tpb, nt, persistent, xcd):
     sheets, pos, sp, seg, boxes = make_batch()
     H = build(pos, sp, seg, boxes, "sell_f64", 16)
     a, b = G.oracle_scales(sheets)
     M = 64
     r = synth.random_phase(pos.shape[0], R, 11)
-    cfg = tbkpm.make_config(1, tpb, nt, 0, 1, persistent)
+    cfg = tbkpm.make_config(1, tpb, nt, xcd, 1, persistent)
     mu = tbkpm.kpm_moments_batched(H, a, b, G.to_dev(r), M, "f64", config=cfg).cpu().numpy()
     assert mu.shape == (len(sheets), R, M)
     for k, s in enumerate(sheets):
@@ -135,6 +136,19 @@ def test_persistent_equals_launch_per_step():
     n = np.diff(seg)[:, None, None]
     assert (np.abs((m0 - m1).cpu().numpy()) <= 1e-12 * n).all()
     torch.testing.assert_close(m1, m2, rtol=0, atol=0)          # bitwise reproducible
+
+
+@pytest.mark.parametrize("tpb", [1, 2, 3])
+def test_xcd_mapping_is_bitwise_neutral(tpb):
+    """The XCD-aware block order changes which workgroup runs a tile, not what
+    a tile computes or the order its partials are summed in."""
+    sheets, pos, sp, seg, boxes = make_batch()
+    H = build(pos, sp, seg, boxes, "sell_f32", 64)
+    a, b = H.scales()
+    r = G.to_dev(synth.random_phase(pos.shape[0], 4, 23, np.complex64))
+    m0 = tbkpm.kpm_moments_batched(H, a, b, r, 120, "c32", config=tbkpm.make_config(2, tpb, 1, 0, 1, 0))
+    m1 = tbkpm.kpm_moments_batched(H, a, b, r, 120, "c32", config=tbkpm.make_config(2, tpb, 1, 1, 1, 0))
+    torch.testing.assert_close(m0, m1, rtol=0, atol=0)
 
 
 def test_persistent_barrier_timeout_is_reported(monkeypatch):
