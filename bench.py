@@ -182,8 +182,9 @@ def bench_snapshots(args, w):
     a, b = H.scales()
     # launch shape: one launch per step (block order plain or XCD-aware) vs one persistent
     # launch (all exact), fastest kept
-    shapes = {"per_step": tbkpm.make_config(2, 2, 1, 0, 1, 0), "per_step_xcd": tbkpm.make_config(2, 2, 1, 1, 1, 0),
-              "persistent": tbkpm.make_config(2, 1, 1, 0, 1, 1)}
+    shapes = {"per_step": tbkpm.make_config(2, 2, 1, 0, 1, 0), "persistent": tbkpm.make_config(2, 1, 1, 0, 1, 1)}
+    for tpb in (1, 2, 4):
+        shapes[f"per_step_xcd_tpb{tpb}"] = tbkpm.make_config(2, tpb, 1, 1, 1, 0)
     timing = {}
     for name, cfg in shapes.items():
         try:
