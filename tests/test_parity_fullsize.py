@@ -106,3 +106,35 @@ def test_fullsize_100M_against_exact_spectrum():
     print(f"[fullsize] 100M vs exact: max dev {dev.max():.3e} (bound {bound:.3e})", flush=True)
     assert np.all(dev <= bound)
     assert tau[2] == pytest.approx(2 * 3 * 2.7 ** 2 / a ** 2 - 1, abs=1e-12)
+
+
+def test_fullsize_snapshot_batch():
+    """All 256 snapshots of the learned-hopping workload (3.43 M atoms, M = 1024,
+    R = 8) with plain hoppings, in one batched recurrence per launch shape the
+    benchmark chooses from: the XCD-aware block orders at 1, 2 and 4 tiles per
+    block equal the plain order bitwise, and three sampled snapshots (the first,
+    the last and the smallest) match the oracle, DOS relative L2 <= 1e-4."""
+    from oracle import oracle as O
+    w = synth.WORKLOADS["graphene_snapshots_256"]
+    snaps = synth.snapshot_set(w["count"], w["seed"])
+    pos, sp, seg, boxes = synth.stack(snaps)
+    N, M, R = int(seg[-1]), w["M"], w["R"]
+    print(f"[fullsize] snapshot batch: {len(snaps)} structures, N={N} M={M} R={R}", flush=True)
+    a, b = G.oracle_scales(snaps)
+    H = tbkpm.build_hamiltonian_batched(G.to_dev(pos), G.to_dev(sp), seg, boxes, (1, 1, 0), [0.0],
+                                        [[synth.T_CC_EV]], fmt="sell_f32", slice=64)
+    r = synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)
+    rd = G.to_dev(r)
+    mu0 = tbkpm.kpm_moments_batched(H, a, b, rd, M, "c32", config=tbkpm.make_config(2, 2, 1, 0, 1, 0))
+    for tpb in (1, 2, 4):
+        mu1 = tbkpm.kpm_moments_batched(H, a, b, rd, M, "c32", config=tbkpm.make_config(2, tpb, 1, 1, 1, 0))
+        torch.testing.assert_close(mu0, mu1, rtol=0, atol=0)
+    mu = mu0.cpu().numpy()
+    for k in sorted({0, len(snaps) - 1, int(np.argmin([s.n for s in snaps]))}):
+        s = snaps[k]
+        csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+        mu_o, _ = O.kpm_moments(csr, a[k], b[k], r[seg[k]:seg[k + 1]].astype(np.complex128), M)
+        E = synth.energy_grid(a[k], b[k])
+        err = G.rel_l2(O.kpm_dos(mu[k].mean(0), a[k], b[k], E), O.kpm_dos(mu_o.mean(0), a[k], b[k], E))
+        print(f"[fullsize] snapshot {k}: N={s.n} DOS relL2={err:.2e}", flush=True)
+        assert err <= 1e-4, (k, err)
