@@ -212,7 +212,7 @@ def bench_snapshots(args, w):
         ev[0].record(stream)
         tbkpm.kpm_moments_batched(Hs, aa, bb, r, M, "c32", work=work, mu=mu, config=cfg, stream=stream)
         ev[1].record(stream)
-        mbar = mu.mean(1)
+        mbar = tbkpm.mean_moments(mu, stream=stream)
         # each snapshot's own grid [b - 0.99 a, b + 0.99 a]
         grid = (torch.tensor(bb, dtype=torch.float64, device=dev)[:, None]
                 + torch.tensor(aa, dtype=torch.float64, device=dev)[:, None] * u[None, :]).contiguous()
@@ -283,7 +283,7 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     med = float(np.median(ms))
-    rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), a, b, E, stream=stream).cpu().numpy()
+    rho = tbkpm.kpm_dos(tbkpm.mean_moments(mu, stream=stream), a, b, E, stream=stream).cpu().numpy()
     dbl = bool(cfg.doubling)
     launches = M // 2 if dbl else M - 1
     launch_bytes = cheb_step_bytes(H, Rp, elem, diag, read_r=not dbl, read_values=not cfg.uniform_values,
@@ -383,7 +383,7 @@ def bench_sk(args, w):
         ev[0].record(stream)
         tbkpm.kpm_moments(Hs, aa, bb, r, M, "c32", work=work, mu=mu, stream=stream, config=cfg)
         ev[1].record(stream)
-        rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream)
+        rho = tbkpm.kpm_dos(tbkpm.mean_moments(mu, stream=stream), aa, bb, E, stream=stream)
         return Hs, aa, bb, rho
 
     log(f"N={N} atoms, {norb * N} orbitals, M={M} R={R}: warmup {args.warmup}, timed {args.steps}")
@@ -595,11 +595,11 @@ def bench_vac(args, w):
             aa, bb = Hs.scale()
             vx = tbkpm.build_velocity(Hs, pos[f], s.box, s.periodic, 0, stream=stream)
             nu = tbkpm.vac_moments(Hs, vx, aa, bb, r, M, n_t, dt, n_cheb, "c32", config=config, stream=stream)
-            sig = tbkpm.vac_sigma(nu.mean(1).contiguous(), aa, bb, dt, E, stream=stream)
+            sig = tbkpm.vac_sigma(tbkpm.mean_moments(nu, stream=stream), aa, bb, dt, E, stream=stream)
             if F > 1:
                 sig_all[f].copy_(sig)
                 mu = tbkpm.kpm_moments(Hs, aa, bb, r_dos, M, "c32", stream=stream, config=config_dos)
-                n_all[f].copy_(tbkpm.integrated_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream))
+                n_all[f].copy_(tbkpm.integrated_dos(tbkpm.mean_moments(mu, stream=stream), aa, bb, E, stream=stream))
         if F > 1:
             res = tbkpm.mobility(sig_all, n_all, 0.5 * N, stream=stream)
         return Hs, sig, res
@@ -746,7 +746,7 @@ def main():
         ev[0].record(stream)
         tbkpm.kpm_moments(Hs, aa, bb, r, M, w["precision"], work=work, mu=mu, stream=stream, config=config)
         ev[1].record(stream)
-        rho = tbkpm.kpm_dos(mu.mean(0).contiguous(), aa, bb, E, stream=stream)
+        rho = tbkpm.kpm_dos(tbkpm.mean_moments(mu, stream=stream), aa, bb, E, stream=stream)
         return Hs, aa, bb, rho
 
     log(f"N={N} M={M} R={R}: warmup {args.warmup}, timed {args.steps}")
@@ -835,7 +835,7 @@ def main():
         ev[3].record(stream)
         torch.cuda.synchronize()
         ms64 = ev[2].elapsed_time(ev[3])
-        rho64 = tbkpm.kpm_dos(mu64.mean(0).contiguous(), aa, bb, E, stream=stream).cpu().numpy()
+        rho64 = tbkpm.kpm_dos(tbkpm.mean_moments(mu64, stream=stream), aa, bb, E, stream=stream).cpu().numpy()
         out["fp64_path"] = {"kpm_ms": ms64, "atom_moments_per_s": N * M * R / (ms64 * 1e-3),
                             "dos_relL2_c32_vs_fp64": float(np.linalg.norm(rho_c - rho64) / np.linalg.norm(rho64)),
                             "max_abs_dmu_over_N": float(np.abs(mu_c - mu64.cpu().numpy()).max() / N)}

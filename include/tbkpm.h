@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 11
+#define TBK_ABI_VERSION 12
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -254,7 +254,21 @@ tbk_status kpm_workspace_size_config(const tbk_ham *h, int32_t R, int32_t M, int
                                      const tbk_kpm_config *cfg, int64_t *bytes);
 
 /*
- * Chebyshev moments of Ht = (H - b)/a over R random vectors:
+ * Scale of the Chebyshev expansion (Sec. 2.4: the expansion needs the spectrum
+ * mapped into [-1, 1]) from spectral bounds, for n systems:
+ *   a[s] = margin (E_hi - E_lo) / 2,  b[s] = (E_hi + E_lo) / 2,
+ * with [E_lo, E_hi] = spec_bounds[2 s], spec_bounds[2 s + 1] (host double,
+ * eV; e.g. the Gershgorin bounds the builders return) and margin >= 1 (1.01
+ * keeps the scaled spectrum inside [-1, 1] with room for rounding).  a, b:
+ * host double [n], caller-allocated.  Host arithmetic only.
+ * Errors: INVALID_ARG (n < 1, NULL, margin < 1 or not finite, E_hi <= E_lo),
+ * NOT_FINITE (a bound is NaN/Inf); nothing is written on an error.
+ */
+tbk_status kpm_scale(int32_t n, const double *spec_bounds, double margin, double *a, double *b);
+
+/*
+ * Chebyshev moments of Ht = (H - b)/a over R random vectors (Sec. 2.4 and the
+ * trace of Eq. (4) by random phases):
  *   T_0 = r, T_1 = Ht r, T_{n+1} = 2 Ht T_n - T_{n-1},
  *   mu[s][v][n] = Re <r_v|T_n>_s  (n = 0..M-1; the overlap is restricted to the
  *   rows of system s).
@@ -262,16 +276,33 @@ tbk_status kpm_workspace_size_config(const tbk_ham *h, int32_t R, int32_t M, int
  * double inside the same kernel; per-block partial sums are reduced in a fixed
  * order, so results are bitwise reproducible for a given launch shape.
  *   a, b   host double [n_seg]: scale a > 0 and shift of each system.
- *   r      device c128|c64 [n_rows][R] in the CALLER's atom order.
- *   work   device, >= kpm_workspace_size bytes, 256-byte aligned.
+ *   r      device c128|c64 [n_rows][R] in the CALLER's atom order (not read
+ *          when n_start > 0; may then be NULL).
+ *   n_start 0: a fresh run, moments 0 .. M-1.  n_start >= 2: continue the run
+ *          whose state `work` holds (checkpoint/resume of the recurrence):
+ *          the last completed call on this `work` was a fresh or continued run
+ *          of the same Hamiltonian (same sizes and values), R, precision, a and
+ *          b that ended at moment n_start - 1 (its M was n_start); work keeps
+ *          T_{n_start-1}, T_{n_start-2}, the start vectors and mu_0, and this
+ *          call writes only mu[.][.][n_start .. M-1], bit for bit what one run
+ *          with this M would write (any launch shape: the vectors do not
+ *          depend on it).  Direct form only (cfg->doubling = 0).
+ *   work   device, >= kpm_workspace_size bytes, 256-byte aligned.  Its
+ *          leading bytes hold the run's state (a record of the run, the start
+ *          vectors, T_{n-1} and T_{n-2}) at offsets that do not depend on M,
+ *          so one buffer sized for the largest M serves every call of a run
+ *          split over calls.
  *   mu     device double [n_seg][R][M].
  * Errors: INVALID_ARG (R < 1 or R > 64, M < 2, a <= 0, precision/format
- * mismatch), BUFFER_TOO_SMALL (work_bytes), SPECTRUM (some |mu_n| >
- * mu_0 (1 + 1e-6): (a, b) does not bound the spectrum; mu is still written),
- * DEVICE.  Synchronises `stream` (to read the spectrum check).
+ * mismatch; n_start not 0 and not in [2, M), doubling with n_start > 0, or
+ * work holding no state that ends at n_start - 1 for these arguments),
+ * BUFFER_TOO_SMALL (work_bytes), SPECTRUM (some |mu_n| > mu_0 (1 + 1e-6):
+ * (a, b) does not bound the spectrum; mu is still written), DEVICE.
+ * Synchronises `stream` (to read the spectrum check and, with n_start > 0,
+ * the state record).
  */
 tbk_status kpm_moments(const tbk_ham *h, const double *a, const double *b, const void *r,
-                       int32_t R, int32_t M, int32_t precision, void *work,
+                       int32_t R, int32_t M, int32_t precision, int32_t n_start, void *work,
                        int64_t work_bytes, double *mu, void *stream);
 
 /* kpm_moments with an explicit launch shape (cfg may be NULL = default); the
@@ -279,7 +310,8 @@ tbk_status kpm_moments(const tbk_ham *h, const double *a, const double *b, const
  * Extra errors: INVALID_ARG for a shape outside the ranges of tbk_kpm_config. */
 tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b, const void *r,
                               int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
-                              void *work, int64_t work_bytes, double *mu, void *stream);
+                              int32_t n_start, void *work, int64_t work_bytes, double *mu,
+                              void *stream);
 
 /*
  * kpm_moments_config with the random-phase start vectors (Sec. 2.4) generated
@@ -287,11 +319,14 @@ tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b
  *   r[i][v] = exp(i phi), phi = 2 pi (x >> 11) 2^-53, x = output number
  *   i R + v of SplitMix64 started at state `seed` (Steele, Lea & Flood 2014),
  * with i the caller's atom index (so the phases do not depend on the row order
- * the builder chose).  Same workspace and errors as kpm_moments_config.
+ * the builder chose).  Same workspace, n_start and errors as
+ * kpm_moments_config (a continued run reads the phases kept in `work`, so
+ * `seed` is then unused).
  */
 tbk_status kpm_moments_seeded(const tbk_ham *h, const double *a, const double *b, uint64_t seed,
                               int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
-                              void *work, int64_t work_bytes, double *mu, void *stream);
+                              int32_t n_start, void *work, int64_t work_bytes, double *mu,
+                              void *stream);
 
 /* The phases kpm_moments_seeded uses, written out: r device c128 (precision
  * 0) or c64 (precision 1) [n][R], caller-allocated.  Asynchronous on `stream`.
@@ -334,7 +369,9 @@ typedef struct {
 
 /*
  * Picks the SELL slice height and the recurrence launch shape for one
- * structure (same inputs as tb_build_hamiltonian) and vector count R: builds
+ * structure (same inputs as tb_build_hamiltonian) and vector count R (the
+ * sparse matrix-vector products of the Chebyshev expansion are the cost of
+ * the LSQT step, Sec. 2.4; only their speed depends on the choice): builds
  * H for each candidate slice, times `steps` recurrence steps of every
  * candidate shape on the GPU (HIP events on `stream`), returns the fastest.
  * Only speed depends on the choice.  Results are cached per device and
@@ -402,7 +439,10 @@ tbk_status tbk_descriptor(const double *pos, int32_t n_seg, const int64_t *seg_a
                           const double *boxes, const int32_t periodic[3], double r_cut,
                           int32_t n_radial, double *v, void *stream);
 
-/* Unordered bonds i < j (atom indices) within r_cut, ordered by (i, j):
+/* Unordered bonds i < j (atom indices) within r_cut, ordered by (i, j): the
+ * edges {i, j} of Eq. (1)/(2) whose hoppings the learned model predicts (half
+ * of the edges: H_ji follows from H_ij by the symmetry stated with Eq. (2)).
+ * Same structure arguments as tbk_descriptor (minimum image, strict r < r_cut).
  * bi, bj int32 and br double (device, capacity cap).  *n_bonds receives the
  * count; BUFFER_TOO_SMALL (nothing written) if it exceeds cap.
  * Synchronises `stream`. */
@@ -422,7 +462,11 @@ tbk_status tbk_descriptor_species(const double *pos, const int32_t *species, int
                                   int32_t n_species, const double *c_nk, double *v, void *stream);
 
 /* Standardised MLP inputs X [nb][16] as bfloat16 bits (device uint16), one
- * rounding from double.  shift, scale: host [16]. */
+ * rounding from double: the edge features of Eq. (2) (the bond's radial
+ * functions f_k(r_ij)) followed by the sum of the node features v_i + v_j.
+ * bi, bj, br from tbk_bonds, v from tbk_descriptor; shift, scale: host [16].
+ * Asynchronous on `stream`.  Errors: UNSUPPORTED (n_radial != 8), INVALID_ARG
+ * (NULL, a zero or non-finite scale or shift). */
 tbk_status tbk_bond_features(int64_t nb, const int32_t *bi, const int32_t *bj, const double *br,
                              const double *v, int32_t n_radial, double r_cut, const double *shift,
                              const double *scale, uint16_t *X, void *stream);
@@ -446,41 +490,63 @@ tbk_status tbk_node_features(int64_t n, const double *v, int32_t n_radial, const
 
 /* Mean and standard deviation (host double [16] each) of the unstandardised
  * bond features over nb bonds (FP64, fixed summation order); used as the
- * fixed feature shift and scale of a model.  Synchronises `stream`. */
+ * fixed feature shift and scale of a model (the input normalisation of the
+ * networks of Eq. (2); Sec. 2.1 normalises during training).  Synchronises
+ * `stream`.  Errors: UNSUPPORTED (n_radial != 8), INVALID_ARG (nb < 1, NULL). */
 tbk_status tbk_feature_moments(int64_t nb, const int32_t *bi, const int32_t *bj, const double *br,
                                const double *v, int32_t n_radial, double r_cut, double *mean,
                                double *stddev, void *stream);
 
-/* Synthetic training target of the learned-hopping workload: the residual
- * y*_b = kappa (z_i + z_j - 2 z0) of a coordination-corrected hopping
- * t = t_plain (1 + y*), with z_i = v[i][0] (device float [nb] output). */
+/* Synthetic training target of the learned-hopping workload (the paper
+ * trains the networks of Eq. (2) against reference data; here the reference
+ * is a coordination-corrected form of the Eq. (1) hopping): the residual
+ * y*_b = kappa (z_i + z_j - 2 z0) of t = t_plain (1 + y*), with
+ * z_i = v[i][0] (device float [nb] output).  Asynchronous on `stream`. */
 tbk_status tbk_coordination_target(int64_t nb, const int32_t *bi, const int32_t *bj,
                                    const double *v, int32_t n_radial, double kappa, double z0,
                                    float *y, void *stream);
 
-/* MLP outputs y [nb] (device float) of inputs X (bf16 bits [nb][16]). */
+/* Forward pass of the hopping network of Eq. (2) (the model of tbk_mlp_model):
+ * y [nb] (device float) of inputs X (bf16 bits [nb][16], tbk_bond_features);
+ * params device float [1633].  Asynchronous on `stream`.  Errors:
+ * INVALID_ARG (nb < 0, NULL). */
 tbk_status tbk_mlp_forward(int64_t nb, const uint16_t *X, const float *params, float *y,
                            void *stream);
 
-/* Loss L = (1/nb) sum_b w_b (y_b - y*_b)^2 (w = NULL: all ones) and dL/dparams:
- * grad device float [1633], loss device double [1] (may be NULL).  Uses `work`
- * (device, >= tbk_mlp_workspace_size(nb) bytes).  Deterministic. */
+/* Training of the hopping network of Eq. (2) by gradient descent (Sec. 2.1;
+ * the loss here is a weighted squared error of the hopping residual, since the
+ * band-structure loss of Eq. (3) needs DFT data):
+ * loss L = (1/nb) sum_b w_b (y_b - y*_b)^2 (w = NULL: all ones) and dL/dparams
+ * by the analytic backward pass, every product with bfloat16 operands as in
+ * the forward pass: grad device float [1633], loss device double [1] (may be
+ * NULL).  Uses `work` (device, >= tbk_mlp_workspace_size(nb) bytes).
+ * Deterministic (fixed-order FP64 reduction of per-wavefront partials).
+ * Errors: INVALID_ARG (nb < 1, NULL), BUFFER_TOO_SMALL (work). */
 tbk_status tbk_mlp_workspace_size(int64_t nb, int64_t *bytes);
 tbk_status tbk_mlp_loss_grad(int64_t nb, const uint16_t *X, const float *target,
                              const float *weight, const float *params, float *grad,
                              double *loss, void *work, int64_t work_bytes, void *stream);
 
-/* One AdamW step (decoupled weight decay) on n FP32 parameters with FP32
- * moment estimates m, v; t = 1-based step count after this update. */
+/* One step of the AdamW optimizer the paper trains with (Sec. 2.1; Loshchilov
+ * & Hutter, decoupled weight decay) on n FP32 parameters p (device) with
+ * gradient g and FP32 moment estimates m, v (device, updated in place);
+ * t = 1-based step count after this update:
+ *   m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ *   p -= lr [(m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps) + wd p].
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (n < 0, t < 1, NULL, lr or
+ * wd < 0, beta outside [0, 1), eps <= 0). */
 tbk_status tbk_adamw_step(int64_t n, float *p, const float *g, float *m, float *v, int64_t t,
                           double lr, double beta1, double beta2, double eps, double wd,
                           void *stream);
 
-/* Training loop on the GPU: `epochs` passes over the nb bonds in minibatches
- * of `batch` (in order), one loss/gradient and one AdamW step per minibatch;
- * *step counts the updates.  loss_history (host [epochs]) receives each
- * epoch's mean loss.  work >= tbk_mlp_workspace_size(min(batch, nb)) + 7168
- * bytes.  Synchronises `stream` once per epoch. */
+/* Training loop on the GPU (Sec. 2.1: AdamW over epochs of the training set;
+ * network of Eq. (2)): `epochs` passes over the nb bonds in minibatches of
+ * `batch` (in order), one tbk_mlp_loss_grad and one tbk_adamw_step per
+ * minibatch; *step counts the updates.  params, m, v device float [1633],
+ * updated in place.  loss_history (host [epochs]) receives each epoch's mean
+ * loss.  work >= tbk_mlp_workspace_size(min(batch, nb)) + 7168 bytes.
+ * Synchronises `stream` once per epoch.  Errors: as tbk_mlp_loss_grad;
+ * INVALID_ARG (epochs < 1, batch < 1). */
 tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *target, const float *weight,
                          float *params, float *m, float *v, int64_t *step, int32_t epochs,
                          int64_t batch, double lr, double beta1, double beta2, double eps,
@@ -520,6 +586,18 @@ tbk_status tb_build_hamiltonian_learned(const double *pos, const int32_t *specie
  */
 tbk_status kpm_dos(const double *mu, int32_t M, double a, double b, int32_t kernel,
                    const double *E, int32_t nE, double *rho, void *stream);
+
+/*
+ * Average of the moments over the R random vectors (the stochastic trace of
+ * Eq. (4), Sec. 2.4: each vector gives an unbiased estimate, their mean the
+ * estimate kpm_dos reconstructs from):
+ *   mean[s][n] = (1/R) sum_{v=0}^{R-1} mu[s][v][n], summed in v order.
+ *   mu device double [n_seg][R][M] (kpm_moments, kpm_moments_batched);
+ *   mean device double [n_seg][M], caller-allocated (may not alias mu).
+ * Asynchronous on `stream`.  Errors: INVALID_ARG (n_seg, R or M < 1, NULL).
+ */
+tbk_status kpm_mean_moments(const double *mu, int32_t n_seg, int32_t R, int32_t M, double *mean,
+                            void *stream);
 
 /* kpm_dos for n_struct structures in one launch (stacked snapshots):
  *   mu  device double [n_struct][M] (each already averaged over vectors),

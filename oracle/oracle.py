@@ -43,6 +43,9 @@ def _lib():
     L.orc_kpm_moments.restype = ctypes.c_int
     L.orc_kpm_moments.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64, _f64,
                                   _c128p, _i32, _i32, _f64p, _f64p]
+    L.orc_kpm_moments_state.restype = ctypes.c_int
+    L.orc_kpm_moments_state.argtypes = [_i64, _i64p, _i32p, _f64p, _f64p, _f64, _f64,
+                                        _c128p, _i32, _i32, _i32, _c128p, _f64p, _f64p]
     L.orc_jackson.restype = None
     L.orc_jackson.argtypes = [_i32, _f64p]
     L.orc_kpm_dos.restype = ctypes.c_int
@@ -185,6 +188,26 @@ def kpm_moments(csr, a, b, r, M):
     if rc != 0:
         raise OracleError("orc_kpm_moments: invalid argument")
     return mu_re, mu_im
+
+
+def kpm_moments_state(csr, a, b, r, M, n_start=0, state=None, mu_re=None, mu_im=None):
+    """The recurrence split over calls: moments n_start..M-1 written into mu_re, mu_im [R][M]
+    (allocated when None), state [R][2][N] complex128 carrying the last two vectors (allocated
+    when None and n_start = 0).  Returns (mu_re, mu_im, state)."""
+    r = _c(r, np.complex128)
+    if r.ndim == 1:
+        r = r.reshape(-1, 1)
+    n, R = r.shape
+    assert n == csr.n
+    if state is None:
+        state = np.zeros((R, 2, n), dtype=np.complex128)
+    mu_re = np.full((R, M), np.nan) if mu_re is None else mu_re
+    mu_im = np.full((R, M), np.nan) if mu_im is None else mu_im
+    rc = _lib().orc_kpm_moments_state(n, csr.row_ptr, csr.col, csr.val, csr.diag, float(a), float(b),
+                                      r.reshape(-1), R, M, int(n_start), state.reshape(-1), mu_re, mu_im)
+    if rc != 0:
+        raise OracleError("orc_kpm_moments_state: invalid argument")
+    return mu_re, mu_im, state
 
 
 def jackson(M):

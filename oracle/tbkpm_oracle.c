@@ -315,6 +315,58 @@ int orc_kpm_moments(int64_t n, const int64_t *row_ptr, const int32_t *col,
     return 0;
 }
 
+/*
+ * The recurrence of orc_kpm_moments split over calls (a checkpoint of the
+ * Chebyshev expansion): state [R][2][n] carries, per vector, the last two
+ * vectors of the recurrence.  n_start = 0 starts from r (T_0 = r,
+ * T_1 = Htilde r) and writes moments 0..M-1; n_start in [2, M) reads
+ * T_{n_start-2}, T_{n_start-1} from state and writes moments n_start..M-1.
+ * Either way state holds T_{M-2}, T_{M-1} on return, so a run split at any
+ * k performs exactly the operations of the one-shot run.  Returns 0, -1 on
+ * bad arguments, -2 when out of memory.
+ */
+int orc_kpm_moments_state(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                          const double *val, const double *diag, double a, double b,
+                          const double complex *r, int32_t R, int32_t M, int32_t n_start,
+                          double complex *state, double *mu_re, double *mu_im)
+{
+    if (n <= 0 || R < 1 || M < 2 || !(a > 0.0) || !state) return -1;
+    if (!(n_start == 0 || (n_start >= 2 && n_start < M))) return -1;
+    double complex *rv = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t0 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t1 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *t2 = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    if (!rv || !t0 || !t1 || !t2) { free(rv); free(t0); free(t1); free(t2); return -2; }
+    for (int32_t v = 0; v < R; ++v) {
+        double complex *sv = state + (int64_t)v * 2 * n;     /* older, then newer vector */
+        for (int64_t i = 0; i < n; ++i) rv[i] = r[i * R + v];
+        double complex m;
+        int32_t k;
+        if (n_start == 0) {
+            for (int64_t i = 0; i < n; ++i) t0[i] = rv[i];
+            m = orc_dot(n, rv, t0);
+            mu_re[(int64_t)v * M + 0] = creal(m); mu_im[(int64_t)v * M + 0] = cimag(m);
+            orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t0, t1);
+            m = orc_dot(n, rv, t1);
+            mu_re[(int64_t)v * M + 1] = creal(m); mu_im[(int64_t)v * M + 1] = cimag(m);
+            k = 2;
+        } else {
+            for (int64_t i = 0; i < n; ++i) { t0[i] = sv[i]; t1[i] = sv[n + i]; }
+            k = n_start;
+        }
+        for (; k < M; ++k) {
+            orc_apply_scaled(n, row_ptr, col, val, diag, a, b, t1, t2);
+            for (int64_t i = 0; i < n; ++i) t2[i] = 2.0 * t2[i] - t0[i];
+            m = orc_dot(n, rv, t2);
+            mu_re[(int64_t)v * M + k] = creal(m); mu_im[(int64_t)v * M + k] = cimag(m);
+            double complex *tmp = t0; t0 = t1; t1 = t2; t2 = tmp;
+        }
+        for (int64_t i = 0; i < n; ++i) { sv[i] = t0[i]; sv[n + i] = t1[i]; }
+    }
+    free(rv); free(t0); free(t1); free(t2);
+    return 0;
+}
+
 /* Jackson damping factors g_n, n = 0..M-1, for an expansion of M moments. */
 void orc_jackson(int32_t M, double *g)
 {

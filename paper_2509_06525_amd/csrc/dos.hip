@@ -146,6 +146,18 @@ __global__ void k_mobility(const double *__restrict__ sigma, int32_t F, int32_t 
     mobility[e] = nb != 0.0 ? 0.1 * best / fabs(nb) : __builtin_nan("");
 }
 
+// mean[s][n] = (1/R) sum_v mu[s][v][n], the sum over v in index order.
+__global__ void k_mean_moments(const double *__restrict__ mu, int32_t n_seg, int32_t R, int32_t M,
+                               double *__restrict__ mean) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_seg * M) return;
+    const int64_t s = idx / M, n = idx % M;
+    const double *p = mu + s * R * (int64_t)M + n;
+    double acc = 0.0;
+    for (int32_t v = 0; v < R; ++v) acc += p[(int64_t)v * M];
+    mean[idx] = acc / R;
+}
+
 tbk_status check_dos(int32_t M, int32_t nE, int32_t kernel) {
     TBK_CHECK(M >= 1, TBK_ERR_INVALID_ARG, "M = %d < 1", M);
     TBK_CHECK(nE >= 0, TBK_ERR_INVALID_ARG, "nE = %d < 0", nE);
@@ -170,6 +182,17 @@ extern "C" tbk_status kpm_dos(const double *mu, int32_t M, double a, double b, i
     hipStream_t s = as_stream(stream);
     k_dos<<<dim3((unsigned)ceil_div(nE, kDosThreads), 1), kDosThreads, 0, s>>>(mu, M, a, b, nullptr, kernel, E, 0,
                                                                                nE, rho);
+    TBK_HIP(hipGetLastError());
+    return TBK_OK;
+}
+
+extern "C" tbk_status kpm_mean_moments(const double *mu, int32_t n_seg, int32_t R, int32_t M, double *mean,
+                                       void *stream) {
+    clear_error();
+    TBK_CHECK(n_seg >= 1 && R >= 1 && M >= 1, TBK_ERR_INVALID_ARG, "n_seg = %d, R = %d, M = %d", n_seg, R, M);
+    TBK_CHECK(mu && mean, TBK_ERR_INVALID_ARG, "NULL argument");
+    const int64_t n = (int64_t)n_seg * M;
+    k_mean_moments<<<(unsigned)ceil_div(n, 256), 256, 0, as_stream(stream)>>>(mu, n_seg, R, M, mean);
     TBK_HIP(hipGetLastError());
     return TBK_OK;
 }

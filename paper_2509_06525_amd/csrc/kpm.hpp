@@ -6,6 +6,9 @@
 
 namespace tbk {
 
+constexpr int kReduceChunk = 2048;                 // partials per first-level reduction block
+constexpr size_t kPartialBudget = 256ull << 20;    // bytes of block partials kept between reductions
+
 struct KpmPlan {
     tbk_kpm_config cfg{};
     int Rp = 1, L = 1, VPT = 1, log2_slice = 0, n_chunks = 1, reduce_every = 1;
@@ -15,14 +18,29 @@ struct KpmPlan {
     bool tile_is_slice = false;
     int uniform_width = 0;      // > 0 when every slice stores this many entries per row
     size_t elem = 0, vec_bytes = 0;
-    size_t off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0, total = 0;
+    size_t off_state = 0, off_r = 0, off_a = 0, off_b = 0, off_part = 0, off_l1 = 0, off_raw = 0, off_flag = 0,
+           total = 0;
     bool block = false;         // block Hamiltonian (kpm_block.hip)
     int norb = 1;               // orbitals per atom of a block Hamiltonian (4 or 9)
     bool geom = false;          // blocks formed in the step from bond displacements
     double geom_params[12] = {};   // integrals at r0, r0, beta (h->sk_geom)
     bool seeded = false;        // start vectors generated on the device from `seed`
     uint64_t seed = 0;
+    int32_t n_start = 0;        // 0: fresh run; >= 2: continue from the state kept in the workspace
 };
+
+// Leading bytes of the recurrence workspace: the record of the last completed
+// run, which a later call with n_start > 0 continues.  The vectors r, T_a, T_b
+// follow at offsets that depend only on (rows, R, precision), not on M.
+struct KpmState {
+    uint64_t magic;             // kStateMagic once a run has completed
+    int64_t n_rows, n_entries;
+    int32_t R, precision, fmt, next_n;   // next_n = M of that run: the next moment to compute
+    double a, b;
+};
+constexpr uint64_t kStateMagic = 0x54424b504d535431ull;
+constexpr size_t kStateMu0 = 512;      // byte offset of mu_0 per vector (<= 64 doubles)
+constexpr size_t kStateBytes = 1024;
 
 // Per-launch scalars of a step (pointers go as separate restrict parameters).
 template <class VT> struct StepScalars {
@@ -72,5 +90,11 @@ tbk_status check_moment_args(const tbk_ham *h, const KpmPlan &pl, const double *
 tbk_status run_plan(const tbk_ham *h, const KpmPlan &pl, double a, double b, const void *r, int32_t R,
                     int32_t M, int32_t precision, char *w, double *mu, hipStream_t s,
                     const void *start = nullptr, const void *left = nullptr);
+
+// One run of the recurrence for vector type VT (double: c128, float: c64), L
+// threads per row and VPT vectors per thread; instantiated in kpm_inst_*.hip.
+template <class VT, int L, int VPT>
+tbk_status run_moments_inst(const tbk_ham *h, const KpmPlan &pl, double a, double b, const VT *r, int32_t R,
+                            int32_t M, char *work, double *mu, hipStream_t s, const VT *start, const VT *left);
 
 }  // namespace tbk

@@ -89,4 +89,15 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[VPT], double *p
     }
 }
 
+// Counter-based random phase exp(i phi) of output k of SplitMix64 started at
+// `seed` (Steele, Lea & Flood 2014): phi = 2 pi (x >> 11) 2^-53.
+__device__ __forceinline__ void seeded_phase(uint64_t seed, uint64_t k, double &c, double &s) {
+    uint64_t z = seed + (k + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    const double phi = 6.283185307179586 * ((double)(z >> 11) * 0x1p-53);
+    sincos(phi, &s, &c);
+}
+
 }  // namespace tbk

@@ -14,7 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtbkpm.so")
 
 TBK_OK = 0
+TBK_ERR_INVALID_ARG = 1
 TBK_ERR_BUFFER_TOO_SMALL = 2
+TBK_ERR_NOT_FINITE = 3
+TBK_ERR_SPECTRUM = 4
 TBK_MLP_PARAMS = 1633      # parameters of one per-bond network (W1, b1, W2, b2, W3, b3)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "BUFFER_TOO_SMALL", 3: "NOT_FINITE",
                 4: "SPECTRUM", 5: "UNSUPPORTED", 6: "DEVICE"}
@@ -54,7 +57,8 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_hamiltonian_size_batched", "tb_build_hamiltonian_batched",
                "tbk_hamiltonian_size_sk", "tb_build_hamiltonian_sk",
                "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
-               "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
+               "kpm_scale", "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
+               "kpm_mean_moments",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -162,13 +166,17 @@ def lib():
     L.kpm_workspace_size.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, ctypes.POINTER(i64)]
     L.kpm_moments.restype = ctypes.c_int
     L.kpm_moments.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64), vp,
-                              i32, i32, i32, vp, i64, vp, vp]
+                              i32, i32, i32, i32, vp, i64, vp, vp]
+    L.kpm_scale.restype = ctypes.c_int
+    L.kpm_scale.argtypes = [i32, ctypes.POINTER(f64), f64, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    L.kpm_mean_moments.restype = ctypes.c_int
+    L.kpm_mean_moments.argtypes = [vp, i32, i32, i32, vp, vp]
     L.kpm_workspace_size_config.restype = ctypes.c_int
     L.kpm_workspace_size_config.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32,
                                             ctypes.POINTER(KpmConfig), ctypes.POINTER(i64)]
     L.kpm_moments_config.restype = ctypes.c_int
     L.kpm_moments_config.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64),
-                                     vp, i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+                                     vp, i32, i32, i32, ctypes.POINTER(KpmConfig), i32, vp, i64, vp, vp]
     L.tbk_autotune.restype = ctypes.c_int
     L.tbk_autotune.argtypes = [vp, vp, i64, ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(TbParams),
                                i32, i32, i32, i32, ctypes.POINTER(TuneResult), vp]
@@ -228,7 +236,8 @@ def lib():
                                                ctypes.POINTER(f64), vp, i64, ctypes.POINTER(i64), vp]
     L.kpm_moments_seeded.restype = ctypes.c_int
     L.kpm_moments_seeded.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64),
-                                     ctypes.c_uint64, i32, i32, i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+                                     ctypes.c_uint64, i32, i32, i32, ctypes.POINTER(KpmConfig), i32, vp, i64, vp,
+                                     vp]
     L.tbk_random_phase.restype = ctypes.c_int
     L.tbk_random_phase.argtypes = [ctypes.c_uint64, i64, i32, i32, vp, vp]
     L.tb_build_velocity.restype = ctypes.c_int
@@ -335,9 +344,10 @@ class Hamiltonian:
         return self.tensors["perm"]
 
     def scale(self, margin=1.01):
-        """(a, b) with a = margin (E_hi - E_lo)/2, b = (E_hi + E_lo)/2 from the Gershgorin bounds."""
-        lo, hi = self.bounds
-        return margin * (hi - lo) / 2.0, (hi + lo) / 2.0
+        """(a, b) of the library's kpm_scale from the Gershgorin bounds:
+        a = margin (E_hi - E_lo)/2, b = (E_hi + E_lo)/2."""
+        a, b = kpm_scale([self.bounds], margin)
+        return a[0], b[0]
 
     def nbytes(self):
         return sum(t.numel() * t.element_size() for t in self.tensors.values())
@@ -526,25 +536,53 @@ def alloc_workspace(H, R, M, precision, device=None, config=None):
     return torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
 
-def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, config=None):
-    """Chebyshev moments mu[v][n] (float64, device) of Ht = (H - b)/a for vectors r [N, R]."""
+def kpm_scale(bounds, margin=1.01):
+    """Lists (a, b) from spectral bounds [(E_lo, E_hi), ...] by the library's kpm_scale."""
+    n = len(bounds)
+    sb = _f64arr([float(v) for lo_hi in bounds for v in lo_hi])
+    a, b = (ctypes.c_double * n)(), (ctypes.c_double * n)()
+    _check(lib().kpm_scale(n, sb, float(margin), a, b))
+    return list(a), list(b)
+
+
+def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, config=None, n_start=0, R=None):
+    """Chebyshev moments mu[v][n] (float64, device) of Ht = (H - b)/a for vectors r [N, R].
+
+    n_start > 0 continues the run whose state `work` holds (r may then be None,
+    with R given); only mu[:, n_start:] is written."""
     L = lib()
-    if precision is None:
-        precision = "c32" if r.dtype == torch.complex64 else "f64"
-    want = torch.complex64 if precision == "c32" else torch.complex128
-    r = _dev(r, want)
-    if r.dim() == 1:
-        r = r.reshape(-1, 1)
-    R = r.shape[1]
+    if r is not None:
+        if precision is None:
+            precision = "c32" if r.dtype == torch.complex64 else "f64"
+        want = torch.complex64 if precision == "c32" else torch.complex128
+        r = _dev(r, want)
+        if r.dim() == 1:
+            r = r.reshape(-1, 1)
+        R = r.shape[1]
+    elif R is None or precision is None or work is None:
+        raise ValueError("continuing a run without r needs R, precision and its work")
+    dev = H.tensors["ptr"].device
     if work is None:
-        work = alloc_workspace(H, R, M, precision, r.device, config)
+        work = alloc_workspace(H, R, M, precision, dev, config)
     if mu is None:
-        mu = torch.empty((R, M), dtype=torch.float64, device=r.device)
+        mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     av = (ctypes.c_double * 1)(float(a))
     bv = (ctypes.c_double * 1)(float(b))
-    _check(L.kpm_moments_config(ctypes.byref(H.st), av, bv, _ptr(r), R, int(M), PRECISIONS[precision],
-                                _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu), _stream(stream)))
+    _check(L.kpm_moments_config(ctypes.byref(H.st), av, bv, _ptr(r), int(R), int(M), PRECISIONS[precision],
+                                _cfg_ref(config), int(n_start), _ptr(work), work.numel(), _ptr(mu),
+                                _stream(stream)))
     return mu
+
+
+def mean_moments(mu, stream=None):
+    """Average over the vectors on the device: mu [R, M] -> [M], or [S, R, M] -> [S, M]."""
+    mu = _dev(mu, torch.float64)
+    one = mu.dim() == 2
+    m3 = mu.reshape(1, *mu.shape) if one else mu
+    S, R, M = m3.shape
+    out = torch.empty((S, M), dtype=torch.float64, device=mu.device)
+    _check(lib().kpm_mean_moments(_ptr(m3), S, R, M, _ptr(out), _stream(stream)))
+    return out[0] if one else out
 
 
 def random_phase(seed, n, R, precision="c32", device="cuda", stream=None):
@@ -556,7 +594,8 @@ def random_phase(seed, n, R, precision="c32", device="cuda", stream=None):
     return r
 
 
-def kpm_moments_seeded(H, a, b, seed, R, M, precision="c32", work=None, mu=None, stream=None, config=None):
+def kpm_moments_seeded(H, a, b, seed, R, M, precision="c32", work=None, mu=None, stream=None, config=None,
+                       n_start=0):
     """kpm_moments with the random-phase start vectors generated on the device from `seed`."""
     L = lib()
     dev = H.tensors["ptr"].device
@@ -566,8 +605,8 @@ def kpm_moments_seeded(H, a, b, seed, R, M, precision="c32", work=None, mu=None,
         mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     av, bv = (ctypes.c_double * 1)(float(a)), (ctypes.c_double * 1)(float(b))
     _check(L.kpm_moments_seeded(ctypes.byref(H.st), av, bv, int(seed) & (2**64 - 1), int(R), int(M),
-                                PRECISIONS[precision], _cfg_ref(config), _ptr(work), work.numel(), _ptr(mu),
-                                _stream(stream)))
+                                PRECISIONS[precision], _cfg_ref(config), int(n_start), _ptr(work), work.numel(),
+                                _ptr(mu), _stream(stream)))
     return mu
 
 
@@ -621,9 +660,8 @@ class BatchedHamiltonian(Hamiltonian):
         return self.st.n_seg
 
     def scales(self, margin=1.01):
-        a = [margin * (hi - lo) / 2.0 for lo, hi in self.bounds]
-        b = [(hi + lo) / 2.0 for lo, hi in self.bounds]
-        return a, b
+        """Lists (a, b) of kpm_scale over the structures' Gershgorin bounds."""
+        return kpm_scale(self.bounds, margin)
 
 
 def build_hamiltonian_batched(pos, species, seg_atoms, boxes, periodic, onsite, t_pair, r_cut=2.0, r0=1.42,

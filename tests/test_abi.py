@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_version_and_error_text_without_gpu(lib):
     """The version, and a successful call leaves the thread's error text empty
     (whatever an earlier call on this thread left there)."""
-    assert lib.tbk_abi_version() == 11
+    assert lib.tbk_abi_version() == 12
     st = tbkpm.HamStruct(fmt=2, slice=256, n_rows=10)
     out = ctypes.c_int64(0)
     assert lib.kpm_workspace_size(ctypes.byref(st), 0, 10, 1, ctypes.byref(out)) == 1
@@ -85,3 +85,21 @@ def test_post_processing_checks_without_gpu(lib):
     assert lib.lsqt_mobility(None, 2, 3, 5, None, float("inf"), None, None, None, None) != 0
     assert lib.lsqt_mobility(None, 2, 3, 5, None, 1.0, None, None, None, None) == 1
     assert b"NULL" in lib.tbk_last_error()
+
+
+def test_scale_is_host_arithmetic(lib):
+    """kpm_scale (no device call): a = margin (E_hi - E_lo)/2, b = (E_hi + E_lo)/2 per
+    system; bad bounds or margins are refused and nothing is written."""
+    a, b = tbkpm.kpm_scale([(-8.1, 8.1), (-4.0, 2.0)], 1.01)
+    assert a == [1.01 * 8.1, 1.01 * 3.0] and b == [0.0, -1.0]
+    a, b = tbkpm.kpm_scale([(-3.25, 5.5)], 1.0)
+    assert (a, b) == ([4.375], [1.125])          # exact in binary
+    sb = (ctypes.c_double * 2)(1.0, 1.0)
+    av, bv = (ctypes.c_double * 1)(7.0), (ctypes.c_double * 1)(7.0)
+    assert lib.kpm_scale(1, sb, 1.01, av, bv) == tbkpm.TBK_ERR_INVALID_ARG     # single-point spectrum
+    assert (av[0], bv[0]) == (7.0, 7.0)
+    sb = (ctypes.c_double * 4)(-1.0, 1.0, float("nan"), 1.0)
+    assert lib.kpm_scale(2, sb, 1.01, av, bv) == tbkpm.TBK_ERR_NOT_FINITE
+    sb = (ctypes.c_double * 2)(-1.0, 1.0)
+    assert lib.kpm_scale(1, sb, 0.99, av, bv) == tbkpm.TBK_ERR_INVALID_ARG     # margin < 1
+    assert lib.kpm_scale(0, sb, 1.01, av, bv) == tbkpm.TBK_ERR_INVALID_ARG

@@ -113,3 +113,54 @@ def test_guard_violated_when_scale_too_small():
     a = 0.5 * (hi - lo) / 2
     mu, _ = O.kpm_moments(csr, a, 0.0, synth.random_phase(s.n, 1, 3), 64)
     assert np.abs(mu).max() > mu[0, 0] * 10
+
+
+@pytest.mark.parametrize("split", [(2,), (37,), (2, 3, 50, 99), (98,)])
+def test_split_run_equals_one_shot_exactly(split):
+    """Checkpoint/resume of the recurrence (Sec. 2.4's Chebyshev expansion, continued
+    from its last two vectors): a run split at any k repeats the one-shot run's
+    operations, so every moment is bit for bit the one-shot moment."""
+    s = synth.graphene_sheet(5, 4, 0.05, 21)
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    lo, hi = O.gershgorin(csr)
+    a, b = 1.01 * (hi - lo) / 2, (hi + lo) / 2 + 0.1
+    r = synth.random_phase(s.n, 3, 5, np.complex128)
+    M = 100
+    re1, im1 = O.kpm_moments(csr, a, b, r, M)
+    stops = list(split) + [M]
+    re2, im2, state = O.kpm_moments_state(csr, a, b, r, stops[0])
+    mu_re, mu_im = np.full((3, M), np.nan), np.full((3, M), np.nan)
+    mu_re[:, :stops[0]], mu_im[:, :stops[0]] = re2, im2
+    for k0, k1 in zip(stops[:-1], stops[1:]):
+        part_re, part_im = np.full((3, k1), np.nan), np.full((3, k1), np.nan)
+        O.kpm_moments_state(csr, a, b, r, k1, n_start=k0, state=state, mu_re=part_re, mu_im=part_im)
+        assert np.isnan(part_re[:, :k0]).all()          # nothing below n_start is written
+        mu_re[:, k0:k1], mu_im[:, k0:k1] = part_re[:, k0:], part_im[:, k0:]
+    np.testing.assert_array_equal(mu_re, re1)
+    np.testing.assert_array_equal(mu_im, im1)
+
+
+def test_split_run_keeps_the_ring_closed_form():
+    """The continued recurrence still gives Tr T_m = (-1)^m n for n | m on a ring
+    (a pin of the continuation that does not go through the one-shot routine)."""
+    n = 9
+    csr = ring(n)
+    eye = np.eye(n, dtype=np.complex128)
+    M = 3 * n + 2
+    re, _, st = O.kpm_moments_state(csr, 5.4, 0.0, eye, 10)
+    full = np.full((n, M), np.nan)
+    full[:, :10] = re
+    O.kpm_moments_state(csr, 5.4, 0.0, eye, M, n_start=10, state=st, mu_re=full, mu_im=np.empty((n, M)))
+    m = np.arange(M)
+    expect = np.where(m % n == 0, (-1.0) ** m * n, 0.0)
+    np.testing.assert_allclose(full.sum(axis=0), expect, atol=1e-10)
+
+
+def test_split_run_rejects_bad_starts():
+    s = synth.graphene_sheet(2, 2)
+    csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
+    r = np.ones((s.n, 1), np.complex128)
+    st = np.zeros((1, 2, s.n), np.complex128)
+    for k in (1, 10, 11, -1):
+        with pytest.raises(O.OracleError):
+            O.kpm_moments_state(csr, 9.0, 0.0, r, 10, n_start=k, state=st)
