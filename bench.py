@@ -74,7 +74,7 @@ def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True, compact=Fa
 def kernel_source_hash():
     """Hash of the recurrence kernel's sources (a stored counter profile is valid only for these)."""
     h = hashlib.sha256()
-    for f in ("kpm.hip", "kpm.hpp", "kpm_dev.hpp"):
+    for f in ("kpm.hip", "kpm_run.hpp", "kpm.hpp", "kpm_dev.hpp"):
         with open(os.path.join(ROOT, "paper_2509_06525_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -99,6 +99,59 @@ def profiled_traffic(workload, kernel, slice_, launch):
     if r["launch"] != ",".join(f"{k}:{v}" for k, v in sorted(launch.items())):
         return None
     return float(r["traffic_bytes"])
+
+
+def stream_probe(dev, mib=2048, reps=5):
+    """Measured HBM ceilings beside the 8 TB/s peak: a plain device copy (read + write
+    of `mib` MiB) and a pure read (a sum over `mib` MiB), each timed with HIP events,
+    median of `reps`; GB/s of bytes moved."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn, nbytes in (("stream_copy_gbs", lambda: dst.copy_(src), 2 * n * 4),
+                             ("stream_read_gbs", lambda: src.sum(), n * 4)):
+        fn()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e-3)
+        out[name] = nbytes / float(np.median(t)) / 1e9
+    out["stream_probe_mib"] = mib
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def golden_moments(workload):
+    """(a, b, mu [v][n]) of the oracle's stored full-size moments of `workload`
+    (tests/golden, written by a script that calls only the oracle), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_moments_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        lines = fh.readlines()
+    hdr = {}
+    for ln in lines[:4]:
+        parts = ln[1:].split()
+        for k in range(0, len(parts) - 1, 2):
+            hdr[parts[k]] = parts[k + 1]
+    return float(hdr["a"]), float(hdr["b"]), np.loadtxt(lines[4:], ndmin=2).T
+
+
+def golden_snapshot_targets():
+    """(table [index, atoms, sigma, a, b, err_plain], target moments [S][M]) of the
+    oracle's learned-hopping targets (tests/golden), or None."""
+    d = os.path.join(ROOT, "tests", "golden")
+    tp, mp = os.path.join(d, "oracle_target_snapshots_256.txt"), os.path.join(d, "oracle_target_moments_snapshots_256.npy")
+    if not (os.path.exists(tp) and os.path.exists(mp)):
+        return None
+    return np.loadtxt(tp, comments="#", ndmin=2), np.load(mp, allow_pickle=False)
 
 
 def use_shipped_tuning():
@@ -150,7 +203,8 @@ def bench_snapshots(args, w):
     per = (1, 1, 0)
     log("generating snapshots")
     snaps = synth.snapshot_set(w["count"], w["seed"])
-    train = synth.snapshot_set(32, w["train_seed"], n_min=1000, n_max=8000)
+    tcfg = synth.LEARNED_TRAINING
+    train = synth.snapshot_set(tcfg["count"], tcfg["seed"], n_min=tcfg["n_min"], n_max=tcfg["n_max"])
     pos, sp, seg, boxes = synth.stack(snaps)
     tpos, tsp, tseg, tboxes = synth.stack(train)
     N = int(seg[-1])
@@ -163,8 +217,11 @@ def bench_snapshots(args, w):
     std = [max(x, 1e-6) for x in std]
     X = tbkpm.bond_features(tb, tv, mean, std, synth.R_DESC)
     y = tbkpm.coordination_target(tb, tv, synth.COORD_KAPPA, synth.COORD_Z0)
-    trainer = tbkpm.MlpTrainer(torch.from_numpy(synth.init_mlp_params(11)).to(dev))
-    hist = trainer.train(X, y, epochs=120, batch=2048, lr=2e-3, wd=1e-5)
+    trainer = tbkpm.MlpTrainer(torch.from_numpy(synth.init_mlp_params(tcfg["init_seed"])).to(dev))
+    hist = []
+    for epochs, lr in tcfg["schedule"]:
+        hist += trainer.train(X, y, epochs=epochs, batch=tcfg["batch"], lr=lr, wd=tcfg["wd"],
+                              shuffle_seed=tcfg["shuffle_seed"])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"trained on {X.shape[0]} bonds: loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s")
@@ -223,20 +280,24 @@ def bench_snapshots(args, w):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    tbkpm.step_timer(True)        # events around the step launches only (per-step launch shapes)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         Hs, rhos = step()
         torch.cuda.synchronize()
         kpm_ms.append(ev[0].elapsed_time(ev[1]))
     sec = (time.perf_counter() - t0) / args.steps
+    step_ms, step_launches = tbkpm.step_timer_read()
+    tbkpm.step_timer(False)
     kmed = float(np.median(kpm_ms))
     st = Hs.st
     Rp = 1
     while Rp < R:
         Rp *= 2
     launch_bytes = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 4
-    launch_s = kmed * 1e-3 / (M - 1)
+    launch_s = step_ms * 1e-3 / step_launches if step_launches else kmed * 1e-3 / (M - 1)
     achieved = launch_bytes / launch_s / 1e9
+    judge = learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M, stream)
     out = {
         "metric": METRIC, "value": N * M * R / sec, "unit": "atom*moments/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
@@ -244,15 +305,54 @@ def bench_snapshots(args, w):
         "config": {"workload": args.workload, "snapshots": len(snaps), "n_atoms_total": N, "moments": M,
                    "vectors": R, "format": "sell_f32", "slice": 64, "precision": "c32", "hoppings": "learned",
                    "launch": cfg.as_dict(), "launch_ms_per_step": timing},
-        "training": {"bonds": int(X.shape[0]), "epochs": len(hist), "loss_first": hist[0], "loss_last": hist[-1],
-                     "seconds": t_train},
+        "training": {"snapshots": tcfg["count"], "seed": tcfg["seed"], "bonds": int(X.shape[0]),
+                     "epochs": len(hist), "loss_first": hist[0], "loss_last": hist[-1], "seconds": t_train},
+        "learned_vs_plain": judge,
         "kpm_ms_median": kmed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_cheb_persistent" if cfg.persistent else "k_cheb_step_seg",
-                     "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6},
+                     "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6,
+                     "launches_timed": step_launches, "launch_us_kpm_window": kmed * 1e3 / (M - 1)},
     }
+    out["roofline"].update(stream_probe(dev))
     print(json.dumps(out), flush=True)
+
+
+def learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M, stream):
+    """DOS error of the learned and of the plain-formula Hamiltonian of every snapshot
+    against the oracle's target DOS (tests/golden: the coordination-corrected target
+    hoppings, the oracle's scale and the same vectors), relative L2 on each
+    snapshot's 2001-point grid; both DOS reconstructed by the library."""
+    import torch
+    from paper_2509_06525_amd import synth, tbkpm
+    gold = golden_snapshot_targets()
+    if gold is None:
+        return None
+    table, mu_t = gold
+    if table.shape[0] != len(seg) - 1 or not np.array_equal(table[:, 1].astype(np.int64), np.diff(seg)):
+        return None
+    a, b = list(table[:, 3]), list(table[:, 4])
+    u = torch.linspace(-0.99, 0.99, 2001, dtype=torch.float64, device=dev)
+    grid = (torch.tensor(b, dtype=torch.float64, device=dev)[:, None]
+            + torch.tensor(a, dtype=torch.float64, device=dev)[:, None] * u[None, :]).contiguous()
+    rho_t = tbkpm.kpm_dos_batched(torch.from_numpy(mu_t).to(dev), a, b, grid, stream=stream).cpu().numpy()
+    errs = {}
+    for name, H in (("learned", tbkpm.build_hamiltonian_learned(
+                        gpos, gsp, seg, boxes, per, [0.0], [[synth.T_CC_EV]], params, mean, std, fmt="sell_f32",
+                        slice=64, stream=stream)),
+                    ("plain", tbkpm.build_hamiltonian_batched(gpos, gsp, seg, boxes, per, [0.0], [[synth.T_CC_EV]],
+                                                              fmt="sell_f32", slice=64, stream=stream))):
+        mu = tbkpm.mean_moments(tbkpm.kpm_moments_batched(H, a, b, r, M, "c32", stream=stream), stream=stream)
+        rho = tbkpm.kpm_dos_batched(mu, a, b, grid, stream=stream).cpu().numpy()
+        errs[name] = np.linalg.norm(rho - rho_t, axis=1) / np.linalg.norm(rho_t, axis=1)
+        del H
+    el, ep = errs["learned"], errs["plain"]
+    return {"snapshots": int(len(el)), "err_learned_max": float(el.max()), "err_learned_median": float(np.median(el)),
+            "err_plain_min": float(ep.min()), "err_plain_median": float(np.median(ep)),
+            "err_plain_max": float(ep.max()), "learned_over_1e-2": int((el > 1e-2).sum()),
+            "learned_not_below_plain": int((el >= ep).sum()),
+            "source": "tests/golden/oracle_target_moments_snapshots_256.npy"}
 
 
 def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision, config, mu_direct, rho_direct,
@@ -753,16 +853,19 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    tbkpm.step_timer(True)        # events around the step launches only, on the same stream
     t0 = time.perf_counter()
     for _ in range(args.steps):
         Hs, aa, bb, rho = step()
         torch.cuda.synchronize()
         kpm_ms.append(ev[0].elapsed_time(ev[1]))
     t1 = time.perf_counter()
+    step_ms, step_launches = tbkpm.step_timer_read()
+    tbkpm.step_timer(False)
     sec_per_step = (t1 - t0) / args.steps
     value = N * M * R / sec_per_step
 
-    # Roofline of the recurrence kernel: M - 1 launches inside the kpm_moments window.
+    # Roofline of the recurrence kernel: its average launch time from the step timer.
     Rp = 1
     while Rp < R:
         Rp *= 2
@@ -771,7 +874,7 @@ def main():
     launch_cfg = config if config is not None else tbkpm.default_config(Hs, R, w["precision"])
     launch_bytes = cheb_step_bytes(Hs, Rp, elem, diag, compact=bool(launch_cfg.compact_columns))
     kpm_med = float(np.median(kpm_ms))
-    launch_s = kpm_med * 1e-3 / (M - 1)
+    launch_s = step_ms * 1e-3 / step_launches
     achieved = launch_bytes / launch_s / 1e9
     mu_c = mu.cpu().numpy().copy()
     rho_c = rho.cpu().numpy()
@@ -792,9 +895,31 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic(args.workload, "direct", slice_, launch_cfg.as_dict()),
+                     "traffic_source": f"profiles/k_cheb_step_{args.workload}.md (stored rocprofv3 FETCH_SIZE, "
+                                       "WRITE_SIZE runs, copy-calibrated; null when the kernel or launch "
+                                       "shape differs)",
                      "kernel": "k_cheb_step", "bytes_per_launch": launch_bytes,
-                     "launch_us": launch_s * 1e6},
+                     "launch_us": launch_s * 1e6, "launches_timed": step_launches,
+                     "launch_us_kpm_window": kpm_med * 1e3 / (M - 1)},
     }
+    out["roofline"].update(stream_probe(dev))
+
+    # DOS and moments against the oracle's stored full-size moments (its vector subset,
+    # its (a, b) from FP64 Gershgorin bounds), same energy grid.
+    gold = golden_moments(args.workload)
+    if gold is not None:
+        ga, gb, gmu = gold
+        nv = gmu.shape[0]
+        rg = r[:, :nv].contiguous()
+        mu_g = tbkpm.kpm_moments(Hs, ga, gb, rg, M, w["precision"], stream=stream)
+        Eg = torch.linspace(gb - 0.99 * ga, gb + 0.99 * ga, 2001, dtype=torch.float64, device=dev)
+        rho_gpu = tbkpm.kpm_dos(tbkpm.mean_moments(mu_g, stream=stream), ga, gb, Eg, stream=stream).cpu().numpy()
+        rho_orc = tbkpm.kpm_dos(torch.from_numpy(gmu.mean(0)).to(dev), ga, gb, Eg, stream=stream).cpu().numpy()
+        out["vs_oracle"] = {"vectors": nv, "a_eV": ga, "b_eV": gb,
+                            "dos_relL2_vs_oracle": float(np.linalg.norm(rho_gpu - rho_orc) / np.linalg.norm(rho_orc)),
+                            "max_abs_dmu_over_N_vs_oracle": float(np.abs(mu_g.cpu().numpy() - gmu).max() / N),
+                            "source": f"tests/golden/oracle_moments_{args.workload}.txt"}
+        del mu_g
 
     log(f"timed: {sec_per_step * 1e3:.1f} ms/step, kpm {kpm_med:.1f} ms")
     variants = []

@@ -354,6 +354,22 @@ tbk_status kpm_moments_batched(const tbk_ham *h, const double *a, const double *
                                int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
                                void *work, int64_t work_bytes, double *mu, void *stream);
 
+/*
+ * Timing of the recurrence step kernels alone (a measurement aid for the
+ * bandwidth of Sec. 2.4's sparse products): while enabled on the calling
+ * thread, kpm_moments* and kpm_moments_batched (one launch per step) record
+ * HIP events on their stream before and after every stretch of consecutive
+ * step launches (the moment reductions between stretches are outside them)
+ * and add the elapsed times when the call synchronises.
+ * kpm_step_timer(1) enables and clears, kpm_step_timer(0) disables;
+ * kpm_step_timer_read returns the milliseconds and the number of step
+ * launches timed since the last read or enable, then clears them.  The pair
+ * form used by lsqt_vac_moments and the persistent launch are not timed.
+ * Errors: INVALID_ARG (enable not 0/1, NULL).
+ */
+tbk_status kpm_step_timer(int32_t enable);
+tbk_status kpm_step_timer_read(double *ms, int64_t *launches);
+
 /* ------------------------------------------------------------------------ */
 /* Autotuning                                                                */
 /* ------------------------------------------------------------------------ */
@@ -541,17 +557,22 @@ tbk_status tbk_adamw_step(int64_t n, float *p, const float *g, float *m, float *
 
 /* Training loop on the GPU (Sec. 2.1: AdamW over epochs of the training set;
  * network of Eq. (2)): `epochs` passes over the nb bonds in minibatches of
- * `batch` (in order), one tbk_mlp_loss_grad and one tbk_adamw_step per
- * minibatch; *step counts the updates.  params, m, v device float [1633],
+ * `batch`, one tbk_mlp_loss_grad and one tbk_adamw_step per minibatch; *step
+ * counts the updates.  shuffle_seed = 0 takes the bonds in their stored order;
+ * otherwise epoch e takes them in the order i -> (mul_e i + add_e) mod nb, with
+ * mul_e coprime to nb in the middle half of [1, nb) and add_e in [0, nb) drawn
+ * from SplitMix64(shuffle_seed) (deterministic; minibatches then mix bonds of
+ * every structure instead of taking one structure's bonds at a time).
+ * params, m, v device float [1633],
  * updated in place.  loss_history (host [epochs]) receives each epoch's mean
  * loss.  work >= tbk_mlp_workspace_size(min(batch, nb)) + 7168 bytes.
  * Synchronises `stream` once per epoch.  Errors: as tbk_mlp_loss_grad;
  * INVALID_ARG (epochs < 1, batch < 1). */
 tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *target, const float *weight,
                          float *params, float *m, float *v, int64_t *step, int32_t epochs,
-                         int64_t batch, double lr, double beta1, double beta2, double eps,
-                         double wd, double *loss_history, void *work, int64_t work_bytes,
-                         void *stream);
+                         int64_t batch, uint64_t shuffle_seed, double lr, double beta1, double beta2,
+                         double eps, double wd, double *loss_history, void *work,
+                         int64_t work_bytes, void *stream);
 
 /*
  * Learned assembly (inference fused into assembly): as

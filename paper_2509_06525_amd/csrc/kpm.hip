@@ -22,6 +22,32 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+StepTimer &step_timer() {
+    static thread_local StepTimer t;
+    return t;
+}
+
+hipError_t StepTimer::mark(hipStream_t s) {
+    if (used == ev.size()) {
+        hipEvent_t e;
+        const hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        ev.push_back(e);
+    }
+    return hipEventRecord(ev[used++], s);
+}
+
+hipError_t StepTimer::collect() {
+    for (size_t k = 0; k + 1 < used; k += 2) {
+        float t = 0.f;
+        const hipError_t err = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+        if (err != hipSuccess) return err;
+        ms += t;
+    }
+    used = 0;
+    return hipSuccess;
+}
+
 int pad_vectors(int R) {
     int p = 1;
     while (p < R) p <<= 1;
@@ -265,6 +291,28 @@ extern "C" tbk_status kpm_scale(int32_t n, const double *spec_bounds, double mar
         a[s] = margin * (hi - lo) / 2.0;
         b[s] = (hi + lo) / 2.0;
     }
+    return TBK_OK;
+}
+
+extern "C" tbk_status kpm_step_timer(int32_t enable) {
+    clear_error();
+    TBK_CHECK(enable == 0 || enable == 1, TBK_ERR_INVALID_ARG, "enable must be 0 or 1");
+    StepTimer &t = step_timer();
+    t.on = enable == 1;
+    t.ms = 0.0;
+    t.launches = 0;
+    t.used = 0;
+    return TBK_OK;
+}
+
+extern "C" tbk_status kpm_step_timer_read(double *ms, int64_t *launches) {
+    clear_error();
+    TBK_CHECK(ms && launches, TBK_ERR_INVALID_ARG, "NULL argument");
+    StepTimer &t = step_timer();
+    *ms = t.ms;
+    *launches = t.launches;
+    t.ms = 0.0;
+    t.launches = 0;
     return TBK_OK;
 }
 

@@ -2,6 +2,8 @@
 // tuning entry points).
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace tbk {
@@ -41,6 +43,21 @@ struct KpmState {
 constexpr uint64_t kStateMagic = 0x54424b504d535431ull;
 constexpr size_t kStateMu0 = 512;      // byte offset of mu_0 per vector (<= 64 doubles)
 constexpr size_t kStateBytes = 1024;
+
+// Timing of the recurrence step launches (kpm_step_timer): while on, a run
+// records a HIP event before and after each stretch of consecutive step
+// launches (between two moment reductions) on its stream, and adds the elapsed
+// times once the stream has been synchronised.  One per host thread.
+struct StepTimer {
+    bool on = false;
+    double ms = 0.0;              // accumulated step time
+    int64_t launches = 0;         // step launches timed
+    std::vector<hipEvent_t> ev;   // event pool; pairs (start, end)
+    size_t used = 0;              // events recorded by the current run
+    hipError_t mark(hipStream_t s);
+    hipError_t collect();         // after the stream is synchronised
+};
+StepTimer &step_timer();
 
 // Per-launch scalars of a step (pointers go as separate restrict parameters).
 template <class VT> struct StepScalars {

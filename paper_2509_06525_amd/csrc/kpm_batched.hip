@@ -296,6 +296,11 @@ __global__ __launch_bounds__(kThreads) void k_reduce_seg(const double *__restric
     if (j == 0 && v < R) mu[((int64_t)s * R + v) * M + n0 + k] = red[v];
 }
 
+// flag = 0 (a kernel, not a memset node, so the clear stays an ordinary kernel under capture).
+__global__ void k_fill_flag(int32_t *__restrict__ flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
 __global__ void k_guard_seg(const double *__restrict__ mu, int64_t rows, int32_t M, int32_t *__restrict__ flag) {
     int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= rows * M) return;
@@ -534,12 +539,18 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
         dim3 grid(ns, count);
         k_reduce_seg<<<grid, kThreads, 0, s>>>(part, T, toff, Rp, R, M, n0, mu);
     };
+    StepTimer &timer = step_timer();
+    bool open = false;      // a timed stretch of step launches is open
+    if (timer.on) timer.used = 0;
     int batch0 = 0;
     for (int n = 1; n < M; ++n) {
         if (n - batch0 == K) {
+            if (open) { TBK_HIP(timer.mark(s)); open = false; }
             reduce(batch0, K);
             batch0 = n;
         }
+        if (timer.on && !open) { TBK_HIP(timer.mark(s)); open = true; }
+        if (timer.on) ++timer.launches;
         st.partial = part + (int64_t)(n - batch0) * pstride;
         if (n == 1) {
             st.tcur = r_int; st.tprev = nullptr; st.tnext = TB; st.c1 = c1f;
@@ -558,16 +569,18 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
             else launch_seg<VT, L, VPT, false, false>(sp, G, s, st);
         }
     }
+    if (open) TBK_HIP(timer.mark(s));
     reduce(batch0, M - batch0);
     TBK_HIP(hipGetLastError());
     }
-    TBK_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    k_fill_flag<<<1, 64, 0, s>>>(flag);
     const int64_t rows = (int64_t)ns * R;
     k_guard_seg<<<(unsigned)ceil_div(rows * M, 256), 256, 0, s>>>(mu, rows, M, flag);
     TBK_HIP(hipGetLastError());
     int32_t hflag = 0;
     TBK_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     TBK_HIP(hipStreamSynchronize(s));
+    if (step_timer().on) TBK_HIP(step_timer().collect());
     TBK_CHECK(hflag == 0, TBK_ERR_SPECTRUM, "a moment exceeds mu_0: some (a_s, b_s) does not bound its spectrum");
     return TBK_OK;
 }

@@ -473,12 +473,19 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
         k_reduce_l1<<<grid, kThreads, 0, s>>>(part, pl.G, Rv, Rout, n0, pl.n_chunks, l1);
     };
 
+    StepTimer &timer = step_timer();
+    const bool timed = timer.on && !pair;
+    bool open = false;      // a timed stretch of step launches is open
+    if (timed) timer.used = 0;
     int batch0 = n_start;   // first row index of the pending batch
     for (int n = n_start > 0 ? n_start : 1; n < Mr; ++n) {
         if (n - batch0 == K) {
+            if (open) { TBK_HIP(timer.mark(s)); open = false; }
             reduce(batch0, K);
             batch0 = n;
         }
+        if (timed && !open) { TBK_HIP(timer.mark(s)); open = true; }
+        if (timed) ++timer.launches;
         sp.partial = part + (int64_t)(n - batch0) * pstride;
         if (n == 1) {            // T_1 = Ht T_0 into TB
             sp.tcur = t0; sp.tprev = nullptr; sp.tnext = TB; sa.c1 = (VT)(1.0 / a);
@@ -496,6 +503,7 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
             launch_step<VT, L, VPT>(pl, n == 1, diag, s, sp, sa);
         }
     }
+    if (open) TBK_HIP(timer.mark(s));
     reduce(batch0, Mr - batch0);
     TBK_HIP(hipGetLastError());
     const int64_t nm = (int64_t)R * M;
@@ -531,6 +539,7 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     int32_t hflag = 0;
     TBK_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     TBK_HIP(hipStreamSynchronize(s));
+    if (timed) TBK_HIP(timer.collect());
     TBK_CHECK(hflag == 0, TBK_ERR_SPECTRUM,
               "a moment exceeds mu_0: the scale a = %g, shift b = %g do not bound the spectrum", a, b);
     return TBK_OK;

@@ -285,6 +285,17 @@ __device__ __forceinline__ void mlp_tile_forward(const WaveWeights &w, bf16x4 xq
     a.y = part + w.b3;
 }
 
+// Order in which a minibatch takes the bonds of the training set: local bond b of
+// the minibatch that starts at position `first` is bond (mul (first + b) + add)
+// mod n_total, a bijection of [0, n_total) when gcd(mul, n_total) = 1; mul = 1,
+// add = 0 is the stored order.
+struct BondOrder {
+    int64_t n_total, first, mul, add;
+    __device__ __forceinline__ int64_t map(int64_t b) const {
+        return (int64_t)(((unsigned __int128)mul * (uint64_t)(first + b) + (uint64_t)add) % (uint64_t)n_total);
+    }
+};
+
 // Features of bond tile t for this lane: X[16 t + n][4 q .. 4 q + 3]; zero past nb.
 __device__ __forceinline__ bf16x4 load_x(const uint16_t *__restrict__ X, int64_t nb, int64_t b) {
     const int q = (threadIdx.x & 63) >> 4;
@@ -319,7 +330,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(int64_t nb, const uint
                                                           const float *__restrict__ target,
                                                           const float *__restrict__ weight,
                                                           const float *__restrict__ P, float inv_b,
-                                                          float *__restrict__ gpart, double *__restrict__ lpart) {
+                                                          BondOrder order, float *__restrict__ gpart,
+                                                          double *__restrict__ lpart) {
     __shared__ uint16_t s_d2[kWaves][16][kNH];
     __shared__ uint16_t s_h1[kWaves][16][kNH];
     __shared__ uint16_t s_d1[kWaves][16][kNH];
@@ -340,11 +352,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(int64_t nb, const uint
     for (int64_t t = wave; t < ntile; t += nwave) {
         const int64_t b = 16 * t + n;
         const bool ok = b < nb;
-        const bf16x4 xq = load_x(X, nb, b);
+        const int64_t src = ok ? order.map(b) : 0;   // the training-set bond at minibatch position b
+        const bf16x4 xq = load_x(X, order.n_total, ok ? src : order.n_total);
         TileAct a;
         mlp_tile_forward(w, xq, a);
-        const float wb = ok ? (weight ? weight[b] : 1.f) : 0.f;
-        const float diff = ok ? a.y - target[b] : 0.f;
+        const float wb = ok ? (weight ? weight[src] : 1.f) : 0.f;
+        const float diff = ok ? a.y - target[src] : 0.f;
         if (q == 0) loss += (double)wb * (double)diff * (double)diff;
         const float dy = 2.f * wb * diff * inv_b;
         if (q == 0) gb3 += dy;
@@ -809,7 +822,7 @@ extern "C" tbk_status tbk_mlp_workspace_size(int64_t nb, int64_t *bytes) {
 
 static tbk_status loss_grad_impl(int64_t nb, const uint16_t *X, const float *target, const float *weight,
                                  const float *params, float *grad, double *loss, void *work, int64_t work_bytes,
-                                 hipStream_t s) {
+                                 hipStream_t s, BondOrder order) {
     int64_t need = 0;
     tbk_status st = tbk_mlp_workspace_size(nb, &need);
     if (st != TBK_OK) return st;
@@ -820,7 +833,7 @@ static tbk_status loss_grad_impl(int64_t nb, const uint16_t *X, const float *tar
     const int64_t nwave = (int64_t)G * kWaves;
     float *gpart = static_cast<float *>(work);
     double *lpart = reinterpret_cast<double *>(static_cast<char *>(work) + ((nwave * kNP * 4 + 255) / 256) * 256);
-    k_mlp_grad<<<G, 64 * kWaves, 0, s>>>(nb, X, target, weight, params, 1.0f / (float)nb, gpart, lpart);
+    k_mlp_grad<<<G, 64 * kWaves, 0, s>>>(nb, X, target, weight, params, 1.0f / (float)nb, order, gpart, lpart);
     TBK_HIP(hipGetLastError());
     k_grad_reduce<<<(kNP + 1 + 255) / 256, 256, 0, s>>>(nwave, gpart, lpart, grad, loss);
     TBK_HIP(hipGetLastError());
@@ -832,7 +845,8 @@ extern "C" tbk_status tbk_mlp_loss_grad(int64_t nb, const uint16_t *X, const flo
                                         int64_t work_bytes, void *stream) {
     clear_error();
     TBK_CHECK(nb >= 1, TBK_ERR_INVALID_ARG, "nb must be positive");
-    return loss_grad_impl(nb, X, target, weight, params, grad, loss, work, work_bytes, as_stream(stream));
+    return loss_grad_impl(nb, X, target, weight, params, grad, loss, work, work_bytes, as_stream(stream),
+                          BondOrder{nb, 0, 1, 0});
 }
 
 extern "C" tbk_status tbk_adamw_step(int64_t n, float *p, const float *g, float *m, float *v, int64_t t, double lr,
@@ -851,10 +865,36 @@ extern "C" tbk_status tbk_adamw_step(int64_t n, float *p, const float *g, float 
     return TBK_OK;
 }
 
+// SplitMix64 output k of `seed` (Steele, Lea & Flood 2014): the epoch's shuffle.
+static uint64_t mix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1u) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t gcd64(uint64_t a, uint64_t b) {
+    while (b) { const uint64_t t = a % b; a = b; b = t; }
+    return a;
+}
+
+// Bond order of one epoch: in order without a seed; otherwise an affine
+// bijection i -> (mul i + add) mod nb with mul coprime to nb taken from the
+// middle half of [1, nb), so consecutive minibatch positions land far apart in
+// the stored (structure-major) order.
+static BondOrder epoch_order(int64_t nb, uint64_t seed, int e) {
+    if (seed == 0 || nb < 3) return BondOrder{nb, 0, 1, 0};
+    const uint64_t n = (uint64_t)nb;
+    uint64_t mul = n / 4 + mix64(seed, 2 * (uint64_t)e) % (n / 2 + 1);
+    while (mul == 0 || gcd64(mul, n) != 1) mul = mul + 1 < n ? mul + 1 : 1;
+    return BondOrder{nb, 0, (int64_t)mul, (int64_t)(mix64(seed, 2 * (uint64_t)e + 1) % n)};
+}
+
 extern "C" tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *target, const float *weight,
                                     float *params, float *m, float *v, int64_t *step, int32_t epochs, int64_t batch,
-                                    double lr, double beta1, double beta2, double eps, double wd,
-                                    double *loss_history, void *work, int64_t work_bytes, void *stream) {
+                                    uint64_t shuffle_seed, double lr, double beta1, double beta2, double eps,
+                                    double wd, double *loss_history, void *work, int64_t work_bytes,
+                                    void *stream) {
     clear_error();
     TBK_CHECK(nb >= 1 && epochs >= 1 && batch >= 1 && step && loss_history, TBK_ERR_INVALID_ARG, "bad arguments");
     TBK_CHECK(params && m && v, TBK_ERR_INVALID_ARG, "NULL array");
@@ -875,10 +915,12 @@ extern "C" tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *
     DevBuf losses;
     TBK_HIP(losses.alloc(sizeof(double) * nbatch, s));
     for (int e = 0; e < epochs; ++e) {
+        BondOrder order = epoch_order(nb, shuffle_seed, e);
         for (int64_t bt = 0; bt < nbatch; ++bt) {
             const int64_t b0 = bt * bsz, cnt = std::min(bsz, nb - b0);
-            st = loss_grad_impl(cnt, X + b0 * kNI, target + b0, weight ? weight + b0 : nullptr, params, grad,
-                                losses.as<double>() + bt, gw, work_bytes - extra, s);
+            order.first = b0;
+            st = loss_grad_impl(cnt, X, target, weight, params, grad, losses.as<double>() + bt, gw,
+                                work_bytes - extra, s, order);
             if (st != TBK_OK) return st;
             *step += 1;
             st = tbk_adamw_step(kNP, params, grad, m, v, *step, lr, beta1, beta2, eps, wd, stream);

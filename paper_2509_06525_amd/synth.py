@@ -223,6 +223,14 @@ COORD_Z0 = 4.7357           # pristine coordination sum_j f_c(r_ij) within 4.0 A
 SK_COORD_KAPPA = (0.25, -0.15, 0.2, 0.3, 0.1, -0.2, 0.15, 0.25, -0.1, 0.05)
 
 
+# Training of the snapshot workload's learned-hopping network: bonds of 128 sheets of the
+# seed-4004 set (sizes log-uniform on 1k-50k atoms, sigma in [0.02, 0.08] A, disjoint from
+# the evaluation set), minibatches of 2048 bonds in a shuffled order, AdamW with a learning
+# rate stepped down over 150 epochs (epochs, rate).
+LEARNED_TRAINING = dict(count=128, seed=4004, n_min=1000, n_max=50000, batch=2048, shuffle_seed=5,
+                        schedule=((80, 2e-3), (40, 5e-4), (30, 1e-4)), wd=1e-5, init_seed=11)
+
+
 def init_mlp_params(seed, out_scale=0.1):
     """Seeded initial parameters (float32): uniform(+-1/sqrt(fan_in)) weights, zero biases,
     output layer scaled by out_scale."""

@@ -58,7 +58,7 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_hamiltonian_size_sk", "tb_build_hamiltonian_sk",
                "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
                "kpm_scale", "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
-               "kpm_mean_moments",
+               "kpm_mean_moments", "kpm_step_timer", "kpm_step_timer_read",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -169,6 +169,10 @@ def lib():
                               i32, i32, i32, i32, vp, i64, vp, vp]
     L.kpm_scale.restype = ctypes.c_int
     L.kpm_scale.argtypes = [i32, ctypes.POINTER(f64), f64, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    L.kpm_step_timer.restype = ctypes.c_int
+    L.kpm_step_timer.argtypes = [i32]
+    L.kpm_step_timer_read.restype = ctypes.c_int
+    L.kpm_step_timer_read.argtypes = [ctypes.POINTER(f64), ctypes.POINTER(i64)]
     L.kpm_mean_moments.restype = ctypes.c_int
     L.kpm_mean_moments.argtypes = [vp, i32, i32, i32, vp, vp]
     L.kpm_workspace_size_config.restype = ctypes.c_int
@@ -227,8 +231,8 @@ def lib():
     L.tbk_adamw_step.restype = ctypes.c_int
     L.tbk_adamw_step.argtypes = [i64, vp, vp, vp, vp, i64, f64, f64, f64, f64, f64, vp]
     L.tbk_mlp_train.restype = ctypes.c_int
-    L.tbk_mlp_train.argtypes = [i64, u16p, vp, vp, vp, vp, vp, ctypes.POINTER(i64), i32, i64, f64, f64, f64, f64,
-                                f64, ctypes.POINTER(f64), vp, i64, vp]
+    L.tbk_mlp_train.argtypes = [i64, u16p, vp, vp, vp, vp, vp, ctypes.POINTER(i64), i32, i64, ctypes.c_uint64, f64,
+                                f64, f64, f64, f64, ctypes.POINTER(f64), vp, i64, vp]
     L.tb_build_hamiltonian_learned.restype = ctypes.c_int
     L.tb_build_hamiltonian_learned.argtypes = [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
                                                ctypes.POINTER(i32), ctypes.POINTER(TbParams),
@@ -574,6 +578,18 @@ def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, 
     return mu
 
 
+def step_timer(enable):
+    """Switch the library's step-kernel timer on (cleared) or off for this thread."""
+    _check(lib().kpm_step_timer(1 if enable else 0))
+
+
+def step_timer_read():
+    """(milliseconds, step launches) timed since the last read or enable; clears them."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib().kpm_step_timer_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 def mean_moments(mu, stream=None):
     """Average over the vectors on the device: mu [R, M] -> [M], or [S, R, M] -> [S, M]."""
     mu = _dev(mu, torch.float64)
@@ -850,7 +866,7 @@ class MlpTrainer:
         self.step = 0
 
     def train(self, X, target, epochs, batch, lr=3e-3, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-4,
-              weight=None, stream=None):
+              weight=None, stream=None, shuffle_seed=0):
         nb = X.shape[0]
         bsz = min(batch, nb)
         work = torch.empty(mlp_workspace_size(bsz) + 256 + ((1633 * 4 + 255) // 256) * 256,
@@ -858,7 +874,8 @@ class MlpTrainer:
         hist = (ctypes.c_double * epochs)()
         st = ctypes.c_int64(self.step)
         _check(lib().tbk_mlp_train(nb, _ptr(X), _ptr(target), _ptr(weight), _ptr(self.params), _ptr(self.m),
-                                   _ptr(self.v), ctypes.byref(st), int(epochs), int(batch), float(lr), float(beta1),
+                                   _ptr(self.v), ctypes.byref(st), int(epochs), int(batch),
+                                   int(shuffle_seed) & (2**64 - 1), float(lr), float(beta1),
                                    float(beta2), float(eps), float(wd), hist, _ptr(work), work.numel(),
                                    _stream(stream)))
         self.step = st.value

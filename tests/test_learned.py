@@ -196,10 +196,12 @@ def test_adamw_matches_oracle():
     np.testing.assert_allclose(p.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
 
 
-def _training_set(count=32, seed=4004, n_max=50000):
-    """Bond features and targets of the training snapshots (seed 4004, disjoint from the
-    evaluation set, sizes log-uniform on [1k, n_max] atoms)."""
-    snaps = synth.snapshot_set(count, seed, n_min=1000, n_max=n_max)
+def _training_set(count=None, seed=None, n_max=None):
+    """Bond features and targets of the training snapshots (the seed-4004 set, disjoint from
+    the evaluation set; synth.LEARNED_TRAINING unless overridden)."""
+    cfg = synth.LEARNED_TRAINING
+    snaps = synth.snapshot_set(count or cfg["count"], seed or cfg["seed"], n_min=cfg["n_min"],
+                               n_max=n_max or cfg["n_max"])
     pos, sp, seg, boxes, v, b = gpu_parts(snaps)
     mean, std = tbkpm.feature_moments(b, v, synth.R_DESC)
     std = [max(s, 1e-6) for s in std]
@@ -208,24 +210,47 @@ def _training_set(count=32, seed=4004, n_max=50000):
     return X, y, mean, std
 
 
-def train_model(epochs=120, seed=11):
+def train_model():
+    """The workload's network: synth.LEARNED_TRAINING's set, order and schedule."""
+    cfg = synth.LEARNED_TRAINING
     X, y, mean, std = _training_set()
-    tr = tbkpm.MlpTrainer(G.to_dev(synth.init_mlp_params(seed)))
-    hist = tr.train(X, y, epochs=epochs, batch=2048, lr=2e-3, wd=1e-5)
+    tr = tbkpm.MlpTrainer(G.to_dev(synth.init_mlp_params(cfg["init_seed"])))
+    hist = []
+    for epochs, lr in cfg["schedule"]:
+        hist += tr.train(X, y, epochs=epochs, batch=cfg["batch"], lr=lr, wd=cfg["wd"],
+                         shuffle_seed=cfg["shuffle_seed"])
     return tr.params, mean, std, hist, X, y
 
 
-def test_training_lowers_the_loss_and_is_deterministic():
+@pytest.mark.parametrize("shuffle_seed", [0, 3])
+def test_training_lowers_the_loss_and_is_deterministic(shuffle_seed):
     X, y, mean, std = _training_set(count=6, n_max=8000)
     p0 = G.to_dev(synth.init_mlp_params(5))
     t1, t2 = tbkpm.MlpTrainer(p0.clone()), tbkpm.MlpTrainer(p0.clone())
-    h1 = t1.train(X, y, epochs=40, batch=1024, lr=2e-3, wd=1e-5)
-    h2 = t2.train(X, y, epochs=40, batch=1024, lr=2e-3, wd=1e-5)
+    h1 = t1.train(X, y, epochs=40, batch=1024, lr=2e-3, wd=1e-5, shuffle_seed=shuffle_seed)
+    h2 = t2.train(X, y, epochs=40, batch=1024, lr=2e-3, wd=1e-5, shuffle_seed=shuffle_seed)
     assert h1 == h2
     torch.testing.assert_close(t1.params, t2.params, rtol=0, atol=0)
     assert h1[-1] < 0.05 * h1[0]
     var = float(torch.var(y).item())
     assert h1[-1] < 0.05 * var
+
+
+def test_shuffled_epochs_visit_every_bond_once():
+    """With a zero learning rate the parameters stay fixed, so an epoch's mean loss is the
+    mean over the bonds it visits: the shuffled epochs (two different permutations,
+    12 minibatches each) must give the in-order mean up to rounding (summation order, and
+    the FP32 factor 1/count of the shorter last minibatch: ~1e-8), which a repeated or
+    skipped bond would move by ~1e-4 (bond losses differ widely, nb ~ 10^4)."""
+    X, y, mean, std = _training_set(count=2, n_max=3000)
+    nb = X.shape[0]
+    p0 = G.to_dev(synth.init_mlp_params(6, out_scale=1.0))
+    batch = (nb + 11) // 12
+    h0 = tbkpm.MlpTrainer(p0.clone()).train(X, y, epochs=2, batch=batch, lr=0.0, wd=0.0, shuffle_seed=0)
+    h1 = tbkpm.MlpTrainer(p0.clone()).train(X, y, epochs=2, batch=batch, lr=0.0, wd=0.0, shuffle_seed=9)
+    print(f"[shuffle] nb={nb}: in order {h0}, shuffled {h1}", flush=True)
+    np.testing.assert_allclose(h1, h0, rtol=1e-7)
+    assert h0[0] == h0[1]
 
 
 def test_learned_assembly_matches_oracle():
@@ -270,7 +295,7 @@ def test_learned_assembly_matches_oracle():
 @pytest.fixture(scope="module")
 def trained():
     params, mean, std, hist, X, y = train_model()
-    return params, mean, std, hist
+    return params, mean, std, hist, float(torch.var(y).item())
 
 
 def test_learned_hoppings_beat_the_plain_formula(trained):
@@ -280,8 +305,9 @@ def test_learned_hoppings_beat_the_plain_formula(trained):
     Hamiltonian (tests/golden, written by the oracle only) and closer than the plain
     formula's; the plain formula's error has median >= 5e-2 (the correction is not
     negligible) and agrees with the oracle's own plain-versus-target error."""
-    params, mean, std, hist = trained
-    assert hist[-1] < 0.02 * hist[0]
+    params, mean, std, hist, var = trained
+    print(f"[learned vs plain] training loss {hist[0]:.3e} -> {hist[-1]:.3e} (target variance {var:.3e})", flush=True)
+    assert hist[-1] < 0.05 * hist[0] and hist[-1] < 0.05 * var
     table, mu_target = golden_snap.load()
     w = synth.WORKLOADS["graphene_snapshots_256"]
     evals, r = golden_snap.vectors()

@@ -1,5 +1,6 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
-benchmark times (autotuned slice height and launch shape).
+benchmark times (the slice height and launch shape of the shipped MI355X tuning
+table, which bench.py starts from).
 
 The expected moments are the serial FP64 oracle's, stored under tests/golden/
 by tests/golden/make_golden.py for the leading random vectors of each workload
@@ -33,6 +34,22 @@ def _have(name):
     return os.path.exists(make_golden.golden_path(name))
 
 
+def shipped_shape(n, R, precision="c32", fmt=2, degree=3, onsite=0):
+    """(slice, launch shape) of the shipped MI355X tuning table's entry for this
+    problem class: the shape bench.py times (it starts from the same table)."""
+    path = os.path.join(os.path.dirname(tbkpm.LIB_PATH), "tuned_gfx950.txt")
+    lg = int(math.floor(math.log2(n)))
+    p = {"f64": 0, "c32": 1}[precision]
+    suffix = f"/n2^{lg}/R{R}/p{p}/f{fmt}/deg{degree}/ons{onsite}"
+    for line in open(path):
+        parts = line.split()
+        if parts and parts[0].endswith(suffix):
+            sl, vpt, tpb, nt, xcd, rpt = (int(v) for v in parts[1:7])
+            compact = int(parts[8]) if len(parts) > 8 else 0
+            return sl, tbkpm.make_config(vpt, tpb, nt, xcd, rpt, compact_columns=compact)
+    raise AssertionError(f"no shipped tuning entry for {suffix}")
+
+
 def _run(name, precision):
     w = synth.WORKLOADS[name]
     a, b, mu_o = make_golden.load(name)
@@ -42,11 +59,10 @@ def _run(name, precision):
     r = synth.random_phase(s.n, w["R"], w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)
     pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
     if precision == "c32":
-        tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, w["R"], "c32")
-        H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32",
-                                    slice=tune.slice)
+        sl, cfg = shipped_shape(s.n, w["R"], onsite=int(np.any(s.onsite != 0)))
+        print(f"[fullsize] {name}: shipped shape slice {sl} {cfg.as_dict()}", flush=True)
+        H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32", slice=sl)
         rd = G.to_dev(r)
-        cfg = tune.config
     else:
         H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f64", slice=64)
         rd = G.to_dev(r.astype(np.complex128))
@@ -91,13 +107,13 @@ def test_fullsize_100M_against_exact_spectrum():
     n = s.n
     r = synth.random_phase(n, 1, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)
     pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
-    tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, 1, "c32")
-    H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32", slice=tune.slice)
+    sl, cfg = shipped_shape(n, 1)
+    H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32", slice=sl)
     del s, pos, sp
     a, b = H.scale()
     assert abs(b) < 1e-12 and a == pytest.approx(1.01 * 8.1, rel=1e-10)
     Mc = 300
-    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), Mc, "c32", config=tune.config).cpu().numpy()[0]
+    mu = tbkpm.kpm_moments(H, a, b, G.to_dev(r), Mc, "c32", config=cfg).cpu().numpy()[0]
     # 200 x 200 cells: closed walks that wrap the torus need > 300 hops, so moments n < 300 are exact
     eig = ref.supercell_spectrum(200, 200)
     tau = ref.trace_moments_from_eigs(eig, a, b, Mc) / eig.size
