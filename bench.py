@@ -102,28 +102,32 @@ def profiled_traffic(workload, kernel, slice_, launch):
 
 
 def stream_probe(dev, mib=2048, reps=5):
-    """Measured HBM ceilings beside the 8 TB/s peak: a plain device copy (read + write
-    of `mib` MiB) and a pure read (a sum over `mib` MiB), each timed with HIP events,
-    median of `reps`; GB/s of bytes moved."""
+    """Measured HBM ceilings beside the 8 TB/s peak, with the library's probe kernels
+    (tbk_bandwidth_probe): a streaming copy (read + write of `mib` MiB) and a streaming
+    read of `mib` MiB, each timed with HIP events on the launch stream, median of `reps`;
+    GB/s of bytes moved."""
     import torch
+    from paper_2509_06525_amd import tbkpm
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
+    folds = torch.empty(max(tbkpm.bandwidth_probe_words(), 1), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
     out = {}
-    for name, fn, nbytes in (("stream_copy_gbs", lambda: dst.copy_(src), 2 * n * 4),
-                             ("stream_read_gbs", lambda: src.sum(), n * 4)):
-        fn()
+    for name, mode, out_t, nbytes in (("stream_copy_gbs", "copy", dst, 2 * n * 4),
+                                      ("stream_read_gbs", "read", folds, n * 4)):
+        tbkpm.bandwidth_probe(src, out_t, mode, stream)
         t = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            fn()
-            e1.record()
+            e0.record(stream)
+            tbkpm.bandwidth_probe(src, out_t, mode, stream)
+            e1.record(stream)
             torch.cuda.synchronize()
             t.append(e0.elapsed_time(e1) * 1e-3)
         out[name] = nbytes / float(np.median(t)) / 1e9
     out["stream_probe_mib"] = mib
-    del src, dst
+    del src, dst, folds
     torch.cuda.empty_cache()
     return out
 

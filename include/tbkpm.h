@@ -370,6 +370,22 @@ tbk_status kpm_moments_batched(const tbk_ham *h, const double *a, const double *
 tbk_status kpm_step_timer(int32_t enable);
 tbk_status kpm_step_timer_read(double *ms, int64_t *launches);
 
+/*
+ * Bandwidth probes (measurement aid: the HBM ceilings a bandwidth-bound step
+ * such as the recurrence of Sec. 2.4 is rated beside):
+ *   mode 1: copy `bytes` from src to dst (device, 16-byte aligned, no overlap);
+ *   mode 0: read `bytes` of src; dst (device, >= 4 tbk_bandwidth_probe_words()
+ *           bytes) receives one XOR fold per workgroup so that every load is used.
+ * bytes: a positive multiple of 16.  Asynchronous on `stream`; the caller times
+ * it (e.g. HIP events).  Loads and stores are non-temporal 16-byte accesses,
+ * four in flight per thread, 8 workgroups of 256 threads per compute unit.
+ * Errors: INVALID_ARG (mode, size, alignment, NULL), DEVICE.
+ * tbk_bandwidth_probe_words: the word count of mode 0's output on the current
+ * device (-1 on a HIP error).
+ */
+tbk_status tbk_bandwidth_probe(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream);
+int64_t tbk_bandwidth_probe_words(void);
+
 /* ------------------------------------------------------------------------ */
 /* Autotuning                                                                */
 /* ------------------------------------------------------------------------ */

@@ -58,7 +58,8 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "tbk_hamiltonian_size_sk", "tb_build_hamiltonian_sk",
                "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
                "kpm_scale", "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
-               "kpm_mean_moments", "kpm_step_timer", "kpm_step_timer_read",
+               "kpm_mean_moments", "kpm_step_timer", "kpm_step_timer_read", "tbk_bandwidth_probe",
+               "tbk_bandwidth_probe_words",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -169,6 +170,10 @@ def lib():
                               i32, i32, i32, i32, vp, i64, vp, vp]
     L.kpm_scale.restype = ctypes.c_int
     L.kpm_scale.argtypes = [i32, ctypes.POINTER(f64), f64, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    L.tbk_bandwidth_probe.restype = ctypes.c_int
+    L.tbk_bandwidth_probe.argtypes = [vp, vp, i64, i32, vp]
+    L.tbk_bandwidth_probe_words.restype = i64
+    L.tbk_bandwidth_probe_words.argtypes = []
     L.kpm_step_timer.restype = ctypes.c_int
     L.kpm_step_timer.argtypes = [i32]
     L.kpm_step_timer_read.restype = ctypes.c_int
@@ -576,6 +581,17 @@ def kpm_moments(H, a, b, r, M, precision=None, work=None, mu=None, stream=None, 
                                 _cfg_ref(config), int(n_start), _ptr(work), work.numel(), _ptr(mu),
                                 _stream(stream)))
     return mu
+
+
+def bandwidth_probe(src, dst, mode, stream=None):
+    """One probe launch over src's bytes: mode "copy" (src -> dst) or "read" (dst receives
+    tbk_bandwidth_probe_words() 32-bit folds)."""
+    _check(lib().tbk_bandwidth_probe(_ptr(src), _ptr(dst), src.numel() * src.element_size(),
+                                     1 if mode == "copy" else 0, _stream(stream)))
+
+
+def bandwidth_probe_words():
+    return int(lib().tbk_bandwidth_probe_words())
 
 
 def step_timer(enable):
