@@ -314,6 +314,26 @@ tbk_status kpm_moments_config(const tbk_ham *h, const double *a, const double *b
                               void *stream);
 
 /*
+ * kpm_moments_config without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array of
+ * the library, 64 MiB on each GPU it runs on, held until the process ends; this
+ * call makes no allocation (no hipMalloc, hipFree or allocating library
+ * routine).  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents: n_start > 0 continues the run the last call on this
+ * GPU left there (as kpm_moments_config continues the run its `work` holds),
+ * and calls that overlap on one GPU (several host threads or streams) race.
+ * Arguments, results (bit for bit those of kpm_moments_config with the same
+ * cfg) and errors as kpm_moments_config, plus BUFFER_TOO_SMALL when
+ * kpm_workspace_size_config for these arguments exceeds 64 MiB (e.g. up to
+ * about 2.7 M rows for one complex-float vector).  The step timer does not
+ * time this call.  Synchronises `stream`.
+ */
+tbk_status kpm_moments_noalloc(const tbk_ham *h, const double *a, const double *b, const void *r,
+                               int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                               int32_t n_start, double *mu, void *stream);
+
+/*
  * kpm_moments_config with the random-phase start vectors (Sec. 2.4) generated
  * on the device instead of read from an [n_rows][R] array:
  *   r[i][v] = exp(i phi), phi = 2 pi (x >> 11) 2^-53, x = output number

@@ -3,6 +3,7 @@
 // instances of kpm_run.hpp, checkpoint/resume of a run, and the C entry points.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "kpm.hpp"
@@ -19,6 +20,31 @@ int log2_exact(int x) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of kpm_moments_noalloc: one array per GPU, part of the loaded code
+// object (no allocation call), shared by every call on that GPU.  Host code
+// uses the device address hipGetSymbolAddress returns for the current device,
+// never the array's name (a host-side stand-in).
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+tbk_status scratch_address(void **out) {
+    int dev = -1;
+    TBK_HIP(hipGetDevice(&dev));
+    TBK_CHECK(dev >= 0 && dev < kScratchDevices, TBK_ERR_UNSUPPORTED, "device %d: no workspace slot", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        TBK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        TBK_CHECK(p != nullptr, TBK_ERR_DEVICE, "no device address for the static workspace");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TBK_OK;
+}
 
 }  // namespace
 
@@ -366,6 +392,38 @@ extern "C" tbk_status kpm_moments_config(const tbk_ham *h, const double *a, cons
     if (st != TBK_OK) return st;
     return run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream),
                     nullptr, nullptr);
+}
+
+extern "C" tbk_status kpm_moments_noalloc(const tbk_ham *h, const double *a, const double *b, const void *r,
+                                          int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
+                                          int32_t n_start, double *mu, void *stream) {
+    clear_error();
+    KpmPlan pl;
+    tbk_status st = make_plan(h, R, M, precision, cfg, pl);
+    if (st != TBK_OK) return st;
+    pl.n_start = n_start;
+    st = check_start(pl, M);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(pl.total <= kScratchBytes, TBK_ERR_BUFFER_TOO_SMALL,
+              "kpm_moments_noalloc: this run needs %lld bytes of workspace, more than the %lld-byte static "
+              "workspace (use kpm_moments_config with a caller-allocated workspace)",
+              (long long)pl.total, (long long)kScratchBytes);
+    void *work = nullptr;
+    st = scratch_address(&work);
+    if (st != TBK_OK) return st;
+    st = check_moment_args(h, pl, a, b, r, work, (int64_t)kScratchBytes, mu);
+    if (st != TBK_OK) return st;
+    TBK_CHECK(pl.cfg.persistent == 0, TBK_ERR_INVALID_ARG, "the persistent launch is for kpm_moments_batched");
+    st = check_resume(h, pl, a[0], b[0], R, M, precision, work, as_stream(stream));
+    if (st != TBK_OK) return st;
+    // the step timer's event pool may grow; this entry point makes no such call
+    StepTimer &timer = step_timer();
+    const bool was_on = timer.on;
+    timer.on = false;
+    st = run_plan(h, pl, a[0], b[0], r, R, M, precision, static_cast<char *>(work), mu, as_stream(stream),
+                  nullptr, nullptr);
+    timer.on = was_on;
+    return st;
 }
 
 extern "C" tbk_status kpm_moments_seeded(const tbk_ham *h, const double *a, const double *b, uint64_t seed,

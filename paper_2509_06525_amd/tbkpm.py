@@ -59,7 +59,7 @@ ABI_SYMBOLS = ("tbk_last_error", "tbk_abi_version",
                "kpm_default_config", "kpm_workspace_size", "kpm_workspace_size_config",
                "kpm_scale", "kpm_moments", "kpm_moments_config", "kpm_moments_seeded", "tbk_random_phase",
                "kpm_mean_moments", "kpm_step_timer", "kpm_step_timer_read", "tbk_bandwidth_probe",
-               "tbk_bandwidth_probe_words",
+               "tbk_bandwidth_probe_words", "kpm_moments_noalloc",
                "kpm_workspace_size_batched", "kpm_moments_batched",
                "kpm_dos", "kpm_dos_batched", "tbk_autotune", "tbk_autotune_form",
                "tbk_descriptor", "tbk_bonds", "tbk_bond_features", "tbk_feature_moments",
@@ -170,6 +170,9 @@ def lib():
                               i32, i32, i32, i32, vp, i64, vp, vp]
     L.kpm_scale.restype = ctypes.c_int
     L.kpm_scale.argtypes = [i32, ctypes.POINTER(f64), f64, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+    L.kpm_moments_noalloc.restype = ctypes.c_int
+    L.kpm_moments_noalloc.argtypes = [ctypes.POINTER(HamStruct), ctypes.POINTER(f64), ctypes.POINTER(f64), vp,
+                                      i32, i32, i32, ctypes.POINTER(KpmConfig), i32, vp, vp]
     L.tbk_bandwidth_probe.restype = ctypes.c_int
     L.tbk_bandwidth_probe.argtypes = [vp, vp, i64, i32, vp]
     L.tbk_bandwidth_probe_words.restype = i64
@@ -604,6 +607,26 @@ def step_timer_read():
     ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
     _check(lib().kpm_step_timer_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def kpm_moments_noalloc(H, a, b, r, M, precision=None, mu=None, stream=None, config=None, n_start=0, R=None):
+    """kpm_moments with the library's static workspace (no allocation in the call; mu must
+    then be given).  n_start > 0 continues the run the last call on this GPU left there."""
+    if r is not None:
+        if precision is None:
+            precision = "c32" if r.dtype == torch.complex64 else "f64"
+        r = _dev(r, torch.complex64 if precision == "c32" else torch.complex128)
+        if r.dim() == 1:
+            r = r.reshape(-1, 1)
+        R = r.shape[1]
+    elif R is None or precision is None:
+        raise ValueError("continuing a run without r needs R and precision")
+    if mu is None:
+        mu = torch.empty((R, M), dtype=torch.float64, device=H.tensors["ptr"].device)
+    av, bv = (ctypes.c_double * 1)(float(a)), (ctypes.c_double * 1)(float(b))
+    _check(lib().kpm_moments_noalloc(ctypes.byref(H.st), av, bv, _ptr(r), int(R), int(M), PRECISIONS[precision],
+                                     _cfg_ref(config), int(n_start), _ptr(mu), _stream(stream)))
+    return mu
 
 
 def mean_moments(mu, stream=None):
