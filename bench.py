@@ -44,6 +44,11 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     p.add_argument("--no-doubling", action="store_true", help="skip the doubling-identity variant")
+    p.add_argument("--train-shuffle-seed", type=int, default=None,
+                   help="snapshot workload: shuffle seed of the network's training (0 = stored order; "
+                        "default: the workload's)")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip every variant form (doubling, uniform values) and the oracle comparison run")
     p.add_argument("--retune", action="store_true",
                    help="tune afresh instead of starting from the shipped MI355X tuning table")
     p.add_argument("--copy-probe-mib", type=int, default=0,
@@ -225,7 +230,8 @@ def bench_snapshots(args, w):
     hist = []
     for epochs, lr in tcfg["schedule"]:
         hist += trainer.train(X, y, epochs=epochs, batch=tcfg["batch"], lr=lr, wd=tcfg["wd"],
-                              shuffle_seed=tcfg["shuffle_seed"])
+                              shuffle_seed=tcfg["shuffle_seed"] if args.train_shuffle_seed is None
+                              else args.train_shuffle_seed)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"trained on {X.shape[0]} bonds: loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s")
@@ -245,7 +251,8 @@ def bench_snapshots(args, w):
     # launch (all exact), fastest kept
     shapes = {"per_step": tbkpm.make_config(2, 2, 1, 0, 1, 0), "persistent": tbkpm.make_config(2, 1, 1, 0, 1, 1)}
     for tpb in (1, 2, 4):
-        shapes[f"per_step_xcd_tpb{tpb}"] = tbkpm.make_config(2, tpb, 1, 1, 1, 0)
+        for xr in (1, 2):
+            shapes[f"per_step_xcd{xr}_tpb{tpb}"] = tbkpm.make_config(2, tpb, 1, xr, 1, 0)
     timing = {}
     for name, cfg in shapes.items():
         try:
@@ -444,7 +451,7 @@ def bench_sk(args, w):
         if geom:
             forms = (1,)
         shapes = [tbkpm.make_config(v, t, nt, xr, 1, atom_rows=at) for at in forms for v in vpts
-                  for t in tpbs for nt in (0, 1) for xr in (0, 1)]
+                  for t in tpbs for nt in (0, 1) for xr in (0, 1, 2)]
         times = []
         for c in shapes:
             tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
@@ -910,7 +917,7 @@ def main():
 
     # DOS and moments against the oracle's stored full-size moments (its vector subset,
     # its (a, b) from FP64 Gershgorin bounds), same energy grid.
-    gold = golden_moments(args.workload)
+    gold = None if args.no_variants else golden_moments(args.workload)
     if gold is not None:
         ga, gb, gmu = gold
         nv = gmu.shape[0]
@@ -927,9 +934,11 @@ def main():
 
     log(f"timed: {sec_per_step * 1e3:.1f} ms/step, kpm {kpm_med:.1f} ms")
     variants = []
-    if not args.no_doubling and M >= 2:
+    if args.no_variants:
+        pass
+    elif not args.no_doubling and M >= 2:
         variants.append(("doubling", {"doubling": 1}))
-    if Hs.st.uniform_hop:
+    if Hs.st.uniform_hop and not args.no_variants:
         variants.append(("uniform_values", {"uniform_values": 1}))
         if not args.no_doubling and M >= 2:
             variants.append(("doubling_uniform_values", {"doubling": 1, "uniform_values": 1}))

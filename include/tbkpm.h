@@ -210,7 +210,13 @@ typedef struct {
     int32_t vectors_per_thread; /* 1, or 2 (C32 only, R >= 2): vectors per thread  */
     int32_t tiles_per_block;    /* >= 1: consecutive tiles one workgroup handles    */
     int32_t nontemporal;        /* 1: streamed arrays use non-temporal loads/stores */
-    int32_t xcd_remap;          /* 1: each XCD sweeps a contiguous eighth of rows   */
+    int32_t xcd_remap;          /* block order over the 8 XCDs (workgroup b runs on
+                                   XCD b % 8): 0 = dispatch order; 1 = each XCD
+                                   sweeps a contiguous eighth of the rows; 2, 3 =
+                                   each XCD takes runs of 16 (2) or 64 (3)
+                                   consecutive blocks, the XCDs' runs side by side
+                                   (one front over the chip, neighbour rows in the
+                                   XCD's own L2)                                  */
     int32_t rows_per_thread;    /* 1, 2 or 4: rows (from consecutive tiles) a
                                    thread advances together; 4 takes effect with
                                    one vector per thread row on width-3 slices and
@@ -595,15 +601,19 @@ tbk_status tbk_adamw_step(int64_t n, float *p, const float *g, float *m, float *
  * network of Eq. (2)): `epochs` passes over the nb bonds in minibatches of
  * `batch`, one tbk_mlp_loss_grad and one tbk_adamw_step per minibatch; *step
  * counts the updates.  shuffle_seed = 0 takes the bonds in their stored order;
- * otherwise epoch e takes them in the order i -> (mul_e i + add_e) mod nb, with
- * mul_e coprime to nb in the middle half of [1, nb) and add_e in [0, nb) drawn
- * from SplitMix64(shuffle_seed) (deterministic; minibatches then mix bonds of
- * every structure instead of taking one structure's bonds at a time).
+ * otherwise epoch e takes the nb / 16 chunks of 16 consecutive bonds in the
+ * order c -> (mul_e c + add_e) mod (nb / 16), with mul_e coprime to nb / 16 in
+ * the middle half of its range and add_e drawn from SplitMix64(shuffle_seed)
+ * (deterministic; the last nb % 16 bonds stay last).  Minibatches then mix
+ * chunks of every structure instead of one structure's bonds at a time, while
+ * each 16-bond tile still reads contiguous features.
  * params, m, v device float [1633],
  * updated in place.  loss_history (host [epochs]) receives each epoch's mean
  * loss.  work >= tbk_mlp_workspace_size(min(batch, nb)) + 7168 bytes.
- * Synchronises `stream` once per epoch.  Errors: as tbk_mlp_loss_grad;
- * INVALID_ARG (epochs < 1, batch < 1). */
+ * Each minibatch's AdamW update is applied inside its gradient reduction (the
+ * arithmetic of tbk_adamw_step).  Synchronises `stream` once per epoch.
+ * Errors: as tbk_mlp_loss_grad; INVALID_ARG (epochs < 1, batch < 1, *step < 0,
+ * AdamW hyper-parameters as tbk_adamw_step). */
 tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *target, const float *weight,
                          float *params, float *m, float *v, int64_t *step, int32_t epochs,
                          int64_t batch, uint64_t shuffle_seed, double lr, double beta1, double beta2,

@@ -250,7 +250,7 @@ tbk_status autotune_impl(const double *pos, const int32_t *species, int64_t n, c
                     if (rpt > tpb) continue;
                     if (rpt == 4 && (Rp / vpt != 1 || hp->max_degree != 3)) continue;   // see rows_per_thread
                     for (int nt : {0, 1})
-                        for (int xr : {0, 1})
+                        for (int xr : {0, 1, 2, 3})
                         for (int cc : {0, 1}) {
                             tbk_kpm_config c{};
                             c.compact_columns = cc;

@@ -85,7 +85,7 @@ tbk_kpm_config default_config(const tbk_ham *h, int32_t R, int32_t precision) {
     c.vectors_per_thread = (precision == TBK_PREC_C32 && pad_vectors(R) >= 2) ? 2 : 1;
     c.tiles_per_block = 2;
     c.nontemporal = 1;
-    c.xcd_remap = 0;
+    c.xcd_remap = 2;            // runs of 16 blocks per XCD: never slower than dispatch order on MI355X
     c.rows_per_thread = 1;
     c.persistent = 0;
     c.doubling = 0;
@@ -137,7 +137,7 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     TBK_CHECK(pl.cfg.tiles_per_block >= 1 && pl.cfg.tiles_per_block <= (1 << 20), TBK_ERR_INVALID_ARG,
               "tiles_per_block = %d outside [1, 2^20]", pl.cfg.tiles_per_block);
     TBK_CHECK(pl.cfg.nontemporal == 0 || pl.cfg.nontemporal == 1, TBK_ERR_INVALID_ARG, "nontemporal must be 0/1");
-    TBK_CHECK(pl.cfg.xcd_remap == 0 || pl.cfg.xcd_remap == 1, TBK_ERR_INVALID_ARG, "xcd_remap must be 0/1");
+    TBK_CHECK(pl.cfg.xcd_remap >= 0 && pl.cfg.xcd_remap <= 3, TBK_ERR_INVALID_ARG, "xcd_remap must be 0..3");
     TBK_CHECK(pl.cfg.rows_per_thread == 1 || pl.cfg.rows_per_thread == 2 || pl.cfg.rows_per_thread == 4,
               TBK_ERR_INVALID_ARG, "rows_per_thread must be 1, 2 or 4");
     TBK_CHECK(pl.cfg.persistent == 0 || pl.cfg.persistent == 1, TBK_ERR_INVALID_ARG, "persistent must be 0/1");
@@ -162,9 +162,11 @@ tbk_status make_plan(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, 
     const int64_t tiled = pl.cfg.atom_rows ? h->n_rows / pl.norb : h->n_rows;
     pl.n_tiles = (tiled + rpb - 1) / rpb;
     int64_t G = (pl.n_tiles + pl.cfg.tiles_per_block - 1) / pl.cfg.tiles_per_block;
-    if (pl.cfg.xcd_remap) {
-        // round up to a multiple of the XCD count; the extra blocks own no tile
-        G = ((G + kNumXcd - 1) / kNumXcd) * kNumXcd;
+    pl.G_real = G;
+    {
+        // round up to the block order's multiple; the extra blocks own no tile
+        const int64_t mult = xcd_grid_multiple(pl.cfg.xcd_remap);
+        G = ((G + mult - 1) / mult) * mult;
     }
     TBK_CHECK(G < (int64_t)INT32_MAX, TBK_ERR_UNSUPPORTED, "grid too large");
     pl.G = G;

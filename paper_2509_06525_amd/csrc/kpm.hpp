@@ -17,6 +17,7 @@ struct KpmPlan {
     int Rv = 1;                 // block partials per step (2 Rp with the doubling identities)
     int Mr = 1;                 // reduced rows: M, or M / 2 + 1 with the doubling identities
     int64_t n_tiles = 0, G = 0;
+    int64_t G_real = 0;         // blocks that own tiles (G rounded up for the XCD block order)
     bool tile_is_slice = false;
     int uniform_width = 0;      // > 0 when every slice stores this many entries per row
     size_t elem = 0, vec_bytes = 0;

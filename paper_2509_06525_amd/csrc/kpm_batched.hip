@@ -532,7 +532,7 @@ tbk_status run_seg(const tbk_ham *h, const SegPlan &sp, const double *a, const d
         TBK_CHECK(habort == 0, TBK_ERR_DEVICE, "persistent recurrence: a team barrier timed out");
     } else {
     int64_t Gt = ceil_div(T, sp.base.cfg.tiles_per_block);
-    if (st.xcd_remap) Gt = ceil_div(Gt, kNumXcd) * kNumXcd;
+    Gt = ceil_div(Gt, xcd_grid_multiple(st.xcd_remap)) * xcd_grid_multiple(st.xcd_remap);
     const unsigned G = (unsigned)Gt;
     const int K = sp.K;
     auto reduce = [&](int n0, int count) {

@@ -59,9 +59,28 @@ __device__ __forceinline__ void store_pack(VT *p, const Pack<VT, VPT> &o) {
     }
 }
 
+// Block order over the XCDs (workgroup b runs on XCD b % 8).  Mode 0: dispatch
+// order.  Mode 1: XCD x sweeps the contiguous eighth [x G/8, (x+1) G/8) of the
+// blocks.  Modes 2 and 3: XCD x takes runs of xcd_run(mode) consecutive blocks
+// and the 8 XCDs' runs lie side by side, so each XCD's neighbour rows stay in its
+// own L2 while the chip as a whole still sweeps one front (one region of HBM and
+// of the memory-side cache at a time).  The grid is a multiple of
+// xcd_grid_multiple(mode); blocks past the last tile own none.
+__host__ __device__ constexpr int64_t xcd_run(int mode) { return mode == 2 ? 16 : (mode == 3 ? 64 : 1); }
+__host__ __device__ constexpr int64_t xcd_grid_multiple(int mode) {
+    return mode == 0 ? 1 : (mode == 1 ? kNumXcd : kNumXcd * xcd_run(mode));
+}
+
 __device__ __forceinline__ int64_t logical_block(int xcd_remap) {
     const int64_t b = blockIdx.x, G = gridDim.x;
-    if (xcd_remap && (G % kNumXcd) == 0) return (b % kNumXcd) * (G / kNumXcd) + b / kNumXcd;
+    if (xcd_remap == 1 && (G % kNumXcd) == 0) return (b % kNumXcd) * (G / kNumXcd) + b / kNumXcd;
+    if (xcd_remap >= 2) {
+        const int64_t C = xcd_run(xcd_remap);
+        if (G % (kNumXcd * C) == 0) {
+            const int64_t x = b % kNumXcd, j = b / kNumXcd;
+            return (j / C) * (kNumXcd * C) + x * C + j % C;
+        }
+    }
     return b;
 }
 

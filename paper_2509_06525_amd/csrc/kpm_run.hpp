@@ -198,11 +198,13 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step(
 // r_int[i][v] = r[perm[i]][v] (v < R), 0 for padded vectors; block partials of
 // |r|^2 (in the doubling layout, each followed by VPT zeros).  With `seeded`
 // the phases are generated for atom perm[i] (output perm[i] R + v) instead of
-// being read from r.
+// being read from r.  Rows are dealt to the first `blocks` workgroups (the
+// blocks that own tiles), so the partition and the partial sums do not depend on
+// how far the grid was rounded up for the XCD block order; the others write 0.
 template <class VT, int L, int VPT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, const int32_t *__restrict__ perm,
                                                       int64_t n_rows, int32_t R, int32_t Rp, int32_t seeded,
-                                                      uint64_t seed, VT *__restrict__ r_int,
+                                                      uint64_t seed, int64_t blocks, VT *__restrict__ r_int,
                                                       double *__restrict__ partial) {
     constexpr int RPB = kThreads / L;
     const int lr = threadIdx.x / L;
@@ -210,7 +212,8 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
     double acc[VPT];
 #pragma unroll
     for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RPB + lr; i < n_rows; i += (int64_t)gridDim.x * RPB) {
+    const int64_t i0 = blockIdx.x < blocks ? (int64_t)blockIdx.x * RPB + lr : n_rows;
+    for (int64_t i = i0; i < n_rows; i += blocks * RPB) {
         const int64_t src = perm ? (int64_t)perm[i] : i;
 #pragma unroll
         for (int q = 0; q < VPT; ++q) {
@@ -247,14 +250,15 @@ __global__ __launch_bounds__(kThreads) void k_prepare(const VT *__restrict__ r, 
 template <class VT, int L, int VPT>
 __global__ __launch_bounds__(kThreads) void k_pair_overlap(const VT *__restrict__ left,
                                                            const VT *__restrict__ start, int64_t n_rows,
-                                                           int32_t Rp, double *__restrict__ partial) {
+                                                           int32_t Rp, int64_t blocks, double *__restrict__ partial) {
     constexpr int RPB = kThreads / L;
     const int lr = threadIdx.x / L;
     const int vs = threadIdx.x % L;
     double acc[VPT];
 #pragma unroll
     for (int q = 0; q < VPT; ++q) acc[q] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RPB + lr; i < n_rows; i += (int64_t)gridDim.x * RPB) {
+    const int64_t i0 = blockIdx.x < blocks ? (int64_t)blockIdx.x * RPB + lr : n_rows;
+    for (int64_t i = i0; i < n_rows; i += blocks * RPB) {
         const int64_t off = 2 * (i * Rp + vs * VPT);
         const Pack<VT, VPT> l = load_pack<false, VT, VPT>(left + off);
         const Pack<VT, VPT> t = load_pack<false, VT, VPT>(start + off);
@@ -442,10 +446,12 @@ tbk_status run_moments_t(const tbk_ham *h, const KpmPlan &pl, double a, double b
     // row 0 goes through the same partial slots as the steps (slot 0 of the first batch);
     // a continued run starts with the step n_start in slot 0
     if (pair)
-        k_pair_overlap<VT, L, VPT><<<(unsigned)pl.G, kThreads, 0, s>>>(left, start, h->n_rows, pl.Rp, part);
+        k_pair_overlap<VT, L, VPT><<<(unsigned)pl.G, kThreads, 0, s>>>(left, start, h->n_rows, pl.Rp, pl.G_real,
+                                                                       part);
     else if (n_start == 0)
         k_prepare<VT, L, VPT, DBL><<<(unsigned)pl.G, kThreads, 0, s>>>(r, h->perm, h->n_rows, R, pl.Rp,
-                                                                        pl.seeded ? 1 : 0, pl.seed, r_int, part);
+                                                                        pl.seeded ? 1 : 0, pl.seed, pl.G_real,
+                                                                        r_int, part);
     TBK_HIP(hipGetLastError());
     const VT *t0 = pair ? start : r_int;
 

@@ -12,7 +12,8 @@
 // MFMA layout (v_mfma_f32_16x16x16_bf16, one wavefront, lane l, n = l % 16,
 // q = l / 16): A[m][k] is held at lane m + 16 (k / 4), element k % 4; B[k][n]
 // at lane n + 16 (k / 4), element k % 4; D[m][n] at lane n + 16 (m / 4),
-// element m % 4.  Activations are kept transposed (hidden x bonds): a tile of
+// element m % 4.  The K = 32 products take one v_mfma_f32_16x16x32_bf16
+// (mfma32) on the two K = 16 halves.  Activations are kept transposed (hidden x bonds): a tile of
 // 16 bonds sits on n, so the D registers of one layer (hidden 16 m + 4 q + i)
 // are exactly the B operand of the next layer's K-block m, with no shuffle.
 // The weight-gradient products (sums over bonds) need bonds on K and go
@@ -65,6 +66,21 @@ __device__ __forceinline__ float rbf(float x) { return bf2f(f2bf(x)); }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// The K = 32 products in one CDNA4 v_mfma_f32_16x16x32_bf16: lane n + 16 q holds
+// K elements 8 q .. 8 q + 7 of A row n and of B column n.  The two K = 16 halves a
+// lane already holds (elements 4 q .. 4 q + 3 of each half) are concatenated, so
+// K element 8 q + j is index 4 q + j of the first half (j < 4) or of the second
+// half (j >= 4) on both operands: the same 32 products as two chained K = 16 MFMAs.
+__device__ __forceinline__ f32x4 mfma32(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+    const s16x8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const s16x8 b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
 }
 
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
@@ -273,8 +289,7 @@ __device__ __forceinline__ void mlp_tile_forward(const WaveWeights &w, bf16x4 xq
     }
     float part = 0.f;
     for (int mo = 0; mo < 2; ++mo) {
-        f32x4 z = mfma16(w.A2[mo][0], hb[0], zero);
-        z = mfma16(w.A2[mo][1], hb[1], z);
+        const f32x4 z = mfma32(w.A2[mo][0], w.A2[mo][1], hb[0], hb[1], zero);
         for (int i = 0; i < 4; ++i) {
             a.h2[mo][i] = tanhf(z[i] + w.b2[mo][i]);
             part += w.w3[mo][i] * rbf(a.h2[mo][i]);
@@ -285,14 +300,21 @@ __device__ __forceinline__ void mlp_tile_forward(const WaveWeights &w, bf16x4 xq
     a.y = part + w.b3;
 }
 
-// Order in which a minibatch takes the bonds of the training set: local bond b of
-// the minibatch that starts at position `first` is bond (mul (first + b) + add)
-// mod n_total, a bijection of [0, n_total) when gcd(mul, n_total) = 1; mul = 1,
-// add = 0 is the stored order.
+// Order in which a minibatch takes the bonds of the training set, in chunks of 16
+// consecutive bonds (one MFMA tile, so a tile's feature loads stay contiguous):
+// position i = first + b lies in chunk c = i / 16, which takes stored chunk
+// (mul c + add) mod n_chunks, a bijection of the n_chunks = n_total / 16 whole
+// chunks when gcd(mul, n_chunks) = 1; the last n_total % 16 bonds keep their
+// positions.  mul = 1, add = 0 is the stored order.
 struct BondOrder {
     int64_t n_total, first, mul, add;
     __device__ __forceinline__ int64_t map(int64_t b) const {
-        return (int64_t)(((unsigned __int128)mul * (uint64_t)(first + b) + (uint64_t)add) % (uint64_t)n_total);
+        const int64_t i = first + b;
+        const int64_t n_chunks = n_total >> 4;
+        const int64_t c = i >> 4;
+        if ((mul == 1 && add == 0) || c >= n_chunks) return i;
+        const uint64_t pc = (uint64_t)(((unsigned __int128)mul * (uint64_t)c + (uint64_t)add) % (uint64_t)n_chunks);
+        return (int64_t)(pc << 4) + (i & 15);
     }
 };
 
@@ -376,8 +398,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(int64_t nb, const uint
         // first layer deltas: d1 = (W2^T d2) * (1 - h1^2)
         f32x4 d1[2];
         for (int ko = 0; ko < 2; ++ko) {
-            f32x4 z = mfma16(w.A2T[ko][0], d2b[0], zero);
-            z = mfma16(w.A2T[ko][1], d2b[1], z);
+            const f32x4 z = mfma32(w.A2T[ko][0], w.A2T[ko][1], d2b[0], d2b[1], zero);
             for (int i = 0; i < 4; ++i) {
                 d1[ko][i] = z[i] * (1.f - a.h1[ko][i] * a.h1[ko][i]);
                 gb1[ko][i] += d1[ko][i];
@@ -442,19 +463,50 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_grad(int64_t nb, const uint
     }
 }
 
-// grad[p] = sum over wavefront partials in order (FP64), loss likewise.
-__global__ void k_grad_reduce(int64_t nwave, const float *__restrict__ gpart, const double *__restrict__ lpart,
-                              float *__restrict__ grad, double *__restrict__ loss) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < kNP) {
-        double s = 0.0;
-        for (int64_t wv = 0; wv < nwave; ++wv) s += (double)gpart[wv * kNP + p];
-        grad[p] = (float)s;
+// grad[p] = sum over the wavefront partials (FP64), loss likewise.  A block
+// serves kRedParams parameters with kRedSplit threads each: thread k of a
+// parameter sums waves k, k + kRedSplit, ... in order and the kRedSplit sums are
+// added in order (a fixed order: deterministic).  With `adam` the block then
+// applies the AdamW update of tbk_adamw_step to its parameters (the training
+// loop's fused step; t-dependent factors c1, c2 precomputed on the host).
+constexpr int kRedParams = 64, kRedSplit = 4;
+
+struct AdamArgs {
+    float *p, *m, *v;
+    float lr, b1, b2, eps, wd, c1, c2;
+};
+
+template <bool ADAM>
+__global__ __launch_bounds__(kRedParams * kRedSplit) void k_grad_reduce(int64_t nwave, const float *__restrict__ gpart,
+                                                                       const double *__restrict__ lpart,
+                                                                       float *__restrict__ grad,
+                                                                       double *__restrict__ loss, AdamArgs ad) {
+    __shared__ double red[kRedSplit][kRedParams];
+    const int pl = threadIdx.x % kRedParams, k = threadIdx.x / kRedParams;
+    const int p = blockIdx.x * kRedParams + pl;
+    double s = 0.0;
+    if (p < kNP)
+        for (int64_t wv = k; wv < nwave; wv += kRedSplit) s += (double)gpart[wv * kNP + p];
+    red[k][pl] = s;
+    __syncthreads();
+    if (k == 0 && p < kNP) {
+        double g = red[0][pl];
+        for (int j = 1; j < kRedSplit; ++j) g += red[j][pl];
+        const float gf = (float)g;
+        if (grad) grad[p] = gf;
+        if constexpr (ADAM) {
+            const float mi = ad.b1 * ad.m[p] + (1.f - ad.b1) * gf;
+            const float vi = ad.b2 * ad.v[p] + (1.f - ad.b2) * gf * gf;
+            ad.m[p] = mi;
+            ad.v[p] = vi;
+            const float mh = mi / ad.c1, vh = vi / ad.c2;
+            ad.p[p] -= ad.lr * (mh / (sqrtf(vh) + ad.eps) + ad.wd * ad.p[p]);
+        }
     }
-    if (p == kNP && loss) {
-        double s = 0.0;
-        for (int64_t wv = 0; wv < nwave; ++wv) s += lpart[wv];
-        *loss = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        double l = 0.0;
+        for (int64_t wv = 0; wv < nwave; ++wv) l += lpart[wv];
+        *loss = l;
     }
 }
 
@@ -554,7 +606,9 @@ __global__ void k_row_bounds(int64_t n, const int64_t *__restrict__ ptr, const V
 
 int mlp_grid(int64_t nb) {
     const int64_t tiles = (nb + 15) / 16;
-    const int64_t want = (tiles + kWaves * 8 - 1) / (kWaves * 8);   // about 8 tiles per wavefront
+    // about 2 tiles per wavefront: a minibatch of 2048 bonds spreads over 16 workgroups
+    // (its tiles' latency chains run side by side; the per-wave partials stay small)
+    const int64_t want = (tiles + kWaves * 2 - 1) / (kWaves * 2);
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024));
 }
 
@@ -822,7 +876,7 @@ extern "C" tbk_status tbk_mlp_workspace_size(int64_t nb, int64_t *bytes) {
 
 static tbk_status loss_grad_impl(int64_t nb, const uint16_t *X, const float *target, const float *weight,
                                  const float *params, float *grad, double *loss, void *work, int64_t work_bytes,
-                                 hipStream_t s, BondOrder order) {
+                                 hipStream_t s, BondOrder order, const AdamArgs *adam = nullptr) {
     int64_t need = 0;
     tbk_status st = tbk_mlp_workspace_size(nb, &need);
     if (st != TBK_OK) return st;
@@ -835,7 +889,11 @@ static tbk_status loss_grad_impl(int64_t nb, const uint16_t *X, const float *tar
     double *lpart = reinterpret_cast<double *>(static_cast<char *>(work) + ((nwave * kNP * 4 + 255) / 256) * 256);
     k_mlp_grad<<<G, 64 * kWaves, 0, s>>>(nb, X, target, weight, params, 1.0f / (float)nb, order, gpart, lpart);
     TBK_HIP(hipGetLastError());
-    k_grad_reduce<<<(kNP + 1 + 255) / 256, 256, 0, s>>>(nwave, gpart, lpart, grad, loss);
+    const unsigned rb = (kNP + kRedParams - 1) / kRedParams;
+    if (adam)
+        k_grad_reduce<true><<<rb, kRedParams * kRedSplit, 0, s>>>(nwave, gpart, lpart, grad, loss, *adam);
+    else
+        k_grad_reduce<false><<<rb, kRedParams * kRedSplit, 0, s>>>(nwave, gpart, lpart, grad, loss, AdamArgs{});
     TBK_HIP(hipGetLastError());
     return TBK_OK;
 }
@@ -878,15 +936,15 @@ static uint64_t gcd64(uint64_t a, uint64_t b) {
     return a;
 }
 
-// Bond order of one epoch: in order without a seed; otherwise an affine
-// bijection i -> (mul i + add) mod nb with mul coprime to nb taken from the
-// middle half of [1, nb), so consecutive minibatch positions land far apart in
-// the stored (structure-major) order.
+// Bond order of one epoch: in order without a seed; otherwise the 16-bond chunks
+// go through an affine bijection c -> (mul c + add) mod n_chunks with mul coprime
+// to n_chunks taken from the middle half of [1, n_chunks), so consecutive chunks of
+// a minibatch land far apart in the stored (structure-major) order.
 static BondOrder epoch_order(int64_t nb, uint64_t seed, int e) {
-    if (seed == 0 || nb < 3) return BondOrder{nb, 0, 1, 0};
-    const uint64_t n = (uint64_t)nb;
+    const uint64_t n = (uint64_t)(nb >> 4);
+    if (seed == 0 || n < 3) return BondOrder{nb, 0, 1, 0};
     uint64_t mul = n / 4 + mix64(seed, 2 * (uint64_t)e) % (n / 2 + 1);
-    while (mul == 0 || gcd64(mul, n) != 1) mul = mul + 1 < n ? mul + 1 : 1;
+    while (mul <= 1 || gcd64(mul, n) != 1) mul = mul + 1 < n ? mul + 1 : 2;
     return BondOrder{nb, 0, (int64_t)mul, (int64_t)(mix64(seed, 2 * (uint64_t)e + 1) % n)};
 }
 
@@ -898,6 +956,9 @@ extern "C" tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *
     clear_error();
     TBK_CHECK(nb >= 1 && epochs >= 1 && batch >= 1 && step && loss_history, TBK_ERR_INVALID_ARG, "bad arguments");
     TBK_CHECK(params && m && v, TBK_ERR_INVALID_ARG, "NULL array");
+    TBK_CHECK(*step >= 0, TBK_ERR_INVALID_ARG, "step count %lld < 0", (long long)*step);
+    TBK_CHECK(lr >= 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && wd >= 0,
+              TBK_ERR_INVALID_ARG, "bad AdamW hyper-parameters");
     hipStream_t s = as_stream(stream);
     const int64_t bsz = std::min(batch, nb);
     int64_t need = 0;
@@ -919,11 +980,13 @@ extern "C" tbk_status tbk_mlp_train(int64_t nb, const uint16_t *X, const float *
         for (int64_t bt = 0; bt < nbatch; ++bt) {
             const int64_t b0 = bt * bsz, cnt = std::min(bsz, nb - b0);
             order.first = b0;
-            st = loss_grad_impl(cnt, X, target, weight, params, grad, losses.as<double>() + bt, gw,
-                                work_bytes - extra, s, order);
-            if (st != TBK_OK) return st;
             *step += 1;
-            st = tbk_adamw_step(kNP, params, grad, m, v, *step, lr, beta1, beta2, eps, wd, stream);
+            // the AdamW update of tbk_adamw_step, fused into the gradient reduction
+            const AdamArgs ad{params, m, v, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)wd,
+                              (float)(1.0 - std::pow(beta1, (double)*step)),
+                              (float)(1.0 - std::pow(beta2, (double)*step))};
+            st = loss_grad_impl(cnt, X, target, weight, params, grad, losses.as<double>() + bt, gw,
+                                work_bytes - extra, s, order, &ad);
             if (st != TBK_OK) return st;
         }
         TBK_HIP(hipMemcpyAsync(hl.data(), losses.as<double>(), sizeof(double) * nbatch, hipMemcpyDeviceToHost, s));

@@ -236,6 +236,22 @@ def test_training_lowers_the_loss_and_is_deterministic(shuffle_seed):
     assert h1[-1] < 0.05 * var
 
 
+def test_training_step_is_loss_grad_then_adamw():
+    """One minibatch of tbk_mlp_train (AdamW fused into the gradient reduction) equals
+    tbk_mlp_loss_grad followed by tbk_adamw_step on the same bonds."""
+    X, y, mean, std = _training_set(count=2, n_max=2000)
+    nb = X.shape[0]
+    p0 = G.to_dev(synth.init_mlp_params(4, out_scale=1.0))
+    tr = tbkpm.MlpTrainer(p0.clone())
+    tr.train(X, y, epochs=1, batch=nb, lr=3e-3, wd=1e-3, shuffle_seed=0)
+    loss, g = tbkpm.mlp_loss_grad(X, y, G.to_dev(synth.init_mlp_params(4, out_scale=1.0)))
+    p1, m, v = p0.clone(), torch.zeros_like(p0), torch.zeros_like(p0)
+    tbkpm.adamw_step(p1, g, m, v, 1, 3e-3, 0.9, 0.999, 1e-8, 1e-3)
+    torch.testing.assert_close(tr.params, p1, rtol=1e-6, atol=1e-7)
+    torch.testing.assert_close(tr.m, m, rtol=1e-6, atol=1e-12)
+    torch.testing.assert_close(tr.v, v, rtol=1e-6, atol=1e-16)
+
+
 def test_shuffled_epochs_visit_every_bond_once():
     """With a zero learning rate the parameters stay fixed, so an epoch's mean loss is the
     mean over the bonds it visits: the shuffled epochs (two different permutations,

@@ -147,8 +147,9 @@ def test_xcd_mapping_is_bitwise_neutral(tpb):
     a, b = H.scales()
     r = G.to_dev(synth.random_phase(pos.shape[0], 4, 23, np.complex64))
     m0 = tbkpm.kpm_moments_batched(H, a, b, r, 120, "c32", config=tbkpm.make_config(2, tpb, 1, 0, 1, 0))
-    m1 = tbkpm.kpm_moments_batched(H, a, b, r, 120, "c32", config=tbkpm.make_config(2, tpb, 1, 1, 1, 0))
-    torch.testing.assert_close(m0, m1, rtol=0, atol=0)
+    for xr in (1, 2, 3):
+        m1 = tbkpm.kpm_moments_batched(H, a, b, r, 120, "c32", config=tbkpm.make_config(2, tpb, 1, xr, 1, 0))
+        torch.testing.assert_close(m0, m1, rtol=0, atol=0)
 
 
 def test_persistent_barrier_timeout_is_reported(monkeypatch):

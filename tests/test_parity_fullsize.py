@@ -143,8 +143,9 @@ def test_fullsize_snapshot_batch():
     rd = G.to_dev(r)
     mu0 = tbkpm.kpm_moments_batched(H, a, b, rd, M, "c32", config=tbkpm.make_config(2, 2, 1, 0, 1, 0))
     for tpb in (1, 2, 4):
-        mu1 = tbkpm.kpm_moments_batched(H, a, b, rd, M, "c32", config=tbkpm.make_config(2, tpb, 1, 1, 1, 0))
-        torch.testing.assert_close(mu0, mu1, rtol=0, atol=0)
+        for xr in (1, 2):
+            mu1 = tbkpm.kpm_moments_batched(H, a, b, rd, M, "c32", config=tbkpm.make_config(2, tpb, 1, xr, 1, 0))
+            torch.testing.assert_close(mu0, mu1, rtol=0, atol=0)
     mu = mu0.cpu().numpy()
     for k in sorted({0, len(snaps) - 1, int(np.argmin([s.n for s in snaps]))}):
         s = snaps[k]

@@ -9,6 +9,7 @@ the clamped tail.
 import itertools
 
 import numpy as np
+import torch
 import pytest
 
 from oracle import oracle as O
@@ -18,7 +19,7 @@ from tests import gpu_util as G
 pytestmark = pytest.mark.gpu
 
 SHAPES = [tbkpm.make_config(1, tpb, nt, xr, rpt)
-          for tpb, nt, xr, rpt in itertools.product([1, 2, 3], [0, 1], [0, 1], [1, 2]) if rpt <= tpb]
+          for tpb, nt, xr, rpt in itertools.product([1, 2, 3], [0, 1], [0, 1, 2, 3], [1, 2]) if rpt <= tpb]
 
 
 def _oracle_mu(s, a, b, r, M):
@@ -57,13 +58,30 @@ def test_c32_shapes_agree(R, vpt):
     mu_o = _oracle_mu(s, a, b, r, M)
     rd = G.to_dev(r)
     base = None
-    for tpb, nt, xr, rpt in [(1, 1, 1, 1), (2, 0, 0, 2), (3, 1, 0, 2), (4, 0, 1, 1)]:
+    for tpb, nt, xr, rpt in [(1, 1, 1, 1), (2, 0, 0, 2), (3, 1, 0, 2), (4, 0, 1, 1), (2, 1, 2, 2), (1, 0, 3, 1)]:
         cfg = tbkpm.make_config(vpt, tpb, nt, xr, rpt)
         mu = tbkpm.kpm_moments(H, a, b, rd, M, "c32", config=cfg).cpu().numpy()
         assert np.abs(mu - mu_o).max() <= 1e-4 * s.n
         if base is None:
             base = mu
         assert np.abs(mu - base).max() <= 1e-12 * s.n
+
+
+@pytest.mark.parametrize("R,tpb,rpt", [(1, 4, 4), (1, 1, 1), (16, 2, 2)])
+def test_xcd_block_orders_are_bitwise_neutral(R, tpb, rpt):
+    """Every block order over the XCDs (dispatch order, contiguous eighths, runs of 16
+    or 64 blocks) gives the same moments bit for bit: a block's tiles and the order
+    in which block partials are summed do not change; blocks past the last tile add
+    exact zeros."""
+    s = synth.graphene_sheet(70, 50, 0.05, 8)          # 14,000 rows: grids of 14 to 55 blocks
+    H = G.build(s, fmt="sell_f32", slice=64 if R == 1 else 16)
+    a, b = G.oracle_ab_of(s)
+    rd = G.to_dev(synth.random_phase(s.n, R, 3, np.complex64))
+    vpt = 2 if R > 1 else 1
+    mus = [tbkpm.kpm_moments(H, a, b, rd, 150, "c32", config=tbkpm.make_config(vpt, tpb, 1, xr, rpt))
+           for xr in (0, 1, 2, 3)]
+    for m in mus[1:]:
+        assert torch.equal(m, mus[0])
 
 
 def test_autotune_choice_is_valid_and_cached(tmp_path, monkeypatch):
@@ -88,7 +106,8 @@ def test_bad_shape_rejected():
     H = G.build(s, fmt="sell_f64", slice=64)
     r = G.to_dev(synth.random_phase(s.n, 2, 1))
     for bad in (tbkpm.make_config(2, 1, 1, 0, 1), tbkpm.make_config(1, 0, 1, 0, 1),
-                tbkpm.make_config(1, 1, 2, 0, 1), tbkpm.make_config(1, 1, 1, 0, 3)):
+                tbkpm.make_config(1, 1, 2, 0, 1), tbkpm.make_config(1, 1, 1, 0, 3),
+                tbkpm.make_config(1, 1, 1, 4, 1), tbkpm.make_config(1, 1, 1, -1, 1)):
         with pytest.raises(tbkpm.TBKError) as e:
             tbkpm.kpm_moments(H, 9.0, 0.0, r, 8, "f64", config=bad)
         assert e.value.name == "INVALID_ARG"
