@@ -47,6 +47,12 @@ def parse():
     p.add_argument("--train-shuffle-seed", type=int, default=None,
                    help="snapshot workload: shuffle seed of the network's training (0 = stored order; "
                         "default: the workload's)")
+    p.add_argument("--launch", default=None,
+                   help="snapshot workload: use this named launch shape instead of timing them all "
+                        "(e.g. per_step_xcd2_tpb1; for counter runs)")
+    p.add_argument("--no-train", action="store_true",
+                   help="snapshot workload: skip the network's training (seeded initial parameters) and the "
+                        "learned-vs-plain comparison (for counter runs of the recurrence)")
     p.add_argument("--no-variants", action="store_true",
                    help="skip every variant form (doubling, uniform values) and the oracle comparison run")
     p.add_argument("--retune", action="store_true",
@@ -228,10 +234,11 @@ def bench_snapshots(args, w):
     y = tbkpm.coordination_target(tb, tv, synth.COORD_KAPPA, synth.COORD_Z0)
     trainer = tbkpm.MlpTrainer(torch.from_numpy(synth.init_mlp_params(tcfg["init_seed"])).to(dev))
     hist = []
-    for epochs, lr in tcfg["schedule"]:
+    for epochs, lr in (() if args.no_train else tcfg["schedule"]):
         hist += trainer.train(X, y, epochs=epochs, batch=tcfg["batch"], lr=lr, wd=tcfg["wd"],
                               shuffle_seed=tcfg["shuffle_seed"] if args.train_shuffle_seed is None
                               else args.train_shuffle_seed)
+    hist = hist or [float("nan")]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"trained on {X.shape[0]} bonds: loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s")
@@ -254,6 +261,8 @@ def bench_snapshots(args, w):
         for xr in (1, 2):
             shapes[f"per_step_xcd{xr}_tpb{tpb}"] = tbkpm.make_config(2, tpb, 1, xr, 1, 0)
     timing = {}
+    if args.launch is not None:
+        shapes = {args.launch: shapes[args.launch]}
     for name, cfg in shapes.items():
         try:
             tbkpm.kpm_moments_batched(H, a, b, r, 32, "c32", config=cfg, stream=stream)
@@ -308,7 +317,8 @@ def bench_snapshots(args, w):
     launch_bytes = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 4
     launch_s = step_ms * 1e-3 / step_launches if step_launches else kmed * 1e-3 / (M - 1)
     achieved = launch_bytes / launch_s / 1e9
-    judge = learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M, stream)
+    judge = None if args.no_train else learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M,
+                                                        stream)
     out = {
         "metric": METRIC, "value": N * M * R / sec, "unit": "atom*moments/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,

@@ -275,13 +275,17 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
         for (int o = 0; o < NORB; ++o)
 #pragma unroll
             for (int q = 0; q < VPT; ++q) { y[o].re[q] = 0; y[o].im[q] = 0; }
+        // the next neighbour's column is loaded before this neighbour's block is
+        // applied, so a neighbour waits for one memory round trip (its gathers)
+        int32_t cn = w > 0 ? ld<NT>(bcol + base) : 0;
         for (int k = 0; k < w; ++k) {
             const int64_t qb = base + (int64_t)k * stride;
-            const int32_t c = ld<NT>(bcol + qb);
+            const int32_t c = cn;
             Pack<VT, VPT> x[NORB];
 #pragma unroll
             for (int b = 0; b < NORB; ++b)
                 x[b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c + b) * Rp + voff));
+            if (k + 1 < w) cn = ld<NT>(bcol + qb + stride);
             const VT *bv = bval + (int64_t)NORB * NORB * qb;
 #pragma unroll
             for (int o = 0; o < NORB; ++o) {
@@ -453,25 +457,35 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
             for (int q = 0; q < VPT; ++q) { y[o].re[q] = 0; y[o].im[q] = 0; }
         // two bonds per pass: both bonds' columns, displacements and neighbour rows are
         // loaded before either block is applied (slots past the width repeat the last one
-        // and are skipped, as are padding slots, d = 0)
+        // and are skipped, as are padding slots, d = 0).  The next pass's columns and
+        // displacements are loaded before this pass's blocks are applied, so a pass waits
+        // for one memory round trip (its gathers) instead of two.
         constexpr int KU = 2;
+        int32_t cn[KU];
+        VT dxn[KU], dyn[KU], dzn[KU];
+        auto load_bonds = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int64_t qb = base + (int64_t)max(0, min(k0 + u, w - 1)) * stride;
+                cn[u] = ld<NT>(bcol + qb);
+                dxn[u] = ld<NT>(geo + 3 * qb);
+                dyn[u] = ld<NT>(geo + 3 * qb + 1);
+                dzn[u] = ld<NT>(geo + 3 * qb + 2);
+            }
+        };
+        if (w > 0) load_bonds(0);
         for (int k0 = 0; k0 < w; k0 += KU) {
             int32_t c[KU];
             VT dx[KU], dy[KU], dz[KU];
 #pragma unroll
-            for (int u = 0; u < KU; ++u) {
-                const int64_t qb = base + (int64_t)min(k0 + u, w - 1) * stride;
-                c[u] = ld<NT>(bcol + qb);
-                dx[u] = ld<NT>(geo + 3 * qb);
-                dy[u] = ld<NT>(geo + 3 * qb + 1);
-                dz[u] = ld<NT>(geo + 3 * qb + 2);
-            }
+            for (int u = 0; u < KU; ++u) { c[u] = cn[u]; dx[u] = dxn[u]; dy[u] = dyn[u]; dz[u] = dzn[u]; }
             Pack<VT, VPT> x[KU][NORB];
 #pragma unroll
             for (int u = 0; u < KU; ++u)
 #pragma unroll
                 for (int b = 0; b < NORB; ++b)
                     x[u][b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c[u] + b) * Rp + voff));
+            if (k0 + KU < w) load_bonds(k0 + KU);
 #pragma unroll
             for (int u = 0; u < KU; ++u) {
                 const VT r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
