@@ -82,20 +82,24 @@ def cheb_step_bytes(H, Rp, elem, diag, read_r=True, read_values=True, compact=Fa
     return b
 
 
-def kernel_source_hash():
-    """Hash of the recurrence kernel's sources (a stored counter profile is valid only for these)."""
+KERNEL_SOURCES = ("kpm.hip", "kpm_run.hpp", "kpm.hpp", "kpm_dev.hpp")
+SEG_KERNEL_SOURCES = ("kpm_batched.hip", "kpm.hpp", "kpm_dev.hpp")
+
+
+def kernel_source_hash(files=KERNEL_SOURCES):
+    """Hash of a recurrence kernel's sources (a stored counter profile is valid only for these)."""
     h = hashlib.sha256()
-    for f in ("kpm.hip", "kpm_run.hpp", "kpm.hpp", "kpm_dev.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2509_06525_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload, kernel, slice_, launch):
+def profiled_traffic(workload, kernel, slice_, launch, prefix="k_cheb_step", files=KERNEL_SOURCES):
     """HBM bytes per launch of `kernel` from the counter profile stored for `workload`
     (FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration), or None when
     the kernel's sources or the launch shape differ from the profiled ones."""
-    path = os.path.join(ROOT, "profiles", f"k_cheb_step_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{prefix}_{workload}.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -105,7 +109,7 @@ def profiled_traffic(workload, kernel, slice_, launch):
                 parts = dict(kv.split("=", 1) for kv in line.split()[1:])
                 rec[parts["kernel"]] = parts
     r = rec.get(kernel)
-    if r is None or r["sources"] != kernel_source_hash() or int(r["slice"]) != int(slice_):
+    if r is None or r["sources"] != kernel_source_hash(files) or int(r["slice"]) != int(slice_):
         return None
     if r["launch"] != ",".join(f"{k}:{v}" for k, v in sorted(launch.items())):
         return None
@@ -331,7 +335,12 @@ def bench_snapshots(args, w):
         "learned_vs_plain": judge,
         "kpm_ms_median": kmed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if cfg.persistent else profiled_traffic(
+                         args.workload, "seg", 64, cfg.as_dict(), "k_cheb_step_seg", SEG_KERNEL_SOURCES),
+                     "traffic_source": f"profiles/k_cheb_step_seg_{args.workload}.md (stored rocprofv3 "
+                                       "FETCH_SIZE, WRITE_SIZE runs, copy-calibrated; null when the kernel or "
+                                       "launch shape differs)",
                      "kernel": "k_cheb_persistent" if cfg.persistent else "k_cheb_step_seg",
                      "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6,
                      "launches_timed": step_launches, "launch_us_kpm_window": kmed * 1e3 / (M - 1)},
