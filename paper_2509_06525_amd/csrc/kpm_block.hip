@@ -234,6 +234,96 @@ __device__ __forceinline__ void finish_rows_staged(const Pack<VT, 1> (&y)[NORB],
     __syncthreads();
 }
 
+// Copies nbytes (a multiple of 4) from global memory to LDS with direct
+// global-to-LDS loads: no register holds the data, and the copy completes at the
+// issuing wave's next wait for all vector memory operations.  Every wave of the
+// block takes 64-chunk runs of 16 bytes (the LDS destination of a run is uniform
+// over the wave); the trailing words of a length that is not a multiple of 16 go
+// through ordinary loads.
+template <bool NT>
+__device__ __forceinline__ void dma_to_lds(const void *g, void *l, int nbytes) {
+    const int lane = threadIdx.x & 63;
+    const int n16 = nbytes >> 4;
+    for (int c0 = (int)(threadIdx.x >> 6) * 64; c0 < n16; c0 += kThreads)
+        if (c0 + lane < n16)
+            __builtin_amdgcn_global_load_lds(static_cast<const char *>(g) + 16 * (int64_t)(c0 + lane),
+                                             (__attribute__((address_space(3))) void *)(static_cast<char *>(l) + 16 * c0),
+                                             16, 0, NT ? 2 : 0);
+    const int w0 = n16 * 4, nw = (nbytes >> 2) - w0;
+    if ((int)threadIdx.x < nw)
+        static_cast<int *>(l)[w0 + threadIdx.x] = static_cast<const int *>(g)[w0 + threadIdx.x];
+}
+
+// One-vector FP32 finish with prefetched streams: the tile's T_{n-1} and r (T_n
+// in the doubling form) were copied to LDS (sprev, sr) when the tile started, so
+// their round trip overlapped the bond loop; here the copies are awaited, the own
+// rows of T_n (diagonal term) and the onsite energies are read, and T_{n+1} is
+// staged through sprev for a contiguous store.
+template <int NORB, bool FIRST, bool DIAG, bool NT, bool DBL>
+__device__ __forceinline__ void finish_rows_prefetched(const Pack<float, 1> (&y)[NORB], const StepScalars<float> &a,
+                                                       int64_t t, int la, int64_t at, bool ok,
+                                                       const float *__restrict__ onsite, const float *__restrict__ tcur,
+                                                       float *tnext, f2v *sprev, const f2v *sr,
+                                                       double (&acc)[DBL ? 2 : 1]) {
+    const int64_t row0 = (int64_t)NORB * (t * kThreads);
+    const int nrow = (int)min((int64_t)NORB * kThreads, a.n_rows - row0);
+    const int mine = NORB * la;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    f2v pv[NORB], rv[NORB], xs[NORB];
+#pragma unroll
+    for (int o = 0; o < NORB; ++o) {
+        if constexpr (!FIRST) pv[o] = sprev[mine + o];
+        rv[o] = sr[mine + o];
+    }
+    float dg[NORB];
+    if constexpr (DIAG) {
+        if constexpr (!DBL) {
+#pragma unroll
+            for (int o = 0; o < NORB; ++o) xs[o] = reinterpret_cast<const f2v *>(tcur)[(int64_t)NORB * at + o];
+        }
+        __syncthreads();                                  // sprev is read; its space takes the onsite energies
+        float *sons = reinterpret_cast<float *>(sprev);
+        if (onsite) dma_to_lds<NT>(onsite + row0, sons, nrow * 4);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < NORB; ++o) dg[o] = (onsite ? sons[mine + o] : 0.0f) - a.shift;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = 0; o < NORB; ++o) {
+        float yr = y[o].re[0], yi = y[o].im[0];
+        if constexpr (DIAG) {
+            const f2v x = DBL ? rv[o] : xs[o];
+            yr += dg[o] * x.x;
+            yi += dg[o] * x.y;
+        }
+        f2v ov;
+        if constexpr (FIRST) {
+            ov.x = a.c1 * yr;
+            ov.y = a.c1 * yi;
+        } else {
+            ov.x = a.c1 * yr - pv[o].x;
+            ov.y = a.c1 * yi - pv[o].y;
+        }
+        if (ok) {
+            const double cr = (double)rv[o].x * (double)ov.x + (double)rv[o].y * (double)ov.y;
+            if constexpr (DBL) {
+                acc[0] += (double)ov.x * (double)ov.x + (double)ov.y * (double)ov.y;
+                acc[1] += cr;
+            } else {
+                acc[0] += cr;
+            }
+        }
+        sprev[mine + o] = ov;
+    }
+    __syncthreads();
+    f2v *g = reinterpret_cast<f2v *>(tnext) + row0;
+    for (int e = threadIdx.x; e < nrow; e += kThreads) st<NT>(g + e, sprev[e]);
+    __syncthreads();
+}
+
 // Atom form: a thread owns every orbital row of one atom (VPT vectors), so
 // each neighbour's NORB orbital rows of T_n are gathered once per atom instead
 // of once per orbital row; the block's rows are read one after the other
@@ -353,63 +443,133 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
     block_reduce_store<L, NA>(acc, partial, lb);
 }
 
-// Integrals and radial law of the displacement form, in the vector type.
+// Integrals and radial law of the displacement form, in the vector type.  The
+// integrals are regrouped on the host into the combinations the projector form
+// uses: ss, sp, pp_sigma - pp_pi, pp_pi, sd, pd_sigma, pd_pi / sqrt(3),
+// dd_sigma - dd_delta, (dd_pi - dd_delta) / 3, dd_delta.
 template <class VT> struct GeomParams {
-    VT v[10];        // integrals at r0
+    VT v[10];        // regrouped integrals at r0
     VT inv_r0;       // 1 / r0
     VT beta;         // decay exponent
+    VT e0, e1;       // f(r) = 2^(e0 - e1 r): e0 = beta / ln 2, e1 = beta / (r0 ln 2)
 };
 
+// One bond's geometry for the projector form: the direction cosines c, sqrt(3) c,
+// the d-orbital sigma vector u along c and the regrouped integrals scaled by f(r).
+// Formed once per bond and used for both components of every vector.
+template <class VT> struct BondFrame {
+    VT k[10];
+    VT l, m, n, sl, sm, sn;
+    VT u[5];
+};
+
+// Direction cosines and f(r) from the displacement d (|d| > 0).  In FP32 the
+// reciprocal square root and the power of two are single instructions (about one
+// ulp each); in FP64 the correctly rounded sqrt, division and exp.
+template <class VT>
+__device__ __forceinline__ BondFrame<VT> bond_frame(const GeomParams<VT> &gp, VT dx, VT dy, VT dz, VT r2) {
+    BondFrame<VT> b;
+    VT inv, f;
+    if constexpr (sizeof(VT) == 4) {
+        inv = __builtin_amdgcn_rsqf(r2);
+        f = __builtin_amdgcn_exp2f(gp.e0 - gp.e1 * (r2 * inv));
+    } else {
+        const VT rr = sqrt(r2);
+        inv = (VT)1 / rr;
+        f = exp(-gp.beta * (rr * gp.inv_r0 - (VT)1));
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) b.k[q] = gp.v[q] * f;
+    const VT s3 = (VT)1.7320508075688772;
+    b.l = dx * inv;
+    b.m = dy * inv;
+    b.n = dz * inv;
+    b.sl = s3 * b.l;
+    b.sm = s3 * b.m;
+    b.sn = s3 * b.n;
+    b.u[0] = b.sl * b.m;
+    b.u[1] = b.sm * b.n;
+    b.u[2] = b.sn * b.l;
+    b.u[3] = (VT)0.5 * (b.sl * b.l - b.sm * b.m);
+    b.u[4] = b.n * b.n - (VT)0.5 * (b.l * b.l + b.m * b.m);
+    return b;
+}
+
 // y += B x for the one-species Slater-Koster block B of a bond with direction
-// cosines c = (l, m, n) and integrals v (already scaled by f(r)), without
-// forming B: with u the d-orbital sigma vector along c (the s-d row of the table
-// divided by V_sd_sigma) and J = du/dc (u is homogeneous of degree 2, so
-// c.grad u_b = 2 u_b), the table's blocks are
+// cosines c = (l, m, n), without forming B: with u the d-orbital sigma vector
+// along c (the s-d row of the table divided by V_sd_sigma) and J = du/dc (u is
+// homogeneous of degree 2, so c.grad u_b = 2 u_b), the table's blocks are
 //   p-p: V_pp_pi I + (V_pp_sigma - V_pp_pi) c c^T,
 //   p-d: V_pd_sigma c u^T + V_pd_pi (J^T - 2 c u^T) / sqrt(3)    (d-p: minus its transpose),
 //   d-d: V_dd_delta I + (V_dd_sigma - V_dd_delta) u u^T + (V_dd_pi - V_dd_delta) J (I - c c^T) J^T / 3,
-// so one bond costs about 76 multiply-adds per vector component instead of the
+// so one bond costs about 70 multiply-adds per vector component instead of the
 // NORB^2 products plus the table.
 template <class VT, int NORB>
-__device__ __forceinline__ void sk_apply(const VT (&v)[10], VT l, VT m, VT n, const VT (&x)[NORB], VT (&y)[NORB]) {
-    const VT ss = v[0], sp = v[1], pps = v[2], ppp = v[3];
+__device__ __forceinline__ void sk_apply(const BondFrame<VT> &b, const VT (&x)[NORB], VT (&y)[NORB]) {
+    const VT ss = b.k[0], sp = b.k[1], ppd = b.k[2], ppp = b.k[3];
+    const VT l = b.l, m = b.m, n = b.n;
     const VT xs = x[0], xp0 = x[1], xp1 = x[2], xp2 = x[3];
     const VT cp = l * xp0 + m * xp1 + n * xp2;
+    // every update is a chain of multiply-adds into y (one rounding per product)
     if constexpr (NORB == 4) {
-        y[0] += ss * xs + sp * cp;
-        const VT t = (pps - ppp) * cp - sp * xs;
-        y[1] += ppp * xp0 + l * t;
-        y[2] += ppp * xp1 + m * t;
-        y[3] += ppp * xp2 + n * t;
+        const VT t = ppd * cp - sp * xs;
+        y[0] += ss * xs;
+        y[0] += sp * cp;
+        y[1] += ppp * xp0;
+        y[1] += l * t;
+        y[2] += ppp * xp1;
+        y[2] += m * t;
+        y[3] += ppp * xp2;
+        y[3] += n * t;
     } else {
-        const VT s3 = (VT)1.7320508075688772;
-        const VT sd = v[4], pds = v[5], pdp = v[6], dds = v[7], ddp = v[8], ddd = v[9];
-        const VT u0 = s3 * l * m, u1 = s3 * m * n, u2 = s3 * n * l;
-        const VT u3 = (VT)0.5 * s3 * (l * l - m * m), u4 = n * n - (VT)0.5 * (l * l + m * m);
+        const VT sd = b.k[4], pds = b.k[5], k1 = b.k[6], ddd_s = b.k[7], k2 = b.k[8], ddd = b.k[9];
+        const VT sl = b.sl, sm = b.sm, sn = b.sn;
         const VT xd0 = x[4], xd1 = x[5], xd2 = x[6], xd3 = x[7], xd4 = x[8];
-        const VT ud = u0 * xd0 + u1 * xd1 + u2 * xd2 + u3 * xd3 + u4 * xd4;
-        // G = J^T x_d
-        const VT gl = s3 * (m * xd0 + n * xd2 + l * xd3) - l * xd4;
-        const VT gm = s3 * (l * xd0 + n * xd1 - m * xd3) - m * xd4;
-        const VT gn = s3 * (m * xd1 + l * xd2) + (VT)2 * n * xd4;
-        const VT ud2 = (VT)2 * ud;
-        const VT pl = gl - ud2 * l, pm = gm - ud2 * m, pn = gn - ud2 * n;      // (I - c c^T) G
-        const VT k1 = pdp / s3, k2 = (ddp - ddd) / (VT)3;
-        y[0] += ss * xs + sp * cp + sd * ud;
-        const VT t = (pps - ppp) * cp + pds * ud - sp * xs;
-        y[1] += ppp * xp0 + l * t + k1 * pl;
-        y[2] += ppp * xp1 + m * t + k1 * pm;
-        y[3] += ppp * xp2 + n * t + k1 * pn;
+        const VT ud = b.u[0] * xd0 + b.u[1] * xd1 + b.u[2] * xd2 + b.u[3] * xd3 + b.u[4] * xd4;
+        // G = J^T x_d, then (I - c c^T) G = G - 2 (u.x_d) c
+        const VT nud2 = (VT)-2 * ud;
+        const VT pl = sm * xd0 + sn * xd2 + sl * xd3 - l * xd4 + nud2 * l;
+        const VT pm = sl * xd0 + sn * xd1 - sm * xd3 - m * xd4 + nud2 * m;
+        const VT pn = sm * xd1 + sl * xd2 + (VT)2 * n * xd4 + nud2 * n;
+        const VT t = ppd * cp + pds * ud - sp * xs;
+        y[0] += ss * xs;
+        y[0] += sp * cp;
+        y[0] += sd * ud;
+        y[1] += ppp * xp0;
+        y[1] += l * t;
+        y[1] += k1 * pl;
+        y[2] += ppp * xp1;
+        y[2] += m * t;
+        y[2] += k1 * pm;
+        y[3] += ppp * xp2;
+        y[3] += n * t;
+        y[3] += k1 * pn;
         // h = -k1 (x_p - c cp) + k2 (I - c c^T) G, then J h
         const VT hl = k2 * pl - k1 * (xp0 - l * cp);
         const VT hm = k2 * pm - k1 * (xp1 - m * cp);
         const VT hn = k2 * pn - k1 * (xp2 - n * cp);
-        const VT w = sd * xs - pds * cp + (dds - ddd) * ud;
-        y[4] += ddd * xd0 + u0 * w + s3 * (m * hl + l * hm);
-        y[5] += ddd * xd1 + u1 * w + s3 * (n * hm + m * hn);
-        y[6] += ddd * xd2 + u2 * w + s3 * (n * hl + l * hn);
-        y[7] += ddd * xd3 + u3 * w + s3 * (l * hl - m * hm);
-        y[8] += ddd * xd4 + u4 * w + ((VT)2 * n * hn - l * hl - m * hm);
+        const VT w = sd * xs - pds * cp + ddd_s * ud;
+        y[4] += ddd * xd0;
+        y[4] += b.u[0] * w;
+        y[4] += sm * hl;
+        y[4] += sl * hm;
+        y[5] += ddd * xd1;
+        y[5] += b.u[1] * w;
+        y[5] += sn * hm;
+        y[5] += sm * hn;
+        y[6] += ddd * xd2;
+        y[6] += b.u[2] * w;
+        y[6] += sn * hl;
+        y[6] += sl * hn;
+        y[7] += ddd * xd3;
+        y[7] += b.u[3] * w;
+        y[7] += sl * hl;
+        y[7] -= sm * hm;
+        y[8] += ddd * xd4;
+        y[8] += b.u[4] * w;
+        y[8] += (VT)2 * n * hn;
+        y[8] -= l * hl;
+        y[8] -= m * hm;
     }
 }
 
@@ -418,7 +578,8 @@ __device__ __forceinline__ void sk_apply(const VT (&v)[10], VT l, VT m, VT n, co
 // applied without being formed: r = |d|, direction cosines d / r, integrals
 // scaled by f(r) = exp(-beta (r / r0 - 1)), then sk_apply in the vector type.
 // Padding slots (d = 0) are skipped.  Per bond this reads 12 B (float) instead
-// of 4 NORB^2 B.
+// of 4 NORB^2 B.  With one FP32 vector and staging, the finish's T_{n-1} and r
+// are copied to LDS when the tile starts (finish_rows_prefetched).
 template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ geo,
@@ -441,6 +602,10 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
 
+    // FP32 one-vector tiles with staging: the finish's streams are copied to LDS
+    // when the tile starts (see finish_rows_prefetched)
+    constexpr bool kPre = L == 1 && VPT == 1 && sizeof(VT) == 4;
+    __shared__ f2v sprev[kPre ? NORB * kThreads : 1], sr[kPre ? NORB * kThreads : 1];
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t au = t * APB + la;
         const bool ok = au <= last;
@@ -473,8 +638,20 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
                 dzn[u] = ld<NT>(geo + 3 * qb + 2);
             }
         };
-        if (w > 0) load_bonds(0);
-        for (int k0 = 0; k0 < w; k0 += KU) {
+        // the finish's streams (T_{n-1}, r) copied to LDS ahead of the bond loop
+        auto prefetch_finish = [&]() {
+            if constexpr (kPre) {
+                if (stage) {
+                    const int64_t row0 = (int64_t)NORB * (t * APB);
+                    const int nbytes = 8 * (int)min((int64_t)NORB * APB, a.n_rows - row0);
+                    if constexpr (!FIRST) dma_to_lds<NT>(reinterpret_cast<const f2v *>(tprev) + row0, sprev, nbytes);
+                    dma_to_lds<NT && !DBL>(reinterpret_cast<const f2v *>(DBL ? tcur : r) + row0, sr, nbytes);
+                }
+            }
+        };
+        // one pass: the gathers of bonds k0, k0 + 1, the next pass's bond loads, then
+        // both blocks
+        auto pass = [&](int k0) {
             int32_t c[KU];
             VT dx[KU], dy[KU], dz[KU];
 #pragma unroll
@@ -490,13 +667,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
             for (int u = 0; u < KU; ++u) {
                 const VT r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
                 if (k0 + u >= w || !(r2 > (VT)0)) continue;
-                const VT rr = sqrt(r2);
-                const VT inv = (VT)1 / rr;
-                const VT f = exp(-gp.beta * (rr * gp.inv_r0 - (VT)1));
-                VT vf[10];
-#pragma unroll
-                for (int l = 0; l < 10; ++l) vf[l] = gp.v[l] * f;
-                const VT cl = dx[u] * inv, cm = dy[u] * inv, cn = dz[u] * inv;
+                const BondFrame<VT> bf = bond_frame(gp, dx[u], dy[u], dz[u], r2);
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
                     VT xr[NORB], xi[NORB], yr[NORB], yi[NORB];
@@ -507,8 +678,8 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
                         yr[b] = y[b].re[q];
                         yi[b] = y[b].im[q];
                     }
-                    sk_apply<VT, NORB>(vf, cl, cm, cn, xr, yr);
-                    sk_apply<VT, NORB>(vf, cl, cm, cn, xi, yi);
+                    sk_apply<VT, NORB>(bf, xr, yr);
+                    sk_apply<VT, NORB>(bf, xi, yi);
 #pragma unroll
                     for (int b = 0; b < NORB; ++b) {
                         y[b].re[q] = yr[b];
@@ -516,9 +687,19 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
                     }
                 }
             }
-        }
+        };
+        // the finish's copies go out with the first bond loads, whose round trip they share
+        if (w > 0) load_bonds(0);
+        prefetch_finish();
+        for (int k0 = 0; k0 < w; k0 += KU) pass(k0);
         bool staged = false;
-        if constexpr (L == 1 && VPT == 1) {
+        if constexpr (kPre) {
+            if (stage) {
+                finish_rows_prefetched<NORB, FIRST, DIAG, NT, DBL>(y, a, t, la, at, ok, onsite, tcur, tnext, sprev, sr,
+                                                                  acc);
+                staged = true;
+            }
+        } else if constexpr (L == 1 && VPT == 1) {
             if (stage) {
                 finish_rows_staged<VT, NORB, FIRST, DIAG, NT, DBL>(y, a, t, la, at, ok, onsite, tcur, tprev, tnext,
                                                                   r, acc);
@@ -577,9 +758,19 @@ void launch_fd(const KpmPlan &pl, hipStream_t s, const StepPtrs<VT> &p, const St
     // enough to keep every CU busy between the staging barriers, 2 = always, 4 = never)
     const int stage = pl.cfg.rows_per_thread == 2 || (pl.cfg.rows_per_thread == 1 && pl.n_tiles >= kStageMinTiles);
     GeomParams<VT> gp;
-    for (int l = 0; l < 10; ++l) gp.v[l] = (VT)pl.geom_params[l];
-    gp.inv_r0 = pl.geom_params[10] > 0 ? (VT)(1.0 / pl.geom_params[10]) : (VT)0;
-    gp.beta = (VT)pl.geom_params[11];
+    {
+        // regroup the integrals (ss, sp, pp_sigma, pp_pi, sd, pd_sigma, pd_pi, dd_sigma,
+        // dd_pi, dd_delta) into the projector form's combinations, in FP64
+        const double *v = pl.geom_params;
+        const double g[10] = {v[0], v[1], v[2] - v[3], v[3], v[4], v[5], v[6] / std::sqrt(3.0),
+                              v[7] - v[9], (v[8] - v[9]) / 3.0, v[9]};
+        for (int l = 0; l < 10; ++l) gp.v[l] = (VT)g[l];
+        const double r0 = pl.geom_params[10], beta = pl.geom_params[11];
+        gp.inv_r0 = r0 > 0 ? (VT)(1.0 / r0) : (VT)0;
+        gp.beta = (VT)beta;
+        gp.e0 = (VT)(beta / std::log(2.0));
+        gp.e1 = r0 > 0 ? (VT)(beta / (r0 * std::log(2.0))) : (VT)0;
+    }
 #define TBK_BLK(NT, DBL)                                                                                    \
     do {                                                                                                    \
         if (pl.geom)                                                                                        \
