@@ -146,6 +146,36 @@ def test_geom_third_neighbours_against_oracle_and_stored_blocks(rows):
     assert G.rel_l2(O.kpm_dos(mg.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
 
 
+@pytest.mark.parametrize("rows", [1, 2])
+def test_geom_partial_last_tile_with_a_vacancy(rows):
+    """A sheet with one atom removed (1343 atoms, 63 in the last 256-atom tile, so the
+    tile's rows of T_{n-1}, r and the onsite energies end on a partial 16-byte chunk):
+    the staged form (rows_per_thread 2, whose FP32 streams are copied to LDS at the
+    tile's start) and the direct form agree with the stored blocks and the oracle."""
+    base = synth.graphene_sheet(24, 14, 0.05, 17)
+    keep = np.arange(base.n) != 700
+    s = synth.Structure(pos=np.ascontiguousarray(base.pos[keep]), species=base.species[keep],
+                        box=base.box, periodic=base.periodic)
+    assert s.n % 256 == 63
+    mk = lambda fmt: tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic,
+                                                *synth.SK_V, synth.SK_ES, synth.SK_EP, r_cut=R3NN, r0=synth.R0,
+                                                beta=synth.BETA, fmt=fmt, slice=64, d=synth.SK_D, e_d=synth.SK_ED)
+    Hg, Hb, Hg64 = mk("bgeom_f32"), mk("bsell4_f32"), mk("bgeom_f64")
+    csr = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10, synth.SK_ES, synth.SK_EP, r_cut=R3NN, r0=synth.R0,
+                           beta=synth.BETA, e_d=synth.SK_ED)[0]
+    a, b = G.oracle_ab(csr)
+    r = synth.random_phase(9 * s.n, 1, 23, np.complex64)
+    cfg = tbkpm.make_config(1, 1, 1, 2, rows, atom_rows=1)
+    mg = tbkpm.kpm_moments(Hg, a, b, G.to_dev(r), 96, "c32", config=cfg).cpu().numpy()
+    mb = tbkpm.kpm_moments(Hb, a, b, G.to_dev(r), 96, "c32", config=cfg).cpu().numpy()
+    assert np.abs(mg - mb).max() <= 1e-4 * 9 * s.n
+    mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 96)
+    E = synth.energy_grid(a, b)
+    assert G.rel_l2(O.kpm_dos(mg.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+    m64 = tbkpm.kpm_moments(Hg64, a, b, G.to_dev(r.astype(np.complex128)), 96, "f64", config=cfg).cpu().numpy()
+    assert np.abs(m64 - mo).max() <= 1e-10 * 9 * s.n
+
+
 def bloch_spectrum(cell, tx, ty):
     """Exact spectrum of the pristine s, p, d third-neighbour sheet on a torus of tx x ty copies
     of the small periodic sheet `cell`, from the oracle's blocks of the small sheet and the
