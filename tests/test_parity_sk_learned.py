@@ -1,18 +1,22 @@
 """GPU parity of the learned Slater-Koster Hamiltonian (Eq. (2): one network per
 two-centre integral on the bond's edge features, angular factors of the table).
 
-Network outputs per bond against the oracle's bfloat16-operand forward (FP32
-accumulation on the GPU: 2e-5 relative to the largest output on bonds whose
-activations sit clear of a bfloat16 rounding boundary); Hamiltonian entries
-against the oracle's table with the same per-bond integral scales (5e-5 relative
-on entries of clear bonds, 1e-2 on all); moments FP64 and C32 DOS against the
-oracle's on the learned Hamiltonian."""
+Network outputs per bond against the oracle's bfloat16-operand forward: the GPU
+forms its activations in FP32, so an activation within 1e-6 of a bfloat16
+rounding boundary may round either way; every output must lie within 1e-6 of an
+output of one admissible set of rounding decisions (tests/mlp_ref.py enumerates
+them), and outputs of bonds with no such activation within 1e-6 of the oracle's.
+Hamiltonian entries against the oracle's table evaluated with the GPU's own
+integral scales (so the assembly is checked to rounding: 2e-15 relative in FP64,
+FP32 storage rounding in FP32); onsite additions likewise; moments FP64 and C32
+DOS against the oracle's on the learned Hamiltonian."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2509_06525_amd import synth, tbkpm
 from tests import gpu_util as G
+from tests import mlp_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -73,22 +77,31 @@ def test_learned_sk_matches_oracle(norb, fmt, slice_):
     csr, Y, clear = oracle_learned(s, P, mean, std, v, hop, norb)
     y = y.cpu().numpy().astype(np.float64)
     assert y.shape == Y.shape
-    assert clear.mean() >= 0.3
-    assert np.abs(y - Y)[:, clear].max() <= 2e-5 * np.abs(Y).max()
     assert np.abs(Y).max() > 0.05                      # the scales are far from 1
+    feats = O.bond_features(hop, v, synth.R_DESC, mean, std)
+    # features whose FP64 value sits within 1e-9 of a bfloat16 boundary may be coded one
+    # ulp apart by the GPU's own FP64 arithmetic (none expected at these sizes)
+    fclear = ~(mlp_ref.bf16_rne(feats * (1 - 1e-9)) != mlp_ref.bf16_rne(feats * (1 + 1e-9))).any(1)
+    assert fclear.mean() > 0.99
+    for k in range(K):
+        cands, kclear = mlp_ref.forward_candidates(feats, P[k].astype(np.float64))
+        exc, _ = mlp_ref.excess(cands, y[k])
+        assert np.all(exc[fclear] <= 1e-6), k
+        assert np.all(np.abs(y[k] - Y[k])[fclear & kclear] <= 1e-6), k
+    # the assembly: the oracle's table with the GPU's own integral scales
+    csr_g, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, V10 if norb == 9 else synth.SK_V, synth.SK_ES,
+                                synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, pairs=hop,
+                                e_d=synth.SK_ED, scale=1.0 + y.T)
     rows, cols, vals, onsite = (G.block_entries(H) if fmt.startswith("bsell4") else G.entries_in_atom_order(H))
-    orow, ocol, oval = G.csr_entries(csr)
+    orow, ocol, oval = G.csr_entries(csr_g)
     o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
     np.testing.assert_array_equal(rows[o1], orow[o2])
     np.testing.assert_array_equal(cols[o1], ocol[o2])
-    bond_of = {(int(i), int(j)): e for e, (i, j) in enumerate(zip(hop[0], hop[1]))}
-    ent_clear = np.array([clear[bond_of[(min(i // norb, j // norb), max(i // norb, j // norb))]]
-                          for i, j in zip(orow[o2], ocol[o2])])
-    err = np.abs(vals[o1] - oval[o2])
     big = np.abs(oval[o2]).max()
-    tol = 5e-5 if fmt.endswith("f64") else 1e-4
-    assert err[ent_clear].max() <= tol * big
-    assert err.max() <= 1e-2 * big
+    if fmt.endswith("f64"):
+        np.testing.assert_allclose(vals[o1], oval[o2], rtol=2e-15, atol=2e-15 * big)
+    else:
+        np.testing.assert_allclose(vals[o1], oval[o2], rtol=2 ** -23, atol=1e-6 * big)
     odiag = csr.diag.astype(np.float32).astype(np.float64) if fmt.endswith("f32") else csr.diag
     np.testing.assert_array_equal(onsite, odiag)
     lo, hi = H.bounds
@@ -219,17 +232,20 @@ def test_onsite_network_matches_oracle(norb, fmt, multi):
     P = onsite_params(ns, nsh, 30)
     X = O.node_features(vo, mean, std)
     add = np.zeros((s.n, 3))
-    clear = None
+    cands = {}
     for a in range(ns):
         for l in range(nsh):
-            y, h1, h2 = O.mlp_forward(X, P[a, l].astype(np.float64), bf16_ops=True, keep=True)
+            y = O.mlp_forward(X, P[a, l].astype(np.float64), bf16_ops=True)
             sel = s.species == a
             add[sel, l] = y[sel]
-            clear = G.bf16_decisions_clear(h1, h2)
+            cands[a, l] = mlp_ref.forward_candidates(X, P[a, l].astype(np.float64))
     vv = (synth.SK_V + synth.SK_D) if norb == 9 else synth.SK_V
     csr, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, vv, synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP,
                               r0=synth.R0, beta=synth.BETA, e_d=synth.SK_ED, onsite_add=add,
                               species=s.species if multi else None, pair_v=pv, species_e=se)
+    csr0, _ = O.sk_hamiltonian(s.pos, s.box, s.periodic, vv, synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP,
+                               r0=synth.R0, beta=synth.BETA, e_d=synth.SK_ED,
+                               species=s.species if multi else None, pair_v=pv, species_e=se)
     H = tbkpm.build_hamiltonian_sk(G.to_dev(s.pos), G.to_dev(s.species), s.box, s.periodic, *synth.SK_V,
                                    synth.SK_ES, synth.SK_EP, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
                                    fmt=fmt, slice=16, d=synth.SK_D if norb == 9 else None, e_d=synth.SK_ED,
@@ -243,11 +259,23 @@ def test_onsite_network_matches_oracle(norb, fmt, multi):
     np.testing.assert_array_equal(cols[o1], ocol[o2])
     tol = 1e-6 if fmt.endswith("f32") else 2e-15
     np.testing.assert_allclose(vals[o1], oval[o2], rtol=tol, atol=tol * np.abs(oval).max())
-    atom_clear = np.repeat(clear, norb)
-    assert atom_clear.mean() >= 0.3
-    d = np.abs(onsite - csr.diag)
+    # the GPU's onsite addition of each atom's shell (row of its first orbital in the
+    # shell) within 1e-6 of an admissible output of that species' and shell's network
+    # (plus FP32 storage rounding of the onsite energy in FP32 formats)
     scale_e = np.abs(csr.diag).max()
-    assert d[atom_clear].max() <= 2e-5 * np.abs(add).max() + (1e-6 * scale_e if fmt.endswith("f32") else 0.0)
-    assert d.max() <= 1e-2 * np.abs(add).max() + 1e-6 * scale_e
+    slack = 1e-6 + (2 ** -23 * scale_e if fmt.endswith("f32") else 0.0)
+    first = (0, 1, 4)
+    for a in range(ns):
+        for l in range(nsh):
+            at = np.nonzero(s.species == a)[0]
+            got = onsite[norb * at + first[l]] - csr0.diag[norb * at + first[l]]
+            c = [cands[a, l][0][i] for i in at]
+            exc, _ = mlp_ref.excess(c, got)
+            assert np.all(exc <= slack), (a, l)
+            width = (1, 3, 5)[l]                    # every orbital of the shell gets the same addition
+            for o in range(1, width):
+                other = onsite[norb * at + first[l] + o] - csr0.diag[norb * at + first[l] + o]
+                np.testing.assert_allclose(other, got, rtol=0, atol=slack)
+    np.testing.assert_allclose(onsite, csr.diag, rtol=0, atol=1e-3 * np.abs(add).max() + slack)
     lo, hi = O.gershgorin(csr)
     assert H.bounds[0] == pytest.approx(lo, rel=1e-3) and H.bounds[1] == pytest.approx(hi, rel=1e-3)
