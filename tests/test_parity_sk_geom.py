@@ -151,7 +151,8 @@ def test_geom_partial_last_tile_with_a_vacancy(rows):
     """A sheet with one atom removed (1343 atoms, 63 in the last 256-atom tile, so the
     tile's rows of T_{n-1}, r and the onsite energies end on a partial 16-byte chunk):
     the staged form (rows_per_thread 2, whose FP32 streams are copied to LDS at the
-    tile's start) and the direct form agree with the stored blocks and the oracle."""
+    tile's start) and the direct form agree with the stored blocks and the oracle, the
+    doubling form (T_n copied instead of r) too."""
     base = synth.graphene_sheet(24, 14, 0.05, 17)
     keep = np.arange(base.n) != 700
     s = synth.Structure(pos=np.ascontiguousarray(base.pos[keep]), species=base.species[keep],
@@ -172,6 +173,8 @@ def test_geom_partial_last_tile_with_a_vacancy(rows):
     mo, _ = O.kpm_moments(csr, a, b, r.astype(np.complex128), 96)
     E = synth.energy_grid(a, b)
     assert G.rel_l2(O.kpm_dos(mg.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
+    md = tbkpm.kpm_moments(Hg, a, b, G.to_dev(r), 96, "c32", config=tbkpm.with_doubling(cfg)).cpu().numpy()
+    assert G.rel_l2(O.kpm_dos(md.mean(0), a, b, E), O.kpm_dos(mo.mean(0), a, b, E)) <= 1e-4
     m64 = tbkpm.kpm_moments(Hg64, a, b, G.to_dev(r.astype(np.complex128)), 96, "f64", config=cfg).cpu().numpy()
     assert np.abs(m64 - mo).max() <= 1e-10 * 9 * s.n
 
