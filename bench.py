@@ -657,7 +657,9 @@ def bench_vac(args, w):
     """Velocity-autocorrelation conductivity (Eq. (3)): per step and frame the Hamiltonian
     and velocity operator are built, the correlation moments of n_t propagation steps
     computed (M - 1 recurrence launches, two Chebyshev-Bessel propagations and one
-    velocity product per time step) and sigma(E, t) formed.  A multi-frame workload also
+    velocity product per time step; the recurrences of B = tbkpm.vac_time_batch(R)
+    consecutive time steps run as one recurrence of R * B vectors) and sigma(E, t)
+    formed.  A multi-frame workload also
     computes each frame's DOS moments and integrated DOS and, over the frames, the
     averaged plateau conductivity, carriers and mobility (Sec. 2.4, Sec. 3)."""
     import torch
@@ -681,8 +683,9 @@ def bench_vac(args, w):
     if not args.no_tune and not sk:
         if not args.retune:
             use_shipped_tuning()
-        tune = tbkpm.autotune(pos[0], sp, s.box, s.periodic, s.onsite, s.t_pair, R, "c32", r_cut=synth.R_HOP,
-                              r0=synth.R0, beta=synth.BETA, stream=stream)
+        # the recurrence runs R * B vectors at a time (B time steps)
+        tune = tbkpm.autotune(pos[0], sp, s.box, s.periodic, s.onsite, s.t_pair, R * tbkpm.vac_time_batch(R), "c32",
+                              r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA, stream=stream)
         slice_, config = tune.slice, tune.config
         log(f"tuned: slice {slice_} {config.as_dict()}")
     if sk:
@@ -750,11 +753,14 @@ def bench_vac(args, w):
         Rp *= 2
     per_val = norb * norb if sk else 1
     hb = st.n_entries * (4 * per_val + 4) + st.n_ptr * 8    # values (FP32) + columns, slice offsets
-    rec = hb + nr * Rp * 8 * 4                          # recurrence launch (pair form: left vector for r)
+    B = tbkpm.vac_time_batch(R)
+    n_batches = -(-n_t // B)
+    # recurrence launches read the matrix once per batch of B time steps and, per time
+    # step, its vectors (pair form: gather T_n, T_{n-1}, left vector, write T_{n+1})
+    rec = n_batches * (M - 1) * hb + n_t * (M - 1) * nr * Rp * 8 * 4
     prop = hb + nr * Rp * 8 * 5                         # propagator term: T_k gather, T_{k-1}, T_{k+1}, acc r/w
     vel = hb + nr * Rp * 8 * 2
-    per_t = (M - 1) * rec + 2 * (n_cheb - 1) * prop + vel
-    total = F * n_t * per_t
+    total = F * (rec + n_t * (2 * (n_cheb - 1) * prop + vel))
     achieved = total / sec / 1e9
     out = {
         "metric": "VAC atom*moments*timesteps/s" if not sk else "VAC orbital*moments*timesteps/s",
@@ -764,7 +770,7 @@ def bench_vac(args, w):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "orbital_rows": nr, "frames": F, "moments": M,
                    "vectors": R,
-                   "time_steps": n_t, "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"],
+                   "time_steps": n_t, "time_batch": B, "dt_fs": dt, "propagator_terms": n_cheb, "format": w["fmt"],
                    "slice": slice_, "precision": "c32", "a_eV": a, "b_eV": b,
                    "launch": None if config is None else config.as_dict()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

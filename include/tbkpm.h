@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 12
+#define TBK_ABI_VERSION 13
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -809,10 +809,12 @@ tbk_status tb_build_velocity(const double *pos, const double box[3], const int32
  * |J_k(z)| < 1e-15, plus one.  -1 on a bad argument. */
 int32_t lsqt_chebyshev_terms(double a, double dt);
 
-/* Bytes of device workspace lsqt_vac_moments needs (recurrence workspace of
- * kpm_workspace_size_config plus six [n_rows][R_pad] vectors). */
+/* Bytes of device workspace lsqt_vac_moments needs for the same (R, M,
+ * precision, time_batch, cfg): the workspace of the recurrence of R * B vectors
+ * (B = the time batch, below), six [n_rows][R_pad] vectors and, when B > 1, the
+ * batch's start and left vectors and moments. */
 tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
-                               const tbk_kpm_config *cfg, int64_t *bytes);
+                               int32_t time_batch, const tbk_kpm_config *cfg, int64_t *bytes);
 
 /*
  * Correlation moments of Eq. (3) with the random-phase trace of Sec. 2.4:
@@ -824,16 +826,23 @@ tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t p
  * Summed over a complete basis, nu[j][.][m] is the T_m moment of
  * Tr[delta(E - H) Re(V V(t_j))]; lsqt_sigma turns nu into sigma(E, t).
  *   r    device c128|c64 [n_rows][R] start vectors, caller's atom order;
- *   vx   from tb_build_velocity (scalar or block layout, as h); cfg: launch
- *        shape of the recurrence (NULL = default; doubling must be 0);
+ *   vx   from tb_build_velocity (scalar or block layout, as h);
+ *   time_batch  B: the recurrences of B consecutive time steps run together as
+ *        one recurrence of R * B vectors (each step's moments are independent of
+ *        the others', so only the order of the FP64 sums' tiling changes; the
+ *        matrix is read once per B steps); 0 = max(1, 16 / R), 1 = one step at a
+ *        time; R * B <= 64;
+ *   cfg  launch shape of that recurrence of R * B vectors (NULL = default;
+ *        doubling must be 0);
  *   nu   device double [n_t][R][M].
  * Synchronises `stream`.  Errors: as kpm_moments_config; INVALID_ARG (dt <= 0,
- * n_t outside [1, 10^6], doubling); SPECTRUM when a moment is not finite.
+ * n_t outside [1, 10^6], doubling, time_batch < 0, R * B > 64); SPECTRUM when a
+ * moment is not finite.
  */
 tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double a, double b, const void *r,
                             int32_t R, int32_t M, int32_t n_t, double dt, int32_t n_cheb,
-                            int32_t precision, const tbk_kpm_config *cfg, void *work,
-                            int64_t work_bytes, double *nu, void *stream);
+                            int32_t precision, int32_t time_batch, const tbk_kpm_config *cfg,
+                            void *work, int64_t work_bytes, double *nu, void *stream);
 
 /*
  * Running conductivity of Eq. (3) without the prefactor 2 e^2 / Omega:

@@ -17,6 +17,7 @@
 // one thread per (row, vector) (for block Hamiltonians: per (orbital row,
 // vector), over the atom's blocks); the M-1 recurrence steps per time step,
 // which dominate, run in the tuned recurrence kernel.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -109,6 +110,26 @@ __global__ void k_permute_in(const VT *__restrict__ r, const int32_t *__restrict
     }
     out[2 * idx] = re;
     out[2 * idx + 1] = im;
+}
+
+// dst[i][col0 + v] = src[i][v] for v < R: one time step's vectors into its
+// columns of a batch ([rows][Rpb] interleaved complex, like every vector here).
+template <class VT>
+__global__ void k_insert_cols(const VT *__restrict__ src, int32_t Rp, int32_t R, int64_t n, int32_t Rpb,
+                              int32_t col0, VT *__restrict__ dst) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * R) return;
+    const int64_t i = idx / R;
+    const int v = (int)(idx % R);
+    const int64_t s = 2 * (i * Rp + v), d = 2 * (i * Rpb + col0 + v);
+    dst[d] = src[s];
+    dst[d + 1] = src[s + 1];
+}
+
+template <class VT>
+__global__ void k_zero(int64_t m, VT *__restrict__ x) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < m) x[idx] = (VT)0;
 }
 
 // y = V x, (V x)_i = i sum_q vx[q] x_col[q].
@@ -260,14 +281,29 @@ int32_t default_terms(double z) {
     return k + 1;
 }
 
+// Time steps whose recurrences run together as one recurrence of R * B vectors
+// (their moments are independent, so batching only changes the summation
+// tiling): 0 picks B = max(1, 16 / R).
+int32_t time_batch_of(int32_t R, int32_t time_batch) {
+    return time_batch > 0 ? time_batch : std::max(1, 16 / R);
+}
+
 struct LsqtLayout {
-    KpmPlan pl;
-    size_t vec = 0, off_vec = 0, total = 0;   // six vectors after the recurrence workspace
+    KpmPlan pl;                 // recurrence of R * B vectors (B time steps)
+    int32_t B = 1;              // time steps per recurrence
+    size_t vec = 0, off_vec = 0;        // six [rows][R_pad] vectors after the recurrence workspace
+    size_t bvec = 0, off_batch = 0;     // start and left vectors of a batch, [rows][pad(R B)] (B > 1)
+    size_t off_mu = 0, total = 0;       // a batch's moments [R B][M] (B > 1)
 };
 
-tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, const tbk_kpm_config *cfg,
-                       LsqtLayout &ly) {
-    tbk_status st = make_plan(h, R, M, precision, cfg, ly.pl);
+tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, int32_t time_batch,
+                       const tbk_kpm_config *cfg, LsqtLayout &ly) {
+    TBK_CHECK(R >= 1 && R <= 64, TBK_ERR_INVALID_ARG, "R = %d outside [1, 64]", R);
+    TBK_CHECK(time_batch >= 0, TBK_ERR_INVALID_ARG, "time_batch = %d < 0", time_batch);
+    ly.B = time_batch_of(R, time_batch);
+    TBK_CHECK((int64_t)R * ly.B <= 64, TBK_ERR_INVALID_ARG, "R * time_batch = %lld exceeds 64 vectors",
+              (long long)R * ly.B);
+    tbk_status st = make_plan(h, R * ly.B, M, precision, cfg, ly.pl);
     if (st != TBK_OK) return st;
     TBK_CHECK(ly.pl.cfg.doubling == 0, TBK_ERR_INVALID_ARG,
               "the doubling identities need the same left and right vectors; VAC moments use the direct form");
@@ -276,9 +312,12 @@ tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision
     TBK_CHECK(h->fmt != TBK_CSR_F64 || h->slice == 1, TBK_ERR_INVALID_ARG, "CSR needs slice 1");
     const size_t elem = precision == TBK_PREC_C32 ? sizeof(float) : sizeof(double);
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    ly.vec = a256((size_t)h->n_rows * ly.pl.Rp * 2 * elem);
+    ly.vec = a256((size_t)h->n_rows * pad_vectors(R) * 2 * elem);
     ly.off_vec = a256(ly.pl.total);
-    ly.total = ly.off_vec + 6 * ly.vec;
+    ly.off_batch = ly.off_vec + 6 * ly.vec;
+    ly.bvec = ly.B > 1 ? a256((size_t)h->n_rows * ly.pl.Rp * 2 * elem) : 0;
+    ly.off_mu = ly.off_batch + 2 * ly.bvec;
+    ly.total = ly.off_mu + (ly.B > 1 ? a256((size_t)R * ly.B * M * sizeof(double)) : 0);
     return TBK_OK;
 }
 
@@ -287,7 +326,7 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
                    int32_t n_t, double dt, int32_t n_cheb, int32_t precision, const LsqtLayout &ly, char *work,
                    double *nu, hipStream_t s) {
     const KpmPlan &pl = ly.pl;
-    const int32_t Rp = pl.Rp;
+    const int32_t Rp = pad_vectors(R);
     const int64_t n = h->n_rows;
     VT *v[6];
     for (int k = 0; k < 6; ++k) v[k] = reinterpret_cast<VT *>(work + ly.off_vec + k * ly.vec);
@@ -351,16 +390,52 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
     k_permute_in<VT><<<g, kLsqtThreads, 0, s>>>(r, h->perm, n, R, Rp, phiR);
     apply_v(phiR, phiL);
     TBK_HIP(hipGetLastError());
-    for (int32_t j = 0; j < n_t; ++j) {
-        apply_v(phiR, wv);
-        TBK_HIP(hipGetLastError());
-        tbk_status st = run_plan(h, pl, a, b, nullptr, R, M, precision, work, nu + (int64_t)j * R * M, s, wv, phiL);
-        if (st != TBK_OK) return st;
-        if (j + 1 < n_t) {
-            st = evolve(phiR);
+    if (ly.B == 1) {
+        for (int32_t j = 0; j < n_t; ++j) {
+            apply_v(phiR, wv);
+            TBK_HIP(hipGetLastError());
+            tbk_status st = run_plan(h, pl, a, b, nullptr, R, M, precision, work, nu + (int64_t)j * R * M, s, wv,
+                                     phiL);
             if (st != TBK_OK) return st;
-            st = evolve(phiL);
+            if (j + 1 < n_t) {
+                st = evolve(phiR);
+                if (st != TBK_OK) return st;
+                st = evolve(phiL);
+                if (st != TBK_OK) return st;
+            }
+        }
+    } else {
+        // B time steps at a time: V phi_R(t_j) and phi_L(t_j) of each step go into
+        // columns q R .. q R + R - 1 of the batch's start and left vectors (unused
+        // columns of a short last batch stay zero), then one pair-form recurrence of
+        // R B vectors gives the batch's moments [q][v][m] = nu[j0 + q][v][m]
+        const int32_t Rb = pl.Rp;
+        VT *start = reinterpret_cast<VT *>(work + ly.off_batch);
+        VT *left = reinterpret_cast<VT *>(work + ly.off_batch + ly.bvec);
+        double *mub = reinterpret_cast<double *>(work + ly.off_mu);
+        const int64_t nb_el = 2 * n * (int64_t)Rb;
+        const unsigned gz = (unsigned)ceil_div(nb_el, kLsqtThreads);
+        const unsigned gi = (unsigned)ceil_div(n * R, kLsqtThreads);
+        for (int32_t j0 = 0; j0 < n_t; j0 += ly.B) {
+            const int32_t nb = std::min(ly.B, n_t - j0);
+            k_zero<VT><<<gz, kLsqtThreads, 0, s>>>(nb_el, start);
+            k_zero<VT><<<gz, kLsqtThreads, 0, s>>>(nb_el, left);
+            for (int32_t q = 0; q < nb; ++q) {
+                apply_v(phiR, wv);
+                k_insert_cols<VT><<<gi, kLsqtThreads, 0, s>>>(wv, Rp, R, n, Rb, q * R, start);
+                k_insert_cols<VT><<<gi, kLsqtThreads, 0, s>>>(phiL, Rp, R, n, Rb, q * R, left);
+                TBK_HIP(hipGetLastError());
+                if (j0 + q + 1 < n_t) {
+                    tbk_status st = evolve(phiR);
+                    if (st != TBK_OK) return st;
+                    st = evolve(phiL);
+                    if (st != TBK_OK) return st;
+                }
+            }
+            tbk_status st = run_plan(h, pl, a, b, nullptr, R * ly.B, M, precision, work, mub, s, start, left);
             if (st != TBK_OK) return st;
+            TBK_HIP(hipMemcpyAsync(nu + (int64_t)j0 * R * M, mub, sizeof(double) * (size_t)nb * R * M,
+                                   hipMemcpyDeviceToDevice, s));
         }
     }
     DevBuf flag;
@@ -432,11 +507,11 @@ extern "C" tbk_status tb_build_velocity(const double *pos, const double box[3], 
 }
 
 extern "C" tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t precision,
-                                          const tbk_kpm_config *cfg, int64_t *bytes) {
+                                          int32_t time_batch, const tbk_kpm_config *cfg, int64_t *bytes) {
     clear_error();
     TBK_CHECK(bytes != nullptr, TBK_ERR_INVALID_ARG, "bytes is NULL");
     LsqtLayout ly;
-    tbk_status st = make_layout(h, R, M, precision, cfg, ly);
+    tbk_status st = make_layout(h, R, M, precision, time_batch, cfg, ly);
     if (st != TBK_OK) return st;
     *bytes = (int64_t)ly.total;
     return TBK_OK;
@@ -444,8 +519,8 @@ extern "C" tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M
 
 extern "C" tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double a, double b, const void *r,
                                        int32_t R, int32_t M, int32_t n_t, double dt, int32_t n_cheb,
-                                       int32_t precision, const tbk_kpm_config *cfg, void *work,
-                                       int64_t work_bytes, double *nu, void *stream) {
+                                       int32_t precision, int32_t time_batch, const tbk_kpm_config *cfg,
+                                       void *work, int64_t work_bytes, double *nu, void *stream) {
     clear_error();
     TBK_CHECK(h && vx && r && work && nu, TBK_ERR_INVALID_ARG, "NULL argument");
     TBK_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(dt), TBK_ERR_NOT_FINITE,
@@ -455,7 +530,7 @@ extern "C" tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double 
     if (n_cheb <= 0) n_cheb = default_terms(a * dt / kHbar);
     TBK_CHECK(n_cheb <= 100000, TBK_ERR_INVALID_ARG, "n_cheb = %d too large", n_cheb);
     LsqtLayout ly;
-    tbk_status st = make_layout(h, R, M, precision, cfg, ly);
+    tbk_status st = make_layout(h, R, M, precision, time_batch, cfg, ly);
     if (st != TBK_OK) return st;
     TBK_CHECK(work_bytes >= (int64_t)ly.total, TBK_ERR_BUFFER_TOO_SMALL, "work has %lld bytes, needs %lld",
               (long long)work_bytes, (long long)ly.total);

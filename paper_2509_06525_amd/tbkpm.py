@@ -258,11 +258,11 @@ def lib():
     L.lsqt_chebyshev_terms.restype = i32
     L.lsqt_chebyshev_terms.argtypes = [f64, f64]
     L.lsqt_workspace_size.restype = ctypes.c_int
-    L.lsqt_workspace_size.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, ctypes.POINTER(KpmConfig),
+    L.lsqt_workspace_size.argtypes = [ctypes.POINTER(HamStruct), i32, i32, i32, i32, ctypes.POINTER(KpmConfig),
                                       ctypes.POINTER(i64)]
     L.lsqt_vac_moments.restype = ctypes.c_int
     L.lsqt_vac_moments.argtypes = [ctypes.POINTER(HamStruct), vp, f64, f64, vp, i32, i32, i32, f64, i32, i32,
-                                   ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
+                                   i32, ctypes.POINTER(KpmConfig), vp, i64, vp, vp]
     L.lsqt_sigma.restype = ctypes.c_int
     L.lsqt_sigma.argtypes = [vp, i32, i32, f64, f64, f64, i32, vp, i32, vp, vp]
     L.kpm_integrated_dos.restype = ctypes.c_int
@@ -985,8 +985,16 @@ def chebyshev_terms(a, dt):
     return int(lib().lsqt_chebyshev_terms(float(a), float(dt)))
 
 
-def vac_moments(H, vx, a, b, r, M, n_t, dt, n_cheb=0, precision=None, config=None, work=None, stream=None):
-    """nu [n_t][R][M] (float64, device): Re <phi_L(t_j)| T_m(Ht) V |phi_R(t_j)> for start vectors r [N, R]."""
+def vac_time_batch(R, time_batch=0):
+    """Time steps per recurrence lsqt_vac_moments uses (0: automatic, max(1, 16 // R))."""
+    return int(time_batch) if time_batch > 0 else max(1, 16 // int(R))
+
+
+def vac_moments(H, vx, a, b, r, M, n_t, dt, n_cheb=0, precision=None, config=None, work=None, stream=None,
+                time_batch=0):
+    """nu [n_t][R][M] (float64, device): Re <phi_L(t_j)| T_m(Ht) V |phi_R(t_j)> for start vectors r [N, R].
+    time_batch: time steps whose recurrences run as one of R * time_batch vectors (0: automatic);
+    config is the launch shape of that recurrence."""
     L = lib()
     if precision is None:
         precision = "c32" if r.dtype == torch.complex64 else "f64"
@@ -997,13 +1005,13 @@ def vac_moments(H, vx, a, b, r, M, n_t, dt, n_cheb=0, precision=None, config=Non
     R = r.shape[1]
     if work is None:
         nbytes = ctypes.c_int64(0)
-        _check(L.lsqt_workspace_size(ctypes.byref(H.st), R, int(M), PRECISIONS[precision], _cfg_ref(config),
-                                     ctypes.byref(nbytes)))
+        _check(L.lsqt_workspace_size(ctypes.byref(H.st), R, int(M), PRECISIONS[precision], int(time_batch),
+                                     _cfg_ref(config), ctypes.byref(nbytes)))
         work = torch.empty(nbytes.value, dtype=torch.uint8, device=r.device)
     nu = torch.empty((int(n_t), R, int(M)), dtype=torch.float64, device=r.device)
     _check(L.lsqt_vac_moments(ctypes.byref(H.st), _ptr(vx), float(a), float(b), _ptr(r), R, int(M), int(n_t),
-                              float(dt), int(n_cheb), PRECISIONS[precision], _cfg_ref(config), _ptr(work),
-                              work.numel(), _ptr(nu), _stream(stream)))
+                              float(dt), int(n_cheb), PRECISIONS[precision], int(time_batch), _cfg_ref(config),
+                              _ptr(work), work.numel(), _ptr(nu), _stream(stream)))
     return nu
 
 

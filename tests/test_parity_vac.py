@@ -2,7 +2,8 @@
 
 Velocity coefficients against the oracle's (FP64: 1e-15 relative); correlation
 moments nu[j][v][m] against the oracle's with the same start vectors and the
-same number of propagator terms (FP64: 1e-10 of the largest moment; complex
+same number of propagator terms, time steps batched into one recurrence or one
+at a time (FP64: 1e-10 of the largest moment, batched = unbatched to 1e-12; complex
 float: the running conductivity within 1e-4 relative L2); the running integral
 against the oracle's from the same moments; and the uniform ring, where H and
 V commute, against its k-space closed form at every time step.
@@ -51,6 +52,30 @@ def test_fp64_vac_moments_match_oracle(R):
     vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0)
     nuo = O.vac_moments(csr, vo, a, b, r, M, n_t, dt, nc)
     assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()
+
+
+@pytest.mark.parametrize("R", [1, 3])
+def test_time_batches_agree(R):
+    """Recurrences of several time steps run as one of R * B vectors: the moments
+    equal the one-step-at-a-time run's up to the tiling of the FP64 sums (1e-12 of the
+    largest), for the automatic batch (16 / R), an explicit batch with a short last
+    batch (7 steps in batches of 3), and match the oracle."""
+    s = synth.hbn_stripes(8, 7, stripe_cells=2, sigma=0.05, seed=4)
+    H, csr = setup(s, "sell_f64", 32)
+    a, b = G.oracle_ab(csr)
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
+    r = G.to_dev(synth.random_phase(s.n, R, 29))
+    M, n_t, dt = 40, 7, 0.5
+    one = tbkpm.vac_moments(H, vx, a, b, r, M, n_t, dt, time_batch=1).cpu().numpy()
+    big = np.abs(one).max()
+    for tb in (0, 3):
+        nu = tbkpm.vac_moments(H, vx, a, b, r, M, n_t, dt, time_batch=tb).cpu().numpy()
+        assert np.abs(nu - one).max() <= 1e-12 * big, tb
+    nc = tbkpm.chebyshev_terms(a, dt)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0)
+    nuo = O.vac_moments(csr, vo, a, b, r.cpu().numpy(), M, n_t, dt, nc)
+    assert np.abs(one - nuo).max() <= 1e-10 * np.abs(nuo).max()
+    assert tbkpm.vac_time_batch(R) == 16 // R
 
 
 def test_c32_conductivity_within_1e_4():
@@ -106,6 +131,10 @@ def test_vac_errors():
     with pytest.raises(tbkpm.TBKError) as e:
         tbkpm.vac_moments(H, vx, a, b, r, 16, 2, -1.0)
     assert e.value.name == "INVALID_ARG"
+    for tb in (-1, 65):                        # negative; R * B above 64 vectors
+        with pytest.raises(tbkpm.TBKError) as e:
+            tbkpm.vac_moments(H, vx, a, b, r, 16, 2, 0.5, time_batch=tb)
+        assert e.value.name == "INVALID_ARG"
     with pytest.raises(tbkpm.TBKError) as e:
         tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 3)
     assert e.value.name == "INVALID_ARG"
@@ -113,14 +142,17 @@ def test_vac_errors():
 
 
 def test_fullsize_vac_first_steps_against_oracle():
-    """The 1M-atom VAC workload in the benchmark's launch shape: its first two time
-    steps (one propagation) of all M moments against the oracle (complex-float bar:
+    """The 1M-atom VAC workload in the benchmark's launch shape (two time steps in one
+    batch, the recurrence's shape tuned for 16 vectors): its first two time steps (one
+    propagation) of all M moments against the oracle (complex-float bar:
     1e-4 of the largest moment; running integral within 1e-4 relative L2)."""
     w = synth.WORKLOADS["graphene_thermal_1M_vac"]
     s = synth.make_structure("graphene_thermal_1M_vac")
     print(f"[fullsize-vac] N={s.n} M={w['M']} n_t=2", flush=True)
     pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
-    tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, w["R"], "c32")
+    # the recurrence the benchmark tunes: R * B vectors (B time steps at a time)
+    tune = tbkpm.autotune(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, w["R"] * tbkpm.vac_time_batch(w["R"]),
+                          "c32")
     H = tbkpm.build_hamiltonian(pos, sp, s.box, s.periodic, s.onsite, s.t_pair, fmt="sell_f32", slice=tune.slice)
     csr, _ = O.hamiltonian(s.pos, s.species, s.box, s.periodic, s.onsite, s.t_pair)
     lo, hi = O.gershgorin(csr)
