@@ -16,7 +16,10 @@
 // complex, like the recurrence's.  The kernels here are plain SELL sweeps with
 // one thread per (row, vector) (for block Hamiltonians: per (orbital row,
 // vector), over the atom's blocks); the M-1 recurrence steps per time step,
-// which dominate, run in the tuned recurrence kernel.
+// which dominate, run in the tuned recurrence kernel, for B time steps at a
+// time as one recurrence of R * B vectors (the moments of different time steps
+// are independent: the phases are propagated B steps ahead and each step's
+// start and left vectors take their own columns).
 #include <algorithm>
 #include <cmath>
 #include <vector>
