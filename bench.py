@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--no-train", action="store_true",
                    help="snapshot workload: skip the network's training (seeded initial parameters) and the "
                         "learned-vs-plain comparison (for counter runs of the recurrence)")
+    p.add_argument("--block-shape", default=None,
+                   help="block (Slater-Koster) workloads: use this slice and launch shape instead of searching, "
+                        "e.g. slice=32,vpt=2,tpb=1,nt=0,xr=2,atom=1 (for counter runs)")
     p.add_argument("--no-variants", action="store_true",
                    help="skip every variant form (doubling, uniform values) and the oracle comparison run")
     p.add_argument("--retune", action="store_true",
@@ -488,7 +491,12 @@ def bench_sk(args, w):
     # atom-slice height and launch shape, searched together (a slice of 64 for the displacement
     # form, whose shape search alone takes seconds at 100 M atoms)
     best_slice, cfg, ms, form_ms = 64, None, float("inf"), {}
-    for sl in ((64,) if geom else (16, 32, 64, 128)):
+    fixed = None
+    if args.block_shape:
+        fixed = {k: int(v) for k, v in (kv.split("=") for kv in args.block_shape.split(","))}
+        best_slice = fixed["slice"]
+        cfg = tbkpm.make_config(fixed["vpt"], fixed["tpb"], fixed["nt"], fixed["xr"], 1, atom_rows=fixed["atom"])
+    for sl in (() if fixed else (64,) if geom else (16, 32, 64, 128)):
         H = build(slice_=sl)
         a, b = H.scale()
         c_, m_, f_ = pick_shape(H, a, b)
