@@ -324,7 +324,7 @@ def bench_snapshots(args, w):
     launch_bytes = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 4
     launch_s = step_ms * 1e-3 / step_launches if step_launches else kmed * 1e-3 / (M - 1)
     achieved = launch_bytes / launch_s / 1e9
-    judge = None if args.no_train else learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M,
+    comparison = None if args.no_train else learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M,
                                                         stream)
     out = {
         "metric": METRIC, "value": N * M * R / sec, "unit": "atom*moments/s", "n_gpus": 1,
@@ -335,7 +335,7 @@ def bench_snapshots(args, w):
                    "launch": cfg.as_dict(), "launch_ms_per_step": timing},
         "training": {"snapshots": tcfg["count"], "seed": tcfg["seed"], "bonds": int(X.shape[0]),
                      "epochs": len(hist), "loss_first": hist[0], "loss_last": hist[-1], "seconds": t_train},
-        "learned_vs_plain": judge,
+        "learned_vs_plain": comparison,
         "kpm_ms_median": kmed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
