@@ -324,8 +324,8 @@ def bench_snapshots(args, w):
     launch_bytes = st.n_entries * 8 + st.n_ptr * 8 + N * Rp * 8 * 4
     launch_s = step_ms * 1e-3 / step_launches if step_launches else kmed * 1e-3 / (M - 1)
     achieved = launch_bytes / launch_s / 1e9
-    comparison = None if args.no_train else learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std, r, M,
-                                                        stream)
+    comparison = None if args.no_train else learned_vs_plain(dev, gpos, gsp, seg, boxes, per, params, mean, std,
+                                                             r, M, stream)
     out = {
         "metric": METRIC, "value": N * M * R / sec, "unit": "atom*moments/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
