@@ -665,7 +665,8 @@ def bench_vac(args, w):
     """Velocity-autocorrelation conductivity (Eq. (3)): per step and frame the Hamiltonian
     and velocity operator are built, the correlation moments of n_t propagation steps
     computed (M - 1 recurrence launches, two Chebyshev-Bessel propagations and one
-    velocity product per time step; the recurrences of B = tbkpm.vac_time_batch(R)
+    velocity product per time step, phi_R and phi_L propagated together; the recurrences of
+    B = tbkpm.vac_time_batch(R)
     consecutive time steps run as one recurrence of R * B vectors) and sigma(E, t)
     formed.  A multi-frame workload also
     computes each frame's DOS moments and integrated DOS and, over the frames, the
@@ -766,9 +767,10 @@ def bench_vac(args, w):
     # recurrence launches read the matrix once per batch of B time steps and, per time
     # step, its vectors (pair form: gather T_n, T_{n-1}, left vector, write T_{n+1})
     rec = n_batches * (M - 1) * hb + n_t * (M - 1) * nr * Rp * 8 * 4
-    prop = hb + nr * Rp * 8 * 5                         # propagator term: T_k gather, T_{k-1}, T_{k+1}, acc r/w
+    # propagator term on phi_R and phi_L together: T_k gather, T_{k-1}, T_{k+1}, acc r/w
+    prop = hb + nr * 2 * Rp * 8 * 5
     vel = hb + nr * Rp * 8 * 2
-    total = F * (rec + n_t * (2 * (n_cheb - 1) * prop + vel))
+    total = F * (rec + n_t * ((n_cheb - 1) * prop + vel))
     achieved = total / sec / 1e9
     out = {
         "metric": "VAC atom*moments*timesteps/s" if not sk else "VAC orbital*moments*timesteps/s",

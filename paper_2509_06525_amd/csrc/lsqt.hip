@@ -135,10 +135,11 @@ __global__ void k_zero(int64_t m, VT *__restrict__ x) {
     if (idx < m) x[idx] = (VT)0;
 }
 
-// y = V x, (V x)_i = i sum_q vx[q] x_col[q].
+// y = V x, (V x)_i = i sum_q vx[q] x_col[q], for Rp vectors; x and y rows hold
+// xld and yld vectors (the vectors may be columns of a wider block).
 template <class VT>
-__global__ void k_apply_velocity(SellView h, const VT *__restrict__ vx, const VT *__restrict__ x, int64_t n,
-                                 int32_t Rp, VT *__restrict__ y) {
+__global__ void k_apply_velocity(SellView h, const VT *__restrict__ vx, const VT *__restrict__ x, int32_t xld,
+                                 int64_t n, int32_t Rp, VT *__restrict__ y, int32_t yld) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= n * Rp) return;
     const int64_t i = idx / Rp;
@@ -150,12 +151,13 @@ __global__ void k_apply_velocity(SellView h, const VT *__restrict__ vx, const VT
     for (int32_t k = 0; k < w; ++k) {
         const int64_t q = base + k * stride;
         const VT c = vx[q];
-        const int64_t xo = 2 * ((int64_t)h.col[q] * Rp + v);
+        const int64_t xo = 2 * ((int64_t)h.col[q] * xld + v);
         sr += c * x[xo];
         si += c * x[xo + 1];
     }
-    y[2 * idx] = -si;
-    y[2 * idx + 1] = sr;
+    const int64_t yo = 2 * (i * yld + v);
+    y[yo] = -si;
+    y[yo + 1] = sr;
 }
 
 // (A x)_i for orbital row i of a block matrix (values a, norb x norb blocks
@@ -184,18 +186,19 @@ __device__ __forceinline__ void block_row_product(const SellView &h, int32_t nor
     }
 }
 
-// y = V x on a block velocity operator.
+// y = V x on a block velocity operator (leading dimensions as k_apply_velocity).
 template <class VT>
 __global__ void k_apply_velocity_blk(SellView h, int32_t norb, const VT *__restrict__ vx, const VT *__restrict__ x,
-                                     int64_t n, int32_t Rp, VT *__restrict__ y) {
+                                     int32_t xld, int64_t n, int32_t Rp, VT *__restrict__ y, int32_t yld) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= n * Rp) return;
     const int64_t i = idx / Rp;
     const int v = (int)(idx % Rp);
     VT sr = 0, si = 0;
-    block_row_product(h, norb, vx, x, i, v, Rp, sr, si);
-    y[2 * idx] = -si;
-    y[2 * idx + 1] = sr;
+    block_row_product(h, norb, vx, x, i, v, xld, sr, si);
+    const int64_t yo = 2 * (i * yld + v);
+    y[yo] = -si;
+    y[yo + 1] = sr;
 }
 
 // One term of the propagator series on a block Hamiltonian (as k_evolve_term).
@@ -294,9 +297,9 @@ int32_t time_batch_of(int32_t R, int32_t time_batch) {
 struct LsqtLayout {
     KpmPlan pl;                 // recurrence of R * B vectors (B time steps)
     int32_t B = 1;              // time steps per recurrence
-    size_t vec = 0, off_vec = 0;        // six [rows][R_pad] vectors after the recurrence workspace
-    size_t bvec = 0, off_batch = 0;     // start and left vectors of a batch, [rows][pad(R B)] (B > 1)
-    size_t off_mu = 0, total = 0;       // a batch's moments [R B][M] (B > 1)
+    size_t vec = 0, off_vec = 0;        // [rows][R_pad] vector units after the recurrence workspace
+    size_t bvec = 0, off_batch = 0;     // start and left vectors of a batch, [rows][pad(R B)]
+    size_t off_mu = 0, total = 0;       // a batch's moments [R B][M]
 };
 
 tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision, int32_t time_batch,
@@ -317,10 +320,10 @@ tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     ly.vec = a256((size_t)h->n_rows * pad_vectors(R) * 2 * elem);
     ly.off_vec = a256(ly.pl.total);
-    ly.off_batch = ly.off_vec + 6 * ly.vec;
-    ly.bvec = ly.B > 1 ? a256((size_t)h->n_rows * ly.pl.Rp * 2 * elem) : 0;
+    ly.off_batch = ly.off_vec + 9 * ly.vec;
+    ly.bvec = a256((size_t)h->n_rows * ly.pl.Rp * 2 * elem);
     ly.off_mu = ly.off_batch + 2 * ly.bvec;
-    ly.total = ly.off_mu + (ly.B > 1 ? a256((size_t)R * ly.B * M * sizeof(double)) : 0);
+    ly.total = ly.off_mu + a256((size_t)R * ly.B * M * sizeof(double));
     return TBK_OK;
 }
 
@@ -330,15 +333,18 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
                    double *nu, hipStream_t s) {
     const KpmPlan &pl = ly.pl;
     const int32_t Rp = pad_vectors(R);
+    const int32_t R2 = 2 * Rp;      // phi_R and phi_L side by side: both propagate in one sweep
     const int64_t n = h->n_rows;
-    VT *v[6];
-    for (int k = 0; k < 6; ++k) v[k] = reinterpret_cast<VT *>(work + ly.off_vec + k * ly.vec);
-    VT *phiR = v[0], *phiL = v[1], *wv = v[2], *e1 = v[3], *e2 = v[4], *acc = v[5];
+    // vector units of [rows][Rp]: the [rows][2 Rp] blocks phi = (phi_R | phi_L), e1, e2, acc of the
+    // propagation, and w = V phi_R
+    auto unit = [&](int k) { return reinterpret_cast<VT *>(work + ly.off_vec + k * ly.vec); };
+    VT *phi = unit(0), *e1 = unit(2), *e2 = unit(4), *acc = unit(6), *wv = unit(8);
+    VT *phiL = phi + 2 * Rp;        // column Rp of phi
     const SellView sv{h->ptr, h->col, log2_of(h->fmt == TBK_CSR_F64 ? 1 : h->slice)};
     const VT *val = static_cast<const VT *>(h->val);
     const VT *ons = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
-    const int64_t nv = n * Rp;
-    const unsigned g = (unsigned)ceil_div(nv, kLsqtThreads);
+    const int64_t nv = n * Rp, nv2 = n * R2;
+    const unsigned g = (unsigned)ceil_div(nv, kLsqtThreads), g2 = (unsigned)ceil_div(nv2, kLsqtThreads);
 
     // series coefficients of U(dt)
     const double z = a * dt / kHbar;
@@ -357,89 +363,77 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
     auto term = [&](bool first, VT c1, const VT *tcur, const VT *tprev, VT *tnext, int32_t k) {
         if (blk) {
             if (first)
-                k_evolve_term_blk<VT, true><<<g, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
-                                                                        tnext, acc, cre[k], cim[k], n, Rp);
+                k_evolve_term_blk<VT, true><<<g2, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
+                                                                         tnext, acc, cre[k], cim[k], n, R2);
             else
-                k_evolve_term_blk<VT, false><<<g, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
-                                                                         tnext, acc, cre[k], cim[k], n, Rp);
+                k_evolve_term_blk<VT, false><<<g2, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
+                                                                          tnext, acc, cre[k], cim[k], n, R2);
         } else {
             if (first)
-                k_evolve_term<VT, true><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext, acc,
-                                                                    cre[k], cim[k], n, Rp);
+                k_evolve_term<VT, true><<<g2, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext, acc,
+                                                                     cre[k], cim[k], n, R2);
             else
-                k_evolve_term<VT, false><<<g, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext,
-                                                                     acc, cre[k], cim[k], n, Rp);
+                k_evolve_term<VT, false><<<g2, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext,
+                                                                      acc, cre[k], cim[k], n, R2);
         }
     };
-    auto apply_v = [&](const VT *x, VT *y) {
-        if (blk) k_apply_velocity_blk<VT><<<g, kLsqtThreads, 0, s>>>(sv, norb, vx, x, n, Rp, y);
-        else k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, x, n, Rp, y);
+    // y = V x for the Rp vectors of x (rows of xld vectors) into y (rows of yld vectors)
+    auto apply_v = [&](const VT *x, int32_t xld, VT *y, int32_t yld) {
+        if (blk) k_apply_velocity_blk<VT><<<g, kLsqtThreads, 0, s>>>(sv, norb, vx, x, xld, n, Rp, y, yld);
+        else k_apply_velocity<VT><<<g, kLsqtThreads, 0, s>>>(sv, vx, x, xld, n, Rp, y, yld);
     };
 
-    auto evolve = [&](VT *psi) -> tbk_status {
-        k_cscale<VT><<<g, kLsqtThreads, 0, s>>>(psi, cre[0], cim[0], nv, acc);
-        if (n_cheb > 1) term(true, (VT)(1.0 / a), psi, nullptr, e1, 1);
+    // phi_R and phi_L <- U(dt) (.), together
+    auto evolve = [&]() -> tbk_status {
+        k_cscale<VT><<<g2, kLsqtThreads, 0, s>>>(phi, cre[0], cim[0], nv2, acc);
+        if (n_cheb > 1) term(true, (VT)(1.0 / a), phi, nullptr, e1, 1);
         for (int32_t k = 2; k < n_cheb; ++k) {
             const VT *tcur = (k & 1) ? e2 : e1;
-            const VT *tprev = k == 2 ? psi : ((k & 1) ? e1 : e2);
+            const VT *tprev = k == 2 ? phi : ((k & 1) ? e1 : e2);
             VT *tnext = (k & 1) ? e1 : e2;
             term(false, (VT)(2.0 / a), tcur, tprev, tnext, k);
         }
-        k_cscale<VT><<<g, kLsqtThreads, 0, s>>>(acc, pr, pi, nv, psi);
+        k_cscale<VT><<<g2, kLsqtThreads, 0, s>>>(acc, pr, pi, nv2, phi);
         TBK_HIP(hipGetLastError());
         return TBK_OK;
     };
 
-    k_permute_in<VT><<<g, kLsqtThreads, 0, s>>>(r, h->perm, n, R, Rp, phiR);
-    apply_v(phiR, phiL);
+    // phi_R(0) = r (padded vectors zero), phi_L(0) = V phi_R(0)
+    k_permute_in<VT><<<g, kLsqtThreads, 0, s>>>(r, h->perm, n, R, Rp, wv);
+    k_insert_cols<VT><<<g, kLsqtThreads, 0, s>>>(wv, Rp, Rp, n, R2, 0, phi);
+    apply_v(phi, R2, phiL, R2);
     TBK_HIP(hipGetLastError());
-    if (ly.B == 1) {
-        for (int32_t j = 0; j < n_t; ++j) {
-            apply_v(phiR, wv);
-            TBK_HIP(hipGetLastError());
-            tbk_status st = run_plan(h, pl, a, b, nullptr, R, M, precision, work, nu + (int64_t)j * R * M, s, wv,
-                                     phiL);
-            if (st != TBK_OK) return st;
-            if (j + 1 < n_t) {
-                st = evolve(phiR);
-                if (st != TBK_OK) return st;
-                st = evolve(phiL);
-                if (st != TBK_OK) return st;
-            }
-        }
-    } else {
-        // B time steps at a time: V phi_R(t_j) and phi_L(t_j) of each step go into
-        // columns q R .. q R + R - 1 of the batch's start and left vectors (unused
-        // columns of a short last batch stay zero), then one pair-form recurrence of
-        // R B vectors gives the batch's moments [q][v][m] = nu[j0 + q][v][m]
-        const int32_t Rb = pl.Rp;
-        VT *start = reinterpret_cast<VT *>(work + ly.off_batch);
-        VT *left = reinterpret_cast<VT *>(work + ly.off_batch + ly.bvec);
-        double *mub = reinterpret_cast<double *>(work + ly.off_mu);
-        const int64_t nb_el = 2 * n * (int64_t)Rb;
-        const unsigned gz = (unsigned)ceil_div(nb_el, kLsqtThreads);
-        const unsigned gi = (unsigned)ceil_div(n * R, kLsqtThreads);
-        for (int32_t j0 = 0; j0 < n_t; j0 += ly.B) {
-            const int32_t nb = std::min(ly.B, n_t - j0);
+    // B time steps at a time: V phi_R(t_j) and phi_L(t_j) of each step go into columns
+    // q R .. q R + R - 1 of the batch's start and left vectors (unused columns of a
+    // short last batch stay zero), then one pair-form recurrence of R B vectors gives
+    // the batch's moments [q][v][m] = nu[j0 + q][v][m]
+    const int32_t Rb = pl.Rp;
+    VT *start = reinterpret_cast<VT *>(work + ly.off_batch);
+    VT *left = reinterpret_cast<VT *>(work + ly.off_batch + ly.bvec);
+    double *mub = reinterpret_cast<double *>(work + ly.off_mu);
+    const int64_t nb_el = 2 * n * (int64_t)Rb;
+    const unsigned gz = (unsigned)ceil_div(nb_el, kLsqtThreads);
+    const unsigned gi = (unsigned)ceil_div(n * R, kLsqtThreads);
+    for (int32_t j0 = 0; j0 < n_t; j0 += ly.B) {
+        const int32_t nb = std::min(ly.B, n_t - j0);
+        if (nb * R < Rb) {
             k_zero<VT><<<gz, kLsqtThreads, 0, s>>>(nb_el, start);
             k_zero<VT><<<gz, kLsqtThreads, 0, s>>>(nb_el, left);
-            for (int32_t q = 0; q < nb; ++q) {
-                apply_v(phiR, wv);
-                k_insert_cols<VT><<<gi, kLsqtThreads, 0, s>>>(wv, Rp, R, n, Rb, q * R, start);
-                k_insert_cols<VT><<<gi, kLsqtThreads, 0, s>>>(phiL, Rp, R, n, Rb, q * R, left);
-                TBK_HIP(hipGetLastError());
-                if (j0 + q + 1 < n_t) {
-                    tbk_status st = evolve(phiR);
-                    if (st != TBK_OK) return st;
-                    st = evolve(phiL);
-                    if (st != TBK_OK) return st;
-                }
-            }
-            tbk_status st = run_plan(h, pl, a, b, nullptr, R * ly.B, M, precision, work, mub, s, start, left);
-            if (st != TBK_OK) return st;
-            TBK_HIP(hipMemcpyAsync(nu + (int64_t)j0 * R * M, mub, sizeof(double) * (size_t)nb * R * M,
-                                   hipMemcpyDeviceToDevice, s));
         }
+        for (int32_t q = 0; q < nb; ++q) {
+            apply_v(phi, R2, wv, Rp);
+            k_insert_cols<VT><<<gi, kLsqtThreads, 0, s>>>(wv, Rp, R, n, Rb, q * R, start);
+            k_insert_cols<VT><<<gi, kLsqtThreads, 0, s>>>(phiL, R2, R, n, Rb, q * R, left);
+            TBK_HIP(hipGetLastError());
+            if (j0 + q + 1 < n_t) {
+                tbk_status st = evolve();
+                if (st != TBK_OK) return st;
+            }
+        }
+        tbk_status st = run_plan(h, pl, a, b, nullptr, R * ly.B, M, precision, work, mub, s, start, left);
+        if (st != TBK_OK) return st;
+        TBK_HIP(hipMemcpyAsync(nu + (int64_t)j0 * R * M, mub, sizeof(double) * (size_t)nb * R * M,
+                               hipMemcpyDeviceToDevice, s));
     }
     DevBuf flag;
     TBK_HIP(flag.alloc(sizeof(int32_t), s));
