@@ -664,13 +664,12 @@ def sk_block_variants(args, w, out, build, pick_shape, Hs, aa, bb, r, M, R, Rp, 
 def bench_vac(args, w):
     """Velocity-autocorrelation conductivity (Eq. (3)): per step and frame the Hamiltonian
     and velocity operator are built, the correlation moments of n_t propagation steps
-    computed (M - 1 recurrence launches, two Chebyshev-Bessel propagations and one
-    velocity product per time step, phi_R and phi_L propagated together; the recurrences of
-    B = tbkpm.vac_time_batch(R)
-    consecutive time steps run as one recurrence of R * B vectors) and sigma(E, t)
-    formed.  A multi-frame workload also
-    computes each frame's DOS moments and integrated DOS and, over the frames, the
-    averaged plateau conductivity, carriers and mobility (Sec. 2.4, Sec. 3)."""
+    computed (M - 1 recurrence launches per time step, whose recurrences run
+    B = tbkpm.vac_time_batch(R) time steps at a time as one of R * B vectors; one
+    Chebyshev-Bessel propagation of phi_R and phi_L together and one velocity product per
+    time step) and sigma(E, t) formed.  A multi-frame workload also computes each frame's
+    DOS moments and integrated DOS and, over the frames, the averaged plateau
+    conductivity, carriers and mobility (Sec. 2.4, Sec. 3)."""
     import torch
     from paper_2509_06525_amd import synth, tbkpm
     dev = torch.device("cuda:0")
