@@ -142,6 +142,49 @@ __global__ void k_descriptor(CellList cl, const double *__restrict__ pos, int64_
     for (int k = 0; k < nk; ++k) v[i * nk + k] = acc[k];
 }
 
+// The same for a compile-time basis size (the workloads' 8 functions): the per-bond
+// basis and the sums stay in registers instead of per-thread scratch memory.
+template <int NK>
+__global__ void k_descriptor_nk(CellList cl, const double *__restrict__ pos, int64_t n, double rc,
+                                const int32_t *__restrict__ species, int32_t ns, const double *__restrict__ cnk,
+                                double *__restrict__ v) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+    for_each_neighbor(cl, pos, (int32_t)i, rc, [&](int32_t j, double r, double, double, double) {
+        const double u = r / rc - 1.0;
+        const double x = 2.0 * u * u - 1.0;
+        const double c = r < rc ? 0.5 * (1.0 + cos(M_PI * r / rc)) : 0.0;
+        double f[NK];
+        double tm = 1.0, tn = x;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            double tk;
+            if (k == 0) tk = 1.0;
+            else if (k == 1) tk = x;
+            else { const double tp = 2.0 * x * tn - tm; tm = tn; tn = tp; tk = tp; }
+            f[k] = 0.5 * (tk + 1.0) * c;
+        }
+        const double *cp = pair_cnk(cnk, species, ns, NK, (int32_t)i, j);
+        if (cp) {
+#pragma unroll
+            for (int a = 0; a < NK; ++a) {
+                double sa = 0.0;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) sa += cp[a * NK + k] * f[k];
+                acc[a] += sa;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) acc[k] += f[k];
+        }
+    });
+#pragma unroll
+    for (int k = 0; k < NK; ++k) v[i * NK + k] = acc[k];
+}
+
 __global__ void k_bond_count(CellList cl, const double *__restrict__ pos, int64_t n, double rc,
                              int64_t *__restrict__ cnt) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -647,7 +690,11 @@ static tbk_status descriptor_impl(const double *pos, int64_t n, int32_t nseg, co
     tbk_status st = cells.build(pos, cnk_dev ? species : nullptr, cnk_dev ? ns : 1, n, nseg, seg_atoms, boxes,
                                 periodic, rc, s);
     if (st != TBK_OK) return st;
-    k_descriptor<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(cells.view, pos, n, rc, nk, species, ns, cnk_dev, v);
+    if (nk == 8)
+        k_descriptor_nk<8><<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(cells.view, pos, n, rc, species, ns, cnk_dev,
+                                                                      v);
+    else
+        k_descriptor<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(cells.view, pos, n, rc, nk, species, ns, cnk_dev, v);
     TBK_HIP(hipGetLastError());
     return TBK_OK;
 }
