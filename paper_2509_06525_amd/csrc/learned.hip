@@ -251,7 +251,7 @@ __global__ void k_node_features(int64_t n, const double *__restrict__ v, FeatNor
 
 // Per-block partial sums of each standardisation-free feature and its square
 // (for the fixed feature shift/scale taken from training data): part[block][2][16].
-__global__ void k_feature_moments(int64_t nb, const int32_t *__restrict__ bi, const int32_t *__restrict__ bj,
+__global__ __launch_bounds__(256) void k_feature_moments(int64_t nb, const int32_t *__restrict__ bi, const int32_t *__restrict__ bj,
                                   const double *__restrict__ br, const double *__restrict__ v, double rc,
                                   double *__restrict__ part) {
     __shared__ double red[2 * kNI][256];

@@ -88,15 +88,23 @@ struct BondScales {
 
 // The integrals of the bond i -> j (caller's atom indices): vu of the ordered
 // species pair (s_i, s_j) and vl of (s_j, s_i), times the bond's learned scales.
+// Both come back by value, so that no address of the parameter block is taken
+// and the block stays out of per-lane memory.
 __device__ __forceinline__ void bond_integrals(const BondScales &bs, const SkValues &sk, int32_t i, int32_t j,
-                                               const double *&vu, const double *&vl, double (&bu)[10],
-                                               double (&bl)[10]) {
-    vu = sk.v;
-    vl = sk.v;
+                                               double (&vu)[10], double (&vl)[10]) {
     if (sk.pv) {
         const int32_t si = sk.species[i], sj = sk.species[j];
-        vu = sk.pv + 10 * ((int64_t)si * sk.ns + sj);
-        vl = sk.pv + 10 * ((int64_t)sj * sk.ns + si);
+        const double *pu = sk.pv + 10 * ((int64_t)si * sk.ns + sj);
+        const double *pl = sk.pv + 10 * ((int64_t)sj * sk.ns + si);
+        for (int l = 0; l < 10; ++l) {
+            vu[l] = pu[l];
+            vl[l] = pl[l];
+        }
+    } else {
+        for (int l = 0; l < 10; ++l) {
+            vu[l] = sk.v[l];
+            vl[l] = sk.v[l];
+        }
     }
     if (!bs.y) return;
     const int32_t lo = min(i, j), hi = max(i, j);
@@ -105,11 +113,9 @@ __device__ __forceinline__ void bond_integrals(const BondScales &bs, const SkVal
         if (bs.bj[q] == hi) { b = q; break; }
     for (int l = 0; l < 10; ++l) {
         const double f = (b >= 0 && l < bs.K) ? 1.0 + (double)bs.y[(int64_t)l * bs.nb + b] : 1.0;
-        bu[l] = vu[l] * f;
-        bl[l] = vl[l] * f;
+        vu[l] *= f;
+        vl[l] *= f;
     }
-    vu = bu;
-    vl = bl;
 }
 
 // The NORB x NORB block of a bond of length r and vector (dx, dy, dz) from the
@@ -135,7 +141,7 @@ __device__ __forceinline__ double sk_onsite(const SkValues &sk, int32_t i, int a
 // q-th neighbour (cell-list order) and its orbital b; padding (own row, value
 // 0) up to the slice width; onsite; row Gershgorin bounds; 16-bit offsets.
 template <class V, int NORB>
-__global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n, int32_t slice,
+__global__ __launch_bounds__(kBlock) void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n, int32_t slice,
                           int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                           const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                           int32_t *__restrict__ col, V *__restrict__ val, V *__restrict__ onsite,
@@ -156,9 +162,8 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
         for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[NORB][NORB], bu[10], bl[10];
-            const double *vu, *vl;
-            bond_integrals(bs, sk, i, j, vu, vl, bu, bl);
+            double B[NORB][NORB], vu[10], vl[10];
+            bond_integrals(bs, sk, i, j, vu, vl);
             sk_block<NORB>(vu, vl, sk, rij, dx, dy, dz, B);
             const int32_t cj = NORB * iperm[j];
             for (int a = 0; a < NORB; ++a)
@@ -197,7 +202,7 @@ __global__ void k_fill_sk(CellList cl, const double *__restrict__ pos, int64_t n
 // order) at slot base + q C of the atom slice, its NORB^2 values row-major at
 // NORB^2 (base + q C); padding blocks (own row, zero) up to the slice width.
 template <class V, int NORB>
-__global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64_t n, int32_t slice,
+__global__ __launch_bounds__(kBlock) void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64_t n, int32_t slice,
                               int32_t log2_slice, double r_cut, SkValues sk, const int32_t *__restrict__ perm,
                               const int32_t *__restrict__ iperm, const int64_t *__restrict__ ptr,
                               int32_t *__restrict__ bcol, V *__restrict__ bval, V *__restrict__ onsite,
@@ -214,9 +219,8 @@ __global__ void k_fill_sk_blk(CellList cl, const double *__restrict__ pos, int64
         for (int a = 0; a < NORB; ++a) asum[a] = 0.0;
         int32_t q = 0;
         for_each_neighbor(cl, pos, i, r_cut, [&](int32_t j, double rij, double dx, double dy, double dz) {
-            double B[NORB][NORB], bu[10], bl[10];
-            const double *vu, *vl;
-            bond_integrals(bs, sk, i, j, vu, vl, bu, bl);
+            double B[NORB][NORB], vu[10], vl[10];
+            bond_integrals(bs, sk, i, j, vu, vl);
             sk_block<NORB>(vu, vl, sk, rij, dx, dy, dz, B);
             if (q < w) {
                 const int64_t slot = base + (int64_t)q * slice;
