@@ -436,6 +436,35 @@ def kpm_variant(args, label, fields, H, a, b, r, M, R, Rp, elem, diag, precision
                          "bytes_per_launch": launch_bytes, "launch_us": launch_s * 1e6}}
 
 
+def block_shape_search(H, a, b, r, geom, stream):
+    """Launch shape of the block recurrence on H for the vectors r, timed over 32 moments
+    (the tuner builds one-orbital Hamiltonians, so the block forms are searched here: a
+    thread per orbital row, a thread per atom).  Returns (shape, ms per moment, best ms
+    per form)."""
+    import torch
+    from paper_2509_06525_amd import tbkpm
+    forms = (0, 1) if H.fmt in (tbkpm.FORMATS["bsell4_f32"], tbkpm.FORMATS["bsell4_f64"]) else (0,)
+    vpts = (1, 2) if r.shape[1] >= 2 else (1,)
+    tpbs = (1, 2) if geom else (1, 2, 4)
+    if geom:
+        forms = (1,)
+    shapes = [tbkpm.make_config(v, t, nt, xr, 1, atom_rows=at) for at in forms for v in vpts
+              for t in tpbs for nt in (0, 1) for xr in (0, 1, 2)]
+    times = []
+    for c in shapes:
+        tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tbkpm.kpm_moments(H, a, b, r, 33, "c32", config=c, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    best = {}
+    for c, t in zip(shapes, times):
+        best[c.atom_rows] = min(best.get(c.atom_rows, float("inf")), t / 32)
+    return shapes[int(np.argmin(times))], min(times) / 32, best
+
+
 def bench_sk(args, w):
     """DOS step on the Slater-Koster orbital Hamiltonian (s, p: 4 rows per atom; s, p, d:
     9): build + moments + DOS per step, the recurrence rated like the one-orbital
@@ -465,28 +494,7 @@ def bench_sk(args, w):
                                           stream=stream, d=dint, e_d=synth.SK_ED)
 
     def pick_shape(H, a, b):
-        # the tuner builds one-orbital Hamiltonians, so time a few shapes here (both forms
-        # of the block kernel: a thread per orbital row, a thread per atom)
-        forms = (0, 1) if H.fmt in (tbkpm.FORMATS["bsell4_f32"], tbkpm.FORMATS["bsell4_f64"]) else (0,)
-        vpts = (1, 2) if R >= 2 else (1,)
-        tpbs = (1, 2) if geom else (1, 2, 4)
-        if geom:
-            forms = (1,)
-        shapes = [tbkpm.make_config(v, t, nt, xr, 1, atom_rows=at) for at in forms for v in vpts
-                  for t in tpbs for nt in (0, 1) for xr in (0, 1, 2)]
-        times = []
-        for c in shapes:
-            tbkpm.kpm_moments(H, a, b, r, 9, "c32", config=c, stream=stream)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            tbkpm.kpm_moments(H, a, b, r, 33, "c32", config=c, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        best = {}
-        for c, t in zip(shapes, times):
-            best[c.atom_rows] = min(best.get(c.atom_rows, float("inf")), t / 32)
-        return shapes[int(np.argmin(times))], min(times) / 32, best
+        return block_shape_search(H, a, b, r, geom, stream)
 
     # atom-slice height and launch shape, searched together (a slice of 64 for the displacement
     # form, whose shape search alone takes seconds at 100 M atoms)
@@ -697,7 +705,7 @@ def bench_vac(args, w):
         slice_, config = tune.slice, tune.config
         log(f"tuned: slice {slice_} {config.as_dict()}")
     if sk:
-        slice_ = 64                                    # atom slices; the default launch shape (atom form)
+        slice_ = 64                                    # atom slices
 
     def build(f):
         if sk:
@@ -710,6 +718,28 @@ def bench_vac(args, w):
                                     into=held.pop() if held else None)
         held.append(H)
         return H
+
+    if sk and args.block_shape:
+        fixed = {k: int(v) for k, v in (kv.split("=") for kv in args.block_shape.split(","))}
+        slice_ = fixed["slice"]
+        config = tbkpm.make_config(fixed["vpt"], fixed["tpb"], fixed["nt"], fixed["xr"], 1, atom_rows=fixed["atom"])
+    elif sk and not args.no_tune:
+        # atom-slice height and block launch shape, searched on the recurrence of R * B
+        # vectors (B time steps at a time) that dominates the step
+        rt = torch.from_numpy(synth.random_phase(nr, R * tbkpm.vac_time_batch(R),
+                                                 w["seed"] + 2 + synth.VECTOR_SEED_OFFSET,
+                                                 np.complex64)).to(dev)
+        best_ms = float("inf")
+        for sl in (16, 32, 64):
+            slice_ = sl
+            Ht = build(0)
+            c_, m_, _ = block_shape_search(Ht, *Ht.scale(), rt, False, stream)
+            if m_ < best_ms:
+                best_ms, best_slice, config = m_, sl, c_
+            del Ht
+        slice_ = best_slice
+        del rt
+        log(f"tuned: slice {slice_} {config.as_dict()} ({best_ms:.3f} ms per moment)")
 
     scales = []
     for f in range(F):

@@ -200,7 +200,31 @@ def test_block_vac_moments_match_oracle(atom, R):
     M, n_t, dt = 40, 3, 0.3
     nc = tbkpm.chebyshev_terms(a, dt)
     nuo = O.vac_moments(csr, vo, a, b, r, M, n_t, dt, nc)
-    for rows in ((2, 4) if atom else (1,)):
-        cfg = tbkpm.make_config(1, 2, 1, 0, rows, atom_rows=atom)
+    # the row groupings, and launch shapes of the kind a block-shape search picks
+    # (several tiles per block, XCD orders)
+    cfgs = [tbkpm.make_config(1, 2, 1, 0, rows, atom_rows=atom) for rows in ((2, 4) if atom else (1,))]
+    cfgs += [tbkpm.make_config(1, 1, 0, 2, 1, atom_rows=atom), tbkpm.make_config(1, 4, 1, 1, 1, atom_rows=atom)]
+    for cfg in cfgs:
         nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, config=cfg).cpu().numpy()
-        assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()
+        assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max(), cfg.as_dict()
+
+
+@pytest.mark.parametrize("slice_", [16, 32])
+@pytest.mark.parametrize("atom", [0, 1])
+def test_block_c32_vac_launch_shapes(atom, slice_):
+    """C32 VAC on stored s, p blocks in the launch shapes a block-shape search picks from
+    (two vectors per thread, tiles per block, XCD orders), against the FP64 oracle."""
+    s = synth.graphene_sheet(12, 10, 0.05, 8)
+    csr = oracle_csr(s)
+    H = build(s, "bsell4_f32", slice_)
+    a, b = G.oracle_ab(csr)
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 0)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 0, n_orb=4)
+    r = synth.random_phase(4 * s.n, 1, 6, np.complex64)
+    M, n_t, dt = 64, 5, 0.3
+    nc = tbkpm.chebyshev_terms(a, dt)
+    nuo = O.vac_moments(csr, vo, a, b, r.astype(np.complex128), M, n_t, dt, nc)
+    for cfg in (tbkpm.make_config(1, 2, 1, 0, 1, atom_rows=atom), tbkpm.make_config(2, 1, 0, 2, 1, atom_rows=atom),
+                tbkpm.make_config(2, 4, 1, 1, 1, atom_rows=atom), tbkpm.make_config(2, 2, 0, 0, 1, atom_rows=atom)):
+        nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, nc, "c32", config=cfg).cpu().numpy()
+        assert np.abs(nu - nuo).max() <= 1e-4 * np.abs(nuo).max(), cfg.as_dict()
