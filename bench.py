@@ -814,7 +814,7 @@ def bench_vac(args, w):
                    "launch": None if config is None else config.as_dict()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "whole VAC step (k_cheb_step_atom pair form, k_evolve_term_blk, "
+                     "kernel": "whole VAC step (k_cheb_step_atom pair form, k_evolve_term_atom, "
                                "k_apply_velocity_blk)" if sk else
                                "whole VAC step (k_cheb_step pair form, k_evolve_term, k_apply_velocity)",
                      "bytes_per_step": total},

@@ -201,27 +201,59 @@ __global__ void k_apply_velocity_blk(SellView h, int32_t norb, const VT *__restr
     y[yo + 1] = sr;
 }
 
-// One term of the propagator series on a block Hamiltonian (as k_evolve_term).
-template <class VT, bool FIRST>
-__global__ void k_evolve_term_blk(SellView h, int32_t norb, const VT *__restrict__ val, const VT *__restrict__ onsite,
-                                  VT shift, VT c1, const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
-                                  VT *__restrict__ acc, double cr, double ci, int64_t n, int32_t Rp) {
+// One term of the propagator series (as k_evolve_term) on NORB x NORB blocks,
+// a thread per (atom, vector): the thread forms the atom's NORB rows of vector
+// v, so each stored block and its column are read once per vector rather than
+// once per orbital row, and the NORB rows' sums are independent chains.  tnext
+// may alias tprev (a thread reads its own rows' old values before writing).
+template <class VT, int NORB, bool FIRST>
+__global__ __launch_bounds__(kLsqtThreads) void k_evolve_term_atom(
+    SellView h, const VT *__restrict__ val, const VT *__restrict__ onsite, VT shift, VT c1,
+    const VT *__restrict__ tcur, const VT *tprev, VT *tnext, VT *__restrict__ acc, double cr, double ci,
+    int64_t n_atoms, int32_t Rp) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= n * Rp) return;
-    const int64_t i = idx / Rp;
+    if (idx >= n_atoms * Rp) return;
+    const int64_t at = idx / Rp;
     const int v = (int)(idx % Rp);
-    const VT d = (onsite ? onsite[i] : (VT)0) - shift;
-    VT yr = d * tcur[2 * idx], yi = d * tcur[2 * idx + 1];
-    block_row_product(h, norb, val, tcur, i, v, Rp, yr, yi);
-    VT tr = c1 * yr, ti = c1 * yi;
-    if (!FIRST) {
-        tr -= tprev[2 * idx];
-        ti -= tprev[2 * idx + 1];
+    VT yr[NORB], yi[NORB];
+    for (int a = 0; a < NORB; ++a) {
+        const int64_t i = (int64_t)NORB * at + a;
+        const VT d = (onsite ? onsite[i] : (VT)0) - shift;
+        yr[a] = d * tcur[2 * (i * Rp + v)];
+        yi[a] = d * tcur[2 * (i * Rp + v) + 1];
     }
-    tnext[2 * idx] = tr;
-    tnext[2 * idx + 1] = ti;
-    acc[2 * idx] += (VT)(cr * (double)tr - ci * (double)ti);
-    acc[2 * idx + 1] += (VT)(cr * (double)ti + ci * (double)tr);
+    int64_t base, stride;
+    int32_t w;
+    row_range(h, at, base, w, stride);
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t q = base + k * stride;
+        const int64_t c0 = (int64_t)NORB * h.col[q];
+        VT xr[NORB], xi[NORB];
+        for (int b = 0; b < NORB; ++b) {
+            const int64_t xo = 2 * ((c0 + b) * Rp + v);
+            xr[b] = tcur[xo];
+            xi[b] = tcur[xo + 1];
+        }
+        const VT *blk = val + (int64_t)NORB * NORB * q;
+        for (int a = 0; a < NORB; ++a)
+            for (int b = 0; b < NORB; ++b) {
+                const VT hv = blk[NORB * a + b];
+                yr[a] += hv * xr[b];
+                yi[a] += hv * xi[b];
+            }
+    }
+    for (int a = 0; a < NORB; ++a) {
+        const int64_t o = 2 * (((int64_t)NORB * at + a) * Rp + v);
+        VT tr = c1 * yr[a], ti = c1 * yi[a];
+        if (!FIRST) {
+            tr -= tprev[o];
+            ti -= tprev[o + 1];
+        }
+        tnext[o] = tr;
+        tnext[o + 1] = ti;
+        acc[o] += (VT)(cr * (double)tr - ci * (double)ti);
+        acc[o + 1] += (VT)(cr * (double)ti + ci * (double)tr);
+    }
 }
 
 // One term of the propagator series: tnext = c1 (H - b) tcur - tprev (tprev
@@ -315,6 +347,8 @@ tbk_status make_layout(const tbk_ham *h, int32_t R, int32_t M, int32_t precision
               "the doubling identities need the same left and right vectors; VAC moments use the direct form");
     TBK_CHECK(h->n_seg == 1, TBK_ERR_UNSUPPORTED, "VAC conductivity takes one structure");
     TBK_CHECK(!ly.pl.geom, TBK_ERR_UNSUPPORTED, "VAC conductivity takes stored blocks, not the displacement form");
+    TBK_CHECK(!ly.pl.block || ly.pl.norb == 4 || ly.pl.norb == 9, TBK_ERR_UNSUPPORTED,
+              "VAC conductivity takes blocks of 4 or 9 orbitals, not %d", ly.pl.norb);
     TBK_CHECK(h->fmt != TBK_CSR_F64 || h->slice == 1, TBK_ERR_INVALID_ARG, "CSR needs slice 1");
     const size_t elem = precision == TBK_PREC_C32 ? sizeof(float) : sizeof(double);
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -362,12 +396,20 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
     const int32_t norb = pl.norb;
     auto term = [&](bool first, VT c1, const VT *tcur, const VT *tprev, VT *tnext, int32_t k) {
         if (blk) {
-            if (first)
-                k_evolve_term_blk<VT, true><<<g2, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
-                                                                         tnext, acc, cre[k], cim[k], n, R2);
+            const int64_t na = n / norb;
+            const unsigned ga = (unsigned)ceil_div(na * R2, kLsqtThreads);
+            if (norb == 4 && first)
+                k_evolve_term_atom<VT, 4, true><<<ga, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev,
+                                                                             tnext, acc, cre[k], cim[k], na, R2);
+            else if (norb == 4)
+                k_evolve_term_atom<VT, 4, false><<<ga, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev,
+                                                                              tnext, acc, cre[k], cim[k], na, R2);
+            else if (first)
+                k_evolve_term_atom<VT, 9, true><<<ga, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev,
+                                                                             tnext, acc, cre[k], cim[k], na, R2);
             else
-                k_evolve_term_blk<VT, false><<<g2, kLsqtThreads, 0, s>>>(sv, norb, val, ons, (VT)b, c1, tcur, tprev,
-                                                                          tnext, acc, cre[k], cim[k], n, R2);
+                k_evolve_term_atom<VT, 9, false><<<ga, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev,
+                                                                              tnext, acc, cre[k], cim[k], na, R2);
         } else {
             if (first)
                 k_evolve_term<VT, true><<<g2, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext, acc,
