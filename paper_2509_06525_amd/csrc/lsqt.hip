@@ -257,37 +257,45 @@ __global__ __launch_bounds__(kLsqtThreads) void k_evolve_term_atom(
 }
 
 // One term of the propagator series: tnext = c1 (H - b) tcur - tprev (tprev
-// absent on the first term), then acc += (cr + i ci) tnext.  tnext may alias
-// tprev (each element reads its own old value before writing).
+// absent on the first term), then acc += (cr + i ci) tnext.  A thread per row
+// and pair of vectors (Rp even: phi_R and phi_L side by side), so each stored
+// value and column is read once per pair and the pair's gathers are one
+// 16-byte (C32) span.  tnext may alias tprev (each element reads its own old
+// value before writing).
 template <class VT, bool FIRST>
-__global__ void k_evolve_term(SellView h, const VT *__restrict__ val, const VT *__restrict__ onsite, VT shift,
-                              VT c1, const VT *__restrict__ tcur, const VT *tprev, VT *tnext, VT *__restrict__ acc,
-                              double cr, double ci, int64_t n, int32_t Rp) {
+__global__ __launch_bounds__(kLsqtThreads) void k_evolve_term(SellView h, const VT *__restrict__ val,
+                                                              const VT *__restrict__ onsite, VT shift, VT c1,
+                                                              const VT *__restrict__ tcur, const VT *tprev, VT *tnext,
+                                                              VT *__restrict__ acc, double cr, double ci, int64_t n,
+                                                              int32_t Rp) {
+    const int32_t hp = Rp / 2;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= n * Rp) return;
-    const int64_t i = idx / Rp;
-    const int v = (int)(idx % Rp);
+    if (idx >= n * hp) return;
+    const int64_t i = idx / hp;
+    const int64_t e = 2 * (i * Rp + 2 * (idx % hp));      // first of the pair's four values
     int64_t base, stride;
     int32_t w;
     row_range(h, i, base, w, stride);
     const VT d = (onsite ? onsite[i] : (VT)0) - shift;
-    VT yr = d * tcur[2 * idx], yi = d * tcur[2 * idx + 1];
+    VT y[4];
+    for (int c = 0; c < 4; ++c) y[c] = d * tcur[e + c];
     for (int32_t k = 0; k < w; ++k) {
         const int64_t q = base + k * stride;
         const VT hv = val[q];
-        const int64_t xo = 2 * ((int64_t)h.col[q] * Rp + v);
-        yr += hv * tcur[xo];
-        yi += hv * tcur[xo + 1];
+        const int64_t xo = 2 * ((int64_t)h.col[q] * Rp) + (e - 2 * i * Rp);
+        for (int c = 0; c < 4; ++c) y[c] += hv * tcur[xo + c];
     }
-    VT tr = c1 * yr, ti = c1 * yi;
-    if (!FIRST) {
-        tr -= tprev[2 * idx];
-        ti -= tprev[2 * idx + 1];
+    for (int c = 0; c < 4; c += 2) {
+        VT tr = c1 * y[c], ti = c1 * y[c + 1];
+        if (!FIRST) {
+            tr -= tprev[e + c];
+            ti -= tprev[e + c + 1];
+        }
+        tnext[e + c] = tr;
+        tnext[e + c + 1] = ti;
+        acc[e + c] += (VT)(cr * (double)tr - ci * (double)ti);
+        acc[e + c + 1] += (VT)(cr * (double)ti + ci * (double)tr);
     }
-    tnext[2 * idx] = tr;
-    tnext[2 * idx + 1] = ti;
-    acc[2 * idx] += (VT)(cr * (double)tr - ci * (double)ti);
-    acc[2 * idx + 1] += (VT)(cr * (double)ti + ci * (double)tr);
 }
 
 // y = (cr + i ci) x
@@ -379,6 +387,7 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
     const VT *ons = h->has_onsite ? static_cast<const VT *>(h->onsite) : nullptr;
     const int64_t nv = n * Rp, nv2 = n * R2;
     const unsigned g = (unsigned)ceil_div(nv, kLsqtThreads), g2 = (unsigned)ceil_div(nv2, kLsqtThreads);
+    const unsigned gp = (unsigned)ceil_div(n * Rp, kLsqtThreads);     // a thread per row and pair of vectors
 
     // series coefficients of U(dt)
     const double z = a * dt / kHbar;
@@ -412,10 +421,10 @@ tbk_status run_vac(const tbk_ham *h, const VT *vx, double a, double b, const VT 
                                                                               tnext, acc, cre[k], cim[k], na, R2);
         } else {
             if (first)
-                k_evolve_term<VT, true><<<g2, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext, acc,
+                k_evolve_term<VT, true><<<gp, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext, acc,
                                                                      cre[k], cim[k], n, R2);
             else
-                k_evolve_term<VT, false><<<g2, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext,
+                k_evolve_term<VT, false><<<gp, kLsqtThreads, 0, s>>>(sv, val, ons, (VT)b, c1, tcur, tprev, tnext,
                                                                       acc, cre[k], cim[k], n, R2);
         }
     };
