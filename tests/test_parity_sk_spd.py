@@ -120,6 +120,31 @@ def test_spd_vac_moments_match_oracle():
     assert np.abs(nu - nuo).max() <= 1e-10 * np.abs(nuo).max()
 
 
+@pytest.mark.parametrize("fmt,slice_,precision,tol", [("bsell4_f64", 16, "f64", 1e-10), ("bsell4_f32", 32, "c32", 1e-4)])
+@pytest.mark.parametrize("atom", [0, 1])
+def test_spd_block_vac_moments_match_oracle(fmt, slice_, precision, tol, atom):
+    """VAC on stored 9x9 blocks: velocity coefficients in the block layout, the
+    propagator's nine-orbital blocks and both recurrence forms, against the oracle."""
+    s = synth.graphene_sheet(5, 4, 0.07, 9)
+    csr = oracle_csr(s)
+    H = build(s, fmt, slice_)
+    a, b = G.oracle_ab(csr)
+    vx = tbkpm.build_velocity(H, G.to_dev(s.pos), s.box, s.periodic, 1)
+    rows, cols, vals, _ = G.block_entries(H, vx)
+    vo = O.velocity_values(csr, s.pos, s.box, s.periodic, 1, n_orb=9)
+    orow, ocol, _ = G.csr_entries(csr)
+    o1, o2 = np.lexsort((cols, rows)), np.lexsort((ocol, orow))
+    vtol = 1e-14 if precision == "f64" else 1e-6
+    np.testing.assert_allclose(vals[o1], vo[o2], rtol=vtol, atol=vtol * np.abs(vo).max())
+    r = synth.random_phase(9 * s.n, 2, 5, np.complex128 if precision == "f64" else np.complex64)
+    M, n_t, dt = 40, 3, 0.3
+    nc = tbkpm.chebyshev_terms(a, dt)
+    cfg = tbkpm.make_config(1, 2, 1, 0, 1, atom_rows=atom)
+    nu = tbkpm.vac_moments(H, vx, a, b, G.to_dev(r), M, n_t, dt, nc, precision, config=cfg).cpu().numpy()
+    nuo = O.vac_moments(csr, vo, a, b, r.astype(np.complex128), M, n_t, dt, nc)
+    assert np.abs(nu - nuo).max() <= tol * np.abs(nuo).max()
+
+
 def test_spd_orbital_count_rejected():
     s = synth.graphene_sheet(3, 3)
     pos, sp = G.to_dev(s.pos), G.to_dev(s.species)
