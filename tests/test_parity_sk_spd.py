@@ -122,9 +122,10 @@ def test_spd_vac_moments_match_oracle():
 
 @pytest.mark.parametrize("fmt,slice_,precision,tol", [("bsell4_f64", 16, "f64", 1e-10), ("bsell4_f32", 32, "c32", 1e-4)])
 @pytest.mark.parametrize("atom", [0, 1])
-def test_spd_block_vac_moments_match_oracle(fmt, slice_, precision, tol, atom):
-    """VAC on stored 9x9 blocks: velocity coefficients in the block layout, the
-    propagator's nine-orbital blocks and both recurrence forms, against the oracle."""
+def test_spd_block_vac_along_y_both_precisions(fmt, slice_, precision, tol, atom):
+    """VAC on stored 9x9 blocks along y, FP64 and C32 against the oracle: velocity
+    coefficients in the block layout, the propagator's nine-orbital blocks and both
+    recurrence forms."""
     s = synth.graphene_sheet(5, 4, 0.07, 9)
     csr = oracle_csr(s)
     H = build(s, fmt, slice_)
