@@ -701,18 +701,17 @@ static tbk_status descriptor_impl(const double *pos, int64_t n, int32_t nseg, co
 
 // Unique bonds (i < j) within rc, ordered by (i, j); bonds written only when
 // cap suffices; returns the count in *nb.
-static tbk_status bonds_impl(const double *pos, int64_t n, int32_t nseg, const int64_t *seg_atoms, const double *boxes,
-                             const int32_t periodic[3], double rc, int64_t cap, int32_t *bi, int32_t *bj, double *br,
-                             int64_t *nb, hipStream_t s) {
-    CellListOwner cells;
-    tbk_status st = cells.build(pos, nullptr, 1, n, nseg, seg_atoms, boxes, periodic, rc, s);
-    if (st != TBK_OK) return st;
+// Bonds i < j within rc over a built cell list: per-atom counts, their offsets,
+// then (bi, bj, br) ordered by (i, j).  *nb = the number of bonds; they are
+// written only when *nb <= cap.
+static tbk_status bonds_on_cells(const CellList &cl, const double *pos, int64_t n, double rc, int64_t cap,
+                                 int32_t *bi, int32_t *bj, double *br, int64_t *nb, hipStream_t s) {
     DevBuf cnt, off, tmp;
     TBK_HIP(cnt.alloc(sizeof(int64_t) * (n + 1), s));
     TBK_HIP(off.alloc(sizeof(int64_t) * (n + 1), s));
     TBK_HIP(hipMemsetAsync(cnt.as<int64_t>() + n, 0, sizeof(int64_t), s));
     const unsigned g = (unsigned)ceil_div(n, 256);
-    k_bond_count<<<g, 256, 0, s>>>(cells.view, pos, n, rc, cnt.as<int64_t>());
+    k_bond_count<<<g, 256, 0, s>>>(cl, pos, n, rc, cnt.as<int64_t>());
     TBK_HIP(hipGetLastError());
     size_t tb = 0;
     TBK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt.as<int64_t>(), off.as<int64_t>(), (int)(n + 1), s));
@@ -725,9 +724,20 @@ static tbk_status bonds_impl(const double *pos, int64_t n, int32_t nseg, const i
     if (total > cap) return TBK_OK;
     TBK_CHECK(total == 0 || (bi && bj && br), TBK_ERR_INVALID_ARG, "bond arrays are NULL");
     if (total > 0) {
-        k_bond_fill<<<g, 256, 0, s>>>(cells.view, pos, n, rc, off.as<int64_t>(), bi, bj, br);
+        k_bond_fill<<<g, 256, 0, s>>>(cl, pos, n, rc, off.as<int64_t>(), bi, bj, br);
         TBK_HIP(hipGetLastError());
     }
+    return TBK_OK;
+}
+
+static tbk_status bonds_impl(const double *pos, int64_t n, int32_t nseg, const int64_t *seg_atoms, const double *boxes,
+                             const int32_t periodic[3], double rc, int64_t cap, int32_t *bi, int32_t *bj, double *br,
+                             int64_t *nb, hipStream_t s) {
+    CellListOwner cells;
+    tbk_status st = cells.build(pos, nullptr, 1, n, nseg, seg_atoms, boxes, periodic, rc, s);
+    if (st != TBK_OK) return st;
+    st = bonds_on_cells(cells.view, pos, n, rc, cap, bi, bj, br, nb, s);
+    if (st != TBK_OK) return st;
     TBK_HIP(hipStreamSynchronize(s));
     return TBK_OK;
 }
@@ -1082,8 +1092,9 @@ extern "C" tbk_status tb_build_hamiltonian_learned(const double *pos, const int3
     TBK_HIP(bj.alloc(sizeof(int32_t) * std::max<int64_t>(nb, 1), s));
     TBK_HIP(br.alloc(sizeof(double) * std::max<int64_t>(nb, 1), s));
     int64_t nb2 = 0;
-    st = bonds_impl(pos, n, n_seg, seg_atoms, boxes, periodic, p->r_cut, nb, bi.as<int32_t>(), bj.as<int32_t>(),
-                    br.as<double>(), &nb2, s);
+    // the hop bonds over the Hamiltonian's own cell list (same cutoff)
+    st = bonds_on_cells(plan.cells.view, pos, n, p->r_cut, nb, bi.as<int32_t>(), bj.as<int32_t>(), br.as<double>(),
+                        &nb2, s);
     if (st != TBK_OK) return st;
     TBK_CHECK(nb2 == nb, TBK_ERR_DEVICE, "bond count mismatch (%lld vs %lld)", (long long)nb2, (long long)nb);
     if (n_bonds) *n_bonds = nb;
