@@ -254,10 +254,16 @@ def bench_snapshots(args, w):
     gsp = torch.from_numpy(sp).to(dev)
     r = torch.from_numpy(synth.random_phase(N, R, w["seed"] + synth.VECTOR_SEED_OFFSET, np.complex64)).to(dev)
 
+    held = []
+
     def build():
-        return tbkpm.build_hamiltonian_learned(gpos, gsp, seg, boxes, per, [0.0], [[synth.T_CC_EV]], params,
-                                               mean, std, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
-                                               r_desc=synth.R_DESC, fmt="sell_f32", slice=64, stream=stream)
+        # each step overwrites the previous step's buffers (same structures: no size pass)
+        H = tbkpm.build_hamiltonian_learned(gpos, gsp, seg, boxes, per, [0.0], [[synth.T_CC_EV]], params,
+                                            mean, std, r_cut=synth.R_HOP, r0=synth.R0, beta=synth.BETA,
+                                            r_desc=synth.R_DESC, fmt="sell_f32", slice=64, stream=stream,
+                                            into=held.pop() if held else None)
+        held.append(H)
+        return H
 
     H = build()
     a, b = H.scales()

@@ -923,8 +923,13 @@ class MlpTrainer:
 
 def build_hamiltonian_learned(pos, species, seg_atoms, boxes, periodic, onsite, t_pair, params, shift, scale,
                               r_cut=2.0, r0=1.42, beta=3.37, r_desc=4.0, fmt="sell_f32", slice=64, reorder=True,
-                              with_bond_y=False, stream=None):
-    """Stacked structures with MLP hoppings t = t_plain (1 + y) (inference fused into assembly)."""
+                              with_bond_y=False, stream=None, into=None):
+    """Stacked structures with MLP hoppings t = t_plain (1 + y) (inference fused into assembly).
+
+    `into`: a Hamiltonian from an earlier call with the same atom count, structure
+    count, format and slice height whose buffers are overwritten (no size pass)
+    when they are large enough; `into` must not be used afterwards (not with
+    with_bond_y)."""
     L = lib()
     pos = _dev(pos, torch.float64)
     species = _dev(species, torch.int32)
@@ -935,12 +940,27 @@ def build_hamiltonian_learned(pos, species, seg_atoms, boxes, periodic, onsite, 
     model = MlpModel(r_cut=float(r_desc), n_radial=8, shift=ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
                      scale=ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)),
                      params=_dev(params, torch.float32).data_ptr())
-    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
     s = _stream(stream)
+    n = pos.shape[0]
+    if (into is not None and not with_bond_y and isinstance(into, BatchedHamiltonian)
+            and into.st.fmt == FORMATS[fmt] and into.st.slice == int(slice) and into.n_rows == n
+            and into.tensors["seg_rows"].numel() == n_seg + 1):
+        t = into.tensors
+        st = HamStruct(fmt=FORMATS[fmt], slice=int(slice), n_rows=n, n_ptr=t["ptr"].numel(),
+                       n_entries=t["col"].numel())
+        st.ptr, st.col, st.val = t["ptr"].data_ptr(), t["col"].data_ptr(), t["val"].data_ptr()
+        st.onsite, st.perm, st.seg_rows = t["onsite"].data_ptr(), t["perm"].data_ptr(), t["seg_rows"].data_ptr()
+        bounds = (ctypes.c_double * (2 * n_seg))()
+        rc = L.tb_build_hamiltonian_learned(_ptr(pos), _ptr(species), n_seg, seg, bx, per, ctypes.byref(p),
+                                            ctypes.byref(model), ctypes.byref(st), bounds, None, 0, None, s)
+        if rc != TBK_ERR_BUFFER_TOO_SMALL:
+            _check(rc)
+            del keep
+            return BatchedHamiltonian(st, t, [(bounds[2 * k], bounds[2 * k + 1]) for k in range(n_seg)])
+    st = HamStruct(fmt=FORMATS[fmt], slice=int(slice))
     _check(L.tbk_hamiltonian_size_batched(_ptr(pos), _ptr(species), n_seg, seg, bx, per, ctypes.byref(p),
                                           ctypes.byref(st), s))
     dev = pos.device
-    n = pos.shape[0]
     vdt = torch.float32 if fmt == "sell_f32" else torch.float64
     t = {
         "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),

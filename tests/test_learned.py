@@ -308,6 +308,46 @@ def test_learned_assembly_matches_oracle():
         assert lo < 0 < hi
 
 
+def test_learned_assembly_into_earlier_buffers_is_bitwise_fresh():
+    """A learned build into an earlier Hamiltonian's buffers (no size pass) equals a
+    fresh build bit for bit: pattern, values, onsite, permutation, bounds; a too
+    small earlier Hamiltonian falls back to a fresh allocation."""
+    ss = sheets_small()
+    p = G.to_dev(synth.init_mlp_params(21, out_scale=1.0))
+    pos, sp, seg, boxes, v, b = gpu_parts(ss)
+    mean, std = oracle_moments(ss)
+    gpos, gsp = G.to_dev(pos), G.to_dev(sp)
+
+    def build(pp, into=None):
+        return tbkpm.build_hamiltonian_learned(gpos, gsp, seg, boxes, PER, [0.0], [[-2.7]], pp, mean, std,
+                                               fmt="sell_f32", slice=64, into=into)
+
+    def same(H, ref, ref_entries):
+        # every stored entry of the atoms' rows (padding rows past the last atom are never read)
+        for k in ("ptr", "onsite", "perm", "seg_rows"):
+            assert torch.equal(H.tensors[k][:ref[k].numel()], ref[k]), k
+        for x, y in zip(G.entries_in_atom_order(H)[:3], ref_entries):
+            np.testing.assert_array_equal(x, y)
+
+    fresh = build(p)
+    ref = {k: t.clone() for k, t in fresh.tensors.items()}
+    ref_entries = G.entries_in_atom_order(fresh)[:3]
+    # an earlier Hamiltonian built with other network weights, then overwritten
+    other = build(p * 0.5)
+    again = build(p, into=other)
+    assert again.tensors["val"].data_ptr() == other.tensors["val"].data_ptr()
+    assert again.st.n_entries == fresh.st.n_entries and again.st.n_ptr == fresh.st.n_ptr
+    same(again, ref, ref_entries)
+    assert again.bounds == fresh.bounds
+    # buffers too small (the library refuses them before writing): a fresh build
+    small = build(p * 0.25)
+    small.tensors["col"] = small.tensors["col"][:8]
+    third = build(p, into=small)
+    assert third.tensors["val"].data_ptr() != small.tensors["val"].data_ptr()
+    same(third, ref, ref_entries)
+    assert third.bounds == fresh.bounds
+
+
 @pytest.fixture(scope="module")
 def trained():
     params, mean, std, hist, X, y = train_model()
