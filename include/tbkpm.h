@@ -836,8 +836,9 @@ tbk_status lsqt_workspace_size(const tbk_ham *h, int32_t R, int32_t M, int32_t p
  *        doubling must be 0);
  *   nu   device double [n_t][R][M].
  * Synchronises `stream`.  Errors: as kpm_moments_config; INVALID_ARG (dt <= 0,
- * n_t outside [1, 10^6], doubling, time_batch < 0, R * B > 64); SPECTRUM when a
- * moment is not finite.
+ * n_t outside [1, 10^6], doubling, time_batch < 0, R * B > 64); UNSUPPORTED
+ * (several structures, the displacement form, blocks of other than 4 or 9
+ * orbitals); SPECTRUM when a moment is not finite.
  */
 tbk_status lsqt_vac_moments(const tbk_ham *h, const void *vx, double a, double b, const void *r,
                             int32_t R, int32_t M, int32_t n_t, double dt, int32_t n_cheb,
