@@ -48,7 +48,7 @@ typedef enum {
 const char *tbk_last_error(void);
 
 /* ABI revision of this header (incremented on any incompatible change). */
-#define TBK_ABI_VERSION 13
+#define TBK_ABI_VERSION 14
 int32_t tbk_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
@@ -77,11 +77,14 @@ typedef enum {
                            no networks): ptr, col as TBK_BSELL4_*; val [3 n_entries],
                            (dx, dy, dz) from the row atom to col[q] (minimum image; zero
                            on padding); the recurrence forms every block from it and the
-                           integrals in h->sk_geom (12 B or 24 B per bond instead of
+                           integrals in h->sk_geom (28 B per bond read instead of
                            n_orb^2 values: the matrix-free form for models whose
                            blocks do not fit in memory)                              */
     TBK_BGEOM_F32 = 6   /* the same with float displacements (complex-float
-                           recurrence, blocks formed in float)                       */
+                           recurrence, blocks formed in float); val [4 n_entries]:
+                           slot q holds (dx, dy, dz, c) with c the bits of col[q] as
+                           a float, one 16-byte record, the only bond data the
+                           recurrence reads                                          */
 } tbk_format;
 
 /* Distance-scaled hopping model of Eq. (1):

@@ -577,9 +577,11 @@ __device__ __forceinline__ void sk_apply(const BondFrame<VT> &b, const VT (&x)[N
 // displacement d = x_j - x_i (3 values) instead of its block.  The block is
 // applied without being formed: r = |d|, direction cosines d / r, integrals
 // scaled by f(r) = exp(-beta (r / r0 - 1)), then sk_apply in the vector type.
-// Padding slots (d = 0) are skipped.  Per bond this reads 12 B (float) instead
-// of 4 NORB^2 B.  With one FP32 vector and staging, the finish's T_{n-1} and r
-// are copied to LDS when the tile starts (finish_rows_prefetched).
+// Padding slots (d = 0) are skipped.  Per float bond this reads one 16-byte
+// record (dx, dy, dz, the column's bits) instead of a column and 4 NORB^2 B;
+// double bonds read the column and 24 B.  With one FP32 vector and staging, the
+// finish's T_{n-1} and r are copied to LDS when the tile starts
+// (finish_rows_prefetched).
 template <class VT, int NORB, int L, int VPT, bool FIRST, bool DIAG, bool NT, bool DBL>
 __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ bcol, const VT *__restrict__ geo,
@@ -632,10 +634,18 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_geom(
 #pragma unroll
             for (int u = 0; u < KU; ++u) {
                 const int64_t qb = base + (int64_t)max(0, min(k0 + u, w - 1)) * stride;
-                cn[u] = ld<NT>(bcol + qb);
-                dxn[u] = ld<NT>(geo + 3 * qb);
-                dyn[u] = ld<NT>(geo + 3 * qb + 1);
-                dzn[u] = ld<NT>(geo + 3 * qb + 2);
+                if constexpr (sizeof(VT) == 4) {      // one 16-byte record (dx, dy, dz, column)
+                    const f4v g = ld<NT>(reinterpret_cast<const f4v *>(geo) + qb);
+                    dxn[u] = g.x;
+                    dyn[u] = g.y;
+                    dzn[u] = g.z;
+                    cn[u] = __float_as_int(g.w);
+                } else {
+                    cn[u] = ld<NT>(bcol + qb);
+                    dxn[u] = ld<NT>(geo + 3 * qb);
+                    dyn[u] = ld<NT>(geo + 3 * qb + 1);
+                    dzn[u] = ld<NT>(geo + 3 * qb + 2);
+                }
             }
         };
         // the finish's streams (T_{n-1}, r) copied to LDS ahead of the bond loop

@@ -208,6 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_sk_blk(CellList cl, const doubl
                               int32_t *__restrict__ bcol, V *__restrict__ bval, V *__restrict__ onsite,
                               int64_t *__restrict__ bound_keys, BondScales bs, bool geom) {
     constexpr int NB = NORB * NORB;
+    constexpr int GE = sizeof(V) == 4 ? 4 : 3;     // values per displacement slot
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     if (r < n) {
@@ -226,9 +227,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_sk_blk(CellList cl, const doubl
                 const int64_t slot = base + (int64_t)q * slice;
                 bcol[slot] = iperm[j];
                 if (geom) {              // the bond's displacement instead of its block
-                    bval[3 * slot] = (V)dx;
-                    bval[3 * slot + 1] = (V)dy;
-                    bval[3 * slot + 2] = (V)dz;
+                    bval[GE * slot] = (V)dx;
+                    bval[GE * slot + 1] = (V)dy;
+                    bval[GE * slot + 2] = (V)dz;
+                    if constexpr (GE == 4) bval[GE * slot + 3] = __int_as_float(iperm[j]);
                 } else {
                     for (int a = 0; a < NORB; ++a)
                         for (int b = 0; b < NORB; ++b) bval[NB * slot + NORB * a + b] = (V)B[a][b];
@@ -242,7 +244,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_sk_blk(CellList cl, const doubl
             const int64_t slot = base + (int64_t)k * slice;
             bcol[slot] = (int32_t)r;
             const int ne = geom ? 3 : NB;
-            for (int e = 0; e < ne; ++e) bval[(int64_t)ne * slot + e] = (V)0;
+            const int64_t e0 = (geom ? GE : NB) * slot;
+            for (int e = 0; e < ne; ++e) bval[e0 + e] = (V)0;
+            if constexpr (GE == 4)
+                if (geom) bval[e0 + 3] = __int_as_float((int32_t)r);
         }
         for (int a = 0; a < NORB; ++a) {
             const double e = sk_onsite(sk, i, a);

@@ -467,7 +467,9 @@ def build_hamiltonian_sk(pos, species, box, periodic, v_ss_sigma, v_sp_sigma, v_
     dev = pos.device
     vdt = torch.float32 if fmt in ("sell_f32", "bsell4_f32", "bgeom_f32") else torch.float64
     # norb x norb blocks, or the bond's displacement (3 values) for the matrix-free form
-    per_entry = norb * norb if fmt.startswith("bsell4") else (3 if fmt.startswith("bgeom") else 1)
+    # displacement form: (dx, dy, dz) per slot; float slots carry the column as a 4th value
+    per_entry = norb * norb if fmt.startswith("bsell4") else (
+        (4 if fmt == "bgeom_f32" else 3) if fmt.startswith("bgeom") else 1)
     t = {
         "ptr": torch.empty(st.n_ptr, dtype=torch.int64, device=dev),
         "col": torch.empty(max(st.n_entries, 1), dtype=torch.int32, device=dev),

@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_version_and_error_text_without_gpu(lib):
     """The version, and a successful call leaves the thread's error text empty
     (whatever an earlier call on this thread left there)."""
-    assert lib.tbk_abi_version() == 13
+    assert lib.tbk_abi_version() == 14
     st = tbkpm.HamStruct(fmt=2, slice=256, n_rows=10)
     out = ctypes.c_int64(0)
     assert lib.kpm_workspace_size(ctypes.byref(st), 0, 10, 1, ctypes.byref(out)) == 1

@@ -72,6 +72,15 @@ def test_displacements_and_pattern(norb):
                     if s.periodic[ax]:
                         d[ax] -= s.box[ax] * np.rint(d[ax] / s.box[ax])
                 np.testing.assert_allclose(geo[q], d, rtol=0, atol=1e-14)
+    # float form: one 16-byte record per slot, (dx, dy, dz) rounded to float and the
+    # column's bits, on every slot of the atoms' rows (padding included)
+    Hf = build(s, norb, "bgeom_f32", 16)
+    tf = {k: v.cpu().numpy() for k, v in Hf.tensors.items()}
+    assert Hf.st.n_entries == ne and tf["val"].size >= 4 * ne
+    rec = tf["val"][: 4 * ne].reshape(ne, 4)
+    np.testing.assert_array_equal(tf["col"][:ne][valid], col[:ne][valid])
+    np.testing.assert_array_equal(rec[valid, :3], geo[valid].astype(np.float32))
+    np.testing.assert_array_equal(rec[valid, 3].view(np.int32), col[:ne][valid])
 
 
 @pytest.mark.parametrize("norb,R,tpb,nt,xr,dbl", [(4, 1, 1, 1, 0, 0), (4, 3, 2, 0, 1, 0), (9, 1, 2, 1, 0, 0),
