@@ -351,6 +351,16 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
 
+    // float blocks with several lanes per atom: each lane loads a contiguous share
+    // of the block (kFpl values, the last lane's share cut at NORB^2) and the atom's
+    // lanes (all in one wavefront) read it whole from LDS, instead of every lane
+    // loading all of it
+    constexpr int kNB = NORB * NORB;
+    constexpr bool kShare = sizeof(VT) == 4 && L >= 2 && L <= 16;
+    constexpr int kFpl = kShare ? (kNB + L - 1) / L : 1;     // block values loaded per lane
+    constexpr int kSS = (kNB + 3) / 4 * 4;                    // LDS stride per atom (16 B multiple)
+    __shared__ __align__(16) VT sblk[kShare ? kSS * APB : 1];
+
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t au = t * APB + la;
         const bool ok = au <= last;
@@ -377,10 +387,31 @@ __global__ __launch_bounds__(kThreads) void k_cheb_step_atom(
                 x[b] = load_pack<false, VT, VPT>(tcur + 2 * (((int64_t)NORB * c + b) * Rp + voff));
             if (k + 1 < w) cn = ld<NT>(bcol + qb + stride);
             const VT *bv = bval + (int64_t)NORB * NORB * qb;
+            VT *sb = sblk + (kShare ? kSS * la : 0);
+            if constexpr (kShare) {
+                VT part[kFpl];
+#pragma unroll
+                for (int e = 0; e < kFpl; ++e)
+                    if (kNB % L == 0 || vs * kFpl + e < kNB) part[e] = ld<NT>(bv + vs * kFpl + e);
+                // the previous neighbour's reads of this atom's slots come before the writes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int e = 0; e < kFpl; ++e)
+                    if (kNB % L == 0 || vs * kFpl + e < kNB) sb[vs * kFpl + e] = part[e];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
 #pragma unroll
             for (int o = 0; o < NORB; ++o) {
                 VT h[NORB];
-                load_row<NORB, NT, VT>(bv + NORB * o, h);
+                if constexpr (kShare) {
+#pragma unroll
+                    for (int b = 0; b < NORB; ++b) h[b] = sb[NORB * o + b];
+                } else {
+                    load_row<NORB, NT, VT>(bv + NORB * o, h);
+                }
 #pragma unroll
                 for (int b = 0; b < NORB; ++b)
 #pragma unroll
